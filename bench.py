@@ -1,0 +1,178 @@
+"""Benchmark: fused-expression effective HBM bandwidth on one MI355X.
+
+Workload (the 2-D expression workload, fp32, 4096 x 4096, column-major):
+    Z = 2*A + B % C - trans(D)        (tiled kernel: trans(D) staged through LDS)
+    W = exp(A) / (1 + abs(B))         (flat kernel)
+    sum(2*A + B % C - trans(D), 0)    (fused per-column sums)
+    sum(2*A + B % C - trans(D), 1)    (fused per-row sums)
+One step runs all four.  Algorithmic bytes per step: every operand read once and
+every output written once: (5 + 3 + 4 + 4) x 64 MiB + 2 x 16 KiB.
+Inputs are seeded synthetic U[-1,1] data resident in HBM before timing starts.
+
+Prints ONE JSON line (see README / DESIGN for the fields).  --gpus above 1 exits:
+this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N = 4096
+MIB64 = N * N * 4
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--cpu-cols", type=int, default=1024, help="columns of the problem the CPU oracle is timed on")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_tile_Z_4096_f32.json"))
+    return p.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is "
+              "described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2508_11385_amd as coot
+    from paper_2508_11385_amd import _coot as cc
+    import synth
+
+    coot.init(0)
+    dev = torch.device("cuda:0")
+    A, B, C, D = synth.matrix_inputs(N, "f32")
+    gA, gB, gC, gD = (coot.Mat.from_numpy(m) for m in (A, B, C, D))
+    Zout = coot.Mat.empty(N, N, "f32")
+    Wout = coot.Mat.empty(N, N, "f32")
+    s0 = coot.Mat.empty(1, N, "f32", "row")
+    s1 = coot.Mat.empty(N, 1, "f32", "col")
+
+    zexpr = 2.0 * gA + gB % gC - coot.trans(gD)
+    wexpr = coot.exp(gA) / (1.0 + coot.abs(gB))
+    zf, wf = coot.flatten(zexpr), coot.flatten(wexpr)
+
+    def handles(flags):
+        return coot.frontend.compiled(zf, flags), coot.frontend.compiled(wf, flags)
+
+    zops = [m.operand() for m in zf.mats]
+    wops = [m.operand() for m in wf.mats]
+    zo, wo, s0o, s1o = Zout.operand(), Wout.operand(), s0.operand(), s1.operand()
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def step(hz, hw):
+        cc.coot_expr_eval(hz, zops, zf.scalars, zo, None, stream)
+        cc.coot_expr_eval(hw, wops, wf.scalars, wo, None, stream)
+        cc.coot_reduce(hz, zops, zf.scalars, cc.COOT_RED_SUM, 0, 0, s0o, None, stream)
+        cc.coot_reduce(hz, zops, zf.scalars, cc.COOT_RED_SUM, 1, 0, s1o, None, stream)
+
+    bytes_step = 16 * MIB64 + 2 * N * 4
+    fused = handles(0)
+    unfused = handles(cc.COOT_CF_UNFUSED)
+
+    def run(h, steps, warmup, z_events=None):
+        for _ in range(warmup):
+            step(*h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            if z_events is not None:
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev1 = torch.cuda.Event(enable_timing=True)
+                ev0.record()
+                cc.coot_expr_eval(h[0], zops, zf.scalars, zo, None, stream)
+                ev1.record()
+                z_events.append((ev0, ev1))
+                cc.coot_expr_eval(h[1], wops, wf.scalars, wo, None, stream)
+                cc.coot_reduce(h[0], zops, zf.scalars, cc.COOT_RED_SUM, 0, 0, s0o, None, stream)
+                cc.coot_reduce(h[0], zops, zf.scalars, cc.COOT_RED_SUM, 1, 0, s1o, None, stream)
+            else:
+                step(*h)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    z_events = []
+    t_fused = run(fused, args.steps, args.warmup, z_events)
+    z_ms = sum(a.elapsed_time(b) for a, b in z_events) / len(z_events)
+    t_unfused = run(unfused, max(3, args.steps // 4), 2)
+
+    value = bytes_step / t_fused / 1e9
+    z_gbs = 5 * MIB64 / (z_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            traffic = json.load(open(args.traffic_json)).get("bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(A, B, C, D, args.cpu_cols)
+
+    out = {
+        "metric": "fused-expr effective HBM GB/s (% of peak); speedup vs unfused per-op kernels",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_fused * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic: seeded U[-1,1] fp32 operands, resident in HBM",
+        "config": {"workload": "Z=2*A+B%C-trans(D), W=exp(A)/(1+abs(B)), sum(Z,0), sum(Z,1) fused; "
+                               "fp32 4096x4096 column-major",
+                   "n_rows": N, "n_cols": N, "bytes_per_step": bytes_step},
+        "pct_of_peak": round(100 * value / PEAK_HBM_GBS, 1),
+        "unfused_ms_per_step": round(t_unfused * 1e3, 4),
+        "speedup_vs_unfused": round(t_unfused / t_fused, 2),
+        "roofline": {"bound": "hbm", "kernel": cc.coot_expr_kernel_name(fused[0]),
+                     "achieved": round(z_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(z_gbs / PEAK_HBM_GBS, 3), "traffic": traffic,
+                     "avg_kernel_us": round(z_ms * 1e3, 2), "algorithmic_bytes": 5 * MIB64},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(A, B, C, D, ncols):
+    """The oracle, as it stands, on the first `ncols` columns of the same step."""
+    import numpy as np
+    from oracle import elementwise as ew
+    from oracle import reduce as rd
+    zp = [("scalar", 0), ("load", 0), ("schur",), ("load", 1), ("load", 2), ("schur",), ("add",), ("load", 3),
+          ("trans",), ("sub",)]
+    wp = [("load", 0), ("exp",), ("scalar", 0), ("load", 1), ("abs",), ("add",), ("div",)]
+    a, b, c, d = A[:, :ncols], B[:, :ncols], C[:, :ncols], D[:ncols, :]
+    t0 = time.perf_counter()
+    Z = ew.evaluate(zp, [a, b, c, d], [2.0], "f32")
+    ew.evaluate(wp, [a, b], [1.0], "f32")
+    Z2 = ew.evaluate(zp, [a, b, c, d], [2.0], "f32")
+    [rd.to_float(q) for q in rd.sum_dim(Z2, 0, "f32")]
+    Z3 = ew.evaluate(zp, [a, b, c, d], [2.0], "f32")
+    [rd.to_float(q) for q in rd.sum_dim(Z3, 1, "f32")]
+    dt = time.perf_counter() - t0
+    nbytes = 16 * N * ncols * 4
+    del Z
+    return {"value": round(nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"the same four expressions on columns 0..{ncols - 1} of the 4096x4096 operands "
+                      f"({ncols / N:.3f} of one step), {dt:.1f} s, numpy single-threaded"}
+
+
+if __name__ == "__main__":
+    main()

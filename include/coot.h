@@ -1,0 +1,219 @@
+/*
+ * coot.h — C ABI of libcoot, a fused dense-expression engine for MI355X (gfx950).
+ *
+ * What it computes.  An Armadillo-style expression over dense matrices — the
+ * element-wise node kinds eOp / eGlue and the dimension-changing Op<.., op_trans>
+ * of the paper's Section 3 ("Internal Design") — is handed over as a postfix list
+ * and evaluated on assignment (delayed evaluation, Section 3) as ONE fused pass
+ * over device memory, or closed by a reduction: accu (sum of all elements, the
+ * sum(A) of Fig. 1 and Section 5 task 1), sum along a dimension, dot, norm.
+ * The axpy update y <- a*x + y of Sections 1 and 5 (task 2) is the expression
+ * SCALAR LOAD(x) SCHUR LOAD(y) ADD written into y.
+ *
+ * Conventions that hold for every call:
+ *   - Every function returns coot_status; nothing throws across the ABI.  On an
+ *     error, coot_last_error() returns a message (thread-local, valid until the
+ *     next coot_* call on the same thread).
+ *   - Matrices are column-major (Section 2 gives the Armadillo API; Armadillo
+ *     stores column-major): element (i, j) of an operand is at
+ *     data + (i + j * ld) * sizeof(eT), with ld >= n_rows.  A Col is n x 1,
+ *     a Row is 1 x n.
+ *   - All data pointers are DEVICE pointers on the device selected by coot_init
+ *     (the paper keeps all matrix data in GPU memory, Section 4).  They are owned
+ *     by the caller and must stay valid until the work queued on `stream` has
+ *     finished.  `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - Work is queued asynchronously on `stream`; device faults surface at the
+ *     caller's next synchronisation, as in HIP.
+ *   - Handles (coot_expr, coot_batch) are owned by the library and freed with the
+ *     matching *_release call.  Compiled code objects are cached process-wide per
+ *     expression signature (in memory and in COOT_CACHE_DIR, default
+ *     ~/.cache/coot), the analogue of the kernel cache of Section 4.
+ *   - Scalars are passed as double and converted to the element type at launch:
+ *     round-to-nearest for f32, exact for f64, truncation toward zero then
+ *     reduction mod 2^32 for u32 / s32.
+ *   - Floating-point semantics: IEEE binary32 / binary64, round-to-nearest-even,
+ *     subnormals kept, no contraction of a*b+c into an FMA, correctly rounded
+ *     division and square root.  Integer arithmetic wraps mod 2^32.
+ */
+#ifndef COOT_H
+#define COOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+typedef enum {
+  COOT_OK = 0,
+  COOT_EINVAL = -1,       /* malformed argument (NULL handle, bad enum, bad slot index) */
+  COOT_ESHAPE = -2,       /* element-wise operands of unequal dimensions, wrong output dims */
+  COOT_ETYPE = -3,        /* mixed element types, or an operation illegal for the type */
+  COOT_EALIAS = -4,       /* output overlaps an operand in a way one pass cannot honour */
+  COOT_ECOMPILE = -5,     /* runtime compilation failed (the log is in coot_last_error) */
+  COOT_EHIP = -6,         /* a HIP runtime call failed */
+  COOT_ENOMEM = -7,       /* device workspace could not be allocated */
+  COOT_EUNSUPPORTED = -8  /* valid request outside what this build implements */
+} coot_status;
+
+/* ---- element types and operand kinds (Section 2: Mat<eT>, Col, Row) ------ */
+typedef enum { COOT_U32 = 0, COOT_S32 = 1, COOT_F32 = 2, COOT_F64 = 3 } coot_dtype;
+typedef enum { COOT_MAT = 0, COOT_COL = 1, COOT_ROW = 2 } coot_kind;
+
+/* ---- postfix opcodes (Section 3: eOp, eGlue and Op<.., op_trans>) -------- */
+typedef enum {
+  COOT_OP_LOAD = 0,    /* push operand slot `arg` */
+  COOT_OP_SCALAR = 1,  /* push scalar slot `arg` (broadcast) */
+  COOT_OP_ADD = 2,     /* eGlue: pop b, pop a, push a + b */
+  COOT_OP_SUB = 3,     /*        a - b */
+  COOT_OP_SCHUR = 4,   /*        a % b (element-wise product) */
+  COOT_OP_DIV = 5,     /*        a / b (floating types only) */
+  COOT_OP_NEG = 6,     /* eOp:  -a */
+  COOT_OP_ABS = 7,     /*        |a| (abs(INT32_MIN) = INT32_MIN) */
+  COOT_OP_EXP = 8,     /*        exp(a) (floating types only) */
+  COOT_OP_LOG = 9,     /*        log(a) (floating types only) */
+  COOT_OP_SQRT = 10,   /*        sqrt(a) (floating types only) */
+  COOT_OP_SQUARE = 11, /*        a * a */
+  COOT_OP_TRANS = 12   /* Op<op_trans>: transpose (an index map, never a pass of its own) */
+} coot_opcode;
+
+typedef struct {
+  int32_t code;  /* coot_opcode */
+  uint32_t arg;  /* slot index for LOAD / SCALAR, 0 otherwise */
+} coot_op;
+
+typedef struct {
+  int32_t dtype; /* coot_dtype: every slot of one expression has the same type */
+  int32_t kind;  /* coot_kind */
+} coot_slot_type;
+
+typedef struct {
+  void* data;     /* device pointer, column-major */
+  int64_t n_rows;
+  int64_t n_cols;
+  int64_t ld;     /* leading dimension in elements, >= n_rows (0 means n_rows) */
+  int32_t dtype;  /* coot_dtype */
+  int32_t kind;   /* coot_kind */
+} coot_operand;
+
+/* Launch configuration.  Any field 0 = chosen by the library.
+ *   vec       elements per 128-bit access group: 1, 2 or 4
+ *   ept       vector groups per thread per loop trip: 1, 2, 4 or 8
+ *   waves     64-lane wavefronts per workgroup: 1, 2, 4 or 8
+ *   grid_mult workgroups per compute unit for grid-stride kernels: 1..16        */
+typedef struct {
+  uint16_t vec;
+  uint16_t ept;
+  uint16_t waves;
+  uint16_t grid_mult;
+} coot_launch_cfg;
+
+typedef enum {
+  COOT_RED_ACCU = 0, /* sum of all elements -> 1 element */
+  COOT_RED_SUM = 1,  /* sum along dim: 0 -> 1 x n_cols (per column), 1 -> n_rows x 1 (per row) */
+  COOT_RED_DOT = 2,  /* dot(a, b): the expression's root must be a % b -> 1 element */
+  COOT_RED_NORM = 3  /* 2-norm (Frobenius for a matrix) -> 1 element; floating types only */
+} coot_red;
+
+/* compile flags */
+#define COOT_CF_UNFUSED 0x1u   /* evaluate one kernel and one temporary per operator (comparator) */
+/* reduce flags */
+#define COOT_RF_PLAIN 0x1u     /* uncompensated fp32/fp64 accumulation (comparator) */
+
+typedef struct coot_expr coot_expr;
+typedef struct coot_batch coot_batch;
+
+/* Select the HIP device used by this thread and later calls (the coot_init of
+ * Section 2, Fig. 2, reduced to the one HIP backend).  Safe to call repeatedly.
+ * Errors: COOT_EHIP if the device cannot be selected. */
+coot_status coot_init(int hip_device);
+
+/* Validate and analyse a postfix expression (Section 3: the whole expression is
+ * analysed before any work is issued).
+ *   ops[n_ops]         postfix list
+ *   slots[n_slots]     dtype and kind of each operand slot (n_slots <= 16)
+ *   n_scalars          number of scalar slots (<= 32)
+ *   flags              0 or COOT_CF_UNFUSED
+ *   out                receives a new handle (library-owned)
+ * Checks arity, one dtype for all slots, operations legal for the dtype, slot
+ * indices; computes each leaf's transpose parity.  No device work and no
+ * compilation happens here; code is generated and compiled on first use, or
+ * ahead of time with coot_expr_prepare.
+ * Errors: COOT_EINVAL, COOT_ETYPE. */
+coot_status coot_expr_compile(const coot_op* ops, uint32_t n_ops, const coot_slot_type* slots,
+                              uint32_t n_slots, uint32_t n_scalars, uint32_t flags, coot_expr** out);
+
+/* Generate and compile (or fetch from the cache) the code a later call will
+ * need, so that compilation stays outside timed regions (the paper's timings
+ * exclude kernel compilation, Section 5).
+ *   mode  -1 = element-wise eval, otherwise a coot_red value
+ *   dim   for COOT_RED_SUM: 0 or 1, else ignored
+ *   rflags COOT_RF_PLAIN or 0
+ *   cfg   launch configuration the call will use (NULL = library default)
+ * Errors: COOT_EINVAL, COOT_ECOMPILE, COOT_EHIP. */
+coot_status coot_expr_prepare(coot_expr* e, int32_t mode, int32_t dim, uint32_t rflags,
+                              const coot_launch_cfg* cfg);
+
+/* Output dimensions of the element-wise result for the given operands.
+ * Errors: COOT_ESHAPE if element-wise operands disagree, COOT_EINVAL. */
+coot_status coot_expr_out_shape(const coot_expr* e, const coot_operand* operands, int64_t* n_rows,
+                                int64_t* n_cols);
+
+/* Evaluate the expression element-wise into `out` in one fused pass.
+ *   operands[n_slots]  device operands matching the compiled slot types
+ *   scalars[n_scalars] host values
+ *   out                caller-allocated device output with the inferred dims
+ *   cfg                NULL = library default / tuned choice
+ * `out` may be the same buffer as an operand that is read untransposed with the
+ * same layout (y = 2.5*x + y, B += 3*A): every element is read before it is
+ * written by the same thread.  Any other overlap gives COOT_EALIAS.
+ * Errors: COOT_EINVAL, COOT_ESHAPE, COOT_ETYPE, COOT_EALIAS, COOT_ECOMPILE,
+ * COOT_EHIP, COOT_ENOMEM (unfused temporaries). */
+coot_status coot_expr_eval(coot_expr* e, const coot_operand* operands, const double* scalars,
+                           coot_operand* out, const coot_launch_cfg* cfg, void* stream);
+
+/* Close the expression with a reduction, fused with its evaluation.
+ *   kind, dim   see coot_red; dim ignored except for COOT_RED_SUM
+ *   flags       0 (compensated: float-float / double-double per-lane sums) or
+ *               COOT_RF_PLAIN (uncompensated comparator)
+ *   out         device output of the expression's dtype: 1 element for ACCU,
+ *               DOT, NORM; 1 x n_cols for SUM dim 0; n_rows x 1 for SUM dim 1
+ * accu of an expression whose root is a % b is evaluated as dot (the product
+ * error is carried, not rounded away).  Integer sums wrap mod 2^32.  The result
+ * is deterministic: a fixed combine order and no floating-point atomics.
+ * Workspace is taken from a per-stream cache owned by the library.
+ * Errors: as coot_expr_eval; COOT_ETYPE for NORM of an integer expression,
+ * COOT_EINVAL for DOT whose root is not a Schur product. */
+coot_status coot_reduce(coot_expr* e, const coot_operand* operands, const double* scalars,
+                        int32_t kind, int32_t dim, uint32_t flags, coot_operand* out,
+                        const coot_launch_cfg* cfg, void* stream);
+
+/* Release a handle from coot_expr_compile.  NULL is ignored. */
+void coot_expr_release(coot_expr* e);
+
+/* Name of the kernel (family + signature hash) a call with these arguments
+ * would launch first, for attributing profiler traces.  Writes at most `cap`
+ * bytes including the terminator.  Errors: COOT_EINVAL. */
+coot_status coot_expr_kernel_name(coot_expr* e, int32_t mode, int32_t dim, char* buf, size_t cap);
+
+/* Counters since process start: out[0] compiles, out[1] memory-cache hits,
+ * out[2] disk-cache hits, out[3] launches, out[4] total compile milliseconds. */
+void coot_stats(double out[5]);
+
+const char* coot_last_error(void);
+
+/* Diagnostic: write the HIP source generated for one request into buf (at most
+ * cap bytes including the terminator) and, if compile != 0, compile it with
+ * hipRTC for gfx950 and report the code-object size.  Needs no device.
+ *   mode -1 eval or a coot_red; fam 0 flat / 1 tiled; vec, ept, ts the
+ *   compile-time variant (ept for flat, ts = tile edge 32 or 64 for tiled).
+ * Errors: COOT_EINVAL, COOT_ECOMPILE (log in coot_last_error). */
+coot_status coot_debug_codegen(coot_expr* e, int32_t mode, int32_t dim, uint32_t rflags, int32_t fam, int32_t vec,
+                               int32_t ept, int32_t ts, int32_t compile, char* buf, size_t cap, size_t* code_size);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COOT_H */

@@ -1,0 +1,10 @@
+"""coot-mi355x: fused dense-expression evaluation on MI355X (gfx950).
+
+`_coot` is the ctypes binding of libcoot's C ABI (include/coot.h); `frontend`
+holds the Armadillo-flavoured lazy expressions (Mat, trans, exp, accu, sum, dot,
+norm, eval).  Importing this package loads libcoot.so and fails if it is not
+built — there is no CPU fallback.
+"""
+from . import _coot  # noqa: F401
+from .frontend import (Expr, Mat, Node, Scalar, abs, accu, dot, eval, exp, flatten, init, log, norm,  # noqa: F401
+                       sqrt, square, sum, trans)

@@ -1,0 +1,174 @@
+"""ctypes binding of libcoot's C ABI (include/coot.h): argument marshalling only.
+
+Every function here has the name of the C entry point it wraps and raises
+CootError (with the library's message) on a non-zero status.  The library is
+loaded from this package directory; if it is missing, importing fails loudly —
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcoot.so")
+
+# enums (coot.h)
+COOT_OK, COOT_EINVAL, COOT_ESHAPE, COOT_ETYPE, COOT_EALIAS, COOT_ECOMPILE, COOT_EHIP, COOT_ENOMEM, \
+    COOT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7, -8
+COOT_U32, COOT_S32, COOT_F32, COOT_F64 = 0, 1, 2, 3
+COOT_MAT, COOT_COL, COOT_ROW = 0, 1, 2
+OPCODES = {"load": 0, "scalar": 1, "add": 2, "sub": 3, "schur": 4, "div": 5, "neg": 6, "abs": 7,
+           "exp": 8, "log": 9, "sqrt": 10, "square": 11, "trans": 12}
+COOT_RED_ACCU, COOT_RED_SUM, COOT_RED_DOT, COOT_RED_NORM = 0, 1, 2, 3
+COOT_CF_UNFUSED = 0x1
+COOT_RF_PLAIN = 0x1
+DTYPE_CODE = {"u32": COOT_U32, "s32": COOT_S32, "f32": COOT_F32, "f64": COOT_F64}
+STATUS_NAME = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ETYPE", -4: "EALIAS", -5: "ECOMPILE", -6: "EHIP",
+               -7: "ENOMEM", -8: "EUNSUPPORTED"}
+
+
+class coot_op(C.Structure):
+    _fields_ = [("code", C.c_int32), ("arg", C.c_uint32)]
+
+
+class coot_slot_type(C.Structure):
+    _fields_ = [("dtype", C.c_int32), ("kind", C.c_int32)]
+
+
+class coot_operand(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("n_rows", C.c_int64), ("n_cols", C.c_int64), ("ld", C.c_int64),
+                ("dtype", C.c_int32), ("kind", C.c_int32)]
+
+
+class coot_launch_cfg(C.Structure):
+    _fields_ = [("vec", C.c_uint16), ("ept", C.c_uint16), ("waves", C.c_uint16), ("grid_mult", C.c_uint16)]
+
+
+class CootError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAME.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libcoot.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+    return C.CDLL(LIB_PATH)
+
+
+lib = _load()
+
+_P = C.c_void_p
+_sig = {
+    "coot_init": (C.c_int, [C.c_int]),
+    "coot_expr_compile": (C.c_int, [C.POINTER(coot_op), C.c_uint32, C.POINTER(coot_slot_type), C.c_uint32,
+                                    C.c_uint32, C.c_uint32, C.POINTER(_P)]),
+    "coot_expr_prepare": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_uint32, C.POINTER(coot_launch_cfg)]),
+    "coot_expr_out_shape": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "coot_expr_eval": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(C.c_double), C.POINTER(coot_operand),
+                                 C.POINTER(coot_launch_cfg), _P]),
+    "coot_reduce": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(C.c_double), C.c_int32, C.c_int32,
+                              C.c_uint32, C.POINTER(coot_operand), C.POINTER(coot_launch_cfg), _P]),
+    "coot_expr_release": (None, [_P]),
+    "coot_expr_kernel_name": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_char_p, C.c_size_t]),
+    "coot_stats": (None, [C.POINTER(C.c_double)]),
+    "coot_last_error": (C.c_char_p, []),
+    "coot_debug_codegen": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_uint32, C.c_int32, C.c_int32, C.c_int32,
+                                     C.c_int32, C.c_int32, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+def _check(status):
+    if status != COOT_OK:
+        raise CootError(status, lib.coot_last_error().decode(errors="replace"))
+
+
+def _arr(ctype, items):
+    items = list(items)
+    a = (ctype * max(1, len(items)))()
+    for i, it in enumerate(items):
+        a[i] = it
+    return a
+
+
+def _cfg(cfg):
+    if cfg is None:
+        return None
+    if isinstance(cfg, coot_launch_cfg):
+        return C.byref(cfg)
+    vec, ept, waves, grid_mult = cfg
+    return C.byref(coot_launch_cfg(vec, ept, waves, grid_mult))
+
+
+# ---- entry points -----------------------------------------------------------------
+
+def coot_init(device: int = 0) -> None:
+    _check(lib.coot_init(device))
+
+
+def coot_expr_compile(postfix, slot_types, n_scalars: int, flags: int = 0) -> int:
+    """postfix: [(name, arg?), ...]; slot_types: [(dtype_code, kind_code), ...]. Returns a handle."""
+    ops = _arr(coot_op, [coot_op(OPCODES[it[0]], it[1] if len(it) > 1 else 0) for it in postfix])
+    slots = _arr(coot_slot_type, [coot_slot_type(d, k) for d, k in slot_types])
+    h = _P()
+    _check(lib.coot_expr_compile(ops, len(postfix), slots, len(slot_types), n_scalars, flags, C.byref(h)))
+    return h.value
+
+
+def coot_expr_prepare(h: int, mode: int = -1, dim: int = -1, rflags: int = 0, cfg=None) -> None:
+    _check(lib.coot_expr_prepare(h, mode, dim, rflags, _cfg(cfg)))
+
+
+def coot_expr_out_shape(h: int, operands) -> tuple:
+    ops = _arr(coot_operand, operands)
+    r, c = C.c_int64(), C.c_int64()
+    _check(lib.coot_expr_out_shape(h, ops, C.byref(r), C.byref(c)))
+    return r.value, c.value
+
+
+def coot_expr_eval(h: int, operands, scalars, out: coot_operand, cfg=None, stream: int = 0) -> None:
+    ops = _arr(coot_operand, operands)
+    sc = _arr(C.c_double, scalars)
+    _check(lib.coot_expr_eval(h, ops, sc, C.byref(out), _cfg(cfg), stream))
+
+
+def coot_reduce(h: int, operands, scalars, kind: int, dim: int, flags: int, out: coot_operand, cfg=None,
+                stream: int = 0) -> None:
+    ops = _arr(coot_operand, operands)
+    sc = _arr(C.c_double, scalars)
+    _check(lib.coot_reduce(h, ops, sc, kind, dim, flags, C.byref(out), _cfg(cfg), stream))
+
+
+def coot_expr_release(h: int) -> None:
+    lib.coot_expr_release(h)
+
+
+def coot_expr_kernel_name(h: int, mode: int = -1, dim: int = -1) -> str:
+    buf = C.create_string_buffer(256)
+    _check(lib.coot_expr_kernel_name(h, mode, dim, buf, 256))
+    return buf.value.decode()
+
+
+def coot_stats() -> dict:
+    a = (C.c_double * 5)()
+    lib.coot_stats(a)
+    return {"compiles": a[0], "mem_hits": a[1], "disk_hits": a[2], "launches": a[3], "compile_ms": a[4]}
+
+
+def coot_last_error() -> str:
+    return lib.coot_last_error().decode(errors="replace")
+
+
+def coot_debug_codegen(h: int, mode: int, dim: int, rflags: int, fam: int, vec: int, ept: int, ts: int,
+                       compile: bool):
+    buf = C.create_string_buffer(1 << 18)
+    n = C.c_size_t()
+    _check(lib.coot_debug_codegen(h, mode, dim, rflags, fam, vec, ept, ts, int(compile), buf, 1 << 18, C.byref(n)))
+    return buf.value.decode(), n.value

@@ -1,0 +1,144 @@
+// Internal declarations of libcoot (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "coot.h"
+
+namespace coot {
+
+constexpr int kMaxSlots = 16;
+constexpr int kMaxScalars = 32;
+
+// Host mirror of the device-side coot_kargs (coot_dev.h); layouts must agree.
+struct KArgs {
+  const void* leaf[kMaxSlots];
+  int64_t ld[kMaxSlots];
+  uint64_t sc[kMaxScalars];
+  void* out;
+  int64_t out_ld;
+  int64_t n_rows, n_cols;
+  void* ws;
+  void* ws2;
+  int64_t n_part;
+};
+static_assert(sizeof(KArgs) == 16 * 8 + 16 * 8 + 32 * 8 + 7 * 8, "kernel argument block layout");
+
+struct Error : std::runtime_error {
+  coot_status code;
+  Error(coot_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+[[noreturn]] void fail(coot_status c, const std::string& msg);
+void hip_check(hipError_t e, const char* what);
+
+size_t dtype_size(int dt);
+const char* dtype_cname(int dt);  // C type used in generated code
+bool dtype_is_int(int dt);
+
+// A leaf is an (operand slot, transpose parity) pair; repeated loads of the same
+// pair share one leaf.
+struct Leaf {
+  uint32_t slot;
+  uint8_t parity;
+};
+
+// Validated expression (the analysis of Section 3's whole-expression view).
+struct Expr {
+  std::vector<coot_op> ops;
+  std::vector<coot_slot_type> slots;
+  uint32_t n_scalars = 0;
+  uint32_t flags = 0;
+  int dtype = COOT_F32;
+  std::vector<Leaf> leaves;
+  std::vector<int> op_leaf;     // per op: leaf index for LOAD, -1 otherwise
+  std::vector<int> op_parity;   // per op: transpose parity of the op's value
+  int n_p1 = 0;                 // number of parity-1 leaves
+  bool root_schur = false;      // root is a Schur product (dot pattern)
+  bool scalar_only = false;     // no LOAD at all
+  std::string canon;            // canonical text (the signature body)
+  // per-request kernel cache: request key -> module-level kernel handles
+  std::mutex mu;
+  std::map<std::string, std::shared_ptr<struct Module>> reqs;
+};
+
+// Analysis
+std::unique_ptr<Expr> analyse(const coot_op* ops, uint32_t n_ops, const coot_slot_type* slots, uint32_t n_slots,
+                              uint32_t n_scalars, uint32_t flags);
+void infer_shape(const Expr& e, const coot_operand* operands, int64_t* rows, int64_t* cols);
+void check_operands(const Expr& e, const coot_operand* operands);
+uint64_t scalar_bits(double v, int dtype);
+
+// Code generation ------------------------------------------------------------
+enum Family { FAM_FLAT = 0, FAM_TILE = 1 };
+enum RedKind { RK_SUM = 0, RK_DOT = 1, RK_SUMSQ = 2 };
+
+struct Variant {  // compile-time parameters of one kernel instance
+  int vec = 4;
+  int ept = 4;     // flat families
+  int ts = 64;     // tiled families
+};
+
+struct Request {
+  int mode = -1;      // -1 eval, else coot_red
+  int dim = -1;       // COOT_RED_SUM dim
+  bool comp = true;   // compensated reduction
+  Family fam = FAM_FLAT;
+  Variant var;
+  std::string key() const;
+};
+
+struct KernelNames {
+  std::string stage1, stage1_fallback, stage2, stage1_rescale, stage2_rescale;
+};
+
+std::string generate(const Expr& e, const Request& rq, const std::string& hash_hint, KernelNames* names);
+const std::string& device_header();
+
+// JIT + caches -----------------------------------------------------------------
+struct Module {
+  hipModule_t mod = nullptr;
+  std::map<std::string, hipFunction_t> fns;
+  KernelNames names;
+  std::vector<char> code;   // code object (kept when not loaded, e.g. compile-only)
+  bool loaded = false;
+  hipFunction_t fn(const std::string& name);
+};
+
+// Compile (or fetch) the module for a request; load it on the current device
+// unless load == false (compile-only, used where no device exists).
+std::shared_ptr<Module> get_module(Expr& e, const Request& rq, bool load);
+std::string compile_source(const std::string& src, const std::string& name_hint, std::vector<char>* code);
+std::string hex128(const std::string& text);
+
+struct Stats {
+  double compiles = 0, mem_hits = 0, disk_hits = 0, launches = 0, compile_ms = 0;
+};
+Stats& stats();
+std::mutex& global_mutex();
+
+// Device / workspace ------------------------------------------------------------
+int num_cus();
+void* workspace(size_t bytes, hipStream_t s, int which);
+void* temp_alloc(size_t bytes, hipStream_t s);
+void temp_free(void* p, size_t bytes, hipStream_t s);
+
+// Execution ---------------------------------------------------------------------
+void launch(hipFunction_t f, unsigned grid, unsigned block, const KArgs& args, hipStream_t s);
+void eval_fused(Expr& e, const coot_operand* ops, const double* scalars, const coot_operand& out,
+                const coot_launch_cfg* cfg, hipStream_t s);
+void eval_unfused(Expr& e, const coot_operand* ops, const double* scalars, const coot_operand& out,
+                  const coot_launch_cfg* cfg, hipStream_t s);
+void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int kind, int dim, uint32_t flags,
+                  const coot_operand& out, const coot_launch_cfg* cfg, hipStream_t s);
+Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, int mode, int dim, bool comp,
+             const coot_launch_cfg* cfg);
+
+}  // namespace coot

@@ -1,0 +1,875 @@
+// coot_dev.h — device side of libcoot for gfx950 (CDNA4, wave64).
+//
+// This header is embedded in libcoot and handed to hipRTC together with a small
+// generated translation unit per expression signature.  The generated part is a
+// struct X with
+//     typedef <element type> T;
+//     NL          number of distinct leaves (operand slot + transpose parity)
+//     NP1         number of leaves read transposed (parity 1)
+//     slot(k)     operand slot of leaf k
+//     par(k)      transpose parity of leaf k (number of trans() above it, mod 2)
+//     p1(k)       index of leaf k among the parity-1 leaves (or -1)
+//     f(L, sc)    the expression body on one element, leaf values L[NL]
+//     f2(L, sc, &a, &b)   for a Schur-product root: its two factors
+// and extern "C" kernels that instantiate the templates below.  Everything that
+// touches memory is written here by hand: the generated body is straight-line
+// arithmetic on registers.
+//
+// The expression model is the paper's (Section 3): eOp / eGlue nodes are
+// element-wise and become the body f; Op<.., op_trans> never becomes a pass of
+// its own — it is folded into the index map of the leaves below it, and a leaf
+// read transposed is staged through LDS so both its reads and the output writes
+// stay coalesced (the implicit transpose Section 3 describes for GEMM, applied to
+// element-wise trees).
+#pragma once
+#pragma clang fp contract(off)
+
+typedef unsigned int u32;
+typedef int s32;
+typedef long long i64;
+typedef unsigned long long u64;
+
+#define COOT_MAX_SLOTS 16
+#define COOT_MAX_SCALARS 32
+
+// Kernel argument block.  Identical layout on the host (coot_kargs in kargs.h).
+struct coot_kargs {
+  const void* leaf[COOT_MAX_SLOTS];  // operand base pointers (column-major)
+  i64 ld[COOT_MAX_SLOTS];            // leading dimensions (elements)
+  u64 sc[COOT_MAX_SCALARS];          // scalars, already converted to the element type (bit pattern)
+  void* out;                         // output (eval) / final result (reduce)
+  i64 out_ld;
+  i64 n_rows, n_cols;                // dimensions of the element-wise result
+  void* ws;                          // workspace: per-block / per-tile partials
+  void* ws2;                         // second workspace word block (norm rescale control)
+  i64 n_part;                        // number of partials written by stage 1
+};
+
+namespace coot {
+
+// ---------------------------------------------------------------------------
+// element types and scalar unpacking
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ T sc_as(u64 bits);
+template <> __device__ __forceinline__ float sc_as<float>(u64 b) { return __uint_as_float((u32)b); }
+template <> __device__ __forceinline__ double sc_as<double>(u64 b) { return __longlong_as_double((i64)b); }
+template <> __device__ __forceinline__ u32 sc_as<u32>(u64 b) { return (u32)b; }
+template <> __device__ __forceinline__ s32 sc_as<s32>(u64 b) { return (s32)(u32)b; }
+
+template <typename T> struct is_int_t { static constexpr bool v = false; };
+template <> struct is_int_t<u32> { static constexpr bool v = true; };
+template <> struct is_int_t<s32> { static constexpr bool v = true; };
+
+// ---------------------------------------------------------------------------
+// element-wise operators.  Floating point: IEEE, round-to-nearest-even, no
+// contraction (pragma above + -ffp-contract=off), correctly rounded / and sqrt.
+// Integers: arithmetic mod 2^32 (s32 computed on the unsigned bit pattern so
+// that wrap-around is defined).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float op_add(float a, float b) { return a + b; }
+__device__ __forceinline__ float op_sub(float a, float b) { return a - b; }
+__device__ __forceinline__ float op_mul(float a, float b) { return a * b; }
+__device__ __forceinline__ float op_div(float a, float b) { return a / b; }
+__device__ __forceinline__ float op_neg(float a) { return -a; }
+__device__ __forceinline__ float op_abs(float a) { return __builtin_fabsf(a); }
+__device__ __forceinline__ float op_sqrt(float a) { return __builtin_sqrtf(a); }
+__device__ __forceinline__ float op_square(float a) { return a * a; }
+__device__ __forceinline__ float op_exp(float a) { return expf(a); }
+__device__ __forceinline__ float op_log(float a) { return logf(a); }
+
+__device__ __forceinline__ double op_add(double a, double b) { return a + b; }
+__device__ __forceinline__ double op_sub(double a, double b) { return a - b; }
+__device__ __forceinline__ double op_mul(double a, double b) { return a * b; }
+__device__ __forceinline__ double op_div(double a, double b) { return a / b; }
+__device__ __forceinline__ double op_neg(double a) { return -a; }
+__device__ __forceinline__ double op_abs(double a) { return __builtin_fabs(a); }
+__device__ __forceinline__ double op_sqrt(double a) { return __builtin_sqrt(a); }
+__device__ __forceinline__ double op_square(double a) { return a * a; }
+__device__ __forceinline__ double op_exp(double a) { return exp(a); }
+__device__ __forceinline__ double op_log(double a) { return log(a); }
+
+__device__ __forceinline__ u32 op_add(u32 a, u32 b) { return a + b; }
+__device__ __forceinline__ u32 op_sub(u32 a, u32 b) { return a - b; }
+__device__ __forceinline__ u32 op_mul(u32 a, u32 b) { return a * b; }
+__device__ __forceinline__ u32 op_neg(u32 a) { return 0u - a; }
+__device__ __forceinline__ u32 op_abs(u32 a) { return a; }
+__device__ __forceinline__ u32 op_square(u32 a) { return a * a; }
+
+__device__ __forceinline__ s32 op_add(s32 a, s32 b) { return (s32)((u32)a + (u32)b); }
+__device__ __forceinline__ s32 op_sub(s32 a, s32 b) { return (s32)((u32)a - (u32)b); }
+__device__ __forceinline__ s32 op_mul(s32 a, s32 b) { return (s32)((u32)a * (u32)b); }
+__device__ __forceinline__ s32 op_neg(s32 a) { return (s32)(0u - (u32)a); }
+__device__ __forceinline__ s32 op_abs(s32 a) { return a < 0 ? (s32)(0u - (u32)a) : a; }
+__device__ __forceinline__ s32 op_square(s32 a) { return (s32)((u32)a * (u32)a); }
+
+// ---------------------------------------------------------------------------
+// vector access: V consecutive elements as one 32/64/128/256-bit access.
+// ---------------------------------------------------------------------------
+template <typename T, int V> struct vt { T v[V]; };
+
+typedef u32 u32x2 __attribute__((ext_vector_type(2)));
+typedef u32 u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int V>
+__device__ __forceinline__ vt<T, V> ldv(const T* p) {
+  vt<T, V> r;
+  constexpr int B = V * (int)sizeof(T);
+  if constexpr (B == 4) {
+    u32 q = *reinterpret_cast<const u32*>(p);
+    __builtin_memcpy(&r, &q, 4);
+  } else if constexpr (B == 8) {
+    u32x2 q = *reinterpret_cast<const u32x2*>(p);
+    __builtin_memcpy(&r, &q, 8);
+  } else if constexpr (B == 16) {
+    u32x4 q = *reinterpret_cast<const u32x4*>(p);
+    __builtin_memcpy(&r, &q, 16);
+  } else {
+    static_assert(B == 32, "vector width");
+    u32x4 q0 = reinterpret_cast<const u32x4*>(p)[0];
+    u32x4 q1 = reinterpret_cast<const u32x4*>(p)[1];
+    __builtin_memcpy(&r, &q0, 16);
+    __builtin_memcpy(reinterpret_cast<char*>(&r) + 16, &q1, 16);
+  }
+  return r;
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void stv(T* p, const vt<T, V>& r) {
+  constexpr int B = V * (int)sizeof(T);
+  if constexpr (B == 4) {
+    u32 q;
+    __builtin_memcpy(&q, &r, 4);
+    *reinterpret_cast<u32*>(p) = q;
+  } else if constexpr (B == 8) {
+    u32x2 q;
+    __builtin_memcpy(&q, &r, 8);
+    *reinterpret_cast<u32x2*>(p) = q;
+  } else if constexpr (B == 16) {
+    u32x4 q;
+    __builtin_memcpy(&q, &r, 16);
+    *reinterpret_cast<u32x4*>(p) = q;
+  } else {
+    u32x4 q0, q1;
+    __builtin_memcpy(&q0, &r, 16);
+    __builtin_memcpy(&q1, reinterpret_cast<const char*>(&r) + 16, 16);
+    reinterpret_cast<u32x4*>(p)[0] = q0;
+    reinterpret_cast<u32x4*>(p)[1] = q1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Error-free transformations (Knuth's TwoSum, FMA-based TwoProd) and the
+// accumulators built from them.  A compensated accumulator keeps (hi, lo) with
+// hi + lo the running sum; every addend's rounding error is carried in lo.
+// ---------------------------------------------------------------------------
+template <typename F>
+__device__ __forceinline__ void two_sum(F a, F b, F& s, F& e) {
+  s = a + b;
+  F bp = s - a;
+  e = (a - (s - bp)) + (b - bp);
+}
+__device__ __forceinline__ void two_prod(float a, float b, float& p, float& e) {
+  p = a * b;
+  e = __builtin_fmaf(a, b, -p);
+}
+__device__ __forceinline__ void two_prod(double a, double b, double& p, double& e) {
+  p = a * b;
+  e = __builtin_fma(a, b, -p);
+}
+
+// Double-word sum (hi, lo) + (hi, lo) with renormalisation.
+template <typename F>
+__device__ __forceinline__ void dw_add(F& h, F& l, F h2, F l2) {
+  F s, e;
+  two_sum(h, h2, s, e);
+  e += l + l2;
+  F hs = s + e;
+  l = e - (hs - s);
+  h = hs;
+}
+
+// Reduction kinds
+enum { RK_SUM = 0, RK_DOT = 1, RK_SUMSQ = 2 };
+
+// Compensated accumulator for floating T; partial type P carries (hi, lo).
+template <typename T>
+struct AccComp {
+  T hi, lo;
+  __device__ __forceinline__ void init() { hi = (T)0; lo = (T)0; }
+  __device__ __forceinline__ void add(T x) {
+    T s, e;
+    two_sum(hi, x, s, e);
+    hi = s;
+    lo += e;
+  }
+  __device__ __forceinline__ void add_prod(T a, T b) {
+    T p, pe;
+    two_prod(a, b, p, pe);
+    T s, e;
+    two_sum(hi, p, s, e);
+    hi = s;
+    lo += e + pe;
+  }
+  __device__ __forceinline__ void merge(T h2, T l2) { dw_add(hi, lo, h2, l2); }
+};
+
+template <typename T>
+struct AccPlain {
+  T s;
+  __device__ __forceinline__ void init() { s = (T)0; }
+  __device__ __forceinline__ void add(T x) { s = s + x; }
+  __device__ __forceinline__ void add_prod(T a, T b) { s = s + a * b; }
+};
+
+// ---------------------------------------------------------------------------
+// wave / block combination helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float shfl_x(float v, int m) { return __shfl_xor(v, m, 64); }
+__device__ __forceinline__ double shfl_x(double v, int m) { return __shfl_xor(v, m, 64); }
+__device__ __forceinline__ u32 shfl_x(u32 v, int m) { return (u32)__shfl_xor((int)v, m, 64); }
+__device__ __forceinline__ s32 shfl_x(s32 v, int m) { return __shfl_xor(v, m, 64); }
+
+// (hi, lo) pairs summed across a whole wavefront with double-word adds.
+template <typename F>
+__device__ __forceinline__ void wave_dw_sum(F& h, F& l) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) {
+    F h2 = shfl_x(h, m), l2 = shfl_x(l, m);
+    dw_add(h, l, h2, l2);
+  }
+}
+template <typename F>
+__device__ __forceinline__ F wave_sum(F v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = op_add(v, shfl_x(v, m));
+  return v;
+}
+// Sum across groups of G consecutive lanes (G a power of two <= 64).
+template <int G, typename F>
+__device__ __forceinline__ void group_dw_sum(F& h, F& l) {
+#pragma unroll
+  for (int m = G / 2; m >= 1; m >>= 1) {
+    F h2 = shfl_x(h, m), l2 = shfl_x(l, m);
+    dw_add(h, l, h2, l2);
+  }
+}
+template <int G, typename F>
+__device__ __forceinline__ F group_sum(F v) {
+#pragma unroll
+  for (int m = G / 2; m >= 1; m >>= 1) v = op_add(v, shfl_x(v, m));
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Leaf access
+// ---------------------------------------------------------------------------
+template <class X, int V>
+__device__ __forceinline__ void load_flat(const coot_kargs& a, i64 v, vt<typename X::T, V> (&x)[X::NL]) {
+  typedef typename X::T T;
+#pragma unroll
+  for (int k = 0; k < X::NL; ++k) x[k] = ldv<T, V>((const T*)a.leaf[X::slot(k)] + v * V);
+}
+
+// ===========================================================================
+// FLAT family: every leaf untransposed and contiguous; out[i] = f(leaves[i]).
+// Grid-stride over V-element groups, E groups in flight per thread per trip,
+// then a scalar tail of n mod V elements handled by the last workgroup.
+// ===========================================================================
+template <class X, int V, int E>
+__device__ __forceinline__ void flat_eval(const coot_kargs& a) {
+  typedef typename X::T T;
+  const i64 n = a.n_rows * a.n_cols;
+  const i64 nv = n / V;
+  const int bs = blockDim.x;
+  const i64 step = (i64)gridDim.x * bs * E;
+  T* out = (T*)a.out;
+  for (i64 b = (i64)blockIdx.x * bs * E + threadIdx.x; b < nv; b += step) {
+    vt<T, V> x[E][X::NL];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const i64 v = b + (i64)e * bs;
+      if (v < nv) load_flat<X, V>(a, v, x[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const i64 v = b + (i64)e * bs;
+      if (v < nv) {
+        vt<T, V> r;
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          T L[X::NL];
+#pragma unroll
+          for (int k = 0; k < X::NL; ++k) L[k] = x[e][k].v[q];
+          r.v[q] = X::f(L, a.sc);
+        }
+        stv<T, V>(out + v * V, r);
+      }
+    }
+  }
+  if (V > 1 && blockIdx.x == gridDim.x - 1) {
+    for (i64 i = nv * V + threadIdx.x; i < n; i += bs) {
+      T L[X::NL];
+#pragma unroll
+      for (int k = 0; k < X::NL; ++k) L[k] = ((const T*)a.leaf[X::slot(k)])[i];
+      out[i] = X::f(L, a.sc);
+    }
+  }
+}
+
+// ===========================================================================
+// Element producers.  `Red` selects what a reduction consumes per element:
+// RK_SUM the value, RK_DOT the two factors of the Schur-product root, RK_SUMSQ
+// the value squared (through the accumulator's product path).
+// ===========================================================================
+template <class X, int RK, class A>
+__device__ __forceinline__ void consume(A& acc, const typename X::T* L, const u64* sc) {
+  if constexpr (RK == RK_SUM) {
+    acc.add(X::f(L, sc));
+  } else if constexpr (RK == RK_DOT) {
+    typename X::T p, q;
+    X::f2(L, sc, p, q);
+    acc.add_prod(p, q);
+  } else {
+    typename X::T v = X::f(L, sc);
+    acc.add_prod(v, v);
+  }
+}
+
+// Integer accumulator: plain wrap-around sum.
+template <typename T>
+struct AccInt {
+  T s;
+  __device__ __forceinline__ void init() { s = (T)0; }
+  __device__ __forceinline__ void add(T x) { s = op_add(s, x); }
+  __device__ __forceinline__ void add_prod(T a, T b) { s = op_add(s, op_mul(a, b)); }
+};
+
+template <typename T, bool COMP> struct AccSel { typedef AccPlain<T> type; };
+template <> struct AccSel<float, true> { typedef AccComp<float> type; };
+template <> struct AccSel<double, true> { typedef AccComp<double> type; };
+template <> struct AccSel<u32, true> { typedef AccInt<u32> type; };
+template <> struct AccSel<u32, false> { typedef AccInt<u32> type; };
+template <> struct AccSel<s32, true> { typedef AccInt<s32> type; };
+template <> struct AccSel<s32, false> { typedef AccInt<s32> type; };
+
+// Partial record written by stage 1 of a full reduction (one per workgroup) and
+// read by stage 2.  Floating compensated: (hi, lo) as binary64 words; fp32
+// partials are exact binary64 conversions of the lane's float pair.  Plain:
+// hi only.  Integers: the u32 bit pattern in hi.  amax: largest |value| seen
+// (sum of squares only, for the rescaling decision).
+struct PartRec {
+  double hi, lo, amax, pad;
+};
+
+template <typename T, bool COMP>
+__device__ __forceinline__ void lane_to_words(const typename AccSel<T, COMP>::type& acc, double& h, double& l) {
+  if constexpr (is_int_t<T>::v) {
+    h = (double)(u32)acc.s;
+    l = 0.0;
+  } else if constexpr (COMP) {
+    if constexpr (sizeof(T) == 4) {
+      h = (double)acc.hi + (double)acc.lo;  // exact: the pair spans < 53 bits
+      l = 0.0;
+    } else {
+      h = acc.hi;
+      l = acc.lo;
+    }
+  } else {
+    h = (double)acc.s;
+    l = 0.0;
+  }
+}
+
+// Combine one pair of words per lane across the workgroup and write the record.
+template <typename T, bool COMP>
+__device__ __forceinline__ void block_words_to_record(double h, double l, double amax, PartRec* dst) {
+  __shared__ double sh[16], sl[16], sm[16];
+  constexpr bool is_int = is_int_t<T>::v;
+  if (is_int) {
+    u32 v = (u32)h;
+    v = wave_sum<u32>(v);
+    h = (double)v;
+  } else if (COMP) {
+    wave_dw_sum<double>(h, l);
+  } else if (sizeof(T) == 4) {
+    float v = (float)h;
+    v = wave_sum<float>(v);
+    h = (double)v;
+  } else {
+    h = wave_sum<double>(h);
+  }
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) amax = __builtin_fmax(amax, __shfl_xor(amax, m, 64));
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[w] = h;
+    sl[w] = l;
+    sm[w] = amax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double H = sh[0], Lo = sl[0], M = sm[0];
+    for (int k = 1; k < nw; ++k) {
+      if (is_int) {
+        H = (double)((u32)H + (u32)sh[k]);
+      } else if (COMP) {
+        dw_add<double>(H, Lo, sh[k], sl[k]);
+      } else if (sizeof(T) == 4) {
+        H = (double)((float)H + (float)sh[k]);
+      } else {
+        H = H + sh[k];
+      }
+      M = __builtin_fmax(M, sm[k]);
+    }
+    PartRec r;
+    r.hi = H;
+    r.lo = Lo;
+    r.amax = M;
+    r.pad = 0.0;
+    *dst = r;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ double abs_of(T v) {
+  if constexpr (is_int_t<T>::v) {
+    return 0.0;
+  } else {
+    return __builtin_fabs((double)v);
+  }
+}
+
+// ===========================================================================
+// Full reduction, FLAT layout: grid-stride over V-groups, one record per block.
+// scale: the sum-of-squares rescaling pass multiplies each value by a power of two.
+// ===========================================================================
+template <class X, int RK, bool COMP, int V, int E, bool SCALED>
+__device__ __forceinline__ void flat_reduce(const coot_kargs& a) {
+  typedef typename X::T T;
+  typedef typename AccSel<T, COMP>::type Acc;
+  T scale = (T)1;
+  if constexpr (SCALED) {
+    const double* ctl = (const double*)a.ws2;
+    if (ctl[0] == 0.0) return;  // no rescaling requested: the whole grid exits
+    scale = (T)ctl[1];
+  }
+  Acc acc;
+  acc.init();
+  double amax = 0.0;
+  const i64 n = a.n_rows * a.n_cols;
+  const i64 nv = n / V;
+  const int bs = blockDim.x;
+  const i64 step = (i64)gridDim.x * bs * E;
+  for (i64 b = (i64)blockIdx.x * bs * E + threadIdx.x; b < nv; b += step) {
+    vt<T, V> x[E][X::NL];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const i64 v = b + (i64)e * bs;
+      if (v < nv) load_flat<X, V>(a, v, x[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const i64 v = b + (i64)e * bs;
+      if (v < nv) {
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          T L[X::NL];
+#pragma unroll
+          for (int k = 0; k < X::NL; ++k) L[k] = x[e][k].v[q];
+          if constexpr (RK == RK_SUMSQ) {
+            T val = X::f(L, a.sc);
+            amax = __builtin_fmax(amax, abs_of<T>(val));
+            val = val * scale;
+            acc.add_prod(val, val);
+          } else {
+            consume<X, RK>(acc, L, a.sc);
+          }
+        }
+      }
+    }
+  }
+  if (V > 1 && blockIdx.x == gridDim.x - 1) {
+    for (i64 i = nv * V + threadIdx.x; i < n; i += bs) {
+      T L[X::NL];
+#pragma unroll
+      for (int k = 0; k < X::NL; ++k) L[k] = ((const T*)a.leaf[X::slot(k)])[i];
+      if constexpr (RK == RK_SUMSQ) {
+        T val = X::f(L, a.sc);
+        amax = __builtin_fmax(amax, abs_of<T>(val));
+        val = val * scale;
+        acc.add_prod(val, val);
+      } else {
+        consume<X, RK>(acc, L, a.sc);
+      }
+    }
+  }
+  double h, l;
+  lane_to_words<T, COMP>(acc, h, l);
+  PartRec* recs = (PartRec*)(SCALED ? (void*)((char*)a.ws2 + 64) : a.ws);
+  block_words_to_record<T, COMP>(h, l, amax, recs + blockIdx.x);
+}
+
+// ===========================================================================
+// TILED traversal.  TS x TS output tiles, 256 threads.  Parity-1 leaves (stored
+// n_cols x n_rows) are read along their own contiguous dimension into LDS;
+// parity-0 leaves and the output are accessed along output columns.  Any
+// leading dimensions and ragged edges; V > 1 only when every contiguous extent,
+// leading dimension and base address allows it (host-checked).
+// A Sink receives each element (with its leaf values) and each finished group.
+// ===========================================================================
+template <class X, int V, int TS, class Sink>
+__device__ __forceinline__ void tiled_walk(const coot_kargs& a, Sink& sink) {
+  typedef typename X::T T;
+  constexpr int NB = 256;
+  constexpr int TPC = TS / V;     // threads along a column segment
+  constexpr int CPP = NB / TPC;   // columns per pass
+  constexpr int NPS = X::NP1 > 0 ? X::NP1 : 1;
+  __shared__ T lds[NPS][TS][TS + 1];
+  const i64 R = a.n_rows, C = a.n_cols;
+  const i64 tr = (R + TS - 1) / TS, tc = (C + TS - 1) / TS, nt = tr * tc;
+  const int lc = threadIdx.x % TPC, lr = threadIdx.x / TPC;
+  for (i64 t = blockIdx.x; t < nt; t += gridDim.x) {
+    const i64 ti = t % tr, tj = t / tr;
+    const i64 i0 = ti * TS, j0 = tj * TS;
+    sink.begin_tile();
+    if constexpr (X::NP1 > 0) {
+      for (int il = lr; il < TS; il += CPP) {
+        const i64 i = i0 + il, j = j0 + (i64)lc * V;
+        const bool in = (i < R) && (j < C);
+#pragma unroll
+        for (int k = 0; k < X::NL; ++k) {
+          if (X::par(k) == 0) continue;
+          vt<T, V> v;
+          if (in) {
+            v = ldv<T, V>((const T*)a.leaf[X::slot(k)] + j + i * a.ld[X::slot(k)]);
+          } else {
+#pragma unroll
+            for (int q = 0; q < V; ++q) v.v[q] = (T)0;
+          }
+#pragma unroll
+          for (int q = 0; q < V; ++q) lds[X::p1(k) < 0 ? 0 : X::p1(k)][il][lc * V + q] = v.v[q];
+        }
+      }
+      __syncthreads();
+    }
+    for (int jl = lr; jl < TS; jl += CPP) {
+      const i64 j = j0 + jl, i = i0 + (i64)lc * V;
+      const bool in = (i < R) && (j < C);
+      vt<T, V> x[X::NL];
+      if (in) {
+#pragma unroll
+        for (int k = 0; k < X::NL; ++k)
+          if (X::par(k) == 0) x[k] = ldv<T, V>((const T*)a.leaf[X::slot(k)] + i + j * a.ld[X::slot(k)]);
+      }
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        T L[X::NL];
+#pragma unroll
+        for (int k = 0; k < X::NL; ++k)
+          L[k] = X::par(k) ? lds[X::p1(k) < 0 ? 0 : X::p1(k)][lc * V + q][jl] : (in ? x[k].v[q] : (T)0);
+        sink.elem(a, q, in, L);
+      }
+      sink.group(a, i, j, jl, lc, in);
+    }
+    sink.end_tile(a, ti, tj, i0, j0, lr, lc);
+    if constexpr (X::NP1 > 0) __syncthreads();
+  }
+}
+
+template <class X, int V>
+struct EvalSink {
+  typedef typename X::T T;
+  vt<T, V> r;
+  __device__ __forceinline__ void begin_tile() {}
+  __device__ __forceinline__ void elem(const coot_kargs& a, int q, bool in, const T* L) {
+    r.v[q] = in ? X::f(L, a.sc) : (T)0;
+  }
+  __device__ __forceinline__ void group(const coot_kargs& a, i64 i, i64 j, int, int, bool in) {
+    if (in) stv<T, V>((T*)a.out + i + j * a.out_ld, r);
+  }
+  __device__ __forceinline__ void end_tile(const coot_kargs&, i64, i64, i64, i64, int, int) {}
+};
+
+template <class X, int V, int TS>
+__device__ __forceinline__ void tiled_eval(const coot_kargs& a) {
+  EvalSink<X, V> s;
+  tiled_walk<X, V, TS>(a, s);
+}
+
+// Full reduction over the tiled traversal (transposed or strided leaves).
+template <class X, int RK, bool COMP, bool SCALED>
+struct AllSink {
+  typedef typename X::T T;
+  typedef typename AccSel<T, COMP>::type Acc;
+  Acc acc;
+  double amax;
+  T scale;
+  __device__ __forceinline__ void begin_tile() {}
+  __device__ __forceinline__ void elem(const coot_kargs& a, int, bool in, const T* L) {
+    if (!in) return;
+    if constexpr (RK == RK_SUMSQ) {
+      T val = X::f(L, a.sc);
+      amax = __builtin_fmax(amax, abs_of<T>(val));
+      val = val * scale;
+      acc.add_prod(val, val);
+    } else {
+      consume<X, RK>(acc, L, a.sc);
+    }
+  }
+  __device__ __forceinline__ void group(const coot_kargs&, i64, i64, int, int, bool) {}
+  __device__ __forceinline__ void end_tile(const coot_kargs&, i64, i64, i64, i64, int, int) {}
+};
+
+template <class X, int RK, bool COMP, int V, int TS, bool SCALED>
+__device__ __forceinline__ void tiled_reduce(const coot_kargs& a) {
+  typedef typename X::T T;
+  AllSink<X, RK, COMP, SCALED> s;
+  s.acc.init();
+  s.amax = 0.0;
+  s.scale = (T)1;
+  if constexpr (SCALED) {
+    const double* ctl = (const double*)a.ws2;
+    if (ctl[0] == 0.0) return;
+    s.scale = (T)ctl[1];
+  }
+  tiled_walk<X, V, TS>(a, s);
+  double h, l;
+  lane_to_words<T, COMP>(s.acc, h, l);
+  PartRec* recs = (PartRec*)(SCALED ? (void*)((char*)a.ws2 + 64) : a.ws);
+  block_words_to_record<T, COMP>(h, l, s.amax, recs + blockIdx.x);
+}
+
+// ===========================================================================
+// Stage 2 of a full reduction: one workgroup of 256 threads folds the records
+// in a fixed order and writes the result in the element type.
+//   RK_SUMSQ writes sqrt of the sum (the 2-norm) and decides whether the
+//   rescaled pass must run: when the largest magnitude is outside
+//   [2^-L, 2^L] the squares may have overflowed or underflowed, so the control
+//   block gets flag = 1 and scale = 2^-e (e the exponent of the largest |value|).
+// ===========================================================================
+template <typename T, int RK, bool COMP, bool SCALED>
+__device__ __forceinline__ void reduce_stage2(const coot_kargs& a) {
+  __shared__ double sh[256], sl[256], sm[256];
+  const PartRec* recs = (const PartRec*)(SCALED ? (const void*)((const char*)a.ws2 + 64) : (const void*)a.ws);
+  double* ctl = (double*)a.ws2;
+  if constexpr (SCALED) {
+    if (ctl[0] == 0.0) return;
+  }
+  constexpr bool is_int = is_int_t<T>::v;
+  double H = 0.0, Lo = 0.0, M = 0.0;
+  for (i64 k = threadIdx.x; k < a.n_part; k += 256) {
+    const PartRec r = recs[k];
+    if (is_int) {
+      H = (double)((u32)H + (u32)r.hi);
+    } else if (COMP) {
+      dw_add<double>(H, Lo, r.hi, r.lo);
+    } else if (sizeof(T) == 4) {
+      H = (double)((float)H + (float)r.hi);
+    } else {
+      H = H + r.hi;
+    }
+    M = __builtin_fmax(M, r.amax);
+  }
+  sh[threadIdx.x] = H;
+  sl[threadIdx.x] = Lo;
+  sm[threadIdx.x] = M;
+  __syncthreads();
+  for (int s = 128; s >= 1; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      double h2 = sh[threadIdx.x + s], l2 = sl[threadIdx.x + s];
+      double h1 = sh[threadIdx.x], l1 = sl[threadIdx.x];
+      if (is_int) {
+        h1 = (double)((u32)h1 + (u32)h2);
+      } else if (COMP) {
+        dw_add<double>(h1, l1, h2, l2);
+      } else if (sizeof(T) == 4) {
+        h1 = (double)((float)h1 + (float)h2);
+      } else {
+        h1 = h1 + h2;
+      }
+      sh[threadIdx.x] = h1;
+      sl[threadIdx.x] = l1;
+      sm[threadIdx.x] = __builtin_fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    T* out = (T*)a.out;
+    const double tot = sh[0] + sl[0];
+    if (is_int) {
+      out[0] = (T)(u32)sh[0];
+    } else if (RK != RK_SUMSQ) {
+      if constexpr (sizeof(T) == 8) {
+        out[0] = (T)tot;
+      } else {
+        out[0] = (T)tot;  // one rounding from binary64
+      }
+    } else {
+      const double mx = sm[0];
+      double scale = SCALED ? ctl[1] : 1.0;
+      double nrm = __builtin_sqrt(tot) / scale;
+      out[0] = (T)nrm;
+      if constexpr (!SCALED) {
+        const double lim_hi = sizeof(T) == 4 ? 0x1p50 : 0x1p400;
+        const double lim_lo = sizeof(T) == 4 ? 0x1p-50 : 0x1p-400;
+        const bool risky = mx > 0.0 && (mx > lim_hi || mx < lim_lo || !(tot < 1e300));
+        if (risky) {
+          int e;
+          (void)__builtin_frexp(mx, &e);
+          ctl[0] = 1.0;
+          ctl[1] = __builtin_ldexp(1.0, -e);
+        } else {
+          ctl[0] = 0.0;
+          ctl[1] = 1.0;
+        }
+      }
+    }
+  }
+}
+
+// ===========================================================================
+// Dimension reductions over the tiled traversal.
+//   DIM 0 (per column, 1 x n_cols): each group of TPC lanes owns one column
+//     segment; the pair-sum over the segment goes to ws[ti * n_cols + j].
+//   DIM 1 (per row, n_rows x 1): each thread keeps V row accumulators across
+//     its passes; at the end of the tile they are folded across the CPP column
+//     passes through LDS and written to ws[tj * n_rows + i].
+// Partials are (hi, lo) pairs of the element type (float-float for fp32).
+// ===========================================================================
+template <typename T> struct Pair { T hi, lo; };
+
+template <class X, bool COMP, int V, int TS>
+struct Dim0Sink {
+  typedef typename X::T T;
+  typedef typename AccSel<T, COMP>::type Acc;
+  Acc g;
+  __device__ __forceinline__ void begin_tile() {}
+  __device__ __forceinline__ void elem(const coot_kargs& a, int q, bool in, const T* L) {
+    if (q == 0) g.init();
+    if (in) g.add(X::f(L, a.sc));
+  }
+  __device__ __forceinline__ void group(const coot_kargs& a, i64 i, i64 j, int jl, int lc, bool) {
+    constexpr int TPC = TS / V;
+    T h, l;
+    if constexpr (is_int_t<T>::v) {
+      h = group_sum<TPC, T>(g.s);
+      l = (T)0;
+    } else if constexpr (COMP) {
+      h = g.hi;
+      l = g.lo;
+      group_dw_sum<TPC, T>(h, l);
+    } else {
+      h = group_sum<TPC, T>(g.s);
+      l = (T)0;
+    }
+    if (lc == 0 && j < a.n_cols) {
+      const i64 ti = i / TS;
+      Pair<T> p;
+      p.hi = h;
+      p.lo = l;
+      ((Pair<T>*)a.ws)[ti * a.n_cols + j] = p;
+    }
+  }
+  __device__ __forceinline__ void end_tile(const coot_kargs&, i64, i64, i64, i64, int, int) {}
+};
+
+template <class X, bool COMP, int V, int TS>
+struct Dim1Sink {
+  typedef typename X::T T;
+  typedef typename AccSel<T, COMP>::type Acc;
+  Acc r[V];
+  __device__ __forceinline__ void begin_tile() {
+#pragma unroll
+    for (int q = 0; q < V; ++q) r[q].init();
+  }
+  __device__ __forceinline__ void elem(const coot_kargs& a, int q, bool in, const T* L) {
+    if (in) {
+#pragma unroll
+      for (int qq = 0; qq < V; ++qq)
+        if (qq == q) r[qq].add(X::f(L, a.sc));
+    }
+  }
+  __device__ __forceinline__ void group(const coot_kargs&, i64, i64, int, int, bool) {}
+  __device__ __forceinline__ void end_tile(const coot_kargs& a, i64, i64 tj, i64 i0, i64, int lr, int lc) {
+    constexpr int TPC = TS / V;
+    constexpr int CPP = 256 / TPC;
+    __shared__ Pair<T> red[CPP][TS];
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      Pair<T> p;
+      if constexpr (is_int_t<T>::v) {
+        p.hi = r[q].s;
+        p.lo = (T)0;
+      } else if constexpr (COMP) {
+        p.hi = r[q].hi;
+        p.lo = r[q].lo;
+      } else {
+        p.hi = r[q].s;
+        p.lo = (T)0;
+      }
+      red[lr][lc * V + q] = p;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < TS) {
+      const int il = threadIdx.x;
+      T h = red[0][il].hi, l = red[0][il].lo;
+      for (int k = 1; k < CPP; ++k) {
+        if constexpr (is_int_t<T>::v) {
+          h = op_add(h, red[k][il].hi);
+        } else if constexpr (COMP) {
+          dw_add<T>(h, l, red[k][il].hi, red[k][il].lo);
+        } else {
+          h = h + red[k][il].hi;
+        }
+      }
+      const i64 i = i0 + il;
+      if (i < a.n_rows) {
+        Pair<T> p;
+        p.hi = h;
+        p.lo = l;
+        ((Pair<T>*)a.ws)[tj * a.n_rows + i] = p;
+      }
+    }
+    __syncthreads();
+  }
+};
+
+template <class X, int DIM, bool COMP, int V, int TS>
+__device__ __forceinline__ void tiled_reduce_dim(const coot_kargs& a) {
+  if constexpr (DIM == 0) {
+    Dim0Sink<X, COMP, V, TS> s;
+    tiled_walk<X, V, TS>(a, s);
+  } else {
+    Dim1Sink<X, COMP, V, TS> s;
+    tiled_walk<X, V, TS>(a, s);
+  }
+}
+
+// Stage 2 of a dimension reduction: one thread per output element folds the
+// n_part tile partials in order.  n_out outputs, partial k of output o at
+// ws[k * n_out + o].
+template <typename T, bool COMP>
+__device__ __forceinline__ void dim_stage2(const coot_kargs& a, i64 n_out) {
+  const Pair<T>* ws = (const Pair<T>*)a.ws;
+  T* out = (T*)a.out;
+  for (i64 o = (i64)blockIdx.x * blockDim.x + threadIdx.x; o < n_out; o += (i64)gridDim.x * blockDim.x) {
+    T h = (T)0, l = (T)0;
+    for (i64 k = 0; k < a.n_part; ++k) {
+      const Pair<T> p = ws[k * n_out + o];
+      if constexpr (is_int_t<T>::v) {
+        h = op_add(h, p.hi);
+      } else if constexpr (COMP) {
+        dw_add<T>(h, l, p.hi, p.lo);
+      } else {
+        h = h + p.hi;
+      }
+    }
+    if constexpr (is_int_t<T>::v) {
+      out[o] = h;
+    } else {
+      out[o] = h + l;
+    }
+  }
+}
+
+}  // namespace coot

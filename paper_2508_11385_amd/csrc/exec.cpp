@@ -1,0 +1,435 @@
+// Execution: launch planning, fused evaluation, fused reductions, and the
+// unfused comparator (one kernel and one temporary per operator).
+#include <algorithm>
+#include <cstring>
+#include <unordered_map>
+
+#include "core.h"
+
+namespace coot {
+
+void fail(coot_status c, const std::string& msg) { throw Error(c, msg); }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(COOT_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int num_cus() {
+  static int cached_dev = -1, cached = 0;
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (dev != cached_dev) {
+    int n = 0;
+    hip_check(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+    cached = n > 0 ? n : 1;
+    cached_dev = dev;
+  }
+  return cached;
+}
+
+// ---- workspace and temporaries ------------------------------------------------
+namespace {
+struct WsKey {
+  hipStream_t s;
+  int which;
+  bool operator==(const WsKey& o) const { return s == o.s && which == o.which; }
+};
+struct WsHash {
+  size_t operator()(const WsKey& k) const { return std::hash<void*>()((void*)k.s) ^ (size_t)k.which; }
+};
+struct WsBuf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+std::unordered_map<WsKey, WsBuf, WsHash>& ws_map() {
+  static std::unordered_map<WsKey, WsBuf, WsHash> m;
+  return m;
+}
+std::map<std::pair<void*, size_t>, std::vector<void*>>& temp_pool() {
+  static std::map<std::pair<void*, size_t>, std::vector<void*>> m;
+  return m;
+}
+}  // namespace
+
+void* workspace(size_t bytes, hipStream_t s, int which) {
+  std::lock_guard<std::mutex> g(global_mutex());
+  WsBuf& b = ws_map()[{s, which}];
+  if (b.n >= bytes && b.p) return b.p;
+  size_t want = std::max<size_t>(bytes, 1 << 16);
+  if (b.p) {
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    hip_check(hipFree(b.p), "hipFree");
+    b.p = nullptr;
+    b.n = 0;
+  }
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    b.p = nullptr;
+    fail(COOT_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+  }
+  b.n = want;
+  return b.p;
+}
+
+void* temp_alloc(size_t bytes, hipStream_t s) {
+  std::lock_guard<std::mutex> g(global_mutex());
+  auto& v = temp_pool()[{(void*)s, bytes}];
+  if (!v.empty()) {
+    void* p = v.back();
+    v.pop_back();
+    return p;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess)
+    fail(COOT_ENOMEM, "temporary allocation of " + std::to_string(bytes) + " bytes failed");
+  return p;
+}
+
+// Stream-ordered reuse: a temporary handed back here is only given out again for
+// work queued later on the same stream.
+void temp_free(void* p, size_t bytes, hipStream_t s) {
+  std::lock_guard<std::mutex> g(global_mutex());
+  temp_pool()[{(void*)s, bytes}].push_back(p);
+}
+
+void launch(hipFunction_t f, unsigned grid, unsigned block, const KArgs& args, hipStream_t s) {
+  KArgs copy = args;
+  void* params[] = {&copy};
+  hip_check(hipModuleLaunchKernel(f, grid, 1, 1, block, 1, 1, 0, s, params, nullptr), "hipModuleLaunchKernel");
+  stats().launches += 1;
+}
+
+// ---- planning ------------------------------------------------------------------
+static int64_t ld_of(const coot_operand& o) { return o.ld ? o.ld : o.n_rows; }
+
+static bool contiguous(const coot_operand& o) { return ld_of(o) == o.n_rows || o.n_cols <= 1; }
+
+static bool aligned(const void* p, size_t bytes) { return ((uintptr_t)p % bytes) == 0; }
+
+static int default_vec(int dt) { return dt == COOT_F64 ? 2 : 4; }
+
+Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, int mode, int dim, bool comp,
+             const coot_launch_cfg* cfg) {
+  Request rq;
+  rq.mode = mode;
+  rq.dim = dim;
+  rq.comp = comp;
+  bool flat = e.n_p1 == 0 && !(mode == COOT_RED_SUM && dim >= 0);
+  for (auto& l : e.leaves)
+    if (!contiguous(ops[l.slot])) flat = false;
+  if (mode < 0 && out && !contiguous(*out)) flat = false;
+  rq.fam = flat ? FAM_FLAT : FAM_TILE;
+  rq.var.vec = cfg && cfg->vec ? cfg->vec : default_vec(e.dtype);
+  rq.var.ept = cfg && cfg->ept ? cfg->ept : 4;
+  if (rq.var.vec != 1 && rq.var.vec != 2 && rq.var.vec != 4) fail(COOT_EINVAL, "vec must be 1, 2 or 4");
+  if (rq.var.ept != 1 && rq.var.ept != 2 && rq.var.ept != 4 && rq.var.ept != 8) fail(COOT_EINVAL, "ept must be 1, 2, 4 or 8");
+  // tile edge: 64, or 32 when the LDS staging of transposed leaves would exceed 64 KiB
+  const size_t es = dtype_size(e.dtype);
+  int ts = 64;
+  if ((size_t)std::max(1, e.n_p1) * 64 * 65 * es > 65536) ts = 32;
+  rq.var.ts = ts;
+  if (rq.fam == FAM_TILE && rq.var.vec > ts / 4) rq.var.vec = ts / 4;
+  if (rq.fam == FAM_FLAT) rq.var.ts = 0;
+  if (rq.fam == FAM_TILE) rq.var.ept = 0;
+  return rq;
+}
+
+// Can the V-wide kernel run on these operands?  Every access must be aligned to
+// V elements: base addresses, leading dimensions and the contiguous extents.
+static bool vec_ok(const Expr& e, const Request& rq, const coot_operand* ops, const coot_operand* out, int64_t R,
+                   int64_t C) {
+  const int V = rq.var.vec;
+  if (V == 1) return true;
+  const size_t vb = V * dtype_size(e.dtype);
+  if (rq.fam == FAM_FLAT) {
+    for (auto& l : e.leaves)
+      if (!aligned(ops[l.slot].data, vb)) return false;
+    if (rq.mode < 0 && !aligned(out->data, vb)) return false;
+    return true;
+  }
+  for (auto& l : e.leaves) {
+    const coot_operand& o = ops[l.slot];
+    if (!aligned(o.data, vb) || ld_of(o) % V) return false;
+    if (l.parity == 0 && R % V) return false;
+    if (l.parity == 1 && C % V) return false;
+  }
+  if (R % V) return false;
+  if (rq.mode < 0 && (!aligned(out->data, vb) || ld_of(*out) % V)) return false;
+  return true;
+}
+
+static void fill_args(const Expr& e, const coot_operand* ops, const double* scalars, KArgs* a) {
+  std::memset(a, 0, sizeof *a);
+  for (size_t k = 0; k < e.slots.size(); ++k) {
+    a->leaf[k] = ops[k].data;
+    a->ld[k] = ld_of(ops[k]);
+  }
+  if (e.n_scalars && !scalars) fail(COOT_EINVAL, "scalars missing");
+  for (uint32_t k = 0; k < e.n_scalars; ++k) a->sc[k] = scalar_bits(scalars[k], e.dtype);
+}
+
+static void check_alias(const Expr& e, const coot_operand* ops, const coot_operand& out, size_t es) {
+  const int64_t oc = out.n_cols, orr = out.n_rows;
+  if (orr * oc == 0) return;
+  const char* ob = (const char*)out.data;
+  const char* oe = ob + (size_t)(ld_of(out) * (oc - 1) + orr) * es;
+  for (size_t k = 0; k < e.slots.size(); ++k) {
+    const coot_operand& o = ops[k];
+    if (o.n_rows * o.n_cols == 0) continue;
+    const char* b = (const char*)o.data;
+    const char* en = b + (size_t)(ld_of(o) * (o.n_cols - 1) + o.n_rows) * es;
+    if (en <= ob || oe <= b) continue;
+    bool identity = b == ob && ld_of(o) == ld_of(out) && o.n_rows == orr && o.n_cols == oc;
+    for (auto& l : e.leaves)
+      if (l.slot == k && l.parity) identity = false;
+    if (!identity) fail(COOT_EALIAS, "output overlaps operand " + std::to_string(k) + " with a different index map");
+  }
+}
+
+static unsigned flat_grid(int64_t n, int V, int E, int bs, int gm) {
+  const int64_t nv = std::max<int64_t>(1, (n + V - 1) / V);
+  const int64_t need = (nv + (int64_t)bs * E - 1) / ((int64_t)bs * E);
+  const int64_t cap = (int64_t)gm * num_cus();
+  return (unsigned)std::max<int64_t>(1, std::min(need, cap));
+}
+
+static unsigned tile_grid(int64_t R, int64_t C, int ts, int gm) {
+  const int64_t nt = ((R + ts - 1) / ts) * ((C + ts - 1) / ts);
+  const int64_t cap = (int64_t)gm * num_cus();
+  return (unsigned)std::max<int64_t>(1, std::min(nt, cap));
+}
+
+void eval_fused(Expr& e, const coot_operand* ops, const double* scalars, const coot_operand& out,
+                const coot_launch_cfg* cfg, hipStream_t s) {
+  check_operands(e, ops);
+  int64_t R = 0, C = 0;
+  infer_shape(e, ops, &R, &C);
+  if (out.dtype != e.dtype) fail(COOT_ETYPE, "output element type differs from the expression's");
+  if (out.n_rows != R || out.n_cols != C)
+    fail(COOT_ESHAPE, "output must be " + std::to_string(R) + "x" + std::to_string(C));
+  if (ld_of(out) < R || (!out.data && R * C)) fail(COOT_EINVAL, "bad output operand");
+  const size_t es = dtype_size(e.dtype);
+  check_alias(e, ops, out, es);
+  if (R * C == 0) return;
+  Request rq = plan(e, ops, &out, -1, -1, true, cfg);
+  auto m = get_module(e, rq, true);
+  KArgs a;
+  fill_args(e, ops, scalars, &a);
+  a.out = out.data;
+  a.out_ld = ld_of(out);
+  a.n_rows = R;
+  a.n_cols = C;
+  const bool v = vec_ok(e, rq, ops, &out, R, C);
+  const std::string& kn = (v || rq.var.vec == 1) ? m->names.stage1 : m->names.stage1_fallback;
+  hipFunction_t f = m->fn(kn);
+  const int waves = cfg && cfg->waves ? cfg->waves : 4;
+  if (rq.fam == FAM_FLAT) {
+    const int bs = 64 * waves;
+    const int gm = cfg && cfg->grid_mult ? cfg->grid_mult : 8;
+    launch(f, flat_grid(R * C, v ? rq.var.vec : 1, rq.var.ept, bs, gm), bs, a, s);
+  } else {
+    const int gm = cfg && cfg->grid_mult ? cfg->grid_mult : 16;
+    launch(f, tile_grid(R, C, rq.var.ts, gm), 256, a, s);
+  }
+}
+
+void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int kind, int dim, uint32_t flags,
+                  const coot_operand& out, const coot_launch_cfg* cfg, hipStream_t s) {
+  check_operands(e, ops);
+  int64_t R = 0, C = 0;
+  infer_shape(e, ops, &R, &C);
+  if (out.dtype != e.dtype) fail(COOT_ETYPE, "output element type differs from the expression's");
+  int mode = kind;
+  if (kind == COOT_RED_ACCU && e.root_schur) mode = COOT_RED_DOT;  // accu(x % y) is dot(x, y)
+  if (kind == COOT_RED_DOT && !e.root_schur) fail(COOT_EINVAL, "dot needs an expression whose root is a % b");
+  if (kind == COOT_RED_NORM && dtype_is_int(e.dtype)) fail(COOT_ETYPE, "norm of an integer expression");
+  if (kind == COOT_RED_SUM && dim != 0 && dim != 1) fail(COOT_EINVAL, "sum needs dim 0 or 1");
+  if (kind < COOT_RED_ACCU || kind > COOT_RED_NORM) fail(COOT_EINVAL, "unknown reduction");
+  int64_t n_out = 1;
+  if (kind == COOT_RED_SUM) {
+    n_out = dim == 0 ? C : R;
+    const bool ok = dim == 0 ? (out.n_rows == 1 && out.n_cols == C) : (out.n_rows == R && out.n_cols == 1);
+    if (!ok) fail(COOT_ESHAPE, dim == 0 ? "sum(X, 0) output must be 1 x n_cols" : "sum(X, 1) output must be n_rows x 1");
+    if (out.n_rows * out.n_cols > 1 && !contiguous(out)) fail(COOT_EINVAL, "reduction output must be contiguous");
+  } else {
+    if (out.n_rows * out.n_cols != 1) fail(COOT_ESHAPE, "a full reduction writes one element");
+  }
+  if (!out.data && n_out) fail(COOT_EINVAL, "NULL output");
+  if (n_out == 0) return;
+  const bool comp = !(flags & COOT_RF_PLAIN);
+  Request rq = plan(e, ops, nullptr, mode, kind == COOT_RED_SUM ? dim : -1, comp, cfg);
+  auto m = get_module(e, rq, true);
+  KArgs a;
+  fill_args(e, ops, scalars, &a);
+  a.out = out.data;
+  a.out_ld = ld_of(out);
+  a.n_rows = R;
+  a.n_cols = C;
+  const bool v = vec_ok(e, rq, ops, nullptr, R, C);
+  const std::string& kn = (v || rq.var.vec == 1) ? m->names.stage1 : m->names.stage1_fallback;
+  const size_t es = dtype_size(e.dtype);
+  const int waves = cfg && cfg->waves ? cfg->waves : 4;
+  if (kind == COOT_RED_SUM) {
+    const int ts = rq.var.ts;
+    const int64_t tr = (R + ts - 1) / ts, tc = (C + ts - 1) / ts;
+    a.n_part = dim == 0 ? tr : tc;
+    a.ws = workspace((size_t)std::max<int64_t>(1, a.n_part * n_out) * 2 * es, s, 0);
+    const int64_t nt = tr * tc;
+    if (nt > 0) launch(m->fn(kn), (unsigned)std::min<int64_t>(nt, 1 << 30), 256, a, s);
+    const unsigned g2 = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_out + 255) / 256, 4096));
+    launch(m->fn(m->names.stage2), g2, 256, a, s);
+    return;
+  }
+  unsigned grid;
+  unsigned block;
+  if (rq.fam == FAM_FLAT) {
+    block = 64 * waves;
+    const int gm = cfg && cfg->grid_mult ? cfg->grid_mult : 8;
+    grid = flat_grid(R * C, v ? rq.var.vec : 1, rq.var.ept, block, gm);
+  } else {
+    block = 256;
+    const int gm = cfg && cfg->grid_mult ? cfg->grid_mult : 8;
+    grid = tile_grid(R, C, rq.var.ts, gm);
+  }
+  a.n_part = grid;
+  a.ws = workspace((size_t)grid * 32, s, 0);
+  a.ws2 = workspace(64 + (size_t)grid * 32, s, 1);
+  launch(m->fn(kn), grid, block, a, s);
+  launch(m->fn(m->names.stage2), 1, 256, a, s);
+  if (mode == COOT_RED_NORM) {
+    // runs only when stage 2 found squares that could have overflowed or underflowed
+    launch(m->fn(m->names.stage1_rescale), grid, block, a, s);
+    launch(m->fn(m->names.stage2_rescale), 1, 256, a, s);
+  }
+}
+
+// ---- unfused comparator -------------------------------------------------------------
+// Each operator runs as its own kernel into a temporary (trans included: it is
+// materialised).  Sub-expressions are compiled through the same machinery.
+namespace {
+std::unordered_map<std::string, std::unique_ptr<Expr>>& sub_cache() {
+  static std::unordered_map<std::string, std::unique_ptr<Expr>> m;
+  return m;
+}
+
+Expr& sub_expr(const std::vector<coot_op>& ops, const std::vector<coot_slot_type>& slots, uint32_t n_sc) {
+  std::string k;
+  for (auto& o : ops) k += std::to_string(o.code) + "." + std::to_string(o.arg) + " ";
+  k += "|";
+  for (auto& sl : slots) k += std::to_string(sl.dtype) + "." + std::to_string(sl.kind) + " ";
+  k += "|" + std::to_string(n_sc);
+  std::lock_guard<std::mutex> g(global_mutex());
+  auto& m = sub_cache();
+  auto it = m.find(k);
+  if (it != m.end()) return *it->second;
+  auto e = analyse(ops.data(), (uint32_t)ops.size(), slots.data(), (uint32_t)slots.size(), n_sc, 0);
+  Expr& r = *e;
+  m[k] = std::move(e);
+  return r;
+}
+
+struct Val {
+  bool scalar = false;
+  uint32_t sidx = 0;
+  coot_operand op{};
+  bool temp = false;
+  size_t bytes = 0;
+};
+}  // namespace
+
+void eval_unfused(Expr& e, const coot_operand* ops, const double* scalars, const coot_operand& out,
+                  const coot_launch_cfg* cfg, hipStream_t s) {
+  check_operands(e, ops);
+  int64_t R = 0, C = 0;
+  infer_shape(e, ops, &R, &C);
+  if (out.n_rows != R || out.n_cols != C) fail(COOT_ESHAPE, "output has the wrong dimensions");
+  if (out.dtype != e.dtype) fail(COOT_ETYPE, "output element type differs from the expression's");
+  if (R * C == 0) return;
+  const size_t es = dtype_size(e.dtype);
+  std::vector<Val> st;
+  auto release = [&](Val& v) {
+    if (v.temp) temp_free(v.op.data, v.bytes, s);
+  };
+  const size_t n_ops = e.ops.size();
+  if (n_ops == 1) {  // a bare LOAD: a copy
+    eval_fused(e, ops, scalars, out, cfg, s);
+    return;
+  }
+  for (size_t i = 0; i < n_ops; ++i) {
+    const coot_op& o = e.ops[i];
+    if (o.code == COOT_OP_LOAD) {
+      Val v;
+      v.op = ops[o.arg];
+      if (!v.op.ld) v.op.ld = v.op.n_rows;
+      st.push_back(v);
+      continue;
+    }
+    if (o.code == COOT_OP_SCALAR) {
+      Val v;
+      v.scalar = true;
+      v.sidx = o.arg;
+      st.push_back(v);
+      continue;
+    }
+    const bool last = i + 1 == n_ops;
+    std::vector<Val> in;
+    const bool bin = o.code >= COOT_OP_ADD && o.code <= COOT_OP_DIV;
+    if (bin) {
+      Val b = st.back();
+      st.pop_back();
+      Val a = st.back();
+      st.pop_back();
+      in = {a, b};
+    } else {
+      in = {st.back()};
+      st.pop_back();
+    }
+    if (o.code == COOT_OP_TRANS && in[0].scalar) {
+      st.push_back(in[0]);
+      continue;
+    }
+    bool all_scalar = true;
+    for (auto& v : in) all_scalar = all_scalar && v.scalar;
+    if (all_scalar) fail(COOT_EUNSUPPORTED, "unfused evaluation of a scalar-only sub-expression");
+    std::vector<coot_op> sops;
+    std::vector<coot_slot_type> sslots;
+    std::vector<coot_operand> sopnds;
+    std::vector<double> ssc;
+    int64_t r = 0, c = 0;
+    for (auto& v : in) {
+      if (v.scalar) {
+        sops.push_back({COOT_OP_SCALAR, (uint32_t)ssc.size()});
+        ssc.push_back(scalars[v.sidx]);
+      } else {
+        sops.push_back({COOT_OP_LOAD, (uint32_t)sslots.size()});
+        sslots.push_back({v.op.dtype, v.op.kind});
+        sopnds.push_back(v.op);
+        r = v.op.n_rows;
+        c = v.op.n_cols;
+      }
+    }
+    sops.push_back({o.code, 0});
+    if (o.code == COOT_OP_TRANS) std::swap(r, c);
+    Expr& se = sub_expr(sops, sslots, (uint32_t)ssc.size());
+    Val res;
+    if (last) {
+      res.op = out;
+    } else {
+      res.temp = true;
+      res.bytes = (size_t)r * c * es;
+      res.op.data = temp_alloc(res.bytes, s);
+      res.op.n_rows = r;
+      res.op.n_cols = c;
+      res.op.ld = r;
+      res.op.dtype = e.dtype;
+      res.op.kind = c == 1 ? COOT_COL : (r == 1 ? COOT_ROW : COOT_MAT);
+      if (r == 1 && c == 1) res.op.kind = COOT_MAT;
+    }
+    // operand kinds of the temporaries must match the slots just declared
+    for (size_t k = 0; k < sopnds.size(); ++k) sslots[k].kind = sopnds[k].kind;
+    eval_fused(se, sopnds.data(), ssc.data(), res.op, cfg, s);
+    for (auto& v : in) release(v);
+    st.push_back(res);
+  }
+}
+
+}  // namespace coot

@@ -1,0 +1,207 @@
+// Runtime compilation and the kernel cache.
+//
+// Section 4 of the paper: the kernel set is compiled at run time for the device
+// found and cached, so the cost is paid once.  Here every (expression
+// signature, request) gets its own module: hipRTC compiles the generated source
+// for gfx950, the code object is kept in memory (process-wide map keyed by a
+// 128-bit hash of source + options + compiler version) and on disk
+// (COOT_CACHE_DIR, default ~/.cache/coot; a header with magic, key and checksum
+// guards every file, and a bad file is simply recompiled).
+#include <hip/hiprtc.h>
+#include <sys/stat.h>
+#include <unistd.h>
+
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <unordered_map>
+
+#include "core.h"
+
+namespace coot {
+
+Stats& stats() {
+  static Stats s;
+  return s;
+}
+std::mutex& global_mutex() {
+  static std::mutex m;
+  return m;
+}
+
+static uint64_t fnv1a(const std::string& s, uint64_t seed) {
+  uint64_t h = 1469598103934665603ull ^ seed;
+  for (unsigned char c : s) {
+    h ^= c;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+std::string hex128(const std::string& text) {
+  char buf[40];
+  std::snprintf(buf, sizeof buf, "%016llx%016llx", (unsigned long long)fnv1a(text, 0),
+                (unsigned long long)fnv1a(text, 0x9e3779b97f4a7c15ull));
+  return buf;
+}
+
+static const std::vector<std::string>& rtc_options() {
+  static const std::vector<std::string> o = {
+      "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
+      "-fhip-fp32-correctly-rounded-divide-sqrt", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+  return o;
+}
+
+static std::string rtc_version() {
+  int ma = 0, mi = 0;
+  hiprtcVersion(&ma, &mi);
+  return std::to_string(ma) + "." + std::to_string(mi);
+}
+
+std::string compile_source(const std::string& src, const std::string& name_hint, std::vector<char>* code) {
+  hiprtcProgram prog;
+  const char* hdr = device_header().c_str();
+  const char* hdr_name = "coot_dev.h";
+  if (hiprtcCreateProgram(&prog, src.c_str(), (name_hint + ".hip").c_str(), 1, &hdr, &hdr_name) != HIPRTC_SUCCESS)
+    fail(COOT_ECOMPILE, "hiprtcCreateProgram failed");
+  std::vector<const char*> opts;
+  for (auto& s : rtc_options()) opts.push_back(s.c_str());
+  if (const char* extra = std::getenv("COOT_HIPRTC_EXTRA")) opts.push_back(extra);
+  const hiprtcResult r = hiprtcCompileProgram(prog, (int)opts.size(), opts.data());
+  size_t log_size = 0;
+  hiprtcGetProgramLogSize(prog, &log_size);
+  std::string log(log_size, '\0');
+  if (log_size) hiprtcGetProgramLog(prog, &log[0]);
+  if (r != HIPRTC_SUCCESS) {
+    hiprtcDestroyProgram(&prog);
+    fail(COOT_ECOMPILE, "hipRTC compilation failed for " + name_hint + ":\n" + log);
+  }
+  size_t n = 0;
+  hiprtcGetCodeSize(prog, &n);
+  code->resize(n);
+  hiprtcGetCode(prog, code->data());
+  hiprtcDestroyProgram(&prog);
+  return log;
+}
+
+// ---- disk cache ------------------------------------------------------------
+static std::string cache_dir() {
+  if (const char* d = std::getenv("COOT_CACHE_DIR")) return d;
+  const char* home = std::getenv("HOME");
+  return std::string(home ? home : "/tmp") + "/.cache/coot";
+}
+
+static void mkdirs(const std::string& p) {
+  std::string cur;
+  for (size_t i = 0; i < p.size(); ++i) {
+    cur += p[i];
+    if (p[i] == '/' && cur.size() > 1) mkdir(cur.c_str(), 0755);
+  }
+  mkdir(p.c_str(), 0755);
+}
+
+struct DiskHeader {
+  char magic[8];
+  char key[32];
+  uint64_t size;
+  uint64_t check;
+};
+
+static bool disk_load(const std::string& key, std::vector<char>* code) {
+  if (std::getenv("COOT_NO_DISK_CACHE")) return false;
+  std::ifstream f(cache_dir() + "/" + key + ".co", std::ios::binary);
+  if (!f) return false;
+  DiskHeader h;
+  if (!f.read(reinterpret_cast<char*>(&h), sizeof h)) return false;
+  if (std::memcmp(h.magic, "COOTCO1", 8) != 0 || std::memcmp(h.key, key.data(), 32) != 0) return false;
+  if (h.size == 0 || h.size > (64u << 20)) return false;
+  std::vector<char> buf(h.size);
+  if (!f.read(buf.data(), (std::streamsize)h.size)) return false;
+  if (fnv1a(std::string(buf.data(), buf.size()), 7) != h.check) return false;
+  code->swap(buf);
+  return true;
+}
+
+static void disk_store(const std::string& key, const std::vector<char>& code) {
+  if (std::getenv("COOT_NO_DISK_CACHE")) return;
+  const std::string dir = cache_dir();
+  mkdirs(dir);
+  DiskHeader h;
+  std::memcpy(h.magic, "COOTCO1", 8);
+  std::memcpy(h.key, key.data(), 32);
+  h.size = code.size();
+  h.check = fnv1a(std::string(code.data(), code.size()), 7);
+  const std::string tmp = dir + "/" + key + ".co.tmp" + std::to_string(getpid());
+  {
+    std::ofstream f(tmp, std::ios::binary);
+    if (!f) return;
+    f.write(reinterpret_cast<const char*>(&h), sizeof h);
+    f.write(code.data(), (std::streamsize)code.size());
+    if (!f) return;
+  }
+  std::rename(tmp.c_str(), (dir + "/" + key + ".co").c_str());
+}
+
+// ---- module cache ------------------------------------------------------------
+hipFunction_t Module::fn(const std::string& name) {
+  auto it = fns.find(name);
+  if (it != fns.end()) return it->second;
+  if (!loaded) fail(COOT_EHIP, "module not loaded on a device");
+  hipFunction_t f = nullptr;
+  hip_check(hipModuleGetFunction(&f, mod, name.c_str()), "hipModuleGetFunction");
+  fns[name] = f;
+  return f;
+}
+
+static std::unordered_map<std::string, std::shared_ptr<Module>>& module_map() {
+  static std::unordered_map<std::string, std::shared_ptr<Module>> m;
+  return m;
+}
+
+std::shared_ptr<Module> get_module(Expr& e, const Request& rq, bool load) {
+  const std::string rk = rq.key();
+  {
+    std::lock_guard<std::mutex> g(e.mu);
+    auto it = e.reqs.find(rk);
+    if (it != e.reqs.end() && (it->second->loaded || !load)) return it->second;
+  }
+  std::lock_guard<std::mutex> g(global_mutex());
+  KernelNames names;
+  const std::string sig = hex128(e.canon);
+  const std::string src = generate(e, rq, sig, &names);
+  std::string opt_text;
+  for (auto& o : rtc_options()) opt_text += o + " ";
+  const std::string key = hex128(src + "\n" + opt_text + rtc_version());
+  auto& mm = module_map();
+  std::shared_ptr<Module> m;
+  auto it = mm.find(key);
+  if (it != mm.end()) {
+    m = it->second;
+    stats().mem_hits += 1;
+  } else {
+    m = std::make_shared<Module>();
+    m->names = names;
+    if (disk_load(key, &m->code)) {
+      stats().disk_hits += 1;
+    } else {
+      auto t0 = std::chrono::steady_clock::now();
+      compile_source(src, names.stage1, &m->code);
+      auto t1 = std::chrono::steady_clock::now();
+      stats().compiles += 1;
+      stats().compile_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
+      disk_store(key, m->code);
+    }
+    mm[key] = m;
+  }
+  if (load && !m->loaded) {
+    hip_check(hipModuleLoadData(&m->mod, m->code.data()), "hipModuleLoadData");
+    m->loaded = true;
+  }
+  std::lock_guard<std::mutex> g2(e.mu);
+  e.reqs[rk] = m;
+  return m;
+}
+
+}  // namespace coot

@@ -1,0 +1,288 @@
+"""Armadillo-flavoured lazy expressions on top of libcoot (expression capture).
+
+Section 3 of the paper: functions and operators return expression objects, not
+matrices; nothing is computed until the whole expression is assigned (delayed
+evaluation).  Here operator overloads build a small tree; `eval` (assignment),
+`+=`, and the closing reductions flatten it to the postfix list of the C ABI and
+issue ONE fused library call.
+
+Storage: a column-major n_rows x n_cols matrix lives in a torch tensor on the
+HIP device whose memory holds the columns one after another (the tensor is kept
+as the logical (n_rows, n_cols) view with strides (1, n_rows)).  PyTorch is used
+for device memory and the current stream only; every element of every result is
+computed by libcoot's kernels.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _coot as cc
+
+_TORCH = {"f32": torch.float32, "f64": torch.float64, "u32": torch.int32, "s32": torch.int32}
+_NP = {"f32": np.float32, "f64": np.float64, "u32": np.uint32, "s32": np.int32}
+_KIND = {"mat": cc.COOT_MAT, "col": cc.COOT_COL, "row": cc.COOT_ROW}
+
+
+class Expr:
+    """A lazy expression node."""
+
+    # element-wise binary (eGlue)
+    def __add__(self, o):
+        return _bin("add", self, o)
+
+    def __radd__(self, o):
+        return _bin("add", o, self)
+
+    def __sub__(self, o):
+        return _bin("sub", self, o)
+
+    def __rsub__(self, o):
+        return _bin("sub", o, self)
+
+    def __mod__(self, o):                     # Schur product, as in Armadillo
+        return _bin("schur", self, o)
+
+    def __truediv__(self, o):
+        return _bin("div", self, o)
+
+    def __rtruediv__(self, o):
+        return _bin("div", o, self)
+
+    def __mul__(self, o):
+        if isinstance(o, Expr):
+            raise NotImplementedError("matrix product is outside the fused element-wise path; use % for Schur")
+        return _bin("schur", self, o)
+
+    def __rmul__(self, o):
+        if isinstance(o, Expr):
+            raise NotImplementedError("matrix product is outside the fused element-wise path")
+        return _bin("schur", o, self)
+
+    def __neg__(self):
+        return Node("neg", [self])
+
+    def t(self):
+        return trans(self)
+
+
+class Node(Expr):
+    __slots__ = ("op", "kids")
+
+    def __init__(self, op, kids):
+        self.op = op
+        self.kids = kids
+
+
+class Scalar(Expr):
+    __slots__ = ("value",)
+
+    def __init__(self, value):
+        self.value = float(value)
+
+
+def _lift(x):
+    if isinstance(x, Expr):
+        return x
+    if isinstance(x, (int, float, np.integer, np.floating)):
+        return Scalar(x)
+    raise TypeError(f"cannot use {type(x).__name__} in an expression")
+
+
+def _bin(op, a, b):
+    return Node(op, [_lift(a), _lift(b)])
+
+
+class Mat(Expr):
+    """Device matrix (Mat<eT>), column vector (Col<eT>) or row vector (Row<eT>)."""
+
+    def __init__(self, tensor: torch.Tensor, dtype: str, kind: str = "mat"):
+        if tensor.dim() != 2:
+            raise ValueError("a Mat wraps the 2-D logical view of its storage")
+        r, c = tensor.shape
+        if r * c > 1 and not (tensor.stride(0) == 1 and tensor.stride(1) >= max(1, r)):
+            raise ValueError("storage must be column-major (strides (1, ld))")
+        self.tensor = tensor
+        self.dtype = dtype
+        self.kind = kind
+        self.n_rows, self.n_cols = int(r), int(c)
+        self.ld = int(tensor.stride(1)) if c > 1 else max(1, int(r))
+
+    # ---- construction ---------------------------------------------------------------
+    @staticmethod
+    def empty(n_rows, n_cols, dtype="f32", kind="mat", device="cuda"):
+        store = torch.empty((n_cols, n_rows), dtype=_TORCH[dtype], device=device)
+        return Mat(store.t(), dtype, kind)
+
+    @staticmethod
+    def from_numpy(a: np.ndarray, dtype: str | None = None, kind: str | None = None, device="cuda"):
+        a = np.asarray(a)
+        if a.ndim == 1:
+            a = a.reshape(-1, 1)
+            kind = kind or "col"
+        dtype = dtype or {np.dtype(np.float32): "f32", np.dtype(np.float64): "f64",
+                          np.dtype(np.uint32): "u32", np.dtype(np.int32): "s32"}[a.dtype]
+        a = a.astype(_NP[dtype], copy=False)
+        if dtype == "u32":
+            a = a.view(np.int32)
+        cm = np.ascontiguousarray(a.T)                 # columns one after another
+        store = torch.from_numpy(cm).to(device)
+        return Mat(store.t(), dtype, kind or "mat")
+
+    def numpy(self) -> np.ndarray:
+        a = self.tensor.detach().cpu().numpy()
+        if self.dtype == "u32":
+            a = a.view(np.uint32)
+        return np.asarray(a)
+
+    def operand(self) -> cc.coot_operand:
+        return cc.coot_operand(self.tensor.data_ptr(), self.n_rows, self.n_cols, self.ld,
+                               cc.DTYPE_CODE[self.dtype], _KIND[self.kind])
+
+    def __iadd__(self, other):                       # B += 3*A : axpy, evaluated in place
+        eval(self + other, out=self)
+        return self
+
+    def __isub__(self, other):
+        eval(self - other, out=self)
+        return self
+
+
+# ---- element-wise functions (eOp) and transpose (Op<op_trans>) -----------------------
+def trans(x):
+    return Node("trans", [_lift(x)])
+
+
+def exp(x):
+    return Node("exp", [_lift(x)])
+
+
+def log(x):
+    return Node("log", [_lift(x)])
+
+
+def sqrt(x):
+    return Node("sqrt", [_lift(x)])
+
+
+def square(x):
+    return Node("square", [_lift(x)])
+
+
+def abs(x):  # noqa: A001 — the Armadillo name
+    return Node("abs", [_lift(x)])
+
+
+# ---- flattening -----------------------------------------------------------------------
+class Flat:
+    __slots__ = ("postfix", "mats", "scalars", "dtype")
+
+    def __init__(self, postfix, mats, scalars, dtype):
+        self.postfix = postfix
+        self.mats = mats
+        self.scalars = scalars
+        self.dtype = dtype
+
+
+def flatten(e: Expr) -> Flat:
+    postfix, mats, scalars = [], [], []
+    ids = {}
+    stack = [(e, False)]
+    while stack:
+        node, done = stack.pop()
+        if isinstance(node, Mat):
+            k = ids.get(id(node))
+            if k is None:
+                k = ids[id(node)] = len(mats)
+                mats.append(node)
+            postfix.append(("load", k))
+        elif isinstance(node, Scalar):
+            postfix.append(("scalar", len(scalars)))
+            scalars.append(node.value)
+        elif done:
+            postfix.append((node.op,))
+        else:
+            stack.append((node, True))
+            for kid in reversed(node.kids):
+                stack.append((kid, False))
+    dts = {m.dtype for m in mats}
+    if len(dts) > 1:
+        raise cc.CootError(cc.COOT_ETYPE, "operands of one expression must share an element type")
+    return Flat(postfix, mats, scalars, dts.pop() if dts else "f32")
+
+
+_handles: dict = {}
+
+
+def compiled(flat: Flat, flags: int = 0) -> int:
+    """Library handle for the flattened expression (compiled once per signature and flags)."""
+    slots = tuple((cc.DTYPE_CODE[m.dtype], _KIND[m.kind]) for m in flat.mats)
+    key = (tuple(flat.postfix), slots, len(flat.scalars), flags)
+    h = _handles.get(key)
+    if h is None:
+        h = cc.coot_expr_compile(flat.postfix, slots, len(flat.scalars), flags)
+        _handles[key] = h
+    return h
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def eval(e: Expr, out: Mat | None = None, cfg=None, unfused: bool = False) -> Mat:  # noqa: A001
+    """Assignment: evaluate the whole expression in one fused pass (or the unfused comparator)."""
+    if isinstance(e, (int, float)):
+        raise TypeError("nothing to evaluate")
+    flat = flatten(_lift(e))
+    h = compiled(flat, cc.COOT_CF_UNFUSED if unfused else 0)
+    ops = [m.operand() for m in flat.mats]
+    if out is None:
+        r, c = cc.coot_expr_out_shape(h, ops)
+        kind = "col" if c == 1 and r != 1 else ("row" if r == 1 and c != 1 else "mat")
+        out = Mat.empty(r, c, flat.dtype, kind, device=flat.mats[0].tensor.device)
+    cc.coot_expr_eval(h, ops, flat.scalars, out.operand(), cfg, _stream())
+    return out
+
+
+def _reduce(e, kind, dim, plain, out_shape, cfg, unfused):
+    flat = flatten(_lift(e))
+    h = compiled(flat, cc.COOT_CF_UNFUSED if unfused else 0)
+    ops = [m.operand() for m in flat.mats]
+    r, c = cc.coot_expr_out_shape(h, ops)
+    orr, oc = out_shape(r, c)
+    okind = "mat" if orr == oc == 1 else ("row" if orr == 1 else "col")
+    out = Mat.empty(orr, oc, flat.dtype, okind, device=flat.mats[0].tensor.device)
+    cc.coot_reduce(h, ops, flat.scalars, kind, dim, cc.COOT_RF_PLAIN if plain else 0, out.operand(), cfg,
+                   _stream())
+    return out
+
+
+def accu(e, plain=False, cfg=None, unfused=False) -> Mat:
+    """Sum of all elements, as a 1x1 device Mat (Fig. 1: sum(A) of a vector)."""
+    return _reduce(e, cc.COOT_RED_ACCU, -1, plain, lambda r, c: (1, 1), cfg, unfused)
+
+
+def sum(e, dim=None, plain=False, cfg=None, unfused=False) -> Mat:  # noqa: A001
+    """sum(X, 0): per column (1 x n_cols); sum(X, 1): per row (n_rows x 1).
+    Without dim: a vector gives its total, a matrix sums per column (Armadillo's convention)."""
+    if dim is None:
+        flat = flatten(_lift(e))
+        r, c = cc.coot_expr_out_shape(compiled(flat), [m.operand() for m in flat.mats])
+        if r == 1 or c == 1:
+            return accu(e, plain, cfg, unfused)
+        dim = 0
+    shape = (lambda r, c: (1, c)) if dim == 0 else (lambda r, c: (r, 1))
+    return _reduce(e, cc.COOT_RED_SUM, dim, plain, shape, cfg, unfused)
+
+
+def dot(a, b, plain=False, cfg=None, unfused=False) -> Mat:
+    return _reduce(_bin("schur", a, b), cc.COOT_RED_DOT, -1, plain, lambda r, c: (1, 1), cfg, unfused)
+
+
+def norm(e, plain=False, cfg=None, unfused=False) -> Mat:
+    """2-norm of a vector / Frobenius norm of a matrix expression."""
+    return _reduce(e, cc.COOT_RED_NORM, -1, plain, lambda r, c: (1, 1), cfg, unfused)
+
+
+def init(device: int = 0) -> None:
+    cc.coot_init(device)

@@ -1,0 +1,322 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances: integers bit-exact; floating element-wise results within 1 ulp of
+the per-operator rounded oracle (0 ulp expected for + - * / sqrt abs neg, trans);
+fp32 reductions within 1e-6 relative error of the exact sum, fp64 within 1e-12.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import elementwise as ew
+from oracle import reduce as rd
+from tests.exact import ulp_distance
+
+pytestmark = pytest.mark.gpu
+
+Z_POST = [("scalar", 0), ("load", 0), ("schur",), ("load", 1), ("load", 2), ("schur",), ("add",), ("load", 3),
+          ("trans",), ("sub",)]
+W_POST = [("load", 0), ("exp",), ("scalar", 0), ("load", 1), ("abs",), ("add",), ("div",)]
+REL = {"f32": 1e-6, "f64": 1e-12}
+
+
+@pytest.fixture(scope="module")
+def coot():
+    import torch
+    import paper_2508_11385_amd as coot
+    coot.init(0)
+    torch.cuda.synchronize()
+    return coot
+
+
+def up(coot, a, kind=None):
+    return coot.Mat.from_numpy(a, kind=kind)
+
+
+def _z(coot, A, B, C, D):
+    return 2.0 * A + B % C - coot.trans(D)
+
+
+def _w(coot, A, B):
+    return coot.exp(A) / (1.0 + coot.abs(B))
+
+
+def _check_rel(got, exact_vals, scale_vals, tol, what):
+    worst = 0.0
+    for g, ref, sc in zip(got, exact_vals, scale_vals):
+        e = rd.rel_err(float(g), ref, sc)
+        worst = max(worst, e)
+    assert worst <= tol, f"{what}: worst relative error {worst:.3e} > {tol:.0e}"
+    return worst
+
+
+SHAPES = [(1, 1), (3, 5), (64, 64), (67, 45), (130, 257), (256, 64), (1000, 3), (5, 1000)]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_Z_and_W_elementwise(coot, dtype, shape):
+    r, c = shape
+    A, B, C, D = synth.matrix_inputs(n_rows=r, n_cols=c, dtype=dtype)
+    gA, gB, gC, gD = (up(coot, x) for x in (A, B, C, D))
+    Z = coot.eval(_z(coot, gA, gB, gC, gD)).numpy()
+    W = coot.eval(_w(coot, gA, gB)).numpy()
+    Zo = ew.evaluate(Z_POST, [A, B, C, D], [2.0], dtype)
+    Wo = ew.evaluate(W_POST, [A, B], [1.0], dtype)
+    assert Z.shape == Zo.shape == (r, c)
+    assert np.max(ulp_distance(Z, Zo)) == 0, "Z uses only correctly rounded operators: 0 ulp expected"
+    dW = ulp_distance(W, Wo)
+    assert np.max(dW) <= 1, f"W: {int(np.sum(dW > 1))} elements beyond 1 ulp"
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("shape", [(1, 1), (67, 45), (130, 257), (1000, 3), (3, 1000), (256, 128)])
+def test_sum_dims_fused_and_materialised(coot, dtype, shape):
+    r, c = shape
+    A, B, C, D = synth.matrix_inputs(n_rows=r, n_cols=c, dtype=dtype)
+    gA, gB, gC, gD = (up(coot, x) for x in (A, B, C, D))
+    Zo = ew.evaluate(Z_POST, [A, B, C, D], [2.0], dtype)
+    gZ = up(coot, Zo)
+    for dim in (0, 1):
+        ex = rd.sum_dim(Zo, dim, dtype)
+        scale = [rd.sum_abs(v) for v in (Zo.T if dim == 0 else Zo)]
+        fused = coot.sum(_z(coot, gA, gB, gC, gD), dim).numpy().ravel()
+        mat = coot.sum(gZ, dim).numpy().ravel()
+        assert fused.size == (c if dim == 0 else r)
+        _check_rel(fused, ex, scale, REL[dtype], f"fused sum dim {dim}")
+        _check_rel(mat, ex, scale, REL[dtype], f"materialised sum dim {dim}")
+
+
+def test_axpy_then_dot_workload(coot):
+    """y <- 2.5*x + y in place, then accu(x % y) with the updated y (n = 1,000,000)."""
+    x, y = synth.axpy_inputs()
+    gx, gy = up(coot, x, "col"), up(coot, y, "col")
+    gy += 2.5 * gx
+    y_new = ew.evaluate([("scalar", 0), ("load", 0), ("schur",), ("load", 1), ("add",)], [x, y], [2.5], "f32")
+    assert np.max(ulp_distance(gy.numpy(), y_new)) == 0
+    got = float(coot.accu(gx % gy).numpy()[0, 0])
+    ref = rd.dot(x, y_new, "f32")
+    err = rd.rel_err(got, ref, rd.to_float(rd.exact_dot(np.abs(x), np.abs(y_new))))
+    assert err <= 1e-6, err
+    got_dot = float(coot.dot(gx, gy).numpy()[0, 0])
+    assert got_dot == got
+    plain = float(coot.accu(gx % gy, plain=True).numpy()[0, 0])
+    assert rd.rel_err(plain, ref, 1.0) < 1e-3          # the comparator is merely less accurate
+
+
+def test_contraction_is_off(coot):
+    """2.5*x + y is rounded per operator on the device (no FMA contraction)."""
+    x = np.full((256, 1), 0.1, np.float32)
+    p = np.float32(np.float64(2.5) * np.float64(np.float32(0.1)))
+    y = np.full((256, 1), np.float32(-p) + np.float32(2.0 ** -30), np.float32)
+    gx, gy = up(coot, x, "col"), up(coot, y, "col")
+    out = coot.eval(2.5 * gx + gy).numpy()
+    want = ew.evaluate([("scalar", 0), ("load", 0), ("schur",), ("load", 1), ("add",)], [x, y], [2.5], "f32")
+    assert np.array_equal(out, want)
+
+
+@pytest.mark.parametrize("shape", [(1000, 700), (67, 45), (8, 8)])
+def test_integer_expressions(coot, shape):
+    r, c = shape
+    A, B, C = synth.int_inputs(which="u32", n_rows=r, n_cols=c)
+    got = coot.eval((up(coot, A) + up(coot, B)) % up(coot, C)).numpy()
+    want = ew.evaluate([("load", 0), ("load", 1), ("add",), ("load", 2), ("schur",)], [A, B, C], [], "u32")
+    assert np.array_equal(got, want)
+    for which in ("s32_full", "s32_small"):
+        A, B = synth.int_inputs(which=which, n_rows=r, n_cols=c)
+        got = coot.eval(up(coot, A) - 3 * up(coot, B)).numpy()
+        want = ew.evaluate([("load", 0), ("scalar", 0), ("load", 1), ("schur",), ("sub",)], [A, B], [3.0], "s32")
+        assert np.array_equal(got, want)
+        # integer reductions wrap mod 2^32 and are bit-exact
+        gA = up(coot, A)
+        assert int(coot.accu(gA).numpy()[0, 0]) == rd.accu(A, "s32")
+        assert [int(v) for v in coot.sum(gA, 0).numpy().ravel()] == rd.sum_dim(A, 0, "s32")
+        assert [int(v) for v in coot.sum(gA, 1).numpy().ravel()] == rd.sum_dim(A, 1, "s32")
+
+
+def test_accu_and_norm_lognormal(coot):
+    x = synth.lognormal_signed(synth.rng_for(2, 9), 1 << 22).reshape(-1, 1)
+    gx = up(coot, x, "col")
+    s_ref = rd.accu(x, "f32")
+    sc = rd.sum_abs(x)
+    got = float(coot.accu(gx).numpy()[0, 0])
+    assert rd.rel_err(got, s_ref, sc) <= 1e-6
+    n_ref = rd.norm(x, "f32")
+    got_n = float(coot.norm(gx).numpy()[0, 0])
+    assert abs(got_n - n_ref) / n_ref <= 1e-6
+    plain = float(coot.accu(gx, plain=True).numpy()[0, 0])
+    print(f"\naccu rel err: compensated {rd.rel_err(got, s_ref, sc):.2e}, plain {rd.rel_err(plain, s_ref, sc):.2e}")
+
+
+def test_norm_rescaling_and_closed_forms(coot):
+    big = np.array([[3 * 2.0 ** 100], [4 * 2.0 ** 100]], np.float32)
+    small = np.array([[3 * 2.0 ** -100], [4 * 2.0 ** -100]], np.float32)
+    assert float(coot.norm(up(coot, big, "col")).numpy()[0, 0]) == 5 * 2.0 ** 100
+    assert float(coot.norm(up(coot, small, "col")).numpy()[0, 0]) == 5 * 2.0 ** -100
+    ones = up(coot, np.ones((1 << 20, 1), np.float32), "col")
+    assert float(coot.accu(ones).numpy()[0, 0]) == float(1 << 20)
+    v = np.concatenate([[np.float32(2 ** 24)], np.ones(1 << 20, np.float32)]).reshape(-1, 1)
+    assert float(coot.accu(up(coot, v, "col")).numpy()[0, 0]) == 2 ** 24 + 2 ** 20
+    x = synth.uniform(synth.rng_for(5, 5), (4096, 1), "f32")
+    gx = up(coot, x, "col")
+    nrm = float(coot.norm(gx).numpy()[0, 0])
+    d = float(coot.dot(gx, gx).numpy()[0, 0])
+    assert abs(nrm * nrm - d) / d < 1e-6
+
+
+def _tree_case(coot, spec, ops, dtype):
+    got = coot.eval(_build(coot, spec, [up(coot, o) for o in ops])).numpy()
+    want = ew.evaluate(spec.postfix, ops, spec.scalars, dtype)
+    return got, want
+
+
+def _build(coot, spec, mats):
+    st = []
+    for it in spec.postfix:
+        op = it[0]
+        if op == "load":
+            st.append(mats[it[1]])
+        elif op == "scalar":
+            st.append(coot.Scalar(spec.scalars[it[1]]))
+        elif op in ("add", "sub", "schur", "div"):
+            b, a = st.pop(), st.pop()
+            st.append(coot.Node(op, [a, b]))
+        else:
+            st.append(coot.Node(op, [st.pop()]))
+    return st[0]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "u32", "s32"])
+def test_random_trees(coot, dtype):
+    g = synth.rng_for(123, {"f32": 0, "u32": 1, "s32": 2}[dtype])
+    n_exp_1ulp = 0
+    for trial in range(60):
+        r, c = int(g.integers(1, 150)), int(g.integers(1, 150))
+        spec = synth.random_tree(g, int(g.integers(1, 7)), int(g.integers(2, 6)), r, c, dtype)
+        ops = synth.operands_for(spec, g)
+        got, want = _tree_case(coot, spec, ops, dtype)
+        if dtype == "f32":
+            d = ulp_distance(got, want)
+            has_exp = any(p[0] == "exp" for p in spec.postfix)
+            limit = 1 if has_exp else 0
+            assert np.max(d) <= limit, (spec.postfix, r, c, np.max(d))
+            n_exp_1ulp += int(np.sum(d == 1))
+        else:
+            assert np.array_equal(got, want), spec.postfix
+
+
+def test_fused_equals_unfused_bitwise(coot):
+    A, B, C, D = synth.matrix_inputs(n_rows=300, n_cols=170)
+    gA, gB, gC, gD = (up(coot, x) for x in (A, B, C, D))
+    for e in (_z(coot, gA, gB, gC, gD), _w(coot, gA, gB)):
+        f = coot.eval(e).numpy()
+        u = coot.eval(e, unfused=True).numpy()
+        assert np.array_equal(f.view(np.uint32), u.view(np.uint32))
+    s_f = coot.sum(_z(coot, gA, gB, gC, gD), 1).numpy()
+    s_u = coot.sum(_z(coot, gA, gB, gC, gD), 1, unfused=True).numpy()
+    assert np.array_equal(s_f, s_u)
+
+
+def test_determinism(coot):
+    x = synth.lognormal_signed(synth.rng_for(2, 10), 3_000_001).reshape(-1, 1)
+    gx = up(coot, x, "col")
+    a = [coot.accu(gx).numpy()[0, 0] for _ in range(3)]
+    assert a[0] == a[1] == a[2]
+    A, B, C, D = synth.matrix_inputs(n_rows=513, n_cols=257)
+    gs = [up(coot, m) for m in (A, B, C, D)]
+    s = [coot.sum(_z(coot, *gs), 1).numpy() for _ in range(2)]
+    assert np.array_equal(s[0], s[1])
+
+
+def test_edge_cases(coot):
+    import paper_2508_11385_amd._coot as cc
+    E = up(coot, np.zeros((0, 5), np.float32))
+    assert coot.eval(E + 1.0).numpy().shape == (0, 5)
+    assert float(coot.accu(E).numpy()[0, 0]) == 0.0
+    assert np.all(coot.sum(E, 0).numpy() == 0)
+    A = up(coot, np.ones((4, 6), np.float32))
+    B = up(coot, np.ones((6, 4), np.float32))
+    with pytest.raises(cc.CootError) as e:
+        coot.eval(A + B)
+    assert e.value.status == cc.COOT_ESHAPE
+    S = up(coot, np.ones((5, 5), np.float32))
+    with pytest.raises(cc.CootError) as e:
+        coot.eval(coot.trans(S) + 1.0, out=S)       # reads S transposed while writing it
+    assert e.value.status == cc.COOT_EALIAS
+    with pytest.raises(cc.CootError) as e:
+        coot.eval(A + A, out=coot.Mat.empty(6, 4))
+    assert e.value.status == cc.COOT_ESHAPE
+    # a strided (submatrix-like) operand goes through the tiled path
+    import torch
+    big = torch.arange(40 * 30, dtype=torch.float32, device="cuda").reshape(30, 40).t()   # 40 x 30, ld 40
+    sub = coot.Mat(big[:33, :], "f32")                                                   # 33 x 30, ld 40
+    got = coot.eval(sub * 2.0).numpy()
+    want = big[:33, :].cpu().numpy() * 2
+    assert np.array_equal(got, want)
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads: sampled outputs the oracle computes one by one, plus
+# properties that hold at any size.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_full_size_matrix_workload(coot, dtype):
+    A, B, C, D = synth.matrix_inputs(4096, dtype)
+    gA, gB, gC, gD = (up(coot, x) for x in (A, B, C, D))
+    Zg = coot.eval(_z(coot, gA, gB, gC, gD))
+    Wg = coot.eval(_w(coot, gA, gB))
+    g = np.random.default_rng(7)
+    rows = g.integers(0, 4096, 50_000)
+    cols = g.integers(0, 4096, 50_000)
+    Z = Zg.numpy()
+    W = Wg.numpy()
+    zo = ew.evaluate_at(Z_POST, [A, B, C, D], [2.0], dtype, rows, cols)
+    wo = ew.evaluate_at(W_POST, [A, B], [1.0], dtype, rows, cols)
+    assert np.max(ulp_distance(Z[rows, cols], zo)) == 0
+    assert np.max(ulp_distance(W[rows, cols], wo)) <= 1
+    s0 = coot.sum(_z(coot, gA, gB, gC, gD), 0).numpy().ravel()
+    s1 = coot.sum(_z(coot, gA, gB, gC, gD), 1).numpy().ravel()
+    jj = g.integers(0, 4096, 24)
+    ii = g.integers(0, 4096, 24)
+    for j in jj:
+        col = ew.evaluate_at(Z_POST, [A, B, C, D], [2.0], dtype, np.arange(4096), np.full(4096, j))
+        assert rd.rel_err(float(s0[j]), rd.exact_sum(col), rd.sum_abs(col)) <= REL[dtype]
+    for i in ii:
+        row = ew.evaluate_at(Z_POST, [A, B, C, D], [2.0], dtype, np.full(4096, i), np.arange(4096))
+        assert rd.rel_err(float(s1[i]), rd.exact_sum(row), rd.sum_abs(row)) <= REL[dtype]
+
+
+def test_full_size_integer_workload(coot):
+    A, B, C = synth.int_inputs(8192, "u32")
+    got = coot.eval((up(coot, A) + up(coot, B)) % up(coot, C)).numpy()
+    g = np.random.default_rng(8)
+    rows, cols = g.integers(0, 8192, 100_000), g.integers(0, 8192, 100_000)
+    post = [("load", 0), ("load", 1), ("add",), ("load", 2), ("schur",)]
+    assert np.array_equal(got[rows, cols], ew.evaluate_at(post, [A, B, C], [], "u32", rows, cols))
+    del got
+    for which in ("s32_full", "s32_small"):
+        A, B = synth.int_inputs(8192, which)
+        got = coot.eval(up(coot, A) - 3 * up(coot, B)).numpy()
+        post = [("load", 0), ("scalar", 0), ("load", 1), ("schur",), ("sub",)]
+        assert np.array_equal(got[rows, cols], ew.evaluate_at(post, [A, B], [3.0], "s32", rows, cols))
+
+
+def test_full_size_hard_reductions(coot):
+    x = synth.hard_reduction_inputs()
+    gx = up(coot, x, "col")
+    got = float(coot.accu(gx).numpy()[0, 0])
+    got_n = float(coot.norm(gx).numpy()[0, 0])
+    plain = float(coot.accu(gx, plain=True).numpy()[0, 0])
+    plain_n = float(coot.norm(gx, plain=True).numpy()[0, 0])
+    ref = rd.accu(x, "f32")
+    sc = rd.sum_abs(x)
+    nref = rd.norm(x, "f32")
+    e_acc = rd.rel_err(got, ref, sc)
+    e_nrm = abs(got_n - nref) / nref
+    print(f"\n2^28 lognormal: accu rel err {e_acc:.2e} (plain {rd.rel_err(plain, ref, sc):.2e}), "
+          f"norm rel err {e_nrm:.2e} (plain {abs(plain_n - nref) / nref:.2e}), "
+          f"kappa {sc / abs(float(ref)):.2f}")
+    assert e_acc <= 1e-6 and e_nrm <= 1e-6
