@@ -33,7 +33,7 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=5)
-    p.add_argument("--cpu-cols", type=int, default=1024, help="columns of the problem the CPU oracle is timed on")
+    p.add_argument("--cpu-cols", type=int, default=4096, help="columns of the problem the CPU oracle is timed on")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_tile_Z_4096_f32.json"))
     return p.parse_args()

@@ -28,14 +28,22 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+DEVICE_HEADERS = ("coot_dev.h", "coot_exp.h", "exp_tables.h")
+
+
 def _embed_header() -> str:
-    src = os.path.join(CSRC, "device", "coot_dev.h")
-    text = open(src).read()
+    """Write the device headers into a C++ file as raw-string literals (name, text pairs)."""
     delim = "COOTDEV"
-    assert ")" + delim + '"' not in text
+    parts = []
+    for name in DEVICE_HEADERS:
+        text = open(os.path.join(CSRC, "device", name)).read()
+        assert ")" + delim + '"' not in text
+        parts.append('  {"' + name + '", R"' + delim + "(" + text + ")" + delim + '"},')
+    body = ("namespace coot {\nstruct EmbeddedHeader { const char* name; const char* text; };\n"
+            "extern const EmbeddedHeader kDeviceHeaders[];\nextern const int kNumDeviceHeaders;\n"
+            "const EmbeddedHeader kDeviceHeaders[] = {\n" + "\n".join(parts) + "\n};\n"
+            "const int kNumDeviceHeaders = " + str(len(parts)) + ";\n}\n")
     out = os.path.join(BUILD, "coot_dev_embed.cpp")
-    body = ('namespace coot {\nextern const char* const kDeviceHeader;\n'
-            'const char* const kDeviceHeader = R"' + delim + "(" + text + ")" + delim + '";\n}\n')
     if not os.path.exists(out) or open(out).read() != body:
         with open(out, "w") as f:
             f.write(body)

@@ -100,7 +100,7 @@ struct KernelNames {
 };
 
 std::string generate(const Expr& e, const Request& rq, const std::string& hash_hint, KernelNames* names);
-const std::string& device_header();
+const std::vector<std::pair<std::string, std::string>>& device_headers();
 
 // JIT + caches -----------------------------------------------------------------
 struct Module {

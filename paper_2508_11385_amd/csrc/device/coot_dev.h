@@ -24,6 +24,8 @@
 #pragma once
 #pragma clang fp contract(off)
 
+#include "coot_exp.h"
+
 typedef unsigned int u32;
 typedef int s32;
 typedef long long i64;
@@ -74,7 +76,7 @@ __device__ __forceinline__ float op_neg(float a) { return -a; }
 __device__ __forceinline__ float op_abs(float a) { return __builtin_fabsf(a); }
 __device__ __forceinline__ float op_sqrt(float a) { return __builtin_sqrtf(a); }
 __device__ __forceinline__ float op_square(float a) { return a * a; }
-__device__ __forceinline__ float op_exp(float a) { return expf(a); }
+__device__ __forceinline__ float op_exp(float a) { return exp_rn<float>(a); }  // correctly rounded (coot_exp.h)
 __device__ __forceinline__ float op_log(float a) { return logf(a); }
 
 __device__ __forceinline__ double op_add(double a, double b) { return a + b; }
@@ -85,7 +87,7 @@ __device__ __forceinline__ double op_neg(double a) { return -a; }
 __device__ __forceinline__ double op_abs(double a) { return __builtin_fabs(a); }
 __device__ __forceinline__ double op_sqrt(double a) { return __builtin_sqrt(a); }
 __device__ __forceinline__ double op_square(double a) { return a * a; }
-__device__ __forceinline__ double op_exp(double a) { return exp(a); }
+__device__ __forceinline__ double op_exp(double a) { return exp_rn<double>(a); }
 __device__ __forceinline__ double op_log(double a) { return log(a); }
 
 __device__ __forceinline__ u32 op_add(u32 a, u32 b) { return a + b; }
@@ -767,7 +769,7 @@ struct Dim0Sink {
       Pair<T> p;
       p.hi = h;
       p.lo = l;
-      ((Pair<T>*)a.ws)[ti * a.n_cols + j] = p;
+      ((Pair<T>*)a.ws)[j * a.n_part + ti] = p;
     }
   }
   __device__ __forceinline__ void end_tile(const coot_kargs&, i64, i64, i64, i64, int, int) {}
@@ -827,7 +829,7 @@ struct Dim1Sink {
         Pair<T> p;
         p.hi = h;
         p.lo = l;
-        ((Pair<T>*)a.ws)[tj * a.n_rows + i] = p;
+        ((Pair<T>*)a.ws)[i * a.n_part + tj] = p;
       }
     }
     __syncthreads();
@@ -845,17 +847,20 @@ __device__ __forceinline__ void tiled_reduce_dim(const coot_kargs& a) {
   }
 }
 
-// Stage 2 of a dimension reduction: one thread per output element folds the
-// n_part tile partials in order.  n_out outputs, partial k of output o at
-// ws[k * n_out + o].
+// Stage 2 of a dimension reduction: one wavefront per output element.  The
+// n_part partials of output o are contiguous (ws[o * n_part + k]); lane l folds
+// k = l, l + 64, ... in order, then the lanes are combined by a fixed butterfly,
+// so the result does not depend on timing.
 template <typename T, bool COMP>
 __device__ __forceinline__ void dim_stage2(const coot_kargs& a, i64 n_out) {
   const Pair<T>* ws = (const Pair<T>*)a.ws;
   T* out = (T*)a.out;
-  for (i64 o = (i64)blockIdx.x * blockDim.x + threadIdx.x; o < n_out; o += (i64)gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int wpb = blockDim.x >> 6;
+  for (i64 o = (i64)blockIdx.x * wpb + (threadIdx.x >> 6); o < n_out; o += (i64)gridDim.x * wpb) {
     T h = (T)0, l = (T)0;
-    for (i64 k = 0; k < a.n_part; ++k) {
-      const Pair<T> p = ws[k * n_out + o];
+    for (i64 k = lane; k < a.n_part; k += 64) {
+      const Pair<T> p = ws[o * a.n_part + k];
       if constexpr (is_int_t<T>::v) {
         h = op_add(h, p.hi);
       } else if constexpr (COMP) {
@@ -865,9 +870,18 @@ __device__ __forceinline__ void dim_stage2(const coot_kargs& a, i64 n_out) {
       }
     }
     if constexpr (is_int_t<T>::v) {
-      out[o] = h;
+      h = wave_sum<T>(h);
+    } else if constexpr (COMP) {
+      wave_dw_sum<T>(h, l);
     } else {
-      out[o] = h + l;
+      h = wave_sum<T>(h);
+    }
+    if (lane == 0) {
+      if constexpr (is_int_t<T>::v) {
+        out[o] = h;
+      } else {
+        out[o] = h + l;
+      }
     }
   }
 }

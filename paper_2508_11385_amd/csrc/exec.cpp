@@ -99,7 +99,7 @@ void launch(hipFunction_t f, unsigned grid, unsigned block, const KArgs& args, h
 }
 
 // ---- planning ------------------------------------------------------------------
-static int64_t ld_of(const coot_operand& o) { return o.ld ? o.ld : o.n_rows; }
+static int64_t ld_of(const coot_operand& o) { return o.ld ? o.ld : (o.n_rows > 0 ? o.n_rows : 1); }
 
 static bool contiguous(const coot_operand& o) { return ld_of(o) == o.n_rows || o.n_cols <= 1; }
 
@@ -275,7 +275,7 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
     a.ws = workspace((size_t)std::max<int64_t>(1, a.n_part * n_out) * 2 * es, s, 0);
     const int64_t nt = tr * tc;
     if (nt > 0) launch(m->fn(kn), (unsigned)std::min<int64_t>(nt, 1 << 30), 256, a, s);
-    const unsigned g2 = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_out + 255) / 256, 4096));
+    const unsigned g2 = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_out + 3) / 4, 65536));
     launch(m->fn(m->names.stage2), g2, 256, a, s);
     return;
   }

@@ -136,7 +136,7 @@ void check_operands(const Expr& e, const coot_operand* operands) {
     if (o.kind == COOT_COL && o.n_cols != 1) fail(COOT_ESHAPE, "a Col operand must have one column");
     if (o.kind == COOT_ROW && o.n_rows != 1) fail(COOT_ESHAPE, "a Row operand must have one row");
     const int64_t ld = o.ld ? o.ld : o.n_rows;
-    if (ld < o.n_rows || ld < 1) fail(COOT_EINVAL, "leading dimension smaller than the row count");
+    if (ld < o.n_rows) fail(COOT_EINVAL, "leading dimension smaller than the row count");
     if (!o.data && o.n_rows * o.n_cols > 0) fail(COOT_EINVAL, "NULL operand data");
   }
 }

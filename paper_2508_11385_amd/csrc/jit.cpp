@@ -62,9 +62,13 @@ static std::string rtc_version() {
 
 std::string compile_source(const std::string& src, const std::string& name_hint, std::vector<char>* code) {
   hiprtcProgram prog;
-  const char* hdr = device_header().c_str();
-  const char* hdr_name = "coot_dev.h";
-  if (hiprtcCreateProgram(&prog, src.c_str(), (name_hint + ".hip").c_str(), 1, &hdr, &hdr_name) != HIPRTC_SUCCESS)
+  std::vector<const char*> hdrs, hdr_names;
+  for (auto& h : device_headers()) {
+    hdr_names.push_back(h.first.c_str());
+    hdrs.push_back(h.second.c_str());
+  }
+  if (hiprtcCreateProgram(&prog, src.c_str(), (name_hint + ".hip").c_str(), (int)hdrs.size(), hdrs.data(),
+                          hdr_names.data()) != HIPRTC_SUCCESS)
     fail(COOT_ECOMPILE, "hiprtcCreateProgram failed");
   std::vector<const char*> opts;
   for (auto& s : rtc_options()) opts.push_back(s.c_str());
@@ -173,7 +177,9 @@ std::shared_ptr<Module> get_module(Expr& e, const Request& rq, bool load) {
   const std::string src = generate(e, rq, sig, &names);
   std::string opt_text;
   for (auto& o : rtc_options()) opt_text += o + " ";
-  const std::string key = hex128(src + "\n" + opt_text + rtc_version());
+  std::string hdr_text;
+  for (auto& h : device_headers()) hdr_text += h.second;
+  const std::string key = hex128(src + "\n" + opt_text + rtc_version() + hex128(hdr_text));
   auto& mm = module_map();
   std::shared_ptr<Module> m;
   auto it = mm.find(key);

@@ -99,14 +99,18 @@ class Mat(Expr):
     def __init__(self, tensor: torch.Tensor, dtype: str, kind: str = "mat"):
         if tensor.dim() != 2:
             raise ValueError("a Mat wraps the 2-D logical view of its storage")
-        r, c = tensor.shape
-        if r * c > 1 and not (tensor.stride(0) == 1 and tensor.stride(1) >= max(1, r)):
-            raise ValueError("storage must be column-major (strides (1, ld))")
+        r, c = (int(v) for v in tensor.shape)
+        s0, s1 = tensor.stride()
+        # a stride along a dimension of extent 1 (or of an empty matrix) carries no meaning
+        if r > 1 and c > 0 and s0 != 1:
+            raise ValueError("storage must be column-major (row stride 1)")
+        if c > 1 and r > 0 and s1 < r:
+            raise ValueError("storage must be column-major (column stride >= n_rows)")
         self.tensor = tensor
         self.dtype = dtype
         self.kind = kind
-        self.n_rows, self.n_cols = int(r), int(c)
-        self.ld = int(tensor.stride(1)) if c > 1 else max(1, int(r))
+        self.n_rows, self.n_cols = r, c
+        self.ld = int(s1) if (c > 1 and r > 0) else max(1, r)
 
     # ---- construction ---------------------------------------------------------------
     @staticmethod

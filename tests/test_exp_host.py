@@ -1,0 +1,67 @@
+"""The kernels' exponential (csrc/device/coot_exp.h) compiled for the host with
+g++ and compared with the oracle's correctly rounded exp on a large sample
+(binary32 and binary64, edges included).  The GPU parity tests check the device
+build of the same code; this test pins its arithmetic without a GPU."""
+import ctypes
+import os
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import elementwise as ew
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+DEV = os.path.join(ROOT, "paper_2508_11385_amd", "csrc", "device")
+
+SRC = r"""
+#define __host__
+#define __device__
+#define __forceinline__ inline
+#include "coot_exp.h"
+extern "C" void expf_n(const float* x, float* y, long n) { for (long i = 0; i < n; ++i) y[i] = coot::exp_cr<float>(x[i]); }
+extern "C" void exp_n(const double* x, double* y, long n) { for (long i = 0; i < n; ++i) y[i] = coot::exp_cr<double>(x[i]); }
+"""
+
+
+@pytest.fixture(scope="module")
+def lib():
+    gxx = shutil.which("g++")
+    if not gxx:
+        pytest.skip("g++ not available")
+    d = tempfile.mkdtemp()
+    src = os.path.join(d, "e.cpp")
+    so = os.path.join(d, "e.so")
+    open(src, "w").write(SRC)
+    subprocess.run([gxx, "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared", "-I", DEV, src, "-o", so],
+                   check=True)
+    L = ctypes.CDLL(so)
+    L.expf_n.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long]
+    L.exp_n.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long]
+    return L
+
+
+def test_binary32_sample(lib):
+    rng = np.random.default_rng(31)
+    bits = rng.integers(0, 1 << 32, size=1 << 20, dtype=np.uint64).astype(np.uint32)
+    x = np.concatenate([bits.view(np.float32), rng.uniform(-104, 89, 1 << 18).astype(np.float32),
+                        np.array([0, -0.0, 88.72283, 88.72284, 88.7228394, -87.33655, -103.27893, -103.97208,
+                                  -103.972084, -104, 1e-8, -1e-8, np.inf, -np.inf, np.nan], np.float32)])
+    y = np.empty_like(x)
+    lib.expf_n(x.ctypes.data, y.ctypes.data, x.size)
+    want = ew.exp_rounded(x, "f32")
+    both_nan = np.isnan(y) & np.isnan(want)
+    assert np.all((y.view(np.uint32) == want.view(np.uint32)) | both_nan)
+
+
+def test_binary64_sample(lib):
+    rng = np.random.default_rng(32)
+    x = np.concatenate([rng.uniform(-1, 1, 1 << 17), rng.uniform(-746, 710, 1 << 17), rng.uniform(-1e-3, 1e-3, 1 << 14),
+                        np.array([0.0, 709.782712893384, 709.7827128933841, -745.1332191019411, -745.1332191019412,
+                                  -708.396418532264, np.inf, -np.inf])])
+    y = np.empty_like(x)
+    lib.exp_n(x.ctypes.data, y.ctypes.data, x.size)
+    want = ew.exp_rounded(x, "f64")
+    assert np.array_equal(y, want)
