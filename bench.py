@@ -36,6 +36,8 @@ def parse():
     p.add_argument("--cpu-cols", type=int, default=4096, help="columns of the problem the CPU oracle is timed on")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_tile_Z_4096_f32.json"))
+    p.add_argument("--profile-kernels", action="store_true",
+                   help="run the copy probe and each kernel of one step 3 times, print their names, exit")
     return p.parse_args()
 
 
@@ -83,6 +85,45 @@ def main():
     fused = handles(0)
     unfused = handles(cc.COOT_CF_UNFUSED)
 
+    # copy probe: out = A through the flat family, 64 MiB read + 64 MiB written
+    copy_flat = coot.flatten(gA + 0.0)
+    copy_flat.postfix = [("load", 0)]
+    copy_flat.scalars = []
+    hcopy = coot.frontend.compiled(copy_flat)
+    copy_out = coot.Mat.empty(N, N, "f32")
+    cops, cout = [gA.operand()], copy_out.operand()
+
+    def copy():
+        cc.coot_expr_eval(hcopy, cops, [], cout, None, stream)
+
+    if args.profile_kernels:
+        for _ in range(3):
+            copy()
+        for _ in range(3):
+            step(*fused)
+        torch.cuda.synchronize()
+        names = {"copy": cc.coot_expr_kernel_name(hcopy), "Z": cc.coot_expr_kernel_name(fused[0]),
+                 "W": cc.coot_expr_kernel_name(fused[1]),
+                 "sumZ0": cc.coot_expr_kernel_name(fused[0], cc.COOT_RED_SUM, 0),
+                 "sumZ1": cc.coot_expr_kernel_name(fused[0], cc.COOT_RED_SUM, 1)}
+        print(json.dumps({"profiled_kernels": names, "copy_bytes": 2 * MIB64, "Z_bytes": 5 * MIB64,
+                          "launches_each": 3}), flush=True)
+        return
+
+    for _ in range(3):
+        copy()
+    torch.cuda.synchronize()
+    cev = []
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        copy()
+        e1.record()
+        cev.append((e0, e1))
+    torch.cuda.synchronize()
+    copy_ms = sorted(a.elapsed_time(b) for a, b in cev)[len(cev) // 2]
+    copy_gbs = 2 * MIB64 / (copy_ms * 1e-3) / 1e9
+
     def run(h, steps, warmup, z_events=None):
         for _ in range(warmup):
             step(*h)
@@ -111,12 +152,7 @@ def main():
 
     value = bytes_step / t_fused / 1e9
     z_gbs = 5 * MIB64 / (z_ms * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        try:
-            traffic = json.load(open(args.traffic_json)).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = measured_traffic(args.traffic_json, cc.coot_expr_kernel_name(fused[0]))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -139,6 +175,8 @@ def main():
                                "fp32 4096x4096 column-major",
                    "n_rows": N, "n_cols": N, "bytes_per_step": bytes_step},
         "pct_of_peak": round(100 * value / PEAK_HBM_GBS, 1),
+        "copy_probe_gbs": round(copy_gbs, 1),
+        "pct_of_copy_probe": round(100 * value / copy_gbs, 1),
         "unfused_ms_per_step": round(t_unfused * 1e3, 4),
         "speedup_vs_unfused": round(t_unfused / t_fused, 2),
         "roofline": {"bound": "hbm", "kernel": cc.coot_expr_kernel_name(fused[0]),
@@ -148,6 +186,32 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the device headers and the code generator (what decides the kernel's traffic)."""
+    import hashlib
+    h = hashlib.sha256()
+    dev = os.path.join(ROOT, "paper_2508_11385_amd", "csrc", "device")
+    for f in sorted(os.listdir(dev)):
+        if f.endswith(".h"):
+            h.update(open(os.path.join(dev, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "paper_2508_11385_amd", "csrc", "codegen.cpp"), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(path, kernel):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary, or None when the
+    kernel or its sources changed since the counters were taken."""
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+    except ValueError:
+        return None
+    if t.get("kernel") != kernel or t.get("source_sha256") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
 
 
 def cpu_baseline(A, B, C, D, ncols):
