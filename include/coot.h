@@ -198,6 +198,51 @@ void coot_expr_release(coot_expr* e);
  * bytes including the terminator.  Errors: COOT_EINVAL. */
 coot_status coot_expr_kernel_name(coot_expr* e, int32_t mode, int32_t dim, char* buf, size_t cap);
 
+/* ---- batches: many small independent expressions in one launch ----------
+ * Section 4 of the paper notes that GPUs need enough parallel work and are
+ * ill-suited to small matrices; a batch fills the device with thousands of small
+ * expressions at once.  Every expression is cut into TS x TS output tiles; one
+ * persistent kernel walks the list of all tiles and interprets each
+ * expression's register bytecode; the launch is captured into a HIP graph.
+ * f32 or f64 only (one type per batch).  Transposed leaves are staged through LDS.
+ *
+ * coot_batch_create
+ *   exprs[n]            compiled expressions (borrowed: they may be released after this call)
+ *   operands[n][...]    each expression's device operands (n_slots of it)
+ *   scalars[n][...]     each expression's scalars (host, copied)
+ *   outs[n]             caller-allocated device outputs with the inferred dims
+ *   cfg                 NULL = default (tile 32 x 32, vectorised where aligned,
+ *                       8 workgroups per CU); else waves 1 / 4 / 16 selects tiles of
+ *                       16 / 32 / 64, vec = 1 forbids 128-bit accesses, grid_mult
+ *                       sets workgroups per CU
+ *   stream              unused at creation (descriptors are uploaded synchronously)
+ * All operand and output buffers must stay allocated, at the same addresses, for
+ * the life of the batch: their addresses are baked into the descriptors.
+ * Errors: COOT_EINVAL, COOT_ESHAPE, COOT_ETYPE, COOT_EALIAS, COOT_EUNSUPPORTED
+ * (integer types, more than 12 leaves, more than 8 registers), COOT_ENOMEM, COOT_EHIP. */
+coot_status coot_batch_create(uint32_t n, coot_expr* const* exprs, const coot_operand* const* operands,
+                              const double* const* scalars, const coot_operand* outs,
+                              const coot_launch_cfg* cfg, void* stream, coot_batch** out);
+
+/* Replay the captured graph on `stream` (one launch for the whole batch). */
+coot_status coot_batch_launch(coot_batch* b, void* stream);
+
+/* Comparator: the same kernel launched once per expression on `stream`. */
+coot_status coot_batch_launch_each(coot_batch* b, void* stream);
+
+/* Autotune the batch launch on `stream` (synchronises it): times every tile size
+ * (16, 32, 64), grid multiplier (2, 4, 8, 16) and vector width (128-bit where
+ * aligned, or scalar), median of 5 launches each; keeps the fastest and
+ * re-captures the graph.  best / best_us may be NULL. */
+coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, float* best_us);
+
+/* info[0] expressions, [1] tiles, [2] algorithmic bytes (each distinct operand
+ * read once + outputs written once), [3] tile edge, [4] grid, [5] expressions on
+ * the 128-bit path. */
+coot_status coot_batch_info(const coot_batch* b, int64_t info[6]);
+
+void coot_batch_release(coot_batch* b);
+
 /* Counters since process start: out[0] compiles, out[1] memory-cache hits,
  * out[2] disk-cache hits, out[3] launches, out[4] total compile milliseconds. */
 void coot_stats(double out[5]);

@@ -6,5 +6,5 @@ norm, eval).  Importing this package loads libcoot.so and fails if it is not
 built — there is no CPU fallback.
 """
 from . import _coot  # noqa: F401
-from .frontend import (Expr, Mat, Node, Scalar, abs, accu, dot, eval, exp, flatten, init, log, norm,  # noqa: F401
+from .frontend import (Batch, Expr, Mat, Node, Scalar, abs, accu, dot, eval, exp, flatten, init, log, norm,  # noqa: F401
                        sqrt, square, sum, trans)

@@ -76,6 +76,14 @@ _sig = {
     "coot_last_error": (C.c_char_p, []),
     "coot_debug_codegen": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_uint32, C.c_int32, C.c_int32, C.c_int32,
                                      C.c_int32, C.c_int32, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "coot_batch_create": (C.c_int, [C.c_uint32, C.POINTER(_P), C.POINTER(C.POINTER(coot_operand)),
+                                    C.POINTER(C.POINTER(C.c_double)), C.POINTER(coot_operand),
+                                    C.POINTER(coot_launch_cfg), _P, C.POINTER(_P)]),
+    "coot_batch_launch": (C.c_int, [_P, _P]),
+    "coot_batch_launch_each": (C.c_int, [_P, _P]),
+    "coot_batch_tune": (C.c_int, [_P, _P, C.POINTER(coot_launch_cfg), C.POINTER(C.c_float)]),
+    "coot_batch_info": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+    "coot_batch_release": (None, [_P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(lib, _name)
@@ -172,3 +180,43 @@ def coot_debug_codegen(h: int, mode: int, dim: int, rflags: int, fam: int, vec: 
     n = C.c_size_t()
     _check(lib.coot_debug_codegen(h, mode, dim, rflags, fam, vec, ept, ts, int(compile), buf, 1 << 18, C.byref(n)))
     return buf.value.decode(), n.value
+
+
+# ---- batches ---------------------------------------------------------------------------
+
+def coot_batch_create(handles, operand_lists, scalar_lists, outs, cfg=None, stream: int = 0) -> int:
+    n = len(handles)
+    hs = (_P * max(1, n))(*handles)
+    op_arrays = [_arr(coot_operand, ops) for ops in operand_lists]
+    sc_arrays = [_arr(C.c_double, sc) for sc in scalar_lists]
+    opp = (C.POINTER(coot_operand) * max(1, n))(*[C.cast(a, C.POINTER(coot_operand)) for a in op_arrays])
+    scp = (C.POINTER(C.c_double) * max(1, n))(*[C.cast(a, C.POINTER(C.c_double)) for a in sc_arrays])
+    outa = _arr(coot_operand, outs)
+    b = _P()
+    _check(lib.coot_batch_create(n, hs, opp, scp, outa, _cfg(cfg), stream, C.byref(b)))
+    return b.value
+
+
+def coot_batch_launch(b: int, stream: int = 0) -> None:
+    _check(lib.coot_batch_launch(b, stream))
+
+
+def coot_batch_launch_each(b: int, stream: int = 0) -> None:
+    _check(lib.coot_batch_launch_each(b, stream))
+
+
+def coot_batch_tune(b: int, stream: int = 0):
+    best = coot_launch_cfg()
+    us = C.c_float()
+    _check(lib.coot_batch_tune(b, stream, C.byref(best), C.byref(us)))
+    return (best.vec, best.ept, best.waves, best.grid_mult), us.value
+
+
+def coot_batch_info(b: int) -> dict:
+    a = (C.c_int64 * 6)()
+    _check(lib.coot_batch_info(b, a))
+    return {"n_exprs": a[0], "n_tiles": a[1], "bytes": a[2], "tile": a[3], "grid": a[4], "vec4_exprs": a[5]}
+
+
+def coot_batch_release(b: int) -> None:
+    lib.coot_batch_release(b)

@@ -6,33 +6,12 @@
 
 using namespace coot;
 
-struct coot_expr {
-  std::unique_ptr<Expr> e;
-};
-
-namespace {
-thread_local std::string g_err;
-
-coot_status guard_status(coot_status s, const std::string& m) {
-  g_err = m;
+namespace coot {
+std::string& last_error() {
+  static thread_local std::string s;
   return s;
 }
-
-template <typename F>
-coot_status guarded(F&& f) {
-  try {
-    g_err.clear();
-    f();
-    return COOT_OK;
-  } catch (const Error& e) {
-    return guard_status(e.code, e.what());
-  } catch (const std::bad_alloc&) {
-    return guard_status(COOT_ENOMEM, "host allocation failed");
-  } catch (const std::exception& e) {
-    return guard_status(COOT_EINVAL, e.what());
-  }
-}
-}  // namespace
+}  // namespace coot
 
 extern "C" {
 
@@ -180,7 +159,7 @@ void coot_stats(double out[5]) {
   out[4] = stats().compile_ms;
 }
 
-const char* coot_last_error(void) { return g_err.c_str(); }
+const char* coot_last_error(void) { return last_error().c_str(); }
 
 // Diagnostic: the generated source for a request, optionally compiled with
 // hipRTC (no device needed).  mode -1 = eval; fam 0 flat / 1 tiled.

@@ -1,0 +1,422 @@
+// Batched evaluation: many small independent expressions in one persistent
+// launch, captured once into a HIP graph and replayed.
+//
+// Each expression's analysed IR (leaves with their transpose parity) becomes
+// register bytecode: the tree is emitted in Sethi-Ullman order (the operand that
+// needs more registers first), so registers behave as a stack of depth
+// need(root) <= 8.  Every expression is cut into TS x TS output tiles; the tile
+// list holds (expression, tile) pairs and a fixed grid walks it round-robin.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <memory>
+
+#include "batch_abi.h"
+#include "core.h"
+
+extern "C" hipError_t coot_batch_launch_kernel(int dtype, int ts, unsigned grid, const void* ex, const void* tiles,
+                                              int t_begin, int t_end, const void* code, const void* scal,
+                                              hipStream_t s);
+
+using namespace coot;
+using coot::batch::BatchExpr;
+
+namespace {
+
+struct Node {
+  int kind;  // 0 leaf, 1 scalar, 2 unary, 3 binary
+  uint32_t op = 0, arg = 0;
+  int a = -1, b = -1;
+  int need = 1;
+};
+
+uint32_t map_op(int code) {
+  using namespace coot::batch;
+  switch (code) {
+    case COOT_OP_ADD: return OP_ADD;
+    case COOT_OP_SUB: return OP_SUB;
+    case COOT_OP_SCHUR: return OP_MUL;
+    case COOT_OP_DIV: return OP_DIV;
+    case COOT_OP_NEG: return OP_NEG;
+    case COOT_OP_ABS: return OP_ABS;
+    case COOT_OP_EXP: return OP_EXP;
+    case COOT_OP_LOG: return OP_LOG;
+    case COOT_OP_SQRT: return OP_SQRT;
+    default: return OP_SQUARE;
+  }
+}
+
+// Register bytecode of one expression; returns the registers used.
+int emit_program(const Expr& e, uint32_t sc_base, std::vector<uint32_t>* code) {
+  using namespace coot::batch;
+  std::vector<Node> nodes;
+  std::vector<int> st;
+  for (size_t i = 0; i < e.ops.size(); ++i) {
+    const coot_op& o = e.ops[i];
+    Node n;
+    if (o.code == COOT_OP_LOAD) {
+      n.kind = 0;
+      n.arg = (uint32_t)e.op_leaf[i];
+    } else if (o.code == COOT_OP_SCALAR) {
+      n.kind = 1;
+      n.arg = sc_base + o.arg;
+    } else if (o.code == COOT_OP_TRANS) {
+      continue;  // index map folded into the leaves
+    } else if (o.code >= COOT_OP_ADD && o.code <= COOT_OP_DIV) {
+      n.kind = 3;
+      n.op = map_op(o.code);
+      n.b = st.back();
+      st.pop_back();
+      n.a = st.back();
+      st.pop_back();
+      const int na = nodes[n.a].need, nb = nodes[n.b].need;
+      n.need = na == nb ? na + 1 : std::max(na, nb);
+    } else {
+      n.kind = 2;
+      n.op = map_op(o.code);
+      n.a = st.back();
+      st.pop_back();
+      n.need = nodes[n.a].need;
+    }
+    nodes.push_back(n);
+    st.push_back((int)nodes.size() - 1);
+  }
+  const int root = st.back();
+  if (nodes[root].need > 8) fail(COOT_EUNSUPPORTED, "expression needs more than 8 registers in the batch interpreter");
+  // iterative Sethi-Ullman emission
+  struct Frame {
+    int node, base, stage;
+  };
+  std::vector<Frame> fs{{root, 0, 0}};
+  int max_reg = 0;
+  while (!fs.empty()) {
+    Frame& f = fs.back();
+    const Node& n = nodes[f.node];
+    max_reg = std::max(max_reg, f.base);
+    if (n.kind == 0) {
+      code->push_back(encode(OP_LEAF, f.base, n.arg));
+      fs.pop_back();
+    } else if (n.kind == 1) {
+      code->push_back(encode(OP_SCAL, f.base, n.arg));
+      fs.pop_back();
+    } else if (n.kind == 2) {
+      if (f.stage == 0) {
+        f.stage = 1;
+        fs.push_back({n.a, f.base, 0});
+      } else {
+        code->push_back(encode(n.op, f.base, 0));
+        fs.pop_back();
+      }
+    } else {
+      const bool left_first = nodes[n.a].need >= nodes[n.b].need;
+      const int first = left_first ? n.a : n.b, second = left_first ? n.b : n.a;
+      if (f.stage == 0) {
+        f.stage = 1;
+        fs.push_back({first, f.base, 0});
+      } else if (f.stage == 1) {
+        f.stage = 2;
+        const int base = f.base;
+        fs.push_back({second, base + 1, 0});
+      } else {
+        uint32_t op = n.op;
+        if (!left_first) {  // r[b] holds b-operand: swap for the non-commutative ops
+          if (op == OP_SUB) op = OP_RSUB;
+          else if (op == OP_DIV) op = OP_RDIV;
+        }
+        code->push_back(encode(op, f.base, 0));
+        fs.pop_back();
+      }
+    }
+  }
+  return max_reg + 1;
+}
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  void upload(const std::vector<T>& v) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = v.size();
+    if (n == 0) return;
+    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) fail(COOT_ENOMEM, "batch descriptor allocation failed");
+    hip_check(hipMemcpy(p, v.data(), n * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+  }
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+struct coot_batch {
+  int dtype = COOT_BATCH_F32;
+  std::vector<BatchExpr> ex;
+  std::vector<uint32_t> code;
+  std::vector<uint64_t> scal_bits;
+  std::vector<std::pair<int, int>> ranges;  // per expression: tile range
+  std::vector<uint32_t> tiles;
+  std::vector<int> vec4_ok;
+  DevBuf<BatchExpr> d_ex;
+  DevBuf<uint32_t> d_code, d_tiles;
+  DevBuf<uint64_t> d_scal32x2;  // scalars packed as the element type
+  int ts = 32;
+  int gm = 8;
+  bool allow_vec = true;
+  unsigned grid = 1;
+  int64_t bytes = 0;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~coot_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
+namespace {
+
+void build_tiles(coot_batch* b) {
+  b->tiles.clear();
+  b->ranges.clear();
+  for (size_t k = 0; k < b->ex.size(); ++k) {
+    BatchExpr& e = b->ex[k];
+    e.tiles_r = (e.n_rows + b->ts - 1) / b->ts;
+    const int tc = (e.n_cols + b->ts - 1) / b->ts;
+    e.vec4 = (b->allow_vec && b->vec4_ok[k]) ? 1 : 0;
+    const int begin = (int)(b->tiles.size() / 2);
+    for (int t = 0; t < e.tiles_r * tc; ++t) {
+      b->tiles.push_back((uint32_t)k);
+      b->tiles.push_back((uint32_t)t);
+    }
+    b->ranges.push_back({begin, (int)(b->tiles.size() / 2)});
+  }
+  b->d_ex.upload(b->ex);
+  b->d_tiles.upload(b->tiles);
+  const int n_tiles = (int)(b->tiles.size() / 2);
+  b->grid = (unsigned)std::max(1, std::min(n_tiles, b->gm * num_cus()));
+}
+
+void launch_all(coot_batch* b, hipStream_t s) {
+  const int n_tiles = (int)(b->tiles.size() / 2);
+  if (n_tiles == 0) return;
+  hip_check(coot_batch_launch_kernel(b->dtype, b->ts, b->grid, b->d_ex.p, b->d_tiles.p, 0, n_tiles, b->d_code.p,
+                                     b->d_scal32x2.p, s),
+            "batch kernel launch");
+}
+
+void capture(coot_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  if (!b->cap) hip_check(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "hipStreamCreate");
+  hip_check(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  try {
+    launch_all(b, b->cap);
+  } catch (...) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(b->cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  hip_check(hipStreamEndCapture(b->cap, &b->graph), "hipStreamEndCapture");
+  hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+}
+
+}  // namespace
+
+extern "C" {
+
+coot_status coot_batch_create(uint32_t n, coot_expr* const* exprs, const coot_operand* const* operands,
+                              const double* const* scalars, const coot_operand* outs, const coot_launch_cfg* cfg,
+                              void* stream, coot_batch** out) {
+  (void)stream;
+  return guarded([&] {
+    if (!out || (n && (!exprs || !operands || !outs))) fail(COOT_EINVAL, "NULL argument");
+    *out = nullptr;
+    auto b = std::make_unique<coot_batch>();
+    if (cfg) {
+      if (cfg->waves) {
+        if (cfg->waves == 1) b->ts = 16;
+        else if (cfg->waves == 4) b->ts = 32;
+        else if (cfg->waves == 16) b->ts = 64;
+        else fail(COOT_EINVAL, "batch waves must be 1, 4 or 16 (tiles of 16, 32 or 64)");
+      }
+      if (cfg->grid_mult) b->gm = cfg->grid_mult;
+      if (cfg->vec == 1) b->allow_vec = false;
+    }
+    int dtype = -1;
+    std::vector<double> scal;
+    for (uint32_t k = 0; k < n; ++k) {
+      if (!exprs[k]) fail(COOT_EINVAL, "NULL expression in the batch");
+      Expr& e = *exprs[k]->e;
+      if (e.dtype != COOT_F32 && e.dtype != COOT_F64) fail(COOT_EUNSUPPORTED, "batch supports f32 and f64 expressions");
+      const int dt = e.dtype == COOT_F32 ? COOT_BATCH_F32 : COOT_BATCH_F64;
+      if (dtype >= 0 && dt != dtype) fail(COOT_ETYPE, "all expressions of a batch must share one element type");
+      dtype = dt;
+      if (e.leaves.size() > COOT_BATCH_MAXL) fail(COOT_EUNSUPPORTED, "too many leaves for the batch interpreter");
+      const coot_operand* ops = operands[k];
+      check_operands(e, ops);
+      int64_t R = 0, C = 0;
+      infer_shape(e, ops, &R, &C);
+      const coot_operand& o = outs[k];
+      if (o.dtype != e.dtype || o.n_rows != R || o.n_cols != C) fail(COOT_ESHAPE, "batch output has the wrong shape or type");
+      if (R > (1 << 30) || C > (1 << 30)) fail(COOT_EUNSUPPORTED, "batch expressions are small matrices");
+      BatchExpr be;
+      std::memset(&be, 0, sizeof be);
+      const size_t es = dtype_size(e.dtype);
+      bool v4 = R % 4 == 0;
+      const int64_t old = o.ld ? o.ld : std::max<int64_t>(1, R);
+      v4 = v4 && old % 4 == 0 && ((uintptr_t)o.data % 16) == 0;
+      for (size_t l = 0; l < e.leaves.size(); ++l) {
+        const coot_operand& lo = ops[e.leaves[l].slot];
+        be.leaf[l] = lo.data;
+        be.ld[l] = lo.ld ? lo.ld : std::max<int64_t>(1, lo.n_rows);
+        if (e.leaves[l].parity) {
+          be.p1_mask |= 1u << l;
+        } else {
+          v4 = v4 && be.ld[l] % 4 == 0 && ((uintptr_t)lo.data % 16) == 0;
+        }
+        // the output may only alias an operand read untransposed with its own layout
+        const char* ob = (const char*)o.data;
+        const char* lb = (const char*)lo.data;
+        if (R * C > 0 && lb == ob && (e.leaves[l].parity || be.ld[l] != old))
+          fail(COOT_EALIAS, "batch output aliases a transposed or differently laid out operand");
+      }
+      be.out = o.data;
+      be.out_ld = old;
+      be.n_rows = (int32_t)R;
+      be.n_cols = (int32_t)C;
+      be.code_off = (int32_t)b->code.size();
+      be.sc_off = 0;
+      emit_program(e, (uint32_t)scal.size(), &b->code);
+      be.code_len = (int32_t)(b->code.size() - be.code_off);
+      if (e.n_scalars && !scalars) fail(COOT_EINVAL, "scalars missing");
+      for (uint32_t s = 0; s < e.n_scalars; ++s) scal.push_back(scalars[k][s]);
+      b->ex.push_back(be);
+      b->vec4_ok.push_back(v4 ? 1 : 0);
+      // algorithmic bytes: each distinct operand slot read once, the output written once
+      std::vector<bool> seen(e.slots.size(), false);
+      int64_t elems = R * C;
+      for (auto& l : e.leaves)
+        if (!seen[l.slot]) {
+          seen[l.slot] = true;
+          elems += ops[l.slot].n_rows * ops[l.slot].n_cols;
+        }
+      b->bytes += elems * (int64_t)es;
+    }
+    b->dtype = dtype < 0 ? COOT_BATCH_F32 : dtype;
+    // scalars in the element type, one 64-bit slot each (fp32 scalars use the low word of a float array)
+    if (b->dtype == COOT_BATCH_F32) {
+      std::vector<uint64_t> packed((scal.size() + 1) / 2 + 1, 0);
+      float* f = reinterpret_cast<float*>(packed.data());
+      for (size_t s = 0; s < scal.size(); ++s) f[s] = (float)scal[s];
+      b->scal_bits = packed;
+    } else {
+      b->scal_bits.resize(scal.size() + 1, 0);
+      std::memcpy(b->scal_bits.data(), scal.data(), scal.size() * 8);
+    }
+    b->d_code.upload(b->code.empty() ? std::vector<uint32_t>{0} : b->code);
+    b->d_scal32x2.upload(b->scal_bits);
+    build_tiles(b.get());
+    capture(b.get());
+    *out = b.release();
+  });
+}
+
+coot_status coot_batch_launch(coot_batch* b, void* stream) {
+  return guarded([&] {
+    if (!b) fail(COOT_EINVAL, "NULL batch");
+    if (b->tiles.empty()) return;
+    hip_check(hipGraphLaunch(b->exec, (hipStream_t)stream), "hipGraphLaunch");
+  });
+}
+
+coot_status coot_batch_launch_each(coot_batch* b, void* stream) {
+  return guarded([&] {
+    if (!b) fail(COOT_EINVAL, "NULL batch");
+    for (auto& r : b->ranges) {
+      if (r.second == r.first) continue;
+      const unsigned g = (unsigned)std::min(r.second - r.first, (int)b->grid);
+      hip_check(coot_batch_launch_kernel(b->dtype, b->ts, g, b->d_ex.p, b->d_tiles.p, r.first, r.second,
+                                         b->d_code.p, b->d_scal32x2.p, (hipStream_t)stream),
+                "batch kernel launch");
+    }
+  });
+}
+
+coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, float* best_us) {
+  return guarded([&] {
+    if (!b) fail(COOT_EINVAL, "NULL batch");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "hipEventCreate");
+    hip_check(hipEventCreate(&e1), "hipEventCreate");
+    float bt = 1e30f;
+    int bts = b->ts, bgm = b->gm;
+    bool bvec = b->allow_vec;
+    for (int ts : {16, 32, 64}) {
+      for (int gm : {2, 4, 8, 16}) {
+        for (bool vec : {true, false}) {
+          b->ts = ts;
+          b->gm = gm;
+          b->allow_vec = vec;
+          build_tiles(b);
+          launch_all(b, s);  // warm-up
+          std::vector<float> ts_ms;
+          for (int rep = 0; rep < 5; ++rep) {
+            hip_check(hipEventRecord(e0, s), "hipEventRecord");
+            launch_all(b, s);
+            hip_check(hipEventRecord(e1, s), "hipEventRecord");
+            hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+            float ms = 0;
+            hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+            ts_ms.push_back(ms);
+          }
+          std::sort(ts_ms.begin(), ts_ms.end());
+          if (ts_ms[2] < bt) {
+            bt = ts_ms[2];
+            bts = ts;
+            bgm = gm;
+            bvec = vec;
+          }
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->ts = bts;
+    b->gm = bgm;
+    b->allow_vec = bvec;
+    build_tiles(b);
+    capture(b);
+    if (best) {
+      best->vec = bvec ? 4 : 1;
+      best->ept = 4;
+      best->waves = (uint16_t)(bts * bts / 256);
+      best->grid_mult = (uint16_t)bgm;
+    }
+    if (best_us) *best_us = bt * 1000.0f;
+  });
+}
+
+coot_status coot_batch_info(const coot_batch* b, int64_t info[6]) {
+  return guarded([&] {
+    if (!b || !info) fail(COOT_EINVAL, "NULL argument");
+    info[0] = (int64_t)b->ex.size();
+    info[1] = (int64_t)(b->tiles.size() / 2);
+    info[2] = b->bytes;
+    info[3] = b->ts;
+    info[4] = b->grid;
+    int64_t v4 = 0;
+    for (auto& e : b->ex) v4 += e.vec4;
+    info[5] = v4;
+  });
+}
+
+void coot_batch_release(coot_batch* b) { delete b; }
+
+}  // extern "C"

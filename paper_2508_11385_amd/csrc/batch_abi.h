@@ -1,0 +1,36 @@
+// Layout shared by the batch interpreter kernel (kernels/batch.hip) and its host
+// side (batch.cpp).
+#pragma once
+#include <stdint.h>
+
+#define COOT_BATCH_MAXL 12   // distinct (operand, transpose parity) leaves per expression
+#define COOT_BATCH_F32 0
+#define COOT_BATCH_F64 1
+
+namespace coot {
+namespace batch {
+
+enum : uint32_t {
+  OP_ADD = 0, OP_SUB = 1, OP_MUL = 2, OP_DIV = 3, OP_RSUB = 4, OP_RDIV = 5,  // binary (R: operands swapped)
+  OP_NEG = 6, OP_ABS = 7, OP_EXP = 8, OP_LOG = 9, OP_SQRT = 10, OP_SQUARE = 11,  // unary
+  OP_LEAF = 12, OP_SCAL = 13
+};
+
+inline constexpr uint32_t encode(uint32_t op, uint32_t reg, uint32_t arg) { return op | (reg << 6) | (arg << 9); }
+
+// One expression of a batch (device memory, 16-byte aligned records).
+struct BatchExpr {
+  const void* leaf[COOT_BATCH_MAXL];  // leaf k: base pointer of its operand
+  int64_t ld[COOT_BATCH_MAXL];        // leading dimension of leaf k's operand
+  void* out;
+  int64_t out_ld;
+  int32_t n_rows, n_cols;             // output dimensions
+  int32_t tiles_r;                    // ceil(n_rows / TS)
+  int32_t code_off, code_len;         // bytecode range
+  int32_t sc_off;                     // first scalar
+  uint32_t p1_mask;                   // bit k: leaf k is read transposed
+  int32_t vec4;                       // 1: 128-bit column-segment accesses are valid
+};
+
+}  // namespace batch
+}  // namespace coot

@@ -141,4 +141,31 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
 Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, int mode, int dim, bool comp,
              const coot_launch_cfg* cfg);
 
+// Thread-local message behind coot_last_error().
+std::string& last_error();
+
+// Run f, mapping exceptions to a status and the thread's last-error message.
+template <typename F>
+coot_status guarded(F&& f) {
+  try {
+    last_error().clear();
+    f();
+    return COOT_OK;
+  } catch (const Error& e) {
+    last_error() = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    last_error() = "host allocation failed";
+    return COOT_ENOMEM;
+  } catch (const std::exception& e) {
+    last_error() = e.what();
+    return COOT_EINVAL;
+  }
+}
+
 }  // namespace coot
+
+// Library-owned expression handle (coot.h's opaque coot_expr).
+struct coot_expr {
+  std::unique_ptr<coot::Expr> e;
+};

@@ -290,3 +290,48 @@ def norm(e, plain=False, cfg=None, unfused=False) -> Mat:
 
 def init(device: int = 0) -> None:
     cc.coot_init(device)
+
+
+class Batch:
+    """Many small independent expressions evaluated by one persistent, graph-captured launch.
+
+    items: list of (expression, out Mat or None).  Outputs are allocated when None.
+    The operands' and outputs' storage must stay alive while the batch exists.
+    """
+
+    def __init__(self, items, cfg=None):
+        handles, ops, scs, outs = [], [], [], []
+        self.outs = []
+        self._keep = []
+        for e, out in items:
+            flat = flatten(_lift(e))
+            h = compiled(flat)
+            o = [m.operand() for m in flat.mats]
+            if out is None:
+                r, c = cc.coot_expr_out_shape(h, o)
+                out = Mat.empty(r, c, flat.dtype, device=flat.mats[0].tensor.device)
+            handles.append(h)
+            ops.append(o)
+            scs.append(flat.scalars)
+            outs.append(out.operand())
+            self.outs.append(out)
+            self._keep.append(flat.mats)
+        self.handle = cc.coot_batch_create(handles, ops, scs, outs, cfg, _stream())
+
+    def launch(self):
+        cc.coot_batch_launch(self.handle, _stream())
+
+    def launch_each(self):
+        cc.coot_batch_launch_each(self.handle, _stream())
+
+    def tune(self):
+        return cc.coot_batch_tune(self.handle, _stream())
+
+    def info(self):
+        return cc.coot_batch_info(self.handle)
+
+    def __del__(self):
+        try:
+            cc.coot_batch_release(self.handle)
+        except Exception:
+            pass
