@@ -69,7 +69,9 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     for src in host + [embed] + kern:
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
         objs.append(obj)
-        lang = ["-x", "hip"] if src.endswith(".hip") else []
+        # hand-written kernels: keep SimplifyCFG from sinking the register-file stores of the batch
+        # interpreter's switch into one indexed store (that would demote the registers to scratch)
+        lang = ["-x", "hip", "-mllvm", "-simplifycfg-sink-common=false"] if src.endswith(".hip") else []
         cmd = [hipcc] + HIP_FLAGS + inc + lang + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)

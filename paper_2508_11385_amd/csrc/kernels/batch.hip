@@ -33,74 +33,66 @@ struct Cfg {
   static constexpr int NP1 = (49152 / BYTES) < 4 ? (49152 / BYTES) : 4;  // LDS-staged transposed leaves
 };
 
-template <typename T>
-__device__ __forceinline__ T apply_bin(u32 op, T a, T b) {
-  switch (op) {
-    case OP_ADD: return op_add(a, b);
-    case OP_SUB: return op_sub(a, b);
-    case OP_MUL: return op_mul(a, b);
-    case OP_DIV: return op_div(a, b);
-    case OP_RSUB: return op_sub(b, a);
-    default: return op_div(b, a);  // OP_RDIV
-  }
-}
-
-template <typename T>
-__device__ __forceinline__ T apply_un(u32 op, T a) {
-  switch (op) {
-    case OP_NEG: return op_neg(a);
-    case OP_ABS: return op_abs(a);
-    case OP_EXP: return op_exp(a);
-    case OP_LOG: return op_log(a);
-    case OP_SQRT: return op_sqrt(a);
-    default: return op_square(a);  // OP_SQUARE
-  }
-}
-
-// register file: 8 registers x 4 elements, addressed only with compile-time
-// indices (the uniform register number selects a case) so nothing spills.
+// Register file: eight named 4-element registers.  They are never addressed
+// through an index: every (register, operation) pair is its own case below, so
+// the registers stay in VGPRs.
 template <typename T>
 struct Regs {
-  T r[8][4];
+  T r0[4], r1[4], r2[4], r3[4], r4[4], r5[4], r6[4], r7[4];
 };
 
-#define COOT_REG_CASES(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
+#define COOT_RB(i) R.r##i
+#define COOT_SET(i) \
+  case i:           \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q) COOT_RB(i)[q] = v[q]; \
+    break;
 
 template <typename T>
 __device__ __forceinline__ void reg_set(Regs<T>& R, u32 b, const T (&v)[4]) {
   switch (b) {
-#define C_(i)                                   \
-  case i:                                       \
-    _Pragma("unroll") for (int q = 0; q < 4; ++q) R.r[i][q] = v[q]; \
-    break;
-    COOT_REG_CASES(C_)
-#undef C_
+    COOT_SET(0) COOT_SET(1) COOT_SET(2) COOT_SET(3) COOT_SET(4) COOT_SET(5) COOT_SET(6) COOT_SET(7)
   }
 }
 
-template <typename T>
-__device__ __forceinline__ void reg_bin(Regs<T>& R, u32 op, u32 b) {
-  switch (b) {
-#define C_(i)                                                                          \
-  case i:                                                                              \
-    if constexpr (i < 7) {                                                             \
-      _Pragma("unroll") for (int q = 0; q < 4; ++q) R.r[i][q] = apply_bin<T>(op, R.r[i][q], R.r[i + 1][q]); \
-    }                                                                                  \
+// key = op * 8 + register
+#define COOT_BIN(OPC, i, j, FN) \
+  case OPC * 8 + i:             \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q) COOT_RB(i)[q] = FN(COOT_RB(i)[q], COOT_RB(j)[q]); \
     break;
-    COOT_REG_CASES(C_)
-#undef C_
-  }
-}
+#define COOT_RBIN(OPC, i, j, FN) \
+  case OPC * 8 + i:              \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q) COOT_RB(i)[q] = FN(COOT_RB(j)[q], COOT_RB(i)[q]); \
+    break;
+#define COOT_UN(OPC, i, FN) \
+  case OPC * 8 + i:         \
+    _Pragma("unroll") for (int q = 0; q < 4; ++q) COOT_RB(i)[q] = FN(COOT_RB(i)[q]); \
+    break;
+#define COOT_BIN_ALL(OPC, FN) \
+  COOT_BIN(OPC, 0, 1, FN) COOT_BIN(OPC, 1, 2, FN) COOT_BIN(OPC, 2, 3, FN) COOT_BIN(OPC, 3, 4, FN) \
+  COOT_BIN(OPC, 4, 5, FN) COOT_BIN(OPC, 5, 6, FN) COOT_BIN(OPC, 6, 7, FN)
+#define COOT_RBIN_ALL(OPC, FN) \
+  COOT_RBIN(OPC, 0, 1, FN) COOT_RBIN(OPC, 1, 2, FN) COOT_RBIN(OPC, 2, 3, FN) COOT_RBIN(OPC, 3, 4, FN) \
+  COOT_RBIN(OPC, 4, 5, FN) COOT_RBIN(OPC, 5, 6, FN) COOT_RBIN(OPC, 6, 7, FN)
+#define COOT_UN_ALL(OPC, FN)                                                                   \
+  COOT_UN(OPC, 0, FN) COOT_UN(OPC, 1, FN) COOT_UN(OPC, 2, FN) COOT_UN(OPC, 3, FN) COOT_UN(OPC, 4, FN) \
+  COOT_UN(OPC, 5, FN) COOT_UN(OPC, 6, FN) COOT_UN(OPC, 7, FN)
 
 template <typename T>
-__device__ __forceinline__ void reg_un(Regs<T>& R, u32 op, u32 b) {
-  switch (b) {
-#define C_(i)                                                                       \
-  case i:                                                                           \
-    _Pragma("unroll") for (int q = 0; q < 4; ++q) R.r[i][q] = apply_un<T>(op, R.r[i][q]); \
-    break;
-    COOT_REG_CASES(C_)
-#undef C_
+__device__ __forceinline__ void reg_op(Regs<T>& R, u32 key) {
+  switch (key) {
+    COOT_BIN_ALL(OP_ADD, op_add)
+    COOT_BIN_ALL(OP_SUB, op_sub)
+    COOT_BIN_ALL(OP_MUL, op_mul)
+    COOT_BIN_ALL(OP_DIV, op_div)
+    COOT_RBIN_ALL(OP_RSUB, op_sub)
+    COOT_RBIN_ALL(OP_RDIV, op_div)
+    COOT_UN_ALL(OP_NEG, op_neg)
+    COOT_UN_ALL(OP_ABS, op_abs)
+    COOT_UN_ALL(OP_EXP, op_exp)
+    COOT_UN_ALL(OP_LOG, op_log)
+    COOT_UN_ALL(OP_SQRT, op_sqrt)
+    COOT_UN_ALL(OP_SQUARE, op_square)
+    default: break;
   }
 }
 
@@ -196,10 +188,8 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
         const T s = scal[e.sc_off + (int)arg];
         T v[4] = {s, s, s, s};
         reg_set<T>(Rg, b, v);
-      } else if (op <= OP_RDIV) {
-        reg_bin<T>(Rg, op, b);
       } else {
-        reg_un<T>(Rg, op, b);
+        reg_op<T>(Rg, op * 8u + b);
       }
     }
     T* out = (T*)e.out;
@@ -208,13 +198,13 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
       if (in[0]) {
         vt<T, 4> g;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) g.v[q] = Rg.r[0][q];
+        for (int q = 0; q < 4; ++q) g.v[q] = Rg.r0[q];
         stv<T, 4>(out + (i64)iq[0] + (i64)jq[0] * old, g);
       }
     } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q)
-        if (in[q]) out[(i64)iq[q] + (i64)jq[q] * old] = Rg.r[0][q];
+        if (in[q]) out[(i64)iq[q] + (i64)jq[q] * old] = Rg.r0[q];
     }
     if (p1) __syncthreads();  // the next tile restages LDS
   }
