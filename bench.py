@@ -36,9 +36,14 @@ def parse():
     p.add_argument("--cpu-cols", type=int, default=4096, help="columns of the problem the CPU oracle is timed on")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_tile_Z_4096_f32.json"))
-    p.add_argument("--workload", default="expr4096", choices=["expr4096", "batch"],
+    p.add_argument("--workload", default="expr4096", choices=["expr4096", "batch", "tuner"],
                    help="expr4096: the fused 2-D expression step (default); batch: 10,000 small expressions")
     p.add_argument("--batch-n", type=int, default=10_000)
+    p.add_argument("--tuner-train", type=int, default=1000, help="training signatures")
+    p.add_argument("--tuner-test", type=int, default=2000, help="held-out signatures (timed exhaustively)")
+    p.add_argument("--tuner-cfgs", type=int, default=50, help="configurations timed per training signature")
+    p.add_argument("--tuner-epochs", type=int, default=200)
+    p.add_argument("--tuner-out", default=os.path.join(ROOT, "gpurun_out", "costmodel_mi355x.bin"))
     p.add_argument("--profile-kernels", action="store_true",
                    help="run the copy probe and each kernel of one step 3 times, print their names, exit")
     return p.parse_args()
@@ -60,6 +65,8 @@ def main():
     coot.init(0)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "tuner":
+        return bench_tuner(args)
     dev = torch.device("cuda:0")
     A, B, C, D = synth.matrix_inputs(N, "f32")
     gA, gB, gC, gD = (coot.Mat.from_numpy(m) for m in (A, B, C, D))
@@ -271,6 +278,61 @@ def bench_batch(args):
         "default_cfg": {"tile": info["tile"], "grid": info["grid"]},
         "vec4_exprs": info2["vec4_exprs"], "pct_of_peak": round(100 * gbs / PEAK_HBM_GBS, 1),
         "tuning_s": round(t_tune, 2), "create_s": round(t_create, 2), "generate_s": round(t_gen, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_tuner(args):
+    """Learned tuner: timing data generated by the autotuner, MLP trained on the GPU, regret of its
+    argmin against exhaustive autotuning on held-out signatures."""
+    import numpy as np
+    from paper_2508_11385_amd import _coot as cc
+    from paper_2508_11385_amd import tuner
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    train = tuner.sample_signatures(args.tuner_train, seed=1)
+    test = tuner.sample_signatures(args.tuner_test, seed=2)
+    t0 = time.perf_counter()
+    h_tr, f_tr = tuner.prepare_all(train)
+    h_te, f_te = tuner.prepare_all(test)
+    t_compile = time.perf_counter() - t0
+    log(f"compiled {len(train) + len(test)} tuning modules in {t_compile:.0f} s")
+    t0 = time.perf_counter()
+    X, y, _ = tuner.build_dataset(train, h_tr, f_tr, configs_per_sig=args.tuner_cfgs, seed=11, log=log)
+    t_train_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, _, tables = tuner.build_dataset(test, h_te, f_te, configs_per_sig=None, seed=12, log=log)
+    t_exh = time.perf_counter() - t0
+    n_exh = int(sum(len(c) for c, _ in tables))
+    log(f"{len(y)} training timings in {t_train_data:.0f} s; {n_exh} held-out timings in {t_exh:.0f} s")
+    init = tuner.he_init(7)
+    t0 = time.perf_counter()
+    cm, losses = cc.coot_costmodel_train(X, y, np.ones(len(y), np.float32), init, 64, 64, args.tuner_epochs, 256, 7,
+                                         1e-3)
+    t_fit = time.perf_counter() - t0
+    r_mlp, r_def, t_pred = tuner.evaluate(cm, test, h_te, tables)
+    cm0, _ = cc.coot_costmodel_train(X, y, np.ones(len(y), np.float32), init, 64, 64, 0, 256, 7, 1e-3)
+    r_untrained, _, _ = tuner.evaluate(cm0, test, h_te, tables)
+    os.makedirs(os.path.dirname(args.tuner_out), exist_ok=True)
+    cc.coot_costmodel_save(cm, args.tuner_out)
+    s_mlp, s_def, s_un = tuner.summarize(r_mlp), tuner.summarize(r_def), tuner.summarize(r_untrained)
+    out = {
+        "metric": "learned tuner: geomean regret of MLP-chosen launch configs vs exhaustive autotune",
+        "value": round(100 * s_mlp["geomean"], 2), "unit": "% regret", "higher_is_better": False, "n_gpus": 1,
+        "dtype": "f32 (MLP); u32/s32/f32/f64 expressions",
+        "data": "synthetic: random trees depth 1-8, rows/cols log-uniform [1,16384], timings generated on this GPU",
+        "config": {"workload": "learned launch-configuration tuner", "train_signatures": len(train),
+                   "train_timings": int(len(y)), "test_signatures": len(test), "test_timings": n_exh,
+                   "epochs": args.tuner_epochs, "hidden": [64, 64]},
+        "mlp": {k: round(v, 4) for k, v in s_mlp.items()},
+        "default_config": {k: round(v, 4) for k, v in s_def.items()},
+        "untrained_mlp": {k: round(v, 4) for k, v in s_un.items()},
+        "final_train_loss": round(float(losses[-1]), 4), "first_train_loss": round(float(losses[0]), 4),
+        "mlp_predict_us_per_signature": round(1e6 * t_pred, 1),
+        "exhaustive_tuning_s_per_signature": round(t_exh / len(test), 4),
+        "compile_s": round(t_compile, 1), "train_data_s": round(t_train_data, 1), "fit_s": round(t_fit, 2),
     }
     print(json.dumps(out), flush=True)
 

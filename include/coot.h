@@ -243,6 +243,100 @@ coot_status coot_batch_info(const coot_batch* b, int64_t info[6]);
 
 void coot_batch_release(coot_batch* b);
 
+/* ---- autotuning of the fused kernels' launch configuration ----------------
+ * A configuration is (vec, ept, waves, grid_mult).  vec and ept select
+ * compile-time variants (one tuning module per expression signature holds all
+ * of them), waves and grid_mult are launch parameters.  Expressions that take
+ * the tiled kernels (transposed or strided leaves) run 256-thread workgroups:
+ * only vec and grid_mult vary there (ept = 1, waves = 4 in their configurations).
+ * Tuning covers element-wise evaluation (mode -1) and accu (mode COOT_RED_ACCU). */
+
+/* Write the configuration space of a kernel family (0 flat, 1 tiled) into
+ * cfgs[0..cap) and return its size (cfgs may be NULL to query the size).
+ * Flat: vec {1,2,4} x ept {1,2,4,8} x waves {1,2,4,8} x grid_mult {2,4,8,16} = 192;
+ * tiled: vec {1,2,4} x grid_mult {2,4,8,16} = 12. */
+uint32_t coot_tune_space(int32_t family, coot_launch_cfg* cfgs, uint32_t cap);
+
+/* Compile (or fetch) the tuning module for these operands without a device and
+ * report which family (0 flat, 1 tiled) the expression takes.  Safe to call from
+ * several host threads at once (compilation runs outside the library's lock).
+ * Errors: COOT_EINVAL, COOT_ESHAPE, COOT_ECOMPILE, COOT_EUNSUPPORTED (mode). */
+coot_status coot_tune_prepare(coot_expr* e, const coot_operand* operands, int32_t mode, int32_t* family);
+
+/* Time each configuration: one warm-up launch, then `reps` launches bracketed by
+ * HIP events on `stream` (flush != 0: each preceded by a 512 MiB write that
+ * evicts L2 and the Infinity Cache); times_us[k] = median, or NaN when the
+ * configuration cannot run on these operands (e.g. vec not allowed by alignment).
+ * Synchronises the stream.  out receives the result as in coot_expr_eval /
+ * coot_reduce.  Errors: as coot_expr_eval, COOT_EINVAL for an invalid configuration. */
+coot_status coot_tune_table(coot_expr* e, const coot_operand* operands, const double* scalars, coot_operand* out,
+                            int32_t mode, const coot_launch_cfg* cfgs, uint32_t n_cfgs, uint32_t reps,
+                            int32_t flush, float* times_us, void* stream);
+
+/* Evaluate with an explicit configuration through the tuning module. */
+coot_status coot_tune_launch(coot_expr* e, const coot_operand* operands, const double* scalars, coot_operand* out,
+                             int32_t mode, const coot_launch_cfg* cfg, void* stream);
+
+/* ---- learned tuner: MLP cost model ------------------------------------------
+ * A 3-Linear-layer ReLU network in -> h1 -> h2 -> 1, binary32, trained on the
+ * device with masked mean-squared error and Adam (beta 0.9 / 0.999, eps 1e-8).
+ * Parameters are one array: W1[h1][in], b1[h1], W2[h2][h1], b2[h2], W3[1][h2], b3.
+ * Activations are sample-major (row b holds one sample's inputs). */
+typedef struct coot_mlp coot_mlp;
+typedef struct coot_costmodel coot_costmodel;
+
+/* params_host: initial parameters (host, copied).  Errors: COOT_EINVAL, COOT_ENOMEM. */
+coot_status coot_mlp_create(int32_t n_in, int32_t h1, int32_t h2, const float* params_host, coot_mlp** out);
+uint32_t coot_mlp_num_params(const coot_mlp* m);
+/* Copy the parameters / the last gradients to host memory (synchronous). */
+coot_status coot_mlp_get_params(const coot_mlp* m, float* host);
+coot_status coot_mlp_get_grads(const coot_mlp* m, float* host);
+/* out[b] = network(X[b]) for X: B x n_in device array; out: B device floats. */
+coot_status coot_mlp_forward(coot_mlp* m, const float* X, int32_t B, float* out, void* stream);
+/* Forward + backward of L = inv_count * sum_b mask_b (out_b - y_b)^2 on device
+ * arrays X (B x n_in), y, mask (B); gradients are kept for coot_mlp_adam_step;
+ * loss (one device float, may be NULL) receives L. */
+coot_status coot_mlp_backward(coot_mlp* m, const float* X, const float* y, const float* mask, int32_t B,
+                              float inv_count, float* loss, void* stream);
+/* One Adam update at step t >= 1 with bias correction. */
+coot_status coot_mlp_adam_step(coot_mlp* m, float lr, float beta1, float beta2, float eps, int32_t t, void* stream);
+/* Minibatch Adam over `epochs` passes of the N device samples (X, y, mask; mask_host
+ * is the same mask on the host, used for each batch's normaliser); batches are a
+ * seeded shuffle; losses_host[epoch] = mean batch loss.  Synchronises the stream. */
+coot_status coot_mlp_train(coot_mlp* m, const float* X, const float* y, const float* mask, const float* mask_host,
+                           int32_t N, int32_t batch, int32_t epochs, uint32_t seed, float lr, float* losses_host,
+                           void* stream);
+void coot_mlp_release(coot_mlp* m);
+
+/* Feature vectors (n x 17, host) of an expression on an n_rows x n_cols shape for
+ * each configuration: n_ops, n_operands, one-hot dtype (u32 s32 f32 f64),
+ * log2(1+rows), log2(1+cols), n_trans, one-hot reduction red (0 none, 1 all,
+ * 2 dim0, 3 dim1), log2 vec, log2 ept, log2 waves, log2 grid_mult. */
+coot_status coot_costmodel_features(const coot_expr* e, int64_t n_rows, int64_t n_cols, int32_t red,
+                                    const coot_launch_cfg* cfgs, uint32_t n, float* out);
+/* Train a cost model on N host rows: feats (N x 17), target = log(time in us),
+ * mask (1 = use the row).  Inputs and target are z-scored with the training
+ * statistics (kept in the model); init_params as for coot_mlp_create with n_in 17. */
+coot_status coot_costmodel_train(const float* feats, const float* target, const float* mask, int32_t N,
+                                 const float* init_params, int32_t h1, int32_t h2, int32_t epochs, int32_t batch,
+                                 uint32_t seed, float lr, float* losses, void* stream, coot_costmodel** out);
+/* Predicted time of each configuration (pred_us may be NULL) and the index of the
+ * smallest (lowest index on ties).  Synchronises the stream. */
+coot_status coot_costmodel_predict(coot_costmodel* cm, const coot_expr* e, int64_t n_rows, int64_t n_cols,
+                                   int32_t red, const coot_launch_cfg* cfgs, uint32_t n, float* pred_us,
+                                   uint32_t* best, void* stream);
+coot_status coot_costmodel_save(const coot_costmodel* cm, const char* path);
+coot_status coot_costmodel_load(const char* path, coot_costmodel** out);
+void coot_costmodel_release(coot_costmodel* cm);
+
+/* Pick a configuration for these operands: policy 0 the library default,
+ * 1 exhaustive (every configuration timed, the fastest kept), 2 the cost model's
+ * argmin (cm required).  best_us (may be NULL) is the chosen configuration's
+ * measured median time (5 launches, caches flushed).  Synchronises the stream. */
+coot_status coot_tune(coot_expr* e, const coot_operand* operands, const double* scalars, coot_operand* out,
+                      int32_t mode, int32_t policy, coot_costmodel* cm, coot_launch_cfg* best, float* best_us,
+                      void* stream);
+
 /* Counters since process start: out[0] compiles, out[1] memory-cache hits,
  * out[2] disk-cache hits, out[3] launches, out[4] total compile milliseconds. */
 void coot_stats(double out[5]);

@@ -84,6 +84,35 @@ _sig = {
     "coot_batch_tune": (C.c_int, [_P, _P, C.POINTER(coot_launch_cfg), C.POINTER(C.c_float)]),
     "coot_batch_info": (C.c_int, [_P, C.POINTER(C.c_int64)]),
     "coot_batch_release": (None, [_P]),
+    "coot_tune_space": (C.c_uint32, [C.c_int32, C.POINTER(coot_launch_cfg), C.c_uint32]),
+    "coot_tune_prepare": (C.c_int, [_P, C.POINTER(coot_operand), C.c_int32, C.POINTER(C.c_int32)]),
+    "coot_tune_table": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(C.c_double), C.POINTER(coot_operand),
+                                  C.c_int32, C.POINTER(coot_launch_cfg), C.c_uint32, C.c_uint32, C.c_int32,
+                                  C.POINTER(C.c_float), _P]),
+    "coot_tune_launch": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(C.c_double), C.POINTER(coot_operand),
+                                   C.c_int32, C.POINTER(coot_launch_cfg), _P]),
+    "coot_mlp_create": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_float), C.POINTER(_P)]),
+    "coot_mlp_num_params": (C.c_uint32, [_P]),
+    "coot_mlp_get_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "coot_mlp_get_grads": (C.c_int, [_P, C.POINTER(C.c_float)]),
+    "coot_mlp_forward": (C.c_int, [_P, _P, C.c_int32, _P, _P]),
+    "coot_mlp_backward": (C.c_int, [_P, _P, _P, _P, C.c_int32, C.c_float, _P, _P]),
+    "coot_mlp_adam_step": (C.c_int, [_P, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32, _P]),
+    "coot_mlp_train": (C.c_int, [_P, _P, _P, _P, C.POINTER(C.c_float), C.c_int32, C.c_int32, C.c_int32,
+                                 C.c_uint32, C.c_float, C.POINTER(C.c_float), _P]),
+    "coot_mlp_release": (None, [_P]),
+    "coot_costmodel_features": (C.c_int, [_P, C.c_int64, C.c_int64, C.c_int32, C.POINTER(coot_launch_cfg),
+                                          C.c_uint32, C.POINTER(C.c_float)]),
+    "coot_costmodel_train": (C.c_int, [C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_int32,
+                                       C.POINTER(C.c_float), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                       C.c_uint32, C.c_float, C.POINTER(C.c_float), _P, C.POINTER(_P)]),
+    "coot_costmodel_predict": (C.c_int, [_P, _P, C.c_int64, C.c_int64, C.c_int32, C.POINTER(coot_launch_cfg),
+                                         C.c_uint32, C.POINTER(C.c_float), C.POINTER(C.c_uint32), _P]),
+    "coot_costmodel_save": (C.c_int, [_P, C.c_char_p]),
+    "coot_costmodel_load": (C.c_int, [C.c_char_p, C.POINTER(_P)]),
+    "coot_costmodel_release": (None, [_P]),
+    "coot_tune": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(C.c_double), C.POINTER(coot_operand), C.c_int32,
+                            C.c_int32, _P, C.POINTER(coot_launch_cfg), C.POINTER(C.c_float), _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(lib, _name)
@@ -220,3 +249,146 @@ def coot_batch_info(b: int) -> dict:
 
 def coot_batch_release(b: int) -> None:
     lib.coot_batch_release(b)
+
+
+# ---- autotuning ---------------------------------------------------------------------------
+
+def coot_tune_space(family: int) -> list:
+    n = lib.coot_tune_space(family, None, 0)
+    a = (coot_launch_cfg * n)()
+    lib.coot_tune_space(family, a, n)
+    return [(c.vec, c.ept, c.waves, c.grid_mult) for c in a]
+
+
+def _cfgs(cfgs):
+    return _arr(coot_launch_cfg, [coot_launch_cfg(*c) for c in cfgs])
+
+
+def coot_tune_prepare(h: int, operands, mode: int = -1) -> int:
+    fam = C.c_int32()
+    _check(lib.coot_tune_prepare(h, _arr(coot_operand, operands), mode, C.byref(fam)))
+    return fam.value
+
+
+def coot_tune_table(h: int, operands, scalars, out: coot_operand, mode: int, cfgs, reps: int = 5, flush: bool = True,
+                    stream: int = 0) -> list:
+    t = (C.c_float * max(1, len(cfgs)))()
+    _check(lib.coot_tune_table(h, _arr(coot_operand, operands), _arr(C.c_double, scalars), C.byref(out), mode,
+                               _cfgs(cfgs), len(cfgs), reps, int(flush), t, stream))
+    return [t[i] for i in range(len(cfgs))]
+
+
+def coot_tune_launch(h: int, operands, scalars, out: coot_operand, mode: int, cfg, stream: int = 0) -> None:
+    _check(lib.coot_tune_launch(h, _arr(coot_operand, operands), _arr(C.c_double, scalars), C.byref(out), mode,
+                                C.byref(coot_launch_cfg(*cfg)), stream))
+
+
+def coot_tune(h: int, operands, scalars, out: coot_operand, mode: int, policy: int, cm: int = 0, stream: int = 0):
+    best = coot_launch_cfg()
+    us = C.c_float()
+    _check(lib.coot_tune(h, _arr(coot_operand, operands), _arr(C.c_double, scalars), C.byref(out), mode, policy,
+                         cm or None, C.byref(best), C.byref(us), stream))
+    return (best.vec, best.ept, best.waves, best.grid_mult), us.value
+
+
+# ---- MLP and cost model -------------------------------------------------------------------
+
+def _fptr(a):
+    """numpy float32 array -> ctypes float pointer (the array must stay alive)."""
+    import numpy as np
+    assert a.dtype == np.float32 and a.flags.c_contiguous
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def coot_mlp_create(n_in: int, h1: int, h2: int, params) -> int:
+    m = _P()
+    _check(lib.coot_mlp_create(n_in, h1, h2, _fptr(params), C.byref(m)))
+    return m.value
+
+
+def coot_mlp_num_params(m: int) -> int:
+    return lib.coot_mlp_num_params(m)
+
+
+def coot_mlp_get_params(m: int):
+    import numpy as np
+    out = np.empty(coot_mlp_num_params(m), np.float32)
+    _check(lib.coot_mlp_get_params(m, _fptr(out)))
+    return out
+
+
+def coot_mlp_get_grads(m: int):
+    import numpy as np
+    out = np.empty(coot_mlp_num_params(m), np.float32)
+    _check(lib.coot_mlp_get_grads(m, _fptr(out)))
+    return out
+
+
+def coot_mlp_forward(m: int, X_dev: int, B: int, out_dev: int, stream: int = 0) -> None:
+    _check(lib.coot_mlp_forward(m, X_dev, B, out_dev, stream))
+
+
+def coot_mlp_backward(m: int, X_dev: int, y_dev: int, mask_dev: int, B: int, inv_count: float, loss_dev: int = 0,
+                      stream: int = 0) -> None:
+    _check(lib.coot_mlp_backward(m, X_dev, y_dev, mask_dev, B, inv_count, loss_dev or None, stream))
+
+
+def coot_mlp_adam_step(m: int, lr: float, beta1: float, beta2: float, eps: float, t: int, stream: int = 0) -> None:
+    _check(lib.coot_mlp_adam_step(m, lr, beta1, beta2, eps, t, stream))
+
+
+def coot_mlp_train(m: int, X_dev: int, y_dev: int, mask_dev: int, mask_host, N: int, batch: int, epochs: int,
+                   seed: int, lr: float, stream: int = 0):
+    import numpy as np
+    losses = np.zeros(max(1, epochs), np.float32)
+    _check(lib.coot_mlp_train(m, X_dev, y_dev, mask_dev, _fptr(mask_host), N, batch, epochs, seed, lr,
+                              _fptr(losses), stream))
+    return losses[:epochs]
+
+
+def coot_mlp_release(m: int) -> None:
+    lib.coot_mlp_release(m)
+
+
+def coot_costmodel_features(h: int, n_rows: int, n_cols: int, red: int, cfgs):
+    import numpy as np
+    out = np.zeros((len(cfgs), 17), np.float32)
+    _check(lib.coot_costmodel_features(h, n_rows, n_cols, red, _cfgs(cfgs), len(cfgs), _fptr(out)))
+    return out
+
+
+def coot_costmodel_train(feats, target, mask, init_params, h1: int, h2: int, epochs: int, batch: int, seed: int,
+                         lr: float, stream: int = 0):
+    import numpy as np
+    feats = np.ascontiguousarray(feats, np.float32)
+    target = np.ascontiguousarray(target, np.float32)
+    mask = np.ascontiguousarray(mask, np.float32)
+    init_params = np.ascontiguousarray(init_params, np.float32)
+    losses = np.zeros(max(1, epochs), np.float32)
+    cm = _P()
+    _check(lib.coot_costmodel_train(_fptr(feats), _fptr(target), _fptr(mask), len(target), _fptr(init_params), h1, h2,
+                                    epochs, batch, seed, lr, _fptr(losses), stream, C.byref(cm)))
+    return cm.value, losses[:epochs]
+
+
+def coot_costmodel_predict(cm: int, h: int, n_rows: int, n_cols: int, red: int, cfgs, stream: int = 0):
+    import numpy as np
+    pred = np.zeros(len(cfgs), np.float32)
+    best = C.c_uint32()
+    _check(lib.coot_costmodel_predict(cm, h, n_rows, n_cols, red, _cfgs(cfgs), len(cfgs), _fptr(pred),
+                                      C.byref(best), stream))
+    return int(best.value), pred
+
+
+def coot_costmodel_save(cm: int, path: str) -> None:
+    _check(lib.coot_costmodel_save(cm, path.encode()))
+
+
+def coot_costmodel_load(path: str) -> int:
+    cm = _P()
+    _check(lib.coot_costmodel_load(path.encode(), C.byref(cm)))
+    return cm.value
+
+
+def coot_costmodel_release(cm: int) -> None:
+    lib.coot_costmodel_release(cm)

@@ -92,8 +92,12 @@ struct Request {
   bool comp = true;   // compensated reduction
   Family fam = FAM_FLAT;
   Variant var;
+  bool all_variants = false;  // tuning module: every vec x ept (flat) or vec (tiled) variant
   std::string key() const;
 };
+
+// Kernel name of one variant (the naming convention codegen uses).
+std::string variant_name(const Expr& e, const Request& rq, int vec, int ept);
 
 struct KernelNames {
   std::string stage1, stage1_fallback, stage2, stage1_rescale, stage2_rescale;
@@ -140,6 +144,12 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
                   const coot_operand& out, const coot_launch_cfg* cfg, hipStream_t s);
 Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, int mode, int dim, bool comp,
              const coot_launch_cfg* cfg);
+
+int64_t ld_of(const coot_operand& o);
+bool vec_ok(const Expr& e, const Request& rq, const coot_operand* ops, const coot_operand* out, int64_t R, int64_t C);
+void fill_args(const Expr& e, const coot_operand* ops, const double* scalars, KArgs* a);
+unsigned flat_grid(int64_t n, int V, int E, int bs, int gm);
+unsigned tile_grid(int64_t R, int64_t C, int ts, int gm);
 
 // Thread-local message behind coot_last_error().
 std::string& last_error();

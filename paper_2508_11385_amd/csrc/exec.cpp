@@ -99,7 +99,7 @@ void launch(hipFunction_t f, unsigned grid, unsigned block, const KArgs& args, h
 }
 
 // ---- planning ------------------------------------------------------------------
-static int64_t ld_of(const coot_operand& o) { return o.ld ? o.ld : (o.n_rows > 0 ? o.n_rows : 1); }
+int64_t ld_of(const coot_operand& o) { return o.ld ? o.ld : (o.n_rows > 0 ? o.n_rows : 1); }
 
 static bool contiguous(const coot_operand& o) { return ld_of(o) == o.n_rows || o.n_cols <= 1; }
 
@@ -135,7 +135,7 @@ Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, in
 
 // Can the V-wide kernel run on these operands?  Every access must be aligned to
 // V elements: base addresses, leading dimensions and the contiguous extents.
-static bool vec_ok(const Expr& e, const Request& rq, const coot_operand* ops, const coot_operand* out, int64_t R,
+bool vec_ok(const Expr& e, const Request& rq, const coot_operand* ops, const coot_operand* out, int64_t R,
                    int64_t C) {
   const int V = rq.var.vec;
   if (V == 1) return true;
@@ -157,7 +157,7 @@ static bool vec_ok(const Expr& e, const Request& rq, const coot_operand* ops, co
   return true;
 }
 
-static void fill_args(const Expr& e, const coot_operand* ops, const double* scalars, KArgs* a) {
+void fill_args(const Expr& e, const coot_operand* ops, const double* scalars, KArgs* a) {
   std::memset(a, 0, sizeof *a);
   for (size_t k = 0; k < e.slots.size(); ++k) {
     a->leaf[k] = ops[k].data;
@@ -185,14 +185,14 @@ static void check_alias(const Expr& e, const coot_operand* ops, const coot_opera
   }
 }
 
-static unsigned flat_grid(int64_t n, int V, int E, int bs, int gm) {
+unsigned flat_grid(int64_t n, int V, int E, int bs, int gm) {
   const int64_t nv = std::max<int64_t>(1, (n + V - 1) / V);
   const int64_t need = (nv + (int64_t)bs * E - 1) / ((int64_t)bs * E);
   const int64_t cap = (int64_t)gm * num_cus();
   return (unsigned)std::max<int64_t>(1, std::min(need, cap));
 }
 
-static unsigned tile_grid(int64_t R, int64_t C, int ts, int gm) {
+unsigned tile_grid(int64_t R, int64_t C, int ts, int gm) {
   const int64_t nt = ((R + ts - 1) / ts) * ((C + ts - 1) / ts);
   const int64_t cap = (int64_t)gm * num_cus();
   return (unsigned)std::max<int64_t>(1, std::min(nt, cap));

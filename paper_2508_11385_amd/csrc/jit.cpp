@@ -150,6 +150,7 @@ static void disk_store(const std::string& key, const std::vector<char>& code) {
 
 // ---- module cache ------------------------------------------------------------
 hipFunction_t Module::fn(const std::string& name) {
+  std::lock_guard<std::mutex> g(global_mutex());
   auto it = fns.find(name);
   if (it != fns.end()) return it->second;
   if (!loaded) fail(COOT_EHIP, "module not loaded on a device");
@@ -171,7 +172,6 @@ std::shared_ptr<Module> get_module(Expr& e, const Request& rq, bool load) {
     auto it = e.reqs.find(rk);
     if (it != e.reqs.end() && (it->second->loaded || !load)) return it->second;
   }
-  std::lock_guard<std::mutex> g(global_mutex());
   KernelNames names;
   const std::string sig = hex128(e.canon);
   const std::string src = generate(e, rq, sig, &names);
@@ -180,30 +180,50 @@ std::shared_ptr<Module> get_module(Expr& e, const Request& rq, bool load) {
   std::string hdr_text;
   for (auto& h : device_headers()) hdr_text += h.second;
   const std::string key = hex128(src + "\n" + opt_text + rtc_version() + hex128(hdr_text));
-  auto& mm = module_map();
   std::shared_ptr<Module> m;
-  auto it = mm.find(key);
-  if (it != mm.end()) {
-    m = it->second;
-    stats().mem_hits += 1;
-  } else {
-    m = std::make_shared<Module>();
-    m->names = names;
-    if (disk_load(key, &m->code)) {
-      stats().disk_hits += 1;
-    } else {
-      auto t0 = std::chrono::steady_clock::now();
-      compile_source(src, names.stage1, &m->code);
-      auto t1 = std::chrono::steady_clock::now();
-      stats().compiles += 1;
-      stats().compile_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
-      disk_store(key, m->code);
+  {
+    std::lock_guard<std::mutex> g(global_mutex());
+    auto& mm = module_map();
+    auto it = mm.find(key);
+    if (it != mm.end()) {
+      m = it->second;
+      stats().mem_hits += 1;
     }
-    mm[key] = m;
   }
-  if (load && !m->loaded) {
-    hip_check(hipModuleLoadData(&m->mod, m->code.data()), "hipModuleLoadData");
-    m->loaded = true;
+  if (!m) {
+    // compile without holding the global lock so that several host threads can compile at once
+    auto fresh = std::make_shared<Module>();
+    fresh->names = names;
+    bool from_disk = disk_load(key, &fresh->code);
+    double ms = 0;
+    if (!from_disk) {
+      auto t0 = std::chrono::steady_clock::now();
+      compile_source(src, names.stage1, &fresh->code);
+      auto t1 = std::chrono::steady_clock::now();
+      ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+      disk_store(key, fresh->code);
+    }
+    std::lock_guard<std::mutex> g(global_mutex());
+    auto& mm = module_map();
+    auto it = mm.find(key);
+    if (it != mm.end()) {
+      m = it->second;  // another thread finished first
+    } else {
+      m = fresh;
+      mm[key] = m;
+    }
+    if (from_disk) stats().disk_hits += 1;
+    else {
+      stats().compiles += 1;
+      stats().compile_ms += ms;
+    }
+  }
+  if (load) {
+    std::lock_guard<std::mutex> g(global_mutex());
+    if (!m->loaded) {
+      hip_check(hipModuleLoadData(&m->mod, m->code.data()), "hipModuleLoadData");
+      m->loaded = true;
+    }
   }
   std::lock_guard<std::mutex> g2(e.mu);
   e.reqs[rk] = m;

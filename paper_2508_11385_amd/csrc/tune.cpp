@@ -1,0 +1,181 @@
+// Autotuning of the fused kernels' launch configuration.
+//
+// A configuration is (vec, ept, waves, grid_mult): elements per 128-bit group,
+// groups in flight per thread, wavefronts per workgroup and workgroups per CU.
+// vec and ept are compile-time (one tuning module per signature holds every
+// variant), waves and grid_mult are launch parameters.  The tiled family runs
+// 256-thread workgroups, so only vec and grid_mult vary there.
+// Timing: one warm-up launch, then `reps` launches each bracketed by HIP events
+// on the caller's stream, optionally after a 512 MiB write that evicts L2 and the
+// Infinity Cache; the median is reported.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "core.h"
+
+extern "C" hipError_t coot_flush_launch(void* buf, size_t bytes, unsigned v, hipStream_t s);
+
+using namespace coot;
+
+namespace {
+
+constexpr size_t kFlushBytes = 512u << 20;
+
+bool tune_mode_ok(int mode) { return mode == -1 || mode == COOT_RED_ACCU; }
+
+struct Prepared {
+  Request rq;
+  std::shared_ptr<Module> m;
+  int64_t R = 0, C = 0;
+};
+
+Prepared prepare(Expr& e, const coot_operand* ops, const coot_operand* out, int mode, bool load) {
+  if (!tune_mode_ok(mode)) fail(COOT_EUNSUPPORTED, "tuning covers element-wise evaluation and accu");
+  Prepared p;
+  check_operands(e, ops);
+  infer_shape(e, ops, &p.R, &p.C);
+  int m = mode;
+  if (mode == COOT_RED_ACCU && e.root_schur) m = COOT_RED_DOT;
+  p.rq = plan(e, ops, mode < 0 ? out : nullptr, m, -1, true, nullptr);
+  p.rq.all_variants = true;
+  p.rq.var.vec = 4;
+  p.rq.var.ept = p.rq.fam == FAM_FLAT ? 4 : 0;
+  p.m = get_module(e, p.rq, load);
+  return p;
+}
+
+// Launch one configuration (returns false if it cannot run on these operands).
+bool launch_cfg(Expr& e, Prepared& p, const coot_launch_cfg& c, const coot_operand* ops, const double* scalars,
+                const coot_operand* out, hipStream_t s) {
+  Request rq = p.rq;
+  rq.var.vec = c.vec;
+  if (rq.fam == FAM_TILE && c.vec > rq.var.ts / 4) return false;
+  if (!vec_ok(e, rq, ops, out, p.R, p.C)) return false;
+  const int ept = rq.fam == FAM_FLAT ? c.ept : 0;
+  hipFunction_t f = p.m->fn(variant_name(e, rq, c.vec, ept));
+  KArgs a;
+  fill_args(e, ops, scalars, &a);
+  a.n_rows = p.R;
+  a.n_cols = p.C;
+  unsigned grid, block;
+  if (rq.fam == FAM_FLAT) {
+    block = 64u * c.waves;
+    grid = flat_grid(p.R * p.C, c.vec, c.ept, (int)block, c.grid_mult);
+  } else {
+    block = 256;
+    grid = tile_grid(p.R, p.C, rq.var.ts, c.grid_mult);
+  }
+  if (rq.mode < 0) {
+    a.out = out->data;
+    a.out_ld = ld_of(*out);
+    launch(f, grid, block, a, s);
+  } else {
+    a.out = out->data;
+    a.n_part = grid;
+    a.ws = workspace((size_t)grid * 32, s, 2);
+    a.ws2 = workspace(64 + (size_t)grid * 32, s, 3);
+    launch(f, grid, block, a, s);
+    launch(p.m->fn(p.m->names.stage2), 1, 256, a, s);
+  }
+  return true;
+}
+
+bool valid_cfg(const coot_launch_cfg& c) {
+  auto pow2 = [](int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; };
+  return pow2(c.vec, 1, 4) && pow2(c.ept, 1, 8) && pow2(c.waves, 1, 8) && pow2(c.grid_mult, 1, 16);
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t coot_tune_space(int32_t family, coot_launch_cfg* cfgs, uint32_t cap) {
+  std::vector<coot_launch_cfg> v;
+  for (uint16_t vec : {1, 2, 4})
+    for (uint16_t ept : {1, 2, 4, 8})
+      for (uint16_t waves : {1, 2, 4, 8})
+        for (uint16_t gm : {2, 4, 8, 16}) {
+          if (family == 1 && (ept != 1 || waves != 4)) continue;
+          v.push_back({vec, ept, waves, gm});
+        }
+  if (cfgs)
+    for (uint32_t i = 0; i < std::min<uint32_t>(cap, (uint32_t)v.size()); ++i) cfgs[i] = v[i];
+  return (uint32_t)v.size();
+}
+
+coot_status coot_tune_prepare(coot_expr* h, const coot_operand* operands, int32_t mode, int32_t* family) {
+  return guarded([&] {
+    if (!h) fail(COOT_EINVAL, "NULL expression");
+    Prepared p = prepare(*h->e, operands, nullptr, mode, false);
+    if (family) *family = p.rq.fam == FAM_FLAT ? 0 : 1;
+  });
+}
+
+coot_status coot_tune_table(coot_expr* h, const coot_operand* operands, const double* scalars, coot_operand* out,
+                            int32_t mode, const coot_launch_cfg* cfgs, uint32_t n_cfgs, uint32_t reps, int32_t flush,
+                            float* times_us, void* stream) {
+  return guarded([&] {
+    if (!h || !out || (n_cfgs && (!cfgs || !times_us))) fail(COOT_EINVAL, "NULL argument");
+    if (reps == 0 || reps > 101) fail(COOT_EINVAL, "reps must be 1..101");
+    Expr& e = *h->e;
+    hipStream_t s = (hipStream_t)stream;
+    if (mode < 0) {
+      int64_t R, C;
+      check_operands(e, operands);
+      infer_shape(e, operands, &R, &C);
+      if (out->n_rows != R || out->n_cols != C || out->dtype != e.dtype) fail(COOT_ESHAPE, "output shape");
+    } else if (out->n_rows * out->n_cols != 1 || out->dtype != e.dtype) {
+      fail(COOT_ESHAPE, "accu writes one element");
+    }
+    Prepared p = prepare(e, operands, out, mode, true);
+    void* fbuf = flush ? workspace(kFlushBytes, s, 4) : nullptr;
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "hipEventCreate");
+    hip_check(hipEventCreate(&e1), "hipEventCreate");
+    unsigned fv = 1;
+    try {
+      for (uint32_t k = 0; k < n_cfgs; ++k) {
+        const coot_launch_cfg& c = cfgs[k];
+        if (!valid_cfg(c)) fail(COOT_EINVAL, "invalid launch configuration");
+        if (!launch_cfg(e, p, c, operands, scalars, out, s)) {  // warm-up, also the validity test
+          times_us[k] = NAN;
+          continue;
+        }
+        std::vector<float> t;
+        for (uint32_t r = 0; r < reps; ++r) {
+          if (fbuf) hip_check(coot_flush_launch(fbuf, kFlushBytes, fv++, s), "flush");
+          hip_check(hipEventRecord(e0, s), "hipEventRecord");
+          launch_cfg(e, p, c, operands, scalars, out, s);
+          hip_check(hipEventRecord(e1, s), "hipEventRecord");
+          hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+          float ms = 0;
+          hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+          t.push_back(ms * 1000.0f);
+        }
+        std::sort(t.begin(), t.end());
+        times_us[k] = t[t.size() / 2];
+      }
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  });
+}
+
+// Launch with an explicit configuration through the tuning module (no extra compile).
+coot_status coot_tune_launch(coot_expr* h, const coot_operand* operands, const double* scalars, coot_operand* out,
+                             int32_t mode, const coot_launch_cfg* cfg, void* stream) {
+  return guarded([&] {
+    if (!h || !out || !cfg) fail(COOT_EINVAL, "NULL argument");
+    if (!valid_cfg(*cfg)) fail(COOT_EINVAL, "invalid launch configuration");
+    Prepared p = prepare(*h->e, operands, out, mode, true);
+    if (!launch_cfg(*h->e, p, *cfg, operands, scalars, out, (hipStream_t)stream))
+      fail(COOT_EINVAL, "configuration not valid for these operands");
+  });
+}
+
+}  // extern "C"

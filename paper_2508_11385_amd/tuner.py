@@ -1,0 +1,154 @@
+"""Learned launch-configuration tuner: timing data, training, evaluation.
+
+The system produces its own training data: random expression signatures
+(random trees of depth 1-8 over 2-5 operands, rows and cols log-uniform in
+[1, 16384], element types u32 / s32 / f32 / f64, element-wise or accu) are timed
+by the autotuner (coot_tune_table) under sampled launch configurations; a cost
+model (coot_costmodel_train: MLP forward / backward / Adam kernels on the GPU)
+learns log(time) from the 17 features; on held-out signatures its argmin is
+compared with exhaustive autotuning (regret = t(pick) / t(best) - 1).
+
+Orchestration only: every timing, the training and the inference run through
+libcoot's entry points.
+"""
+from __future__ import annotations
+
+import math
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import torch
+
+import synth
+from . import _coot as cc
+from . import frontend
+
+TORCH = {"f32": torch.float32, "f64": torch.float64, "u32": torch.int32, "s32": torch.int32}
+
+
+def sample_signatures(n: int, seed: int, depth_hi: int = 8, dim_hi: int = 16384, p_accu: float = 0.2):
+    """(TreeSpec, mode) pairs: mode -1 element-wise, 0 accu."""
+    g = synth.rng_for(5, seed)
+    out = []
+    for _ in range(n):
+        dt = ("u32", "s32", "f32", "f64")[int(g.integers(0, 4))]
+        r = synth.log_uniform_int(g, 1, dim_hi)
+        c = synth.log_uniform_int(g, 1, dim_hi)
+        spec = synth.random_tree(g, int(g.integers(1, depth_hi + 1)), int(g.integers(2, 6)), r, c, dt)
+        mode = 0 if g.random() < p_accu else -1
+        out.append((spec, mode))
+    return out
+
+
+def _handle(spec):
+    slots = [(cc.DTYPE_CODE[spec.dtype], cc.COOT_MAT)] * len(spec.slot_shapes)
+    return cc.coot_expr_compile(spec.postfix, slots, len(spec.scalars))
+
+
+def _fake_operands(spec):
+    """Descriptors with the real shapes and an aligned placeholder address (planning only)."""
+    return [cc.coot_operand(0x100000, r, c, max(1, r), cc.DTYPE_CODE[spec.dtype], cc.COOT_MAT)
+            for r, c in spec.slot_shapes]
+
+
+def prepare_all(sigs, threads: int = 16):
+    """Compile every signature's tuning module on `threads` host threads; returns (handles, families)."""
+    handles = [_handle(s) for s, _ in sigs]
+
+    def prep(i):
+        spec, mode = sigs[i]
+        return cc.coot_tune_prepare(handles[i], _fake_operands(spec), mode)
+
+    with ThreadPoolExecutor(threads) as ex:
+        fams = list(ex.map(prep, range(len(sigs))))
+    return handles, fams
+
+
+def _operands(spec, g):
+    mats = []
+    for r, c in spec.slot_shapes:
+        store = torch.empty((c, r), dtype=TORCH[spec.dtype], device="cuda")
+        if spec.dtype in ("f32", "f64"):
+            store.uniform_(-1.0, 1.0, generator=g)
+        else:
+            store.random_(0, 1 << 16, generator=g)
+        mats.append(frontend.Mat(store.t(), spec.dtype))
+    return mats
+
+
+def time_signature(h, spec, mode, cfgs, reps=3, flush=False, seed=0):
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    mats = _operands(spec, g)
+    r, c = spec.out_shape
+    out = frontend.Mat.empty(r, c, spec.dtype) if mode < 0 else frontend.Mat.empty(1, 1, spec.dtype)
+    t = cc.coot_tune_table(h, [m.operand() for m in mats], spec.scalars, out.operand(), mode, cfgs, reps, flush,
+                           torch.cuda.current_stream().cuda_stream)
+    del mats, out
+    return np.asarray(t, np.float64)
+
+
+def build_dataset(sigs, handles, fams, configs_per_sig=None, seed=0, log=None):
+    """Rows of (features, log time) for every timed (signature, configuration)."""
+    spaces = {0: cc.coot_tune_space(0), 1: cc.coot_tune_space(1)}
+    g = np.random.default_rng(seed)
+    feats, target, tables = [], [], []
+    t0 = time.time()
+    for i, ((spec, mode), h, fam) in enumerate(zip(sigs, handles, fams)):
+        space = spaces[fam]
+        if configs_per_sig is None or configs_per_sig >= len(space):
+            cfgs = space
+        else:
+            cfgs = [space[k] for k in sorted(g.choice(len(space), configs_per_sig, replace=False))]
+        t = time_signature(h, spec, mode, cfgs, seed=seed * 100003 + i)
+        red = 0 if mode < 0 else 1
+        f = cc.coot_costmodel_features(h, spec.out_shape[0], spec.out_shape[1], red, cfgs)
+        ok = np.isfinite(t) & (t > 0)
+        feats.append(f[ok])
+        target.append(np.log(t[ok]))
+        tables.append((cfgs, t))
+        if log and (i + 1) % 100 == 0:
+            log(f"timed {i + 1}/{len(sigs)} signatures ({time.time() - t0:.0f} s)")
+    return np.concatenate(feats).astype(np.float32), np.concatenate(target).astype(np.float32), tables
+
+
+def he_init(seed: int, f: int = 17, h1: int = 64, h2: int = 64):
+    """He-normal initial parameters (weights N(0, 2/fan_in), biases 0), flat in the library's order."""
+    g = synth.rng_for(6, seed)
+    parts = [g.normal(0, math.sqrt(2 / f), (h1, f)), np.zeros(h1), g.normal(0, math.sqrt(2 / h1), (h2, h1)),
+             np.zeros(h2), g.normal(0, math.sqrt(2 / h2), (1, h2)), np.zeros(1)]
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+
+
+def regrets(tables, picks):
+    """t(pick) / t(best) - 1 per signature (NaN-safe), from the exhaustive timing tables."""
+    out = []
+    for (cfgs, t), k in zip(tables, picks):
+        best = np.nanmin(t)
+        tk = t[k] if np.isfinite(t[k]) else np.nanmax(t)
+        out.append(tk / best - 1.0)
+    return np.asarray(out)
+
+
+def summarize(r):
+    g = float(np.exp(np.mean(np.log1p(r))) - 1.0)
+    return {"geomean": g, "p90": float(np.percentile(r, 90)), "max": float(np.max(r)),
+            "within_5pct": float(np.mean(r <= 0.05))}
+
+
+def default_index(cfgs, dtype):
+    want = (2 if dtype == "f64" else 4, 4, 4, 8) if len(cfgs) > 12 else (2 if dtype == "f64" else 4, 1, 4, 16)
+    return cfgs.index(want) if want in cfgs else 0
+
+
+def evaluate(cm, sigs, handles, tables):
+    """Cost-model picks vs exhaustive; also the default configuration and an untrained network."""
+    picks, t_pred = [], 0.0
+    for (spec, mode), h, (cfgs, t) in zip(sigs, handles, tables):
+        t0 = time.perf_counter()
+        k, _ = cc.coot_costmodel_predict(cm, h, spec.out_shape[0], spec.out_shape[1], 0 if mode < 0 else 1, cfgs)
+        t_pred += time.perf_counter() - t0
+        picks.append(k)
+    dflt = [default_index(cfgs, s.dtype) for (s, _), (cfgs, _t) in zip(sigs, tables)]
+    return regrets(tables, picks), regrets(tables, dflt), t_pred / max(1, len(sigs))

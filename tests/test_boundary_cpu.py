@@ -2,6 +2,8 @@
 header declares, validates expressions and shapes, and every generated kernel
 family compiles for gfx950 through hipRTC (no device needed)."""
 import ctypes
+
+import numpy as np
 import os
 import re
 
@@ -144,3 +146,34 @@ def test_random_trees_generate_and_leaf_parities(cc):
         transposed_slots = {k for k, (r, c) in enumerate(spec.slot_shapes) if (r, c) == (13, 9)}
         assert n_p1 == len(transposed_slots)
         cc.coot_expr_release(h)
+
+
+def test_costmodel_features_match_oracle_definition(cc):
+    from oracle import features as of
+    g = synth.rng_for(78)
+    space = cc.coot_tune_space(0)
+    assert len(space) == 192 and len(cc.coot_tune_space(1)) == 12
+    for trial in range(25):
+        dt = ["u32", "s32", "f32", "f64"][trial % 4]
+        r, c = int(g.integers(1, 20000)), int(g.integers(1, 20000))
+        spec = synth.random_tree(g, int(g.integers(1, 9)), int(g.integers(2, 6)), 7, 7, dt)
+        h = cc.coot_expr_compile(spec.postfix, [(cc.DTYPE_CODE[dt], 0)] * len(spec.slot_shapes), len(spec.scalars))
+        red = trial % 4
+        cfgs = [space[k] for k in g.integers(0, len(space), 7)]
+        got = cc.coot_costmodel_features(h, r, c, red, cfgs)
+        for k, cfg in enumerate(cfgs):
+            want = of.features(spec.postfix, dt, r, c, of.RED_ORDER[red], cfg)
+            assert np.allclose(got[k], want, rtol=1e-6, atol=1e-6), (spec.postfix, got[k], want)
+        cc.coot_expr_release(h)
+
+
+def test_tuning_module_compiles_every_variant(cc):
+    h = cc.coot_expr_compile(W, _ops(2), 1)
+    assert cc.coot_tune_prepare(h, [_opnd(cc, 100, 50)] * 2, -1) == 0
+    hz = cc.coot_expr_compile(Z, _ops(4), 1)
+    assert cc.coot_tune_prepare(hz, [_opnd(cc, 100, 50)] * 3 + [_opnd(cc, 50, 100)], -1) == 1
+    hd = cc.coot_expr_compile([("load", 0), ("load", 1), ("schur",)], _ops(2), 0)
+    assert cc.coot_tune_prepare(hd, [_opnd(cc, 1000, 1)] * 2, 0) == 0
+    with pytest.raises(cc.CootError) as e:
+        cc.coot_tune_prepare(hd, [_opnd(cc, 1000, 1)] * 2, 1)
+    assert e.value.status == cc.COOT_EUNSUPPORTED

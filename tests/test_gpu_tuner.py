@@ -1,0 +1,167 @@
+"""The learned tuner on the GPU: MLP forward / gradients / Adam against the binary64
+oracle, training, the autotuner's timing table and its policies."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import mlp as om
+from oracle import elementwise as ew
+
+pytestmark = pytest.mark.gpu
+
+F, H1, H2 = 17, 64, 64
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2508_11385_amd as coot
+    from paper_2508_11385_amd import _coot as cc
+    coot.init(0)
+    torch.cuda.synchronize()
+    return coot, cc, torch
+
+
+def _init_params(seed, f=F, h1=H1, h2=H2):
+    """He-initialised weights drawn on the host (the random numbers are inputs to both sides)."""
+    g = synth.rng_for(40, seed)
+    p = {"W1": g.normal(0, math.sqrt(2 / f), (h1, f)), "b1": g.normal(0, 0.05, h1),
+         "W2": g.normal(0, math.sqrt(2 / h1), (h2, h1)), "b2": g.normal(0, 0.05, h2),
+         "W3": g.normal(0, math.sqrt(2 / h2), (1, h2)), "b3": g.normal(0, 0.05, 1)}
+    p = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+    flat = np.concatenate([p[k].ravel() for k in om.PARAM_ORDER]).astype(np.float32)
+    return p, flat
+
+
+def _unflat(flat, f=F, h1=H1, h2=H2):
+    shapes = {"W1": (h1, f), "b1": (h1,), "W2": (h2, h1), "b2": (h2,), "W3": (1, h2), "b3": (1,)}
+    out, o = {}, 0
+    for k in om.PARAM_ORDER:
+        n = int(np.prod(shapes[k]))
+        out[k] = flat[o:o + n].reshape(shapes[k]).astype(np.float64)
+        o += n
+    return out
+
+
+def _batch(seed, B):
+    g = synth.rng_for(41, seed)
+    X = g.normal(size=(B, F)).astype(np.float32)
+    y = g.normal(size=B).astype(np.float32)
+    mask = (g.uniform(size=B) < 0.85).astype(np.float32)
+    return X, y, mask
+
+
+def test_forward_and_gradients_match_oracle(env):
+    coot, cc, torch = env
+    p, flat = _init_params(1)
+    X, y, mask = _batch(1, 96)
+    m = cc.coot_mlp_create(F, H1, H2, flat)
+    dX, dy, dm = (torch.from_numpy(a).cuda() for a in (X, y, mask))
+    out = torch.empty(96, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    cc.coot_mlp_forward(m, dX.data_ptr(), 96, out.data_ptr())
+    ref_out, cache = om.forward(p, X.astype(np.float64))
+    assert np.allclose(out.cpu().numpy(), ref_out, rtol=1e-5, atol=1e-5)
+    inv = 1.0 / float(mask.sum())
+    cc.coot_mlp_backward(m, dX.data_ptr(), dy.data_ptr(), dm.data_ptr(), 96, inv, loss.data_ptr())
+    torch.cuda.synchronize()
+    assert abs(loss.item() - om.loss(ref_out, y, mask)) <= 1e-5 * max(1.0, om.loss(ref_out, y, mask))
+    g = _unflat(cc.coot_mlp_get_grads(m))
+    ref = om.backward(p, cache, ref_out, y.astype(np.float64), mask.astype(np.float64))
+    for k in om.PARAM_ORDER:
+        err = np.linalg.norm(g[k] - ref[k]) / max(np.linalg.norm(ref[k]), 1e-30)
+        assert err <= 1e-4, (k, err)
+    cc.coot_mlp_release(m)
+
+
+def test_adam_step_matches_oracle(env):
+    coot, cc, torch = env
+    p, flat = _init_params(2)
+    X, y, mask = _batch(2, 64)
+    m = cc.coot_mlp_create(F, H1, H2, flat)
+    dX, dy, dm = (torch.from_numpy(a).cuda() for a in (X, y, mask))
+    inv = 1.0 / float(mask.sum())
+    pp = {k: v.copy() for k, v in p.items()}
+    mom, vel = om.zeros_like(pp), om.zeros_like(pp)
+    for t in (1, 2, 3):
+        cc.coot_mlp_backward(m, dX.data_ptr(), dy.data_ptr(), dm.data_ptr(), 64, inv)
+        cc.coot_mlp_adam_step(m, 1e-3, 0.9, 0.999, 1e-8, t)
+        out, cache = om.forward(pp, X.astype(np.float64))
+        gr = om.backward(pp, cache, out, y.astype(np.float64), mask.astype(np.float64))
+        pp, mom, vel = om.adam_step(pp, gr, mom, vel, t)
+    got = _unflat(cc.coot_mlp_get_params(m))
+    for k in om.PARAM_ORDER:
+        # each Adam step moves a parameter by about lr; fp32 vs fp64 differ far below that
+        assert np.max(np.abs(got[k] - pp[k])) <= 2e-5, k
+    cc.coot_mlp_release(m)
+
+
+def test_training_reduces_loss(env):
+    coot, cc, torch = env
+    _, flat = _init_params(3)
+    g = synth.rng_for(42)
+    X = g.normal(size=(2048, F)).astype(np.float32)
+    w = g.normal(size=F)
+    y = (np.tanh(X @ w * 0.3) + 0.1 * X[:, 0] ** 2).astype(np.float32)
+    mask = np.ones(2048, np.float32)
+    m = cc.coot_mlp_create(F, H1, H2, flat)
+    dX, dy, dm = (torch.from_numpy(a).cuda() for a in (X, y, mask))
+    losses = cc.coot_mlp_train(m, dX.data_ptr(), dy.data_ptr(), dm.data_ptr(), mask, 2048, 256, 40, 7, 3e-3)
+    assert losses[-1] < 0.2 * losses[0], losses
+    cc.coot_mlp_release(m)
+
+
+def test_tune_table_and_policies(env):
+    coot, cc, torch = env
+    A, B, C, D = synth.matrix_inputs(n_rows=1000, n_cols=300)
+    gA, gB = coot.Mat.from_numpy(A), coot.Mat.from_numpy(B)
+    e = coot.exp(gA) / (1.0 + coot.abs(gB))
+    flat = coot.flatten(e)
+    h = coot.frontend.compiled(flat)
+    ops = [m_.operand() for m_ in flat.mats]
+    out = coot.Mat.empty(1000, 300)
+    fam = cc.coot_tune_prepare(h, ops, -1)
+    space = cc.coot_tune_space(fam)
+    t = cc.coot_tune_table(h, ops, flat.scalars, out.operand(), -1, space, reps=3, flush=True)
+    assert len(t) == len(space) and all(x > 0 for x in t if not math.isnan(x))
+    want = ew.evaluate(flat.postfix, [A, B], flat.scalars, "f32")
+    for cfg in (space[0], space[len(space) // 2], space[-1]):
+        out.tensor.zero_()
+        cc.coot_tune_launch(h, ops, flat.scalars, out.operand(), -1, cfg)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.numpy(), want)
+    best, us = cc.coot_tune(h, ops, flat.scalars, out.operand(), -1, 1)
+    assert best in space and us > 0
+    dflt, us_d = cc.coot_tune(h, ops, flat.scalars, out.operand(), -1, 0)
+    assert us <= us_d * 1.5
+    # accu through the tuning module matches the fused reduction
+    hx = coot.frontend.compiled(coot.flatten(gA % gB))
+    acc = coot.Mat.empty(1, 1)
+    cc.coot_tune_launch(hx, [gA.operand(), gB.operand()], [], acc.operand(), 0, (4, 4, 4, 8))
+    ref = coot.accu(gA % gB).numpy()[0, 0]
+    torch.cuda.synchronize()
+    assert acc.numpy()[0, 0] == ref
+
+
+def test_costmodel_roundtrip_and_prediction(env, tmp_path):
+    coot, cc, torch = env
+    _, flat = _init_params(4)
+    g = synth.rng_for(43)
+    X = g.normal(size=(512, F)).astype(np.float32)
+    y = (X[:, 6] + 0.5 * X[:, 13]).astype(np.float32)     # depends on rows and vec
+    mask = np.ones(512, np.float32)
+    cm, losses = cc.coot_costmodel_train(X, y, mask, flat, H1, H2, 30, 128, 5, 3e-3)
+    assert losses[-1] < losses[0]
+    h = cc.coot_expr_compile([("load", 0), ("load", 1), ("add",)], [(cc.COOT_F32, 0)] * 2, 0)
+    space = cc.coot_tune_space(0)
+    best, pred = cc.coot_costmodel_predict(cm, h, 4096, 4096, 0, space)
+    assert 0 <= best < len(space) and np.all(pred > 0) and pred[best] == pred.min()
+    path = str(tmp_path / "cm.bin")
+    cc.coot_costmodel_save(cm, path)
+    cm2 = cc.coot_costmodel_load(path)
+    best2, pred2 = cc.coot_costmodel_predict(cm2, h, 4096, 4096, 0, space)
+    assert best2 == best and np.array_equal(pred, pred2)
+    cc.coot_costmodel_release(cm)
+    cc.coot_costmodel_release(cm2)
