@@ -292,18 +292,19 @@ def bench_tuner(args):
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
+    os.environ.setdefault("COOT_CACHE_DIR", "/tmp/coot_cache")   # shared by the compile workers
     train = tuner.sample_signatures(args.tuner_train, seed=1)
     test = tuner.sample_signatures(args.tuner_test, seed=2)
     t0 = time.perf_counter()
-    h_tr, f_tr = tuner.prepare_all(train)
-    h_te, f_te = tuner.prepare_all(test)
+    h_tr, f_tr = tuner.prepare_all(train, log=log)
+    h_te, f_te = tuner.prepare_all(test, log=log)
     t_compile = time.perf_counter() - t0
     log(f"compiled {len(train) + len(test)} tuning modules in {t_compile:.0f} s")
     t0 = time.perf_counter()
     X, y, _ = tuner.build_dataset(train, h_tr, f_tr, configs_per_sig=args.tuner_cfgs, seed=11, log=log)
     t_train_data = time.perf_counter() - t0
     t0 = time.perf_counter()
-    _, _, tables = tuner.build_dataset(test, h_te, f_te, configs_per_sig=None, seed=12, log=log)
+    _, _, tables = tuner.build_dataset(test, h_te, f_te, configs_per_sig=None, seed=12, log=log, reps=5)
     t_exh = time.perf_counter() - t0
     n_exh = int(sum(len(c) for c, _ in tables))
     log(f"{len(y)} training timings in {t_train_data:.0f} s; {n_exh} held-out timings in {t_exh:.0f} s")

@@ -14,6 +14,8 @@ libcoot's entry points.
 from __future__ import annotations
 
 import math
+import multiprocessing as mp
+import os
 import time
 from concurrent.futures import ThreadPoolExecutor
 
@@ -52,16 +54,34 @@ def _fake_operands(spec):
             for r, c in spec.slot_shapes]
 
 
-def prepare_all(sigs, threads: int = 16):
-    """Compile every signature's tuning module on `threads` host threads; returns (handles, families)."""
+def _compile_worker(job):
+    """Spawned process: compile one tuning module into the on-disk code-object cache (no device use)."""
+    postfix, dtype, shapes, n_sc, mode = job
+    from paper_2508_11385_amd import _coot as c2
+    slots = [(c2.DTYPE_CODE[dtype], c2.COOT_MAT)] * len(shapes)
+    h = c2.coot_expr_compile(postfix, slots, n_sc)
+    ops = [c2.coot_operand(0x100000, r, c, max(1, r), c2.DTYPE_CODE[dtype], c2.COOT_MAT) for r, c in shapes]
+    fam = c2.coot_tune_prepare(h, ops, mode)
+    c2.coot_expr_release(h)
+    return fam
+
+
+def prepare_all(sigs, workers: int = 16, log=None):
+    """Compile every signature's tuning module; returns (handles, families).
+
+    hipRTC compilations do not overlap across threads of one process, so they run in
+    `workers` spawned processes that fill the on-disk code-object cache; this process
+    then loads every module from that cache.
+    """
+    jobs = [(s.postfix, s.dtype, s.slot_shapes, len(s.scalars), m) for s, m in sigs]
+    if workers > 1 and len(jobs) > 1 and not os.environ.get("COOT_NO_DISK_CACHE"):
+        t0 = time.time()
+        with mp.get_context("spawn").Pool(workers) as pool:
+            for k, _ in enumerate(pool.imap_unordered(_compile_worker, jobs, chunksize=4), start=1):
+                if log and k % 200 == 0:
+                    log(f"compiled {k}/{len(jobs)} tuning modules ({time.time() - t0:.0f} s)")
     handles = [_handle(s) for s, _ in sigs]
-
-    def prep(i):
-        spec, mode = sigs[i]
-        return cc.coot_tune_prepare(handles[i], _fake_operands(spec), mode)
-
-    with ThreadPoolExecutor(threads) as ex:
-        fams = list(ex.map(prep, range(len(sigs))))
+    fams = [cc.coot_tune_prepare(h, _fake_operands(s), m) for h, (s, m) in zip(handles, sigs)]
     return handles, fams
 
 
@@ -89,8 +109,12 @@ def time_signature(h, spec, mode, cfgs, reps=3, flush=False, seed=0):
     return np.asarray(t, np.float64)
 
 
-def build_dataset(sigs, handles, fams, configs_per_sig=None, seed=0, log=None):
-    """Rows of (features, log time) for every timed (signature, configuration)."""
+def build_dataset(sigs, handles, fams, configs_per_sig=None, seed=0, log=None, reps=3, relative=True):
+    """Rows of (features, log time) for every timed (signature, configuration).
+
+    relative: the target is log(time) minus the mean log(time) of the signature's timed
+    configurations (its geometric-mean time), so the network learns how the configuration
+    changes the time of a given expression on a given shape."""
     spaces = {0: cc.coot_tune_space(0), 1: cc.coot_tune_space(1)}
     g = np.random.default_rng(seed)
     feats, target, tables = [], [], []
@@ -101,12 +125,14 @@ def build_dataset(sigs, handles, fams, configs_per_sig=None, seed=0, log=None):
             cfgs = space
         else:
             cfgs = [space[k] for k in sorted(g.choice(len(space), configs_per_sig, replace=False))]
-        t = time_signature(h, spec, mode, cfgs, seed=seed * 100003 + i)
+        t = time_signature(h, spec, mode, cfgs, reps=reps, seed=seed * 100003 + i)
         red = 0 if mode < 0 else 1
         f = cc.coot_costmodel_features(h, spec.out_shape[0], spec.out_shape[1], red, cfgs)
         ok = np.isfinite(t) & (t > 0)
+        lt = np.log(t[ok])
         feats.append(f[ok])
-        target.append(np.log(t[ok]))
+        # relative log-time within the signature: the argmin only needs the ranking of its configurations
+        target.append(lt - lt.mean() if relative else lt)
         tables.append((cfgs, t))
         if log and (i + 1) % 100 == 0:
             log(f"timed {i + 1}/{len(sigs)} signatures ({time.time() - t0:.0f} s)")
