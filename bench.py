@@ -43,6 +43,8 @@ def parse():
     p.add_argument("--tuner-test", type=int, default=2000, help="held-out signatures (timed exhaustively)")
     p.add_argument("--tuner-cfgs", type=int, default=50, help="configurations timed per training signature")
     p.add_argument("--tuner-epochs", type=int, default=200)
+    p.add_argument("--tuner-reps", type=int, default=5, help="timing rounds per configuration")
+    p.add_argument("--tuner-dump", default="", help="write the timing tables here (.npz)")
     p.add_argument("--tuner-out", default=os.path.join(ROOT, "gpurun_out", "costmodel_mi355x.bin"))
     p.add_argument("--profile-kernels", action="store_true",
                    help="run the copy probe and each kernel of one step 3 times, print their names, exit")
@@ -301,39 +303,58 @@ def bench_tuner(args):
     t_compile = time.perf_counter() - t0
     log(f"compiled {len(train) + len(test)} tuning modules in {t_compile:.0f} s")
     t0 = time.perf_counter()
-    X, y, _ = tuner.build_dataset(train, h_tr, f_tr, configs_per_sig=args.tuner_cfgs, seed=11, log=log)
-    t_train_data = time.perf_counter() - t0
+    tab_tr = tuner.time_tables(train, h_tr, f_tr, reps=args.tuner_reps, seed=11, log=log, what="training signatures")
+    t_train_tab = time.perf_counter() - t0
     t0 = time.perf_counter()
-    _, _, tables = tuner.build_dataset(test, h_te, f_te, configs_per_sig=None, seed=12, log=log, reps=5)
+    tab_te = tuner.time_tables(test, h_te, f_te, reps=args.tuner_reps, seed=12, log=log, what="held-out signatures")
     t_exh = time.perf_counter() - t0
-    n_exh = int(sum(len(c) for c, _ in tables))
-    log(f"{len(y)} training timings in {t_train_data:.0f} s; {n_exh} held-out timings in {t_exh:.0f} s")
+    X, y = tuner.dataset(train, h_tr, tab_tr, configs_per_sig=args.tuner_cfgs, seed=13)
+    n_exh = int(sum(np.isfinite(t).sum() for _, t in tab_te))
+    log(f"{len(y)} training timings; {n_exh} held-out timings in {t_exh:.0f} s")
+    if args.tuner_dump:
+        tuner.save_tables(args.tuner_dump, train + test, f_tr + f_te, h_tr + h_te, tab_tr + tab_te,
+                          [0] * len(train) + [1] * len(test))
     init = tuner.he_init(7)
     t0 = time.perf_counter()
     cm, losses = cc.coot_costmodel_train(X, y, np.ones(len(y), np.float32), init, 64, 64, args.tuner_epochs, 256, 7,
                                          1e-3)
     t_fit = time.perf_counter() - t0
-    r_mlp, r_def, t_pred = tuner.evaluate(cm, test, h_te, tables)
+    P, t_pred = tuner.picks(cm, test, h_te, tab_te)
     cm0, _ = cc.coot_costmodel_train(X, y, np.ones(len(y), np.float32), init, 64, 64, 0, 256, 7, 1e-3)
-    r_untrained, _, _ = tuner.evaluate(cm0, test, h_te, tables)
+    P0, _ = tuner.picks(cm0, test, h_te, tab_te)
+    # columns: exhaustive, MLP, default configuration, untrained MLP
+    sets = np.stack([P[:, 0], P[:, 1], P[:, 2], P0[:, 1]], 1)
+    t0 = time.perf_counter()
+    fresh = tuner.retime(test, h_te, tab_te, sets, reps=11, seed=14)
+    t_retime = time.perf_counter() - t0
+    if args.tuner_dump:
+        base = os.path.splitext(args.tuner_dump)[0]
+        np.savez_compressed(base + "_picks.npz", picks=sets, fresh_us=fresh)
     os.makedirs(os.path.dirname(args.tuner_out), exist_ok=True)
     cc.coot_costmodel_save(cm, args.tuner_out)
-    s_mlp, s_def, s_un = tuner.summarize(r_mlp), tuner.summarize(r_def), tuner.summarize(r_untrained)
+    reg = {name: tuner.summarize(fresh[:, j] / fresh[:, 0] - 1.0)
+           for j, name in ((1, "mlp"), (2, "default_config"), (3, "untrained_mlp"))}
+    in_table = {name: tuner.summarize(tuner.regrets_from_table(tab_te, sets[:, j]))
+                for j, name in ((1, "mlp"), (2, "default_config"), (3, "untrained_mlp"))}
+    rnd = lambda d: {k: round(v, 4) for k, v in d.items()}
     out = {
         "metric": "learned tuner: geomean regret of MLP-chosen launch configs vs exhaustive autotune",
-        "value": round(100 * s_mlp["geomean"], 2), "unit": "% regret", "higher_is_better": False, "n_gpus": 1,
+        "value": round(100 * reg["mlp"]["geomean"], 2), "unit": "% regret", "higher_is_better": False, "n_gpus": 1,
         "dtype": "f32 (MLP); u32/s32/f32/f64 expressions",
         "data": "synthetic: random trees depth 1-8, rows/cols log-uniform [1,16384], timings generated on this GPU",
         "config": {"workload": "learned launch-configuration tuner", "train_signatures": len(train),
                    "train_timings": int(len(y)), "test_signatures": len(test), "test_timings": n_exh,
-                   "epochs": args.tuner_epochs, "hidden": [64, 64]},
-        "mlp": {k: round(v, 4) for k, v in s_mlp.items()},
-        "default_config": {k: round(v, 4) for k, v in s_def.items()},
-        "untrained_mlp": {k: round(v, 4) for k, v in s_un.items()},
+                   "epochs": args.tuner_epochs, "hidden": [64, 64], "reps": args.tuner_reps},
+        "regret_definition": "t(pick)/t(exhaustive argmin) - 1, both picks re-timed side by side (11 interleaved "
+                             "rounds of back-to-back launches) after the exhaustive table chose its argmin",
+        "mlp": rnd(reg["mlp"]), "default_config": rnd(reg["default_config"]),
+        "untrained_mlp": rnd(reg["untrained_mlp"]),
+        "regret_within_exhaustive_table": {k: rnd(v) for k, v in in_table.items()},
         "final_train_loss": round(float(losses[-1]), 4), "first_train_loss": round(float(losses[0]), 4),
         "mlp_predict_us_per_signature": round(1e6 * t_pred, 1),
         "exhaustive_tuning_s_per_signature": round(t_exh / len(test), 4),
-        "compile_s": round(t_compile, 1), "train_data_s": round(t_train_data, 1), "fit_s": round(t_fit, 2),
+        "compile_s": round(t_compile, 1), "train_tables_s": round(t_train_tab, 1), "fit_s": round(t_fit, 2),
+        "retime_s": round(t_retime, 1),
     }
     print(json.dumps(out), flush=True)
 

@@ -211,10 +211,12 @@ coot_status coot_expr_kernel_name(coot_expr* e, int32_t mode, int32_t dim, char*
  *   operands[n][...]    each expression's device operands (n_slots of it)
  *   scalars[n][...]     each expression's scalars (host, copied)
  *   outs[n]             caller-allocated device outputs with the inferred dims
- *   cfg                 NULL = default (tile 32 x 32, vectorised where aligned,
- *                       8 workgroups per CU); else waves 1 / 4 / 16 selects tiles of
- *                       16 / 32 / 64, vec = 1 forbids 128-bit accesses, grid_mult
- *                       sets workgroups per CU
+ *   cfg                 NULL = default (tiles of 32 x 32 elements, vectorised
+ *                       where aligned, 8 workgroups per CU); else waves 1 / 4
+ *                       selects tiles of 16 x 16 / 32 x 32 elements (4 per thread),
+ *                       vec = 1 forbids 128-bit accesses, grid_mult sets
+ *                       workgroups per CU.  Expressions with untransposed contiguous
+ *                       leaves are cut into flat chunks of the same element count.
  *   stream              unused at creation (descriptors are uploaded synchronously)
  * All operand and output buffers must stay allocated, at the same addresses, for
  * the life of the batch: their addresses are baked into the descriptors.
@@ -231,15 +233,16 @@ coot_status coot_batch_launch(coot_batch* b, void* stream);
 coot_status coot_batch_launch_each(coot_batch* b, void* stream);
 
 /* Autotune the batch launch on `stream` (synchronises it): times every tile size
- * (16, 32, 64), grid multiplier (2, 4, 8, 16) and vector width (128-bit where
+ * (16, 32), grid multiplier (2, 4, 8, 16) and vector width (128-bit where
  * aligned, or scalar), median of 5 launches each; keeps the fastest and
  * re-captures the graph.  best / best_us may be NULL. */
 coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, float* best_us);
 
 /* info[0] expressions, [1] tiles, [2] algorithmic bytes (each distinct operand
  * read once + outputs written once), [3] tile edge, [4] grid, [5] expressions on
- * the 128-bit path. */
-coot_status coot_batch_info(const coot_batch* b, int64_t info[6]);
+ * the 128-bit path, [6] expressions cut into flat chunks, [7] LDS stack entries
+ * per thread, [8] transposed-leaf tiles staged in LDS per workgroup. */
+coot_status coot_batch_info(const coot_batch* b, int64_t info[9]);
 
 void coot_batch_release(coot_batch* b);
 
@@ -263,10 +266,20 @@ uint32_t coot_tune_space(int32_t family, coot_launch_cfg* cfgs, uint32_t cap);
  * Errors: COOT_EINVAL, COOT_ESHAPE, COOT_ECOMPILE, COOT_EUNSUPPORTED (mode). */
 coot_status coot_tune_prepare(coot_expr* e, const coot_operand* operands, int32_t mode, int32_t* family);
 
-/* Time each configuration: one warm-up launch, then `reps` launches bracketed by
- * HIP events on `stream` (flush != 0: each preceded by a 512 MiB write that
- * evicts L2 and the Infinity Cache); times_us[k] = median, or NaN when the
- * configuration cannot run on these operands (e.g. vec not allowed by alignment).
+/* runnable[k] = 1 when configuration k can run on these operands (its vector
+ * width fits their alignment, leading dimensions and, for the tiled family, the
+ * tile), else 0; no device work.  out is needed for mode -1 (element-wise).
+ * Errors: as coot_tune_prepare, COOT_EINVAL for an invalid configuration. */
+coot_status coot_tune_runnable(coot_expr* e, const coot_operand* operands, const coot_operand* out, int32_t mode,
+                               const coot_launch_cfg* cfgs, uint32_t n_cfgs, int32_t* runnable);
+
+/* Time each configuration: one warm-up launch each, then `reps` rounds (1..101),
+ * each round timing every configuration once with HIP events on `stream` around
+ * enough back-to-back launches to span 40 us (the per-launch time of a repeated
+ * call, launch overhead included); flush != 0 instead times single launches, each
+ * after a 512 MiB write that evicts L2 and the Infinity Cache.  times_us[k] =
+ * median per launch, or NaN when the configuration cannot run on these operands
+ * (e.g. vec not allowed by alignment).
  * Synchronises the stream.  out receives the result as in coot_expr_eval /
  * coot_reduce.  Errors: as coot_expr_eval, COOT_EINVAL for an invalid configuration. */
 coot_status coot_tune_table(coot_expr* e, const coot_operand* operands, const double* scalars, coot_operand* out,

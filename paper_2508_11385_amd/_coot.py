@@ -86,6 +86,8 @@ _sig = {
     "coot_batch_release": (None, [_P]),
     "coot_tune_space": (C.c_uint32, [C.c_int32, C.POINTER(coot_launch_cfg), C.c_uint32]),
     "coot_tune_prepare": (C.c_int, [_P, C.POINTER(coot_operand), C.c_int32, C.POINTER(C.c_int32)]),
+    "coot_tune_runnable": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(coot_operand), C.c_int32,
+                                     C.POINTER(coot_launch_cfg), C.c_uint32, C.POINTER(C.c_int32)]),
     "coot_tune_table": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(C.c_double), C.POINTER(coot_operand),
                                   C.c_int32, C.POINTER(coot_launch_cfg), C.c_uint32, C.c_uint32, C.c_int32,
                                   C.POINTER(C.c_float), _P]),
@@ -242,9 +244,10 @@ def coot_batch_tune(b: int, stream: int = 0):
 
 
 def coot_batch_info(b: int) -> dict:
-    a = (C.c_int64 * 6)()
+    a = (C.c_int64 * 9)()
     _check(lib.coot_batch_info(b, a))
-    return {"n_exprs": a[0], "n_tiles": a[1], "bytes": a[2], "tile": a[3], "grid": a[4], "vec4_exprs": a[5]}
+    return {"n_exprs": a[0], "n_tiles": a[1], "bytes": a[2], "tile": a[3], "grid": a[4], "vec4_exprs": a[5],
+            "flat_exprs": a[6], "lds_stack": a[7], "lds_staged": a[8]}
 
 
 def coot_batch_release(b: int) -> None:
@@ -268,6 +271,13 @@ def coot_tune_prepare(h: int, operands, mode: int = -1) -> int:
     fam = C.c_int32()
     _check(lib.coot_tune_prepare(h, _arr(coot_operand, operands), mode, C.byref(fam)))
     return fam.value
+
+
+def coot_tune_runnable(h: int, operands, out, mode: int, cfgs) -> list:
+    ok = (C.c_int32 * max(1, len(cfgs)))()
+    _check(lib.coot_tune_runnable(h, _arr(coot_operand, operands), C.byref(out) if out is not None else None, mode,
+                                  _cfgs(cfgs), len(cfgs), ok))
+    return [bool(ok[i]) for i in range(len(cfgs))]
 
 
 def coot_tune_table(h: int, operands, scalars, out: coot_operand, mode: int, cfgs, reps: int = 5, flush: bool = True,

@@ -15,8 +15,8 @@
 #include "core.h"
 
 extern "C" hipError_t coot_batch_launch_kernel(int dtype, int ts, unsigned grid, const void* ex, const void* tiles,
-                                              int t_begin, int t_end, const void* code, const void* scal,
-                                              hipStream_t s);
+                                              int t_begin, int t_end, const void* code, const void* scal, int nstk,
+                                              int np1, hipStream_t s);
 
 using namespace coot;
 using coot::batch::BatchExpr;
@@ -157,12 +157,14 @@ struct coot_batch {
   std::vector<uint64_t> scal_bits;
   std::vector<std::pair<int, int>> ranges;  // per expression: tile range
   std::vector<uint32_t> tiles;
-  std::vector<int> vec4_ok;
+  std::vector<int> vec4_ok, flat_ok;
   DevBuf<BatchExpr> d_ex;
   DevBuf<uint32_t> d_code, d_tiles;
   DevBuf<uint64_t> d_scal32x2;  // scalars packed as the element type
   int ts = 32;
   int gm = 8;
+  int nstk = 1;    // LDS stack entries: the deepest expression's registers minus the top
+  int max_p1 = 0;  // most transposed leaves in one expression
   bool allow_vec = true;
   unsigned grid = 1;
   int64_t bytes = 0;
@@ -183,11 +185,14 @@ void build_tiles(coot_batch* b) {
   b->ranges.clear();
   for (size_t k = 0; k < b->ex.size(); ++k) {
     BatchExpr& e = b->ex[k];
+    e.flat = b->flat_ok[k];
     e.tiles_r = (e.n_rows + b->ts - 1) / b->ts;
     const int tc = (e.n_cols + b->ts - 1) / b->ts;
     e.vec4 = (b->allow_vec && b->vec4_ok[k]) ? 1 : 0;
     const int begin = (int)(b->tiles.size() / 2);
-    for (int t = 0; t < e.tiles_r * tc; ++t) {
+    const int64_t chunk = (int64_t)b->ts * b->ts;  // flat tiles: 4 elements per thread, ts*ts/4 threads
+    const int64_t nt = e.flat ? ((int64_t)e.n_rows * e.n_cols + chunk - 1) / chunk : (int64_t)e.tiles_r * tc;
+    for (int64_t t = 0; t < nt; ++t) {
       b->tiles.push_back((uint32_t)k);
       b->tiles.push_back((uint32_t)t);
     }
@@ -199,11 +204,24 @@ void build_tiles(coot_batch* b) {
   b->grid = (unsigned)std::max(1, std::min(n_tiles, b->gm * num_cus()));
 }
 
+// Transposed-leaf tiles staged in LDS: as many as an expression needs (at most 4)
+// while the workgroup's LDS stays within 32 KB (several workgroups per CU), and
+// always within the 64 KB a workgroup may hold; the rest are read directly.
+int staged_tiles(const coot_batch* b) {
+  const size_t es = b->dtype == COOT_BATCH_F32 ? 4 : 8;
+  const size_t stack = (size_t)b->nstk * (b->ts * b->ts / 4) * 4 * es;
+  const size_t slot = (size_t)b->ts * (b->ts + 1) * es;
+  const size_t budget = std::max<size_t>(32768, stack + slot);
+  size_t n = std::min<size_t>({(size_t)b->max_p1, 4, budget > stack ? (budget - stack) / slot : 0});
+  while (n > 0 && stack + n * slot > 65536) --n;
+  return (int)n;
+}
+
 void launch_all(coot_batch* b, hipStream_t s) {
   const int n_tiles = (int)(b->tiles.size() / 2);
   if (n_tiles == 0) return;
   hip_check(coot_batch_launch_kernel(b->dtype, b->ts, b->grid, b->d_ex.p, b->d_tiles.p, 0, n_tiles, b->d_code.p,
-                                     b->d_scal32x2.p, s),
+                                     b->d_scal32x2.p, b->nstk, staged_tiles(b), s),
             "batch kernel launch");
 }
 
@@ -242,8 +260,7 @@ coot_status coot_batch_create(uint32_t n, coot_expr* const* exprs, const coot_op
       if (cfg->waves) {
         if (cfg->waves == 1) b->ts = 16;
         else if (cfg->waves == 4) b->ts = 32;
-        else if (cfg->waves == 16) b->ts = 64;
-        else fail(COOT_EINVAL, "batch waves must be 1, 4 or 16 (tiles of 16, 32 or 64)");
+        else fail(COOT_EINVAL, "batch waves must be 1 or 4 (tiles of 16 x 16 or 32 x 32 elements)");
       }
       if (cfg->grid_mult) b->gm = cfg->grid_mult;
       if (cfg->vec == 1) b->allow_vec = false;
@@ -268,17 +285,22 @@ coot_status coot_batch_create(uint32_t n, coot_expr* const* exprs, const coot_op
       BatchExpr be;
       std::memset(&be, 0, sizeof be);
       const size_t es = dtype_size(e.dtype);
-      bool v4 = R % 4 == 0;
       const int64_t old = o.ld ? o.ld : std::max<int64_t>(1, R);
-      v4 = v4 && old % 4 == 0 && ((uintptr_t)o.data % 16) == 0;
+      // 2-D tiles: 4-row column segments need R, every untransposed ld and 16-byte alignment
+      bool v4 = R % 4 == 0 && old % 4 == 0 && ((uintptr_t)o.data % 16) == 0;
+      // flat chunks: every leaf untransposed and contiguous, like the output
+      bool flat = e.n_p1 == 0 && (old == R || C <= 1);
+      bool aligned = ((uintptr_t)o.data % 16) == 0;
       for (size_t l = 0; l < e.leaves.size(); ++l) {
         const coot_operand& lo = ops[e.leaves[l].slot];
         be.leaf[l] = lo.data;
         be.ld[l] = lo.ld ? lo.ld : std::max<int64_t>(1, lo.n_rows);
+        aligned = aligned && ((uintptr_t)lo.data % 16) == 0;
         if (e.leaves[l].parity) {
           be.p1_mask |= 1u << l;
         } else {
           v4 = v4 && be.ld[l] % 4 == 0 && ((uintptr_t)lo.data % 16) == 0;
+          flat = flat && (be.ld[l] == lo.n_rows || lo.n_cols <= 1);
         }
         // the output may only alias an operand read untransposed with its own layout
         const char* ob = (const char*)o.data;
@@ -286,18 +308,22 @@ coot_status coot_batch_create(uint32_t n, coot_expr* const* exprs, const coot_op
         if (R * C > 0 && lb == ob && (e.leaves[l].parity || be.ld[l] != old))
           fail(COOT_EALIAS, "batch output aliases a transposed or differently laid out operand");
       }
+      if (flat) v4 = aligned;
       be.out = o.data;
       be.out_ld = old;
       be.n_rows = (int32_t)R;
       be.n_cols = (int32_t)C;
       be.code_off = (int32_t)b->code.size();
       be.sc_off = 0;
-      emit_program(e, (uint32_t)scal.size(), &b->code);
+      const int regs = emit_program(e, (uint32_t)scal.size(), &b->code);
+      b->nstk = std::max(b->nstk, regs - 1);
+      b->max_p1 = std::max(b->max_p1, __builtin_popcount(be.p1_mask));
       be.code_len = (int32_t)(b->code.size() - be.code_off);
       if (e.n_scalars && !scalars) fail(COOT_EINVAL, "scalars missing");
       for (uint32_t s = 0; s < e.n_scalars; ++s) scal.push_back(scalars[k][s]);
       b->ex.push_back(be);
       b->vec4_ok.push_back(v4 ? 1 : 0);
+      b->flat_ok.push_back(flat ? 1 : 0);
       // algorithmic bytes: each distinct operand slot read once, the output written once
       std::vector<bool> seen(e.slots.size(), false);
       int64_t elems = R * C;
@@ -342,7 +368,7 @@ coot_status coot_batch_launch_each(coot_batch* b, void* stream) {
       if (r.second == r.first) continue;
       const unsigned g = (unsigned)std::min(r.second - r.first, (int)b->grid);
       hip_check(coot_batch_launch_kernel(b->dtype, b->ts, g, b->d_ex.p, b->d_tiles.p, r.first, r.second,
-                                         b->d_code.p, b->d_scal32x2.p, (hipStream_t)stream),
+                                         b->d_code.p, b->d_scal32x2.p, b->nstk, staged_tiles(b), (hipStream_t)stream),
                 "batch kernel launch");
     }
   });
@@ -358,7 +384,7 @@ coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, 
     float bt = 1e30f;
     int bts = b->ts, bgm = b->gm;
     bool bvec = b->allow_vec;
-    for (int ts : {16, 32, 64}) {
+    for (int ts : {16, 32}) {
       for (int gm : {2, 4, 8, 16}) {
         for (bool vec : {true, false}) {
           b->ts = ts;
@@ -403,7 +429,7 @@ coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, 
   });
 }
 
-coot_status coot_batch_info(const coot_batch* b, int64_t info[6]) {
+coot_status coot_batch_info(const coot_batch* b, int64_t info[9]) {
   return guarded([&] {
     if (!b || !info) fail(COOT_EINVAL, "NULL argument");
     info[0] = (int64_t)b->ex.size();
@@ -411,9 +437,15 @@ coot_status coot_batch_info(const coot_batch* b, int64_t info[6]) {
     info[2] = b->bytes;
     info[3] = b->ts;
     info[4] = b->grid;
-    int64_t v4 = 0;
-    for (auto& e : b->ex) v4 += e.vec4;
+    int64_t v4 = 0, fl = 0;
+    for (auto& e : b->ex) {
+      v4 += e.vec4;
+      fl += e.flat;
+    }
     info[5] = v4;
+    info[6] = fl;
+    info[7] = b->nstk;
+    info[8] = staged_tiles(b);
   });
 }
 

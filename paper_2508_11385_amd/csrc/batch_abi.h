@@ -29,7 +29,9 @@ struct BatchExpr {
   int32_t code_off, code_len;         // bytecode range
   int32_t sc_off;                     // first scalar
   uint32_t p1_mask;                   // bit k: leaf k is read transposed
-  int32_t vec4;                       // 1: 128-bit column-segment accesses are valid
+  int32_t vec4;                       // 1: 128-bit accesses are valid
+  int32_t flat;                       // 1: untransposed contiguous leaves and output: flat chunks
+  int32_t pad_;
 };
 
 }  // namespace batch

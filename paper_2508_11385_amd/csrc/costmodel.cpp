@@ -475,11 +475,18 @@ coot_status coot_tune(coot_expr* h, const coot_operand* operands, const double* 
       if (!cm) fail(COOT_EINVAL, "the MLP policy needs a cost model");
       int64_t R, C;
       infer_shape(*h->e, operands, &R, &C);
+      // rank only the configurations these operands allow (alignment, tile)
+      std::vector<int32_t> ok(space.size());
+      st = coot_tune_runnable(h, operands, out, mode, space.data(), (uint32_t)space.size(), ok.data());
+      if (st != COOT_OK) fail(st, last_error());
+      std::vector<coot_launch_cfg> live;
+      for (size_t i = 0; i < space.size(); ++i)
+        if (ok[i]) live.push_back(space[i]);
       uint32_t bi = 0;
-      st = coot_costmodel_predict(cm, h, R, C, mode < 0 ? 0 : 1, space.data(), (uint32_t)space.size(), nullptr, &bi,
+      st = coot_costmodel_predict(cm, h, R, C, mode < 0 ? 0 : 1, live.data(), (uint32_t)live.size(), nullptr, &bi,
                                   stream);
       if (st != COOT_OK) fail(st, last_error());
-      cand.push_back(space[bi]);
+      cand.push_back(live[bi]);
     } else {
       fail(COOT_EINVAL, "policy must be 0, 1 or 2");
     }

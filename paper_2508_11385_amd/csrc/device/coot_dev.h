@@ -246,21 +246,6 @@ __device__ __forceinline__ F wave_sum(F v) {
   for (int m = 32; m >= 1; m >>= 1) v = op_add(v, shfl_x(v, m));
   return v;
 }
-// Sum across groups of G consecutive lanes (G a power of two <= 64).
-template <int G, typename F>
-__device__ __forceinline__ void group_dw_sum(F& h, F& l) {
-#pragma unroll
-  for (int m = G / 2; m >= 1; m >>= 1) {
-    F h2 = shfl_x(h, m), l2 = shfl_x(l, m);
-    dw_add(h, l, h2, l2);
-  }
-}
-template <int G, typename F>
-__device__ __forceinline__ F group_sum(F v) {
-#pragma unroll
-  for (int m = G / 2; m >= 1; m >>= 1) v = op_add(v, shfl_x(v, m));
-  return v;
-}
 
 // ---------------------------------------------------------------------------
 // Leaf access
@@ -740,96 +725,185 @@ __device__ __forceinline__ void reduce_stage2(const coot_kargs& a) {
 // ===========================================================================
 template <typename T> struct Pair { T hi, lo; };
 
+template <typename T, bool COMP>
+__device__ __forceinline__ Pair<T> acc_pair(const typename AccSel<T, COMP>::type& g) {
+  Pair<T> p;
+  if constexpr (!is_int_t<T>::v && COMP) {
+    p.hi = g.hi;
+    p.lo = g.lo;
+  } else {
+    p.hi = g.s;
+    p.lo = (T)0;
+  }
+  return p;
+}
+
+template <typename T, bool COMP>
+__device__ __forceinline__ void pair_add(T& h, T& l, const Pair<T>& p) {
+  if constexpr (is_int_t<T>::v) {
+    h = op_add(h, p.hi);
+  } else if constexpr (COMP) {
+    dw_add<T>(h, l, p.hi, p.lo);
+  } else {
+    h = h + p.hi;
+  }
+}
+
+// ===========================================================================
+// Dimension reductions over segments.  The tiles along the reduced dimension are
+// cut into n_part segments of K = ceil(tiles / n_part) consecutive tiles; one
+// workgroup walks a whole segment, each lane accumulating its elements in
+// registers (float-float when compensated), and writes one partial per output
+// element of the segment, ws[o * n_part + segment], after a single combine of the
+// lanes through LDS.  The tile traversal (coalesced column segments, transposed
+// leaves staged through LDS) is the one of tiled_walk.
+// ===========================================================================
+template <class X, int V, int TS, int DIM, class Sink>
+__device__ __forceinline__ void tiled_walk_seg(const coot_kargs& a, Sink& sink) {
+  typedef typename X::T T;
+  constexpr int NB = 256;
+  constexpr int TPC = TS / V;       // threads along a column segment
+  constexpr int CPP = NB / TPC;     // columns per pass
+  constexpr int NPASS = TS / CPP;   // passes per tile
+  constexpr int NPS = X::NP1 > 0 ? X::NP1 : 1;
+  __shared__ T lds[NPS][TS][TS + 1];
+  const i64 R = a.n_rows, C = a.n_cols;
+  const i64 tr = (R + TS - 1) / TS, tc = (C + TS - 1) / TS;
+  const i64 nred = DIM == 0 ? tr : tc, nkeep = DIM == 0 ? tc : tr;
+  const i64 K = (nred + a.n_part - 1) / a.n_part;
+  const i64 nseg = nkeep * a.n_part;
+  const int lc = threadIdx.x % TPC, lr = threadIdx.x / TPC;
+  for (i64 sgi = blockIdx.x; sgi < nseg; sgi += gridDim.x) {
+    // neighbouring workgroups take neighbouring row strips of the same column
+    // strip, so that together they stream whole columns of the column-major leaves
+    const i64 keep = DIM == 0 ? sgi / a.n_part : sgi % nkeep;
+    const i64 sg = DIM == 0 ? sgi % a.n_part : sgi / nkeep;
+    sink.begin_seg();
+    const i64 r_end = sg * K + K < nred ? sg * K + K : nred;
+    for (i64 r = sg * K; r < r_end; ++r) {
+      const i64 ti = DIM == 0 ? r : keep, tj = DIM == 0 ? keep : r;
+      const i64 i0 = ti * TS, j0 = tj * TS;
+      if constexpr (X::NP1 > 0) {
+        for (int il = lr; il < TS; il += CPP) {
+          const i64 i = i0 + il, j = j0 + (i64)lc * V;
+          const bool in = (i < R) && (j < C);
+#pragma unroll
+          for (int k = 0; k < X::NL; ++k) {
+            if (X::par(k) == 0) continue;
+            vt<T, V> v;
+            if (in) {
+              v = ldv<T, V>((const T*)a.leaf[X::slot(k)] + j + i * a.ld[X::slot(k)]);
+            } else {
+#pragma unroll
+              for (int q = 0; q < V; ++q) v.v[q] = (T)0;
+            }
+#pragma unroll
+            for (int q = 0; q < V; ++q) lds[X::p1(k) < 0 ? 0 : X::p1(k)][il][lc * V + q] = v.v[q];
+          }
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int p = 0; p < NPASS; ++p) {
+        const int jl = lr + p * CPP;
+        const i64 j = j0 + jl, i = i0 + (i64)lc * V;
+        const bool in = (i < R) && (j < C);
+        vt<T, V> x[X::NL];
+        if (in) {
+#pragma unroll
+          for (int k = 0; k < X::NL; ++k)
+            if (X::par(k) == 0) x[k] = ldv<T, V>((const T*)a.leaf[X::slot(k)] + i + j * a.ld[X::slot(k)]);
+        }
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          T L[X::NL];
+#pragma unroll
+          for (int k = 0; k < X::NL; ++k)
+            L[k] = X::par(k) ? lds[X::p1(k) < 0 ? 0 : X::p1(k)][lc * V + q][jl] : (in ? x[k].v[q] : (T)0);
+          sink.elem(a, p, q, in, L);
+        }
+      }
+      if constexpr (X::NP1 > 0) __syncthreads();
+    }
+    sink.end_seg(a, keep * TS, sg, lr, lc);
+  }
+}
+
+// sum(., 0): lane (lr, lc) of pass p covers column lr + p * CPP of the tile, rows
+// lc * V .. lc * V + V - 1; it keeps one accumulator per pass.  At the end of the
+// segment the TPC lanes of each column are combined in LDS by one thread per column.
 template <class X, bool COMP, int V, int TS>
-struct Dim0Sink {
+struct Dim0SegSink {
   typedef typename X::T T;
   typedef typename AccSel<T, COMP>::type Acc;
-  Acc g;
-  __device__ __forceinline__ void begin_tile() {}
-  __device__ __forceinline__ void elem(const coot_kargs& a, int q, bool in, const T* L) {
-    if (q == 0) g.init();
-    if (in) g.add(X::f(L, a.sc));
+  static constexpr int TPC = TS / V, CPP = 256 / TPC, NPASS = TS / CPP;
+  Acc g[NPASS];
+  __device__ __forceinline__ void begin_seg() {
+#pragma unroll
+    for (int p = 0; p < NPASS; ++p) g[p].init();
   }
-  __device__ __forceinline__ void group(const coot_kargs& a, i64 i, i64 j, int jl, int lc, bool) {
-    constexpr int TPC = TS / V;
-    T h, l;
-    if constexpr (is_int_t<T>::v) {
-      h = group_sum<TPC, T>(g.s);
-      l = (T)0;
-    } else if constexpr (COMP) {
-      h = g.hi;
-      l = g.lo;
-      group_dw_sum<TPC, T>(h, l);
-    } else {
-      h = group_sum<TPC, T>(g.s);
-      l = (T)0;
-    }
-    if (lc == 0 && j < a.n_cols) {
-      const i64 ti = i / TS;
-      Pair<T> p;
-      p.hi = h;
-      p.lo = l;
-      ((Pair<T>*)a.ws)[j * a.n_part + ti] = p;
+  __device__ __forceinline__ void elem(const coot_kargs& a, int p, int, bool in, const T* L) {
+    if (in) {
+#pragma unroll
+      for (int pp = 0; pp < NPASS; ++pp)
+        if (pp == p) g[pp].add(X::f(L, a.sc));
     }
   }
-  __device__ __forceinline__ void end_tile(const coot_kargs&, i64, i64, i64, i64, int, int) {}
+  __device__ __forceinline__ void end_seg(const coot_kargs& a, i64 j0, i64 sg, int lr, int lc) {
+    __shared__ Pair<T> red[TS][TPC + 1];
+#pragma unroll
+    for (int p = 0; p < NPASS; ++p) red[lr + p * CPP][lc] = acc_pair<T, COMP>(g[p]);
+    __syncthreads();
+    if ((int)threadIdx.x < TS) {
+      const int jl = threadIdx.x;
+      T h = red[jl][0].hi, l = red[jl][0].lo;
+      for (int k = 1; k < TPC; ++k) pair_add<T, COMP>(h, l, red[jl][k]);
+      const i64 j = j0 + jl;
+      if (j < a.n_cols) {
+        Pair<T> q;
+        q.hi = h;
+        q.lo = l;
+        ((Pair<T>*)a.ws)[j * a.n_part + sg] = q;
+      }
+    }
+    __syncthreads();
+  }
 };
 
+// sum(., 1): a lane's rows (lc * V .. lc * V + V - 1 of the row strip) stay fixed over
+// the segment; its V accumulators are combined across the CPP lanes of each row in LDS.
 template <class X, bool COMP, int V, int TS>
-struct Dim1Sink {
+struct Dim1SegSink {
   typedef typename X::T T;
   typedef typename AccSel<T, COMP>::type Acc;
+  static constexpr int TPC = TS / V, CPP = 256 / TPC;
   Acc r[V];
-  __device__ __forceinline__ void begin_tile() {
+  __device__ __forceinline__ void begin_seg() {
 #pragma unroll
     for (int q = 0; q < V; ++q) r[q].init();
   }
-  __device__ __forceinline__ void elem(const coot_kargs& a, int q, bool in, const T* L) {
+  __device__ __forceinline__ void elem(const coot_kargs& a, int, int q, bool in, const T* L) {
     if (in) {
 #pragma unroll
       for (int qq = 0; qq < V; ++qq)
         if (qq == q) r[qq].add(X::f(L, a.sc));
     }
   }
-  __device__ __forceinline__ void group(const coot_kargs&, i64, i64, int, int, bool) {}
-  __device__ __forceinline__ void end_tile(const coot_kargs& a, i64, i64 tj, i64 i0, i64, int lr, int lc) {
-    constexpr int TPC = TS / V;
-    constexpr int CPP = 256 / TPC;
+  __device__ __forceinline__ void end_seg(const coot_kargs& a, i64 i0, i64 sg, int lr, int lc) {
     __shared__ Pair<T> red[CPP][TS];
 #pragma unroll
-    for (int q = 0; q < V; ++q) {
-      Pair<T> p;
-      if constexpr (is_int_t<T>::v) {
-        p.hi = r[q].s;
-        p.lo = (T)0;
-      } else if constexpr (COMP) {
-        p.hi = r[q].hi;
-        p.lo = r[q].lo;
-      } else {
-        p.hi = r[q].s;
-        p.lo = (T)0;
-      }
-      red[lr][lc * V + q] = p;
-    }
+    for (int q = 0; q < V; ++q) red[lr][lc * V + q] = acc_pair<T, COMP>(r[q]);
     __syncthreads();
     if ((int)threadIdx.x < TS) {
       const int il = threadIdx.x;
       T h = red[0][il].hi, l = red[0][il].lo;
-      for (int k = 1; k < CPP; ++k) {
-        if constexpr (is_int_t<T>::v) {
-          h = op_add(h, red[k][il].hi);
-        } else if constexpr (COMP) {
-          dw_add<T>(h, l, red[k][il].hi, red[k][il].lo);
-        } else {
-          h = h + red[k][il].hi;
-        }
-      }
+      for (int k = 1; k < CPP; ++k) pair_add<T, COMP>(h, l, red[k][il]);
       const i64 i = i0 + il;
       if (i < a.n_rows) {
-        Pair<T> p;
-        p.hi = h;
-        p.lo = l;
-        ((Pair<T>*)a.ws)[i * a.n_part + tj] = p;
+        Pair<T> q;
+        q.hi = h;
+        q.lo = l;
+        ((Pair<T>*)a.ws)[i * a.n_part + sg] = q;
       }
     }
     __syncthreads();
@@ -839,11 +913,11 @@ struct Dim1Sink {
 template <class X, int DIM, bool COMP, int V, int TS>
 __device__ __forceinline__ void tiled_reduce_dim(const coot_kargs& a) {
   if constexpr (DIM == 0) {
-    Dim0Sink<X, COMP, V, TS> s;
-    tiled_walk<X, V, TS>(a, s);
+    Dim0SegSink<X, COMP, V, TS> s;
+    tiled_walk_seg<X, V, TS, 0>(a, s);
   } else {
-    Dim1Sink<X, COMP, V, TS> s;
-    tiled_walk<X, V, TS>(a, s);
+    Dim1SegSink<X, COMP, V, TS> s;
+    tiled_walk_seg<X, V, TS, 1>(a, s);
   }
 }
 

@@ -45,7 +45,8 @@ template <> struct ExpConst<float> {
   // fast path: inputs whose result is a normal number, k in [-125, 127]
   static __host__ __device__ __forceinline__ float FAST_LO() { return -86.0f; }
   static __host__ __device__ __forceinline__ float FAST_HI() { return 88.0f; }
-  static __host__ __device__ __forceinline__ float MARGIN() { return 0x1p-38f; }  // >= 8x the fast path's error
+  // fast path: half a unit in the last place minus 2^-14 units (>= 4x the error bound)
+  static __host__ __device__ __forceinline__ float HALF_LESS_MARGIN() { return 0.5f - 0x1p-14f; }
   static constexpr int SUB = 149;           // subnormal grid 2^-SUB
   static __host__ __device__ __forceinline__ void tab(int j, float& t0, float& t1, float& t2) {
     t0 = coot_exp_tab_f[j][0];
@@ -67,7 +68,7 @@ template <> struct ExpConst<double> {
   static constexpr int SUB = 1074;
   static __host__ __device__ __forceinline__ double FAST_LO() { return -707.0; }
   static __host__ __device__ __forceinline__ double FAST_HI() { return 709.0; }
-  static __host__ __device__ __forceinline__ double MARGIN() { return 0x1p-66; }
+  static __host__ __device__ __forceinline__ double HALF_LESS_MARGIN() { return 0.5 - 0x1p-14; }
   static __host__ __device__ __forceinline__ void tab(int j, double& t0, double& t1, double& t2) {
     t0 = coot_exp_tab_d[j][0];
     t1 = coot_exp_tab_d[j][1];
@@ -198,9 +199,9 @@ __host__ __device__ __forceinline__ F exp_cr(F x) {
 // Two-level evaluation (Ziv's strategy): a cheaper double-word evaluation with
 // relative error about 2^-41 (binary32) / 2^-70 (binary64), then a test whether
 // rounding its result is unambiguous, i.e. whether the computed remainder stays
-// MARGIN (>= 8x the error bound) away from half the gap to the neighbour.  Only
-// ambiguous lanes (about 1 in 10^4) and inputs outside the normal-result range
-// run exp_cr above, out of line.
+// 2^-14 units in the last place (8x the error bound of 2^-17 units) below half a
+// unit.  Only ambiguous lanes (about 1 in 10^4) and inputs outside the
+// normal-result range run exp_cr above, out of line.
 // ---------------------------------------------------------------------------
 template <typename F>
 __host__ __device__ __forceinline__ F exp_fast(F x, bool& ok) {
@@ -218,13 +219,14 @@ __host__ __device__ __forceinline__ F exp_fast(F x, bool& ok) {
   F rh, rl;
   ef_two_sum(s0, -c, rh, rl);
   // exp(r) - 1 = rh + [rl + rh*rl + rh^2 (1/2 + rh/6 + ...)]
-  F q;
+  F poly;
   if constexpr (sizeof(F) == 4) {
-    q = (rh * rh) * ((F)0.5 + rh * ((F)(1.0 / 6) + rh * (F)(1.0 / 24)));
+    poly = x_fma(rh, x_fma(rh, (F)(1.0 / 24), (F)(1.0 / 6)), (F)0.5);
   } else {
-    q = (rh * rh) * (0.5 + rh * (1.0 / 6 + rh * (1.0 / 24 + rh * (1.0 / 120 + rh * (1.0 / 720 + rh * (1.0 / 5040))))));
+    poly = x_fma(rh, x_fma(rh, x_fma(rh, x_fma(rh, x_fma(rh, 1.0 / 5040, 1.0 / 720), 1.0 / 120), 1.0 / 24), 1.0 / 6),
+                 0.5);
   }
-  const F pl = x_fma(rh, rl, q) + rl;
+  const F pl = x_fma(rh * rh, poly, x_fma(rh, rl, rl));
   F T0, T1, T2;
   K::tab(j, T0, T1, T2);
   F m_hi, m_lo;
@@ -233,13 +235,15 @@ __host__ __device__ __forceinline__ F exp_fast(F x, bool& ok) {
   const F e = m_hi - (s - T0);
   const F u = e + (m_lo + x_fma(T0, pl, x_fma(T1, rh, T1)));
   const F y = s + u;
-  const F d = u - (y - s);                   // s + u = y + d exactly
-  int ey;
-  const F fr = x_frexp(y, &ey);
-  constexpr int P = sizeof(F) == 4 ? 24 : 53;
-  const F hu = x_ldexp((F)1, ey - P - 1);    // half the gap above y
-  const F dist = x_abs(x_abs(d) - hu);
-  ok = ok && dist > K::MARGIN() * y && fr != (F)0.5;
+  const F d = u - (y - s);                   // s + u = y + d exactly, |d| <= half a unit of y
+  // y lies in [0.997, 1.995): with P significand bits (24 or 53) the gap between
+  // neighbours is 2^-(P-1) above 1 and 2^-P below, and for y = 1 the side d points
+  // to decides.  Rounding is unambiguous when |d| plus the error stays under half
+  // that gap.
+  const bool upper = y > (F)1 || (y == (F)1 && d >= (F)0);
+  const F unit_inv_hi = sizeof(F) == 4 ? (F)0x1p23 : (F)0x1p52;   // 2^(P-1)
+  const F t = x_abs(d) * (upper ? unit_inv_hi : (F)2 * unit_inv_hi);
+  ok = ok && t < K::HALF_LESS_MARGIN();
   return x_ldexp(y, k);
 }
 

@@ -271,10 +271,14 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
   if (kind == COOT_RED_SUM) {
     const int ts = rq.var.ts;
     const int64_t tr = (R + ts - 1) / ts, tc = (C + ts - 1) / ts;
-    a.n_part = dim == 0 ? tr : tc;
+    // segments of K tiles along the reduced dimension, K growing once there are
+    // more than 8 tiles per CU (at most 16): fewer partials, fewer lane combines
+    const int64_t nred = dim == 0 ? tr : tc, nkeep = dim == 0 ? tc : tr;
+    const int64_t K = std::max<int64_t>(1, std::min<int64_t>({16, nred, (nred * nkeep) / (8 * (int64_t)num_cus())}));
+    a.n_part = std::max<int64_t>(1, (nred + K - 1) / K);
     a.ws = workspace((size_t)std::max<int64_t>(1, a.n_part * n_out) * 2 * es, s, 0);
-    const int64_t nt = tr * tc;
-    if (nt > 0) launch(m->fn(kn), (unsigned)std::min<int64_t>(nt, 1 << 30), 256, a, s);
+    const int64_t nseg = nkeep * a.n_part;
+    if (nseg > 0) launch(m->fn(kn), (unsigned)std::min<int64_t>(nseg, 1 << 30), 256, a, s);
     const unsigned g2 = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_out + 3) / 4, 65536));
     launch(m->fn(m->names.stage2), g2, 256, a, s);
     return;

@@ -5,9 +5,12 @@
 // vec and ept are compile-time (one tuning module per signature holds every
 // variant), waves and grid_mult are launch parameters.  The tiled family runs
 // 256-thread workgroups, so only vec and grid_mult vary there.
-// Timing: one warm-up launch, then `reps` launches each bracketed by HIP events
-// on the caller's stream, optionally after a 512 MiB write that evicts L2 and the
-// Infinity Cache; the median is reported.
+// Timing: one warm-up launch per configuration, then `reps` rounds; in each round
+// every configuration is timed once with HIP events on the caller's stream around
+// enough back-to-back launches to span 40 us (the per-launch time of a repeated
+// call, with launch overhead included), or around a single launch after a 512 MiB
+// write that evicts L2 and the Infinity Cache.  The median per configuration is
+// reported.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -21,6 +24,7 @@ using namespace coot;
 namespace {
 
 constexpr size_t kFlushBytes = 512u << 20;
+constexpr float kSampleUs = 40.0f;  // a timing sample spans at least this many microseconds
 
 bool tune_mode_ok(int mode) { return mode == -1 || mode == COOT_RED_ACCU; }
 
@@ -45,13 +49,21 @@ Prepared prepare(Expr& e, const coot_operand* ops, const coot_operand* out, int 
   return p;
 }
 
-// Launch one configuration (returns false if it cannot run on these operands).
-bool launch_cfg(Expr& e, Prepared& p, const coot_launch_cfg& c, const coot_operand* ops, const double* scalars,
-                const coot_operand* out, hipStream_t s) {
+// Whether a configuration can run on these operands (vector width vs alignment and tile).
+bool cfg_runnable(Expr& e, const Prepared& p, const coot_launch_cfg& c, const coot_operand* ops,
+                  const coot_operand* out) {
   Request rq = p.rq;
   rq.var.vec = c.vec;
   if (rq.fam == FAM_TILE && c.vec > rq.var.ts / 4) return false;
-  if (!vec_ok(e, rq, ops, out, p.R, p.C)) return false;
+  return vec_ok(e, rq, ops, out, p.R, p.C);
+}
+
+// Launch one configuration (returns false if it cannot run on these operands).
+bool launch_cfg(Expr& e, Prepared& p, const coot_launch_cfg& c, const coot_operand* ops, const double* scalars,
+                const coot_operand* out, hipStream_t s) {
+  if (!cfg_runnable(e, p, c, ops, out)) return false;
+  Request rq = p.rq;
+  rq.var.vec = c.vec;
   const int ept = rq.fam == FAM_FLAT ? c.ept : 0;
   hipFunction_t f = p.m->fn(variant_name(e, rq, c.vec, ept));
   KArgs a;
@@ -112,6 +124,18 @@ coot_status coot_tune_prepare(coot_expr* h, const coot_operand* operands, int32_
   });
 }
 
+coot_status coot_tune_runnable(coot_expr* h, const coot_operand* operands, const coot_operand* out, int32_t mode,
+                               const coot_launch_cfg* cfgs, uint32_t n_cfgs, int32_t* runnable) {
+  return guarded([&] {
+    if (!h || (n_cfgs && (!cfgs || !runnable)) || (mode < 0 && !out)) fail(COOT_EINVAL, "NULL argument");
+    Prepared p = prepare(*h->e, operands, nullptr, mode, false);
+    for (uint32_t k = 0; k < n_cfgs; ++k) {
+      if (!valid_cfg(cfgs[k])) fail(COOT_EINVAL, "invalid launch configuration");
+      runnable[k] = cfg_runnable(*h->e, p, cfgs[k], operands, mode < 0 ? out : nullptr) ? 1 : 0;
+    }
+  });
+}
+
 coot_status coot_tune_table(coot_expr* h, const coot_operand* operands, const double* scalars, coot_operand* out,
                             int32_t mode, const coot_launch_cfg* cfgs, uint32_t n_cfgs, uint32_t reps, int32_t flush,
                             float* times_us, void* stream) {
@@ -134,27 +158,39 @@ coot_status coot_tune_table(coot_expr* h, const coot_operand* operands, const do
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");
     unsigned fv = 1;
+    auto timed = [&](const coot_launch_cfg& c, uint32_t launches) {
+      if (fbuf) hip_check(coot_flush_launch(fbuf, kFlushBytes, fv++, s), "flush");
+      hip_check(hipEventRecord(e0, s), "hipEventRecord");
+      for (uint32_t l = 0; l < launches; ++l) launch_cfg(e, p, c, operands, scalars, out, s);
+      hip_check(hipEventRecord(e1, s), "hipEventRecord");
+      hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+      float ms = 0;
+      hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      return ms * 1000.0f / (float)launches;
+    };
     try {
+      // warm-up launch of every configuration, which is also its validity test
+      std::vector<uint32_t> live;
       for (uint32_t k = 0; k < n_cfgs; ++k) {
-        const coot_launch_cfg& c = cfgs[k];
-        if (!valid_cfg(c)) fail(COOT_EINVAL, "invalid launch configuration");
-        if (!launch_cfg(e, p, c, operands, scalars, out, s)) {  // warm-up, also the validity test
-          times_us[k] = NAN;
-          continue;
+        if (!valid_cfg(cfgs[k])) fail(COOT_EINVAL, "invalid launch configuration");
+        times_us[k] = NAN;
+        if (launch_cfg(e, p, cfgs[k], operands, scalars, out, s)) live.push_back(k);
+      }
+      if (!live.empty()) {
+        // launches per sample: enough back-to-back launches to span kSampleUs (one when flushing)
+        uint32_t launches = 1;
+        if (!fbuf) {
+          const float t1 = std::max(0.5f, timed(cfgs[live[0]], 1));
+          launches = (uint32_t)std::min(64.0f, std::max(1.0f, std::ceil(kSampleUs / t1)));
         }
-        std::vector<float> t;
-        for (uint32_t r = 0; r < reps; ++r) {
-          if (fbuf) hip_check(coot_flush_launch(fbuf, kFlushBytes, fv++, s), "flush");
-          hip_check(hipEventRecord(e0, s), "hipEventRecord");
-          launch_cfg(e, p, c, operands, scalars, out, s);
-          hip_check(hipEventRecord(e1, s), "hipEventRecord");
-          hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
-          float ms = 0;
-          hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-          t.push_back(ms * 1000.0f);
+        // rounds over all configurations, so that drift in clocks or temperature spreads evenly
+        std::vector<std::vector<float>> t(live.size());
+        for (uint32_t r = 0; r < reps; ++r)
+          for (size_t i = 0; i < live.size(); ++i) t[i].push_back(timed(cfgs[live[i]], launches));
+        for (size_t i = 0; i < live.size(); ++i) {
+          std::sort(t[i].begin(), t[i].end());
+          times_us[live[i]] = t[i][t[i].size() / 2];
         }
-        std::sort(t.begin(), t.end());
-        times_us[k] = t[t.size() / 2];
       }
     } catch (...) {
       (void)hipEventDestroy(e0);

@@ -3,10 +3,12 @@
 The system produces its own training data: random expression signatures
 (random trees of depth 1-8 over 2-5 operands, rows and cols log-uniform in
 [1, 16384], element types u32 / s32 / f32 / f64, element-wise or accu) are timed
-by the autotuner (coot_tune_table) under sampled launch configurations; a cost
+by the autotuner (coot_tune_table) over their family's configuration space; the
+training set samples configurations from the training signatures' tables; a cost
 model (coot_costmodel_train: MLP forward / backward / Adam kernels on the GPU)
-learns log(time) from the 17 features; on held-out signatures its argmin is
-compared with exhaustive autotuning (regret = t(pick) / t(best) - 1).
+learns log-time relative to the default configuration from the 17 features; on
+held-out signatures its argmin and the exhaustive argmin are re-timed side by
+side (regret = t(pick) / t(exhaustive pick) - 1).
 
 Orchestration only: every timing, the training and the inference run through
 libcoot's entry points.
@@ -17,7 +19,6 @@ import math
 import multiprocessing as mp
 import os
 import time
-from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import torch
@@ -97,7 +98,8 @@ def _operands(spec, g):
     return mats
 
 
-def time_signature(h, spec, mode, cfgs, reps=3, flush=False, seed=0):
+def time_signature(h, spec, mode, cfgs, reps=5, flush=False, seed=0):
+    """Median per-launch time (us) of each configuration on fresh operands of the signature's shape."""
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
     mats = _operands(spec, g)
@@ -109,34 +111,55 @@ def time_signature(h, spec, mode, cfgs, reps=3, flush=False, seed=0):
     return np.asarray(t, np.float64)
 
 
-def build_dataset(sigs, handles, fams, configs_per_sig=None, seed=0, log=None, reps=3, relative=True):
-    """Rows of (features, log time) for every timed (signature, configuration).
-
-    relative: the target is log(time) minus the mean log(time) of the signature's timed
-    configurations (its geometric-mean time), so the network learns how the configuration
-    changes the time of a given expression on a given shape."""
+def time_tables(sigs, handles, fams, reps=5, seed=0, log=None, what="signatures"):
+    """Exhaustive timing table (configurations, times) of every signature over its family's space."""
     spaces = {0: cc.coot_tune_space(0), 1: cc.coot_tune_space(1)}
-    g = np.random.default_rng(seed)
-    feats, target, tables = [], [], []
+    tables = []
     t0 = time.time()
     for i, ((spec, mode), h, fam) in enumerate(zip(sigs, handles, fams)):
-        space = spaces[fam]
-        if configs_per_sig is None or configs_per_sig >= len(space):
-            cfgs = space
+        cfgs = spaces[fam]
+        tables.append((cfgs, time_signature(h, spec, mode, cfgs, reps=reps, seed=seed * 100003 + i)))
+        if log and (i + 1) % 250 == 0:
+            log(f"timed {i + 1}/{len(sigs)} {what} ({time.time() - t0:.0f} s)")
+    return tables
+
+
+def _valid(t):
+    return np.flatnonzero(np.isfinite(t) & (t > 0))
+
+
+def default_index(cfgs, dtype):
+    """The library's default configuration (what coot_expr_eval launches without a tuner)."""
+    want = (2 if dtype == "f64" else 4, 4, 4, 8) if len(cfgs) > 12 else (2 if dtype == "f64" else 4, 1, 4, 16)
+    return cfgs.index(want) if want in cfgs else 0
+
+
+def dataset(sigs, handles, tables, configs_per_sig=None, seed=0):
+    """Rows of (features, target) from the timing tables.
+
+    Each signature contributes `configs_per_sig` sampled runnable configurations (all when
+    None), always including the default one.  The target is log(time) minus log(time of
+    the default configuration): the argmin only needs the ranking of a signature's
+    configurations, and a common reference keeps targets comparable across signatures."""
+    g = np.random.default_rng(seed)
+    feats, target = [], []
+    for (spec, mode), h, (cfgs, t) in zip(sigs, handles, tables):
+        ok = _valid(t)
+        if ok.size == 0:
+            continue
+        d = default_index(cfgs, spec.dtype)
+        ref = math.log(t[d]) if d in ok else float(np.mean(np.log(t[ok])))
+        if configs_per_sig is None or configs_per_sig >= ok.size:
+            pick = ok
         else:
-            cfgs = [space[k] for k in sorted(g.choice(len(space), configs_per_sig, replace=False))]
-        t = time_signature(h, spec, mode, cfgs, reps=reps, seed=seed * 100003 + i)
+            rest = ok[ok != d]
+            n = configs_per_sig - (1 if d in ok else 0)
+            pick = np.sort(np.concatenate([[d] if d in ok else [], g.choice(rest, n, replace=False)]).astype(int))
         red = 0 if mode < 0 else 1
-        f = cc.coot_costmodel_features(h, spec.out_shape[0], spec.out_shape[1], red, cfgs)
-        ok = np.isfinite(t) & (t > 0)
-        lt = np.log(t[ok])
-        feats.append(f[ok])
-        # relative log-time within the signature: the argmin only needs the ranking of its configurations
-        target.append(lt - lt.mean() if relative else lt)
-        tables.append((cfgs, t))
-        if log and (i + 1) % 100 == 0:
-            log(f"timed {i + 1}/{len(sigs)} signatures ({time.time() - t0:.0f} s)")
-    return np.concatenate(feats).astype(np.float32), np.concatenate(target).astype(np.float32), tables
+        f = cc.coot_costmodel_features(h, spec.out_shape[0], spec.out_shape[1], red, [cfgs[k] for k in pick])
+        feats.append(f)
+        target.append(np.log(t[pick]) - ref)
+    return np.concatenate(feats).astype(np.float32), np.concatenate(target).astype(np.float32)
 
 
 def he_init(seed: int, f: int = 17, h1: int = 64, h2: int = 64):
@@ -147,34 +170,61 @@ def he_init(seed: int, f: int = 17, h1: int = 64, h2: int = 64):
     return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
 
 
-def regrets(tables, picks):
-    """t(pick) / t(best) - 1 per signature (NaN-safe), from the exhaustive timing tables."""
+def picks(cm, sigs, handles, tables):
+    """Per signature: (exhaustive argmin, cost-model argmin, default) as indices into its
+    configuration list; the cost model ranks only the runnable configurations."""
+    out, t_pred = [], 0.0
+    for (spec, mode), h, (cfgs, t) in zip(sigs, handles, tables):
+        ok = _valid(t)
+        exh = int(ok[np.argmin(t[ok])])
+        t0 = time.perf_counter()
+        k, _ = cc.coot_costmodel_predict(cm, h, spec.out_shape[0], spec.out_shape[1], 0 if mode < 0 else 1,
+                                         [cfgs[i] for i in ok])
+        t_pred += time.perf_counter() - t0
+        d = default_index(cfgs, spec.dtype)
+        out.append((exh, int(ok[k]), d if d in ok else exh))
+    return np.asarray(out, np.int64), t_pred / max(1, len(sigs))
+
+
+def retime(sigs, handles, tables, pick_sets, reps=11, seed=0):
+    """Fresh per-launch times of the picked configurations, timed side by side (interleaved
+    rounds), so that no pick profits from the noise of the table it was chosen from.
+    pick_sets: (n_signatures, n_policies) indices; returns times of the same shape."""
+    res = np.zeros(pick_sets.shape, np.float64)
+    for i, ((spec, mode), h, (cfgs, _t)) in enumerate(zip(sigs, handles, tables)):
+        uniq = sorted(set(int(k) for k in pick_sets[i]))
+        tt = time_signature(h, spec, mode, [cfgs[k] for k in uniq], reps=reps, seed=seed * 100003 + i)
+        m = dict(zip(uniq, tt))
+        res[i] = [m[int(k)] for k in pick_sets[i]]
+    return res
+
+
+def regrets_from_table(tables, idx):
+    """t(pick) / t(best) - 1 within the exhaustive timing tables."""
     out = []
-    for (cfgs, t), k in zip(tables, picks):
-        best = np.nanmin(t)
-        tk = t[k] if np.isfinite(t[k]) else np.nanmax(t)
-        out.append(tk / best - 1.0)
+    for (cfgs, t), k in zip(tables, idx):
+        out.append(t[k] / np.nanmin(t) - 1.0)
     return np.asarray(out)
 
 
 def summarize(r):
+    """Geometric-mean regret (geomean of the time ratios, minus 1), p90, max, share within 5%."""
     g = float(np.exp(np.mean(np.log1p(r))) - 1.0)
     return {"geomean": g, "p90": float(np.percentile(r, 90)), "max": float(np.max(r)),
             "within_5pct": float(np.mean(r <= 0.05))}
 
 
-def default_index(cfgs, dtype):
-    want = (2 if dtype == "f64" else 4, 4, 4, 8) if len(cfgs) > 12 else (2 if dtype == "f64" else 4, 1, 4, 16)
-    return cfgs.index(want) if want in cfgs else 0
-
-
-def evaluate(cm, sigs, handles, tables):
-    """Cost-model picks vs exhaustive; also the default configuration and an untrained network."""
-    picks, t_pred = [], 0.0
-    for (spec, mode), h, (cfgs, t) in zip(sigs, handles, tables):
-        t0 = time.perf_counter()
-        k, _ = cc.coot_costmodel_predict(cm, h, spec.out_shape[0], spec.out_shape[1], 0 if mode < 0 else 1, cfgs)
-        t_pred += time.perf_counter() - t0
-        picks.append(k)
-    dflt = [default_index(cfgs, s.dtype) for (s, _), (cfgs, _t) in zip(sigs, tables)]
-    return regrets(tables, picks), regrets(tables, dflt), t_pred / max(1, len(sigs))
+def save_tables(path, sigs, fams, handles, tables, split):
+    """Timing tables and signature descriptors as plain arrays (numpy .npz, no pickled objects)."""
+    meta, rows = [], []
+    for i, ((spec, mode), fam, h, (cfgs, t)) in enumerate(zip(sigs, fams, handles, tables)):
+        n_ops = sum(1 for it in spec.postfix if it[0] not in ("load", "scalar"))
+        n_tr = sum(1 for it in spec.postfix if it[0] == "trans")
+        meta.append([spec.out_shape[0], spec.out_shape[1], ("u32", "s32", "f32", "f64").index(spec.dtype), mode, fam,
+                     n_ops, len(spec.slot_shapes), n_tr, split[i]])
+        f = cc.coot_costmodel_features(h, spec.out_shape[0], spec.out_shape[1], 0 if mode < 0 else 1, cfgs)
+        for k, c in enumerate(cfgs):
+            rows.append((i, *c, t[k], *f[k]))
+    rows = np.asarray(rows, np.float64)
+    np.savez_compressed(path, meta=np.asarray(meta, np.int64), sig=rows[:, 0].astype(np.int64),
+                        cfg=rows[:, 1:5].astype(np.int64), us=rows[:, 5], feat=rows[:, 6:].astype(np.float32))

@@ -177,3 +177,22 @@ def test_tuning_module_compiles_every_variant(cc):
     with pytest.raises(cc.CootError) as e:
         cc.coot_tune_prepare(hd, [_opnd(cc, 1000, 1)] * 2, 1)
     assert e.value.status == cc.COOT_EUNSUPPORTED
+
+
+def test_runnable_configurations(cc):
+    """Vector widths that the operands' alignment or shape forbid are reported, without a device."""
+    flat = cc.coot_tune_space(0)
+    h = cc.coot_expr_compile(W, _ops(2), 1)
+    ok = cc.coot_tune_runnable(h, [_opnd(cc, 100, 50)] * 2, _opnd(cc, 100, 50), -1, flat)
+    assert all(ok)
+    mis = cc.coot_operand(0x100004, 100, 50, 100, cc.COOT_F32, cc.COOT_MAT)   # 4-byte aligned only
+    ok = cc.coot_tune_runnable(h, [mis, _opnd(cc, 100, 50)], _opnd(cc, 100, 50), -1, flat)
+    assert all(o == (c[0] == 1) for o, c in zip(ok, flat))
+    tiled = cc.coot_tune_space(1)
+    hz = cc.coot_expr_compile(Z, _ops(4), 1)
+    ops = [_opnd(cc, 6, 8)] * 3 + [_opnd(cc, 8, 6)]                            # 6 rows: 2 | 6, 4 does not
+    ok = cc.coot_tune_runnable(hz, ops, _opnd(cc, 6, 8), -1, tiled)
+    assert all(o == (c[0] in (1, 2)) for o, c in zip(ok, tiled))
+    with pytest.raises(cc.CootError) as e:
+        cc.coot_tune_runnable(hz, ops, None, -1, tiled)
+    assert e.value.status == cc.COOT_EINVAL

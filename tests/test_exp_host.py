@@ -23,6 +23,13 @@ SRC = r"""
 #include "coot_exp.h"
 extern "C" void expf_n(const float* x, float* y, long n) { for (long i = 0; i < n; ++i) y[i] = coot::exp_cr<float>(x[i]); }
 extern "C" void exp_n(const double* x, double* y, long n) { for (long i = 0; i < n; ++i) y[i] = coot::exp_cr<double>(x[i]); }
+extern "C" void expf_rn_n(const float* x, float* y, long n) { for (long i = 0; i < n; ++i) y[i] = coot::exp_rn<float>(x[i]); }
+extern "C" void exp_rn_n(const double* x, double* y, long n) { for (long i = 0; i < n; ++i) y[i] = coot::exp_rn<double>(x[i]); }
+extern "C" long expf_fast_misses(const float* x, long n) {
+  long m = 0;
+  for (long i = 0; i < n; ++i) { bool ok; (void)coot::exp_fast<float>(x[i], ok); m += !ok; }
+  return m;
+}
 """
 
 
@@ -40,6 +47,10 @@ def lib():
     L = ctypes.CDLL(so)
     L.expf_n.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long]
     L.exp_n.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long]
+    L.expf_rn_n.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long]
+    L.exp_rn_n.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long]
+    L.expf_fast_misses.argtypes = [ctypes.c_void_p, ctypes.c_long]
+    L.expf_fast_misses.restype = ctypes.c_long
     return L
 
 
@@ -63,5 +74,34 @@ def test_binary64_sample(lib):
                                   -708.396418532264, np.inf, -np.inf])])
     y = np.empty_like(x)
     lib.exp_n(x.ctypes.data, y.ctypes.data, x.size)
+    want = ew.exp_rounded(x, "f64")
+    assert np.array_equal(y, want)
+
+
+def test_binary32_two_level_path(lib):
+    """exp_rn<float>: the binary64-evaluated fast path with its ambiguity test, plus the
+    exact slow path for the lanes it rejects, on a sample dense in the fast range."""
+    rng = np.random.default_rng(33)
+    bits = rng.integers(0, 1 << 32, size=1 << 20, dtype=np.uint64).astype(np.uint32)
+    x = np.concatenate([bits.view(np.float32), rng.uniform(-86, 88, 1 << 20).astype(np.float32),
+                        rng.uniform(-1e-3, 1e-3, 1 << 16).astype(np.float32),
+                        np.array([0, -0.0, -86, 88, -85.99999, 87.99999, 88.72283, -87.33655, -103.97208,
+                                  np.inf, -np.inf, np.nan], np.float32)])
+    y = np.empty_like(x)
+    lib.expf_rn_n(x.ctypes.data, y.ctypes.data, x.size)
+    want = ew.exp_rounded(x, "f32")
+    both_nan = np.isnan(y) & np.isnan(want)
+    assert np.all((y.view(np.uint32) == want.view(np.uint32)) | both_nan)
+    # the fast path decides nearly every lane of its range (rejections about 1 in 10^4)
+    inr = rng.uniform(-86, 88, 1 << 20).astype(np.float32)
+    assert lib.expf_fast_misses(inr.ctypes.data, inr.size) <= 1000
+
+
+def test_binary64_two_level_path(lib):
+    rng = np.random.default_rng(34)
+    x = np.concatenate([rng.uniform(-1, 1, 1 << 17), rng.uniform(-708, 709, 1 << 17),
+                        np.array([0.0, -707.0, 709.0, 709.782712893384, -745.1332191019411, np.inf, -np.inf])])
+    y = np.empty_like(x)
+    lib.exp_rn_n(x.ctypes.data, y.ctypes.data, x.size)
     want = ew.exp_rounded(x, "f64")
     assert np.array_equal(y, want)
