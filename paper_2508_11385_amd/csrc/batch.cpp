@@ -206,14 +206,16 @@ void build_tiles(coot_batch* b) {
 
 // Transposed-leaf tiles staged in LDS: as many as an expression needs (at most 4)
 // while the workgroup's LDS stays within 32 KB (several workgroups per CU), and
-// always within the 64 KB a workgroup may hold; the rest are read directly.
+// always within the 64 KB a workgroup may hold (2 KB of it hold the exp table);
+// the rest are read directly.
+constexpr size_t kMaxDynLds = 65536 - 2048;
 int staged_tiles(const coot_batch* b) {
   const size_t es = b->dtype == COOT_BATCH_F32 ? 4 : 8;
   const size_t stack = (size_t)b->nstk * (b->ts * b->ts / 4) * 4 * es;
   const size_t slot = (size_t)b->ts * (b->ts + 1) * es;
   const size_t budget = std::max<size_t>(32768, stack + slot);
   size_t n = std::min<size_t>({(size_t)b->max_p1, 4, budget > stack ? (budget - stack) / slot : 0});
-  while (n > 0 && stack + n * slot > 65536) --n;
+  while (n > 0 && stack + n * slot > kMaxDynLds) --n;
   return (int)n;
 }
 

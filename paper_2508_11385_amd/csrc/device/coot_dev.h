@@ -135,27 +135,30 @@ __device__ __forceinline__ vt<T, V> ldv(const T* p) {
   return r;
 }
 
+// Results are written with non-temporal stores: an expression's output is streamed
+// once, and keeping it out of L2 and the Infinity Cache leaves no dirty lines to be
+// written back while the next kernel streams its own operands.
 template <typename T, int V>
 __device__ __forceinline__ void stv(T* p, const vt<T, V>& r) {
   constexpr int B = V * (int)sizeof(T);
   if constexpr (B == 4) {
     u32 q;
     __builtin_memcpy(&q, &r, 4);
-    *reinterpret_cast<u32*>(p) = q;
+    __builtin_nontemporal_store(q, reinterpret_cast<u32*>(p));
   } else if constexpr (B == 8) {
     u32x2 q;
     __builtin_memcpy(&q, &r, 8);
-    *reinterpret_cast<u32x2*>(p) = q;
+    __builtin_nontemporal_store(q, reinterpret_cast<u32x2*>(p));
   } else if constexpr (B == 16) {
     u32x4 q;
     __builtin_memcpy(&q, &r, 16);
-    *reinterpret_cast<u32x4*>(p) = q;
+    __builtin_nontemporal_store(q, reinterpret_cast<u32x4*>(p));
   } else {
     u32x4 q0, q1;
     __builtin_memcpy(&q0, &r, 16);
     __builtin_memcpy(&q1, reinterpret_cast<const char*>(&r) + 16, 16);
-    reinterpret_cast<u32x4*>(p)[0] = q0;
-    reinterpret_cast<u32x4*>(p)[1] = q1;
+    __builtin_nontemporal_store(q0, reinterpret_cast<u32x4*>(p));
+    __builtin_nontemporal_store(q1, reinterpret_cast<u32x4*>(p) + 1);
   }
 }
 
@@ -755,8 +758,9 @@ __device__ __forceinline__ void pair_add(T& h, T& l, const Pair<T>& p) {
 // workgroup walks a whole segment, each lane accumulating its elements in
 // registers (float-float when compensated), and writes one partial per output
 // element of the segment, ws[o * n_part + segment], after a single combine of the
-// lanes through LDS.  The tile traversal (coalesced column segments, transposed
-// leaves staged through LDS) is the one of tiled_walk.
+// lanes through LDS; dim_stage2 folds each output's partials.  The tile traversal
+// (coalesced column segments, transposed leaves staged through LDS) is the one of
+// tiled_walk.
 // ===========================================================================
 template <class X, int V, int TS, int DIM, class Sink>
 __device__ __forceinline__ void tiled_walk_seg(const coot_kargs& a, Sink& sink) {
@@ -774,10 +778,9 @@ __device__ __forceinline__ void tiled_walk_seg(const coot_kargs& a, Sink& sink) 
   const i64 nseg = nkeep * a.n_part;
   const int lc = threadIdx.x % TPC, lr = threadIdx.x / TPC;
   for (i64 sgi = blockIdx.x; sgi < nseg; sgi += gridDim.x) {
-    // neighbouring workgroups take neighbouring row strips of the same column
-    // strip, so that together they stream whole columns of the column-major leaves
-    const i64 keep = DIM == 0 ? sgi / a.n_part : sgi % nkeep;
-    const i64 sg = DIM == 0 ? sgi % a.n_part : sgi / nkeep;
+    // neighbouring workgroups take neighbouring output strips of the same segment
+    // (measured faster for sum(., 0) than neighbouring segments of one strip)
+    const i64 keep = sgi % nkeep, sg = sgi / nkeep;
     sink.begin_seg();
     const i64 r_end = sg * K + K < nred ? sg * K + K : nred;
     for (i64 r = sg * K; r < r_end; ++r) {
@@ -826,6 +829,30 @@ __device__ __forceinline__ void tiled_walk_seg(const coot_kargs& a, Sink& sink) 
       if constexpr (X::NP1 > 0) __syncthreads();
     }
     sink.end_seg(a, keep * TS, sg, lr, lc);
+  }
+}
+
+// One output's n_part partials folded by one wavefront: lane l takes k = l, l + 64,
+// ... in order, then a fixed butterfly combines the lanes (the result does not
+// depend on timing).  Stage 2 of a dimension sum runs one wavefront per output.
+template <typename T, bool COMP>
+__device__ __forceinline__ void fold_output(const coot_kargs& a, i64 o, int lane) {
+  const Pair<T>* ws = (const Pair<T>*)a.ws;
+  T h = (T)0, l = (T)0;
+  for (i64 k = lane; k < a.n_part; k += 64) pair_add<T, COMP>(h, l, ws[o * a.n_part + k]);
+  if constexpr (is_int_t<T>::v) {
+    h = wave_sum<T>(h);
+  } else if constexpr (COMP) {
+    wave_dw_sum<T>(h, l);
+  } else {
+    h = wave_sum<T>(h);
+  }
+  if (lane == 0) {
+    if constexpr (is_int_t<T>::v) {
+      ((T*)a.out)[o] = h;
+    } else {
+      ((T*)a.out)[o] = h + l;
+    }
   }
 }
 
@@ -921,43 +948,12 @@ __device__ __forceinline__ void tiled_reduce_dim(const coot_kargs& a) {
   }
 }
 
-// Stage 2 of a dimension reduction: one wavefront per output element.  The
-// n_part partials of output o are contiguous (ws[o * n_part + k]); lane l folds
-// k = l, l + 64, ... in order, then the lanes are combined by a fixed butterfly,
-// so the result does not depend on timing.
 template <typename T, bool COMP>
 __device__ __forceinline__ void dim_stage2(const coot_kargs& a, i64 n_out) {
-  const Pair<T>* ws = (const Pair<T>*)a.ws;
-  T* out = (T*)a.out;
   const int lane = threadIdx.x & 63;
   const int wpb = blockDim.x >> 6;
-  for (i64 o = (i64)blockIdx.x * wpb + (threadIdx.x >> 6); o < n_out; o += (i64)gridDim.x * wpb) {
-    T h = (T)0, l = (T)0;
-    for (i64 k = lane; k < a.n_part; k += 64) {
-      const Pair<T> p = ws[o * a.n_part + k];
-      if constexpr (is_int_t<T>::v) {
-        h = op_add(h, p.hi);
-      } else if constexpr (COMP) {
-        dw_add<T>(h, l, p.hi, p.lo);
-      } else {
-        h = h + p.hi;
-      }
-    }
-    if constexpr (is_int_t<T>::v) {
-      h = wave_sum<T>(h);
-    } else if constexpr (COMP) {
-      wave_dw_sum<T>(h, l);
-    } else {
-      h = wave_sum<T>(h);
-    }
-    if (lane == 0) {
-      if constexpr (is_int_t<T>::v) {
-        out[o] = h;
-      } else {
-        out[o] = h + l;
-      }
-    }
-  }
+  for (i64 o = (i64)blockIdx.x * wpb + (threadIdx.x >> 6); o < n_out; o += (i64)gridDim.x * wpb)
+    fold_output<T, COMP>(a, o, lane);
 }
 
 }  // namespace coot

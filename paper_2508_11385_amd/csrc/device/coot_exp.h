@@ -30,6 +30,17 @@
 
 namespace coot {
 
+// On the device the table's leading words are read from an LDS copy that every
+// kernel evaluating exp fills first (exp_table_to_lds): a wavefront's 64 lanes
+// index the table at scattered rows, which LDS serves in a few cycles while the
+// texture path would spend a cycle per distinct cache line.  Host builds (tests)
+// read the global table.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define COOT_EXP_TABLE_IN_LDS 1
+__shared__ float coot_exp_lds_f[128][2];
+__shared__ double coot_exp_lds_d[128][2];
+#endif
+
 template <typename F> struct ExpConst;
 
 template <> struct ExpConst<float> {
@@ -49,8 +60,13 @@ template <> struct ExpConst<float> {
   static __host__ __device__ __forceinline__ float HALF_LESS_MARGIN() { return 0.5f - 0x1p-14f; }
   static constexpr int SUB = 149;           // subnormal grid 2^-SUB
   static __host__ __device__ __forceinline__ void tab(int j, float& t0, float& t1, float& t2) {
+#ifdef COOT_EXP_TABLE_IN_LDS
+    t0 = coot_exp_lds_f[j][0];
+    t1 = coot_exp_lds_f[j][1];
+#else
     t0 = coot_exp_tab_f[j][0];
     t1 = coot_exp_tab_f[j][1];
+#endif
     t2 = coot_exp_tab_f[j][2];
   }
 };
@@ -70,8 +86,13 @@ template <> struct ExpConst<double> {
   static __host__ __device__ __forceinline__ double FAST_HI() { return 709.0; }
   static __host__ __device__ __forceinline__ double HALF_LESS_MARGIN() { return 0.5 - 0x1p-14; }
   static __host__ __device__ __forceinline__ void tab(int j, double& t0, double& t1, double& t2) {
+#ifdef COOT_EXP_TABLE_IN_LDS
+    t0 = coot_exp_lds_d[j][0];
+    t1 = coot_exp_lds_d[j][1];
+#else
     t0 = coot_exp_tab_d[j][0];
     t1 = coot_exp_tab_d[j][1];
+#endif
     t2 = 0.0;
   }
 };
@@ -246,6 +267,27 @@ __host__ __device__ __forceinline__ F exp_fast(F x, bool& ok) {
   ok = ok && t < K::HALF_LESS_MARGIN();
   return x_ldexp(y, k);
 }
+
+#ifdef COOT_EXP_TABLE_IN_LDS
+// Copy the table's leading words to LDS; every thread of the workgroup calls it
+// before its first exp (it ends with a barrier).
+template <typename F>
+__device__ __forceinline__ void exp_table_to_lds() {
+  for (int k = threadIdx.x; k < 128; k += blockDim.x) {
+    if constexpr (sizeof(F) == 4) {
+      coot_exp_lds_f[k][0] = coot_exp_tab_f[k][0];
+      coot_exp_lds_f[k][1] = coot_exp_tab_f[k][1];
+    } else {
+      coot_exp_lds_d[k][0] = coot_exp_tab_d[k][0];
+      coot_exp_lds_d[k][1] = coot_exp_tab_d[k][1];
+    }
+  }
+  __syncthreads();
+}
+#else
+template <typename F>
+__host__ __device__ __forceinline__ void exp_table_to_lds() {}
+#endif
 
 template <typename F>
 __host__ __device__ __attribute__((noinline)) F exp_slow(F x) {

@@ -66,6 +66,7 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
   vt<T, 4>* stk = reinterpret_cast<vt<T, 4>*>(smem);                              // [nstk][NT]
   T* stage = reinterpret_cast<T*>(smem + (size_t)nstk * NT * sizeof(vt<T, 4>));  // [np1][TS][TS + 1]
   const int tid = threadIdx.x;
+  exp_table_to_lds<T>();
   for (int t = t_begin + (int)blockIdx.x; t < t_end; t += (int)gridDim.x) {
     const u32 eid = tiles[2 * t], tin = tiles[2 * t + 1];
     const BatchExpr& e = ex[eid];
@@ -229,7 +230,7 @@ extern "C" hipError_t coot_batch_launch_kernel(int dtype, int ts, unsigned grid,
   const u32* cd = (const u32*)code;
   const size_t es = dtype == COOT_BATCH_F32 ? 4 : 8;
   const size_t shmem = (size_t)nstk * (ts * ts / 4) * 4 * es + (size_t)np1 * ts * (ts + 1) * es;
-  if (nstk < 1 || np1 < 0 || shmem > 65536) return hipErrorInvalidValue;
+  if (nstk < 1 || np1 < 0 || shmem > 65536 - 2048) return hipErrorInvalidValue;  // 2 KB: the exp table
   if (dtype == COOT_BATCH_F32) {
     const float* sc = (const float*)scal;
     switch (ts) {

@@ -230,6 +230,26 @@ def test_determinism(coot):
     assert np.array_equal(s[0], s[1])
 
 
+def test_dim_sums_many_partials_and_repeats(coot):
+    """Tall and wide operands give hundreds of segment partials per output; calls of
+    different shapes alternate and repeat and must give identical bits each time."""
+    g = synth.rng_for(2, 11)
+    T = synth.uniform(g, (20000, 130), "f32")
+    Wd = synth.uniform(g, (130, 20000), "f32")
+    S = synth.uniform(g, (67, 45), "f32")
+    gT, gW, gS = up(coot, T), up(coot, Wd), up(coot, S)
+    calls = [(gT, 0), (gW, 1), (gS, 0), (gT, 1), (gW, 0), (gS, 1)]
+    first = [coot.sum(m, d).numpy().ravel() for m, d in calls]
+    for _ in range(2):
+        again = [coot.sum(m, d).numpy().ravel() for m, d in calls]
+        assert all(np.array_equal(a, b) for a, b in zip(first, again))
+    for (m, d), got in zip(calls, first):
+        h = {id(gT): T, id(gW): Wd, id(gS): S}[id(m)]
+        ex = rd.sum_dim(h, d, "f32")
+        scale = [rd.sum_abs(v) for v in (h.T if d == 0 else h)]
+        _check_rel(got, ex, scale, REL["f32"], f"sum dim {d} of {h.shape}")
+
+
 def test_edge_cases(coot):
     import paper_2508_11385_amd._coot as cc
     E = up(coot, np.zeros((0, 5), np.float32))
