@@ -44,6 +44,7 @@ def parse():
     p.add_argument("--tuner-cfgs", type=int, default=50, help="configurations timed per training signature")
     p.add_argument("--tuner-epochs", type=int, default=200)
     p.add_argument("--tuner-reps", type=int, default=5, help="timing rounds per configuration")
+    p.add_argument("--tuner-models", type=int, default=5, help="networks in the cost-model ensemble")
     p.add_argument("--tuner-dump", default="", help="write the timing tables here (.npz)")
     p.add_argument("--tuner-out", default=os.path.join(ROOT, "gpurun_out", "costmodel_mi355x.bin"))
     p.add_argument("--profile-kernels", action="store_true",
@@ -314,13 +315,14 @@ def bench_tuner(args):
     if args.tuner_dump:
         tuner.save_tables(args.tuner_dump, train + test, f_tr + f_te, h_tr + h_te, tab_tr + tab_te,
                           [0] * len(train) + [1] * len(test))
-    init = tuner.he_init(7)
+    init = tuner.he_init(7, n_models=args.tuner_models)
     t0 = time.perf_counter()
     cm, losses = cc.coot_costmodel_train(X, y, np.ones(len(y), np.float32), init, 64, 64, args.tuner_epochs, 256, 7,
-                                         1e-3)
+                                         1e-3, n_models=args.tuner_models)
     t_fit = time.perf_counter() - t0
     P, t_pred = tuner.picks(cm, test, h_te, tab_te)
-    cm0, _ = cc.coot_costmodel_train(X, y, np.ones(len(y), np.float32), init, 64, 64, 0, 256, 7, 1e-3)
+    cm0, _ = cc.coot_costmodel_train(X, y, np.ones(len(y), np.float32), init, 64, 64, 0, 256, 7, 1e-3,
+                                     n_models=args.tuner_models)
     P0, _ = tuner.picks(cm0, test, h_te, tab_te)
     # columns: exhaustive, MLP, default configuration, untrained MLP
     sets = np.stack([P[:, 0], P[:, 1], P[:, 2], P0[:, 1]], 1)
@@ -344,7 +346,8 @@ def bench_tuner(args):
         "data": "synthetic: random trees depth 1-8, rows/cols log-uniform [1,16384], timings generated on this GPU",
         "config": {"workload": "learned launch-configuration tuner", "train_signatures": len(train),
                    "train_timings": int(len(y)), "test_signatures": len(test), "test_timings": n_exh,
-                   "epochs": args.tuner_epochs, "hidden": [64, 64], "reps": args.tuner_reps},
+                   "epochs": args.tuner_epochs, "hidden": [64, 64], "ensemble": args.tuner_models,
+                   "reps": args.tuner_reps},
         "regret_definition": "t(pick)/t(exhaustive argmin) - 1, both picks re-timed side by side (11 interleaved "
                              "rounds of back-to-back launches) after the exhaustive table chose its argmin",
         "mlp": rnd(reg["mlp"]), "default_config": rnd(reg["default_config"]),

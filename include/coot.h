@@ -321,20 +321,29 @@ coot_status coot_mlp_train(coot_mlp* m, const float* X, const float* y, const fl
                            void* stream);
 void coot_mlp_release(coot_mlp* m);
 
-/* Feature vectors (n x 17, host) of an expression on an n_rows x n_cols shape for
+/* Feature vectors (n x 21, host) of an expression on an n_rows x n_cols shape for
  * each configuration: n_ops, n_operands, one-hot dtype (u32 s32 f32 f64),
  * log2(1+rows), log2(1+cols), n_trans, one-hot reduction red (0 none, 1 all,
- * 2 dim0, 3 dim1), log2 vec, log2 ept, log2 waves, log2 grid_mult. */
+ * 2 dim0, 3 dim1), log2 vec, log2 ept, log2 waves, log2 grid_mult, then the launch
+ * the configuration implies for contiguous operands on 256 CUs: log2(1+elements),
+ * tiled family (transposed leaves or a dimension sum: 64 x 64 tiles, 256 threads),
+ * log2(workgroups), log2(1 + elements per thread). */
 coot_status coot_costmodel_features(const coot_expr* e, int64_t n_rows, int64_t n_cols, int32_t red,
                                     const coot_launch_cfg* cfgs, uint32_t n, float* out);
-/* Train a cost model on N host rows: feats (N x 17), target = log(time in us),
- * mask (1 = use the row).  Inputs and target are z-scored with the training
- * statistics (kept in the model); init_params as for coot_mlp_create with n_in 17. */
+/* Train a cost model on N host rows: feats (N x 21), target = log(time in us)
+ * (any per-signature offset may be subtracted: only the ranking within a
+ * signature matters), mask (1 = use the row).  Inputs and target are z-scored with
+ * the training statistics (kept in the model).  The model is an ensemble of
+ * n_models (1..16) networks; network k starts from init_params[k * P .. (k+1) * P)
+ * (P parameters each, layout as for coot_mlp_create with n_in 21) and draws its
+ * batches with seed + k.  losses (may be NULL): the networks' mean loss per epoch. */
 coot_status coot_costmodel_train(const float* feats, const float* target, const float* mask, int32_t N,
-                                 const float* init_params, int32_t h1, int32_t h2, int32_t epochs, int32_t batch,
-                                 uint32_t seed, float lr, float* losses, void* stream, coot_costmodel** out);
-/* Predicted time of each configuration (pred_us may be NULL) and the index of the
- * smallest (lowest index on ties).  Synchronises the stream. */
+                                 const float* init_params, int32_t n_models, int32_t h1, int32_t h2, int32_t epochs,
+                                 int32_t batch, uint32_t seed, float lr, float* losses, void* stream,
+                                 coot_costmodel** out);
+/* Predicted time of each configuration (the exponential of the networks' mean
+ * output; pred_us may be NULL) and the index of the smallest (lowest index on
+ * ties).  Synchronises the stream. */
 coot_status coot_costmodel_predict(coot_costmodel* cm, const coot_expr* e, int64_t n_rows, int64_t n_cols,
                                    int32_t red, const coot_launch_cfg* cfgs, uint32_t n, float* pred_us,
                                    uint32_t* best, void* stream);

@@ -24,6 +24,7 @@ COOT_RED_ACCU, COOT_RED_SUM, COOT_RED_DOT, COOT_RED_NORM = 0, 1, 2, 3
 COOT_CF_UNFUSED = 0x1
 COOT_RF_PLAIN = 0x1
 DTYPE_CODE = {"u32": COOT_U32, "s32": COOT_S32, "f32": COOT_F32, "f64": COOT_F64}
+N_FEATURES = 21  # cost-model feature vector length
 STATUS_NAME = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ETYPE", -4: "EALIAS", -5: "ECOMPILE", -6: "EHIP",
                -7: "ENOMEM", -8: "EUNSUPPORTED"}
 
@@ -106,7 +107,7 @@ _sig = {
     "coot_costmodel_features": (C.c_int, [_P, C.c_int64, C.c_int64, C.c_int32, C.POINTER(coot_launch_cfg),
                                           C.c_uint32, C.POINTER(C.c_float)]),
     "coot_costmodel_train": (C.c_int, [C.POINTER(C.c_float), C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_int32,
-                                       C.POINTER(C.c_float), C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                       C.POINTER(C.c_float), C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                        C.c_uint32, C.c_float, C.POINTER(C.c_float), _P, C.POINTER(_P)]),
     "coot_costmodel_predict": (C.c_int, [_P, _P, C.c_int64, C.c_int64, C.c_int32, C.POINTER(coot_launch_cfg),
                                          C.c_uint32, C.POINTER(C.c_float), C.POINTER(C.c_uint32), _P]),
@@ -362,22 +363,26 @@ def coot_mlp_release(m: int) -> None:
 
 def coot_costmodel_features(h: int, n_rows: int, n_cols: int, red: int, cfgs):
     import numpy as np
-    out = np.zeros((len(cfgs), 17), np.float32)
+    out = np.zeros((len(cfgs), N_FEATURES), np.float32)
     _check(lib.coot_costmodel_features(h, n_rows, n_cols, red, _cfgs(cfgs), len(cfgs), _fptr(out)))
     return out
 
 
 def coot_costmodel_train(feats, target, mask, init_params, h1: int, h2: int, epochs: int, batch: int, seed: int,
-                         lr: float, stream: int = 0):
+                         lr: float, stream: int = 0, n_models: int = 1):
+    """init_params: n_models parameter vectors, concatenated (or a (n_models, P) array)."""
     import numpy as np
     feats = np.ascontiguousarray(feats, np.float32)
     target = np.ascontiguousarray(target, np.float32)
     mask = np.ascontiguousarray(mask, np.float32)
-    init_params = np.ascontiguousarray(init_params, np.float32)
+    init_params = np.ascontiguousarray(np.ravel(init_params), np.float32)
+    n_par = h1 * N_FEATURES + h1 + h2 * h1 + h2 + h2 + 1
+    if init_params.size != n_models * n_par:
+        raise ValueError(f"init_params must hold {n_models} x {n_par} values")
     losses = np.zeros(max(1, epochs), np.float32)
     cm = _P()
-    _check(lib.coot_costmodel_train(_fptr(feats), _fptr(target), _fptr(mask), len(target), _fptr(init_params), h1, h2,
-                                    epochs, batch, seed, lr, _fptr(losses), stream, C.byref(cm)))
+    _check(lib.coot_costmodel_train(_fptr(feats), _fptr(target), _fptr(mask), len(target), _fptr(init_params),
+                                    n_models, h1, h2, epochs, batch, seed, lr, _fptr(losses), stream, C.byref(cm)))
     return cm.value, losses[:epochs]
 
 

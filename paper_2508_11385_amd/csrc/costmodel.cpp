@@ -3,10 +3,14 @@
 // predicts log(time) for every configuration of an expression signature on a
 // shape; the prediction's argmin is the chosen configuration.
 //
-// Feature vector (17 values): n_ops, n_operands, one-hot dtype (u32 s32 f32 f64),
+// Feature vector (21 values): n_ops, n_operands, one-hot dtype (u32 s32 f32 f64),
 // log2(1 + rows), log2(1 + cols), n_trans, one-hot reduction (none all dim0 dim1),
-// log2 vec, log2 ept, log2 waves, log2 grid_mult.  Inputs and the target are
-// z-scored with the training set's statistics, stored with the weights.
+// log2 vec, log2 ept, log2 waves, log2 grid_mult, then four launch quantities the
+// configuration implies (for contiguous operands on 256 CUs): log2(1 + elements),
+// the tiled-family flag, log2(workgroups launched), log2(1 + elements per thread).
+// Inputs and the target are z-scored with the training set's statistics, stored
+// with the weights.  A model is an ensemble of networks trained from different
+// initial parameters and batch orders; its prediction is their mean.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -246,17 +250,19 @@ void coot_mlp_release(coot_mlp* m) { delete m; }
 // ---------------------------------------------------------------------------------
 // Cost model
 // ---------------------------------------------------------------------------------
-static constexpr int kNF = 17;
+static constexpr int kNF = 21;
+static constexpr int kFeatCUs = 256;  // CU count the launch-quantity features assume
+static constexpr int kMaxModels = 16;
 
 struct coot_costmodel {
-  coot_mlp* mlp = nullptr;
+  std::vector<coot_mlp*> mlps;
   float mean[kNF], stdv[kNF];
   float y_mean = 0, y_std = 1;
   float* d_feat = nullptr;
   float* d_out = nullptr;
   int cap = 0;
   ~coot_costmodel() {
-    delete mlp;
+    for (auto* m : mlps) delete m;
     if (d_feat) (void)hipFree(d_feat);
     if (d_out) (void)hipFree(d_out);
   }
@@ -291,6 +297,25 @@ void features_of(const Expr& e, int64_t R, int64_t C, int red, const coot_launch
   f[k++] = (float)std::log2((double)c.ept);
   f[k++] = (float)std::log2((double)c.waves);
   f[k++] = (float)std::log2((double)c.grid_mult);
+  // launch quantities: the tiled family (transposed leaves or a dimension sum) runs
+  // 256 threads per 64 x 64 tile; the flat family 64 * waves threads, each taking
+  // ept groups of vec elements per pass
+  const double n = (double)R * (double)C;
+  const bool tiled = e.n_p1 > 0 || red >= 2;
+  const double cap = (double)c.grid_mult * kFeatCUs;
+  double grid, threads;
+  if (tiled) {
+    grid = std::min(std::ceil((double)R / 64) * std::ceil((double)C / 64), cap);
+    threads = 256;
+  } else {
+    threads = 64.0 * c.waves;
+    grid = std::min(std::ceil(std::max(1.0, std::ceil(n / c.vec)) / (threads * c.ept)), cap);
+  }
+  grid = std::max(1.0, grid);
+  f[k++] = (float)std::log2(1.0 + n);
+  f[k++] = tiled ? 1.0f : 0.0f;
+  f[k++] = (float)std::log2(grid);
+  f[k++] = (float)std::log2(1.0 + n / (grid * threads));
 }
 
 }  // namespace
@@ -307,10 +332,12 @@ coot_status coot_costmodel_features(const coot_expr* h, int64_t n_rows, int64_t 
 }
 
 coot_status coot_costmodel_train(const float* feats, const float* target, const float* mask, int32_t N,
-                                 const float* init_params, int32_t h1, int32_t h2, int32_t epochs, int32_t batch,
-                                 uint32_t seed, float lr, float* losses, void* stream, coot_costmodel** out) {
+                                 const float* init_params, int32_t n_models, int32_t h1, int32_t h2, int32_t epochs,
+                                 int32_t batch, uint32_t seed, float lr, float* losses, void* stream,
+                                 coot_costmodel** out) {
   return guarded([&] {
     if (!feats || !target || !mask || !init_params || !out || N <= 1) fail(COOT_EINVAL, "bad training arguments");
+    if (n_models < 1 || n_models > kMaxModels) fail(COOT_EINVAL, "n_models must be 1..16");
     auto cm = std::make_unique<coot_costmodel>();
     // z-score statistics of the training set (binary64 accumulation)
     for (int j = 0; j < kNF; ++j) {
@@ -343,10 +370,6 @@ coot_status coot_costmodel_train(const float* feats, const float* target, const 
       yn[i] = mask[i] > 0 ? (float)((target[i] - ym) / cm->y_std) : 0.0f;
     }
     hipStream_t s = (hipStream_t)stream;
-    coot_mlp* m = nullptr;
-    coot_status st = coot_mlp_create(kNF, h1, h2, init_params, &m);
-    if (st != COOT_OK) fail(st, last_error());
-    cm->mlp = m;
     float* dX = (float*)dmalloc(Xn.size() * 4);
     float* dy = (float*)dmalloc((size_t)N * 4);
     float* dm = (float*)dmalloc((size_t)N * 4);
@@ -354,8 +377,19 @@ coot_status coot_costmodel_train(const float* feats, const float* target, const 
       hip_check(hipMemcpy(dX, Xn.data(), Xn.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
       hip_check(hipMemcpy(dy, yn.data(), (size_t)N * 4, hipMemcpyHostToDevice), "hipMemcpy");
       hip_check(hipMemcpy(dm, mask, (size_t)N * 4, hipMemcpyHostToDevice), "hipMemcpy");
-      st = coot_mlp_train(m, dX, dy, dm, mask, N, batch, epochs, seed, lr, losses, s);
-      if (st != COOT_OK) fail(st, last_error());
+      const size_t np = (size_t)h1 * kNF + h1 + (size_t)h2 * h1 + h2 + h2 + 1;
+      std::vector<float> ls(std::max(1, epochs));
+      for (int k = 0; k < n_models; ++k) {
+        coot_mlp* m = nullptr;
+        coot_status st = coot_mlp_create(kNF, h1, h2, init_params + k * np, &m);
+        if (st != COOT_OK) fail(st, last_error());
+        cm->mlps.push_back(m);
+        // network k: its own initial parameters and batch order (seed + k)
+        st = coot_mlp_train(m, dX, dy, dm, mask, N, batch, epochs, seed + (uint32_t)k, lr, ls.data(), s);
+        if (st != COOT_OK) fail(st, last_error());
+        if (losses)
+          for (int e = 0; e < epochs; ++e) losses[e] = (k == 0 ? 0.0f : losses[e]) + ls[e] / (float)n_models;
+      }
     } catch (...) {
       (void)hipFree(dX);
       (void)hipFree(dy);
@@ -389,10 +423,13 @@ coot_status coot_costmodel_predict(coot_costmodel* cm, const coot_expr* h, int64
     }
     hipStream_t s = (hipStream_t)stream;
     hip_check(hipMemcpyAsync(cm->d_feat, f.data(), f.size() * 4, hipMemcpyHostToDevice, s), "hipMemcpyAsync");
-    forward(cm->mlp, cm->d_feat, (int)n, s);
-    std::vector<float> y(n);
-    hip_check(hipMemcpyAsync(y.data(), cm->mlp->A3, (size_t)n * 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
-    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    std::vector<float> y(n, 0.0f), yk(n);
+    for (auto* m : cm->mlps) {
+      forward(m, cm->d_feat, (int)n, s);
+      hip_check(hipMemcpyAsync(yk.data(), m->A3, (size_t)n * 4, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+      hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
+      for (uint32_t i = 0; i < n; ++i) y[i] += yk[i] / (float)cm->mlps.size();
+    }
     uint32_t bi = 0;
     for (uint32_t i = 0; i < n; ++i) {
       const float us = std::exp(y[i] * cm->y_std + cm->y_mean);
@@ -406,19 +443,23 @@ coot_status coot_costmodel_predict(coot_costmodel* cm, const coot_expr* h, int64
 coot_status coot_costmodel_save(const coot_costmodel* cm, const char* path) {
   return guarded([&] {
     if (!cm || !path) fail(COOT_EINVAL, "NULL argument");
-    std::vector<float> p(cm->mlp->n);
-    hip_check(hipMemcpy(p.data(), cm->mlp->P, p.size() * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+    if (cm->mlps.empty()) fail(COOT_EINVAL, "empty cost model");
+    const coot_mlp* m0 = cm->mlps[0];
     std::ofstream f(path, std::ios::binary);
     if (!f) fail(COOT_EINVAL, std::string("cannot write ") + path);
-    const char magic[8] = {'C', 'O', 'O', 'T', 'M', 'L', 'P', '1'};
-    const int32_t dims[3] = {cm->mlp->F, cm->mlp->H1, cm->mlp->H2};
+    const char magic[8] = {'C', 'O', 'O', 'T', 'M', 'L', 'P', '2'};
+    const int32_t dims[4] = {m0->F, m0->H1, m0->H2, (int32_t)cm->mlps.size()};
     f.write(magic, 8);
     f.write((const char*)dims, sizeof dims);
     f.write((const char*)cm->mean, sizeof cm->mean);
     f.write((const char*)cm->stdv, sizeof cm->stdv);
     f.write((const char*)&cm->y_mean, 4);
     f.write((const char*)&cm->y_std, 4);
-    f.write((const char*)p.data(), (std::streamsize)(p.size() * 4));
+    for (const auto* m : cm->mlps) {
+      std::vector<float> p(m->n);
+      hip_check(hipMemcpy(p.data(), m->P, p.size() * 4, hipMemcpyDeviceToHost), "hipMemcpy");
+      f.write((const char*)p.data(), (std::streamsize)(p.size() * 4));
+    }
     if (!f) fail(COOT_EINVAL, std::string("write failed: ") + path);
   });
 }
@@ -429,11 +470,11 @@ coot_status coot_costmodel_load(const char* path, coot_costmodel** out) {
     std::ifstream f(path, std::ios::binary);
     if (!f) fail(COOT_EINVAL, std::string("cannot read ") + path);
     char magic[8];
-    int32_t dims[3];
+    int32_t dims[4];
     f.read(magic, 8);
     f.read((char*)dims, sizeof dims);
-    if (!f || std::memcmp(magic, "COOTMLP1", 8) != 0 || dims[0] != kNF || dims[1] <= 0 || dims[2] <= 0 ||
-        dims[1] > 4096 || dims[2] > 4096)
+    if (!f || std::memcmp(magic, "COOTMLP2", 8) != 0 || dims[0] != kNF || dims[1] <= 0 || dims[2] <= 0 ||
+        dims[1] > 4096 || dims[2] > 4096 || dims[3] < 1 || dims[3] > kMaxModels)
       fail(COOT_EINVAL, "not a cost-model file");
     auto cm = std::make_unique<coot_costmodel>();
     f.read((char*)cm->mean, sizeof cm->mean);
@@ -441,13 +482,15 @@ coot_status coot_costmodel_load(const char* path, coot_costmodel** out) {
     f.read((char*)&cm->y_mean, 4);
     f.read((char*)&cm->y_std, 4);
     const size_t n = (size_t)dims[1] * dims[0] + dims[1] + (size_t)dims[2] * dims[1] + dims[2] + dims[2] + 1;
-    std::vector<float> p(n);
-    f.read((char*)p.data(), (std::streamsize)(n * 4));
-    if (!f) fail(COOT_EINVAL, "truncated cost-model file");
-    coot_mlp* m = nullptr;
-    coot_status st = coot_mlp_create(dims[0], dims[1], dims[2], p.data(), &m);
-    if (st != COOT_OK) fail(st, last_error());
-    cm->mlp = m;
+    for (int k = 0; k < dims[3]; ++k) {
+      std::vector<float> p(n);
+      f.read((char*)p.data(), (std::streamsize)(n * 4));
+      if (!f) fail(COOT_EINVAL, "truncated cost-model file");
+      coot_mlp* m = nullptr;
+      coot_status st = coot_mlp_create(dims[0], dims[1], dims[2], p.data(), &m);
+      if (st != COOT_OK) fail(st, last_error());
+      cm->mlps.push_back(m);
+    }
     *out = cm.release();
   });
 }

@@ -6,7 +6,7 @@ The system produces its own training data: random expression signatures
 by the autotuner (coot_tune_table) over their family's configuration space; the
 training set samples configurations from the training signatures' tables; a cost
 model (coot_costmodel_train: MLP forward / backward / Adam kernels on the GPU)
-learns log-time relative to the default configuration from the 17 features; on
+learns log-time relative to the default configuration from the 21 features; on
 held-out signatures its argmin and the exhaustive argmin are re-timed side by
 side (regret = t(pick) / t(exhaustive pick) - 1).
 
@@ -128,10 +128,14 @@ def _valid(t):
     return np.flatnonzero(np.isfinite(t) & (t > 0))
 
 
-def default_index(cfgs, dtype):
-    """The library's default configuration (what coot_expr_eval launches without a tuner)."""
+def default_index(cfgs, dtype, t=None):
+    """What coot_expr_eval launches without a tuner: the default configuration, or, when
+    the operands do not allow its vector width (t[k] NaN), the same with scalar accesses."""
     want = (2 if dtype == "f64" else 4, 4, 4, 8) if len(cfgs) > 12 else (2 if dtype == "f64" else 4, 1, 4, 16)
-    return cfgs.index(want) if want in cfgs else 0
+    k = cfgs.index(want)
+    if t is not None and not np.isfinite(t[k]):
+        k = cfgs.index((1,) + want[1:])
+    return k
 
 
 def dataset(sigs, handles, tables, configs_per_sig=None, seed=0):
@@ -147,7 +151,7 @@ def dataset(sigs, handles, tables, configs_per_sig=None, seed=0):
         ok = _valid(t)
         if ok.size == 0:
             continue
-        d = default_index(cfgs, spec.dtype)
+        d = default_index(cfgs, spec.dtype, t)
         ref = math.log(t[d]) if d in ok else float(np.mean(np.log(t[ok])))
         if configs_per_sig is None or configs_per_sig >= ok.size:
             pick = ok
@@ -162,12 +166,16 @@ def dataset(sigs, handles, tables, configs_per_sig=None, seed=0):
     return np.concatenate(feats).astype(np.float32), np.concatenate(target).astype(np.float32)
 
 
-def he_init(seed: int, f: int = 17, h1: int = 64, h2: int = 64):
-    """He-normal initial parameters (weights N(0, 2/fan_in), biases 0), flat in the library's order."""
-    g = synth.rng_for(6, seed)
-    parts = [g.normal(0, math.sqrt(2 / f), (h1, f)), np.zeros(h1), g.normal(0, math.sqrt(2 / h1), (h2, h1)),
-             np.zeros(h2), g.normal(0, math.sqrt(2 / h2), (1, h2)), np.zeros(1)]
-    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+def he_init(seed: int, f: int = cc.N_FEATURES, h1: int = 64, h2: int = 64, n_models: int = 1):
+    """He-normal initial parameters (weights N(0, 2/fan_in), biases 0) of n_models networks,
+    each flat in the library's order, concatenated."""
+    out = []
+    for k in range(n_models):
+        g = synth.rng_for(6, seed, k)
+        parts = [g.normal(0, math.sqrt(2 / f), (h1, f)), np.zeros(h1), g.normal(0, math.sqrt(2 / h1), (h2, h1)),
+                 np.zeros(h2), g.normal(0, math.sqrt(2 / h2), (1, h2)), np.zeros(1)]
+        out.append(np.concatenate([p.ravel() for p in parts]))
+    return np.concatenate(out).astype(np.float32)
 
 
 def picks(cm, sigs, handles, tables):
@@ -181,8 +189,7 @@ def picks(cm, sigs, handles, tables):
         k, _ = cc.coot_costmodel_predict(cm, h, spec.out_shape[0], spec.out_shape[1], 0 if mode < 0 else 1,
                                          [cfgs[i] for i in ok])
         t_pred += time.perf_counter() - t0
-        d = default_index(cfgs, spec.dtype)
-        out.append((exh, int(ok[k]), d if d in ok else exh))
+        out.append((exh, int(ok[k]), default_index(cfgs, spec.dtype, t)))
     return np.asarray(out, np.int64), t_pred / max(1, len(sigs))
 
 

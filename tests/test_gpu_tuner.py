@@ -147,12 +147,13 @@ def test_tune_table_and_policies(env):
 
 def test_costmodel_roundtrip_and_prediction(env, tmp_path):
     coot, cc, torch = env
-    _, flat = _init_params(4)
+    NF = cc.N_FEATURES
+    flat = np.concatenate([_init_params(4 + k, f=NF)[1] for k in range(3)])   # an ensemble of 3
     g = synth.rng_for(43)
-    X = g.normal(size=(512, F)).astype(np.float32)
+    X = g.normal(size=(512, NF)).astype(np.float32)
     y = (X[:, 6] + 0.5 * X[:, 13]).astype(np.float32)     # depends on rows and vec
     mask = np.ones(512, np.float32)
-    cm, losses = cc.coot_costmodel_train(X, y, mask, flat, H1, H2, 30, 128, 5, 3e-3)
+    cm, losses = cc.coot_costmodel_train(X, y, mask, flat, H1, H2, 30, 128, 5, 3e-3, n_models=3)
     assert losses[-1] < losses[0]
     h = cc.coot_expr_compile([("load", 0), ("load", 1), ("add",)], [(cc.COOT_F32, 0)] * 2, 0)
     space = cc.coot_tune_space(0)

@@ -80,5 +80,22 @@ def test_features_hand_example():
                ("load", 3), ("trans",), ("sub",)]
     f = features.features(postfix, "f32", 4096, 4096, "dim1", (4, 2, 4, 8))
     assert f.shape == (features.N_FEATURES,)
-    want = [5, 4, 0, 0, 1, 0, math.log2(4097), math.log2(4097), 1, 0, 0, 0, 1, 2, 1, 2, 3]
+    # tiled: 64 x 64 = 4096 tiles, capped at 8 * 256 = 2048 workgroups of 256 threads, 32 elements each
+    want = [5, 4, 0, 0, 1, 0, math.log2(4097), math.log2(4097), 1, 0, 0, 0, 1, 2, 1, 2, 3,
+            math.log2(1 + 4096 * 4096), 1, 11, math.log2(33)]
     assert np.allclose(f, want)
+    # exp(A) / (1 + abs(B)) on 1000 x 3, element-wise: flat, 750 groups of 4 fit one workgroup of
+    # 256 threads x 4 groups; 3000 / 256 elements per thread
+    wpost = [("load", 0), ("exp",), ("scalar", 0), ("load", 1), ("abs",), ("add",), ("div",)]
+    f = features.features(wpost, "f32", 1000, 3, "none", (4, 4, 4, 8))
+    want = [4, 2, 0, 0, 1, 0, math.log2(1001), 2, 0, 1, 0, 0, 0, 2, 2, 2, 3,
+            math.log2(3001), 0, 0, math.log2(1 + 3000 / 256)]
+    assert np.allclose(f, want)
+
+
+def test_transposed_leaf_detection():
+    A, B = ("load", 0), ("load", 1)
+    assert not features.has_transposed_leaf([A, ("trans",), ("trans",), B, ("add",)])
+    assert features.has_transposed_leaf([A, B, ("trans",), ("add",), ("trans",)])     # A under one trans
+    assert not features.has_transposed_leaf([A, ("trans",), ("neg",), ("trans",)])
+    assert features.has_transposed_leaf([("scalar", 0), A, ("trans",), ("schur",)])
