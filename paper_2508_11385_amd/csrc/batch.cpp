@@ -4,7 +4,8 @@
 // Each expression's analysed IR (leaves with their transpose parity) becomes
 // register bytecode: the tree is emitted in Sethi-Ullman order (the operand that
 // needs more registers first), so registers behave as a stack of depth
-// need(root) <= 8.  Every expression is cut into TS x TS output tiles; the tile
+// need(root) <= 8; a binary op with a leaf or scalar operand takes it directly
+// (one instruction, no register).  Every expression is cut into TS x TS output tiles; the tile
 // list holds (expression, tile) pairs and a fixed grid walks it round-robin.
 #include <algorithm>
 #include <chrono>
@@ -70,7 +71,11 @@ int emit_program(const Expr& e, uint32_t sc_base, std::vector<uint32_t>* code) {
       n.a = st.back();
       st.pop_back();
       const int na = nodes[n.a].need, nb = nodes[n.b].need;
-      n.need = na == nb ? na + 1 : std::max(na, nb);
+      const bool pa = nodes[n.a].kind <= 1, pb = nodes[n.b].kind <= 1;  // plain leaf or scalar
+      // a plain operand is taken directly by the op, so only the other one needs registers
+      if (pb) n.need = na;
+      else if (pa) n.need = nb;
+      else n.need = na == nb ? na + 1 : std::max(na, nb);
     } else {
       n.kind = 2;
       n.op = map_op(o.code);
@@ -108,11 +113,23 @@ int emit_program(const Expr& e, uint32_t sc_base, std::vector<uint32_t>* code) {
         fs.pop_back();
       }
     } else {
-      const bool left_first = nodes[n.a].need >= nodes[n.b].need;
+      const bool pa = nodes[n.a].kind <= 1, pb = nodes[n.b].kind <= 1;
+      // a plain operand (leaf or scalar) goes second and is fused into the op; otherwise
+      // the operand needing more registers goes first
+      const bool left_first = pb ? true : pa ? false : nodes[n.a].need >= nodes[n.b].need;
       const int first = left_first ? n.a : n.b, second = left_first ? n.b : n.a;
       if (f.stage == 0) {
         f.stage = 1;
         fs.push_back({first, f.base, 0});
+      } else if (f.stage == 1 && nodes[second].kind <= 1) {
+        uint32_t op = n.op;
+        if (!left_first) {  // r[b] holds the b-operand: swap the non-commutative ops
+          if (op == OP_SUB) op = OP_RSUB;
+          else if (op == OP_DIV) op = OP_RDIV;
+        }
+        const Node& x = nodes[second];
+        code->push_back(encode((x.kind == 0 ? OP_WITH_LEAF : OP_WITH_SCAL) + op, f.base, x.arg));
+        fs.pop_back();
       } else if (f.stage == 1) {
         f.stage = 2;
         const int base = f.base;
@@ -315,6 +332,7 @@ coot_status coot_batch_create(uint32_t n, coot_expr* const* exprs, const coot_op
       be.out_ld = old;
       be.n_rows = (int32_t)R;
       be.n_cols = (int32_t)C;
+      be.n_leaves = (int32_t)e.leaves.size();
       be.code_off = (int32_t)b->code.size();
       be.sc_off = 0;
       const int regs = emit_program(e, (uint32_t)scal.size(), &b->code);

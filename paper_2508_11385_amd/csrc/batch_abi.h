@@ -13,7 +13,10 @@ namespace batch {
 enum : uint32_t {
   OP_ADD = 0, OP_SUB = 1, OP_MUL = 2, OP_DIV = 3, OP_RSUB = 4, OP_RDIV = 5,  // binary (R: operands swapped)
   OP_NEG = 6, OP_ABS = 7, OP_EXP = 8, OP_LOG = 9, OP_SQRT = 10, OP_SQUARE = 11,  // unary
-  OP_LEAF = 12, OP_SCAL = 13
+  OP_LEAF = 12, OP_SCAL = 13,
+  // binary op whose second operand is a leaf / a scalar, taken directly: r[b] = op(r[b], x)
+  OP_WITH_LEAF = 16,  // + binary opcode (0..5)
+  OP_WITH_SCAL = 24   // + binary opcode (0..5)
 };
 
 inline constexpr uint32_t encode(uint32_t op, uint32_t reg, uint32_t arg) { return op | (reg << 6) | (arg << 9); }
@@ -31,7 +34,7 @@ struct BatchExpr {
   uint32_t p1_mask;                   // bit k: leaf k is read transposed
   int32_t vec4;                       // 1: 128-bit accesses are valid
   int32_t flat;                       // 1: untransposed contiguous leaves and output: flat chunks
-  int32_t pad_;
+  int32_t n_leaves;                   // leaves used (leaf[0 .. n_leaves))
 };
 
 }  // namespace batch

@@ -18,6 +18,7 @@
 // emitted in Sethi-Ullman order so registers form a stack:
 //   LEAF / SCAL   push into register b (the previous top, register b-1, moves to LDS)
 //   binary op     r[b] = op(r[b], r[b+1]); R-variant r[b] = op(r[b+1], r[b])
+//   op WITH_LEAF / WITH_SCAL   r[b] = op(r[b], leaf or scalar `argument`)
 //   unary op      r[b] = op(r[b])
 // The top of the stack stays in VGPRs (`acc`); the entries below it live in a
 // per-thread LDS stack indexed by the (wave-uniform) register number, so no
@@ -33,35 +34,76 @@
 namespace coot {
 namespace batch {
 
+// acc[q] = op(acc[q], x[q]) (R-variants: op(x[q], acc[q])); one dispatch for the 4 values
 template <typename T>
-__device__ __forceinline__ T bin_op(u32 op, T a, T b) {
+__device__ __forceinline__ void apply_bin(u32 op, T (&acc)[4], const vt<T, 4>& x) {
   switch (op) {
-    case OP_ADD: return op_add(a, b);
-    case OP_SUB: return op_sub(a, b);
-    case OP_MUL: return op_mul(a, b);
-    case OP_DIV: return op_div(a, b);
-    case OP_RSUB: return op_sub(b, a);
-    default: return op_div(b, a);  // OP_RDIV
+    case OP_ADD:
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = op_add(acc[q], x.v[q]);
+      break;
+    case OP_SUB:
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = op_sub(acc[q], x.v[q]);
+      break;
+    case OP_MUL:
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = op_mul(acc[q], x.v[q]);
+      break;
+    case OP_DIV:
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = op_div(acc[q], x.v[q]);
+      break;
+    case OP_RSUB:
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = op_sub(x.v[q], acc[q]);
+      break;
+    default:  // OP_RDIV
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = op_div(x.v[q], acc[q]);
+      break;
   }
 }
 
 template <typename T>
-__device__ __forceinline__ T un_op(u32 op, T a) {
+__device__ __forceinline__ void apply_un(u32 op, T (&acc)[4]) {
   switch (op) {
-    case OP_NEG: return op_neg(a);
-    case OP_ABS: return op_abs(a);
-    case OP_EXP: return op_exp(a);
-    case OP_LOG: return op_log(a);
-    case OP_SQRT: return op_sqrt(a);
-    default: return op_square(a);  // OP_SQUARE
+    case OP_NEG:
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = op_neg(acc[q]);
+      break;
+    case OP_ABS:
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = op_abs(acc[q]);
+      break;
+    case OP_EXP:
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = op_exp(acc[q]);
+      break;
+    case OP_LOG:
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = op_log(acc[q]);
+      break;
+    case OP_SQRT:
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = op_sqrt(acc[q]);
+      break;
+    default:  // OP_SQUARE
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = op_square(acc[q]);
+      break;
   }
 }
+
+// untransposed leaves loaded before the bytecode runs
+template <typename T> struct Prefetch { static constexpr int N = sizeof(T) == 4 ? 6 : 4; };
 
 template <typename T, int TS>
 __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restrict__ ex, const u32* __restrict__ tiles,
                                                       int t_begin, int t_end, const u32* __restrict__ code,
                                                       const T* __restrict__ scal, int nstk, int np1) {
   constexpr int NT = TS * TS / 4;  // threads: 4 elements each
+  constexpr int PF = Prefetch<T>::N;
   extern __shared__ __align__(16) unsigned char smem[];
   vt<T, 4>* stk = reinterpret_cast<vt<T, 4>*>(smem);                              // [nstk][NT]
   T* stage = reinterpret_cast<T*>(smem + (size_t)nstk * NT * sizeof(vt<T, 4>));  // [np1][TS][TS + 1]
@@ -121,12 +163,86 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
       for (int q = 0; q < 4; ++q) in[q] = iq[q] < R && jq[q] < C;
     }
     const bool all_in = in[0] && in[1] && in[2] && in[3];
+    // an untransposed leaf's 4 values for this thread (flat chunk or 2-D tile layout)
+    auto load_direct = [&](int k) __attribute__((always_inline)) {
+      vt<T, 4> g;
+      const T* src = (const T*)e.leaf[k];
+      if (flat) {
+        if (v4 && all_in) {
+          g = ldv<T, 4>(src + fbase);
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) g.v[q] = in[q] ? src[fbase + q] : (T)0;
+        }
+      } else {
+        const i64 ld = e.ld[k];
+        if (v4) {
+          if (in[0]) {
+            g = ldv<T, 4>(src + (i64)iq[0] + (i64)jq[0] * ld);
+          } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) g.v[q] = (T)0;
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) g.v[q] = in[q] ? src[(i64)iq[q] + (i64)jq[q] * ld] : (T)0;
+        }
+      }
+      return g;
+    };
+    // the first PF untransposed leaves are loaded up front, all in flight together,
+    // instead of one round trip per LEAF instruction
+    typedef T pfvec __attribute__((ext_vector_type(4 * PF)));
+    pfvec pf;
+#pragma unroll
+    for (int k = 0; k < PF; ++k)
+      if (k < e.n_leaves && !((p1 >> k) & 1u)) {
+        const vt<T, 4> g = load_direct(k);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pf[4 * k + q] = g.v[q];
+      }
+    // value of leaf k for this thread's 4 elements
+    auto fetch_leaf = [&](u32 k) __attribute__((always_inline)) {
+      vt<T, 4> g;
+      if (!flat && ((p1 >> k) & 1u)) {
+        // transposed leaf: staged in LDS (slot = staged leaves before it) or read directly
+        const int slot = __builtin_popcount(p1 & ((1u << k) - 1u));
+        if (slot < np1) {
+          const T* st = stage + slot * TS * (TS + 1);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) g.v[q] = in[q] ? st[(iq[q] - i0) * (TS + 1) + (jq[q] - j0)] : (T)0;
+        } else {
+          const T* src = (const T*)e.leaf[k];
+          const i64 ld = e.ld[k];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) g.v[q] = in[q] ? src[(i64)jq[q] + (i64)iq[q] * ld] : (T)0;
+        }
+      } else if ((int)k < PF) {
+        // wave-uniform index into a register vector
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g.v[q] = pf[4 * (int)k + q];
+      } else {
+        g = load_direct((int)k);
+      }
+      return g;
+    };
     T acc[4];
     const u32* prog = code + e.code_off;
     for (int pc = 0; pc < e.code_len; ++pc) {
       const u32 ins = prog[pc];
       const u32 op = ins & 63u, b = (ins >> 6) & 7u, arg = ins >> 9;
-      if (op == OP_LEAF || op == OP_SCAL) {
+      if (op >= OP_WITH_LEAF) {
+        // binary op with a leaf or scalar operand taken directly
+        vt<T, 4> x;
+        if (op >= OP_WITH_SCAL) {
+          const T sv = scal[e.sc_off + (int)arg];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) x.v[q] = sv;
+        } else {
+          x = fetch_leaf(arg);
+        }
+        apply_bin<T>(op & 7u, acc, x);
+      } else if (op == OP_LEAF || op == OP_SCAL) {
         if (b > 0) {
           vt<T, 4> s;
 #pragma unroll
@@ -137,53 +253,23 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
           const T sv = scal[e.sc_off + (int)arg];
 #pragma unroll
           for (int q = 0; q < 4; ++q) acc[q] = sv;
-        } else if (flat) {
-          const T* src = (const T*)e.leaf[arg];
-          if (v4 && all_in) {
-            const vt<T, 4> g = ldv<T, 4>(src + fbase);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = g.v[q];
-          } else {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = in[q] ? src[fbase + q] : (T)0;
-          }
-        } else if ((p1 >> arg) & 1u) {
-          // transposed leaf: staged in LDS (slot = staged leaves before it) or read directly
-          const int slot = __builtin_popcount(p1 & ((1u << arg) - 1u));
-          if (slot < np1) {
-            const T* st = stage + slot * TS * (TS + 1);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = in[q] ? st[(iq[q] - i0) * (TS + 1) + (jq[q] - j0)] : (T)0;
-          } else {
-            const T* src = (const T*)e.leaf[arg];
-            const i64 ld = e.ld[arg];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = in[q] ? src[(i64)jq[q] + (i64)iq[q] * ld] : (T)0;
-          }
         } else {
-          const T* src = (const T*)e.leaf[arg];
-          const i64 ld = e.ld[arg];
-          if (v4) {
-            if (in[0]) {
-              const vt<T, 4> g = ldv<T, 4>(src + (i64)iq[0] + (i64)jq[0] * ld);
+          const vt<T, 4> g = fetch_leaf(arg);
 #pragma unroll
-              for (int q = 0; q < 4; ++q) acc[q] = g.v[q];
-            } else {
-#pragma unroll
-              for (int q = 0; q < 4; ++q) acc[q] = (T)0;
-            }
-          } else {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q] = in[q] ? src[(i64)iq[q] + (i64)jq[q] * ld] : (T)0;
-          }
+          for (int q = 0; q < 4; ++q) acc[q] = g.v[q];
         }
       } else if (op <= OP_RDIV) {
+        // r[b] = op(r[b], r[b+1]): r[b] from the LDS stack, r[b+1] the top
         const vt<T, 4> a = stk[b * NT + tid];
+        vt<T, 4> top;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = bin_op<T>(op, a.v[q], acc[q]);
+        for (int q = 0; q < 4; ++q) {
+          top.v[q] = acc[q];
+          acc[q] = a.v[q];
+        }
+        apply_bin<T>(op, acc, top);
       } else {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = un_op<T>(op, acc[q]);
+        apply_un<T>(op, acc);
       }
     }
     T* out = (T*)e.out;
