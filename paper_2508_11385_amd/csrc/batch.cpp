@@ -5,8 +5,9 @@
 // register bytecode: the tree is emitted in Sethi-Ullman order (the operand that
 // needs more registers first), so registers behave as a stack of depth
 // need(root) <= 8; a binary op with a leaf or scalar operand takes it directly
-// (one instruction, no register).  Every expression is cut into TS x TS output tiles; the tile
-// list holds (expression, tile) pairs and a fixed grid walks it round-robin.
+// (one instruction, no register).  Every expression is cut into tiles (flat
+// chunks or TS x TS output tiles); the tile list holds (expression, tile) pairs
+// and a fixed grid walks it round-robin.
 #include <algorithm>
 #include <chrono>
 #include <cstring>

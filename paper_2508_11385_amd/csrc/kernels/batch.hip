@@ -95,6 +95,8 @@ __device__ __forceinline__ void apply_un(u32 op, T (&acc)[4]) {
   }
 }
 
+constexpr int kMaxStaged = 4;  // transposed leaves staged in LDS per tile (at most)
+
 // untransposed leaves loaded before the bytecode runs
 template <typename T> struct Prefetch { static constexpr int N = sizeof(T) == 4 ? 6 : 4; };
 
@@ -118,6 +120,7 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
     const u32 p1 = e.p1_mask;
     int iq[4], jq[4];
     bool in[4];
+    vt<T, 4> sv[kMaxStaged];
     i64 fbase = 0;
     int i0 = 0, j0 = 0;
     if (flat) {
@@ -129,21 +132,6 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
       const int ti = (int)(tin % (u32)e.tiles_r), tj = (int)(tin / (u32)e.tiles_r);
       i0 = ti * TS;
       j0 = tj * TS;
-      if (p1 && np1 > 0) {
-        int slot = 0;
-        for (int k = 0; k < COOT_BATCH_MAXL && slot < np1; ++k) {
-          if (!((p1 >> k) & 1u)) continue;
-          const T* src = (const T*)e.leaf[k];
-          const i64 ld = e.ld[k];
-          for (int idx = tid; idx < TS * TS; idx += NT) {
-            const int sc = idx % TS, il = idx / TS;
-            const int i = i0 + il, j = j0 + sc;
-            stage[(slot * TS + il) * (TS + 1) + sc] = (i < R && j < C) ? src[(i64)j + (i64)i * ld] : (T)0;
-          }
-          ++slot;
-        }
-        __syncthreads();
-      }
       if (v4) {
         const int lc = tid % (TS / 4), lr = tid / (TS / 4);
 #pragma unroll
@@ -161,6 +149,26 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) in[q] = iq[q] < R && jq[q] < C;
+      // staged transposed leaves: this thread's 4 values of each (element idx = tid + q * NT
+      // of the tile, read along the leaf's contiguous dimension), loads issued together
+      if (p1 && np1 > 0) {
+        u32 rest = p1;
+#pragma unroll
+        for (int sl = 0; sl < kMaxStaged; ++sl) {
+          if (sl < np1 && rest != 0u) {
+            const int k = __builtin_ctz(rest);
+            rest &= rest - 1u;
+            const T* src = (const T*)e.leaf[k];
+            const i64 ld = e.ld[k];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int idx = tid + q * NT, sc = idx % TS, il = idx / TS;
+              const int i = i0 + il, j = j0 + sc;
+              sv[sl].v[q] = (i < R && j < C) ? src[(i64)j + (i64)i * ld] : (T)0;
+            }
+          }
+        }
+      }
     }
     const bool all_in = in[0] && in[1] && in[2] && in[3];
     // an untransposed leaf's 4 values for this thread (flat chunk or 2-D tile layout)
@@ -226,6 +234,22 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
       }
       return g;
     };
+    if (!flat && p1 && np1 > 0) {
+      __syncthreads();  // the previous tile's reads of the staging area are done
+      u32 rest = p1;
+#pragma unroll
+      for (int sl = 0; sl < kMaxStaged; ++sl) {
+        if (sl < np1 && rest != 0u) {
+          rest &= rest - 1u;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int idx = tid + q * NT;
+            stage[(sl * TS + idx / TS) * (TS + 1) + idx % TS] = sv[sl].v[q];
+          }
+        }
+      }
+      __syncthreads();
+    }
     T acc[4];
     const u32* prog = code + e.code_off;
     for (int pc = 0; pc < e.code_len; ++pc) {
@@ -298,7 +322,6 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
         for (int q = 0; q < 4; ++q)
           if (in[q]) out[(i64)iq[q] + (i64)jq[q] * old] = acc[q];
       }
-      if (p1 && np1 > 0) __syncthreads();  // the next tile restages LDS
     }
   }
 }
