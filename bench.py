@@ -39,6 +39,8 @@ def parse():
     p.add_argument("--workload", default="expr4096", choices=["expr4096", "batch", "tuner"],
                    help="expr4096: the fused 2-D expression step (default); batch: 10,000 small expressions")
     p.add_argument("--batch-n", type=int, default=10_000)
+    p.add_argument("--batch-fused-sample", type=int, default=500,
+                   help="expressions timed with the plain fused kernel, one launch each")
     p.add_argument("--tuner-train", type=int, default=1000, help="training signatures")
     p.add_argument("--tuner-test", type=int, default=2000, help="held-out signatures (timed exhaustively)")
     p.add_argument("--tuner-cfgs", type=int, default=50, help="configurations timed per training signature")
@@ -261,6 +263,31 @@ def bench_batch(args):
 
     t_default = timed(b.launch, max(5, args.steps))
     t_each = timed(b.launch_each, 3)
+    # the plain fused kernel, one launch per expression, on a sample of the workload (its
+    # kernels compiled ahead of time, outside the timing, like the batch's bytecode)
+    import ctypes
+    from paper_2508_11385_amd import _coot as cc
+    ns = min(args.batch_fused_sample, len(exprs))
+    t0 = time.perf_counter()
+    flats = coot.precompile(exprs[:ns])
+    t_pre = time.perf_counter() - t0
+    stream = torch.cuda.current_stream().cuda_stream
+    calls = []
+    for k, f in enumerate(flats):
+        ops = (cc.coot_operand * len(f.mats))(*[m.operand() for m in f.mats])
+        sc = (ctypes.c_double * max(1, len(f.scalars)))(*f.scalars)
+        calls.append((coot.frontend.compiled(f), ops, sc, b.outs[k].operand()))
+
+    def fused_each():
+        for h, ops, sc, out in calls:
+            st = cc.lib.coot_expr_eval(h, ops, sc, ctypes.byref(out), None, stream)
+            if st != cc.COOT_OK:
+                raise RuntimeError(cc.lib.coot_last_error().decode())
+
+    t_fused_each = timed(fused_each, 3)
+    bsub = coot.Batch([(e, None) for e in exprs[:ns]])
+    bsub.tune()
+    t_bsub = timed(bsub.launch, max(5, args.steps))
     t0 = time.perf_counter()
     cfg, tuned_us = b.tune()
     t_tune = time.perf_counter() - t0
@@ -277,6 +304,10 @@ def bench_batch(args):
         "ms_tuned": round(t_tuned * 1e3, 4), "ms_default": round(t_default * 1e3, 4),
         "ms_per_expression_launches": round(t_each * 1e3, 3),
         "speedup_vs_per_expression_launches": round(t_each / t_tuned, 1),
+        "fused_kernel_per_expression_sample": {
+            "expressions": ns, "ms_fused_kernel_launches": round(t_fused_each * 1e3, 3),
+            "ms_batch": round(t_bsub * 1e3, 4), "speedup": round(t_fused_each / t_bsub, 1),
+            "precompile_s": round(t_pre, 1)},
         "tuned_cfg": {"vec": cfg[0], "waves": cfg[2], "tile": info2["tile"], "grid_mult": cfg[3]},
         "default_cfg": {"tile": info["tile"], "grid": info["grid"]},
         "vec4_exprs": info2["vec4_exprs"], "pct_of_peak": round(100 * gbs / PEAK_HBM_GBS, 1),

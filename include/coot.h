@@ -121,6 +121,10 @@ typedef enum {
 #define COOT_CF_UNFUSED 0x1u   /* evaluate one kernel and one temporary per operator (comparator) */
 /* reduce flags */
 #define COOT_RF_PLAIN 0x1u     /* uncompensated fp32/fp64 accumulation (comparator) */
+/* prepare flag: compile into the in-memory and on-disk code-object caches only,
+ * without loading the code object (no device work: usable without a GPU, e.g. from
+ * helper processes that fill the on-disk cache) */
+#define COOT_PF_COMPILE_ONLY 0x100u
 
 typedef struct coot_expr coot_expr;
 typedef struct coot_batch coot_batch;
@@ -150,7 +154,7 @@ coot_status coot_expr_compile(const coot_op* ops, uint32_t n_ops, const coot_slo
  * exclude kernel compilation, Section 5).
  *   mode  -1 = element-wise eval, otherwise a coot_red value
  *   dim   for COOT_RED_SUM: 0 or 1, else ignored
- *   rflags COOT_RF_PLAIN or 0
+ *   rflags COOT_RF_PLAIN or 0, optionally | COOT_PF_COMPILE_ONLY
  *   cfg   launch configuration the call will use (NULL = library default)
  * Errors: COOT_EINVAL, COOT_ECOMPILE, COOT_EHIP. */
 coot_status coot_expr_prepare(coot_expr* e, int32_t mode, int32_t dim, uint32_t rflags,

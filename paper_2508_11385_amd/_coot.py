@@ -23,6 +23,7 @@ OPCODES = {"load": 0, "scalar": 1, "add": 2, "sub": 3, "schur": 4, "div": 5, "ne
 COOT_RED_ACCU, COOT_RED_SUM, COOT_RED_DOT, COOT_RED_NORM = 0, 1, 2, 3
 COOT_CF_UNFUSED = 0x1
 COOT_RF_PLAIN = 0x1
+COOT_PF_COMPILE_ONLY = 0x100
 DTYPE_CODE = {"u32": COOT_U32, "s32": COOT_S32, "f32": COOT_F32, "f64": COOT_F64}
 N_FEATURES = 21  # cost-model feature vector length
 STATUS_NAME = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ETYPE", -4: "EALIAS", -5: "ECOMPILE", -6: "EHIP",

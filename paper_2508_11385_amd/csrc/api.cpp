@@ -46,6 +46,7 @@ coot_status coot_expr_prepare(coot_expr* h, int32_t mode, int32_t dim, uint32_t 
     if (!h) fail(COOT_EINVAL, "NULL expression");
     Expr& e = *h->e;
     if (mode < -1 || mode > COOT_RED_NORM) fail(COOT_EINVAL, "bad mode");
+    if (rflags & ~(COOT_RF_PLAIN | COOT_PF_COMPILE_ONLY)) fail(COOT_EINVAL, "unknown prepare flag");
     int m = mode;
     if (mode == COOT_RED_ACCU && e.root_schur) m = COOT_RED_DOT;
     if (mode == COOT_RED_DOT && !e.root_schur) fail(COOT_EINVAL, "dot needs a % b at the root");
@@ -62,7 +63,7 @@ coot_status coot_expr_prepare(coot_expr* h, int32_t mode, int32_t dim, uint32_t 
     coot_operand o{};
     o.n_rows = o.n_cols = o.ld = 1;
     Request rq = plan(e, fake.data(), &o, m, mode == COOT_RED_SUM ? dim : -1, !(rflags & COOT_RF_PLAIN), cfg);
-    get_module(e, rq, true);
+    get_module(e, rq, !(rflags & COOT_PF_COMPILE_ONLY));
   });
 }
 

@@ -229,6 +229,38 @@ def compiled(flat: Flat, flags: int = 0) -> int:
     return h
 
 
+def _prepare_worker(job):
+    """Spawned process: compile one expression's element-wise module into the on-disk
+    code-object cache (no device use)."""
+    postfix, slots, n_sc = job
+    from paper_2508_11385_amd import _coot as c2
+    h = c2.coot_expr_compile(postfix, list(slots), n_sc)
+    c2.coot_expr_prepare(h, -1, rflags=c2.COOT_PF_COMPILE_ONLY)
+    c2.coot_expr_release(h)
+    return True
+
+
+def precompile(exprs, workers: int = 12) -> list:
+    """Compile the element-wise kernels of many expressions ahead of time; returns their
+    flattened forms.  hipRTC compilations do not overlap across threads of one process, so
+    they run in `workers` spawned processes (no device use in them) that fill the on-disk
+    code-object cache (COOT_CACHE_DIR chooses it); this process then loads every module
+    from there."""
+    import multiprocessing as mp
+    import os
+    flats = [flatten(_lift(e)) for e in exprs]
+    jobs = {}
+    for f in flats:
+        slots = tuple((cc.DTYPE_CODE[m.dtype], _KIND[m.kind]) for m in f.mats)
+        jobs[(tuple(f.postfix), slots, len(f.scalars))] = None
+    if workers > 1 and len(jobs) > 1 and not os.environ.get("COOT_NO_DISK_CACHE"):
+        with mp.get_context("spawn").Pool(min(workers, len(jobs))) as pool:
+            list(pool.imap_unordered(_prepare_worker, list(jobs), chunksize=4))
+    for f in flats:
+        cc.coot_expr_prepare(compiled(f), -1)
+    return flats
+
+
 def _stream() -> int:
     return torch.cuda.current_stream().cuda_stream
 

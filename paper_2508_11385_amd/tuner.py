@@ -67,7 +67,7 @@ def _compile_worker(job):
     return fam
 
 
-def prepare_all(sigs, workers: int = 16, log=None):
+def prepare_all(sigs, workers: int = 12, log=None):
     """Compile every signature's tuning module; returns (handles, families).
 
     hipRTC compilations do not overlap across threads of one process, so they run in

@@ -196,3 +196,17 @@ def test_runnable_configurations(cc):
     with pytest.raises(cc.CootError) as e:
         cc.coot_tune_runnable(hz, ops, None, -1, tiled)
     assert e.value.status == cc.COOT_EINVAL
+
+
+def test_compile_only_prepare_needs_no_device(cc, tmp_path, monkeypatch):
+    """COOT_PF_COMPILE_ONLY generates and compiles into the caches without loading a code
+    object, so it runs here without a GPU; the on-disk cache receives the module."""
+    import os
+    monkeypatch.setenv("COOT_CACHE_DIR", str(tmp_path))
+    h = cc.coot_expr_compile([("load", 0), ("scalar", 0), ("schur",), ("load", 1), ("add",)], _ops(2), 1)
+    cc.coot_expr_prepare(h, -1, rflags=cc.COOT_PF_COMPILE_ONLY)
+    assert any(f.endswith(".co") for f in os.listdir(tmp_path))
+    with pytest.raises(cc.CootError) as e:
+        cc.coot_expr_prepare(h, -1, rflags=0x8000)
+    assert e.value.status == cc.COOT_EINVAL
+    cc.coot_expr_release(h)
