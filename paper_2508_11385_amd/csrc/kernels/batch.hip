@@ -96,6 +96,7 @@ __device__ __forceinline__ void apply_un(u32 op, T (&acc)[4]) {
 }
 
 constexpr int kMaxStaged = 4;  // transposed leaves staged in LDS per tile (at most)
+constexpr int kXcds = 8;       // accelerator complex dies of an MI355X, each with its own L2
 
 // untransposed leaves loaded before the bytecode runs
 template <typename T> struct Prefetch { static constexpr int N = sizeof(T) == 4 ? 6 : 4; };
@@ -111,7 +112,13 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
   T* stage = reinterpret_cast<T*>(smem + (size_t)nstk * NT * sizeof(vt<T, 4>));  // [np1][TS][TS + 1]
   const int tid = threadIdx.x;
   exp_table_to_lds<T>();
-  for (int t = t_begin + (int)blockIdx.x; t < t_end; t += (int)gridDim.x) {
+  // Workgroup i runs on XCD i % 8.  Renumber workgroups so that consecutive logical
+  // numbers share an XCD: neighbouring tiles of an expression (whose column segments
+  // share cache lines when the leading dimension is not a multiple of the line) then
+  // meet in the same L2.
+  const int g = (int)gridDim.x, bid = (int)blockIdx.x;
+  const int lb = (g % kXcds == 0) ? (bid % kXcds) * (g / kXcds) + bid / kXcds : bid;
+  for (int t = t_begin + lb; t < t_end; t += g) {
     const u32 eid = tiles[2 * t], tin = tiles[2 * t + 1];
     const BatchExpr& e = ex[eid];
     const int R = e.n_rows, C = e.n_cols;
