@@ -39,6 +39,9 @@ def parse():
     p.add_argument("--workload", default="expr4096", choices=["expr4096", "batch", "tuner"],
                    help="expr4096: the fused 2-D expression step (default); batch: 10,000 small expressions")
     p.add_argument("--batch-n", type=int, default=10_000)
+    p.add_argument("--tune", default="none", choices=["exhaustive", "none"],
+                   help="launch configurations of Z and W: the library defaults, or the exhaustive autotuner's "
+                        "pick (timed alone, before the timed region; within the step the defaults measured faster)")
     p.add_argument("--batch-fused-sample", type=int, default=500,
                    help="expressions timed with the plain fused kernel, one launch each")
     p.add_argument("--tuner-train", type=int, default=1000, help="training signatures")
@@ -92,15 +95,24 @@ def main():
     zo, wo, s0o, s1o = Zout.operand(), Wout.operand(), s0.operand(), s1.operand()
     stream = torch.cuda.current_stream().cuda_stream
 
-    def step(hz, hw):
-        cc.coot_expr_eval(hz, zops, zf.scalars, zo, None, stream)
-        cc.coot_expr_eval(hw, wops, wf.scalars, wo, None, stream)
-        cc.coot_reduce(hz, zops, zf.scalars, cc.COOT_RED_SUM, 0, 0, s0o, None, stream)
-        cc.coot_reduce(hz, zops, zf.scalars, cc.COOT_RED_SUM, 1, 0, s1o, None, stream)
-
     bytes_step = 16 * MIB64 + 2 * N * 4
     fused = handles(0)
     unfused = handles(cc.COOT_CF_UNFUSED)
+
+    # launch configurations of the element-wise kernels: the project's autotuner (exhaustive
+    # over the family's space, cold-cache timings), run once before any timed region
+    cfgs = {"Z": None, "W": None}
+    t0 = time.perf_counter()
+    if args.tune == "exhaustive":
+        cfgs["Z"] = cc.coot_tune(fused[0], zops, zf.scalars, zo, -1, 1, stream=stream)[0]
+        cfgs["W"] = cc.coot_tune(fused[1], wops, wf.scalars, wo, -1, 1, stream=stream)[0]
+    t_tune = time.perf_counter() - t0
+
+    def step(hz, hw, zc=None, wc=None):
+        cc.coot_expr_eval(hz, zops, zf.scalars, zo, zc, stream)
+        cc.coot_expr_eval(hw, wops, wf.scalars, wo, wc, stream)
+        cc.coot_reduce(hz, zops, zf.scalars, cc.COOT_RED_SUM, 0, 0, s0o, None, stream)
+        cc.coot_reduce(hz, zops, zf.scalars, cc.COOT_RED_SUM, 1, 0, s1o, None, stream)
 
     # copy probe: out = A through the flat family, 64 MiB read + 64 MiB written
     copy_flat = coot.flatten(gA + 0.0)
@@ -117,10 +129,10 @@ def main():
         for _ in range(3):
             copy()
         for _ in range(3):
-            step(*fused)
+            step(*fused, cfgs["Z"], cfgs["W"])
         torch.cuda.synchronize()
-        names = {"copy": cc.coot_expr_kernel_name(hcopy), "Z": cc.coot_expr_kernel_name(fused[0]),
-                 "W": cc.coot_expr_kernel_name(fused[1]),
+        names = {"copy": cc.coot_expr_kernel_name(hcopy), "Z": cc.coot_expr_kernel_name(fused[0], cfg=cfgs["Z"]),
+                 "W": cc.coot_expr_kernel_name(fused[1], cfg=cfgs["W"]),
                  "sumZ0": cc.coot_expr_kernel_name(fused[0], cc.COOT_RED_SUM, 0),
                  "sumZ1": cc.coot_expr_kernel_name(fused[0], cc.COOT_RED_SUM, 1)}
         print(json.dumps({"profiled_kernels": names, "copy_bytes": 2 * MIB64, "Z_bytes": 5 * MIB64,
@@ -141,9 +153,9 @@ def main():
     copy_ms = sorted(a.elapsed_time(b) for a, b in cev)[len(cev) // 2]
     copy_gbs = 2 * MIB64 / (copy_ms * 1e-3) / 1e9
 
-    def run(h, steps, warmup, z_events=None):
+    def run(h, steps, warmup, zc=None, wc=None, z_events=None):
         for _ in range(warmup):
-            step(*h)
+            step(*h, zc, wc)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -151,25 +163,39 @@ def main():
                 ev0 = torch.cuda.Event(enable_timing=True)
                 ev1 = torch.cuda.Event(enable_timing=True)
                 ev0.record()
-                cc.coot_expr_eval(h[0], zops, zf.scalars, zo, None, stream)
+                cc.coot_expr_eval(h[0], zops, zf.scalars, zo, zc, stream)
                 ev1.record()
                 z_events.append((ev0, ev1))
-                cc.coot_expr_eval(h[1], wops, wf.scalars, wo, None, stream)
+                cc.coot_expr_eval(h[1], wops, wf.scalars, wo, wc, stream)
                 cc.coot_reduce(h[0], zops, zf.scalars, cc.COOT_RED_SUM, 0, 0, s0o, None, stream)
                 cc.coot_reduce(h[0], zops, zf.scalars, cc.COOT_RED_SUM, 1, 0, s1o, None, stream)
             else:
-                step(*h)
+                step(*h, zc, wc)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
+    # the tuned and the default configurations are timed in alternating blocks of steps, so
+    # that clock and temperature drift over the run affects both alike
     z_events = []
-    t_fused = run(fused, args.steps, args.warmup, z_events)
+    for _ in range(args.warmup):
+        step(*fused, cfgs["Z"], cfgs["W"])
+        step(*fused)
+    blocks = 4 if args.steps >= 4 else 1
+    per = [args.steps // blocks + (1 if k < args.steps % blocks else 0) for k in range(blocks)]
+    t_fused = t_default = 0.0
+    for n in per:
+        t_fused += run(fused, n, 0, cfgs["Z"], cfgs["W"], z_events) * n
+        if args.tune != "none":
+            t_default += run(fused, n, 0) * n
+    t_fused /= args.steps
+    t_default = t_default / args.steps if args.tune != "none" else t_fused
     z_ms = sum(a.elapsed_time(b) for a, b in z_events) / len(z_events)
     t_unfused = run(unfused, max(3, args.steps // 4), 2)
 
     value = bytes_step / t_fused / 1e9
     z_gbs = 5 * MIB64 / (z_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.traffic_json, cc.coot_expr_kernel_name(fused[0]))
+    zname = cc.coot_expr_kernel_name(fused[0], cfg=cfgs["Z"])
+    traffic = measured_traffic(args.traffic_json, zname)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -194,9 +220,13 @@ def main():
         "pct_of_peak": round(100 * value / PEAK_HBM_GBS, 1),
         "copy_probe_gbs": round(copy_gbs, 1),
         "pct_of_copy_probe": round(100 * value / copy_gbs, 1),
+        "launch_cfgs": {"Z": cfgs["Z"], "W": cfgs["W"], "sums": "library default",
+                        "chosen_by": "exhaustive autotuner before timing" if args.tune == "exhaustive"
+                        else "library defaults", "tuning_s": round(t_tune, 2)},
+        "default_cfg_ms_per_step": round(t_default * 1e3, 4),
         "unfused_ms_per_step": round(t_unfused * 1e3, 4),
         "speedup_vs_unfused": round(t_unfused / t_fused, 2),
-        "roofline": {"bound": "hbm", "kernel": cc.coot_expr_kernel_name(fused[0]),
+        "roofline": {"bound": "hbm", "kernel": zname,
                      "achieved": round(z_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(z_gbs / PEAK_HBM_GBS, 3), "traffic": traffic,
                      "avg_kernel_us": round(z_ms * 1e3, 2), "algorithmic_bytes": 5 * MIB64},

@@ -197,10 +197,12 @@ coot_status coot_reduce(coot_expr* e, const coot_operand* operands, const double
 /* Release a handle from coot_expr_compile.  NULL is ignored. */
 void coot_expr_release(coot_expr* e);
 
-/* Name of the kernel (family + signature hash) a call with these arguments
- * would launch first, for attributing profiler traces.  Writes at most `cap`
- * bytes including the terminator.  Errors: COOT_EINVAL. */
-coot_status coot_expr_kernel_name(coot_expr* e, int32_t mode, int32_t dim, char* buf, size_t cap);
+/* Name of the kernel (family + signature hash + variant) a call with these
+ * arguments and launch configuration (NULL = library default) would launch
+ * first, for attributing profiler traces.  Writes at most `cap` bytes including
+ * the terminator.  Errors: COOT_EINVAL. */
+coot_status coot_expr_kernel_name(coot_expr* e, int32_t mode, int32_t dim, const coot_launch_cfg* cfg, char* buf,
+                                  size_t cap);
 
 /* ---- batches: many small independent expressions in one launch ----------
  * Section 4 of the paper notes that GPUs need enough parallel work and are
@@ -357,8 +359,10 @@ void coot_costmodel_release(coot_costmodel* cm);
 
 /* Pick a configuration for these operands: policy 0 the library default,
  * 1 exhaustive (every configuration timed, the fastest kept), 2 the cost model's
- * argmin (cm required).  best_us (may be NULL) is the chosen configuration's
- * measured median time (5 launches, caches flushed).  Synchronises the stream. */
+ * argmin over the configurations these operands allow (cm required).  Timing is
+ * that of coot_tune_table with 5 rounds and no flush (the per-launch time of
+ * repeated calls); best_us (may be NULL) is the chosen configuration's median.
+ * Synchronises the stream. */
 coot_status coot_tune(coot_expr* e, const coot_operand* operands, const double* scalars, coot_operand* out,
                       int32_t mode, int32_t policy, coot_costmodel* cm, coot_launch_cfg* best, float* best_us,
                       void* stream);

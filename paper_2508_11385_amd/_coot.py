@@ -73,7 +73,8 @@ _sig = {
     "coot_reduce": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(C.c_double), C.c_int32, C.c_int32,
                               C.c_uint32, C.POINTER(coot_operand), C.POINTER(coot_launch_cfg), _P]),
     "coot_expr_release": (None, [_P]),
-    "coot_expr_kernel_name": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_char_p, C.c_size_t]),
+    "coot_expr_kernel_name": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(coot_launch_cfg), C.c_char_p,
+                                        C.c_size_t]),
     "coot_stats": (None, [C.POINTER(C.c_double)]),
     "coot_last_error": (C.c_char_p, []),
     "coot_debug_codegen": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_uint32, C.c_int32, C.c_int32, C.c_int32,
@@ -191,9 +192,9 @@ def coot_expr_release(h: int) -> None:
     lib.coot_expr_release(h)
 
 
-def coot_expr_kernel_name(h: int, mode: int = -1, dim: int = -1) -> str:
+def coot_expr_kernel_name(h: int, mode: int = -1, dim: int = -1, cfg=None) -> str:
     buf = C.create_string_buffer(256)
-    _check(lib.coot_expr_kernel_name(h, mode, dim, buf, 256))
+    _check(lib.coot_expr_kernel_name(h, mode, dim, _cfg(cfg), buf, 256))
     return buf.value.decode()
 
 

@@ -128,7 +128,8 @@ coot_status coot_reduce(coot_expr* h, const coot_operand* operands, const double
 
 void coot_expr_release(coot_expr* h) { delete h; }
 
-coot_status coot_expr_kernel_name(coot_expr* h, int32_t mode, int32_t dim, char* buf, size_t cap) {
+coot_status coot_expr_kernel_name(coot_expr* h, int32_t mode, int32_t dim, const coot_launch_cfg* cfg, char* buf,
+                                  size_t cap) {
   return guarded([&] {
     if (!h || !buf || cap == 0) fail(COOT_EINVAL, "NULL argument");
     Expr& e = *h->e;
@@ -142,7 +143,7 @@ coot_status coot_expr_kernel_name(coot_expr* h, int32_t mode, int32_t dim, char*
     o.n_rows = o.n_cols = o.ld = 1;
     int m = mode;
     if (mode == COOT_RED_ACCU && e.root_schur) m = COOT_RED_DOT;
-    Request rq = plan(e, fake.data(), &o, m, mode == COOT_RED_SUM ? dim : -1, true, nullptr);
+    Request rq = plan(e, fake.data(), &o, m, mode == COOT_RED_SUM ? dim : -1, true, cfg);
     KernelNames names;
     generate(e, rq, hex128(e.canon), &names);
     std::strncpy(buf, names.stage1.c_str(), cap - 1);

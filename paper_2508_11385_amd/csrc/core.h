@@ -142,6 +142,9 @@ void eval_unfused(Expr& e, const coot_operand* ops, const double* scalars, const
                   const coot_launch_cfg* cfg, hipStream_t s);
 void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int kind, int dim, uint32_t flags,
                   const coot_operand& out, const coot_launch_cfg* cfg, hipStream_t s);
+// The library's launch configuration for a family when the caller gives none
+// (fields 0 there are filled from it); waves and ept are 0/unused where fixed.
+coot_launch_cfg default_cfg(int fam, int mode, int dim, int dtype);
 Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, int mode, int dim, bool comp,
              const coot_launch_cfg* cfg);
 

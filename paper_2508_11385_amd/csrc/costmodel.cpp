@@ -510,8 +510,9 @@ coot_status coot_tune(coot_expr* h, const coot_operand* operands, const double* 
     coot_tune_space(fam, space.data(), (uint32_t)space.size());
     std::vector<coot_launch_cfg> cand;
     if (policy == 0) {
-      cand.push_back({(uint16_t)(h->e->dtype == COOT_F64 ? 2 : 4), (uint16_t)(fam == 0 ? 4 : 1), 4,
-                      (uint16_t)(fam == 0 ? 8 : 16)});
+      coot_launch_cfg d = default_cfg(fam == 0 ? FAM_FLAT : FAM_TILE, mode, -1, h->e->dtype);
+      if (!d.ept) d.ept = 1;  // the tiled family's configurations carry ept 1
+      cand.push_back(d);
     } else if (policy == 1) {
       cand = space;
     } else if (policy == 2) {
@@ -534,7 +535,7 @@ coot_status coot_tune(coot_expr* h, const coot_operand* operands, const double* 
       fail(COOT_EINVAL, "policy must be 0, 1 or 2");
     }
     std::vector<float> t(cand.size());
-    st = coot_tune_table(h, operands, scalars, out, mode, cand.data(), (uint32_t)cand.size(), 5, 1, t.data(), stream);
+    st = coot_tune_table(h, operands, scalars, out, mode, cand.data(), (uint32_t)cand.size(), 5, 0, t.data(), stream);
     if (st != COOT_OK) fail(st, last_error());
     size_t bi = 0;
     for (size_t i = 0; i < t.size(); ++i)

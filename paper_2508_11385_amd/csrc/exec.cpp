@@ -105,7 +105,29 @@ static bool contiguous(const coot_operand& o) { return ld_of(o) == o.n_rows || o
 
 static bool aligned(const void* p, size_t bytes) { return ((uintptr_t)p % bytes) == 0; }
 
-static int default_vec(int dt) { return dt == COOT_F64 ? 2 : 4; }
+// Library defaults (any field a caller leaves 0), chosen from the autotuner's
+// exhaustive tables over 3,000 random signatures on MI355X as the single
+// configuration with the lowest geometric-mean time ratio to each signature's best:
+//   flat family:   16-byte groups, 1 group per thread per trip, 4 waves, 4 workgroups per CU
+//   tiled family:  2-element groups, 4 waves (fixed), 8 workgroups per CU
+//   dimension sums: 16-byte groups (one workgroup per segment)
+coot_launch_cfg default_cfg(int fam, int mode, int dim, int dtype) {
+  const uint16_t v16 = dtype == COOT_F64 ? 2 : 4;
+  if (mode == COOT_RED_SUM && dim >= 0) return {v16, 0, 4, 8};
+  if (fam == FAM_FLAT) return {v16, 1, 4, 4};
+  return {2, 0, 4, 8};
+}
+
+coot_launch_cfg resolve_cfg(const coot_launch_cfg* cfg, int fam, int mode, int dim, int dtype) {
+  coot_launch_cfg c = default_cfg(fam, mode, dim, dtype);
+  if (cfg) {
+    if (cfg->vec) c.vec = cfg->vec;
+    if (cfg->ept) c.ept = cfg->ept;
+    if (cfg->waves) c.waves = cfg->waves;
+    if (cfg->grid_mult) c.grid_mult = cfg->grid_mult;
+  }
+  return c;
+}
 
 Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, int mode, int dim, bool comp,
              const coot_launch_cfg* cfg) {
@@ -118,8 +140,9 @@ Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, in
     if (!contiguous(ops[l.slot])) flat = false;
   if (mode < 0 && out && !contiguous(*out)) flat = false;
   rq.fam = flat ? FAM_FLAT : FAM_TILE;
-  rq.var.vec = cfg && cfg->vec ? cfg->vec : default_vec(e.dtype);
-  rq.var.ept = cfg && cfg->ept ? cfg->ept : 4;
+  const coot_launch_cfg c = resolve_cfg(cfg, rq.fam, mode, dim, e.dtype);
+  rq.var.vec = c.vec;
+  rq.var.ept = c.ept ? c.ept : 1;
   if (rq.var.vec != 1 && rq.var.vec != 2 && rq.var.vec != 4) fail(COOT_EINVAL, "vec must be 1, 2 or 4");
   if (rq.var.ept != 1 && rq.var.ept != 2 && rq.var.ept != 4 && rq.var.ept != 8) fail(COOT_EINVAL, "ept must be 1, 2, 4 or 8");
   // tile edge: 64, or 32 when the LDS staging of transposed leaves would exceed 64 KiB
@@ -221,14 +244,12 @@ void eval_fused(Expr& e, const coot_operand* ops, const double* scalars, const c
   const bool v = vec_ok(e, rq, ops, &out, R, C);
   const std::string& kn = (v || rq.var.vec == 1) ? m->names.stage1 : m->names.stage1_fallback;
   hipFunction_t f = m->fn(kn);
-  const int waves = cfg && cfg->waves ? cfg->waves : 4;
+  const coot_launch_cfg c = resolve_cfg(cfg, rq.fam, -1, -1, e.dtype);
   if (rq.fam == FAM_FLAT) {
-    const int bs = 64 * waves;
-    const int gm = cfg && cfg->grid_mult ? cfg->grid_mult : 8;
-    launch(f, flat_grid(R * C, v ? rq.var.vec : 1, rq.var.ept, bs, gm), bs, a, s);
+    const int bs = 64 * c.waves;
+    launch(f, flat_grid(R * C, v ? rq.var.vec : 1, rq.var.ept, bs, c.grid_mult), bs, a, s);
   } else {
-    const int gm = cfg && cfg->grid_mult ? cfg->grid_mult : 16;
-    launch(f, tile_grid(R, C, rq.var.ts, gm), 256, a, s);
+    launch(f, tile_grid(R, C, rq.var.ts, c.grid_mult), 256, a, s);
   }
 }
 
@@ -267,7 +288,7 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
   const bool v = vec_ok(e, rq, ops, nullptr, R, C);
   const std::string& kn = (v || rq.var.vec == 1) ? m->names.stage1 : m->names.stage1_fallback;
   const size_t es = dtype_size(e.dtype);
-  const int waves = cfg && cfg->waves ? cfg->waves : 4;
+  const coot_launch_cfg c = resolve_cfg(cfg, rq.fam, mode, kind == COOT_RED_SUM ? dim : -1, e.dtype);
   if (kind == COOT_RED_SUM) {
     const int ts = rq.var.ts;
     const int64_t tr = (R + ts - 1) / ts, tc = (C + ts - 1) / ts;
@@ -286,13 +307,11 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
   unsigned grid;
   unsigned block;
   if (rq.fam == FAM_FLAT) {
-    block = 64 * waves;
-    const int gm = cfg && cfg->grid_mult ? cfg->grid_mult : 8;
-    grid = flat_grid(R * C, v ? rq.var.vec : 1, rq.var.ept, block, gm);
+    block = 64 * c.waves;
+    grid = flat_grid(R * C, v ? rq.var.vec : 1, rq.var.ept, block, c.grid_mult);
   } else {
     block = 256;
-    const int gm = cfg && cfg->grid_mult ? cfg->grid_mult : 8;
-    grid = tile_grid(R, C, rq.var.ts, gm);
+    grid = tile_grid(R, C, rq.var.ts, c.grid_mult);
   }
   a.n_part = grid;
   a.ws = workspace((size_t)grid * 32, s, 0);

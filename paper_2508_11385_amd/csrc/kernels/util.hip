@@ -1,10 +1,20 @@
-// Utility kernels: cache flush for timing (writes a buffer larger than L2 + MALL).
+// Utility kernels: cache flush for timing.  It streams through a buffer larger than
+// L2 + the Infinity Cache, reading it (a written buffer would leave dirty lines whose
+// write-back the next, timed kernel would pay for); each thread folds what it read
+// into one word of a small per-thread slot area at the buffer's start, so the reads
+// cannot be dropped and almost nothing is left dirty.
 #include <hip/hip_runtime.h>
 
 namespace {
 __global__ __launch_bounds__(256) void flush_kernel(uint4* buf, size_t n, unsigned v) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    buf[i] = make_uint4(v, v + 1u, v + 2u, v + 3u);
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t nt = (size_t)gridDim.x * blockDim.x;
+  unsigned x = v;
+  for (size_t i = nt + tid; i < n; i += nt) {
+    const uint4 q = buf[i];
+    x ^= q.x ^ q.y ^ q.z ^ q.w;
+  }
+  reinterpret_cast<unsigned*>(buf)[tid] = x;
 }
 }  // namespace
 

@@ -131,7 +131,7 @@ def _valid(t):
 def default_index(cfgs, dtype, t=None):
     """What coot_expr_eval launches without a tuner: the default configuration, or, when
     the operands do not allow its vector width (t[k] NaN), the same with scalar accesses."""
-    want = (2 if dtype == "f64" else 4, 4, 4, 8) if len(cfgs) > 12 else (2 if dtype == "f64" else 4, 1, 4, 16)
+    want = (2 if dtype == "f64" else 4, 1, 4, 4) if len(cfgs) > 12 else (2, 1, 4, 8)
     k = cfgs.index(want)
     if t is not None and not np.isfinite(t[k]):
         k = cfgs.index((1,) + want[1:])
