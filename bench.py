@@ -36,7 +36,7 @@ def parse():
     p.add_argument("--cpu-cols", type=int, default=4096, help="columns of the problem the CPU oracle is timed on")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_tile_Z_4096_f32.json"))
-    p.add_argument("--workload", default="expr4096", choices=["expr4096", "batch", "tuner"],
+    p.add_argument("--workload", default="expr4096", choices=["expr4096", "batch", "tuner", "suite"],
                    help="expr4096: the fused 2-D expression step (default); batch: 10,000 small expressions")
     p.add_argument("--batch-n", type=int, default=10_000)
     p.add_argument("--tune", default="none", choices=["exhaustive", "none"],
@@ -75,6 +75,8 @@ def main():
         return bench_batch(args)
     if args.workload == "tuner":
         return bench_tuner(args)
+    if args.workload == "suite":
+        return bench_suite(args)
     dev = torch.device("cuda:0")
     A, B, C, D = synth.matrix_inputs(N, "f32")
     gA, gB, gC, gD = (coot.Mat.from_numpy(m) for m in (A, B, C, D))
@@ -343,6 +345,93 @@ def bench_batch(args):
         "vec4_exprs": info2["vec4_exprs"], "pct_of_peak": round(100 * gbs / PEAK_HBM_GBS, 1),
         "tuning_s": round(t_tune, 2), "create_s": round(t_create, 2), "generate_s": round(t_gen, 1),
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_suite(args):
+    """The other workloads of the method at their full sizes, GPU time by HIP events (inputs
+    resident in HBM): axpy + dot on 1e6 fp32, the 4096 x 4096 step in fp64, the u32 / s32
+    8192 x 8192 expressions, and accu / norm / plain accu over 2^28 lognormal fp32 values."""
+    import numpy as np
+    import torch
+    import paper_2508_11385_amd as coot
+    import synth
+
+    def gpu_us(fn, reps=10):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    res = {}
+    # axpy y = 2.5 x + y in place, then accu(x % y) (the dot pattern) on 1e6 fp32
+    x, y = synth.axpy_inputs()
+    gx, gy = coot.Mat.from_numpy(x, kind="col"), coot.Mat.from_numpy(y, kind="col")
+    n = x.shape[0]
+
+    def axpy_dot():
+        coot.eval(2.5 * gx + gy, out=gy)
+        return coot.accu(gx % gy)
+    us = gpu_us(axpy_dot, 50)
+    res["axpy_then_dot_1e6_f32"] = {"us": round(us, 2), "GBps": round(20 * n / us / 1e3, 1),
+                                    "note": "two launches + one stage-2; latency-bound at this size"}
+    del gx, gy
+    log(f"axpy+dot: {res['axpy_then_dot_1e6_f32']}")
+    # the 2-D step in fp64
+    A, B, C, D = synth.matrix_inputs(N, "f64")
+    gA, gB, gC, gD = (coot.Mat.from_numpy(m) for m in (A, B, C, D))
+    del A, B, C, D
+    Z = 2.0 * gA + gB % gC - coot.trans(gD)
+    W = coot.exp(gA) / (1.0 + coot.abs(gB))
+    oz, ow = coot.Mat.empty(N, N, "f64"), coot.Mat.empty(N, N, "f64")
+
+    def step64():
+        coot.eval(Z, out=oz)
+        coot.eval(W, out=ow)
+        coot.sum(Z, 0)
+        coot.sum(Z, 1)
+    us = gpu_us(step64)
+    res["step_4096_f64"] = {"us": round(us, 1), "GBps": round(2 * (16 * MIB64 + 2 * N * 4) / us / 1e3, 1)}
+    del gA, gB, gC, gD, Z, W, oz, ow
+    torch.cuda.empty_cache()
+    log(f"fp64 step: {res['step_4096_f64']}")
+    # integers on 8192 x 8192
+    M = 8192
+    Ai, Bi, Ci = synth.int_inputs(M, "u32")
+    gA, gB, gC = (coot.Mat.from_numpy(m) for m in (Ai, Bi, Ci))
+    o = coot.Mat.empty(M, M, "u32")
+    us = gpu_us(lambda: coot.eval((gA + gB) % gC, out=o))
+    res["u32_(A+B)%C_8192"] = {"us": round(us, 1), "GBps": round(4 * 4 * M * M / us / 1e3, 1)}
+    del gA, gB, gC, o
+    As, Bs = synth.int_inputs(M, "s32_full")
+    gA, gB = coot.Mat.from_numpy(As), coot.Mat.from_numpy(Bs)
+    o = coot.Mat.empty(M, M, "s32")
+    us = gpu_us(lambda: coot.eval(gA - 3 * gB, out=o))
+    res["s32_A-3B_8192"] = {"us": round(us, 1), "GBps": round(3 * 4 * M * M / us / 1e3, 1)}
+    del gA, gB, o
+    torch.cuda.empty_cache()
+    log("integers done")
+    # reductions over 2^28 lognormal(0, 4) fp32 values with random signs
+    h = synth.hard_reduction_inputs()
+    gh = coot.Mat.from_numpy(h, kind="col")
+    del h
+    for name, fn in (("accu", lambda: coot.accu(gh)), ("norm", lambda: coot.norm(gh)),
+                     ("accu_plain", lambda: coot.accu(gh, plain=True))):
+        us = gpu_us(fn)
+        res[f"{name}_2^28_f32"] = {"us": round(us, 1), "GBps": round(4 * (1 << 28) / us / 1e3, 1)}
+    out = {"metric": "throughput of the other workloads (GB/s of algorithmic bytes)", "value": None,
+           "unit": "GB/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic, seeded, resident in HBM",
+           "config": {"workload": "axpy+dot 1e6 f32; 4096^2 step f64; u32/s32 8192^2; accu/norm 2^28 f32"},
+           "results": res}
     print(json.dumps(out), flush=True)
 
 
