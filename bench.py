@@ -561,7 +561,8 @@ def cpu_baseline(A, B, C, D, ncols):
     del Z
     return {"value": round(nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"the same four expressions on columns 0..{ncols - 1} of the 4096x4096 operands "
-                      f"({ncols / N:.3f} of one step), {dt:.1f} s, numpy single-threaded"}
+                      f"({ncols / N:.3f} of one step), {dt:.1f} s, numpy single-threaded "
+                      f"(1 of {os.cpu_count()} host cores)"}
 
 
 if __name__ == "__main__":
