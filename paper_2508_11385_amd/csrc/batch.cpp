@@ -18,7 +18,7 @@
 
 extern "C" hipError_t coot_batch_launch_kernel(int dtype, int ts, unsigned grid, const void* ex, const void* tiles,
                                               int t_begin, int t_end, const void* code, const void* scal, int nstk,
-                                              int np1, hipStream_t s);
+                                              int np1, int flat_only, hipStream_t s);
 
 using namespace coot;
 using coot::batch::BatchExpr;
@@ -174,6 +174,7 @@ struct coot_batch {
   std::vector<uint32_t> code;
   std::vector<uint64_t> scal_bits;
   std::vector<std::pair<int, int>> ranges;  // per expression: tile range
+  int n_flat_tiles = 0;                      // tiles [0, n_flat_tiles) are flat chunks
   std::vector<uint32_t> tiles;
   std::vector<int> vec4_ok, flat_ok;
   DevBuf<BatchExpr> d_ex;
@@ -198,10 +199,17 @@ struct coot_batch {
 
 namespace {
 
+// The work-list holds the flat-chunk tiles first (one launch of the flat-only
+// interpreter), then the 2-D tiles (the general interpreter).
 void build_tiles(coot_batch* b) {
   b->tiles.clear();
-  b->ranges.clear();
-  for (size_t k = 0; k < b->ex.size(); ++k) {
+  b->ranges.assign(b->ex.size(), {0, 0});
+  std::vector<size_t> order;
+  for (int pass = 0; pass < 2; ++pass)
+    for (size_t k = 0; k < b->ex.size(); ++k)
+      if ((b->flat_ok[k] != 0) == (pass == 0)) order.push_back(k);
+  b->n_flat_tiles = 0;
+  for (size_t k : order) {
     BatchExpr& e = b->ex[k];
     e.flat = b->flat_ok[k];
     e.tiles_r = (e.n_rows + b->ts - 1) / b->ts;
@@ -214,7 +222,8 @@ void build_tiles(coot_batch* b) {
       b->tiles.push_back((uint32_t)k);
       b->tiles.push_back((uint32_t)t);
     }
-    b->ranges.push_back({begin, (int)(b->tiles.size() / 2)});
+    b->ranges[k] = {begin, (int)(b->tiles.size() / 2)};
+    if (e.flat) b->n_flat_tiles = (int)(b->tiles.size() / 2);
   }
   b->d_ex.upload(b->ex);
   b->d_tiles.upload(b->tiles);
@@ -239,10 +248,17 @@ int staged_tiles(const coot_batch* b) {
 
 void launch_all(coot_batch* b, hipStream_t s) {
   const int n_tiles = (int)(b->tiles.size() / 2);
-  if (n_tiles == 0) return;
-  hip_check(coot_batch_launch_kernel(b->dtype, b->ts, b->grid, b->d_ex.p, b->d_tiles.p, 0, n_tiles, b->d_code.p,
-                                     b->d_scal32x2.p, b->nstk, staged_tiles(b), s),
-            "batch kernel launch");
+  const int nf = b->n_flat_tiles;
+  // each part gets the configured grid, or fewer workgroups when it has fewer tiles
+  if (nf > 0)
+    hip_check(coot_batch_launch_kernel(b->dtype, b->ts, std::min<unsigned>(b->grid, (unsigned)nf), b->d_ex.p,
+                                       b->d_tiles.p, 0, nf, b->d_code.p, b->d_scal32x2.p, b->nstk, 0, 1, s),
+              "batch kernel launch");
+  if (n_tiles > nf)
+    hip_check(coot_batch_launch_kernel(b->dtype, b->ts, std::min<unsigned>(b->grid, (unsigned)(n_tiles - nf)),
+                                       b->d_ex.p, b->d_tiles.p, nf, n_tiles, b->d_code.p, b->d_scal32x2.p, b->nstk,
+                                       staged_tiles(b), 0, s),
+              "batch kernel launch");
 }
 
 void capture(coot_batch* b) {
@@ -388,8 +404,10 @@ coot_status coot_batch_launch_each(coot_batch* b, void* stream) {
     for (auto& r : b->ranges) {
       if (r.second == r.first) continue;
       const unsigned g = (unsigned)std::min(r.second - r.first, (int)b->grid);
+      const int fl = r.second <= b->n_flat_tiles ? 1 : 0;
       hip_check(coot_batch_launch_kernel(b->dtype, b->ts, g, b->d_ex.p, b->d_tiles.p, r.first, r.second,
-                                         b->d_code.p, b->d_scal32x2.p, b->nstk, staged_tiles(b), (hipStream_t)stream),
+                                         b->d_code.p, b->d_scal32x2.p, b->nstk, fl ? 0 : staged_tiles(b), fl,
+                                         (hipStream_t)stream),
                 "batch kernel launch");
     }
   });

@@ -98,15 +98,20 @@ __device__ __forceinline__ void apply_un(u32 op, T (&acc)[4]) {
 constexpr int kMaxStaged = 4;  // transposed leaves staged in LDS per tile (at most)
 constexpr int kXcds = 8;       // accelerator complex dies of an MI355X, each with its own L2
 
-// untransposed leaves loaded before the bytecode runs
-template <typename T> struct Prefetch { static constexpr int N = sizeof(T) == 4 ? 6 : 4; };
+// untransposed leaves loaded before the bytecode runs (2-D tiles also hold their
+// staged transposed leaves in registers, so they prefetch fewer)
+template <typename T, bool FLAT> struct Prefetch {
+  static constexpr int N = FLAT ? (sizeof(T) == 4 ? 6 : 4) : (sizeof(T) == 4 ? 3 : 2);
+};
 
-template <typename T, int TS>
+// FLAT: the tile range holds flat chunks only (no staging, no 2-D index maps: fewer
+// registers, more waves per SIMD); otherwise 2-D tiles only.
+template <typename T, int TS, bool FLAT>
 __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restrict__ ex, const u32* __restrict__ tiles,
                                                       int t_begin, int t_end, const u32* __restrict__ code,
                                                       const T* __restrict__ scal, int nstk, int np1) {
   constexpr int NT = TS * TS / 4;  // threads: 4 elements each
-  constexpr int PF = Prefetch<T>::N;
+  constexpr int PF = Prefetch<T, FLAT>::N;
   extern __shared__ __align__(16) unsigned char smem[];
   vt<T, 4>* stk = reinterpret_cast<vt<T, 4>*>(smem);                              // [nstk][NT]
   T* stage = reinterpret_cast<T*>(smem + (size_t)nstk * NT * sizeof(vt<T, 4>));  // [np1][TS][TS + 1]
@@ -122,7 +127,7 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
     const u32 eid = tiles[2 * t], tin = tiles[2 * t + 1];
     const BatchExpr& e = ex[eid];
     const int R = e.n_rows, C = e.n_cols;
-    const bool flat = e.flat != 0;
+    constexpr bool flat = FLAT;
     const bool v4 = e.vec4 != 0;
     const u32 p1 = e.p1_mask;
     int iq[4], jq[4];
@@ -130,7 +135,7 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
     vt<T, 4> sv[kMaxStaged];
     i64 fbase = 0;
     int i0 = 0, j0 = 0;
-    if (flat) {
+    if constexpr (FLAT) {
       const i64 n = (i64)R * C;
       fbase = (i64)tin * (4 * NT) + 4 * tid;
 #pragma unroll
@@ -219,7 +224,7 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
     // value of leaf k for this thread's 4 elements
     auto fetch_leaf = [&](u32 k) __attribute__((always_inline)) {
       vt<T, 4> g;
-      if (!flat && ((p1 >> k) & 1u)) {
+      if (!FLAT && ((p1 >> k) & 1u)) {
         // transposed leaf: staged in LDS (slot = staged leaves before it) or read directly
         const int slot = __builtin_popcount(p1 & ((1u << k) - 1u));
         if (slot < np1) {
@@ -241,7 +246,7 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
       }
       return g;
     };
-    if (!flat && p1 && np1 > 0) {
+    if (!FLAT && p1 && np1 > 0) {
       __syncthreads();  // the previous tile's reads of the staging area are done
       u32 rest = p1;
 #pragma unroll
@@ -339,7 +344,7 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
 // host-side launcher (called from batch.cpp)
 extern "C" hipError_t coot_batch_launch_kernel(int dtype, int ts, unsigned grid, const void* ex, const void* tiles,
                                               int t_begin, int t_end, const void* code, const void* scal, int nstk,
-                                              int np1, hipStream_t s) {
+                                              int np1, int flat_only, hipStream_t s) {
   using namespace coot::batch;
   const BatchExpr* e = (const BatchExpr*)ex;
   const u32* tl = (const u32*)tiles;
@@ -351,10 +356,16 @@ extern "C" hipError_t coot_batch_launch_kernel(int dtype, int ts, unsigned grid,
     const float* sc = (const float*)scal;
     switch (ts) {
       case 16:
-        hipLaunchKernelGGL((interp<float, 16>), dim3(grid), dim3(64), shmem, s, e, tl, t_begin, t_end, cd, sc, nstk, np1);
+        if (flat_only)
+          hipLaunchKernelGGL((interp<float, 16, true>), dim3(grid), dim3(64), shmem, s, e, tl, t_begin, t_end, cd, sc, nstk, 0);
+        else
+          hipLaunchKernelGGL((interp<float, 16, false>), dim3(grid), dim3(64), shmem, s, e, tl, t_begin, t_end, cd, sc, nstk, np1);
         break;
       case 32:
-        hipLaunchKernelGGL((interp<float, 32>), dim3(grid), dim3(256), shmem, s, e, tl, t_begin, t_end, cd, sc, nstk, np1);
+        if (flat_only)
+          hipLaunchKernelGGL((interp<float, 32, true>), dim3(grid), dim3(256), shmem, s, e, tl, t_begin, t_end, cd, sc, nstk, 0);
+        else
+          hipLaunchKernelGGL((interp<float, 32, false>), dim3(grid), dim3(256), shmem, s, e, tl, t_begin, t_end, cd, sc, nstk, np1);
         break;
       default: return hipErrorInvalidValue;
     }
@@ -362,10 +373,16 @@ extern "C" hipError_t coot_batch_launch_kernel(int dtype, int ts, unsigned grid,
     const double* sc = (const double*)scal;
     switch (ts) {
       case 16:
-        hipLaunchKernelGGL((interp<double, 16>), dim3(grid), dim3(64), shmem, s, e, tl, t_begin, t_end, cd, sc, nstk, np1);
+        if (flat_only)
+          hipLaunchKernelGGL((interp<double, 16, true>), dim3(grid), dim3(64), shmem, s, e, tl, t_begin, t_end, cd, sc, nstk, 0);
+        else
+          hipLaunchKernelGGL((interp<double, 16, false>), dim3(grid), dim3(64), shmem, s, e, tl, t_begin, t_end, cd, sc, nstk, np1);
         break;
       case 32:
-        hipLaunchKernelGGL((interp<double, 32>), dim3(grid), dim3(256), shmem, s, e, tl, t_begin, t_end, cd, sc, nstk, np1);
+        if (flat_only)
+          hipLaunchKernelGGL((interp<double, 32, true>), dim3(grid), dim3(256), shmem, s, e, tl, t_begin, t_end, cd, sc, nstk, 0);
+        else
+          hipLaunchKernelGGL((interp<double, 32, false>), dim3(grid), dim3(256), shmem, s, e, tl, t_begin, t_end, cd, sc, nstk, np1);
         break;
       default: return hipErrorInvalidValue;
     }
