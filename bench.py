@@ -39,9 +39,11 @@ def parse():
     p.add_argument("--workload", default="expr4096", choices=["expr4096", "batch", "tuner", "suite"],
                    help="expr4096: the fused 2-D expression step (default); batch: 10,000 small expressions")
     p.add_argument("--batch-n", type=int, default=10_000)
-    p.add_argument("--tune", default="none", choices=["exhaustive", "none"],
-                   help="launch configurations of Z and W: the library defaults, or the exhaustive autotuner's "
-                        "pick (timed alone, before the timed region; within the step the defaults measured faster)")
+    p.add_argument("--tune", default="exhaustive", choices=["exhaustive", "none"],
+                   help="launch configurations of Z and W: the exhaustive autotuner's pick (before the timed "
+                        "region; the step with the library defaults is timed too) or the library defaults")
+    p.add_argument("--z-cfg", default="", help="launch configuration vec,ept,waves,grid_mult for Z (default: library's)")
+    p.add_argument("--w-cfg", default="", help="launch configuration vec,ept,waves,grid_mult for W (default: library's)")
     p.add_argument("--batch-fused-sample", type=int, default=500,
                    help="expressions timed with the plain fused kernel, one launch each")
     p.add_argument("--tuner-train", type=int, default=1800, help="training signatures (~50,000 timings)")
@@ -104,6 +106,9 @@ def main():
     # launch configurations of the element-wise kernels: the project's autotuner (exhaustive
     # over the family's space, cold-cache timings), run once before any timed region
     cfgs = {"Z": None, "W": None}
+    for k, v in (("Z", args.z_cfg), ("W", args.w_cfg)):
+        if v:
+            cfgs[k] = tuple(int(x) for x in v.split(","))
     t0 = time.perf_counter()
     if args.tune == "exhaustive":
         cfgs["Z"] = cc.coot_tune(fused[0], zops, zf.scalars, zo, -1, 1, stream=stream)[0]
@@ -176,9 +181,9 @@ def main():
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
-    # the tuned and the default configurations are timed in alternating blocks of steps, so
-    # that clock and temperature drift over the run affects both alike
-    z_events = []
+    # the chosen and the default configurations are timed in alternating blocks of steps, so
+    # that clock and temperature drift over the run affects both alike; no events are
+    # recorded inside these steps (a pair of event records costs several microseconds)
     for _ in range(args.warmup):
         step(*fused, cfgs["Z"], cfgs["W"])
         step(*fused)
@@ -186,11 +191,15 @@ def main():
     per = [args.steps // blocks + (1 if k < args.steps % blocks else 0) for k in range(blocks)]
     t_fused = t_default = 0.0
     for n in per:
-        t_fused += run(fused, n, 0, cfgs["Z"], cfgs["W"], z_events) * n
-        if args.tune != "none":
+        t_fused += run(fused, n, 0, cfgs["Z"], cfgs["W"]) * n
+        if cfgs["Z"] or cfgs["W"]:
             t_default += run(fused, n, 0) * n
     t_fused /= args.steps
-    t_default = t_default / args.steps if args.tune != "none" else t_fused
+    t_default = t_default / args.steps if (cfgs["Z"] or cfgs["W"]) else t_fused
+    # the Z kernel's launch duration for the roofline: the same steps again, with HIP events
+    # around each Z launch on its stream
+    z_events = []
+    run(fused, args.steps, 0, cfgs["Z"], cfgs["W"], z_events)
     z_ms = sum(a.elapsed_time(b) for a, b in z_events) / len(z_events)
     t_unfused = run(unfused, max(3, args.steps // 4), 2)
 
@@ -224,7 +233,8 @@ def main():
         "pct_of_copy_probe": round(100 * value / copy_gbs, 1),
         "launch_cfgs": {"Z": cfgs["Z"], "W": cfgs["W"], "sums": "library default",
                         "chosen_by": "exhaustive autotuner before timing" if args.tune == "exhaustive"
-                        else "library defaults", "tuning_s": round(t_tune, 2)},
+                        else ("given" if (cfgs["Z"] or cfgs["W"]) else "library defaults"),
+                        "tuning_s": round(t_tune, 2)},
         "default_cfg_ms_per_step": round(t_default * 1e3, 4),
         "unfused_ms_per_step": round(t_unfused * 1e3, 4),
         "speedup_vs_unfused": round(t_unfused / t_fused, 2),
