@@ -231,6 +231,10 @@ def main():
         "pct_of_peak": round(100 * value / PEAK_HBM_GBS, 1),
         "copy_probe_gbs": round(copy_gbs, 1),
         "pct_of_copy_probe": round(100 * value / copy_gbs, 1),
+        "kernels": {"copy": cc.coot_expr_kernel_name(hcopy), "Z": zname,
+                    "W": cc.coot_expr_kernel_name(fused[1], cfg=cfgs["W"]),
+                    "sumZ0": cc.coot_expr_kernel_name(fused[0], cc.COOT_RED_SUM, 0),
+                    "sumZ1": cc.coot_expr_kernel_name(fused[0], cc.COOT_RED_SUM, 1)},
         "launch_cfgs": {"Z": cfgs["Z"], "W": cfgs["W"], "sums": "library default",
                         "chosen_by": "exhaustive autotuner before timing" if args.tune == "exhaustive"
                         else ("given" if (cfgs["Z"] or cfgs["W"]) else "library defaults"),
