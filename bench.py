@@ -354,7 +354,9 @@ def bench_batch(args):
             "expressions": ns, "ms_fused_kernel_launches": round(t_fused_each * 1e3, 3),
             "ms_batch": round(t_bsub * 1e3, 4), "speedup": round(t_fused_each / t_bsub, 1),
             "precompile_s": round(t_pre, 1)},
-        "tuned_cfg": {"vec": cfg[0], "waves": cfg[2], "tile": info2["tile"], "grid_mult": cfg[3]},
+        "tuned_cfg": {"flat_part": {"tile": info2["tile"], "grid": info2["grid"], "vec": cfg[0]},
+                      "2d_part": {"tile": info2["tile_2d"], "grid": info2["grid_2d"]},
+                      "flat_tiles": info2["flat_tiles"]},
         "default_cfg": {"tile": info["tile"], "grid": info["grid"]},
         "vec4_exprs": info2["vec4_exprs"], "pct_of_peak": round(100 * gbs / PEAK_HBM_GBS, 1),
         "tuning_s": round(t_tune, 2), "create_s": round(t_create, 2), "generate_s": round(t_gen, 1),

@@ -221,8 +221,10 @@ coot_status coot_expr_kernel_name(coot_expr* e, int32_t mode, int32_t dim, const
  *                       where aligned, 8 workgroups per CU); else waves 1 / 4
  *                       selects tiles of 16 x 16 / 32 x 32 elements (4 per thread),
  *                       vec = 1 forbids 128-bit accesses, grid_mult sets
- *                       workgroups per CU.  Expressions with untransposed contiguous
- *                       leaves are cut into flat chunks of the same element count.
+ *                       workgroups per CU, all for both parts.  Expressions with
+ *                       untransposed contiguous leaves are cut into flat chunks of
+ *                       the same element count and run in a launch of their own
+ *                       (the flat part); the others in 2-D tiles (the 2-D part).
  *   stream              unused at creation (descriptors are uploaded synchronously)
  * All operand and output buffers must stay allocated, at the same addresses, for
  * the life of the batch: their addresses are baked into the descriptors.
@@ -238,17 +240,22 @@ coot_status coot_batch_launch(coot_batch* b, void* stream);
 /* Comparator: the same kernel launched once per expression on `stream`. */
 coot_status coot_batch_launch_each(coot_batch* b, void* stream);
 
-/* Autotune the batch launch on `stream` (synchronises it): times every tile size
- * (16, 32), grid multiplier (2, 4, 8, 16) and vector width (128-bit where
- * aligned, or scalar), median of 5 launches each; keeps the fastest and
- * re-captures the graph.  best / best_us may be NULL. */
+/* Autotune the batch launch on `stream` (synchronises it).  The flat-chunk part
+ * and the 2-D-tile part of the batch are tuned separately, each on its own
+ * launch: every tile size (16, 32), grid multiplier (2, 4, 8, 16) and vector
+ * width (128-bit where aligned, or scalar), median of 5 launches each; the
+ * fastest of each part is kept and the graph re-captured.  best (may be NULL)
+ * receives the flat part's settings (coot_batch_info reports both parts);
+ * best_us (may be NULL) the sum of the two parts' medians. */
 coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, float* best_us);
 
 /* info[0] expressions, [1] tiles, [2] algorithmic bytes (each distinct operand
- * read once + outputs written once), [3] tile edge, [4] grid, [5] expressions on
- * the 128-bit path, [6] expressions cut into flat chunks, [7] LDS stack entries
- * per thread, [8] transposed-leaf tiles staged in LDS per workgroup. */
-coot_status coot_batch_info(const coot_batch* b, int64_t info[9]);
+ * read once + outputs written once), [3] tile edge of the flat part (chunks of
+ * edge^2 elements), [4] its grid, [5] expressions on the 128-bit path,
+ * [6] expressions cut into flat chunks, [7] LDS stack entries per thread,
+ * [8] transposed-leaf tiles staged in LDS per workgroup, [9] tile edge of the 2-D
+ * part, [10] its grid, [11] tiles of the flat part (the work-list's first). */
+coot_status coot_batch_info(const coot_batch* b, int64_t info[12]);
 
 void coot_batch_release(coot_batch* b);
 

@@ -180,12 +180,13 @@ struct coot_batch {
   DevBuf<BatchExpr> d_ex;
   DevBuf<uint32_t> d_code, d_tiles;
   DevBuf<uint64_t> d_scal32x2;  // scalars packed as the element type
-  int ts = 32;
-  int gm = 8;
+  // launch settings of the two parts: [0] flat chunks, [1] 2-D tiles
+  int ts[2] = {32, 32};             // tile edge (a flat chunk holds ts * ts elements)
+  int gm[2] = {8, 8};               // workgroups per CU
+  bool allow_vec[2] = {true, true};  // 128-bit accesses where the layout allows them
+  unsigned grid[2] = {1, 1};
   int nstk = 1;    // LDS stack entries: the deepest expression's registers minus the top
   int max_p1 = 0;  // most transposed leaves in one expression
-  bool allow_vec = true;
-  unsigned grid = 1;
   int64_t bytes = 0;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -212,11 +213,12 @@ void build_tiles(coot_batch* b) {
   for (size_t k : order) {
     BatchExpr& e = b->ex[k];
     e.flat = b->flat_ok[k];
-    e.tiles_r = (e.n_rows + b->ts - 1) / b->ts;
-    const int tc = (e.n_cols + b->ts - 1) / b->ts;
-    e.vec4 = (b->allow_vec && b->vec4_ok[k]) ? 1 : 0;
+    const int part = e.flat ? 0 : 1, ts = b->ts[part];
+    e.tiles_r = (e.n_rows + ts - 1) / ts;
+    const int tc = (e.n_cols + ts - 1) / ts;
+    e.vec4 = (b->allow_vec[part] && b->vec4_ok[k]) ? 1 : 0;
     const int begin = (int)(b->tiles.size() / 2);
-    const int64_t chunk = (int64_t)b->ts * b->ts;  // flat tiles: 4 elements per thread, ts*ts/4 threads
+    const int64_t chunk = (int64_t)ts * ts;  // flat tiles: 4 elements per thread, ts*ts/4 threads
     const int64_t nt = e.flat ? ((int64_t)e.n_rows * e.n_cols + chunk - 1) / chunk : (int64_t)e.tiles_r * tc;
     for (int64_t t = 0; t < nt; ++t) {
       b->tiles.push_back((uint32_t)k);
@@ -228,7 +230,8 @@ void build_tiles(coot_batch* b) {
   b->d_ex.upload(b->ex);
   b->d_tiles.upload(b->tiles);
   const int n_tiles = (int)(b->tiles.size() / 2);
-  b->grid = (unsigned)std::max(1, std::min(n_tiles, b->gm * num_cus()));
+  const int n_part[2] = {b->n_flat_tiles, n_tiles - b->n_flat_tiles};
+  for (int p = 0; p < 2; ++p) b->grid[p] = (unsigned)std::max(1, std::min(n_part[p], b->gm[p] * num_cus()));
 }
 
 // Transposed-leaf tiles staged in LDS: as many as an expression needs (at most 4)
@@ -238,27 +241,29 @@ void build_tiles(coot_batch* b) {
 constexpr size_t kMaxDynLds = 65536 - 2048;
 int staged_tiles(const coot_batch* b) {
   const size_t es = b->dtype == COOT_BATCH_F32 ? 4 : 8;
-  const size_t stack = (size_t)b->nstk * (b->ts * b->ts / 4) * 4 * es;
-  const size_t slot = (size_t)b->ts * (b->ts + 1) * es;
+  const int ts = b->ts[1];
+  const size_t stack = (size_t)b->nstk * (ts * ts / 4) * 4 * es;
+  const size_t slot = (size_t)ts * (ts + 1) * es;
   const size_t budget = std::max<size_t>(32768, stack + slot);
   size_t n = std::min<size_t>({(size_t)b->max_p1, 4, budget > stack ? (budget - stack) / slot : 0});
   while (n > 0 && stack + n * slot > kMaxDynLds) --n;
   return (int)n;
 }
 
+// part 0: the flat-chunk tiles with the flat-only interpreter; part 1: the 2-D tiles
+void launch_part(coot_batch* b, int part, hipStream_t s) {
+  const int n_tiles = (int)(b->tiles.size() / 2), nf = b->n_flat_tiles;
+  const int t0 = part == 0 ? 0 : nf, t1 = part == 0 ? nf : n_tiles;
+  if (t1 <= t0) return;
+  hip_check(coot_batch_launch_kernel(b->dtype, b->ts[part], b->grid[part], b->d_ex.p, b->d_tiles.p, t0, t1,
+                                     b->d_code.p, b->d_scal32x2.p, b->nstk, part == 0 ? 0 : staged_tiles(b),
+                                     part == 0 ? 1 : 0, s),
+            "batch kernel launch");
+}
+
 void launch_all(coot_batch* b, hipStream_t s) {
-  const int n_tiles = (int)(b->tiles.size() / 2);
-  const int nf = b->n_flat_tiles;
-  // each part gets the configured grid, or fewer workgroups when it has fewer tiles
-  if (nf > 0)
-    hip_check(coot_batch_launch_kernel(b->dtype, b->ts, std::min<unsigned>(b->grid, (unsigned)nf), b->d_ex.p,
-                                       b->d_tiles.p, 0, nf, b->d_code.p, b->d_scal32x2.p, b->nstk, 0, 1, s),
-              "batch kernel launch");
-  if (n_tiles > nf)
-    hip_check(coot_batch_launch_kernel(b->dtype, b->ts, std::min<unsigned>(b->grid, (unsigned)(n_tiles - nf)),
-                                       b->d_ex.p, b->d_tiles.p, nf, n_tiles, b->d_code.p, b->d_scal32x2.p, b->nstk,
-                                       staged_tiles(b), 0, s),
-              "batch kernel launch");
+  launch_part(b, 0, s);
+  launch_part(b, 1, s);
 }
 
 void capture(coot_batch* b) {
@@ -292,14 +297,16 @@ coot_status coot_batch_create(uint32_t n, coot_expr* const* exprs, const coot_op
     if (!out || (n && (!exprs || !operands || !outs))) fail(COOT_EINVAL, "NULL argument");
     *out = nullptr;
     auto b = std::make_unique<coot_batch>();
-    if (cfg) {
-      if (cfg->waves) {
-        if (cfg->waves == 1) b->ts = 16;
-        else if (cfg->waves == 4) b->ts = 32;
-        else fail(COOT_EINVAL, "batch waves must be 1 or 4 (tiles of 16 x 16 or 32 x 32 elements)");
+    if (cfg) {  // the same settings for both parts
+      for (int p = 0; p < 2; ++p) {
+        if (cfg->waves) {
+          if (cfg->waves == 1) b->ts[p] = 16;
+          else if (cfg->waves == 4) b->ts[p] = 32;
+          else fail(COOT_EINVAL, "batch waves must be 1 or 4 (tiles of 16 x 16 or 32 x 32 elements)");
+        }
+        if (cfg->grid_mult) b->gm[p] = cfg->grid_mult;
+        if (cfg->vec == 1) b->allow_vec[p] = false;
       }
-      if (cfg->grid_mult) b->gm = cfg->grid_mult;
-      if (cfg->vec == 1) b->allow_vec = false;
     }
     int dtype = -1;
     std::vector<double> scal;
@@ -403,9 +410,9 @@ coot_status coot_batch_launch_each(coot_batch* b, void* stream) {
     if (!b) fail(COOT_EINVAL, "NULL batch");
     for (auto& r : b->ranges) {
       if (r.second == r.first) continue;
-      const unsigned g = (unsigned)std::min(r.second - r.first, (int)b->grid);
-      const int fl = r.second <= b->n_flat_tiles ? 1 : 0;
-      hip_check(coot_batch_launch_kernel(b->dtype, b->ts, g, b->d_ex.p, b->d_tiles.p, r.first, r.second,
+      const int fl = r.second <= b->n_flat_tiles ? 1 : 0, part = fl ? 0 : 1;
+      const unsigned g = (unsigned)std::min(r.second - r.first, (int)b->grid[part]);
+      hip_check(coot_batch_launch_kernel(b->dtype, b->ts[part], g, b->d_ex.p, b->d_tiles.p, r.first, r.second,
                                          b->d_code.p, b->d_scal32x2.p, b->nstk, fl ? 0 : staged_tiles(b), fl,
                                          (hipStream_t)stream),
                 "batch kernel launch");
@@ -420,62 +427,76 @@ coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, 
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");
-    float bt = 1e30f;
-    int bts = b->ts, bgm = b->gm;
-    bool bvec = b->allow_vec;
-    for (int ts : {16, 32}) {
-      for (int gm : {2, 4, 8, 16}) {
-        for (bool vec : {true, false}) {
-          b->ts = ts;
-          b->gm = gm;
-          b->allow_vec = vec;
-          build_tiles(b);
-          launch_all(b, s);  // warm-up
-          std::vector<float> ts_ms;
-          for (int rep = 0; rep < 5; ++rep) {
-            hip_check(hipEventRecord(e0, s), "hipEventRecord");
-            launch_all(b, s);
-            hip_check(hipEventRecord(e1, s), "hipEventRecord");
-            hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
-            float ms = 0;
-            hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-            ts_ms.push_back(ms);
-          }
-          std::sort(ts_ms.begin(), ts_ms.end());
-          if (ts_ms[2] < bt) {
-            bt = ts_ms[2];
-            bts = ts;
-            bgm = gm;
-            bvec = vec;
+    float total = 0;
+    try {
+      // each part is tuned on its own launch (the other part's settings do not affect it)
+      for (int part = 0; part < 2; ++part) {
+        float bt = 1e30f;
+        int bts = b->ts[part], bgm = b->gm[part];
+        bool bvec = b->allow_vec[part];
+        for (int ts : {16, 32}) {
+          for (int gm : {2, 4, 8, 16}) {
+            for (bool vec : {true, false}) {
+              b->ts[part] = ts;
+              b->gm[part] = gm;
+              b->allow_vec[part] = vec;
+              build_tiles(b);
+              launch_part(b, part, s);  // warm-up
+              std::vector<float> t_ms;
+              for (int rep = 0; rep < 5; ++rep) {
+                hip_check(hipEventRecord(e0, s), "hipEventRecord");
+                launch_part(b, part, s);
+                hip_check(hipEventRecord(e1, s), "hipEventRecord");
+                hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+                float ms = 0;
+                hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+                t_ms.push_back(ms);
+              }
+              std::sort(t_ms.begin(), t_ms.end());
+              if (t_ms[2] < bt) {
+                bt = t_ms[2];
+                bts = ts;
+                bgm = gm;
+                bvec = vec;
+              }
+            }
           }
         }
+        b->ts[part] = bts;
+        b->gm[part] = bgm;
+        b->allow_vec[part] = bvec;
+        total += bt;
       }
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    b->ts = bts;
-    b->gm = bgm;
-    b->allow_vec = bvec;
     build_tiles(b);
     capture(b);
-    if (best) {
-      best->vec = bvec ? 4 : 1;
+    if (best) {  // the flat part's settings (coot_batch_info reports both parts)
+      best->vec = b->allow_vec[0] ? 4 : 1;
       best->ept = 4;
-      best->waves = (uint16_t)(bts * bts / 256);
-      best->grid_mult = (uint16_t)bgm;
+      best->waves = (uint16_t)(b->ts[0] * b->ts[0] / 256);
+      best->grid_mult = (uint16_t)b->gm[0];
     }
-    if (best_us) *best_us = bt * 1000.0f;
+    if (best_us) *best_us = total * 1000.0f;
   });
 }
 
-coot_status coot_batch_info(const coot_batch* b, int64_t info[9]) {
+coot_status coot_batch_info(const coot_batch* b, int64_t info[12]) {
   return guarded([&] {
     if (!b || !info) fail(COOT_EINVAL, "NULL argument");
     info[0] = (int64_t)b->ex.size();
     info[1] = (int64_t)(b->tiles.size() / 2);
     info[2] = b->bytes;
-    info[3] = b->ts;
-    info[4] = b->grid;
+    info[3] = b->ts[0];
+    info[4] = b->grid[0];
+    info[9] = b->ts[1];
+    info[10] = b->grid[1];
+    info[11] = b->n_flat_tiles;
     int64_t v4 = 0, fl = 0;
     for (auto& e : b->ex) {
       v4 += e.vec4;
