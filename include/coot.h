@@ -134,6 +134,20 @@ typedef struct coot_batch coot_batch;
  * Errors: COOT_EHIP if the device cannot be selected. */
 coot_status coot_init(int hip_device);
 
+/* Device memory for the library's workspaces (reduction partials) and the
+ * unfused comparator's temporaries comes from alloc / dealloc when given (for
+ * example the caller's caching allocator), else from hipMalloc / hipFree.
+ * alloc(bytes, stream, ctx) returns device memory usable in stream order on
+ * `stream` (NULL: COOT_ENOMEM for the call that needed it); dealloc(ptr, stream,
+ * ctx) returns it in stream order.  The call waits for the device, hands every
+ * held buffer back to the allocator that provided it, then installs the new
+ * one; give both functions or neither (back to hipMalloc).  Batches, models and
+ * code objects keep using hipMalloc.  Errors: COOT_EINVAL (one function NULL, or
+ * called while a comparator temporary is in use), COOT_EHIP. */
+typedef void* (*coot_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*coot_free_fn)(void* ptr, void* stream, void* ctx);
+coot_status coot_set_allocator(coot_alloc_fn alloc, coot_free_fn dealloc, void* ctx);
+
 /* Validate and analyse a postfix expression (Section 3: the whole expression is
  * analysed before any work is issued).
  *   ops[n_ops]         postfix list

@@ -7,4 +7,4 @@ built — there is no CPU fallback.
 """
 from . import _coot  # noqa: F401
 from .frontend import (Batch, Expr, Mat, Node, Scalar, abs, accu, dot, eval, exp, flatten, init, log, norm,  # noqa: F401
-                       precompile, sqrt, square, sum, trans)
+                       precompile, sqrt, square, sum, trans, use_torch_allocator)

@@ -64,6 +64,7 @@ lib = _load()
 _P = C.c_void_p
 _sig = {
     "coot_init": (C.c_int, [C.c_int]),
+    "coot_set_allocator": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "coot_expr_compile": (C.c_int, [C.POINTER(coot_op), C.c_uint32, C.POINTER(coot_slot_type), C.c_uint32,
                                     C.c_uint32, C.c_uint32, C.POINTER(_P)]),
     "coot_expr_prepare": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_uint32, C.POINTER(coot_launch_cfg)]),
@@ -162,6 +163,25 @@ def coot_expr_compile(postfix, slot_types, n_scalars: int, flags: int = 0) -> in
     h = _P()
     _check(lib.coot_expr_compile(ops, len(postfix), slots, len(slot_types), n_scalars, flags, C.byref(h)))
     return h.value
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+_allocator_refs = []  # keeps the installed callbacks alive
+
+
+def coot_set_allocator(alloc=None, dealloc=None) -> None:
+    """alloc(bytes, stream) -> int device pointer, dealloc(ptr, stream); None, None for hipMalloc."""
+    if (alloc is None) != (dealloc is None):
+        raise ValueError("give both functions or neither")
+    if alloc is None:
+        _check(lib.coot_set_allocator(None, None, None))
+        _allocator_refs.clear()
+        return
+    fa = ALLOC_FN(lambda n, s, ctx: alloc(n, s or 0))
+    fd = FREE_FN(lambda p, s, ctx: dealloc(p, s or 0))
+    _check(lib.coot_set_allocator(C.cast(fa, C.c_void_p), C.cast(fd, C.c_void_p), None))
+    _allocator_refs[:] = [fa, fd]
 
 
 def coot_expr_prepare(h: int, mode: int = -1, dim: int = -1, rflags: int = 0, cfg=None) -> None:

@@ -41,6 +41,17 @@ coot_status coot_expr_compile(const coot_op* ops, uint32_t n_ops, const coot_slo
   });
 }
 
+coot_status coot_set_allocator(coot_alloc_fn alloc, coot_free_fn dealloc, void* ctx) {
+  return guarded([&] {
+    if ((alloc == nullptr) != (dealloc == nullptr)) fail(COOT_EINVAL, "give both functions or neither");
+    DevAllocator a;
+    a.alloc = alloc;
+    a.dealloc = dealloc;
+    a.ctx = ctx;
+    set_allocator(a);
+  });
+}
+
 coot_status coot_expr_prepare(coot_expr* h, int32_t mode, int32_t dim, uint32_t rflags, const coot_launch_cfg* cfg) {
   return guarded([&] {
     if (!h) fail(COOT_EINVAL, "NULL expression");

@@ -130,6 +130,16 @@ std::mutex& global_mutex();
 
 // Device / workspace ------------------------------------------------------------
 int num_cus();
+// Device memory of workspaces and temporaries: the caller's allocator
+// (coot_set_allocator) or hipMalloc / hipFree; each buffer remembers which.
+struct DevAllocator {
+  void* (*alloc)(size_t, void*, void*) = nullptr;
+  void (*dealloc)(void*, void*, void*) = nullptr;
+  void* ctx = nullptr;
+};
+void* dev_alloc(size_t bytes, hipStream_t s, DevAllocator* used);
+void dev_free(void* p, hipStream_t s, const DevAllocator& used);
+void set_allocator(const DevAllocator& a);
 void* workspace(size_t bytes, hipStream_t s, int which);
 void* temp_alloc(size_t bytes, hipStream_t s);
 void temp_free(void* p, size_t bytes, hipStream_t s);

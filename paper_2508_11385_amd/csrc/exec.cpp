@@ -27,6 +27,33 @@ int num_cus() {
   return cached;
 }
 
+// ---- device memory: the caller's allocator, or hipMalloc ----------------------------
+namespace {
+DevAllocator& current_allocator() {
+  static DevAllocator a;  // all NULL: hipMalloc / hipFree
+  return a;
+}
+}  // namespace
+
+void* dev_alloc(size_t bytes, hipStream_t s, DevAllocator* used) {
+  const DevAllocator a = current_allocator();
+  void* p = nullptr;
+  if (a.alloc) {
+    p = a.alloc(bytes, (void*)s, a.ctx);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (!p) fail(COOT_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  *used = a;
+  return p;
+}
+
+void dev_free(void* p, hipStream_t s, const DevAllocator& used) {
+  if (!p) return;
+  if (used.dealloc) used.dealloc(p, (void*)s, used.ctx);
+  else (void)hipFree(p);
+}
+
 // ---- workspace and temporaries ------------------------------------------------
 namespace {
 struct WsKey {
@@ -40,13 +67,23 @@ struct WsHash {
 struct WsBuf {
   void* p = nullptr;
   size_t n = 0;
+  DevAllocator al;  // what allocated p
 };
 std::unordered_map<WsKey, WsBuf, WsHash>& ws_map() {
   static std::unordered_map<WsKey, WsBuf, WsHash> m;
   return m;
 }
-std::map<std::pair<void*, size_t>, std::vector<void*>>& temp_pool() {
-  static std::map<std::pair<void*, size_t>, std::vector<void*>> m;
+struct Temp {
+  void* p;
+  DevAllocator al;
+};
+std::map<std::pair<void*, size_t>, std::vector<Temp>>& temp_pool() {
+  static std::map<std::pair<void*, size_t>, std::vector<Temp>> m;
+  return m;
+}
+// allocator of every temporary handed out and not yet returned to the pool
+std::map<void*, DevAllocator>& temps_out() {
+  static std::map<void*, DevAllocator> m;
   return m;
 }
 }  // namespace
@@ -58,14 +95,11 @@ void* workspace(size_t bytes, hipStream_t s, int which) {
   size_t want = std::max<size_t>(bytes, 1 << 16);
   if (b.p) {
     hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
-    hip_check(hipFree(b.p), "hipFree");
+    dev_free(b.p, s, b.al);
     b.p = nullptr;
     b.n = 0;
   }
-  if (hipMalloc(&b.p, want) != hipSuccess) {
-    b.p = nullptr;
-    fail(COOT_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
-  }
+  b.p = dev_alloc(want, s, &b.al);
   b.n = want;
   return b.p;
 }
@@ -73,22 +107,39 @@ void* workspace(size_t bytes, hipStream_t s, int which) {
 void* temp_alloc(size_t bytes, hipStream_t s) {
   std::lock_guard<std::mutex> g(global_mutex());
   auto& v = temp_pool()[{(void*)s, bytes}];
+  Temp t;
   if (!v.empty()) {
-    void* p = v.back();
+    t = v.back();
     v.pop_back();
-    return p;
+  } else {
+    t.p = dev_alloc(std::max<size_t>(bytes, 256), s, &t.al);
   }
-  void* p = nullptr;
-  if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess)
-    fail(COOT_ENOMEM, "temporary allocation of " + std::to_string(bytes) + " bytes failed");
-  return p;
+  temps_out()[t.p] = t.al;
+  return t.p;
 }
 
 // Stream-ordered reuse: a temporary handed back here is only given out again for
 // work queued later on the same stream.
 void temp_free(void* p, size_t bytes, hipStream_t s) {
   std::lock_guard<std::mutex> g(global_mutex());
-  temp_pool()[{(void*)s, bytes}].push_back(p);
+  auto it = temps_out().find(p);
+  const DevAllocator al = it != temps_out().end() ? it->second : DevAllocator{};
+  if (it != temps_out().end()) temps_out().erase(it);
+  temp_pool()[{(void*)s, bytes}].push_back({p, al});
+}
+
+// Waits for the device, returns every workspace and pooled temporary to the
+// allocator that provided it, and makes `a` the allocator of later ones.
+void set_allocator(const DevAllocator& a) {
+  std::lock_guard<std::mutex> g(global_mutex());
+  if (!temps_out().empty()) fail(COOT_EINVAL, "temporaries are in use");
+  hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  for (auto& kv : ws_map()) dev_free(kv.second.p, kv.first.s, kv.second.al);
+  ws_map().clear();
+  for (auto& kv : temp_pool())
+    for (auto& t : kv.second) dev_free(t.p, (hipStream_t)kv.first.first, t.al);
+  temp_pool().clear();
+  current_allocator() = a;
 }
 
 void launch(hipFunction_t f, unsigned grid, unsigned block, const KArgs& args, hipStream_t s) {

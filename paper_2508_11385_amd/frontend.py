@@ -261,6 +261,23 @@ def precompile(exprs, workers: int = 12) -> list:
     return flats
 
 
+def use_torch_allocator(enable: bool = True) -> None:
+    """Take the library's workspaces and comparator temporaries from PyTorch's caching
+    allocator (stream-ordered), or give them back to hipMalloc."""
+    if not enable:
+        cc.coot_set_allocator(None, None)
+        return
+    dev = torch.cuda.current_device()
+
+    def alloc(n, stream):
+        return int(torch.cuda.caching_allocator_alloc(int(n), device=dev, stream=int(stream)))
+
+    def dealloc(p, stream):
+        torch.cuda.caching_allocator_delete(int(p))
+
+    cc.coot_set_allocator(alloc, dealloc)
+
+
 def _stream() -> int:
     return torch.cuda.current_stream().cuda_stream
 

@@ -210,3 +210,14 @@ def test_compile_only_prepare_needs_no_device(cc, tmp_path, monkeypatch):
         cc.coot_expr_prepare(h, -1, rflags=0x8000)
     assert e.value.status == cc.COOT_EINVAL
     cc.coot_expr_release(h)
+
+
+def test_set_allocator_needs_both_functions(cc):
+    import ctypes
+    f = cc.ALLOC_FN(lambda n, s, ctx: 0)
+    with pytest.raises(cc.CootError) as e:
+        _ = cc.lib.coot_set_allocator(ctypes.cast(f, ctypes.c_void_p), None, None)
+        cc._check(_)
+    assert e.value.status == cc.COOT_EINVAL
+    with pytest.raises(ValueError):
+        cc.coot_set_allocator(lambda n, s: 0, None)

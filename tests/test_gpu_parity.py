@@ -340,3 +340,41 @@ def test_full_size_hard_reductions(coot):
           f"norm rel err {e_nrm:.2e} (plain {abs(plain_n - nref) / nref:.2e}), "
           f"kappa {sc / abs(float(ref)):.2f}")
     assert e_acc <= 1e-6 and e_nrm <= 1e-6
+
+
+def test_caller_allocator_for_workspaces_and_temporaries(coot):
+    """Workspaces and comparator temporaries come from PyTorch's caching allocator while it
+    is installed, results are bitwise those of hipMalloc'd buffers, and switching back
+    hands every buffer to the allocator that provided it."""
+    import torch
+    import paper_2508_11385_amd._coot as cc
+    A, B, C, D = synth.matrix_inputs(n_rows=300, n_cols=200)
+    gs = [up(coot, m) for m in (A, B, C, D)]
+    flat = coot.flatten(_z(coot, *gs))
+    h = coot.frontend.compiled(flat)
+    hu = coot.frontend.compiled(flat, cc.COOT_CF_UNFUSED)
+    ops = [m.operand() for m in flat.mats]
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def run():
+        s0, u = coot.Mat.empty(1, 200, "f32", "row"), coot.Mat.empty(300, 200)
+        cc.coot_reduce(h, ops, flat.scalars, cc.COOT_RED_SUM, 0, 0, s0.operand(), None, stream)
+        cc.coot_expr_eval(hu, ops, flat.scalars, u.operand(), None, stream)
+        torch.cuda.synchronize()
+        return s0.numpy(), u.numpy()
+
+    ref = run()
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    coot.use_torch_allocator(True)
+    try:
+        got = run()
+        during = torch.cuda.memory_allocated()
+    finally:
+        coot.use_torch_allocator(False)
+    # the library holds at least one 64 KiB workspace from the caching allocator, and
+    # hands it back when the allocator is switched off
+    assert during - base >= 65536, "no library buffer came from the caching allocator"
+    assert during - torch.cuda.memory_allocated() >= 65536
+    assert all(np.array_equal(a, b) for a, b in zip(ref, got))
+    assert all(np.array_equal(a, b) for a, b in zip(ref, run()))
