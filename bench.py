@@ -356,8 +356,10 @@ def bench_batch(args):
             "precompile_s": round(t_pre, 1)},
         "tuned_cfg": {"flat_part": {"tile": info2["tile"], "grid": info2["grid"], "vec": cfg[0]},
                       "2d_part": {"tile": info2["tile_2d"], "grid": info2["grid_2d"]},
-                      "flat_tiles": info2["flat_tiles"]},
-        "default_cfg": {"tile": info["tile"], "grid": info["grid"]},
+                      "flat_tiles": info2["flat_tiles"], "parts_side_by_side": bool(info2["concurrent"])},
+        "default_cfg": {"flat_part": {"tile": info["tile"], "grid": info["grid"]},
+                        "2d_part": {"tile": info["tile_2d"], "grid": info["grid_2d"]},
+                        "parts_side_by_side": bool(info["concurrent"])},
         "vec4_exprs": info2["vec4_exprs"], "pct_of_peak": round(100 * gbs / PEAK_HBM_GBS, 1),
         "tuning_s": round(t_tune, 2), "create_s": round(t_create, 2), "generate_s": round(t_gen, 1),
     }
@@ -387,6 +389,27 @@ def bench_suite(args):
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
+
+    from paper_2508_11385_amd import _coot as cc
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def tuned_cfg(e, out, mode):
+        """the exhaustive autotuner's pick for this expression (mode -1 element-wise, else accu)"""
+        f = coot.flatten(e)
+        h = coot.frontend.compiled(f)
+        return cc.coot_tune(h, [m.operand() for m in f.mats], f.scalars, out.operand(), mode, 1, stream=stream)[0]
+
+    def both(name, fn, e, out, mode, nbytes):
+        """time with the library defaults and with the autotuned configuration"""
+        us_d = gpu_us(lambda: fn(None))
+        t0 = time.perf_counter()
+        cfg = tuned_cfg(e, out, mode)
+        t_tune = time.perf_counter() - t0
+        us_t = gpu_us(lambda: fn(cfg))
+        res[name] = {"us": round(us_d, 1), "GBps": round(nbytes / us_d / 1e3, 1),
+                     "us_tuned": round(us_t, 1), "GBps_tuned": round(nbytes / us_t / 1e3, 1),
+                     "tuned_cfg": list(cfg), "tuning_s": round(t_tune, 2)}
+        return cfg
 
     res = {}
     # axpy y = 2.5 x + y in place, then accu(x % y) (the dot pattern) on 1e6 fp32
@@ -425,25 +448,29 @@ def bench_suite(args):
     Ai, Bi, Ci = synth.int_inputs(M, "u32")
     gA, gB, gC = (coot.Mat.from_numpy(m) for m in (Ai, Bi, Ci))
     o = coot.Mat.empty(M, M, "u32")
-    us = gpu_us(lambda: coot.eval((gA + gB) % gC, out=o))
-    res["u32_(A+B)%C_8192"] = {"us": round(us, 1), "GBps": round(4 * 4 * M * M / us / 1e3, 1)}
-    del gA, gB, gC, o
+    eu = (gA + gB) % gC
+    both("u32_(A+B)%C_8192", lambda cfg: coot.eval(eu, out=o, cfg=cfg), eu, o, -1, 4 * 4 * M * M)
+    del gA, gB, gC, o, eu
     As, Bs = synth.int_inputs(M, "s32_full")
     gA, gB = coot.Mat.from_numpy(As), coot.Mat.from_numpy(Bs)
     o = coot.Mat.empty(M, M, "s32")
-    us = gpu_us(lambda: coot.eval(gA - 3 * gB, out=o))
-    res["s32_A-3B_8192"] = {"us": round(us, 1), "GBps": round(3 * 4 * M * M / us / 1e3, 1)}
-    del gA, gB, o
+    es = gA - 3 * gB
+    both("s32_A-3B_8192", lambda cfg: coot.eval(es, out=o, cfg=cfg), es, o, -1, 3 * 4 * M * M)
+    del gA, gB, o, es
     torch.cuda.empty_cache()
     log("integers done")
     # reductions over 2^28 lognormal(0, 4) fp32 values with random signs
     h = synth.hard_reduction_inputs()
     gh = coot.Mat.from_numpy(h, kind="col")
     del h
-    for name, fn in (("accu", lambda: coot.accu(gh)), ("norm", lambda: coot.norm(gh)),
-                     ("accu_plain", lambda: coot.accu(gh, plain=True))):
+    o1 = coot.Mat.empty(1, 1, "f32")
+    nb = 4 * (1 << 28)
+    both("accu_2^28_f32", lambda c: coot.accu(gh, cfg=c), gh, o1, cc.COOT_RED_ACCU, nb)
+    # (the autotuner covers element-wise evaluation and accu: norm and the plain sum run
+    # with the library defaults)
+    for name, fn in (("norm", lambda: coot.norm(gh)), ("accu_plain", lambda: coot.accu(gh, plain=True))):
         us = gpu_us(fn)
-        res[f"{name}_2^28_f32"] = {"us": round(us, 1), "GBps": round(4 * (1 << 28) / us / 1e3, 1)}
+        res[f"{name}_2^28_f32"] = {"us": round(us, 1), "GBps": round(nb / us / 1e3, 1)}
     out = {"metric": "throughput of the other workloads (GB/s of algorithmic bytes)", "value": None,
            "unit": "GB/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic, seeded, resident in HBM",
            "config": {"workload": "axpy+dot 1e6 f32; 4096^2 step f64; u32/s32 8192^2; accu/norm 2^28 f32"},

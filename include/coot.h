@@ -231,8 +231,9 @@ coot_status coot_expr_kernel_name(coot_expr* e, int32_t mode, int32_t dim, const
  *   operands[n][...]    each expression's device operands (n_slots of it)
  *   scalars[n][...]     each expression's scalars (host, copied)
  *   outs[n]             caller-allocated device outputs with the inferred dims
- *   cfg                 NULL = default (tiles of 32 x 32 elements, vectorised
- *                       where aligned, 8 workgroups per CU); else waves 1 / 4
+ *   cfg                 NULL = default (flat chunks of 32 x 32 elements, 2-D tiles
+ *                       of 16 x 16, vectorised where aligned, 16 workgroups per
+ *                       CU); else waves 1 / 4
  *                       selects tiles of 16 x 16 / 32 x 32 elements (4 per thread),
  *                       vec = 1 forbids 128-bit accesses, grid_mult sets
  *                       workgroups per CU, all for both parts.  Expressions with
@@ -241,9 +242,13 @@ coot_status coot_expr_kernel_name(coot_expr* e, int32_t mode, int32_t dim, const
  *                       (the flat part); the others in 2-D tiles (the 2-D part).
  *   stream              unused at creation (descriptors are uploaded synchronously)
  * All operand and output buffers must stay allocated, at the same addresses, for
- * the life of the batch: their addresses are baked into the descriptors.
+ * the life of the batch: their addresses are baked into the descriptors.  The
+ * graph runs the two parts side by side (fork / join on two captured streams).
+ * The kernel addresses each operand and output as a raw buffer with 32-bit byte
+ * offsets, so each must span less than 2 GiB (else COOT_EUNSUPPORTED).
  * Errors: COOT_EINVAL, COOT_ESHAPE, COOT_ETYPE, COOT_EALIAS, COOT_EUNSUPPORTED
- * (integer types, more than 12 leaves, more than 8 registers), COOT_ENOMEM, COOT_EHIP. */
+ * (integer types, more than 12 leaves, more than 8 registers, an operand of 2 GiB
+ * or more), COOT_ENOMEM, COOT_EHIP. */
 coot_status coot_batch_create(uint32_t n, coot_expr* const* exprs, const coot_operand* const* operands,
                               const double* const* scalars, const coot_operand* outs,
                               const coot_launch_cfg* cfg, void* stream, coot_batch** out);
@@ -258,9 +263,10 @@ coot_status coot_batch_launch_each(coot_batch* b, void* stream);
  * and the 2-D-tile part of the batch are tuned separately, each on its own
  * launch: every tile size (16, 32), grid multiplier (2, 4, 8, 16) and vector
  * width (128-bit where aligned, or scalar), median of 5 launches each; the
- * fastest of each part is kept and the graph re-captured.  best (may be NULL)
- * receives the flat part's settings (coot_batch_info reports both parts);
- * best_us (may be NULL) the sum of the two parts' medians. */
+ * fastest of each part is kept.  Then the whole graph is timed with the parts
+ * side by side and one after the other, and the faster is captured.  best (may
+ * be NULL) receives the flat part's settings (coot_batch_info reports both
+ * parts); best_us (may be NULL) the median time of the captured graph. */
 coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, float* best_us);
 
 /* info[0] expressions, [1] tiles, [2] algorithmic bytes (each distinct operand
@@ -268,8 +274,9 @@ coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, 
  * edge^2 elements), [4] its grid, [5] expressions on the 128-bit path,
  * [6] expressions cut into flat chunks, [7] LDS stack entries per thread,
  * [8] transposed-leaf tiles staged in LDS per workgroup, [9] tile edge of the 2-D
- * part, [10] its grid, [11] tiles of the flat part (the work-list's first). */
-coot_status coot_batch_info(const coot_batch* b, int64_t info[12]);
+ * part, [10] its grid, [11] tiles of the flat part (the work-list's first),
+ * [12] 1 if the graph runs the two parts side by side. */
+coot_status coot_batch_info(const coot_batch* b, int64_t info[13]);
 
 void coot_batch_release(coot_batch* b);
 

@@ -181,24 +181,36 @@ struct coot_batch {
   DevBuf<uint32_t> d_code, d_tiles;
   DevBuf<uint64_t> d_scal32x2;  // scalars packed as the element type
   // launch settings of the two parts: [0] flat chunks, [1] 2-D tiles
-  int ts[2] = {32, 32};             // tile edge (a flat chunk holds ts * ts elements)
-  int gm[2] = {8, 8};               // workgroups per CU
+  int ts[2] = {32, 16};             // tile edge (a flat chunk holds ts * ts elements)
+  int gm[2] = {16, 16};             // workgroups per CU
   bool allow_vec[2] = {true, true};  // 128-bit accesses where the layout allows them
   unsigned grid[2] = {1, 1};
   int nstk = 1;    // LDS stack entries: the deepest expression's registers minus the top
   int max_p1 = 0;  // most transposed leaves in one expression
   int64_t bytes = 0;
-  hipStream_t cap = nullptr;
+  bool concurrent = true;  // the graph runs the two parts side by side (fork / join)
+  hipStream_t cap = nullptr, cap2 = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   ~coot_batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (cap2) (void)hipStreamDestroy(cap2);
     if (cap) (void)hipStreamDestroy(cap);
   }
 };
 
 namespace {
+
+// each part's persistent grid: gm workgroups per CU, at most one per tile
+void set_grids(coot_batch* b) {
+  const int n_tiles = (int)(b->tiles.size() / 2);
+  const int n_part[2] = {b->n_flat_tiles, n_tiles - b->n_flat_tiles};
+  for (int p = 0; p < 2; ++p) b->grid[p] = (unsigned)std::max(1, std::min(n_part[p], b->gm[p] * num_cus()));
+}
 
 // The work-list holds the flat-chunk tiles first (one launch of the flat-only
 // interpreter), then the 2-D tiles (the general interpreter).
@@ -214,24 +226,32 @@ void build_tiles(coot_batch* b) {
     BatchExpr& e = b->ex[k];
     e.flat = b->flat_ok[k];
     const int part = e.flat ? 0 : 1, ts = b->ts[part];
-    e.tiles_r = (e.n_rows + ts - 1) / ts;
-    const int tc = (e.n_cols + ts - 1) / ts;
+    const int tr = (e.n_rows + ts - 1) / ts, tc = (e.n_cols + ts - 1) / ts;
+    e.tile_shift = 0;
+    while ((1 << e.tile_shift) < tr) ++e.tile_shift;
+    e.tile_mask = (1u << e.tile_shift) - 1u;
     e.vec4 = (b->allow_vec[part] && b->vec4_ok[k]) ? 1 : 0;
     const int begin = (int)(b->tiles.size() / 2);
     const int64_t chunk = (int64_t)ts * ts;  // flat tiles: 4 elements per thread, ts*ts/4 threads
-    const int64_t nt = e.flat ? ((int64_t)e.n_rows * e.n_cols + chunk - 1) / chunk : (int64_t)e.tiles_r * tc;
-    for (int64_t t = 0; t < nt; ++t) {
-      b->tiles.push_back((uint32_t)k);
-      b->tiles.push_back((uint32_t)t);
+    if (e.flat) {
+      const int64_t nt = ((int64_t)e.n_rows * e.n_cols + chunk - 1) / chunk;
+      for (int64_t t = 0; t < nt; ++t) {
+        b->tiles.push_back((uint32_t)k);
+        b->tiles.push_back((uint32_t)t);
+      }
+    } else {  // column-major tile order; the tile coordinates packed, no division on the device
+      for (int tj = 0; tj < tc; ++tj)
+        for (int ti = 0; ti < tr; ++ti) {
+          b->tiles.push_back((uint32_t)k);
+          b->tiles.push_back((uint32_t)ti | ((uint32_t)tj << e.tile_shift));
+        }
     }
     b->ranges[k] = {begin, (int)(b->tiles.size() / 2)};
     if (e.flat) b->n_flat_tiles = (int)(b->tiles.size() / 2);
   }
   b->d_ex.upload(b->ex);
   b->d_tiles.upload(b->tiles);
-  const int n_tiles = (int)(b->tiles.size() / 2);
-  const int n_part[2] = {b->n_flat_tiles, n_tiles - b->n_flat_tiles};
-  for (int p = 0; p < 2; ++p) b->grid[p] = (unsigned)std::max(1, std::min(n_part[p], b->gm[p] * num_cus()));
+  set_grids(b);
 }
 
 // Transposed-leaf tiles staged in LDS: as many as an expression needs (at most 4)
@@ -261,9 +281,23 @@ void launch_part(coot_batch* b, int part, hipStream_t s) {
             "batch kernel launch");
 }
 
-void launch_all(coot_batch* b, hipStream_t s) {
-  launch_part(b, 0, s);
+// Both parts, in stream order or side by side: the 2-D part (latency bound: header,
+// staging and leaf loads in a chain per tile) leaves memory bandwidth idle that the
+// flat part's workgroups use when they share the CUs.  `s2` is a second stream
+// forked from `s` (both captured into the same graph).
+void launch_all(coot_batch* b, hipStream_t s, hipStream_t s2) {
+  const int nf = b->n_flat_tiles, n = (int)(b->tiles.size() / 2);
+  if (!b->concurrent || !s2 || nf == 0 || nf == n) {
+    launch_part(b, 0, s);
+    launch_part(b, 1, s);
+    return;
+  }
+  hip_check(hipEventRecord(b->fork, s), "hipEventRecord");
+  hip_check(hipStreamWaitEvent(s2, b->fork, 0), "hipStreamWaitEvent");
   launch_part(b, 1, s);
+  launch_part(b, 0, s2);
+  hip_check(hipEventRecord(b->join, s2), "hipEventRecord");
+  hip_check(hipStreamWaitEvent(s, b->join, 0), "hipStreamWaitEvent");
 }
 
 void capture(coot_batch* b) {
@@ -272,9 +306,12 @@ void capture(coot_batch* b) {
   b->exec = nullptr;
   b->graph = nullptr;
   if (!b->cap) hip_check(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "hipStreamCreate");
+  if (!b->cap2) hip_check(hipStreamCreateWithFlags(&b->cap2, hipStreamNonBlocking), "hipStreamCreate");
+  if (!b->fork) hip_check(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming), "hipEventCreate");
+  if (!b->join) hip_check(hipEventCreateWithFlags(&b->join, hipEventDisableTiming), "hipEventCreate");
   hip_check(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
   try {
-    launch_all(b, b->cap);
+    launch_all(b, b->cap, b->cap2);
   } catch (...) {
     hipGraph_t g = nullptr;
     (void)hipStreamEndCapture(b->cap, &g);
@@ -324,11 +361,17 @@ coot_status coot_batch_create(uint32_t n, coot_expr* const* exprs, const coot_op
       infer_shape(e, ops, &R, &C);
       const coot_operand& o = outs[k];
       if (o.dtype != e.dtype || o.n_rows != R || o.n_cols != C) fail(COOT_ESHAPE, "batch output has the wrong shape or type");
-      if (R > (1 << 30) || C > (1 << 30)) fail(COOT_EUNSUPPORTED, "batch expressions are small matrices");
       BatchExpr be;
       std::memset(&be, 0, sizeof be);
       const size_t es = dtype_size(e.dtype);
       const int64_t old = o.ld ? o.ld : std::max<int64_t>(1, R);
+      // the interpreter addresses every operand as a raw buffer with 32-bit byte offsets
+      auto extent = [&](int64_t rows, int64_t cols, int64_t ld) -> uint32_t {
+        const int64_t bytes = rows > 0 && cols > 0 ? ((cols - 1) * ld + rows) * (int64_t)es : 0;
+        if (bytes >= (int64_t(1) << 31) || ld >= (int64_t(1) << 31))
+          fail(COOT_EUNSUPPORTED, "batch operands must each span less than 2 GiB");
+        return (uint32_t)bytes;
+      };
       // 2-D tiles: 4-row column segments need R, every untransposed ld and 16-byte alignment
       bool v4 = R % 4 == 0 && old % 4 == 0 && ((uintptr_t)o.data % 16) == 0;
       // flat chunks: every leaf untransposed and contiguous, like the output
@@ -336,24 +379,27 @@ coot_status coot_batch_create(uint32_t n, coot_expr* const* exprs, const coot_op
       bool aligned = ((uintptr_t)o.data % 16) == 0;
       for (size_t l = 0; l < e.leaves.size(); ++l) {
         const coot_operand& lo = ops[e.leaves[l].slot];
+        const int64_t lld = lo.ld ? lo.ld : std::max<int64_t>(1, lo.n_rows);
         be.leaf[l] = lo.data;
-        be.ld[l] = lo.ld ? lo.ld : std::max<int64_t>(1, lo.n_rows);
+        be.nrec[l] = extent(lo.n_rows, lo.n_cols, lld);
+        be.ld[l] = (uint32_t)lld;
         aligned = aligned && ((uintptr_t)lo.data % 16) == 0;
         if (e.leaves[l].parity) {
           be.p1_mask |= 1u << l;
         } else {
-          v4 = v4 && be.ld[l] % 4 == 0 && ((uintptr_t)lo.data % 16) == 0;
-          flat = flat && (be.ld[l] == lo.n_rows || lo.n_cols <= 1);
+          v4 = v4 && lld % 4 == 0 && ((uintptr_t)lo.data % 16) == 0;
+          flat = flat && (lld == lo.n_rows || lo.n_cols <= 1);
         }
         // the output may only alias an operand read untransposed with its own layout
         const char* ob = (const char*)o.data;
         const char* lb = (const char*)lo.data;
-        if (R * C > 0 && lb == ob && (e.leaves[l].parity || be.ld[l] != old))
+        if (R * C > 0 && lb == ob && (e.leaves[l].parity || lld != old))
           fail(COOT_EALIAS, "batch output aliases a transposed or differently laid out operand");
       }
       if (flat) v4 = aligned;
       be.out = o.data;
-      be.out_ld = old;
+      be.out_nrec = extent(R, C, old);
+      be.out_ld = (uint32_t)old;
       be.n_rows = (int32_t)R;
       be.n_cols = (int32_t)C;
       be.n_leaves = (int32_t)e.leaves.size();
@@ -428,6 +474,22 @@ coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, 
     hip_check(hipEventCreate(&e0), "hipEventCreate");
     hip_check(hipEventCreate(&e1), "hipEventCreate");
     float total = 0;
+    // median of 5 timed runs of fn (after one warm-up run)
+    auto median_ms = [&](auto&& fn) {
+      fn();
+      std::vector<float> t_ms;
+      for (int rep = 0; rep < 5; ++rep) {
+        hip_check(hipEventRecord(e0, s), "hipEventRecord");
+        fn();
+        hip_check(hipEventRecord(e1, s), "hipEventRecord");
+        hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0;
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        t_ms.push_back(ms);
+      }
+      std::sort(t_ms.begin(), t_ms.end());
+      return t_ms[2];
+    };
     try {
       // each part is tuned on its own launch (the other part's settings do not affect it)
       for (int part = 0; part < 2; ++part) {
@@ -435,26 +497,16 @@ coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, 
         int bts = b->ts[part], bgm = b->gm[part];
         bool bvec = b->allow_vec[part];
         for (int ts : {16, 32}) {
-          for (int gm : {2, 4, 8, 16}) {
-            for (bool vec : {true, false}) {
-              b->ts[part] = ts;
+          for (bool vec : {true, false}) {
+            b->ts[part] = ts;
+            b->allow_vec[part] = vec;
+            build_tiles(b);
+            for (int gm : {2, 4, 8, 16}) {
               b->gm[part] = gm;
-              b->allow_vec[part] = vec;
-              build_tiles(b);
-              launch_part(b, part, s);  // warm-up
-              std::vector<float> t_ms;
-              for (int rep = 0; rep < 5; ++rep) {
-                hip_check(hipEventRecord(e0, s), "hipEventRecord");
-                launch_part(b, part, s);
-                hip_check(hipEventRecord(e1, s), "hipEventRecord");
-                hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
-                float ms = 0;
-                hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-                t_ms.push_back(ms);
-              }
-              std::sort(t_ms.begin(), t_ms.end());
-              if (t_ms[2] < bt) {
-                bt = t_ms[2];
+              set_grids(b);
+              const float t = median_ms([&] { launch_part(b, part, s); });
+              if (t < bt) {
+                bt = t;
                 bts = ts;
                 bgm = gm;
                 bvec = vec;
@@ -465,8 +517,21 @@ coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, 
         b->ts[part] = bts;
         b->gm[part] = bgm;
         b->allow_vec[part] = bvec;
-        total += bt;
       }
+      // then the graph: the parts side by side or one after the other, the faster
+      build_tiles(b);
+      bool best_c = true;
+      total = 1e30f;
+      for (bool c : {true, false}) {
+        b->concurrent = c;
+        capture(b);
+        const float t = median_ms([&] { hip_check(hipGraphLaunch(b->exec, s), "hipGraphLaunch"); });
+        if (t < total) {
+          total = t;
+          best_c = c;
+        }
+      }
+      b->concurrent = best_c;
     } catch (...) {
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
@@ -474,7 +539,6 @@ coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, 
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    build_tiles(b);
     capture(b);
     if (best) {  // the flat part's settings (coot_batch_info reports both parts)
       best->vec = b->allow_vec[0] ? 4 : 1;
@@ -486,7 +550,7 @@ coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, 
   });
 }
 
-coot_status coot_batch_info(const coot_batch* b, int64_t info[12]) {
+coot_status coot_batch_info(const coot_batch* b, int64_t info[13]) {
   return guarded([&] {
     if (!b || !info) fail(COOT_EINVAL, "NULL argument");
     info[0] = (int64_t)b->ex.size();
@@ -497,6 +561,7 @@ coot_status coot_batch_info(const coot_batch* b, int64_t info[12]) {
     info[9] = b->ts[1];
     info[10] = b->grid[1];
     info[11] = b->n_flat_tiles;
+    info[12] = b->concurrent ? 1 : 0;
     int64_t v4 = 0, fl = 0;
     for (auto& e : b->ex) {
       v4 += e.vec4;

@@ -21,21 +21,27 @@ enum : uint32_t {
 
 inline constexpr uint32_t encode(uint32_t op, uint32_t reg, uint32_t arg) { return op | (reg << 6) | (arg << 9); }
 
-// One expression of a batch (device memory, 16-byte aligned records).
+// One expression of a batch (device memory, 256-byte records).  Every leaf and the
+// output are addressed as raw buffers: offsets are 32-bit byte offsets below the
+// operand's extent `nrec`, which the host keeps under 2^31 bytes.
 struct BatchExpr {
   const void* leaf[COOT_BATCH_MAXL];  // leaf k: base pointer of its operand
-  int64_t ld[COOT_BATCH_MAXL];        // leading dimension of leaf k's operand
+  uint32_t ld[COOT_BATCH_MAXL];       // leading dimension of leaf k's operand (elements)
+  uint32_t nrec[COOT_BATCH_MAXL];     // bytes of leaf k's operand from leaf[k] on (its buffer range)
   void* out;
-  int64_t out_ld;
+  uint32_t out_ld, out_nrec;          // output leading dimension (elements) and extent (bytes)
   int32_t n_rows, n_cols;             // output dimensions
-  int32_t tiles_r;                    // ceil(n_rows / TS)
+  int32_t tile_shift;                 // 2-D tile number = ti | tj << tile_shift
+  uint32_t tile_mask;                 // (1 << tile_shift) - 1
   int32_t code_off, code_len;         // bytecode range
   int32_t sc_off;                     // first scalar
   uint32_t p1_mask;                   // bit k: leaf k is read transposed
   int32_t vec4;                       // 1: 128-bit accesses are valid
   int32_t flat;                       // 1: untransposed contiguous leaves and output: flat chunks
   int32_t n_leaves;                   // leaves used (leaf[0 .. n_leaves))
+  int32_t pad_;
 };
+static_assert(sizeof(BatchExpr) == 256, "BatchExpr is a 256-byte record");
 
 }  // namespace batch
 }  // namespace coot

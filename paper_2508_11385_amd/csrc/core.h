@@ -154,7 +154,8 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
                   const coot_operand& out, const coot_launch_cfg* cfg, hipStream_t s);
 // The library's launch configuration for a family when the caller gives none
 // (fields 0 there are filled from it); waves and ept are 0/unused where fixed.
-coot_launch_cfg default_cfg(int fam, int mode, int dim, int dtype);
+constexpr int64_t kStreamElems = int64_t(1) << 24;  // larger flat launches take the streaming defaults
+coot_launch_cfg default_cfg(int fam, int mode, int dim, int dtype, int64_t n);
 Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, int mode, int dim, bool comp,
              const coot_launch_cfg* cfg);
 

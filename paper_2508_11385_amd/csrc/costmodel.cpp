@@ -510,7 +510,9 @@ coot_status coot_tune(coot_expr* h, const coot_operand* operands, const double* 
     coot_tune_space(fam, space.data(), (uint32_t)space.size());
     std::vector<coot_launch_cfg> cand;
     if (policy == 0) {
-      coot_launch_cfg d = default_cfg(fam == 0 ? FAM_FLAT : FAM_TILE, mode, -1, h->e->dtype);
+      int64_t R, C;
+      infer_shape(*h->e, operands, &R, &C);
+      coot_launch_cfg d = default_cfg(fam == 0 ? FAM_FLAT : FAM_TILE, mode, -1, h->e->dtype, R * C);
       if (!d.ept) d.ept = 1;  // the tiled family's configurations carry ept 1
       cand.push_back(d);
     } else if (policy == 1) {

@@ -162,15 +162,23 @@ static bool aligned(const void* p, size_t bytes) { return ((uintptr_t)p % bytes)
 //   flat family:   16-byte groups, 1 group per thread per trip, 4 waves, 4 workgroups per CU
 //   tiled family:  2-element groups, 4 waves (fixed), 8 workgroups per CU
 //   dimension sums: 16-byte groups (one workgroup per segment)
-coot_launch_cfg default_cfg(int fam, int mode, int dim, int dtype) {
+coot_launch_cfg default_cfg(int fam, int mode, int dim, int dtype, int64_t n) {
   const uint16_t v16 = dtype == COOT_F64 ? 2 : 4;
   if (mode == COOT_RED_SUM && dim >= 0) return {v16, 0, 4, 8};
-  if (fam == FAM_FLAT) return {v16, 1, 4, 4};
+  if (fam == FAM_FLAT) {
+    // Past 2^24 elements (the streaming regime) fewer, longer-lived workgroups win:
+    // the best geomean over the largest signatures of the autotuner's timing tables.
+    if (n > kStreamElems) {
+      if (mode < 0) return {v16, 1, 4, 2};
+      return dtype == COOT_F64 ? coot_launch_cfg{2, 4, 8, 8} : coot_launch_cfg{4, 4, 4, 2};
+    }
+    return {v16, 1, 4, 4};
+  }
   return {2, 0, 4, 8};
 }
 
-coot_launch_cfg resolve_cfg(const coot_launch_cfg* cfg, int fam, int mode, int dim, int dtype) {
-  coot_launch_cfg c = default_cfg(fam, mode, dim, dtype);
+coot_launch_cfg resolve_cfg(const coot_launch_cfg* cfg, int fam, int mode, int dim, int dtype, int64_t n) {
+  coot_launch_cfg c = default_cfg(fam, mode, dim, dtype, n);
   if (cfg) {
     if (cfg->vec) c.vec = cfg->vec;
     if (cfg->ept) c.ept = cfg->ept;
@@ -191,7 +199,9 @@ Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, in
     if (!contiguous(ops[l.slot])) flat = false;
   if (mode < 0 && out && !contiguous(*out)) flat = false;
   rq.fam = flat ? FAM_FLAT : FAM_TILE;
-  const coot_launch_cfg c = resolve_cfg(cfg, rq.fam, mode, dim, e.dtype);
+  int64_t R = 0, C = 0;
+  infer_shape(e, ops, &R, &C);
+  const coot_launch_cfg c = resolve_cfg(cfg, rq.fam, mode, dim, e.dtype, R * C);
   rq.var.vec = c.vec;
   rq.var.ept = c.ept ? c.ept : 1;
   if (rq.var.vec != 1 && rq.var.vec != 2 && rq.var.vec != 4) fail(COOT_EINVAL, "vec must be 1, 2 or 4");
@@ -295,7 +305,7 @@ void eval_fused(Expr& e, const coot_operand* ops, const double* scalars, const c
   const bool v = vec_ok(e, rq, ops, &out, R, C);
   const std::string& kn = (v || rq.var.vec == 1) ? m->names.stage1 : m->names.stage1_fallback;
   hipFunction_t f = m->fn(kn);
-  const coot_launch_cfg c = resolve_cfg(cfg, rq.fam, -1, -1, e.dtype);
+  const coot_launch_cfg c = resolve_cfg(cfg, rq.fam, -1, -1, e.dtype, R * C);
   if (rq.fam == FAM_FLAT) {
     const int bs = 64 * c.waves;
     launch(f, flat_grid(R * C, v ? rq.var.vec : 1, rq.var.ept, bs, c.grid_mult), bs, a, s);
@@ -339,7 +349,7 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
   const bool v = vec_ok(e, rq, ops, nullptr, R, C);
   const std::string& kn = (v || rq.var.vec == 1) ? m->names.stage1 : m->names.stage1_fallback;
   const size_t es = dtype_size(e.dtype);
-  const coot_launch_cfg c = resolve_cfg(cfg, rq.fam, mode, kind == COOT_RED_SUM ? dim : -1, e.dtype);
+  const coot_launch_cfg c = resolve_cfg(cfg, rq.fam, mode, kind == COOT_RED_SUM ? dim : -1, e.dtype, R * C);
   if (kind == COOT_RED_SUM) {
     const int ts = rq.var.ts;
     const int64_t tr = (R + ts - 1) / ts, tc = (C + ts - 1) / ts;

@@ -98,6 +98,68 @@ __device__ __forceinline__ void apply_un(u32 op, T (&acc)[4]) {
 constexpr int kMaxStaged = 4;  // transposed leaves staged in LDS per tile (at most)
 constexpr int kXcds = 8;       // accelerator complex dies of an MI355X, each with its own L2
 
+// Raw buffer access.  Every leaf and every output is addressed through a buffer
+// resource whose range is the operand's extent (under 2^31 bytes).  A lane that
+// must not touch memory (an element past the matrix edge) passes an offset beyond
+// every range: the hardware returns 0 for such a load and drops such a store, so
+// no access needs a per-lane branch (exec-mask save and restore) around it.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // gfx9 raw buffer descriptor: 32-bit data format, no swizzle
+constexpr int kStoreNt = 2;             // cache policy of result stores: non-temporal
+
+// byte offset o (below 2^31) if the lane's element exists, else an offset outside
+// every range (bit 31 set), without a branch
+__device__ __forceinline__ u32 masked(u32 o, bool in) { return o | ((u32)!in << 31); }
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void* p, u32 bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kRsrcWord3);
+}
+
+template <typename T> struct Buf;
+template <> struct Buf<float> {
+  static __device__ __forceinline__ float ld1(rsrc_t r, u32 off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  }
+  static __device__ __forceinline__ vt<float, 4> ld4(rsrc_t r, u32 off) {
+    // (copied whole: a bit cast of one element of a vector value reads element 0)
+    const u32x4 q = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    vt<float, 4> g;
+    __builtin_memcpy(&g, &q, 16);
+    return g;
+  }
+  static __device__ __forceinline__ void st1(rsrc_t r, u32 off, float x) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(u32, x), r, off, 0, kStoreNt);
+  }
+  static __device__ __forceinline__ void st4(rsrc_t r, u32 off, const float (&x)[4]) {
+    u32x4 q;
+    __builtin_memcpy(&q, x, 16);
+    __builtin_amdgcn_raw_buffer_store_b128(q, r, off, 0, kStoreNt);
+  }
+};
+template <> struct Buf<double> {
+  static __device__ __forceinline__ double ld1(rsrc_t r, u32 off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+  }
+  static __device__ __forceinline__ vt<double, 4> ld4(rsrc_t r, u32 off) {
+    const u32x4 q0 = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    const u32x4 q1 = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16u, 0, 0);
+    vt<double, 4> g;
+    __builtin_memcpy(&g.v[0], &q0, 16);
+    __builtin_memcpy(&g.v[2], &q1, 16);
+    return g;
+  }
+  static __device__ __forceinline__ void st1(rsrc_t r, u32 off, double x) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, off, 0, kStoreNt);
+  }
+  static __device__ __forceinline__ void st4(rsrc_t r, u32 off, const double (&x)[4]) {
+    u32x4 q0, q1;
+    __builtin_memcpy(&q0, &x[0], 16);
+    __builtin_memcpy(&q1, &x[2], 16);
+    __builtin_amdgcn_raw_buffer_store_b128(q0, r, off, 0, kStoreNt);
+    __builtin_amdgcn_raw_buffer_store_b128(q1, r, off + 16u, 0, kStoreNt);
+  }
+};
+
 // untransposed leaves loaded before the bytecode runs (2-D tiles also hold their
 // staged transposed leaves in registers, so they prefetch fewer)
 template <typename T, bool FLAT> struct Prefetch {
@@ -106,12 +168,14 @@ template <typename T, bool FLAT> struct Prefetch {
 
 // FLAT: the tile range holds flat chunks only (no staging, no 2-D index maps: fewer
 // registers, more waves per SIMD); otherwise 2-D tiles only.
+// (fp32 flat chunks fit 64 registers: 8 waves per SIMD)
 template <typename T, int TS, bool FLAT>
-__global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restrict__ ex, const u32* __restrict__ tiles,
+__global__ __launch_bounds__(TS * TS / 4) __attribute__((amdgpu_waves_per_eu(FLAT && sizeof(T) == 4 ? 8 : 1))) void interp(const BatchExpr* __restrict__ ex, const u32* __restrict__ tiles,
                                                       int t_begin, int t_end, const u32* __restrict__ code,
                                                       const T* __restrict__ scal, int nstk, int np1) {
   constexpr int NT = TS * TS / 4;  // threads: 4 elements each
   constexpr int PF = Prefetch<T, FLAT>::N;
+  constexpr u32 ES = sizeof(T);
   extern __shared__ __align__(16) unsigned char smem[];
   vt<T, 4>* stk = reinterpret_cast<vt<T, 4>*>(smem);                              // [nstk][NT]
   T* stage = reinterpret_cast<T*>(smem + (size_t)nstk * NT * sizeof(vt<T, 4>));  // [np1][TS][TS + 1]
@@ -127,23 +191,24 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
     const u32 eid = tiles[2 * t], tin = tiles[2 * t + 1];
     const BatchExpr& e = ex[eid];
     const int R = e.n_rows, C = e.n_cols;
-    constexpr bool flat = FLAT;
     const bool v4 = e.vec4 != 0;
     const u32 p1 = e.p1_mask;
+    // this thread's 4 elements: rows iq[q], columns jq[q] (2-D) or flat indices fbase + q
     int iq[4], jq[4];
     bool in[4];
     vt<T, 4> sv[kMaxStaged];
-    i64 fbase = 0;
+    u32 fbase = 0;
+    bool full = false;  // flat: every element of the chunk exists (uniform)
     int i0 = 0, j0 = 0;
     if constexpr (FLAT) {
-      const i64 n = (i64)R * C;
-      fbase = (i64)tin * (4 * NT) + 4 * tid;
+      const u32 n = (u32)R * (u32)C, tb = tin * (u32)(4 * NT);
+      fbase = tb + 4u * (u32)tid;
+      full = tb + (u32)(4 * NT) <= n;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) in[q] = fbase + q < n;
+      for (int q = 0; q < 4; ++q) in[q] = fbase + (u32)q < n;
     } else {
-      const int ti = (int)(tin % (u32)e.tiles_r), tj = (int)(tin / (u32)e.tiles_r);
-      i0 = ti * TS;
-      j0 = tj * TS;
+      i0 = (int)(tin & e.tile_mask) * TS;
+      j0 = (int)(tin >> e.tile_shift) * TS;
       if (v4) {
         const int lc = tid % (TS / 4), lr = tid / (TS / 4);
 #pragma unroll
@@ -170,45 +235,38 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
           if (sl < np1 && rest != 0u) {
             const int k = __builtin_ctz(rest);
             rest &= rest - 1u;
-            const T* src = (const T*)e.leaf[k];
-            const i64 ld = e.ld[k];
+            const rsrc_t r = make_rsrc(e.leaf[k], e.nrec[k]);
+            const u32 ld = e.ld[k];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-              const int idx = tid + q * NT, sc = idx % TS, il = idx / TS;
-              const int i = i0 + il, j = j0 + sc;
-              sv[sl].v[q] = (i < R && j < C) ? src[(i64)j + (i64)i * ld] : (T)0;
+              const int idx = tid + q * NT, i = i0 + idx / TS, j = j0 + idx % TS;
+              sv[sl].v[q] = Buf<T>::ld1(r, masked(((u32)j + (u32)i * ld) * ES, i < R && j < C));
             }
           }
         }
       }
     }
-    const bool all_in = in[0] && in[1] && in[2] && in[3];
     // an untransposed leaf's 4 values for this thread (flat chunk or 2-D tile layout)
     auto load_direct = [&](int k) __attribute__((always_inline)) {
-      vt<T, 4> g;
-      const T* src = (const T*)e.leaf[k];
-      if (flat) {
-        if (v4 && all_in) {
-          g = ldv<T, 4>(src + fbase);
+      vt<T, 4> v;
+      const rsrc_t r = make_rsrc(e.leaf[k], e.nrec[k]);
+      if (FLAT) {
+        if (v4 && full) {
+          v = Buf<T>::ld4(r, fbase * ES);
         } else {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) g.v[q] = in[q] ? src[fbase + q] : (T)0;
+          for (int q = 0; q < 4; ++q) v.v[q] = Buf<T>::ld1(r, masked((fbase + (u32)q) * ES, in[q]));
         }
       } else {
-        const i64 ld = e.ld[k];
+        const u32 ld = e.ld[k];
         if (v4) {
-          if (in[0]) {
-            g = ldv<T, 4>(src + (i64)iq[0] + (i64)jq[0] * ld);
-          } else {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) g.v[q] = (T)0;
-          }
+          v = Buf<T>::ld4(r, masked(((u32)iq[0] + (u32)jq[0] * ld) * ES, in[0]));
         } else {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) g.v[q] = in[q] ? src[(i64)iq[q] + (i64)jq[q] * ld] : (T)0;
+          for (int q = 0; q < 4; ++q) v.v[q] = Buf<T>::ld1(r, masked(((u32)iq[q] + (u32)jq[q] * ld) * ES, in[q]));
         }
       }
-      return g;
+      return v;
     };
     // the first PF untransposed leaves are loaded up front, all in flight together,
     // instead of one round trip per LEAF instruction
@@ -217,34 +275,35 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
 #pragma unroll
     for (int k = 0; k < PF; ++k)
       if (k < e.n_leaves && !((p1 >> k) & 1u)) {
-        const vt<T, 4> g = load_direct(k);
+        const vt<T, 4> v = load_direct(k);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) pf[4 * k + q] = g.v[q];
+        for (int q = 0; q < 4; ++q) pf[4 * k + q] = v.v[q];
       }
-    // value of leaf k for this thread's 4 elements
+    // value of leaf k for this thread's 4 elements (lanes past the edge hold 0 or a
+    // value that is never stored)
     auto fetch_leaf = [&](u32 k) __attribute__((always_inline)) {
-      vt<T, 4> g;
+      vt<T, 4> v;
       if (!FLAT && ((p1 >> k) & 1u)) {
         // transposed leaf: staged in LDS (slot = staged leaves before it) or read directly
         const int slot = __builtin_popcount(p1 & ((1u << k) - 1u));
         if (slot < np1) {
           const T* st = stage + slot * TS * (TS + 1);
 #pragma unroll
-          for (int q = 0; q < 4; ++q) g.v[q] = in[q] ? st[(iq[q] - i0) * (TS + 1) + (jq[q] - j0)] : (T)0;
+          for (int q = 0; q < 4; ++q) v.v[q] = st[(iq[q] - i0) * (TS + 1) + (jq[q] - j0)];
         } else {
-          const T* src = (const T*)e.leaf[k];
-          const i64 ld = e.ld[k];
+          const rsrc_t r = make_rsrc(e.leaf[k], e.nrec[k]);
+          const u32 ld = e.ld[k];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) g.v[q] = in[q] ? src[(i64)jq[q] + (i64)iq[q] * ld] : (T)0;
+          for (int q = 0; q < 4; ++q) v.v[q] = Buf<T>::ld1(r, masked(((u32)jq[q] + (u32)iq[q] * ld) * ES, in[q]));
         }
       } else if ((int)k < PF) {
         // wave-uniform index into a register vector
 #pragma unroll
-        for (int q = 0; q < 4; ++q) g.v[q] = pf[4 * (int)k + q];
+        for (int q = 0; q < 4; ++q) v.v[q] = pf[4 * (int)k + q];
       } else {
-        g = load_direct((int)k);
+        v = load_direct((int)k);
       }
-      return g;
+      return v;
     };
     if (!FLAT && p1 && np1 > 0) {
       __syncthreads();  // the previous tile's reads of the staging area are done
@@ -271,9 +330,9 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
         // binary op with a leaf or scalar operand taken directly
         vt<T, 4> x;
         if (op >= OP_WITH_SCAL) {
-          const T sv = scal[e.sc_off + (int)arg];
+          const T s = scal[e.sc_off + (int)arg];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) x.v[q] = sv;
+          for (int q = 0; q < 4; ++q) x.v[q] = s;
         } else {
           x = fetch_leaf(arg);
         }
@@ -286,13 +345,13 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
           stk[(b - 1) * NT + tid] = s;
         }
         if (op == OP_SCAL) {
-          const T sv = scal[e.sc_off + (int)arg];
+          const T s = scal[e.sc_off + (int)arg];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) acc[q] = sv;
+          for (int q = 0; q < 4; ++q) acc[q] = s;
         } else {
-          const vt<T, 4> g = fetch_leaf(arg);
+          const vt<T, 4> v = fetch_leaf(arg);
 #pragma unroll
-          for (int q = 0; q < 4; ++q) acc[q] = g.v[q];
+          for (int q = 0; q < 4; ++q) acc[q] = v.v[q];
         }
       } else if (op <= OP_RDIV) {
         // r[b] = op(r[b], r[b+1]): r[b] from the LDS stack, r[b+1] the top
@@ -308,31 +367,21 @@ __global__ __launch_bounds__(TS * TS / 4) void interp(const BatchExpr* __restric
         apply_un<T>(op, acc);
       }
     }
-    T* out = (T*)e.out;
-    if (flat) {
-      if (v4 && all_in) {
-        vt<T, 4> g;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) g.v[q] = acc[q];
-        stv<T, 4>(out + fbase, g);
+    const rsrc_t ro = make_rsrc(e.out, e.out_nrec);
+    if (FLAT) {
+      if (v4 && full) {
+        Buf<T>::st4(ro, fbase * ES, acc);
       } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (in[q]) out[fbase + q] = acc[q];
+        for (int q = 0; q < 4; ++q) Buf<T>::st1(ro, masked((fbase + (u32)q) * ES, in[q]), acc[q]);
       }
     } else {
-      const i64 old = e.out_ld;
+      const u32 old = e.out_ld;
       if (v4) {
-        if (in[0]) {
-          vt<T, 4> g;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) g.v[q] = acc[q];
-          stv<T, 4>(out + (i64)iq[0] + (i64)jq[0] * old, g);
-        }
+        Buf<T>::st4(ro, masked(((u32)iq[0] + (u32)jq[0] * old) * ES, in[0]), acc);
       } else {
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (in[q]) out[(i64)iq[q] + (i64)jq[q] * old] = acc[q];
+        for (int q = 0; q < 4; ++q) Buf<T>::st1(ro, masked(((u32)iq[q] + (u32)jq[q] * old) * ES, in[q]), acc[q]);
       }
     }
   }

@@ -128,10 +128,20 @@ def _valid(t):
     return np.flatnonzero(np.isfinite(t) & (t > 0))
 
 
-def default_index(cfgs, dtype, t=None):
-    """What coot_expr_eval launches without a tuner: the default configuration, or, when
-    the operands do not allow its vector width (t[k] NaN), the same with scalar accesses."""
-    want = (2 if dtype == "f64" else 4, 1, 4, 4) if len(cfgs) > 12 else (2, 1, 4, 8)
+STREAM_ELEMS = 1 << 24  # flat launches past this many elements take the library's streaming defaults
+
+
+def default_index(cfgs, dtype, t=None, n=0, mode=-1):
+    """What the library launches without a tuner for n elements in this mode (-1
+    element-wise, else a full reduction): the default configuration, or, when the operands
+    do not allow its vector width (t[k] NaN), the same with scalar accesses."""
+    v = 2 if dtype == "f64" else 4
+    if len(cfgs) <= 12:
+        want = (2, 1, 4, 8)
+    elif n > STREAM_ELEMS:
+        want = (v, 1, 4, 2) if mode < 0 else ((2, 4, 8, 8) if dtype == "f64" else (4, 4, 4, 2))
+    else:
+        want = (v, 1, 4, 4)
     k = cfgs.index(want)
     if t is not None and not np.isfinite(t[k]):
         k = cfgs.index((1,) + want[1:])
@@ -151,7 +161,7 @@ def dataset(sigs, handles, tables, configs_per_sig=None, seed=0):
         ok = _valid(t)
         if ok.size == 0:
             continue
-        d = default_index(cfgs, spec.dtype, t)
+        d = default_index(cfgs, spec.dtype, t, spec.out_shape[0] * spec.out_shape[1], mode)
         ref = math.log(t[d]) if d in ok else float(np.mean(np.log(t[ok])))
         if configs_per_sig is None or configs_per_sig >= ok.size:
             pick = ok
@@ -189,7 +199,7 @@ def picks(cm, sigs, handles, tables):
         k, _ = cc.coot_costmodel_predict(cm, h, spec.out_shape[0], spec.out_shape[1], 0 if mode < 0 else 1,
                                          [cfgs[i] for i in ok])
         t_pred += time.perf_counter() - t0
-        out.append((exh, int(ok[k]), default_index(cfgs, spec.dtype, t)))
+        out.append((exh, int(ok[k]), default_index(cfgs, spec.dtype, t, spec.out_shape[0] * spec.out_shape[1], mode)))
     return np.asarray(out, np.int64), t_pred / max(1, len(sigs))
 
 

@@ -112,7 +112,7 @@ def test_per_expression_launches_and_tuning_agree(coot):
         assert np.array_equal(r, o.numpy())
 
 
-@pytest.mark.parametrize("cfg", [(1, 4, 1, 2), (4, 4, 4, 8), (4, 4, 1, 4), (1, 4, 4, 16)])
+@pytest.mark.parametrize("cfg", [(1, 1, 1, 2), (4, 2, 4, 8), (4, 8, 1, 4), (1, 4, 4, 16)])
 def test_every_tile_size_and_vector_width(coot, cfg):
     import torch
     specs, host, exprs = _make(coot, 40, 45, lo=1, hi=200)
@@ -150,6 +150,15 @@ def test_batch_errors(coot):
     with pytest.raises(cc.CootError) as e:
         coot.Batch([(coot.trans(S) + 1.0, S)])
     assert e.value.status == cc.COOT_EALIAS
+    # an operand spanning 2 GiB or more (its two columns 2^29 floats apart): the interpreter's
+    # 32-bit buffer offsets cannot reach it
+    import torch
+    big = torch.empty(2**29 + 64, dtype=torch.float32, device="cuda")
+    W = coot.Mat(big.as_strided((4, 2), (1, 2**29)), "f32")
+    with pytest.raises(cc.CootError) as e:
+        coot.Batch([(W + 1.0, None)])
+    assert e.value.status == cc.COOT_EUNSUPPORTED
+    del W, big
 
 
 def test_full_batch_workload_sampled(coot):
