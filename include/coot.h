@@ -231,8 +231,8 @@ coot_status coot_expr_kernel_name(coot_expr* e, int32_t mode, int32_t dim, const
  *   operands[n][...]    each expression's device operands (n_slots of it)
  *   scalars[n][...]     each expression's scalars (host, copied)
  *   outs[n]             caller-allocated device outputs with the inferred dims
- *   cfg                 NULL = default (flat chunks of 32 x 32 elements, 2-D tiles
- *                       of 16 x 16, vectorised where aligned, 16 workgroups per
+ *   cfg                 NULL = default (flat chunks and 2-D tiles of 32 x 32
+ *                       elements, vectorised where aligned, 16 workgroups per
  *                       CU); else waves 1 / 4
  *                       selects tiles of 16 x 16 / 32 x 32 elements (4 per thread),
  *                       vec = 1 forbids 128-bit accesses, grid_mult sets

@@ -181,7 +181,7 @@ struct coot_batch {
   DevBuf<uint32_t> d_code, d_tiles;
   DevBuf<uint64_t> d_scal32x2;  // scalars packed as the element type
   // launch settings of the two parts: [0] flat chunks, [1] 2-D tiles
-  int ts[2] = {32, 16};             // tile edge (a flat chunk holds ts * ts elements)
+  int ts[2] = {32, 32};             // tile edge (a flat chunk holds ts * ts elements)
   int gm[2] = {16, 16};             // workgroups per CU
   bool allow_vec[2] = {true, true};  // 128-bit accesses where the layout allows them
   unsigned grid[2] = {1, 1};
@@ -254,18 +254,19 @@ void build_tiles(coot_batch* b) {
   set_grids(b);
 }
 
-// Transposed-leaf tiles staged in LDS: as many as an expression needs (at most 4)
-// while the workgroup's LDS stays within 32 KB (several workgroups per CU), and
-// always within the 64 KB a workgroup may hold (2 KB of it hold the exp table);
-// the rest are read directly.
+// Transposed-leaf tiles staged in LDS: as many as an expression needs (at most 4 on
+// one-wave 16 x 16 tiles, staged by LDS DMA; 2 on 32 x 32 tiles, staged through
+// registers) while the workgroup's LDS stays within 32 KB (several workgroups per
+// CU), and always within the 64 KB a workgroup may hold (2 KB of it hold the exp
+// table); the rest are read directly.
 constexpr size_t kMaxDynLds = 65536 - 2048;
 int staged_tiles(const coot_batch* b) {
   const size_t es = b->dtype == COOT_BATCH_F32 ? 4 : 8;
   const int ts = b->ts[1];
   const size_t stack = (size_t)b->nstk * (ts * ts / 4) * 4 * es;
-  const size_t slot = (size_t)ts * (ts + 1) * es;
+  const size_t slot = (size_t)ts * (ts == 16 ? ts : ts + 1) * es;  // as the kernel lays them out
   const size_t budget = std::max<size_t>(32768, stack + slot);
-  size_t n = std::min<size_t>({(size_t)b->max_p1, 4, budget > stack ? (budget - stack) / slot : 0});
+  size_t n = std::min<size_t>({(size_t)b->max_p1, ts == 16 ? 4u : 2u, budget > stack ? (budget - stack) / slot : 0});
   while (n > 0 && stack + n * slot > kMaxDynLds) --n;
   return (int)n;
 }

@@ -95,7 +95,9 @@ __device__ __forceinline__ void apply_un(u32 op, T (&acc)[4]) {
   }
 }
 
-constexpr int kMaxStaged = 4;  // transposed leaves staged in LDS per tile (at most)
+// transposed leaves staged in LDS per tile (at most): 4 by LDS DMA on one-wave tiles,
+// 2 through registers on larger ones (each costs 4 registers per thread in flight)
+template <int NT> struct Staged { static constexpr int N = NT == 64 ? 4 : 2; };
 constexpr int kXcds = 8;       // accelerator complex dies of an MI355X, each with its own L2
 
 // Raw buffer access.  Every leaf and every output is addressed through a buffer
@@ -176,6 +178,14 @@ __global__ __launch_bounds__(TS * TS / 4) __attribute__((amdgpu_waves_per_eu(FLA
   constexpr int NT = TS * TS / 4;  // threads: 4 elements each
   constexpr int PF = Prefetch<T, FLAT>::N;
   constexpr u32 ES = sizeof(T);
+  // One-wave 2-D tiles stage their transposed leaves by LDS DMA (buffer loads that
+  // write LDS directly): no registers hold them in flight and, the wave being alone
+  // in its workgroup, no barrier orders the staging area.  Slot layout: element
+  // (row il, column sc) of the tile at il * TS + ((sc + il) mod TS), the rotation
+  // spreading a column's reads over the LDS banks.  Larger tiles stage through
+  // registers into a padded [TS][TS + 1] layout between two barriers.
+  constexpr bool DMA = !FLAT && NT == 64;
+  constexpr int kMaxStaged = Staged<NT>::N;
   extern __shared__ __align__(16) unsigned char smem[];
   vt<T, 4>* stk = reinterpret_cast<vt<T, 4>*>(smem);                              // [nstk][NT]
   T* stage = reinterpret_cast<T*>(smem + (size_t)nstk * NT * sizeof(vt<T, 4>));  // [np1][TS][TS + 1]
@@ -228,7 +238,30 @@ __global__ __launch_bounds__(TS * TS / 4) __attribute__((amdgpu_waves_per_eu(FLA
       for (int q = 0; q < 4; ++q) in[q] = iq[q] < R && jq[q] < C;
       // staged transposed leaves: this thread's 4 values of each (element idx = tid + q * NT
       // of the tile, read along the leaf's contiguous dimension), loads issued together
-      if (p1 && np1 > 0) {
+      if (DMA && p1 && np1 > 0) {
+        // (the previous tile's reads of the staging area are complete: their values were used)
+        constexpr int W = sizeof(T) / 4;  // dwords per element
+        u32 rest = p1;
+#pragma unroll
+        for (int sl = 0; sl < kMaxStaged; ++sl) {
+          if (sl < np1 && rest != 0u) {
+            const int k = __builtin_ctz(rest);
+            rest &= rest - 1u;
+            const rsrc_t r = make_rsrc(e.leaf[k], e.nrec[k]);
+            const u32 ld = e.ld[k];
+#pragma unroll
+            for (int q = 0; q < 4 * W; ++q) {
+              // dword p = q * 64 + lane of the slot: element p / W (its half p % W)
+              const int el = (q * 64 + tid) / W, half = (q * 64 + tid) % W;
+              const int il = el / TS, sc = (el % TS - il) & (TS - 1);
+              const int i = i0 + il, j = j0 + sc;
+              const u32 off = masked(((u32)j + (u32)i * ld) * ES + 4u * (u32)half, i < R && j < C);
+              __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                  r, (__attribute__((address_space(3))) void*)(stage + sl * TS * TS + q * 64 / W), 4, off, 0, 0, 0);
+            }
+          }
+        }
+      } else if (p1 && np1 > 0) {
         u32 rest = p1;
 #pragma unroll
         for (int sl = 0; sl < kMaxStaged; ++sl) {
@@ -286,7 +319,14 @@ __global__ __launch_bounds__(TS * TS / 4) __attribute__((amdgpu_waves_per_eu(FLA
       if (!FLAT && ((p1 >> k) & 1u)) {
         // transposed leaf: staged in LDS (slot = staged leaves before it) or read directly
         const int slot = __builtin_popcount(p1 & ((1u << k) - 1u));
-        if (slot < np1) {
+        if (slot < np1 && DMA) {
+          const T* st = stage + slot * TS * TS;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int il = iq[q] - i0;
+            v.v[q] = st[il * TS + ((jq[q] - j0 + il) & (TS - 1))];
+          }
+        } else if (slot < np1) {
           const T* st = stage + slot * TS * (TS + 1);
 #pragma unroll
           for (int q = 0; q < 4; ++q) v.v[q] = st[(iq[q] - i0) * (TS + 1) + (jq[q] - j0)];
@@ -305,7 +345,12 @@ __global__ __launch_bounds__(TS * TS / 4) __attribute__((amdgpu_waves_per_eu(FLA
       }
       return v;
     };
-    if (!FLAT && p1 && np1 > 0) {
+    if (DMA && p1 && np1 > 0) {
+      // the LDS DMA writes land before the staging area is read (the compiler does not
+      // track them): vmcnt(0), expcnt and lgkmcnt unconstrained
+      __builtin_amdgcn_s_waitcnt(0x0F70);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    } else if (!FLAT && p1 && np1 > 0) {
       __syncthreads();  // the previous tile's reads of the staging area are done
       u32 rest = p1;
 #pragma unroll
@@ -399,7 +444,9 @@ extern "C" hipError_t coot_batch_launch_kernel(int dtype, int ts, unsigned grid,
   const u32* tl = (const u32*)tiles;
   const u32* cd = (const u32*)code;
   const size_t es = dtype == COOT_BATCH_F32 ? 4 : 8;
-  const size_t shmem = (size_t)nstk * (ts * ts / 4) * 4 * es + (size_t)np1 * ts * (ts + 1) * es;
+  // staging slots: [TS][TS] for the one-wave tiles (LDS DMA), [TS][TS + 1] otherwise
+  const size_t slot = (size_t)ts * (ts == 16 ? ts : ts + 1) * es;
+  const size_t shmem = (size_t)nstk * (ts * ts / 4) * 4 * es + (size_t)np1 * slot;
   if (nstk < 1 || np1 < 0 || shmem > 65536 - 2048) return hipErrorInvalidValue;  // 2 KB: the exp table
   if (dtype == COOT_BATCH_F32) {
     const float* sc = (const float*)scal;
