@@ -10,9 +10,9 @@ What it computes (plain definitions, no fusion, no blocking):
 * `elementwise.evaluate` — an Armadillo-style expression given as a postfix list
   (the Op / eOp / eGlue node kinds of Section 3, evaluated on assignment as the
   delayed-evaluation paragraph of Section 3 describes) computed one operator at a
-  time into a full temporary.  Floating types: each operator's exact result
-  rounded once to the element type.  u32 / s32: exact integer arithmetic reduced
-  mod 2^32.
+  time into a full temporary.  Floating types (f32, f64 and the 16-bit storage
+  types f16, bf16): each operator's exact result rounded once to the element
+  type.  u32 / s32: exact integer arithmetic reduced mod 2^32.
 * `reduce` — accu / sum along a dimension / dot / norm (Fig. 1 and Section 5,
   task 1) as exact sums of the element values (Fractions), rounded once for
   reporting; integer sums mod 2^32.

@@ -8,7 +8,8 @@ Semantics followed:
     is assigned; this oracle then evaluates it the plain way, one operator at a
     time, each into a full temporary.
   * Section 2 (element types): Mat<float>, Mat<double>; u32 / s32 follow the same
-    Mat<eT> template.
+    Mat<eT> template, and so do the 16-bit storage types f16 (IEEE binary16) and
+    bf16 (bfloat16: binary32's exponent range, 8 significant bits).
 
 Readings where the paper is silent (each is listed in the design doc):
   * `%` is the element-wise (Schur) product, as in Armadillo.
@@ -22,6 +23,11 @@ Readings where the paper is silent (each is listed in the design doc):
   * A scalar is converted to the element type before use: nearest-even for floats,
     truncation toward zero then mod 2^32 for integers.
   * One dtype per expression; mixing is an error.
+  * f16 / bf16 follow the floating rule above with their own rounding: each
+    operator's binary64 result (exact for + - * of 16-bit operands, correctly
+    rounded for / sqrt exp log) is rounded once more, to nearest-even in the
+    16-bit type; 53 >= 2*11 + 2 makes that second rounding innocuous.  bf16 values
+    are held in float32 arrays (every bf16 value is a binary32 value).
 """
 from __future__ import annotations
 
@@ -31,9 +37,12 @@ from fractions import Fraction
 
 import numpy as np
 
-FLOATS = ("f32", "f64")
+FLOATS = ("f32", "f64", "f16", "bf16")
+HALVES = ("f16", "bf16")
 INTS = ("u32", "s32")
-NP = {"u32": np.uint32, "s32": np.int32, "f32": np.float32, "f64": np.float64}
+# element type -> numpy container (bf16 values live in float32 arrays)
+NP = {"u32": np.uint32, "s32": np.int32, "f32": np.float32, "f64": np.float64, "f16": np.float16,
+      "bf16": np.float32}
 BINARY = ("add", "sub", "schur", "div")
 UNARY = ("neg", "abs", "exp", "log", "sqrt", "square")
 INT_ILLEGAL = ("div", "exp", "log", "sqrt")
@@ -48,6 +57,45 @@ class OracleError(Exception):
 
 
 # ---------------------------------------------------------------------------
+# Rounding to the 16-bit types
+# ---------------------------------------------------------------------------
+
+def round_bf16(x) -> np.ndarray:
+    """Round binary64 values to bfloat16, nearest-even, in one step; float32 containers.
+
+    bfloat16 keeps 8 significant bits over binary32's exponent range, so its
+    spacing is 2^(e-8) for a value m * 2^e (m in [0.5, 1)) down to the subnormal
+    spacing 2^-133.  The value is scaled by a power of two (exact) so that its
+    spacing becomes 1, rounded to an integer with ties to even, and scaled back.
+    Results of 2^128 or more (the largest finite value plus half its spacing,
+    rounded up) become infinite; NaN stays NaN.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    with np.errstate(all="ignore"):
+        ax = np.abs(x)
+        _, e = np.frexp(ax)
+        q = np.maximum(e.astype(np.int64) - 8, -133)
+        v = np.ldexp(np.rint(np.ldexp(ax, -q)), q)
+        v = np.where(v >= 2.0 ** 128, np.inf, v)
+        v = np.where(np.isnan(x), np.nan, np.copysign(v, x))
+    return v.astype(np.float32)
+
+
+def round_to(r64, dtype: str) -> np.ndarray:
+    """Round binary64 values to the element type (nearest-even; one rounding)."""
+    if dtype == "bf16":
+        return round_bf16(r64)
+    with np.errstate(all="ignore"):
+        return np.asarray(r64, dtype=np.float64).astype(NP[dtype])
+
+
+def is_bf16(x) -> bool:
+    """Every value of a float32 array is a bfloat16 value (its low 16 bits are zero)."""
+    b = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32)
+    return bool(np.all((b & 0xFFFF) == 0))
+
+
+# ---------------------------------------------------------------------------
 # Scalars
 # ---------------------------------------------------------------------------
 
@@ -57,6 +105,8 @@ def scalar_to(s: float, dtype: str):
         return np.float32(s)
     if dtype == "f64":
         return np.float64(s)
+    if dtype in HALVES:
+        return round_to(np.float64(s), dtype)[()]
     if not math.isfinite(s):
         raise OracleError("invalid", "non-finite scalar for an integer expression")
     v = int(s) & 0xFFFFFFFF          # int() truncates toward zero
@@ -171,7 +221,6 @@ def log_rounded(x: np.ndarray, dtype: str) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 def _float_binary(op, a, b, dtype):
-    t = NP[dtype]
     with np.errstate(all="ignore"):
         a64 = np.asarray(a, dtype=np.float64)
         b64 = np.asarray(b, dtype=np.float64)
@@ -183,7 +232,7 @@ def _float_binary(op, a, b, dtype):
             r = a64 * b64
         else:
             r = a64 / b64
-        return r.astype(t)
+        return round_to(r, dtype)
 
 
 def _float_unary(op, a, dtype):
@@ -196,9 +245,13 @@ def _float_unary(op, a, dtype):
             return np.abs(a).astype(t)
         if op == "square":
             a64 = a.astype(np.float64)
-            return (a64 * a64).astype(t)
+            return round_to(a64 * a64, dtype)
         if op == "sqrt":
-            return np.sqrt(a.astype(np.float64)).astype(t)
+            return round_to(np.sqrt(a.astype(np.float64)), dtype)
+        if op in ("exp", "log") and dtype in HALVES:
+            # correctly rounded binary64, then rounded to the 16-bit type
+            f = exp_rounded if op == "exp" else log_rounded
+            return round_to(f(a.astype(np.float64), "f64"), dtype)
         if op == "exp":
             return exp_rounded(a, dtype)
         if op == "log":
@@ -275,6 +328,8 @@ def check_dtype(operands, dtype):
     for k, x in enumerate(operands):
         if np.asarray(x).dtype != np.dtype(NP[dtype]):
             raise OracleError("type", f"operand {k} has dtype {np.asarray(x).dtype}, expression is {dtype}")
+        if dtype == "bf16" and not is_bf16(x):
+            raise OracleError("type", f"operand {k} holds values that are not bfloat16 values")
 
 
 def evaluate(postfix, operands, scalars, dtype: str) -> np.ndarray:

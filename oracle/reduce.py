@@ -23,6 +23,8 @@ from fractions import Fraction
 
 import numpy as np
 
+from .elementwise import FLOATS, round_to
+
 
 CHUNK = 1 << 25          # elements per exact-summation pass; keeps every bucket below 2^26
 
@@ -110,8 +112,8 @@ def exact_dot(x: np.ndarray, y: np.ndarray) -> Fraction:
         raise ValueError("dot: length mismatch")
     if x.size == 0:
         return Fraction(0)
-    if x.dtype == np.float32 and y.dtype == np.float32:
-        p = x.astype(np.float64) * y.astype(np.float64)     # exact: 24 + 24 bits
+    if x.dtype in (np.float32, np.float16) and y.dtype in (np.float32, np.float16):
+        p = x.astype(np.float64) * y.astype(np.float64)     # exact: at most 24 + 24 bits
         _finite_or_raise(p)
         return exact_sum(p)
     # binary64 operands: products from integer mantissas (4 partial products of <= 27 bits)
@@ -159,6 +161,16 @@ def to_float(q: Fraction) -> float:
     return float(q)
 
 
+def round_exact(q: Fraction, dtype: str) -> float:
+    """An exact value rounded once to the element type (nearest-even), as a Python float.
+
+    float() of a Fraction is correctly rounded to binary64; a second rounding to
+    binary32 or a 16-bit type is innocuous (53 >= 2p + 2), so the result is the
+    correctly rounded value of q in that type.
+    """
+    return float(round_to(np.float64(float(q)), dtype))
+
+
 def sum_abs(x: np.ndarray) -> float:
     """sum |x_i| rounded to binary64 (the scale used when the exact sum is 0)."""
     return to_float(exact_sum(np.abs(np.asarray(x))))
@@ -171,7 +183,7 @@ def sum_abs(x: np.ndarray) -> float:
 def accu(x: np.ndarray, dtype: str):
     """Sum of all elements: exact Fraction for floats, int mod 2^32 (as the dtype's value) for integers."""
     x = np.asarray(x)
-    if dtype in ("f32", "f64"):
+    if dtype in FLOATS:
         return exact_sum(x)
     u = x.astype(np.int64).astype(np.uint64) if dtype == "s32" else x.astype(np.uint64)
     tot = int(np.sum(u, dtype=np.uint64)) & 0xFFFFFFFF      # uint64 wraps mod 2^64 -> exact mod 2^32
@@ -183,7 +195,7 @@ def accu(x: np.ndarray, dtype: str):
 def sum_dim(X: np.ndarray, dim: int, dtype: str):
     """Per-column / per-row sums; Fractions for floats, ints mod 2^32 for integers."""
     X = np.asarray(X)
-    if dtype in ("f32", "f64"):
+    if dtype in FLOATS:
         return exact_sum_dim(X, dim)
     u = X.astype(np.int64).astype(np.uint64) if dtype == "s32" else X.astype(np.uint64)
     s = np.sum(u, axis=0 if dim == 0 else 1, dtype=np.uint64) & np.uint64(0xFFFFFFFF)
@@ -194,7 +206,7 @@ def sum_dim(X: np.ndarray, dim: int, dtype: str):
 
 
 def dot(x, y, dtype: str):
-    if dtype not in ("f32", "f64"):
+    if dtype not in FLOATS:
         raise ValueError("dot is defined here for floating types only")
     return exact_dot(x, y)
 
@@ -205,7 +217,7 @@ def norm(x, dtype: str) -> float:
     The exact sum is scaled by an even power of two before the square root so that
     neither the sum nor its root leaves the binary64 range.
     """
-    if dtype not in ("f32", "f64"):
+    if dtype not in FLOATS:
         raise ValueError("norm is defined here for floating types only")
     s = exact_dot(x, x)
     if s == 0:

@@ -25,8 +25,19 @@ import numpy as np
 
 SEED_ROOT = (2508, 11385)
 
-DTYPES = ("u32", "s32", "f32", "f64")
-NP_DTYPE = {"u32": np.uint32, "s32": np.int32, "f32": np.float32, "f64": np.float64}
+DTYPES = ("u32", "s32", "f32", "f64", "f16", "bf16")
+# numpy container of each element type (bfloat16 values are held in float32 arrays)
+NP_DTYPE = {"u32": np.uint32, "s32": np.int32, "f32": np.float32, "f64": np.float64, "f16": np.float16,
+            "bf16": np.float32}
+
+
+def _to_dtype(x: np.ndarray, dtype: str) -> np.ndarray:
+    """binary64 draws as the element type: a numpy cast, and for bf16 the binary32 cast
+    with its low 16 bits cleared (a bfloat16 value, truncated toward zero)."""
+    if dtype != "bf16":
+        return x.astype(NP_DTYPE[dtype])
+    b = x.astype(np.float32).view(np.uint32) & np.uint32(0xFFFF0000)
+    return b.view(np.float32)
 
 BINARY = ("add", "sub", "schur", "div")
 UNARY = ("neg", "abs", "exp", "log", "sqrt", "square")
@@ -39,9 +50,9 @@ def rng_for(*key: int) -> np.random.Generator:
 
 
 def uniform(rng: np.random.Generator, shape, dtype: str, lo: float = -1.0, hi: float = 1.0) -> np.ndarray:
-    """Uniform[lo, hi) drawn in binary64, then rounded to dtype (float types only)."""
+    """Uniform[lo, hi) drawn in binary64, then converted to dtype (float types only)."""
     x = rng.uniform(lo, hi, size=shape)
-    return x.astype(NP_DTYPE[dtype])
+    return _to_dtype(x, dtype)
 
 
 def uniform_int(rng: np.random.Generator, shape, dtype: str, lo: int, hi: int) -> np.ndarray:
@@ -61,7 +72,7 @@ def lognormal_signed(rng: np.random.Generator, n: int, sigma: float = 4.0, dtype
         mag = rng.lognormal(0.0, sigma, size=m)
         sign = rng.integers(0, 2, size=m, dtype=np.int8)
         mag[sign == 1] *= -1.0
-        out[s:s + m] = mag.astype(NP_DTYPE[dtype])
+        out[s:s + m] = _to_dtype(mag, dtype)
     return out
 
 
