@@ -443,6 +443,27 @@ def bench_suite(args):
     del gA, gB, gC, gD, Z, W, oz, ow
     torch.cuda.empty_cache()
     log(f"fp64 step: {res['step_4096_f64']}")
+    # the same step on 16-bit storage (binary32 arithmetic, every operator rounded to the type)
+    for dt in ("f16", "bf16"):
+        A, B, C, D = synth.matrix_inputs(N, dt)
+        gA, gB, gC, gD = (coot.Mat.from_numpy(m, dtype=dt) for m in (A, B, C, D))
+        del A, B, C, D
+        Z = 2.0 * gA + gB % gC - coot.trans(gD)
+        W = coot.exp(gA) / (1.0 + coot.abs(gB))
+        oz, ow = coot.Mat.empty(N, N, dt), coot.Mat.empty(N, N, dt)
+
+        def step16():
+            coot.eval(Z, out=oz)
+            coot.eval(W, out=ow)
+            coot.sum(Z, 0)
+            coot.sum(Z, 1)
+        us = gpu_us(step16)
+        nb = (16 * MIB64 + 2 * N * 4) // 2
+        res[f"step_4096_{dt}"] = {"us": round(us, 1), "GBps": round(nb / us / 1e3, 1),
+                                  "elements_per_ns": round(16 * N * N / us / 1e3, 1)}
+        del gA, gB, gC, gD, Z, W, oz, ow
+        torch.cuda.empty_cache()
+        log(f"{dt} step: {res[f'step_4096_{dt}']}")
     # integers on 8192 x 8192
     M = 8192
     Ai, Bi, Ci = synth.int_inputs(M, "u32")
@@ -473,7 +494,7 @@ def bench_suite(args):
         res[f"{name}_2^28_f32"] = {"us": round(us, 1), "GBps": round(nb / us / 1e3, 1)}
     out = {"metric": "throughput of the other workloads (GB/s of algorithmic bytes)", "value": None,
            "unit": "GB/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic, seeded, resident in HBM",
-           "config": {"workload": "axpy+dot 1e6 f32; 4096^2 step f64; u32/s32 8192^2; accu/norm 2^28 f32"},
+           "config": {"workload": "axpy+dot 1e6 f32; 4096^2 step f64, f16, bf16; u32/s32 8192^2; accu/norm 2^28 f32"},
            "results": res}
     print(json.dumps(out), flush=True)
 

@@ -59,7 +59,15 @@ typedef enum {
 } coot_status;
 
 /* ---- element types and operand kinds (Section 2: Mat<eT>, Col, Row) ------ */
-typedef enum { COOT_U32 = 0, COOT_S32 = 1, COOT_F32 = 2, COOT_F64 = 3 } coot_dtype;
+typedef enum { COOT_U32 = 0, COOT_S32 = 1, COOT_F32 = 2, COOT_F64 = 3, COOT_F16 = 4, COOT_BF16 = 5 } coot_dtype;
+/* COOT_F16 (IEEE binary16) and COOT_BF16 (bfloat16: binary32's exponent range,
+ * 8 significant bits) are 16-bit storage types: operands and results are stored
+ * in 16 bits, every operator computes in binary32 and its result is rounded to
+ * the storage type (nearest-even), which is the correctly rounded 16-bit result
+ * (for bf16 while the binary32 result is normal).  Scalars are rounded to the
+ * storage type.  Reductions accumulate in compensated binary32 (float-float) and
+ * round the result once to the storage type.  Batches and the cost model take
+ * f32 / f64 only (COOT_EUNSUPPORTED). */
 typedef enum { COOT_MAT = 0, COOT_COL = 1, COOT_ROW = 2 } coot_kind;
 
 /* ---- postfix opcodes (Section 3: eOp, eGlue and Op<.., op_trans>) -------- */

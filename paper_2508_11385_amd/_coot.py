@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libcoot.so")
 # enums (coot.h)
 COOT_OK, COOT_EINVAL, COOT_ESHAPE, COOT_ETYPE, COOT_EALIAS, COOT_ECOMPILE, COOT_EHIP, COOT_ENOMEM, \
     COOT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7, -8
-COOT_U32, COOT_S32, COOT_F32, COOT_F64 = 0, 1, 2, 3
+COOT_U32, COOT_S32, COOT_F32, COOT_F64, COOT_F16, COOT_BF16 = 0, 1, 2, 3, 4, 5
 COOT_MAT, COOT_COL, COOT_ROW = 0, 1, 2
 OPCODES = {"load": 0, "scalar": 1, "add": 2, "sub": 3, "schur": 4, "div": 5, "neg": 6, "abs": 7,
            "exp": 8, "log": 9, "sqrt": 10, "square": 11, "trans": 12}
@@ -24,7 +24,8 @@ COOT_RED_ACCU, COOT_RED_SUM, COOT_RED_DOT, COOT_RED_NORM = 0, 1, 2, 3
 COOT_CF_UNFUSED = 0x1
 COOT_RF_PLAIN = 0x1
 COOT_PF_COMPILE_ONLY = 0x100
-DTYPE_CODE = {"u32": COOT_U32, "s32": COOT_S32, "f32": COOT_F32, "f64": COOT_F64}
+DTYPE_CODE = {"u32": COOT_U32, "s32": COOT_S32, "f32": COOT_F32, "f64": COOT_F64, "f16": COOT_F16,
+              "bf16": COOT_BF16}
 N_FEATURES = 21  # cost-model feature vector length
 STATUS_NAME = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ETYPE", -4: "EALIAS", -5: "ECOMPILE", -6: "EHIP",
                -7: "ENOMEM", -8: "EUNSUPPORTED"}

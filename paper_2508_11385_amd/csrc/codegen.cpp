@@ -76,6 +76,9 @@ static const char* op_fn(int c) {
 // for a binary root, of its two operands.
 static void emit_body(const Expr& e, std::ostringstream& os, std::string* root, std::string* lhs, std::string* rhs) {
   std::vector<std::string> st;
+  // 16-bit storage types: every operator's binary32 result is rounded to the storage type
+  const bool half = dtype_is_half(e.dtype);
+  const std::string rnd_open = half ? "coot::St<S>::rnd(" : "", rnd_close = half ? ")" : "";
   int t = 0;
   for (size_t i = 0; i < e.ops.size(); ++i) {
     const coot_op& o = e.ops[i];
@@ -97,12 +100,13 @@ static void emit_body(const Expr& e, std::ostringstream& os, std::string* root, 
         if (lhs) *lhs = a;
         if (rhs) *rhs = b;
       }
-      os << "    const T " << name << " = " << op_fn(o.code) << "(" << a << ", " << b << ");\n";
+      os << "    const T " << name << " = " << rnd_open << op_fn(o.code) << "(" << a << ", " << b << ")" << rnd_close
+         << ";\n";
       st.push_back(name);
     } else {
       std::string a = st.back();
       st.pop_back();
-      os << "    const T " << name << " = " << op_fn(o.code) << "(" << a << ");\n";
+      os << "    const T " << name << " = " << rnd_open << op_fn(o.code) << "(" << a << ")" << rnd_close << ";\n";
       st.push_back(name);
     }
   }
@@ -123,7 +127,10 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
   os << "#include \"coot_dev.h\"\n";
   os << "namespace {\n";
   os << "struct X {\n";
-  os << "  typedef " << dtype_cname(e.dtype) << " T;\n";
+  // S: the storage type of the operands and the result; T: the type every operator
+  // computes in (binary32 for the 16-bit types, whose results are rounded back to S)
+  os << "  typedef " << dtype_cname(e.dtype) << " S;\n";
+  os << "  typedef typename coot::St<S>::C T;\n";
   os << "  static constexpr int NL = " << (e.leaves.empty() ? 1 : e.leaves.size()) << ";\n";
   os << "  static constexpr int NP1 = " << e.n_p1 << ";\n";
   std::vector<int> slot, par, p1;
@@ -192,7 +199,7 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
     if (rq.mode >= 0) {
       const std::string rks2 = std::to_string(red_kind(rq.mode));
       names->stage2 = "coot_rfin_" + hs + "_k" + rks2 + "c" + (rq.comp ? "1" : "0") + "_tm";
-      wrap(names->stage2, "coot::reduce_stage2<X::T, " + rks2 + ", " + comp + ", false>(a)", 256);
+      wrap(names->stage2, "coot::reduce_stage2<X::S, " + rks2 + ", " + comp + ", false>(a)", 256);
     }
     return os.str();
   }
@@ -223,7 +230,7 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
     wrap(names->stage1, inst(V), 256);
     if (V != 1) wrap(names->stage1_fallback, inst(1), 256);
     wrap(names->stage2,
-         "coot::dim_stage2<X::T, " + comp + ">(a, " + (rq.dim == 0 ? std::string("a.n_cols") : "a.n_rows") + ")",
+         "coot::dim_stage2<X::S, " + comp + ">(a, " + (rq.dim == 0 ? std::string("a.n_cols") : "a.n_rows") + ")",
          256);
     return os.str();
   }
@@ -259,10 +266,10 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
       wrap(names->stage1_rescale, inst(1, true), 256);
     }
   }
-  wrap(names->stage2, "coot::reduce_stage2<X::T, " + rks + ", " + comp + ", false>(a)", 256);
+  wrap(names->stage2, "coot::reduce_stage2<X::S, " + rks + ", " + comp + ", false>(a)", 256);
   if (rk == RK_SUMSQ) {
     names->stage2_rescale = names->stage2 + "_rescale";
-    wrap(names->stage2_rescale, "coot::reduce_stage2<X::T, " + rks + ", " + comp + ", true>(a)", 256);
+    wrap(names->stage2_rescale, "coot::reduce_stage2<X::S, " + rks + ", " + comp + ", true>(a)", 256);
   }
   return os.str();
 }

@@ -42,6 +42,7 @@ void hip_check(hipError_t e, const char* what);
 size_t dtype_size(int dt);
 const char* dtype_cname(int dt);  // C type used in generated code
 bool dtype_is_int(int dt);
+bool dtype_is_half(int dt);  // f16 / bf16: 16-bit storage, binary32 arithmetic
 
 // A leaf is an (operand slot, transpose parity) pair; repeated loads of the same
 // pair share one leaf.

@@ -271,6 +271,7 @@ struct coot_costmodel {
 namespace {
 
 void features_of(const Expr& e, int64_t R, int64_t C, int red, const coot_launch_cfg& c, float* f) {
+  if (dtype_is_half(e.dtype)) fail(COOT_EUNSUPPORTED, "the cost model covers u32, s32, f32 and f64 expressions");
   int n_ops = 0, n_trans = 0;
   std::vector<bool> seen(e.slots.size(), false);
   int n_operands = 0;

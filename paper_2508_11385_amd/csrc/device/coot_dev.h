@@ -58,6 +58,51 @@ template <> __device__ __forceinline__ double sc_as<double>(u64 b) { return __lo
 template <> __device__ __forceinline__ u32 sc_as<u32>(u64 b) { return (u32)b; }
 template <> __device__ __forceinline__ s32 sc_as<s32>(u64 b) { return (s32)(u32)b; }
 
+// ---------------------------------------------------------------------------
+// 16-bit storage types.  An expression over f16 (IEEE binary16) or bf16
+// (bfloat16) operands computes in binary32 and rounds every operator's result to
+// the storage type, nearest-even: binary32 carries at least 2p + 2 bits of a p-bit
+// type, so the two roundings give the correctly rounded 16-bit result (for bf16,
+// while the binary32 result is normal).  Leaves are widened when loaded and
+// results narrowed when stored; St<S> maps a storage type to its compute type.
+// ---------------------------------------------------------------------------
+struct f16 { unsigned short b; };
+struct bf16 { unsigned short b; };
+
+template <typename S> struct St {
+  typedef S C;
+  static __device__ __forceinline__ C in(S x) { return x; }
+  static __device__ __forceinline__ S out(C x) { return x; }
+  static __device__ __forceinline__ C rnd(C x) { return x; }
+};
+template <> struct St<f16> {
+  typedef float C;
+  static __device__ __forceinline__ float in(f16 x) { return (float)__builtin_bit_cast(_Float16, x.b); }
+  static __device__ __forceinline__ f16 out(float x) { return f16{__builtin_bit_cast(unsigned short, (_Float16)x)}; }
+  // nearest-even binary16 value of x, kept in binary32, by integer steps on the
+  // binary32 fields (no conversion instructions between operators): normal range:
+  // round the fraction to 10 bits; from 65520 on: infinity; below 2^-14: the
+  // spacing 2^-24 is that of binary32 at 0.5, so x + 0.5 rounds it
+  static __device__ __forceinline__ float rnd(float x) {
+    const u32 u = __float_as_uint(x), a = u & 0x7fffffffu, sg = u & 0x80000000u;
+    if (a >= 0x7f800000u) return x;                         // infinities and NaN
+    if (a >= 0x477ff000u) return __uint_as_float(sg | 0x7f800000u);
+    if (a >= 0x38800000u) return __uint_as_float(sg | ((a + 0xfffu + ((a >> 13) & 1u)) & 0xffffe000u));
+    const float v = (__uint_as_float(a) + 0.5f) - 0.5f;    // exact subtraction
+    return __uint_as_float(sg | __float_as_uint(v));
+  }
+};
+template <> struct St<bf16> {
+  typedef float C;
+  static __device__ __forceinline__ float in(bf16 x) { return __uint_as_float((u32)x.b << 16); }
+  static __device__ __forceinline__ bf16 out(float x) {
+    const u32 u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return bf16{(unsigned short)((u >> 16) | 0x40u)};  // NaN: quiet, kept
+    return bf16{(unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16)};                  // nearest-even
+  }
+  static __device__ __forceinline__ float rnd(float x) { return in(out(x)); }
+};
+
 template <typename T> struct is_int_t { static constexpr bool v = false; };
 template <> struct is_int_t<u32> { static constexpr bool v = true; };
 template <> struct is_int_t<s32> { static constexpr bool v = true; };
@@ -116,7 +161,10 @@ template <typename T, int V>
 __device__ __forceinline__ vt<T, V> ldv(const T* p) {
   vt<T, V> r;
   constexpr int B = V * (int)sizeof(T);
-  if constexpr (B == 4) {
+  if constexpr (B == 2) {
+    unsigned short q = *reinterpret_cast<const unsigned short*>(p);
+    __builtin_memcpy(&r, &q, 2);
+  } else if constexpr (B == 4) {
     u32 q = *reinterpret_cast<const u32*>(p);
     __builtin_memcpy(&r, &q, 4);
   } else if constexpr (B == 8) {
@@ -141,7 +189,11 @@ __device__ __forceinline__ vt<T, V> ldv(const T* p) {
 template <typename T, int V>
 __device__ __forceinline__ void stv(T* p, const vt<T, V>& r) {
   constexpr int B = V * (int)sizeof(T);
-  if constexpr (B == 4) {
+  if constexpr (B == 2) {
+    unsigned short q;
+    __builtin_memcpy(&q, &r, 2);
+    __builtin_nontemporal_store(q, reinterpret_cast<unsigned short*>(p));
+  } else if constexpr (B == 4) {
     u32 q;
     __builtin_memcpy(&q, &r, 4);
     __builtin_nontemporal_store(q, reinterpret_cast<u32*>(p));
@@ -159,6 +211,31 @@ __device__ __forceinline__ void stv(T* p, const vt<T, V>& r) {
     __builtin_memcpy(&q1, reinterpret_cast<const char*>(&r) + 16, 16);
     __builtin_nontemporal_store(q0, reinterpret_cast<u32x4*>(p));
     __builtin_nontemporal_store(q1, reinterpret_cast<u32x4*>(p) + 1);
+  }
+}
+
+// V storage elements widened to the compute type / narrowed from it (16-bit types)
+template <typename S, int V>
+__device__ __forceinline__ vt<typename St<S>::C, V> ldc(const S* p) {
+  if constexpr (sizeof(S) == 2) {
+    const vt<S, V> r = ldv<S, V>(p);
+    vt<typename St<S>::C, V> c;
+#pragma unroll
+    for (int q = 0; q < V; ++q) c.v[q] = St<S>::in(r.v[q]);
+    return c;
+  } else {
+    return ldv<S, V>(p);
+  }
+}
+template <typename S, int V>
+__device__ __forceinline__ void stc(S* p, const vt<typename St<S>::C, V>& c) {
+  if constexpr (sizeof(S) == 2) {
+    vt<S, V> r;
+#pragma unroll
+    for (int q = 0; q < V; ++q) r.v[q] = St<S>::out(c.v[q]);
+    stv<S, V>(p, r);
+  } else {
+    stv<S, V>(p, c);
   }
 }
 
@@ -255,9 +332,16 @@ __device__ __forceinline__ F wave_sum(F v) {
 // ---------------------------------------------------------------------------
 template <class X, int V>
 __device__ __forceinline__ void load_flat(const coot_kargs& a, i64 v, vt<typename X::T, V> (&x)[X::NL]) {
-  typedef typename X::T T;
+  typedef typename X::S S;
 #pragma unroll
-  for (int k = 0; k < X::NL; ++k) x[k] = ldv<T, V>((const T*)a.leaf[X::slot(k)] + v * V);
+  for (int k = 0; k < X::NL; ++k) x[k] = ldc<S, V>((const S*)a.leaf[X::slot(k)] + v * V);
+}
+
+// leaf k's element i (scalar tails), widened to the compute type
+template <class X>
+__device__ __forceinline__ typename X::T leaf_at(const coot_kargs& a, int k, i64 i) {
+  typedef typename X::S S;
+  return St<S>::in(((const S*)a.leaf[X::slot(k)])[i]);
 }
 
 // ===========================================================================
@@ -272,7 +356,8 @@ __device__ __forceinline__ void flat_eval(const coot_kargs& a) {
   const i64 nv = n / V;
   const int bs = blockDim.x;
   const i64 step = (i64)gridDim.x * bs * E;
-  T* out = (T*)a.out;
+  typedef typename X::S S;
+  S* out = (S*)a.out;
   for (i64 b = (i64)blockIdx.x * bs * E + threadIdx.x; b < nv; b += step) {
     vt<T, V> x[E][X::NL];
 #pragma unroll
@@ -292,7 +377,7 @@ __device__ __forceinline__ void flat_eval(const coot_kargs& a) {
           for (int k = 0; k < X::NL; ++k) L[k] = x[e][k].v[q];
           r.v[q] = X::f(L, a.sc);
         }
-        stv<T, V>(out + v * V, r);
+        stc<S, V>(out + v * V, r);
       }
     }
   }
@@ -300,8 +385,8 @@ __device__ __forceinline__ void flat_eval(const coot_kargs& a) {
     for (i64 i = nv * V + threadIdx.x; i < n; i += bs) {
       T L[X::NL];
 #pragma unroll
-      for (int k = 0; k < X::NL; ++k) L[k] = ((const T*)a.leaf[X::slot(k)])[i];
-      out[i] = X::f(L, a.sc);
+      for (int k = 0; k < X::NL; ++k) L[k] = leaf_at<X>(a, k, i);
+      out[i] = St<S>::out(X::f(L, a.sc));
     }
   }
 }
@@ -482,7 +567,7 @@ __device__ __forceinline__ void flat_reduce(const coot_kargs& a) {
     for (i64 i = nv * V + threadIdx.x; i < n; i += bs) {
       T L[X::NL];
 #pragma unroll
-      for (int k = 0; k < X::NL; ++k) L[k] = ((const T*)a.leaf[X::slot(k)])[i];
+      for (int k = 0; k < X::NL; ++k) L[k] = leaf_at<X>(a, k, i);
       if constexpr (RK == RK_SUMSQ) {
         T val = X::f(L, a.sc);
         amax = __builtin_fmax(amax, abs_of<T>(val));
@@ -531,7 +616,7 @@ __device__ __forceinline__ void tiled_walk(const coot_kargs& a, Sink& sink) {
           if (X::par(k) == 0) continue;
           vt<T, V> v;
           if (in) {
-            v = ldv<T, V>((const T*)a.leaf[X::slot(k)] + j + i * a.ld[X::slot(k)]);
+            v = ldc<typename X::S, V>((const typename X::S*)a.leaf[X::slot(k)] + j + i * a.ld[X::slot(k)]);
           } else {
 #pragma unroll
             for (int q = 0; q < V; ++q) v.v[q] = (T)0;
@@ -549,7 +634,8 @@ __device__ __forceinline__ void tiled_walk(const coot_kargs& a, Sink& sink) {
       if (in) {
 #pragma unroll
         for (int k = 0; k < X::NL; ++k)
-          if (X::par(k) == 0) x[k] = ldv<T, V>((const T*)a.leaf[X::slot(k)] + i + j * a.ld[X::slot(k)]);
+          if (X::par(k) == 0)
+            x[k] = ldc<typename X::S, V>((const typename X::S*)a.leaf[X::slot(k)] + i + j * a.ld[X::slot(k)]);
       }
 #pragma unroll
       for (int q = 0; q < V; ++q) {
@@ -575,7 +661,7 @@ struct EvalSink {
     r.v[q] = in ? X::f(L, a.sc) : (T)0;
   }
   __device__ __forceinline__ void group(const coot_kargs& a, i64 i, i64 j, int, int, bool in) {
-    if (in) stv<T, V>((T*)a.out + i + j * a.out_ld, r);
+    if (in) stc<typename X::S, V>((typename X::S*)a.out + i + j * a.out_ld, r);
   }
   __device__ __forceinline__ void end_tile(const coot_kargs&, i64, i64, i64, i64, int, int) {}
 };
@@ -637,8 +723,9 @@ __device__ __forceinline__ void tiled_reduce(const coot_kargs& a) {
 //   [2^-L, 2^L] the squares may have overflowed or underflowed, so the control
 //   block gets flag = 1 and scale = 2^-e (e the exponent of the largest |value|).
 // ===========================================================================
-template <typename T, int RK, bool COMP, bool SCALED>
+template <typename S, int RK, bool COMP, bool SCALED>
 __device__ __forceinline__ void reduce_stage2(const coot_kargs& a) {
+  typedef typename St<S>::C T;  // compute type; the result is stored as S
   __shared__ double sh[256], sl[256], sm[256];
   const PartRec* recs = (const PartRec*)(SCALED ? (const void*)((const char*)a.ws2 + 64) : (const void*)a.ws);
   double* ctl = (double*)a.ws2;
@@ -684,21 +771,18 @@ __device__ __forceinline__ void reduce_stage2(const coot_kargs& a) {
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    T* out = (T*)a.out;
+    S* out = (S*)a.out;
     const double tot = sh[0] + sl[0];
     if (is_int) {
-      out[0] = (T)(u32)sh[0];
+      out[0] = St<S>::out((T)(u32)sh[0]);
     } else if (RK != RK_SUMSQ) {
-      if constexpr (sizeof(T) == 8) {
-        out[0] = (T)tot;
-      } else {
-        out[0] = (T)tot;  // one rounding from binary64
-      }
+      // one rounding from binary64 (a second one, to a 16-bit type, is innocuous)
+      out[0] = St<S>::out((T)tot);
     } else {
       const double mx = sm[0];
       double scale = SCALED ? ctl[1] : 1.0;
       double nrm = __builtin_sqrt(tot) / scale;
-      out[0] = (T)nrm;
+      out[0] = St<S>::out((T)nrm);
       if constexpr (!SCALED) {
         const double lim_hi = sizeof(T) == 4 ? 0x1p50 : 0x1p400;
         const double lim_lo = sizeof(T) == 4 ? 0x1p-50 : 0x1p-400;
@@ -795,7 +879,7 @@ __device__ __forceinline__ void tiled_walk_seg(const coot_kargs& a, Sink& sink) 
             if (X::par(k) == 0) continue;
             vt<T, V> v;
             if (in) {
-              v = ldv<T, V>((const T*)a.leaf[X::slot(k)] + j + i * a.ld[X::slot(k)]);
+              v = ldc<typename X::S, V>((const typename X::S*)a.leaf[X::slot(k)] + j + i * a.ld[X::slot(k)]);
             } else {
 #pragma unroll
               for (int q = 0; q < V; ++q) v.v[q] = (T)0;
@@ -815,7 +899,8 @@ __device__ __forceinline__ void tiled_walk_seg(const coot_kargs& a, Sink& sink) 
         if (in) {
 #pragma unroll
           for (int k = 0; k < X::NL; ++k)
-            if (X::par(k) == 0) x[k] = ldv<T, V>((const T*)a.leaf[X::slot(k)] + i + j * a.ld[X::slot(k)]);
+            if (X::par(k) == 0)
+            x[k] = ldc<typename X::S, V>((const typename X::S*)a.leaf[X::slot(k)] + i + j * a.ld[X::slot(k)]);
         }
 #pragma unroll
         for (int q = 0; q < V; ++q) {
@@ -835,8 +920,9 @@ __device__ __forceinline__ void tiled_walk_seg(const coot_kargs& a, Sink& sink) 
 // One output's n_part partials folded by one wavefront: lane l takes k = l, l + 64,
 // ... in order, then a fixed butterfly combines the lanes (the result does not
 // depend on timing).  Stage 2 of a dimension sum runs one wavefront per output.
-template <typename T, bool COMP>
+template <typename S, bool COMP>
 __device__ __forceinline__ void fold_output(const coot_kargs& a, i64 o, int lane) {
+  typedef typename St<S>::C T;  // partials in the compute type, the result stored as S
   const Pair<T>* ws = (const Pair<T>*)a.ws;
   T h = (T)0, l = (T)0;
   for (i64 k = lane; k < a.n_part; k += 64) pair_add<T, COMP>(h, l, ws[o * a.n_part + k]);
@@ -849,9 +935,9 @@ __device__ __forceinline__ void fold_output(const coot_kargs& a, i64 o, int lane
   }
   if (lane == 0) {
     if constexpr (is_int_t<T>::v) {
-      ((T*)a.out)[o] = h;
+      ((S*)a.out)[o] = St<S>::out(h);
     } else {
-      ((T*)a.out)[o] = h + l;
+      ((S*)a.out)[o] = St<S>::out(h + l);
     }
   }
 }
@@ -948,12 +1034,12 @@ __device__ __forceinline__ void tiled_reduce_dim(const coot_kargs& a) {
   }
 }
 
-template <typename T, bool COMP>
+template <typename S, bool COMP>
 __device__ __forceinline__ void dim_stage2(const coot_kargs& a, i64 n_out) {
   const int lane = threadIdx.x & 63;
   const int wpb = blockDim.x >> 6;
   for (i64 o = (i64)blockIdx.x * wpb + (threadIdx.x >> 6); o < n_out; o += (i64)gridDim.x * wpb)
-    fold_output<T, COMP>(a, o, lane);
+    fold_output<S, COMP>(a, o, lane);
 }
 
 }  // namespace coot

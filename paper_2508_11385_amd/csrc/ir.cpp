@@ -7,6 +7,7 @@
 // the tree arrives as a postfix list.  Every trans() is pushed down to the
 // leaves: a leaf under an odd number of trans() is read with its index map
 // swapped, so transposition never costs a pass of its own.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <sstream>
@@ -15,16 +16,45 @@
 
 namespace coot {
 
-size_t dtype_size(int dt) { return dt == COOT_F64 ? 8 : 4; }
+size_t dtype_size(int dt) { return dt == COOT_F64 ? 8 : (dtype_is_half(dt) ? 2 : 4); }
 const char* dtype_cname(int dt) {
   switch (dt) {
     case COOT_U32: return "u32";
     case COOT_S32: return "s32";
     case COOT_F32: return "float";
+    case COOT_F16: return "coot::f16";
+    case COOT_BF16: return "coot::bf16";
     default: return "double";
   }
 }
 bool dtype_is_int(int dt) { return dt == COOT_U32 || dt == COOT_S32; }
+bool dtype_is_half(int dt) { return dt == COOT_F16 || dt == COOT_BF16; }
+
+// binary32 value -> nearest-even value of a 16-bit type, returned as binary32
+// (the same rounding the kernels apply to every operator's result)
+static float round_half(float f, int dt) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  const uint32_t a = u & 0x7fffffffu;
+  if (a > 0x7f800000u) return f;  // NaN
+  if (dt == COOT_BF16) {
+    u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+  } else {
+    // binary16: 11 significant bits, exponents down to 2^-14, subnormal spacing 2^-24
+    if (a == 0x7f800000u) return f;  // infinities
+    const double ax = std::fabs((double)f);
+    int e;
+    (void)std::frexp(ax, &e);
+    const int q = std::max(e - 11, -24);
+    double v = std::ldexp(std::nearbyint(std::ldexp(ax, -q)), q);  // ties to even (default rounding mode)
+    if (v >= 65520.0) v = INFINITY;  // 65504 plus half its spacing, and beyond
+    const float r = (float)v;
+    return std::signbit(f) ? -r : r;
+  }
+  float r;
+  std::memcpy(&r, &u, 4);
+  return r;
+}
 
 static bool is_binary(int c) { return c >= COOT_OP_ADD && c <= COOT_OP_DIV; }
 static bool is_unary(int c) { return c >= COOT_OP_NEG && c <= COOT_OP_SQUARE; }
@@ -46,7 +76,7 @@ std::unique_ptr<Expr> analyse(const coot_op* ops, uint32_t n_ops, const coot_slo
   e->flags = flags;
   e->dtype = n_slots ? slots[0].dtype : COOT_F32;
   for (uint32_t k = 0; k < n_slots; ++k) {
-    if (slots[k].dtype < COOT_U32 || slots[k].dtype > COOT_F64) fail(COOT_EINVAL, "bad dtype in slot");
+    if (slots[k].dtype < COOT_U32 || slots[k].dtype > COOT_BF16) fail(COOT_EINVAL, "bad dtype in slot");
     if (slots[k].kind < COOT_MAT || slots[k].kind > COOT_ROW) fail(COOT_EINVAL, "bad kind in slot");
     if (slots[k].dtype != e->dtype) fail(COOT_ETYPE, "operand slots have different element types");
   }
@@ -185,6 +215,15 @@ uint64_t scalar_bits(double v, int dtype) {
     case COOT_F64: {
       uint64_t b;
       std::memcpy(&b, &v, 8);
+      return b;
+    }
+    case COOT_F16:
+    case COOT_BF16: {
+      // the scalar in the 16-bit type, carried as binary32 (the kernels' compute type):
+      // binary64 -> binary32 -> 16 bits, nearest-even each time, is one correct rounding
+      float f = round_half((float)v, dtype);
+      uint32_t b;
+      std::memcpy(&b, &f, 4);
       return b;
     }
     default: {

@@ -19,8 +19,11 @@ import torch
 
 from . import _coot as cc
 
-_TORCH = {"f32": torch.float32, "f64": torch.float64, "u32": torch.int32, "s32": torch.int32}
-_NP = {"f32": np.float32, "f64": np.float64, "u32": np.uint32, "s32": np.int32}
+_TORCH = {"f32": torch.float32, "f64": torch.float64, "u32": torch.int32, "s32": torch.int32,
+          "f16": torch.float16, "bf16": torch.bfloat16}
+# host arrays of each element type (bfloat16 values travel as float32 arrays)
+_NP = {"f32": np.float32, "f64": np.float64, "u32": np.uint32, "s32": np.int32, "f16": np.float16,
+       "bf16": np.float32}
 _KIND = {"mat": cc.COOT_MAT, "col": cc.COOT_COL, "row": cc.COOT_ROW}
 
 
@@ -125,16 +128,23 @@ class Mat(Expr):
             a = a.reshape(-1, 1)
             kind = kind or "col"
         dtype = dtype or {np.dtype(np.float32): "f32", np.dtype(np.float64): "f64",
-                          np.dtype(np.uint32): "u32", np.dtype(np.int32): "s32"}[a.dtype]
+                          np.dtype(np.uint32): "u32", np.dtype(np.int32): "s32",
+                          np.dtype(np.float16): "f16"}[a.dtype]
         a = a.astype(_NP[dtype], copy=False)
         if dtype == "u32":
             a = a.view(np.int32)
         cm = np.ascontiguousarray(a.T)                 # columns one after another
-        store = torch.from_numpy(cm).to(device)
+        store = torch.from_numpy(cm)
+        if dtype == "bf16":
+            store = store.to(torch.bfloat16)           # exact for values that are bfloat16 values
+        store = store.to(device)
         return Mat(store.t(), dtype, kind or "mat")
 
     def numpy(self) -> np.ndarray:
-        a = self.tensor.detach().cpu().numpy()
+        t = self.tensor.detach()
+        if self.dtype == "bf16":
+            t = t.float()                              # exact: every bfloat16 value is a binary32 value
+        a = t.cpu().numpy()
         if self.dtype == "u32":
             a = a.view(np.uint32)
         return np.asarray(a)

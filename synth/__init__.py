@@ -302,7 +302,7 @@ def operands_for(spec: TreeSpec, rng: np.random.Generator) -> list:
     """Operand arrays for a tree: U[-1,1] for floats, [0, 2^16) for integers."""
     out = []
     for shp in spec.slot_shapes:
-        if spec.dtype in ("f32", "f64"):
+        if spec.dtype in ("f32", "f64", "f16", "bf16"):
             out.append(uniform(rng, shp, spec.dtype))
         else:
             out.append(uniform_int(rng, shp, spec.dtype, 0, 1 << 16))

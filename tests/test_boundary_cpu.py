@@ -106,6 +106,12 @@ FAMILIES = [
     (Z, 4, 1, 0, -1, 1, 4, 0, 64, "f64"),
     ([("load", 0), ("load", 1), ("add",), ("load", 2), ("schur",)], 3, 0, -1, -1, 0, 4, 4, 0, "u32"),
     ([("load", 0), ("scalar", 0), ("load", 1), ("schur",), ("sub",)], 2, 1, -1, -1, 0, 4, 4, 0, "s32"),
+    (Z, 4, 1, -1, -1, 1, 4, 0, 64, "f16"),
+    (W, 2, 1, -1, -1, 0, 4, 4, 0, "bf16"),
+    (Z, 4, 1, 1, 0, 1, 4, 0, 64, "bf16"),
+    (Z, 4, 1, 0, -1, 1, 4, 0, 64, "f16"),
+    ([("load", 0)], 1, 0, 3, -1, 0, 4, 8, 0, "f16"),
+    ([("load", 0), ("load", 1), ("schur",)], 2, 0, 2, -1, 0, 4, 4, 0, "bf16"),
 ]
 
 
@@ -119,6 +125,20 @@ def test_codegen_compiles_for_gfx950(cc, case):
     if mode < 0 and any(p[0] == "trans" for p in post):
         assert "tiled_eval" in src
     cc.coot_expr_release(h)
+
+
+def test_half_types_round_each_operator_and_stay_out_of_the_cost_model(cc):
+    for dt in ("f16", "bf16"):
+        h = cc.coot_expr_compile(W, _ops(2, dt), 1)
+        src, _ = cc.coot_debug_codegen(h, -1, -1, 0, 0, 4, 1, 0, False)
+        assert f"typedef coot::{dt} S;" in src
+        start = src.index("T f(const T* L")
+        body = src[start:src.index("return t", start)]
+        assert body.count("coot::St<S>::rnd(") == 4          # exp, abs, +, /: each rounded to the type
+        with pytest.raises(cc.CootError) as e:
+            cc.coot_costmodel_features(h, 8, 8, 0, [(4, 1, 4, 4)])
+        assert e.value.status == cc.COOT_EUNSUPPORTED
+        cc.coot_expr_release(h)
 
 
 def test_generated_body_has_one_statement_per_operator(cc):
@@ -177,6 +197,11 @@ def test_tuning_module_compiles_every_variant(cc):
     with pytest.raises(cc.CootError) as e:
         cc.coot_tune_prepare(hd, [_opnd(cc, 1000, 1)] * 2, 1)
     assert e.value.status == cc.COOT_EUNSUPPORTED
+    for dt in ("f16", "bf16"):       # the 16-bit types' tuning modules (every variant) compile too
+        hw = cc.coot_expr_compile(W, _ops(2, dt), 1)
+        assert cc.coot_tune_prepare(hw, [_opnd(cc, 100, 50, dt)] * 2, -1) == 0
+        hz = cc.coot_expr_compile(Z, _ops(4, dt), 1)
+        assert cc.coot_tune_prepare(hz, [_opnd(cc, 100, 50, dt)] * 3 + [_opnd(cc, 50, 100, dt)], -1) == 1
 
 
 def test_runnable_configurations(cc):

@@ -125,3 +125,7 @@ def test_synthetic_inputs_of_the_type(dtype):
     assert a.dtype == ew.NP[dtype] and np.all(np.abs(a) <= 1)
     if dtype == "bf16":
         assert ew.is_bf16(a)
+    spec = synth.random_tree(g, 3, 3, 5, 6, dtype)
+    ops = synth.operands_for(spec, g)
+    assert all(o.dtype == ew.NP[dtype] for o in ops)
+    assert ew.evaluate(spec.postfix, ops, spec.scalars, dtype).dtype == ew.NP[dtype]
