@@ -299,7 +299,10 @@ void coot_batch_release(coot_batch* b);
 /* Write the configuration space of a kernel family (0 flat, 1 tiled) into
  * cfgs[0..cap) and return its size (cfgs may be NULL to query the size).
  * Flat: vec {1,2,4} x ept {1,2,4,8} x waves {1,2,4,8} x grid_mult {2,4,8,16} = 192;
- * tiled: vec {1,2,4} x grid_mult {2,4,8,16} = 12. */
+ * tiled: vec {1,2,4} x grid_mult {2,4,8,16} = 12.  For the 16-bit types vec 8
+ * (16-byte groups) is valid too: their tuning modules hold those variants,
+ * coot_tune_table accepts them (NaN for other types) and coot_tune's exhaustive
+ * policy adds them to this space. */
 uint32_t coot_tune_space(int32_t family, coot_launch_cfg* cfgs, uint32_t cap);
 
 /* Compile (or fetch) the tuning module for these operands without a device and

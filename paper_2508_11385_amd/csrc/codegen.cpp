@@ -173,9 +173,11 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
   };
   const std::string hs = h.substr(0, 16);
   if (rq.all_variants) {
-    // tuning module: every variant of the family (vec in {1,2,4}; ept in {1,2,4,8} for flat kernels)
+    // tuning module: every variant of the family (vec in {1,2,4}, and 8 for 16-bit types;
+    // ept in {1,2,4,8} for flat kernels)
     const int ts = rq.var.ts;
-    for (int v : {1, 2, 4}) {
+    for (int v : {1, 2, 4, 8}) {
+      if (v == 8 && !dtype_is_half(e.dtype)) continue;
       for (int ept : {1, 2, 4, 8}) {
         if (rq.fam == FAM_TILE && ept != 1) continue;
         if (rq.fam == FAM_TILE && v > ts / 4) continue;

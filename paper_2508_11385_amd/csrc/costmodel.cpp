@@ -518,6 +518,9 @@ coot_status coot_tune(coot_expr* h, const coot_operand* operands, const double* 
       cand.push_back(d);
     } else if (policy == 1) {
       cand = space;
+      if (dtype_is_half(h->e->dtype))  // 16-byte groups of 16-bit elements as well
+        for (const auto& c : space)
+          if (c.vec == 4) cand.push_back({8, c.ept, c.waves, c.grid_mult});
     } else if (policy == 2) {
       if (!cm) fail(COOT_EINVAL, "the MLP policy needs a cost model");
       int64_t R, C;

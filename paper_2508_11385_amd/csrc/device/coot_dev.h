@@ -79,17 +79,14 @@ template <> struct St<f16> {
   typedef float C;
   static __device__ __forceinline__ float in(f16 x) { return (float)__builtin_bit_cast(_Float16, x.b); }
   static __device__ __forceinline__ f16 out(float x) { return f16{__builtin_bit_cast(unsigned short, (_Float16)x)}; }
-  // nearest-even binary16 value of x, kept in binary32, by integer steps on the
-  // binary32 fields (no conversion instructions between operators): normal range:
-  // round the fraction to 10 bits; from 65520 on: infinity; below 2^-14: the
-  // spacing 2^-24 is that of binary32 at 0.5, so x + 0.5 rounds it
+  // nearest-even binary16 value of x, kept in binary32: the hardware conversions
+  // there and back (two instructions).  They are written as one asm statement so
+  // that the compiler sees an opaque value between operators: folding the
+  // conversions into neighbouring operators has crashed its instruction selection.
   static __device__ __forceinline__ float rnd(float x) {
-    const u32 u = __float_as_uint(x), a = u & 0x7fffffffu, sg = u & 0x80000000u;
-    if (a >= 0x7f800000u) return x;                         // infinities and NaN
-    if (a >= 0x477ff000u) return __uint_as_float(sg | 0x7f800000u);
-    if (a >= 0x38800000u) return __uint_as_float(sg | ((a + 0xfffu + ((a >> 13) & 1u)) & 0xffffe000u));
-    const float v = (__uint_as_float(a) + 0.5f) - 0.5f;    // exact subtraction
-    return __uint_as_float(sg | __float_as_uint(v));
+    float r;
+    asm("v_cvt_f16_f32 %0, %1\n\tv_cvt_f32_f16 %0, %0" : "=v"(r) : "v"(x));
+    return r;
   }
 };
 template <> struct St<bf16> {
@@ -100,7 +97,13 @@ template <> struct St<bf16> {
     if ((u & 0x7fffffffu) > 0x7f800000u) return bf16{(unsigned short)((u >> 16) | 0x40u)};  // NaN: quiet, kept
     return bf16{(unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16)};                  // nearest-even
   }
-  static __device__ __forceinline__ float rnd(float x) { return in(out(x)); }
+  // nearest-even bfloat16 value of x, kept in binary32: the packed conversion
+  // (both halves from x) and a mask keeping one of them
+  static __device__ __forceinline__ float rnd(float x) {
+    float r;
+    asm("v_cvt_pk_bf16_f32 %0, %1, %1\n\tv_and_b32 %0, 0xffff0000, %0" : "=v"(r) : "v"(x));
+    return r;
+  }
 };
 
 template <typename T> struct is_int_t { static constexpr bool v = false; };

@@ -162,9 +162,14 @@ static bool aligned(const void* p, size_t bytes) { return ((uintptr_t)p % bytes)
 //   flat family:   16-byte groups, 1 group per thread per trip, 4 waves, 4 workgroups per CU
 //   tiled family:  2-element groups, 4 waves (fixed), 8 workgroups per CU
 //   dimension sums: 16-byte groups (one workgroup per segment)
+// (the tables hold 32- and 64-bit types; the 16-bit types' defaults are measured)
 coot_launch_cfg default_cfg(int fam, int mode, int dim, int dtype, int64_t n) {
-  const uint16_t v16 = dtype == COOT_F64 ? 2 : 4;
+  const uint16_t v16 = dtype == COOT_F64 ? 2 : (dtype_is_half(dtype) ? 8 : 4);  // 16-byte groups
   if (mode == COOT_RED_SUM && dim >= 0) return {v16, 0, 4, 8};
+  // 16-bit types: 16-byte groups, 8 waves and 16 workgroups per CU for element-wise
+  // flat launches, 16 workgroups per CU for tiles (measured on the 4096 x 4096 step)
+  if (dtype_is_half(dtype) && fam == FAM_FLAT && mode < 0) return {8, 1, 8, 16};
+  if (dtype_is_half(dtype) && fam != FAM_FLAT) return {8, 0, 4, 16};
   if (fam == FAM_FLAT) {
     // Past 2^24 elements (the streaming regime) fewer, longer-lived workgroups win:
     // the best geomean over the largest signatures of the autotuner's timing tables.
@@ -204,7 +209,9 @@ Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, in
   const coot_launch_cfg c = resolve_cfg(cfg, rq.fam, mode, dim, e.dtype, R * C);
   rq.var.vec = c.vec;
   rq.var.ept = c.ept ? c.ept : 1;
-  if (rq.var.vec != 1 && rq.var.vec != 2 && rq.var.vec != 4) fail(COOT_EINVAL, "vec must be 1, 2 or 4");
+  // vec 8 (16-byte groups) for the 16-bit types only
+  if (rq.var.vec != 1 && rq.var.vec != 2 && rq.var.vec != 4 && !(rq.var.vec == 8 && dtype_is_half(e.dtype)))
+    fail(COOT_EINVAL, "vec must be 1, 2 or 4 (or 8 for 16-bit types)");
   if (rq.var.ept != 1 && rq.var.ept != 2 && rq.var.ept != 4 && rq.var.ept != 8) fail(COOT_EINVAL, "ept must be 1, 2, 4 or 8");
   // tile edge: 64, or 32 when the LDS staging of transposed leaves would exceed 64 KiB
   const size_t es = dtype_size(e.dtype);

@@ -52,6 +52,7 @@ Prepared prepare(Expr& e, const coot_operand* ops, const coot_operand* out, int 
 // Whether a configuration can run on these operands (vector width vs alignment and tile).
 bool cfg_runnable(Expr& e, const Prepared& p, const coot_launch_cfg& c, const coot_operand* ops,
                   const coot_operand* out) {
+  if (c.vec == 8 && !dtype_is_half(e.dtype)) return false;  // 16-byte groups of 16-bit elements only
   Request rq = p.rq;
   rq.var.vec = c.vec;
   if (rq.fam == FAM_TILE && c.vec > rq.var.ts / 4) return false;
@@ -95,7 +96,7 @@ bool launch_cfg(Expr& e, Prepared& p, const coot_launch_cfg& c, const coot_opera
 
 bool valid_cfg(const coot_launch_cfg& c) {
   auto pow2 = [](int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; };
-  return pow2(c.vec, 1, 4) && pow2(c.ept, 1, 8) && pow2(c.waves, 1, 8) && pow2(c.grid_mult, 1, 16);
+  return pow2(c.vec, 1, 8) && pow2(c.ept, 1, 8) && pow2(c.waves, 1, 8) && pow2(c.grid_mult, 1, 16);
 }
 
 }  // namespace

@@ -162,3 +162,58 @@ def test_halves_outside_batches_and_cost_model(coot):
     with pytest.raises(cc.CootError) as e:
         cc.coot_costmodel_features(h, 4, 4, 0, [(4, 1, 4, 4)])
     assert e.value.status == cc.COOT_EUNSUPPORTED
+
+
+def _edge_values(dtype):
+    """Finite extremes, subnormals, zeros of both signs, infinities and NaN of the type."""
+    if dtype == "f16":
+        bits = [0x0000, 0x8000, 0x3C00, 0xBC00, 0x7BFF, 0xFBFF, 0x0400, 0x0001, 0x0003, 0x03FF, 0x2E66, 0x63D0,
+                0x7C00, 0xFC00, 0x7E00]
+        return np.array(bits, np.uint16).view(np.float16)
+    bits = [0x0000, 0x8000, 0x3F80, 0xBF80, 0x7F7F, 0xFF7F, 0x0080, 0x0001, 0x0003, 0x007F, 0x3DCD, 0x7149,
+            0x7F80, 0xFF80, 0x7FC0]
+    return (np.array(bits, np.uint32) << 16).view(np.float32)
+
+
+@pytest.mark.parametrize("dtype", HALVES)
+def test_special_values(coot, dtype):
+    """Every pair of edge values through each operator: overflow to infinity, gradual
+    underflow, signed zeros, NaN propagation, as the oracle rounds them."""
+    v = _edge_values(dtype)
+    n = len(v)
+    A = np.repeat(v[:, None], n, axis=1)
+    B = np.repeat(v[None, :], n, axis=0)
+    gA, gB = up(coot, A, dtype), up(coot, B, dtype)
+    cases = [
+        ([("load", 0), ("load", 1), ("add",)], gA + gB, []),
+        ([("load", 0), ("load", 1), ("sub",)], gA - gB, []),
+        ([("load", 0), ("load", 1), ("schur",)], gA % gB, []),
+        ([("load", 0), ("load", 1), ("div",)], gA / gB, []),
+        ([("load", 0), ("sqrt",)], coot.sqrt(gA), []),
+        ([("load", 0), ("exp",)], coot.exp(gA), []),
+        ([("load", 0), ("log",)], coot.log(gA), []),
+        ([("load", 0), ("square",)], coot.square(gA), []),
+        ([("load", 0), ("neg",), ("abs",)], coot.abs(-gA), []),
+        ([("scalar", 0), ("load", 0), ("schur",), ("load", 1), ("add",)], 0.001 * gA + gB, [0.001]),
+        ([("load", 0), ("scalar", 0), ("schur",)], gA * 1e-3, [1e-3]),
+    ]
+    for post, e, sc in cases:
+        got = coot.eval(e).numpy()
+        want = ew.evaluate(post, [A, B][:1 + any(p == ("load", 1) for p in post)], sc, dtype)
+        assert_exact(got, want, dtype, str(post))
+
+
+@pytest.mark.parametrize("dtype", HALVES)
+@pytest.mark.parametrize("cfg", [(8, 1, 4, 4), (8, 4, 2, 8), (8, 1, 4, 16), (4, 2, 8, 2)])
+def test_sixteen_byte_groups(coot, dtype, cfg):
+    """vec 8: 16-byte accesses of 16-bit elements, flat and tiled, ragged shapes."""
+    for r, c in ((130, 257), (1000, 3), (64, 64)):
+        A, B, C, D = synth.matrix_inputs(n_rows=r, n_cols=c, dtype=dtype)
+        gA, gB, gC, gD = (up(coot, x, dtype) for x in (A, B, C, D))
+        Z = coot.eval(_z(coot, gA, gB, gC, gD), cfg=cfg).numpy()
+        W = coot.eval(_w(coot, gA, gB), cfg=cfg).numpy()
+        assert_exact(Z, ew.evaluate(Z_POST, [A, B, C, D], [2.0], dtype), dtype, f"Z {cfg}")
+        assert_exact(W, ew.evaluate(W_POST, [A, B], [1.0], dtype), dtype, f"W {cfg}")
+        s0 = coot.sum(_z(coot, gA, gB, gC, gD), 0, cfg=cfg).numpy().ravel()
+        want = [rd.round_exact(q, dtype) for q in rd.sum_dim(ew.evaluate(Z_POST, [A, B, C, D], [2.0], dtype), 0, dtype)]
+        assert ulp16(s0, want, dtype).max() <= 1
