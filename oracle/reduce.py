@@ -1,7 +1,9 @@
 """Exact reductions that close an expression (test infrastructure only).
 
 accu (sum of all elements, Fig. 1 and Section 5 task 1), sum along a dimension,
-dot and norm, defined as the exact sum of the real values that enter them.
+dot and norm, defined as the exact sum of the real values that enter them; and
+the further closing reductions min, max, mean, 1-norm and infinity norm (Armadillo
+functions of the same names), from the same exact sums or the element values.
 
 * Floating types: each binary32 / binary64 value is an integer mantissa times a
   power of two.  Mantissas are summed per exponent in integer-exact arithmetic
@@ -225,6 +227,70 @@ def norm(x, dtype: str) -> float:
     k = (s.numerator.bit_length() - s.denominator.bit_length()) // 2
     scaled = s / Fraction(2) ** (2 * k)
     return math.ldexp(math.sqrt(float(scaled)), k)
+
+
+# ---------------------------------------------------------------------------
+# Further closing reductions (min, max, mean, 1-norm, infinity norm)
+# ---------------------------------------------------------------------------
+
+def _values(x, dtype):
+    x = np.asarray(x).ravel()
+    if x.size == 0:
+        raise ValueError("min / max of an empty operand")
+    return x
+
+
+def vmax(x, dtype):
+    """Largest element (an element value of the type).  NaN as soon as one element is
+    NaN (the NaN-propagating maximum of IEEE 754-2019)."""
+    x = _values(x, dtype)
+    if dtype in FLOATS:
+        x64 = x.astype(np.float64)
+        if np.isnan(x64).any():
+            return math.nan
+        return float(x64.max())
+    return int(x.astype(np.int64).max())
+
+
+def vmin(x, dtype):
+    """Smallest element, NaN-propagating like vmax."""
+    x = _values(x, dtype)
+    if dtype in FLOATS:
+        x64 = x.astype(np.float64)
+        if np.isnan(x64).any():
+            return math.nan
+        return float(x64.min())
+    return int(x.astype(np.int64).min())
+
+
+def mean(x, dtype) -> Fraction:
+    """Exact mean: the exact sum divided by the element count (floating types)."""
+    if dtype not in FLOATS:
+        raise ValueError("mean is defined here for floating types only")
+    x = np.asarray(x)
+    if x.size == 0:
+        raise ValueError("mean of an empty operand")
+    return exact_sum(x) / x.size
+
+
+def norm1(x, dtype) -> Fraction:
+    """1-norm of the elements taken as a vector: the exact sum of |x_i|."""
+    if dtype not in FLOATS:
+        raise ValueError("norm1 is defined here for floating types only")
+    return exact_sum(np.abs(np.asarray(x)))
+
+
+def norm_inf(x, dtype) -> float:
+    """Infinity norm of the elements taken as a vector: the largest |x_i| (0 for an empty
+    operand), NaN as soon as one element is NaN."""
+    if dtype not in FLOATS:
+        raise ValueError("norm_inf is defined here for floating types only")
+    x64 = np.abs(np.asarray(x).astype(np.float64)).ravel()
+    if x64.size == 0:
+        return 0.0
+    if np.isnan(x64).any():
+        return math.nan
+    return float(x64.max())
 
 
 def rel_err(got: float, ref: Fraction, scale: float) -> float:
