@@ -122,7 +122,12 @@ typedef enum {
   COOT_RED_ACCU = 0, /* sum of all elements -> 1 element */
   COOT_RED_SUM = 1,  /* sum along dim: 0 -> 1 x n_cols (per column), 1 -> n_rows x 1 (per row) */
   COOT_RED_DOT = 2,  /* dot(a, b): the expression's root must be a % b -> 1 element */
-  COOT_RED_NORM = 3  /* 2-norm (Frobenius for a matrix) -> 1 element; floating types only */
+  COOT_RED_NORM = 3, /* 2-norm (Frobenius for a matrix) -> 1 element; floating types only */
+  COOT_RED_MIN = 4,  /* smallest element -> 1 element; NaN if any element is NaN */
+  COOT_RED_MAX = 5,  /* largest element -> 1 element; NaN if any element is NaN */
+  COOT_RED_MEAN = 6, /* sum / number of elements -> 1 element; floating types only */
+  COOT_RED_NORM1 = 7,  /* sum of |x| (1-norm of the elements as a vector); floating types only */
+  COOT_RED_NORMINF = 8 /* largest |x| (infinity norm of the elements); floating; NaN if any is NaN */
 } coot_red;
 
 /* compile flags */
@@ -204,14 +209,17 @@ coot_status coot_expr_eval(coot_expr* e, const coot_operand* operands, const dou
  *   kind, dim   see coot_red; dim ignored except for COOT_RED_SUM
  *   flags       0 (compensated: float-float / double-double per-lane sums) or
  *               COOT_RF_PLAIN (uncompensated comparator)
- *   out         device output of the expression's dtype: 1 element for ACCU,
- *               DOT, NORM; 1 x n_cols for SUM dim 0; n_rows x 1 for SUM dim 1
+ *   out         device output of the expression's dtype: 1 element for every
+ *               kind but SUM; 1 x n_cols for SUM dim 0; n_rows x 1 for SUM dim 1
  * accu of an expression whose root is a % b is evaluated as dot (the product
- * error is carried, not rounded away).  Integer sums wrap mod 2^32.  The result
- * is deterministic: a fixed combine order and no floating-point atomics.
- * Workspace is taken from a per-stream cache owned by the library.
- * Errors: as coot_expr_eval; COOT_ETYPE for NORM of an integer expression,
- * COOT_EINVAL for DOT whose root is not a Schur product. */
+ * error is carried, not rounded away).  Integer sums wrap mod 2^32.  MEAN and
+ * NORM1 use the compensated sum (MEAN divides it by the element count in
+ * binary64 and rounds once); MIN, MAX and NORMINF are exact (an element value).
+ * The result is deterministic: a fixed combine order and no floating-point
+ * atomics.  Workspace is taken from a per-stream cache owned by the library.
+ * Errors: as coot_expr_eval; COOT_ETYPE for NORM, MEAN, NORM1, NORMINF of an
+ * integer expression; COOT_EINVAL for DOT whose root is not a Schur product and
+ * for MIN, MAX, MEAN of an empty expression. */
 coot_status coot_reduce(coot_expr* e, const coot_operand* operands, const double* scalars,
                         int32_t kind, int32_t dim, uint32_t flags, coot_operand* out,
                         const coot_launch_cfg* cfg, void* stream);

@@ -2,9 +2,9 @@
 
 `_coot` is the ctypes binding of libcoot's C ABI (include/coot.h); `frontend`
 holds the Armadillo-flavoured lazy expressions (Mat, trans, exp, accu, sum, dot,
-norm, eval).  Importing this package loads libcoot.so and fails if it is not
+norm, min, max, mean, norm1, norm_inf, eval).  Importing this package loads libcoot.so and fails if it is not
 built — there is no CPU fallback.
 """
 from . import _coot  # noqa: F401
-from .frontend import (Batch, Expr, Mat, Node, Scalar, abs, accu, dot, eval, exp, flatten, init, log, norm,  # noqa: F401
-                       precompile, sqrt, square, sum, trans, use_torch_allocator)
+from .frontend import (Batch, Expr, Mat, Node, Scalar, abs, accu, dot, eval, exp, flatten, init, log, max,  # noqa: F401
+                       mean, min, norm, norm1, norm_inf, precompile, sqrt, square, sum, trans, use_torch_allocator)

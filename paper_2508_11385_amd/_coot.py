@@ -21,6 +21,7 @@ COOT_MAT, COOT_COL, COOT_ROW = 0, 1, 2
 OPCODES = {"load": 0, "scalar": 1, "add": 2, "sub": 3, "schur": 4, "div": 5, "neg": 6, "abs": 7,
            "exp": 8, "log": 9, "sqrt": 10, "square": 11, "trans": 12}
 COOT_RED_ACCU, COOT_RED_SUM, COOT_RED_DOT, COOT_RED_NORM = 0, 1, 2, 3
+COOT_RED_MIN, COOT_RED_MAX, COOT_RED_MEAN, COOT_RED_NORM1, COOT_RED_NORMINF = 4, 5, 6, 7, 8
 COOT_CF_UNFUSED = 0x1
 COOT_RF_PLAIN = 0x1
 COOT_PF_COMPILE_ONLY = 0x100

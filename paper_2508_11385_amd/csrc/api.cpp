@@ -56,12 +56,11 @@ coot_status coot_expr_prepare(coot_expr* h, int32_t mode, int32_t dim, uint32_t 
   return guarded([&] {
     if (!h) fail(COOT_EINVAL, "NULL expression");
     Expr& e = *h->e;
-    if (mode < -1 || mode > COOT_RED_NORM) fail(COOT_EINVAL, "bad mode");
+    if (mode < -1 || mode > COOT_RED_NORMINF) fail(COOT_EINVAL, "bad mode");
     if (rflags & ~(COOT_RF_PLAIN | COOT_PF_COMPILE_ONLY)) fail(COOT_EINVAL, "unknown prepare flag");
     int m = mode;
     if (mode == COOT_RED_ACCU && e.root_schur) m = COOT_RED_DOT;
-    if (mode == COOT_RED_DOT && !e.root_schur) fail(COOT_EINVAL, "dot needs a % b at the root");
-    if (mode == COOT_RED_NORM && dtype_is_int(e.dtype)) fail(COOT_ETYPE, "norm of an integer expression");
+    if (mode >= 0) check_red_mode(e, mode);
     // plan with no operands: contiguous untransposed leaves are assumed (the common case)
     std::vector<coot_operand> fake(e.slots.size());
     for (size_t k = 0; k < fake.size(); ++k) {

@@ -33,7 +33,18 @@ std::string Request::key() const {
   return os.str();
 }
 
-static int red_kind(int mode) { return mode == COOT_RED_DOT ? RK_DOT : mode == COOT_RED_NORM ? RK_SUMSQ : RK_SUM; }
+int red_kind(int mode) {
+  switch (mode) {
+    case COOT_RED_DOT: return RK_DOT;
+    case COOT_RED_NORM: return RK_SUMSQ;
+    case COOT_RED_MIN: return RK_MIN;
+    case COOT_RED_MAX: return RK_MAX;
+    case COOT_RED_MEAN: return RK_MEAN;
+    case COOT_RED_NORM1: return RK_ABSSUM;
+    case COOT_RED_NORMINF: return RK_AMAX;
+    default: return RK_SUM;
+  }
+}
 
 // Kernels of a tuning module carry a "_tm" suffix, so that profiles tell tuning
 // launches from the library's own.
@@ -236,8 +247,8 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
          256);
     return os.str();
   }
-  // full reductions: accu / dot / norm
-  const int rk = rq.mode == COOT_RED_DOT ? RK_DOT : rq.mode == COOT_RED_NORM ? RK_SUMSQ : RK_SUM;
+  // full reductions: accu / dot / norm / min / max / mean / norm1 / norm_inf
+  const int rk = red_kind(rq.mode);
   const std::string rks = std::to_string(rk);
   const std::string tag = "k" + rks + "c" + (rq.comp ? "1" : "0");
   names->stage2 = "coot_rfin_" + hs + "_" + tag;

@@ -79,7 +79,12 @@ uint64_t scalar_bits(double v, int dtype);
 
 // Code generation ------------------------------------------------------------
 enum Family { FAM_FLAT = 0, FAM_TILE = 1 };
-enum RedKind { RK_SUM = 0, RK_DOT = 1, RK_SUMSQ = 2 };
+// reduction kinds of the generated kernels (the same numbers as in coot_dev.h)
+enum RedKind { RK_SUM = 0, RK_DOT = 1, RK_SUMSQ = 2, RK_ABSSUM = 3, RK_MAX = 4, RK_MIN = 5, RK_AMAX = 6, RK_MEAN = 7 };
+// the kernel kind of a full reduction mode (accu, dot, norm, min, max, mean, norm1, norm_inf)
+int red_kind(int mode);
+// a reduction mode's arguments are valid for this expression (fails with the reason)
+void check_red_mode(const Expr& e, int mode);
 
 struct Variant {  // compile-time parameters of one kernel instance
   int vec = 4;

@@ -274,7 +274,17 @@ __device__ __forceinline__ void dw_add(F& h, F& l, F h2, F l2) {
 }
 
 // Reduction kinds
-enum { RK_SUM = 0, RK_DOT = 1, RK_SUMSQ = 2 };
+enum { RK_SUM = 0, RK_DOT = 1, RK_SUMSQ = 2, RK_ABSSUM = 3, RK_MAX = 4, RK_MIN = 5, RK_AMAX = 6, RK_MEAN = 7 };
+
+// Extremum kinds carry one binary64 value per lane instead of a sum: the largest
+// value (RK_MAX), the largest negated value (RK_MIN), the largest magnitude
+// (RK_AMAX).  Every element value of every type is exact in binary64.
+template <int RK> struct RkExt { static constexpr bool v = RK == RK_MAX || RK == RK_MIN || RK == RK_AMAX; };
+template <int RK> __device__ __forceinline__ double ext_identity() {
+  return RK == RK_MAX || RK == RK_MIN ? -__builtin_inf() : 0.0;
+}
+// NaN-propagating maximum (IEEE 754-2019 maximum): NaN as soon as either is NaN
+__device__ __forceinline__ double nmax(double a, double b) { return a != a ? a : (b != b ? b : (a > b ? a : b)); }
 
 // Compensated accumulator for floating T; partial type P carries (hi, lo).
 template <typename T>
@@ -400,9 +410,17 @@ __device__ __forceinline__ void flat_eval(const coot_kargs& a) {
 // the value squared (through the accumulator's product path).
 // ===========================================================================
 template <class X, int RK, class A>
-__device__ __forceinline__ void consume(A& acc, const typename X::T* L, const u64* sc) {
-  if constexpr (RK == RK_SUM) {
+__device__ __forceinline__ void consume(A& acc, double& mx, const typename X::T* L, const u64* sc) {
+  if constexpr (RK == RK_SUM || RK == RK_MEAN) {
     acc.add(X::f(L, sc));
+  } else if constexpr (RK == RK_ABSSUM) {
+    acc.add(op_abs(X::f(L, sc)));
+  } else if constexpr (RK == RK_MAX) {
+    mx = nmax(mx, (double)X::f(L, sc));
+  } else if constexpr (RK == RK_MIN) {
+    mx = nmax(mx, -(double)X::f(L, sc));
+  } else if constexpr (RK == RK_AMAX) {
+    mx = nmax(mx, __builtin_fabs((double)X::f(L, sc)));
   } else if constexpr (RK == RK_DOT) {
     typename X::T p, q;
     X::f2(L, sc, p, q);
@@ -477,7 +495,7 @@ __device__ __forceinline__ void block_words_to_record(double h, double l, double
     h = wave_sum<double>(h);
   }
 #pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) amax = __builtin_fmax(amax, __shfl_xor(amax, m, 64));
+  for (int m = 32; m >= 1; m >>= 1) amax = nmax(amax, __shfl_xor(amax, m, 64));
   const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   if ((threadIdx.x & 63) == 0) {
     sh[w] = h;
@@ -497,7 +515,7 @@ __device__ __forceinline__ void block_words_to_record(double h, double l, double
       } else {
         H = H + sh[k];
       }
-      M = __builtin_fmax(M, sm[k]);
+      M = nmax(M, sm[k]);
     }
     PartRec r;
     r.hi = H;
@@ -533,7 +551,7 @@ __device__ __forceinline__ void flat_reduce(const coot_kargs& a) {
   }
   Acc acc;
   acc.init();
-  double amax = 0.0;
+  double amax = ext_identity<RK>();
   const i64 n = a.n_rows * a.n_cols;
   const i64 nv = n / V;
   const int bs = blockDim.x;
@@ -560,7 +578,7 @@ __device__ __forceinline__ void flat_reduce(const coot_kargs& a) {
             val = val * scale;
             acc.add_prod(val, val);
           } else {
-            consume<X, RK>(acc, L, a.sc);
+            consume<X, RK>(acc, amax, L, a.sc);
           }
         }
       }
@@ -577,7 +595,7 @@ __device__ __forceinline__ void flat_reduce(const coot_kargs& a) {
         val = val * scale;
         acc.add_prod(val, val);
       } else {
-        consume<X, RK>(acc, L, a.sc);
+        consume<X, RK>(acc, amax, L, a.sc);
       }
     }
   }
@@ -692,7 +710,7 @@ struct AllSink {
       val = val * scale;
       acc.add_prod(val, val);
     } else {
-      consume<X, RK>(acc, L, a.sc);
+      consume<X, RK>(acc, amax, L, a.sc);
     }
   }
   __device__ __forceinline__ void group(const coot_kargs&, i64, i64, int, int, bool) {}
@@ -704,7 +722,7 @@ __device__ __forceinline__ void tiled_reduce(const coot_kargs& a) {
   typedef typename X::T T;
   AllSink<X, RK, COMP, SCALED> s;
   s.acc.init();
-  s.amax = 0.0;
+  s.amax = ext_identity<RK>();
   s.scale = (T)1;
   if constexpr (SCALED) {
     const double* ctl = (const double*)a.ws2;
@@ -736,7 +754,7 @@ __device__ __forceinline__ void reduce_stage2(const coot_kargs& a) {
     if (ctl[0] == 0.0) return;
   }
   constexpr bool is_int = is_int_t<T>::v;
-  double H = 0.0, Lo = 0.0, M = 0.0;
+  double H = 0.0, Lo = 0.0, M = ext_identity<RK>();
   for (i64 k = threadIdx.x; k < a.n_part; k += 256) {
     const PartRec r = recs[k];
     if (is_int) {
@@ -748,7 +766,7 @@ __device__ __forceinline__ void reduce_stage2(const coot_kargs& a) {
     } else {
       H = H + r.hi;
     }
-    M = __builtin_fmax(M, r.amax);
+    M = nmax(M, r.amax);
   }
   sh[threadIdx.x] = H;
   sl[threadIdx.x] = Lo;
@@ -769,15 +787,21 @@ __device__ __forceinline__ void reduce_stage2(const coot_kargs& a) {
       }
       sh[threadIdx.x] = h1;
       sl[threadIdx.x] = l1;
-      sm[threadIdx.x] = __builtin_fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
+      sm[threadIdx.x] = nmax(sm[threadIdx.x], sm[threadIdx.x + s]);
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     S* out = (S*)a.out;
     const double tot = sh[0] + sl[0];
-    if (is_int) {
+    if (RK == RK_MAX || RK == RK_AMAX) {
+      out[0] = St<S>::out((T)sm[0]);  // an element value (or its magnitude): exact
+    } else if (RK == RK_MIN) {
+      out[0] = St<S>::out((T)(-sm[0]));
+    } else if (is_int) {
       out[0] = St<S>::out((T)(u32)sh[0]);
+    } else if (RK == RK_MEAN) {
+      out[0] = St<S>::out((T)(tot / (double)(a.n_rows * a.n_cols)));
     } else if (RK != RK_SUMSQ) {
       // one rounding from binary64 (a second one, to a 16-bit type, is innocuous)
       out[0] = St<S>::out((T)tot);

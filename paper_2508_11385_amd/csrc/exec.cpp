@@ -321,6 +321,14 @@ void eval_fused(Expr& e, const coot_operand* ops, const double* scalars, const c
   }
 }
 
+void check_red_mode(const Expr& e, int mode) {
+  if (mode < COOT_RED_ACCU || mode > COOT_RED_NORMINF) fail(COOT_EINVAL, "unknown reduction");
+  if (mode == COOT_RED_DOT && !e.root_schur) fail(COOT_EINVAL, "dot needs an expression whose root is a % b");
+  const bool float_only = mode == COOT_RED_NORM || mode == COOT_RED_MEAN || mode == COOT_RED_NORM1 ||
+                          mode == COOT_RED_NORMINF;
+  if (float_only && dtype_is_int(e.dtype)) fail(COOT_ETYPE, "norm / mean of an integer expression");
+}
+
 void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int kind, int dim, uint32_t flags,
                   const coot_operand& out, const coot_launch_cfg* cfg, hipStream_t s) {
   check_operands(e, ops);
@@ -329,10 +337,10 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
   if (out.dtype != e.dtype) fail(COOT_ETYPE, "output element type differs from the expression's");
   int mode = kind;
   if (kind == COOT_RED_ACCU && e.root_schur) mode = COOT_RED_DOT;  // accu(x % y) is dot(x, y)
-  if (kind == COOT_RED_DOT && !e.root_schur) fail(COOT_EINVAL, "dot needs an expression whose root is a % b");
-  if (kind == COOT_RED_NORM && dtype_is_int(e.dtype)) fail(COOT_ETYPE, "norm of an integer expression");
+  check_red_mode(e, kind);
   if (kind == COOT_RED_SUM && dim != 0 && dim != 1) fail(COOT_EINVAL, "sum needs dim 0 or 1");
-  if (kind < COOT_RED_ACCU || kind > COOT_RED_NORM) fail(COOT_EINVAL, "unknown reduction");
+  if ((kind == COOT_RED_MIN || kind == COOT_RED_MAX || kind == COOT_RED_MEAN) && R * C == 0)
+    fail(COOT_EINVAL, "min / max / mean of an empty expression");
   int64_t n_out = 1;
   if (kind == COOT_RED_SUM) {
     n_out = dim == 0 ? C : R;

@@ -14,6 +14,8 @@ computed by libcoot's kernels.
 """
 from __future__ import annotations
 
+import builtins
+
 import numpy as np
 import torch
 
@@ -113,7 +115,7 @@ class Mat(Expr):
         self.dtype = dtype
         self.kind = kind
         self.n_rows, self.n_cols = r, c
-        self.ld = int(s1) if (c > 1 and r > 0) else max(1, r)
+        self.ld = int(s1) if (c > 1 and r > 0) else builtins.max(1, r)
 
     # ---- construction ---------------------------------------------------------------
     @staticmethod
@@ -264,7 +266,7 @@ def precompile(exprs, workers: int = 12) -> list:
         slots = tuple((cc.DTYPE_CODE[m.dtype], _KIND[m.kind]) for m in f.mats)
         jobs[(tuple(f.postfix), slots, len(f.scalars))] = None
     if workers > 1 and len(jobs) > 1 and not os.environ.get("COOT_NO_DISK_CACHE"):
-        with mp.get_context("spawn").Pool(min(workers, len(jobs))) as pool:
+        with mp.get_context("spawn").Pool(builtins.min(workers, len(jobs))) as pool:
             list(pool.imap_unordered(_prepare_worker, list(jobs), chunksize=4))
     for f in flats:
         cc.coot_expr_prepare(compiled(f), -1)
@@ -345,6 +347,31 @@ def dot(a, b, plain=False, cfg=None, unfused=False) -> Mat:
 def norm(e, plain=False, cfg=None, unfused=False) -> Mat:
     """2-norm of a vector / Frobenius norm of a matrix expression."""
     return _reduce(e, cc.COOT_RED_NORM, -1, plain, lambda r, c: (1, 1), cfg, unfused)
+
+
+def min(e, cfg=None, unfused=False) -> Mat:  # noqa: A001 — the Armadillo name
+    """Smallest element, as a 1x1 device Mat (NaN if any element is NaN)."""
+    return _reduce(e, cc.COOT_RED_MIN, -1, False, lambda r, c: (1, 1), cfg, unfused)
+
+
+def max(e, cfg=None, unfused=False) -> Mat:  # noqa: A001
+    """Largest element, as a 1x1 device Mat (NaN if any element is NaN)."""
+    return _reduce(e, cc.COOT_RED_MAX, -1, False, lambda r, c: (1, 1), cfg, unfused)
+
+
+def mean(e, plain=False, cfg=None, unfused=False) -> Mat:
+    """Mean of all elements (compensated sum / count, rounded once)."""
+    return _reduce(e, cc.COOT_RED_MEAN, -1, plain, lambda r, c: (1, 1), cfg, unfused)
+
+
+def norm1(e, plain=False, cfg=None, unfused=False) -> Mat:
+    """Sum of |x| over the elements (the 1-norm of the elements taken as a vector)."""
+    return _reduce(e, cc.COOT_RED_NORM1, -1, plain, lambda r, c: (1, 1), cfg, unfused)
+
+
+def norm_inf(e, cfg=None, unfused=False) -> Mat:
+    """Largest |x| over the elements (the infinity norm of the elements as a vector)."""
+    return _reduce(e, cc.COOT_RED_NORMINF, -1, False, lambda r, c: (1, 1), cfg, unfused)
 
 
 def init(device: int = 0) -> None:

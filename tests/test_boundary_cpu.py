@@ -112,6 +112,12 @@ FAMILIES = [
     (Z, 4, 1, 0, -1, 1, 4, 0, 64, "f16"),
     ([("load", 0)], 1, 0, 3, -1, 0, 4, 8, 0, "f16"),
     ([("load", 0), ("load", 1), ("schur",)], 2, 0, 2, -1, 0, 4, 4, 0, "bf16"),
+    (Z, 4, 1, 4, -1, 1, 4, 0, 64, "f32"),     # min, tiled
+    (W, 2, 1, 5, -1, 0, 4, 4, 0, "f64"),      # max, flat
+    ([("load", 0)], 1, 0, 5, -1, 0, 4, 4, 0, "s32"),
+    (W, 2, 1, 6, -1, 0, 4, 4, 0, "f32"),      # mean
+    (Z, 4, 1, 7, -1, 1, 2, 0, 32, "f64"),     # norm1
+    (W, 2, 1, 8, -1, 0, 8, 1, 0, "f16"),      # norm_inf
 ]
 
 
