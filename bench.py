@@ -489,12 +489,15 @@ def bench_suite(args):
     both("accu_2^28_f32", lambda c: coot.accu(gh, cfg=c), gh, o1, cc.COOT_RED_ACCU, nb)
     # (the autotuner covers element-wise evaluation and accu: norm and the plain sum run
     # with the library defaults)
-    for name, fn in (("norm", lambda: coot.norm(gh)), ("accu_plain", lambda: coot.accu(gh, plain=True))):
+    for name, fn in (("norm", lambda: coot.norm(gh)), ("accu_plain", lambda: coot.accu(gh, plain=True)),
+                     ("max", lambda: coot.max(gh)), ("min", lambda: coot.min(gh)), ("mean", lambda: coot.mean(gh)),
+                     ("norm1", lambda: coot.norm1(gh)), ("norm_inf", lambda: coot.norm_inf(gh))):
         us = gpu_us(fn)
         res[f"{name}_2^28_f32"] = {"us": round(us, 1), "GBps": round(nb / us / 1e3, 1)}
     out = {"metric": "throughput of the other workloads (GB/s of algorithmic bytes)", "value": None,
            "unit": "GB/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic, seeded, resident in HBM",
-           "config": {"workload": "axpy+dot 1e6 f32; 4096^2 step f64, f16, bf16; u32/s32 8192^2; accu/norm 2^28 f32"},
+           "config": {"workload": "axpy+dot 1e6 f32; 4096^2 step f64, f16, bf16; u32/s32 8192^2; "
+                              "accu/norm/min/max/mean/norm1/norm_inf 2^28 f32"},
            "results": res}
     print(json.dumps(out), flush=True)
 

@@ -276,15 +276,46 @@ __device__ __forceinline__ void dw_add(F& h, F& l, F h2, F l2) {
 // Reduction kinds
 enum { RK_SUM = 0, RK_DOT = 1, RK_SUMSQ = 2, RK_ABSSUM = 3, RK_MAX = 4, RK_MIN = 5, RK_AMAX = 6, RK_MEAN = 7 };
 
-// Extremum kinds carry one binary64 value per lane instead of a sum: the largest
-// value (RK_MAX), the largest negated value (RK_MIN), the largest magnitude
-// (RK_AMAX).  Every element value of every type is exact in binary64.
-template <int RK> struct RkExt { static constexpr bool v = RK == RK_MAX || RK == RK_MIN || RK == RK_AMAX; };
+// Extremum kinds keep, per lane and in the compute type, the largest value
+// (RK_MAX), the smallest (RK_MIN) or the largest magnitude (RK_AMAX), plus a flag
+// for a NaN seen (the result is then NaN: the NaN-propagating extremum of IEEE
+// 754-2019).  The lane's value enters the partial record as one binary64 word
+// (exact for every type); RK_MIN stores it negated so that records and stage 2
+// combine every kind by the same maximum.
 template <int RK> __device__ __forceinline__ double ext_identity() {
   return RK == RK_MAX || RK == RK_MIN ? -__builtin_inf() : 0.0;
 }
-// NaN-propagating maximum (IEEE 754-2019 maximum): NaN as soon as either is NaN
+// NaN-propagating maximum of two record words
 __device__ __forceinline__ double nmax(double a, double b) { return a != a ? a : (b != b ? b : (a > b ? a : b)); }
+
+template <typename T, int RK>
+struct Ext {
+  static constexpr bool is_int = is_int_t<T>::v;
+  T m;
+  bool nan;
+  __device__ __forceinline__ void init() {
+    nan = false;
+    if constexpr (is_int) {
+      constexpr bool uns = (T)-1 > (T)0;  // u32: identities 2^32 - 1 (min) and 0 (max)
+      m = RK == RK_MIN ? (uns ? (T)0xffffffffu : (T)0x7fffffff) : (uns ? (T)0 : (T)0x80000000u);
+    } else {
+      m = RK == RK_MAX ? (T)-__builtin_inf() : (RK == RK_MIN ? (T)__builtin_inf() : (T)0);
+    }
+  }
+  __device__ __forceinline__ void add(T v) {
+    if constexpr (is_int) {
+      m = RK == RK_MIN ? (v < m ? v : m) : (v > m ? v : m);
+    } else {
+      if (RK == RK_AMAX) v = __builtin_fabs(v);
+      nan = nan || v != v;
+      m = RK == RK_MIN ? __builtin_fmin(m, v) : __builtin_fmax(m, v);  // NaN-ignoring; the flag keeps it
+    }
+  }
+  __device__ __forceinline__ double word() const {
+    const double d = nan ? __builtin_nan("") : (double)m;
+    return RK == RK_MIN ? -d : d;
+  }
+};
 
 // Compensated accumulator for floating T; partial type P carries (hi, lo).
 template <typename T>
@@ -410,17 +441,13 @@ __device__ __forceinline__ void flat_eval(const coot_kargs& a) {
 // the value squared (through the accumulator's product path).
 // ===========================================================================
 template <class X, int RK, class A>
-__device__ __forceinline__ void consume(A& acc, double& mx, const typename X::T* L, const u64* sc) {
+__device__ __forceinline__ void consume(A& acc, Ext<typename X::T, RK>& ext, const typename X::T* L, const u64* sc) {
   if constexpr (RK == RK_SUM || RK == RK_MEAN) {
     acc.add(X::f(L, sc));
   } else if constexpr (RK == RK_ABSSUM) {
     acc.add(op_abs(X::f(L, sc)));
-  } else if constexpr (RK == RK_MAX) {
-    mx = nmax(mx, (double)X::f(L, sc));
-  } else if constexpr (RK == RK_MIN) {
-    mx = nmax(mx, -(double)X::f(L, sc));
-  } else if constexpr (RK == RK_AMAX) {
-    mx = nmax(mx, __builtin_fabs((double)X::f(L, sc)));
+  } else if constexpr (RK == RK_MAX || RK == RK_MIN || RK == RK_AMAX) {
+    ext.add(X::f(L, sc));
   } else if constexpr (RK == RK_DOT) {
     typename X::T p, q;
     X::f2(L, sc, p, q);
@@ -551,7 +578,9 @@ __device__ __forceinline__ void flat_reduce(const coot_kargs& a) {
   }
   Acc acc;
   acc.init();
-  double amax = ext_identity<RK>();
+  Ext<T, RK> ext;
+  ext.init();
+  double amax = 0.0;  // largest magnitude (sum of squares: the rescaling decision)
   const i64 n = a.n_rows * a.n_cols;
   const i64 nv = n / V;
   const int bs = blockDim.x;
@@ -578,7 +607,7 @@ __device__ __forceinline__ void flat_reduce(const coot_kargs& a) {
             val = val * scale;
             acc.add_prod(val, val);
           } else {
-            consume<X, RK>(acc, amax, L, a.sc);
+            consume<X, RK>(acc, ext, L, a.sc);
           }
         }
       }
@@ -595,12 +624,13 @@ __device__ __forceinline__ void flat_reduce(const coot_kargs& a) {
         val = val * scale;
         acc.add_prod(val, val);
       } else {
-        consume<X, RK>(acc, amax, L, a.sc);
+        consume<X, RK>(acc, ext, L, a.sc);
       }
     }
   }
   double h, l;
   lane_to_words<T, COMP>(acc, h, l);
+  if constexpr (RK == RK_MAX || RK == RK_MIN || RK == RK_AMAX) amax = ext.word();
   PartRec* recs = (PartRec*)(SCALED ? (void*)((char*)a.ws2 + 64) : a.ws);
   block_words_to_record<T, COMP>(h, l, amax, recs + blockIdx.x);
 }
@@ -699,6 +729,7 @@ struct AllSink {
   typedef typename X::T T;
   typedef typename AccSel<T, COMP>::type Acc;
   Acc acc;
+  Ext<T, RK> ext;
   double amax;
   T scale;
   __device__ __forceinline__ void begin_tile() {}
@@ -710,7 +741,7 @@ struct AllSink {
       val = val * scale;
       acc.add_prod(val, val);
     } else {
-      consume<X, RK>(acc, amax, L, a.sc);
+      consume<X, RK>(acc, ext, L, a.sc);
     }
   }
   __device__ __forceinline__ void group(const coot_kargs&, i64, i64, int, int, bool) {}
@@ -722,7 +753,8 @@ __device__ __forceinline__ void tiled_reduce(const coot_kargs& a) {
   typedef typename X::T T;
   AllSink<X, RK, COMP, SCALED> s;
   s.acc.init();
-  s.amax = ext_identity<RK>();
+  s.ext.init();
+  s.amax = 0.0;
   s.scale = (T)1;
   if constexpr (SCALED) {
     const double* ctl = (const double*)a.ws2;
@@ -732,6 +764,7 @@ __device__ __forceinline__ void tiled_reduce(const coot_kargs& a) {
   tiled_walk<X, V, TS>(a, s);
   double h, l;
   lane_to_words<T, COMP>(s.acc, h, l);
+  if constexpr (RK == RK_MAX || RK == RK_MIN || RK == RK_AMAX) s.amax = s.ext.word();
   PartRec* recs = (PartRec*)(SCALED ? (void*)((char*)a.ws2 + 64) : a.ws);
   block_words_to_record<T, COMP>(h, l, s.amax, recs + blockIdx.x);
 }
