@@ -68,7 +68,13 @@ typedef enum { COOT_U32 = 0, COOT_S32 = 1, COOT_F32 = 2, COOT_F64 = 3, COOT_F16 
  * storage type.  Reductions accumulate in compensated binary32 (float-float) and
  * round the result once to the storage type.  Batches and the cost model take
  * f32 / f64 only (COOT_EUNSUPPORTED). */
-typedef enum { COOT_MAT = 0, COOT_COL = 1, COOT_ROW = 2 } coot_kind;
+typedef enum { COOT_MAT = 0, COOT_COL = 1, COOT_ROW = 2, COOT_BCAST = 3 } coot_kind;
+/* COOT_BCAST: a column vector of n_rows contiguous elements read as an n_rows x
+ * n_cols matrix whose every column is that vector (Armadillo's each_col()
+ * broadcasting: the index map's column stride is 0); ld must be 0.  A row
+ * vector broadcast down the rows is the trans() of such an operand.  Broadcast
+ * operands are read through the tiled kernels, never written, and are not taken
+ * by batches (COOT_EUNSUPPORTED). */
 
 /* ---- postfix opcodes (Section 3: eOp, eGlue and Op<.., op_trans>) -------- */
 typedef enum {
@@ -101,7 +107,7 @@ typedef struct {
   void* data;     /* device pointer, column-major */
   int64_t n_rows;
   int64_t n_cols;
-  int64_t ld;     /* leading dimension in elements, >= n_rows (0 means n_rows) */
+  int64_t ld;     /* leading dimension in elements, >= n_rows (0 means n_rows; COOT_BCAST: 0) */
   int32_t dtype;  /* coot_dtype */
   int32_t kind;   /* coot_kind */
 } coot_operand;

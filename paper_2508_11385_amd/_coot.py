@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libcoot.so")
 COOT_OK, COOT_EINVAL, COOT_ESHAPE, COOT_ETYPE, COOT_EALIAS, COOT_ECOMPILE, COOT_EHIP, COOT_ENOMEM, \
     COOT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7, -8
 COOT_U32, COOT_S32, COOT_F32, COOT_F64, COOT_F16, COOT_BF16 = 0, 1, 2, 3, 4, 5
-COOT_MAT, COOT_COL, COOT_ROW = 0, 1, 2
+COOT_MAT, COOT_COL, COOT_ROW, COOT_BCAST = 0, 1, 2, 3
 OPCODES = {"load": 0, "scalar": 1, "add": 2, "sub": 3, "schur": 4, "div": 5, "neg": 6, "abs": 7,
            "exp": 8, "log": 9, "sqrt": 10, "square": 11, "trans": 12}
 COOT_RED_ACCU, COOT_RED_SUM, COOT_RED_DOT, COOT_RED_NORM = 0, 1, 2, 3

@@ -358,6 +358,8 @@ coot_status coot_batch_create(uint32_t n, coot_expr* const* exprs, const coot_op
       if (e.leaves.size() > COOT_BATCH_MAXL) fail(COOT_EUNSUPPORTED, "too many leaves for the batch interpreter");
       const coot_operand* ops = operands[k];
       check_operands(e, ops);
+      for (size_t l = 0; l < e.slots.size(); ++l)
+        if (ops[l].kind == COOT_BCAST) fail(COOT_EUNSUPPORTED, "broadcast operands are not taken by batches");
       int64_t R = 0, C = 0;
       infer_shape(e, ops, &R, &C);
       const coot_operand& o = outs[k];

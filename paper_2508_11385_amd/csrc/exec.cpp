@@ -150,7 +150,11 @@ void launch(hipFunction_t f, unsigned grid, unsigned block, const KArgs& args, h
 }
 
 // ---- planning ------------------------------------------------------------------
-int64_t ld_of(const coot_operand& o) { return o.ld ? o.ld : (o.n_rows > 0 ? o.n_rows : 1); }
+// column stride in elements: the leading dimension, 0 for a broadcast column (COOT_BCAST)
+int64_t ld_of(const coot_operand& o) {
+  if (o.kind == COOT_BCAST) return o.n_cols > 1 ? 0 : (o.n_rows > 0 ? o.n_rows : 1);
+  return o.ld ? o.ld : (o.n_rows > 0 ? o.n_rows : 1);
+}
 
 static bool contiguous(const coot_operand& o) { return ld_of(o) == o.n_rows || o.n_cols <= 1; }
 

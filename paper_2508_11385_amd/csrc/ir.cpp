@@ -77,7 +77,7 @@ std::unique_ptr<Expr> analyse(const coot_op* ops, uint32_t n_ops, const coot_slo
   e->dtype = n_slots ? slots[0].dtype : COOT_F32;
   for (uint32_t k = 0; k < n_slots; ++k) {
     if (slots[k].dtype < COOT_U32 || slots[k].dtype > COOT_BF16) fail(COOT_EINVAL, "bad dtype in slot");
-    if (slots[k].kind < COOT_MAT || slots[k].kind > COOT_ROW) fail(COOT_EINVAL, "bad kind in slot");
+    if (slots[k].kind < COOT_MAT || slots[k].kind > COOT_BCAST) fail(COOT_EINVAL, "bad kind in slot");
     if (slots[k].dtype != e->dtype) fail(COOT_ETYPE, "operand slots have different element types");
   }
   // arity and legality
@@ -165,8 +165,12 @@ void check_operands(const Expr& e, const coot_operand* operands) {
     if (o.n_rows < 0 || o.n_cols < 0) fail(COOT_ESHAPE, "negative dimension");
     if (o.kind == COOT_COL && o.n_cols != 1) fail(COOT_ESHAPE, "a Col operand must have one column");
     if (o.kind == COOT_ROW && o.n_rows != 1) fail(COOT_ESHAPE, "a Row operand must have one row");
-    const int64_t ld = o.ld ? o.ld : o.n_rows;
-    if (ld < o.n_rows) fail(COOT_EINVAL, "leading dimension smaller than the row count");
+    if (o.kind == COOT_BCAST) {
+      if (o.ld != 0) fail(COOT_EINVAL, "a broadcast operand has ld 0 (its columns are one vector)");
+    } else {
+      const int64_t ld = o.ld ? o.ld : o.n_rows;
+      if (ld < o.n_rows) fail(COOT_EINVAL, "leading dimension smaller than the row count");
+    }
     if (!o.data && o.n_rows * o.n_cols > 0) fail(COOT_EINVAL, "NULL operand data");
   }
 }

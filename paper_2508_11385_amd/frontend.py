@@ -26,7 +26,7 @@ _TORCH = {"f32": torch.float32, "f64": torch.float64, "u32": torch.int32, "s32":
 # host arrays of each element type (bfloat16 values travel as float32 arrays)
 _NP = {"f32": np.float32, "f64": np.float64, "u32": np.uint32, "s32": np.int32, "f16": np.float16,
        "bf16": np.float32}
-_KIND = {"mat": cc.COOT_MAT, "col": cc.COOT_COL, "row": cc.COOT_ROW}
+_KIND = {"mat": cc.COOT_MAT, "col": cc.COOT_COL, "row": cc.COOT_ROW, "bcast": cc.COOT_BCAST}
 
 
 class Expr:
@@ -109,13 +109,16 @@ class Mat(Expr):
         # a stride along a dimension of extent 1 (or of an empty matrix) carries no meaning
         if r > 1 and c > 0 and s0 != 1:
             raise ValueError("storage must be column-major (row stride 1)")
-        if c > 1 and r > 0 and s1 < r:
+        if kind == "bcast":
+            if c > 1 and s1 != 0:
+                raise ValueError("a broadcast operand repeats one column (column stride 0)")
+        elif c > 1 and r > 0 and s1 < r:
             raise ValueError("storage must be column-major (column stride >= n_rows)")
         self.tensor = tensor
         self.dtype = dtype
         self.kind = kind
         self.n_rows, self.n_cols = r, c
-        self.ld = int(s1) if (c > 1 and r > 0) else builtins.max(1, r)
+        self.ld = 0 if kind == "bcast" else (int(s1) if (c > 1 and r > 0) else builtins.max(1, r))
 
     # ---- construction ---------------------------------------------------------------
     @staticmethod
@@ -155,12 +158,75 @@ class Mat(Expr):
         return cc.coot_operand(self.tensor.data_ptr(), self.n_rows, self.n_cols, self.ld,
                                cc.DTYPE_CODE[self.dtype], _KIND[self.kind])
 
+    def diag(self):
+        """The main diagonal as a 1 x min(n_rows, n_cols) Row view whose elements lie ld + 1
+        apart (trans() of it is the column Armadillo's diag() returns); it can be read in
+        expressions and updated in place (d = Z.diag(); d += 100)."""
+        n = builtins.min(self.n_rows, self.n_cols)
+        view = torch.as_strided(self.tensor, (1, n), (1, self.ld + 1), self.tensor.storage_offset())
+        return Mat(view, self.dtype, "row")
+
+    def each_col(self):
+        """Armadillo's each_col(): X.each_col() + v adds the column vector v to every column."""
+        return _Each(self, bcast_col)
+
+    def each_row(self):
+        """Armadillo's each_row(): X.each_row() % w multiplies every row by the row vector w."""
+        return _Each(self, bcast_row)
+
     def __iadd__(self, other):                       # B += 3*A : axpy, evaluated in place
         eval(self + other, out=self)
         return self
 
     def __isub__(self, other):
         eval(self - other, out=self)
+        return self
+
+
+# ---- broadcasting (each_col / each_row) ------------------------------------------------
+def bcast_col(v: Mat, n_cols: int) -> Mat:
+    """The n_rows x 1 column v repeated across n_cols columns: a broadcast operand (column
+    stride 0), read in place of a materialised copy."""
+    if v.n_cols != 1 or (v.n_rows > 1 and v.tensor.stride(0) != 1):
+        raise ValueError("bcast_col needs a contiguous column vector")
+    return Mat(v.tensor.expand(v.n_rows, n_cols), v.dtype, "bcast")
+
+
+def bcast_row(w: Mat, n_rows: int) -> Expr:
+    """The 1 x n_cols row w repeated down n_rows rows: trans() of the broadcast of w's
+    elements taken as a column."""
+    if w.n_rows != 1 or (w.n_cols > 1 and w.tensor.stride(1) != 1):
+        raise ValueError("bcast_row needs a row vector with contiguous elements")
+    return trans(bcast_col(Mat(w.tensor.t(), w.dtype, "col"), n_rows))
+
+
+class _Each:
+    """X.each_col() / X.each_row(): binary operators with a vector broadcast over X."""
+
+    def __init__(self, m: Mat, how):
+        self.m, self.how = m, how
+
+    def _b(self, v):
+        return self.how(v, self.m.n_cols if self.how is bcast_col else self.m.n_rows)
+
+    def __add__(self, v):
+        return self.m + self._b(v)
+
+    def __sub__(self, v):
+        return self.m - self._b(v)
+
+    def __mod__(self, v):
+        return self.m % self._b(v)
+
+    def __truediv__(self, v):
+        return self.m / self._b(v)
+
+    def __iadd__(self, v):
+        eval(self.m + self._b(v), out=self.m)
+        return self
+
+    def __isub__(self, v):
+        eval(self.m - self._b(v), out=self.m)
         return self
 
 
