@@ -200,14 +200,56 @@ def bcast_row(w: Mat, n_rows: int) -> Expr:
     return trans(bcast_col(Mat(w.tensor.t(), w.dtype, "col"), n_rows))
 
 
+def _leaf_trans(e, flip=False):
+    """The same expression with every trans() moved down onto the leaves (element-wise
+    operators commute with transposition)."""
+    if isinstance(e, Scalar):
+        return e
+    if isinstance(e, Mat):
+        return trans(e) if flip else e
+    if e.op == "trans":
+        return _leaf_trans(_lift(e.kids[0]), not flip)
+    return Node(e.op, [_leaf_trans(_lift(k), flip) for k in e.kids])
+
+
+def _bcast_cols(e, n_cols: int):
+    """An expression over column vectors, repeated across n_cols columns: broadcasting
+    commutes with element-wise operators, so it is pushed down to the leaves (as trans()
+    is), and every leaf becomes a broadcast operand."""
+    def rec(x):
+        if isinstance(x, Scalar):
+            return x
+        if isinstance(x, Mat):
+            return bcast_col(x, n_cols)
+        if x.op == "trans":           # a row vector read as a column
+            k = x.kids[0]
+            if isinstance(k, Mat) and k.n_rows == 1 and (k.n_cols <= 1 or k.tensor.stride(1) == 1):
+                return bcast_col(Mat(k.tensor.t(), k.dtype, "col"), n_cols)
+            raise ValueError("broadcasting needs column vectors (or rows with contiguous elements)")
+        return Node(x.op, [rec(_lift(k)) for k in x.kids])
+    return rec(_leaf_trans(_lift(e)))
+
+
+def _bcast_rows(e, n_rows: int):
+    """An expression over row vectors repeated down n_rows rows: the trans() of the
+    column broadcast of its transpose."""
+    if isinstance(e, Scalar):
+        return e
+    return trans(_bcast_cols(trans(e), n_rows))
+
+
 class _Each:
-    """X.each_col() / X.each_row(): binary operators with a vector broadcast over X."""
+    """X.each_col() / X.each_row(): binary operators with a vector (or an expression of
+    vectors) broadcast over X."""
 
     def __init__(self, m: Mat, how):
         self.m, self.how = m, how
 
     def _b(self, v):
-        return self.how(v, self.m.n_cols if self.how is bcast_col else self.m.n_rows)
+        v = _lift(v)
+        if self.how is bcast_col:
+            return _bcast_cols(v, self.m.n_cols)
+        return _bcast_rows(v, self.m.n_rows)
 
     def __add__(self, v):
         return self.m + self._b(v)
