@@ -230,6 +230,28 @@ coot_status coot_reduce(coot_expr* e, const coot_operand* operands, const double
                         int32_t kind, int32_t dim, uint32_t flags, coot_operand* out,
                         const coot_launch_cfg* cfg, void* stream);
 
+/* Two statements in one pass (multi-statement fusion): evaluate e into out and
+ * close the expression r with a full reduction into r_out, reading every operand
+ * once and writing out once (y = 2.5*x + y; d = accu(x % y) moves 12 bytes per
+ * element instead of 20).  The statement pair extends the whole-expression
+ * analysis of Section 3 across two assignments.
+ *   operands, scalars  e's operands and scalars, as in coot_expr_eval
+ *   out                e's output (it may alias an operand as in coot_expr_eval)
+ *   r_src[k]           r's operand slot k: an index into `operands` (read as
+ *                      loaded, before out is written) or -1 for the value of e just
+ *                      computed (read as out's layout)
+ *   r_scalars          r's scalars (host)
+ *   kind               COOT_RED_ACCU (DOT when r's root is a % b), DOT, MIN, MAX,
+ *                      MEAN, NORM1, NORMINF; r_out: one element of the dtype
+ * Both statements must take the flat kernels: every leaf untransposed and
+ * contiguous, out contiguous, the same shape; r may read only operands that e
+ * reads.  Errors: as coot_expr_eval and coot_reduce; COOT_EUNSUPPORTED for
+ * transposed or strided leaves, SUM / NORM, more than 32 scalars in the pair, or
+ * compile-flagged comparators. */
+coot_status coot_expr_eval_reduce(coot_expr* e, const coot_operand* operands, const double* scalars, coot_operand* out,
+                                  coot_expr* r, const int32_t* r_src, const double* r_scalars, int32_t kind,
+                                  coot_operand* r_out, const coot_launch_cfg* cfg, void* stream);
+
 /* Release a handle from coot_expr_compile.  NULL is ignored. */
 void coot_expr_release(coot_expr* e);
 

@@ -6,6 +6,7 @@ norm, min, max, mean, norm1, norm_inf, eval).  Importing this package loads libc
 built — there is no CPU fallback.
 """
 from . import _coot  # noqa: F401
-from .frontend import (Batch, Expr, Mat, Node, Scalar, abs, accu, bcast_col, bcast_row, dot, eval, exp,  # noqa: F401
+from .frontend import (Batch, Expr, Mat, Node, Scalar, abs, accu, bcast_col, bcast_row, dot, eval,  # noqa: F401
+                       eval_reduce, exp,
                        flatten, init, log, max, mean, min, norm, norm1, norm_inf, precompile, sqrt, square, sum,
                        trans, use_torch_allocator)

@@ -75,6 +75,9 @@ _sig = {
                                  C.POINTER(coot_launch_cfg), _P]),
     "coot_reduce": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(C.c_double), C.c_int32, C.c_int32,
                               C.c_uint32, C.POINTER(coot_operand), C.POINTER(coot_launch_cfg), _P]),
+    "coot_expr_eval_reduce": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(C.c_double), C.POINTER(coot_operand),
+                                        _P, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int32,
+                                        C.POINTER(coot_operand), C.POINTER(coot_launch_cfg), _P]),
     "coot_expr_release": (None, [_P]),
     "coot_expr_kernel_name": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(coot_launch_cfg), C.c_char_p,
                                         C.c_size_t]),
@@ -201,6 +204,13 @@ def coot_expr_eval(h: int, operands, scalars, out: coot_operand, cfg=None, strea
     ops = _arr(coot_operand, operands)
     sc = _arr(C.c_double, scalars)
     _check(lib.coot_expr_eval(h, ops, sc, C.byref(out), _cfg(cfg), stream))
+
+
+def coot_expr_eval_reduce(h: int, operands, scalars, out: coot_operand, r: int, r_src, r_scalars, kind: int,
+                          r_out: coot_operand, cfg=None, stream: int = 0) -> None:
+    _check(lib.coot_expr_eval_reduce(h, _arr(coot_operand, operands), _arr(C.c_double, scalars), C.byref(out), r,
+                                     _arr(C.c_int32, r_src), _arr(C.c_double, r_scalars), kind, C.byref(r_out),
+                                     _cfg(cfg), stream))
 
 
 def coot_reduce(h: int, operands, scalars, kind: int, dim: int, flags: int, out: coot_operand, cfg=None,

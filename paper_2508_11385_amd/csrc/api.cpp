@@ -96,6 +96,16 @@ coot_status coot_expr_eval(coot_expr* h, const coot_operand* operands, const dou
   });
 }
 
+coot_status coot_expr_eval_reduce(coot_expr* h, const coot_operand* operands, const double* scalars, coot_operand* out,
+                                  coot_expr* r, const int32_t* r_src, const double* r_scalars, int32_t kind,
+                                  coot_operand* r_out, const coot_launch_cfg* cfg, void* stream) {
+  return guarded([&] {
+    if (!h || !out || !r || !r_out) fail(COOT_EINVAL, "NULL argument");
+    if ((h->e->flags | r->e->flags) & COOT_CF_UNFUSED) fail(COOT_EUNSUPPORTED, "the comparator has no fused pair");
+    eval_reduce(*h->e, operands, scalars, *out, *r->e, r_src, r_scalars, kind, *r_out, cfg, (hipStream_t)stream);
+  });
+}
+
 coot_status coot_reduce(coot_expr* h, const coot_operand* operands, const double* scalars, int32_t kind, int32_t dim,
                         uint32_t flags, coot_operand* out, const coot_launch_cfg* cfg, void* stream) {
   return guarded([&] {

@@ -4,6 +4,7 @@
 // templates of coot_dev.h.  This is the fused-kernel generation the paper's
 // conclusion leaves to follow-up work, done at run time (the kernel set of
 // Section 4 is also compiled at run time and cached).
+#include <functional>
 #include <sstream>
 
 #include "core.h"
@@ -85,7 +86,10 @@ static const char* op_fn(int c) {
 
 // Emit the SSA statements of the body; returns the names of the last value and,
 // for a binary root, of its two operands.
-static void emit_body(const Expr& e, std::ostringstream& os, std::string* root, std::string* lhs, std::string* rhs) {
+// leaf(i): the index into L of LOAD op i (default: the expression's own leaf
+// list); sc_off: where the expression's scalars start in the scalar block.
+static void emit_body(const Expr& e, std::ostringstream& os, std::string* root, std::string* lhs, std::string* rhs,
+                      const std::function<int(size_t)>& leaf = nullptr, uint32_t sc_off = 0) {
   std::vector<std::string> st;
   // 16-bit storage types: every operator's binary32 result is rounded to the storage type
   const bool half = dtype_is_half(e.dtype);
@@ -95,10 +99,10 @@ static void emit_body(const Expr& e, std::ostringstream& os, std::string* root, 
     const coot_op& o = e.ops[i];
     std::string name = "t" + std::to_string(t++);
     if (o.code == COOT_OP_LOAD) {
-      os << "    const T " << name << " = L[" << e.op_leaf[i] << "];\n";
+      os << "    const T " << name << " = L[" << (leaf ? leaf(i) : e.op_leaf[i]) << "];\n";
       st.push_back(name);
     } else if (o.code == COOT_OP_SCALAR) {
-      os << "    const T " << name << " = sc_as<T>(sc[" << o.arg << "]);\n";
+      os << "    const T " << name << " = sc_as<T>(sc[" << o.arg + sc_off << "]);\n";
       st.push_back(name);
     } else if (o.code == COOT_OP_TRANS) {
       // index map already folded into the leaves
@@ -284,6 +288,84 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
     names->stage2_rescale = names->stage2 + "_rescale";
     wrap(names->stage2_rescale, "coot::reduce_stage2<X::S, " + rks + ", " + comp + ", true>(a)", 256);
   }
+  return os.str();
+}
+
+// Two statements in one pass: out = e(leaves) and a full reduction of r, whose
+// operand slot k reads e's leaf of operand r_src[k] (the value loaded before the
+// store) or, for r_src[k] = -1, the value just computed.  Both are flat (leaves
+// untransposed and contiguous).  Struct X is e; struct Z is r over e's leaves with
+// the computed value appended (L[X::NL]); r's scalars follow e's.
+std::string generate_pair(const Expr& e, const Expr& r, const std::vector<int>& r_src, int kind, const Request& rq,
+                          const std::string& h, KernelNames* names) {
+  std::ostringstream os;
+  os << "// generated by libcoot: " << e.canon << " ; then " << r.canon << "\n";
+  os << "#include \"coot_dev.h\"\n";
+  os << "namespace {\n";
+  auto head = [&](const char* nm, size_t nl) {
+    os << "struct " << nm << " {\n";
+    os << "  typedef " << dtype_cname(e.dtype) << " S;\n";
+    os << "  typedef typename coot::St<S>::C T;\n";
+    os << "  static constexpr int NL = " << nl << ";\n";
+    os << "  static constexpr int NP1 = 0;\n";
+  };
+  std::vector<int> slot, par, p1;
+  for (auto& l : e.leaves) {
+    slot.push_back((int)l.slot);
+    par.push_back(0);
+    p1.push_back(-1);
+  }
+  head("X", e.leaves.size());
+  os << meta_fn("slot", slot) << meta_fn("par", par) << meta_fn("p1", p1);
+  std::string root, lhs, rhs;
+  std::ostringstream body;
+  emit_body(e, body, &root, &lhs, &rhs);
+  os << "  static __device__ __forceinline__ T f(const T* L, const u64* sc) {\n";
+  os << "    using namespace coot;\n" << body.str() << "    return " << root << ";\n  }\n};\n";
+  // r's LOAD op i reads slot s: e's leaf of operand r_src[s], or the computed value
+  auto leaf_of = [&](size_t i) -> int {
+    const int src = r_src[r.ops[i].arg];
+    if (src < 0) return (int)e.leaves.size();
+    for (size_t k = 0; k < e.leaves.size(); ++k)
+      if ((int)e.leaves[k].slot == src) return (int)k;
+    fail(COOT_EUNSUPPORTED, "the reduction reads an operand the evaluated expression does not read");
+  };
+  head("Z", e.leaves.size() + 1);
+  std::string rroot, rlhs, rrhs;
+  std::ostringstream rbody;
+  emit_body(r, rbody, &rroot, &rlhs, &rrhs, leaf_of, e.n_scalars);
+  os << "  static __device__ __forceinline__ T f(const T* L, const u64* sc) {\n";
+  os << "    using namespace coot;\n" << rbody.str() << "    return " << rroot << ";\n  }\n";
+  os << "  static __device__ __forceinline__ void f2(const T* L, const u64* sc, T& fa, T& fb) {\n";
+  os << "    using namespace coot;\n";
+  if (r.root_schur) {
+    os << rbody.str() << "    fa = " << rlhs << ";\n    fb = " << rrhs << ";\n";
+  } else {
+    os << "    fa = f(L, sc);\n    fb = (T)1;\n";
+  }
+  os << "  }\n};\n}  // namespace\n";
+  bool has_exp = false;
+  for (auto& o : e.ops) has_exp = has_exp || o.code == COOT_OP_EXP;
+  for (auto& o : r.ops) has_exp = has_exp || o.code == COOT_OP_EXP;
+  const std::string prologue = has_exp ? "coot::exp_table_to_lds<X::T>(); " : "";
+  auto wrap = [&](const std::string& name, const std::string& call, int bounds) {
+    os << "extern \"C\" __global__ void __launch_bounds__(" << bounds << ") " << name << "(coot_kargs a) { "
+       << prologue << call << "; }\n";
+  };
+  const int V = rq.var.vec, E = rq.var.ept;
+  const std::string comp = rq.comp ? "true" : "false";
+  const std::string rks = std::to_string(red_kind(kind));
+  const std::string hs = h.substr(0, 16), tag = "k" + rks + "c" + (rq.comp ? "1" : "0");
+  auto inst = [&](int v) {
+    return "coot::flat_eval_reduce<X, Z, " + rks + ", " + comp + ", " + std::to_string(v) + ", " + std::to_string(E) +
+           ">(a)";
+  };
+  names->stage1 = "coot_fer_" + hs + "_" + tag + "_v" + std::to_string(V) + "e" + std::to_string(E);
+  names->stage1_fallback = "coot_fer_" + hs + "_" + tag + "_v1e" + std::to_string(E);
+  names->stage2 = "coot_ferfin_" + hs + "_" + tag;
+  wrap(names->stage1, inst(V), 512);
+  if (V != 1) wrap(names->stage1_fallback, inst(1), 512);
+  wrap(names->stage2, "coot::reduce_stage2<X::S, " + rks + ", " + comp + ", false>(a)", 256);
   return os.str();
 }
 

@@ -110,6 +110,9 @@ struct KernelNames {
 };
 
 std::string generate(const Expr& e, const Request& rq, const std::string& hash_hint, KernelNames* names);
+// out = e and a full reduction of r in one pass (r_src: r's slots -> e's operands, -1 = the result)
+std::string generate_pair(const Expr& e, const Expr& r, const std::vector<int>& r_src, int kind, const Request& rq,
+                          const std::string& hash_hint, KernelNames* names);
 const std::vector<std::pair<std::string, std::string>>& device_headers();
 
 // JIT + caches -----------------------------------------------------------------
@@ -125,6 +128,8 @@ struct Module {
 // Compile (or fetch) the module for a request; load it on the current device
 // unless load == false (compile-only, used where no device exists).
 std::shared_ptr<Module> get_module(Expr& e, const Request& rq, bool load);
+std::shared_ptr<Module> get_module_pair(Expr& e, const Expr& r, const std::vector<int>& r_src, int kind,
+                                        const Request& rq, bool load);
 std::string compile_source(const std::string& src, const std::string& name_hint, std::vector<char>* code);
 std::string hex128(const std::string& text);
 
@@ -156,6 +161,9 @@ void eval_fused(Expr& e, const coot_operand* ops, const double* scalars, const c
                 const coot_launch_cfg* cfg, hipStream_t s);
 void eval_unfused(Expr& e, const coot_operand* ops, const double* scalars, const coot_operand& out,
                   const coot_launch_cfg* cfg, hipStream_t s);
+void eval_reduce(Expr& e, const coot_operand* ops, const double* scalars, const coot_operand& out, Expr& r,
+                 const int32_t* r_src, const double* r_scalars, int kind, const coot_operand& r_out,
+                 const coot_launch_cfg* cfg, hipStream_t s);
 void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int kind, int dim, uint32_t flags,
                   const coot_operand& out, const coot_launch_cfg* cfg, hipStream_t s);
 // The library's launch configuration for a family when the caller gives none

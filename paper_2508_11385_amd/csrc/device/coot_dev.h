@@ -636,6 +636,67 @@ __device__ __forceinline__ void flat_reduce(const coot_kargs& a) {
 }
 
 // ===========================================================================
+// Two statements in one pass (multi-statement fusion): out = X, stored in the
+// storage type, and the full reduction of Z, whose leaves are X's leaves as
+// loaded (before the store) followed by the value just computed (L[X::NL]).
+// y = 2.5*x + y then accu(x % y) reads x and y once and writes y once.
+// ===========================================================================
+template <class X, class Z, int RK, bool COMP, int V, int E>
+__device__ __forceinline__ void flat_eval_reduce(const coot_kargs& a) {
+  typedef typename X::T T;
+  typedef typename X::S S;
+  typedef typename AccSel<T, COMP>::type Acc;
+  Acc acc;
+  acc.init();
+  Ext<T, RK> ext;
+  ext.init();
+  double amax = 0.0;
+  const i64 n = a.n_rows * a.n_cols;
+  const i64 nv = n / V;
+  const int bs = blockDim.x;
+  const i64 step = (i64)gridDim.x * bs * E;
+  S* out = (S*)a.out;
+  for (i64 b = (i64)blockIdx.x * bs * E + threadIdx.x; b < nv; b += step) {
+    vt<T, V> x[E][X::NL];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const i64 v = b + (i64)e * bs;
+      if (v < nv) load_flat<X, V>(a, v, x[e]);
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const i64 v = b + (i64)e * bs;
+      if (v < nv) {
+        vt<T, V> r;
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          T L[X::NL + 1];
+#pragma unroll
+          for (int k = 0; k < X::NL; ++k) L[k] = x[e][k].v[q];
+          L[X::NL] = r.v[q] = X::f(L, a.sc);
+          consume<Z, RK>(acc, ext, L, a.sc);
+        }
+        stc<S, V>(out + v * V, r);
+      }
+    }
+  }
+  if (V > 1 && blockIdx.x == gridDim.x - 1) {
+    for (i64 i = nv * V + threadIdx.x; i < n; i += bs) {
+      T L[X::NL + 1];
+#pragma unroll
+      for (int k = 0; k < X::NL; ++k) L[k] = leaf_at<X>(a, k, i);
+      L[X::NL] = X::f(L, a.sc);
+      out[i] = St<S>::out(L[X::NL]);
+      consume<Z, RK>(acc, ext, L, a.sc);
+    }
+  }
+  double h, l;
+  lane_to_words<T, COMP>(acc, h, l);
+  if constexpr (RK == RK_MAX || RK == RK_MIN || RK == RK_AMAX) amax = ext.word();
+  block_words_to_record<T, COMP>(h, l, amax, (PartRec*)a.ws + blockIdx.x);
+}
+
+// ===========================================================================
 // TILED traversal.  TS x TS output tiles, 256 threads.  Parity-1 leaves (stored
 // n_cols x n_rows) are read along their own contiguous dimension into LDS;
 // parity-0 leaves and the output are accessed along output columns.  Any

@@ -325,6 +325,72 @@ void eval_fused(Expr& e, const coot_operand* ops, const double* scalars, const c
   }
 }
 
+// out = e, then a full reduction of r over e's operands and the result, in one
+// pass (see generate_pair).  Both statements must be flat: every leaf untransposed
+// and contiguous; r's operand slot k is operand r_src[k] of e, or out for -1.
+void eval_reduce(Expr& e, const coot_operand* ops, const double* scalars, const coot_operand& out, Expr& r,
+                 const int32_t* r_src, const double* r_scalars, int kind, const coot_operand& r_out,
+                 const coot_launch_cfg* cfg, hipStream_t s) {
+  check_operands(e, ops);
+  int64_t R = 0, C = 0;
+  infer_shape(e, ops, &R, &C);
+  if (out.dtype != e.dtype || r.dtype != e.dtype || r_out.dtype != e.dtype)
+    fail(COOT_ETYPE, "both statements and both outputs take one element type");
+  if (out.n_rows != R || out.n_cols != C)
+    fail(COOT_ESHAPE, "output must be " + std::to_string(R) + "x" + std::to_string(C));
+  if (ld_of(out) < R || (!out.data && R * C)) fail(COOT_EINVAL, "bad output operand");
+  const size_t es = dtype_size(e.dtype);
+  check_alias(e, ops, out, es);
+  check_red_mode(r, kind);
+  if (kind == COOT_RED_SUM || kind == COOT_RED_NORM)
+    fail(COOT_EUNSUPPORTED, "a fused statement pair closes with accu, dot, min, max, mean, norm1 or norm_inf");
+  if (r_out.n_rows * r_out.n_cols != 1 || !r_out.data) fail(COOT_ESHAPE, "the reduction writes one element");
+  if (e.n_scalars + r.n_scalars > (uint32_t)kMaxScalars) fail(COOT_EUNSUPPORTED, "more than 32 scalars in the pair");
+  if (r.n_scalars && !r_scalars) fail(COOT_EINVAL, "scalars of the reduced statement missing");
+  if (!r.slots.empty() && !r_src) fail(COOT_EINVAL, "operand map of the reduced statement missing");
+  std::vector<coot_operand> rops(r.slots.size());
+  std::vector<int> src(r.slots.size());
+  for (size_t k = 0; k < r.slots.size(); ++k) {
+    src[k] = r_src[k];
+    if (src[k] == -1) {
+      rops[k] = out;
+      rops[k].kind = r.slots[k].kind;  // the result read as the slot declares it (same layout)
+    } else if (src[k] >= 0 && (size_t)src[k] < e.slots.size()) {
+      rops[k] = ops[src[k]];
+    } else {
+      fail(COOT_EINVAL, "operand map entry out of range");
+    }
+  }
+  check_operands(r, rops.data());
+  int64_t RR = 0, RC = 0;
+  infer_shape(r, rops.data(), &RR, &RC);
+  if (RR != R || RC != C) fail(COOT_ESHAPE, "the two statements have different shapes");
+  if (r.n_p1 != 0 || e.n_p1 != 0) fail(COOT_EUNSUPPORTED, "a fused statement pair reads every leaf untransposed");
+  if ((kind == COOT_RED_MIN || kind == COOT_RED_MAX || kind == COOT_RED_MEAN) && R * C == 0)
+    fail(COOT_EINVAL, "min / max / mean of an empty expression");
+  Request rq = plan(e, ops, &out, -1, -1, true, cfg);
+  if (rq.fam != FAM_FLAT) fail(COOT_EUNSUPPORTED, "a fused statement pair needs contiguous operands and output");
+  const int mode = kind == COOT_RED_ACCU && r.root_schur ? COOT_RED_DOT : kind;
+  auto m = get_module_pair(e, r, src, mode, rq, true);
+  KArgs a;
+  fill_args(e, ops, scalars, &a);
+  for (uint32_t k = 0; k < r.n_scalars; ++k) a.sc[e.n_scalars + k] = scalar_bits(r_scalars[k], e.dtype);
+  a.out = out.data;
+  a.out_ld = ld_of(out);
+  a.n_rows = R;
+  a.n_cols = C;
+  const bool v = vec_ok(e, rq, ops, &out, R, C);
+  const std::string& kn = (v || rq.var.vec == 1) ? m->names.stage1 : m->names.stage1_fallback;
+  const coot_launch_cfg c = resolve_cfg(cfg, FAM_FLAT, -1, -1, e.dtype, R * C);
+  const unsigned block = 64u * c.waves;
+  const unsigned grid = flat_grid(R * C, v ? rq.var.vec : 1, rq.var.ept, (int)block, c.grid_mult);
+  a.n_part = grid;
+  a.ws = workspace((size_t)grid * 32, s, 0);
+  launch(m->fn(kn), grid, block, a, s);
+  a.out = r_out.data;  // stage 2 writes the reduction's result
+  launch(m->fn(m->names.stage2), 1, 256, a, s);
+}
+
 void check_red_mode(const Expr& e, int mode) {
   if (mode < COOT_RED_ACCU || mode > COOT_RED_NORMINF) fail(COOT_EINVAL, "unknown reduction");
   if (mode == COOT_RED_DOT && !e.root_schur) fail(COOT_EINVAL, "dot needs an expression whose root is a % b");

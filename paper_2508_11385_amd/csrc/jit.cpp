@@ -165,6 +165,11 @@ static std::unordered_map<std::string, std::shared_ptr<Module>>& module_map() {
   return m;
 }
 
+// The module of one generated source, cached under the request key `rk` of `owner`
+// (in memory per expression, then by the source's hash process-wide and on disk).
+static std::shared_ptr<Module> module_for(Expr& e, const std::string& rk, const std::string& src,
+                                          const KernelNames& names, bool load);
+
 std::shared_ptr<Module> get_module(Expr& e, const Request& rq, bool load) {
   const std::string rk = rq.key();
   {
@@ -173,8 +178,26 @@ std::shared_ptr<Module> get_module(Expr& e, const Request& rq, bool load) {
     if (it != e.reqs.end() && (it->second->loaded || !load)) return it->second;
   }
   KernelNames names;
-  const std::string sig = hex128(e.canon);
-  const std::string src = generate(e, rq, sig, &names);
+  const std::string src = generate(e, rq, hex128(e.canon), &names);
+  return module_for(e, rk, src, names, load);
+}
+
+std::shared_ptr<Module> get_module_pair(Expr& e, const Expr& r, const std::vector<int>& r_src, int kind,
+                                        const Request& rq, bool load) {
+  std::string rk = "pair:" + rq.key() + "|" + r.canon + "|" + std::to_string(kind) + "|";
+  for (int v : r_src) rk += std::to_string(v) + ",";
+  {
+    std::lock_guard<std::mutex> g(e.mu);
+    auto it = e.reqs.find(rk);
+    if (it != e.reqs.end() && (it->second->loaded || !load)) return it->second;
+  }
+  KernelNames names;
+  const std::string src = generate_pair(e, r, r_src, kind, rq, hex128(rk + e.canon), &names);
+  return module_for(e, rk, src, names, load);
+}
+
+static std::shared_ptr<Module> module_for(Expr& e, const std::string& rk, const std::string& src,
+                                          const KernelNames& names, bool load) {
   std::string opt_text;
   for (auto& o : rtc_options()) opt_text += o + " ";
   std::string hdr_text;

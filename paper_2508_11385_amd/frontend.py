@@ -417,6 +417,36 @@ def eval(e: Expr, out: Mat | None = None, cfg=None, unfused: bool = False) -> Ma
     return out
 
 
+_RED_KIND = {"accu": cc.COOT_RED_ACCU, "dot": cc.COOT_RED_DOT, "min": cc.COOT_RED_MIN, "max": cc.COOT_RED_MAX,
+             "mean": cc.COOT_RED_MEAN, "norm1": cc.COOT_RED_NORM1, "norm_inf": cc.COOT_RED_NORMINF}
+
+
+def eval_reduce(e: Expr, out: Mat, r: Expr, kind: str = "accu", cfg=None) -> Mat:
+    """Two statements in one pass: out = e, then the reduction `kind` of r, which may read
+    e's operands and `out` (the value just computed): y = 2.5*x + y; d = accu(x % y) becomes
+    eval_reduce(2.5 * x + y, y, x % y).  Returns the 1x1 result."""
+    fe, fr = flatten(_lift(e)), flatten(_lift(r))
+    he, hr = compiled(fe), compiled(fr)
+
+    def same(a: Mat, b: Mat):
+        return (a.tensor.data_ptr() == b.tensor.data_ptr() and a.n_rows == b.n_rows and a.n_cols == b.n_cols
+                and a.ld == b.ld)
+
+    src = []
+    for m in fr.mats:
+        if same(m, out):
+            src.append(-1)
+        else:
+            k = next((i for i, a in enumerate(fe.mats) if same(m, a)), None)
+            if k is None:
+                raise ValueError("the reduced statement may read only the operands of the first one and its result")
+            src.append(k)
+    res = Mat.empty(1, 1, fe.dtype, device=out.tensor.device)
+    cc.coot_expr_eval_reduce(he, [m.operand() for m in fe.mats], fe.scalars, out.operand(), hr, src, fr.scalars,
+                             _RED_KIND[kind], res.operand(), cfg, _stream())
+    return res
+
+
 def _reduce(e, kind, dim, plain, out_shape, cfg, unfused):
     flat = flatten(_lift(e))
     h = compiled(flat, cc.COOT_CF_UNFUSED if unfused else 0)
