@@ -423,6 +423,10 @@ def bench_suite(args):
     us = gpu_us(axpy_dot, 50)
     res["axpy_then_dot_1e6_f32"] = {"us": round(us, 2), "GBps": round(20 * n / us / 1e3, 1),
                                     "note": "two launches + one stage-2; latency-bound at this size"}
+    # the same two statements as one pass (reads x and y once, writes y once: 12 bytes per element)
+    us = gpu_us(lambda: coot.eval_reduce(2.5 * gx + gy, gy, gx % gy), 50)
+    res["axpy_dot_one_pass_1e6_f32"] = {"us": round(us, 2), "GBps": round(12 * n / us / 1e3, 1),
+                                        "note": "one launch + one stage-2 (coot_expr_eval_reduce)"}
     del gx, gy
     log(f"axpy+dot: {res['axpy_then_dot_1e6_f32']}")
     # the 2-D step in fp64
