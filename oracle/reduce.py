@@ -3,7 +3,9 @@
 accu (sum of all elements, Fig. 1 and Section 5 task 1), sum along a dimension,
 dot and norm, defined as the exact sum of the real values that enter them; and
 the further closing reductions min, max, mean, 1-norm and infinity norm (Armadillo
-functions of the same names), from the same exact sums or the element values.
+functions of the same names), from the same exact sums or the element values; and
+the statistics mean and variance along a dimension and variance of all elements
+(listed among the library's functions, Section 2), from exact sums as well.
 
 * Floating types: each binary32 / binary64 value is an integer mantissa times a
   power of two.  Mantissas are summed per exponent in integer-exact arithmetic
@@ -291,6 +293,73 @@ def norm_inf(x, dtype) -> float:
     if np.isnan(x64).any():
         return math.nan
     return float(x64.max())
+
+
+# ---------------------------------------------------------------------------
+# Statistics: mean along a dimension, variance (Section 2 lists mean and variance
+# among the library's functions; the semantics are Armadillo's mean(X, dim) and
+# var(X, norm_type, dim))
+# ---------------------------------------------------------------------------
+
+def mean_dim(X, dim: int, dtype: str) -> list:
+    """Exact per-column (dim 0) or per-row (dim 1) means as Fractions; None where the
+    count is 0 (the mean of no elements, 0 / 0, is NaN)."""
+    if dtype not in FLOATS:
+        raise ValueError("mean is defined here for floating types only")
+    X = np.asarray(X)
+    cnt = X.shape[0] if dim == 0 else X.shape[1]
+    sums = exact_sum_dim(X, dim)
+    return [None if cnt == 0 else q / cnt for q in sums]
+
+
+def _sum_sq_dev(x: np.ndarray) -> Fraction:
+    """Exact sum over the elements of (x_i - mu)^2, mu the exact mean.
+
+    Expanding the square, sum (x_i - mu)^2 = sum x_i^2 - 2 mu sum x_i + n mu^2
+    = sum x_i^2 - (sum x_i)^2 / n, an identity of rational numbers, so the value
+    is exact; both sums are the exact ones above (the squares through exact_dot).
+    """
+    x = np.asarray(x).ravel()
+    n = x.size
+    s1 = exact_sum(x)
+    s2 = exact_dot(x, x)
+    return s2 - s1 * s1 / n
+
+
+def _var_from(ss: Fraction | None, n: int, norm_type: int):
+    """Sum of squared deviations over n elements -> variance: divided by n - 1
+    (norm_type 0, the default) or by n (norm_type 1); one element gives 0 and no
+    elements give None (NaN)."""
+    if n == 0 or ss is None:
+        return None
+    den = n if norm_type == 1 else n - 1
+    return Fraction(0) if den == 0 else ss / den
+
+
+def var(x, dtype: str, norm_type: int = 0):
+    """Exact variance of all elements (a Fraction), normalised by N - 1 or N."""
+    if dtype not in FLOATS:
+        raise ValueError("var is defined here for floating types only")
+    x = np.asarray(x)
+    if x.size == 0:
+        raise ValueError("var of an empty operand")
+    _finite_or_raise(x.astype(np.float64))
+    return _var_from(_sum_sq_dev(x), x.size, norm_type)
+
+
+def var_dim(X, dim: int, dtype: str, norm_type: int = 0) -> list:
+    """Exact per-column (dim 0) or per-row (dim 1) variances as Fractions (None where
+    the count is 0)."""
+    if dtype not in FLOATS:
+        raise ValueError("var is defined here for floating types only")
+    X = np.asarray(X)
+    if dim not in (0, 1):
+        raise ValueError("dim must be 0 or 1")
+    groups = [X[:, j] for j in range(X.shape[1])] if dim == 0 else [X[i, :] for i in range(X.shape[0])]
+    out = []
+    for g in groups:
+        out.append(None if g.size == 0 else _var_from(_sum_sq_dev(g), g.size, norm_type))
+    return out
 
 
 def rel_err(got: float, ref: Fraction, scale: float) -> float:
