@@ -468,6 +468,21 @@ def bench_suite(args):
         del gA, gB, gC, gD, Z, W, oz, ow
         torch.cuda.empty_cache()
         log(f"{dt} step: {res[f'step_4096_{dt}']}")
+    # statistics along a dimension on the fp32 Z (algorithmic bytes: one read of the four
+    # operands; a variance makes two passes, so it moves twice that)
+    A, B, C, D = synth.matrix_inputs(N, "f32")
+    gA, gB, gC, gD = (coot.Mat.from_numpy(m, dtype="f32") for m in (A, B, C, D))
+    del A, B, C, D
+    Z = 2.0 * gA + gB % gC - coot.trans(gD)
+    nb = 4 * 4 * N * N
+    for name, fn in (("mean_dim0", lambda: coot.mean(Z, dim=0)), ("mean_dim1", lambda: coot.mean(Z, dim=1)),
+                     ("var_dim0", lambda: coot.var(Z, dim=0)), ("var_dim1", lambda: coot.var(Z, dim=1)),
+                     ("var_all", lambda: coot.var(Z))):
+        us = gpu_us(fn)
+        res[f"{name}_Z_4096_f32"] = {"us": round(us, 1), "GBps": round(nb / us / 1e3, 1)}
+    del gA, gB, gC, gD, Z
+    torch.cuda.empty_cache()
+    log("statistics done")
     # integers on 8192 x 8192
     M = 8192
     Ai, Bi, Ci = synth.int_inputs(M, "u32")
@@ -495,13 +510,15 @@ def bench_suite(args):
     # with the library defaults)
     for name, fn in (("norm", lambda: coot.norm(gh)), ("accu_plain", lambda: coot.accu(gh, plain=True)),
                      ("max", lambda: coot.max(gh)), ("min", lambda: coot.min(gh)), ("mean", lambda: coot.mean(gh)),
-                     ("norm1", lambda: coot.norm1(gh)), ("norm_inf", lambda: coot.norm_inf(gh))):
+                     ("norm1", lambda: coot.norm1(gh)), ("norm_inf", lambda: coot.norm_inf(gh)),
+                     ("var", lambda: coot.var(gh))):
         us = gpu_us(fn)
         res[f"{name}_2^28_f32"] = {"us": round(us, 1), "GBps": round(nb / us / 1e3, 1)}
     out = {"metric": "throughput of the other workloads (GB/s of algorithmic bytes)", "value": None,
            "unit": "GB/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic, seeded, resident in HBM",
-           "config": {"workload": "axpy+dot 1e6 f32; 4096^2 step f64, f16, bf16; u32/s32 8192^2; "
-                              "accu/norm/min/max/mean/norm1/norm_inf 2^28 f32"},
+           "config": {"workload": "axpy+dot 1e6 f32; 4096^2 step f64, f16, bf16; mean / var along dims and "
+                              "var of Z 4096^2 f32; u32/s32 8192^2; "
+                              "accu/norm/min/max/mean/norm1/norm_inf/var 2^28 f32"},
            "results": res}
     print(json.dumps(out), flush=True)
 

@@ -133,13 +133,17 @@ typedef enum {
   COOT_RED_MAX = 5,  /* largest element -> 1 element; NaN if any element is NaN */
   COOT_RED_MEAN = 6, /* sum / number of elements -> 1 element; floating types only */
   COOT_RED_NORM1 = 7,  /* sum of |x| (1-norm of the elements as a vector); floating types only */
-  COOT_RED_NORMINF = 8 /* largest |x| (infinity norm of the elements); floating; NaN if any is NaN */
+  COOT_RED_NORMINF = 8, /* largest |x| (infinity norm of the elements); floating; NaN if any is NaN */
+  COOT_RED_MEAN_DIM = 9, /* mean along dim (shapes as SUM); floating types only */
+  COOT_RED_VAR = 10,     /* variance of all elements -> 1 element; floating types only */
+  COOT_RED_VAR_DIM = 11  /* variance along dim (shapes as SUM); floating types only */
 } coot_red;
 
 /* compile flags */
 #define COOT_CF_UNFUSED 0x1u   /* evaluate one kernel and one temporary per operator (comparator) */
 /* reduce flags */
 #define COOT_RF_PLAIN 0x1u     /* uncompensated fp32/fp64 accumulation (comparator) */
+#define COOT_RF_VAR_N 0x2u     /* VAR, VAR_DIM: divide by the count N instead of N - 1 */
 /* prepare flag: compile into the in-memory and on-disk code-object caches only,
  * without loading the code object (no device work: usable without a GPU, e.g. from
  * helper processes that fill the on-disk cache) */
@@ -186,7 +190,7 @@ coot_status coot_expr_compile(const coot_op* ops, uint32_t n_ops, const coot_slo
  * need, so that compilation stays outside timed regions (the paper's timings
  * exclude kernel compilation, Section 5).
  *   mode  -1 = element-wise eval, otherwise a coot_red value
- *   dim   for COOT_RED_SUM: 0 or 1, else ignored
+ *   dim   for COOT_RED_SUM, MEAN_DIM and VAR_DIM: 0 or 1, else ignored
  *   rflags COOT_RF_PLAIN or 0, optionally | COOT_PF_COMPILE_ONLY
  *   cfg   launch configuration the call will use (NULL = library default)
  * Errors: COOT_EINVAL, COOT_ECOMPILE, COOT_EHIP. */
@@ -212,20 +216,30 @@ coot_status coot_expr_eval(coot_expr* e, const coot_operand* operands, const dou
                            coot_operand* out, const coot_launch_cfg* cfg, void* stream);
 
 /* Close the expression with a reduction, fused with its evaluation.
- *   kind, dim   see coot_red; dim ignored except for COOT_RED_SUM
+ *   kind, dim   see coot_red; dim ignored except for SUM, MEAN_DIM and VAR_DIM
  *   flags       0 (compensated: float-float / double-double per-lane sums) or
- *               COOT_RF_PLAIN (uncompensated comparator)
- *   out         device output of the expression's dtype: 1 element for every
- *               kind but SUM; 1 x n_cols for SUM dim 0; n_rows x 1 for SUM dim 1
+ *               COOT_RF_PLAIN (uncompensated comparator); | COOT_RF_VAR_N for a
+ *               variance normalised by N (default N - 1, Armadillo's norm_type 0)
+ *   out         device output of the expression's dtype: 1 element for a full
+ *               reduction; 1 x n_cols along dim 0; n_rows x 1 along dim 1
  * accu of an expression whose root is a % b is evaluated as dot (the product
  * error is carried, not rounded away).  Integer sums wrap mod 2^32.  MEAN and
  * NORM1 use the compensated sum (MEAN divides it by the element count in
  * binary64 and rounds once); MIN, MAX and NORMINF are exact (an element value).
+ * Statistics (the paper lists mean and variance among the functions, Section 2):
+ * MEAN_DIM divides each compensated sum by the count along dim; VAR and VAR_DIM
+ * take two passes over the expression (the expression is evaluated twice, its
+ * operands read twice): the first writes the mean as an unevaluated pair of the
+ * compute type into library workspace, the second accumulates the squared
+ * deviations from that pair (compensated), and the sum is divided by N - 1 (or N)
+ * in binary64 and rounded once.  A count of 1 gives 0 for either normalisation.
+ * Inf or NaN elements give NaN.
  * The result is deterministic: a fixed combine order and no floating-point
  * atomics.  Workspace is taken from a per-stream cache owned by the library.
  * Errors: as coot_expr_eval; COOT_ETYPE for NORM, MEAN, NORM1, NORMINF of an
- * integer expression; COOT_EINVAL for DOT whose root is not a Schur product and
- * for MIN, MAX, MEAN of an empty expression. */
+ * integer expression (and for MEAN_DIM, VAR, VAR_DIM); COOT_EINVAL for DOT whose
+ * root is not a Schur product, for MIN, MAX, MEAN, VAR of an empty expression and
+ * for COOT_RF_VAR_N with another kind. */
 coot_status coot_reduce(coot_expr* e, const coot_operand* operands, const double* scalars,
                         int32_t kind, int32_t dim, uint32_t flags, coot_operand* out,
                         const coot_launch_cfg* cfg, void* stream);

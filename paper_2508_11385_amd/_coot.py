@@ -22,8 +22,10 @@ OPCODES = {"load": 0, "scalar": 1, "add": 2, "sub": 3, "schur": 4, "div": 5, "ne
            "exp": 8, "log": 9, "sqrt": 10, "square": 11, "trans": 12}
 COOT_RED_ACCU, COOT_RED_SUM, COOT_RED_DOT, COOT_RED_NORM = 0, 1, 2, 3
 COOT_RED_MIN, COOT_RED_MAX, COOT_RED_MEAN, COOT_RED_NORM1, COOT_RED_NORMINF = 4, 5, 6, 7, 8
+COOT_RED_MEAN_DIM, COOT_RED_VAR, COOT_RED_VAR_DIM = 9, 10, 11
 COOT_CF_UNFUSED = 0x1
 COOT_RF_PLAIN = 0x1
+COOT_RF_VAR_N = 0x2
 COOT_PF_COMPILE_ONLY = 0x100
 DTYPE_CODE = {"u32": COOT_U32, "s32": COOT_S32, "f32": COOT_F32, "f64": COOT_F64, "f16": COOT_F16,
               "bf16": COOT_BF16}

@@ -56,8 +56,8 @@ coot_status coot_expr_prepare(coot_expr* h, int32_t mode, int32_t dim, uint32_t 
   return guarded([&] {
     if (!h) fail(COOT_EINVAL, "NULL expression");
     Expr& e = *h->e;
-    if (mode < -1 || mode > COOT_RED_NORMINF) fail(COOT_EINVAL, "bad mode");
-    if (rflags & ~(COOT_RF_PLAIN | COOT_PF_COMPILE_ONLY)) fail(COOT_EINVAL, "unknown prepare flag");
+    if (mode < -1 || mode > COOT_RED_VAR_DIM) fail(COOT_EINVAL, "bad mode");
+    if (rflags & ~(COOT_RF_PLAIN | COOT_RF_VAR_N | COOT_PF_COMPILE_ONLY)) fail(COOT_EINVAL, "unknown prepare flag");
     int m = mode;
     if (mode == COOT_RED_ACCU && e.root_schur) m = COOT_RED_DOT;
     if (mode >= 0) check_red_mode(e, mode);
@@ -72,7 +72,7 @@ coot_status coot_expr_prepare(coot_expr* h, int32_t mode, int32_t dim, uint32_t 
     }
     coot_operand o{};
     o.n_rows = o.n_cols = o.ld = 1;
-    Request rq = plan(e, fake.data(), &o, m, mode == COOT_RED_SUM ? dim : -1, !(rflags & COOT_RF_PLAIN), cfg);
+    Request rq = plan(e, fake.data(), &o, m, is_dim_kind(mode) ? dim : -1, !(rflags & COOT_RF_PLAIN), cfg);
     get_module(e, rq, !(rflags & COOT_PF_COMPILE_ONLY));
   });
 }
@@ -110,7 +110,7 @@ coot_status coot_reduce(coot_expr* h, const coot_operand* operands, const double
                         uint32_t flags, coot_operand* out, const coot_launch_cfg* cfg, void* stream) {
   return guarded([&] {
     if (!h || !out) fail(COOT_EINVAL, "NULL argument");
-    if (flags & ~COOT_RF_PLAIN) fail(COOT_EINVAL, "unknown reduce flag");
+    if (flags & ~(COOT_RF_PLAIN | COOT_RF_VAR_N)) fail(COOT_EINVAL, "unknown reduce flag");
     Expr& e = *h->e;
     hipStream_t s = (hipStream_t)stream;
     if (!(e.flags & COOT_CF_UNFUSED)) {
@@ -163,7 +163,7 @@ coot_status coot_expr_kernel_name(coot_expr* h, int32_t mode, int32_t dim, const
     o.n_rows = o.n_cols = o.ld = 1;
     int m = mode;
     if (mode == COOT_RED_ACCU && e.root_schur) m = COOT_RED_DOT;
-    Request rq = plan(e, fake.data(), &o, m, mode == COOT_RED_SUM ? dim : -1, true, cfg);
+    Request rq = plan(e, fake.data(), &o, m, is_dim_kind(mode) ? dim : -1, true, cfg);
     KernelNames names;
     generate(e, rq, hex128(e.canon), &names);
     std::strncpy(buf, names.stage1.c_str(), cap - 1);
@@ -193,7 +193,7 @@ coot_status coot_debug_codegen(coot_expr* h, int32_t mode, int32_t dim, uint32_t
     Request rq;
     rq.mode = mode;
     if (mode == COOT_RED_ACCU && e.root_schur) rq.mode = COOT_RED_DOT;
-    rq.dim = mode == COOT_RED_SUM ? dim : -1;
+    rq.dim = is_dim_kind(mode) ? dim : -1;
     rq.comp = !(rflags & COOT_RF_PLAIN);
     rq.fam = fam ? FAM_TILE : FAM_FLAT;
     rq.var.vec = vec;

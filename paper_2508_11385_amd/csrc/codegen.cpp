@@ -43,6 +43,7 @@ int red_kind(int mode) {
     case COOT_RED_MEAN: return RK_MEAN;
     case COOT_RED_NORM1: return RK_ABSSUM;
     case COOT_RED_NORMINF: return RK_AMAX;
+    case COOT_RED_VAR: return RK_VAR;
     default: return RK_SUM;
   }
 }
@@ -60,7 +61,7 @@ std::string variant_name(const Expr& e, const Request& rq, int V, int E) {
     if (rq.fam == FAM_FLAT) return "coot_flat_" + hs + "_v" + std::to_string(V) + "e" + std::to_string(E);
     return "coot_tile_" + hs + "_v" + std::to_string(V) + "t" + std::to_string(rq.var.ts);
   }
-  if (rq.mode == COOT_RED_SUM && rq.dim >= 0)
+  if (is_dim_kind(rq.mode) && rq.dim >= 0)
     return "coot_rdim_" + hs + "_d" + std::to_string(rq.dim) + "c" + (rq.comp ? "1" : "0") + "_v" + std::to_string(V) +
            "t" + std::to_string(rq.var.ts);
   const std::string tag = "k" + std::to_string(red_kind(rq.mode)) + "c" + (rq.comp ? "1" : "0");
@@ -234,59 +235,85 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
     }
     return os.str();
   }
-  if (rq.mode == COOT_RED_SUM && rq.dim >= 0) {
+  if (is_dim_kind(rq.mode) && rq.dim >= 0) {
+    // sum / mean / variance along dim: the sum pass (stage 1) and its stage 2; a
+    // variance adds the deviation pass and its stage 2
     const std::string d = std::to_string(rq.dim);
-    names->stage1 = "coot_rdim_" + hs + "_d" + d + "c" + (rq.comp ? "1" : "0") + "_v" + std::to_string(V) + "t" +
-                    std::to_string(TS);
-    names->stage1_fallback = "coot_rdim_" + hs + "_d" + d + "c" + (rq.comp ? "1" : "0") + "_v1t" + std::to_string(TS);
-    names->stage2 = "coot_rdfin_" + hs + "_d" + d + "c" + (rq.comp ? "1" : "0");
-    auto inst = [&](int v) {
+    const std::string dc = "_d" + d + "c" + (rq.comp ? "1" : "0");
+    const std::string vt = "_v" + std::to_string(V) + "t" + std::to_string(TS);
+    const std::string v1t = "_v1t" + std::to_string(TS);
+    const std::string n_out = rq.dim == 0 ? "a.n_cols" : "a.n_rows";
+    const std::string cnt = rq.dim == 0 ? "a.n_rows" : "a.n_cols";
+    auto inst = [&](int v, bool dev) {
       return "coot::tiled_reduce_dim<X, " + d + ", " + comp + ", " + std::to_string(v) + ", " + std::to_string(TS) +
-             ">(a)";
+             (dev ? ", true" : ", false") + ">(a)";
     };
-    wrap(names->stage1, inst(V), 256);
-    if (V != 1) wrap(names->stage1_fallback, inst(1), 256);
-    wrap(names->stage2,
-         "coot::dim_stage2<X::S, " + comp + ">(a, " + (rq.dim == 0 ? std::string("a.n_cols") : "a.n_rows") + ")",
-         256);
-    return os.str();
-  }
-  // full reductions: accu / dot / norm / min / max / mean / norm1 / norm_inf
-  const int rk = red_kind(rq.mode);
-  const std::string rks = std::to_string(rk);
-  const std::string tag = "k" + rks + "c" + (rq.comp ? "1" : "0");
-  names->stage2 = "coot_rfin_" + hs + "_" + tag;
-  if (rq.fam == FAM_FLAT) {
-    auto inst = [&](int v, bool scaled) {
-      return "coot::flat_reduce<X, " + rks + ", " + comp + ", " + std::to_string(v) + ", " + std::to_string(E) +
-             ", " + (scaled ? "true" : "false") + ">(a)";
+    auto fin = [&](const std::string& mode) {
+      return "coot::dim_stage2<X::S, " + comp + ", coot::" + mode + ">(a, " + n_out + ", " + cnt + ")";
     };
-    names->stage1 = "coot_rall_" + hs + "_" + tag + "_v" + std::to_string(V) + "e" + std::to_string(E);
-    names->stage1_fallback = "coot_rall_" + hs + "_" + tag + "_v1e" + std::to_string(E);
-    wrap(names->stage1, inst(V, false), 512);
-    if (V != 1) wrap(names->stage1_fallback, inst(1, false), 512);
-    if (rk == RK_SUMSQ) {
-      names->stage1_rescale = "coot_rall_" + hs + "_" + tag + "_rescale";
-      wrap(names->stage1_rescale, inst(1, true), 512);
-    }
-  } else {
-    auto inst = [&](int v, bool scaled) {
-      return "coot::tiled_reduce<X, " + rks + ", " + comp + ", " + std::to_string(v) + ", " + std::to_string(TS) +
-             ", " + (scaled ? "true" : "false") + ">(a)";
-    };
-    names->stage1 = "coot_rtall_" + hs + "_" + tag + "_v" + std::to_string(V) + "t" + std::to_string(TS);
-    names->stage1_fallback = "coot_rtall_" + hs + "_" + tag + "_v1t" + std::to_string(TS);
+    names->stage1 = "coot_rdim_" + hs + dc + vt;
+    names->stage1_fallback = "coot_rdim_" + hs + dc + v1t;
     wrap(names->stage1, inst(V, false), 256);
     if (V != 1) wrap(names->stage1_fallback, inst(1, false), 256);
-    if (rk == RK_SUMSQ) {
-      names->stage1_rescale = "coot_rtall_" + hs + "_" + tag + "_rescale";
-      wrap(names->stage1_rescale, inst(1, true), 256);
+    const std::string fin_name = "coot_rdfin_" + hs + dc;
+    if (rq.mode == COOT_RED_SUM) {
+      names->stage2 = fin_name;
+      wrap(names->stage2, fin("DM_SUM"), 256);
+    } else if (rq.mode == COOT_RED_MEAN_DIM) {
+      names->stage2 = fin_name + "_mean";
+      wrap(names->stage2, fin("DM_MEAN"), 256);
+    } else {
+      names->stage2 = fin_name + "_mpair";
+      wrap(names->stage2, fin("DM_MEANPAIR"), 256);
+      names->stage1_dev = "coot_rdvar_" + hs + dc + vt;
+      names->stage1_dev_fallback = "coot_rdvar_" + hs + dc + v1t;
+      wrap(names->stage1_dev, inst(V, true), 256);
+      if (V != 1) wrap(names->stage1_dev_fallback, inst(1, true), 256);
+      names->stage2_dev = fin_name + "_var";
+      names->stage2_dev_n = fin_name + "_varn";
+      wrap(names->stage2_dev, fin("DM_VAR"), 256);
+      wrap(names->stage2_dev_n, fin("DM_VARN"), 256);
     }
+    return os.str();
   }
-  wrap(names->stage2, "coot::reduce_stage2<X::S, " + rks + ", " + comp + ", false>(a)", 256);
+  // full reductions: accu / dot / norm / min / max / mean / norm1 / norm_inf / var
+  const bool var = rq.mode == COOT_RED_VAR;
+  const int rk = var ? (int)RK_MEAN : red_kind(rq.mode);  // what stage 1 accumulates
+  const std::string rks = std::to_string(rk);
+  const std::string cs = rq.comp ? "1" : "0";
+  const std::string tag = "k" + std::to_string(red_kind(rq.mode)) + "c" + cs;
+  const bool flat = rq.fam == FAM_FLAT;
+  const std::string pre = (flat ? "coot_rall_" : "coot_rtall_") + hs + "_";
+  const std::string vs = flat ? "e" + std::to_string(E) : "t" + std::to_string(TS);
+  auto inst = [&](int k, int v, bool scaled) {
+    return (flat ? "coot::flat_reduce<X, " : "coot::tiled_reduce<X, ") + std::to_string(k) + ", " + comp + ", " +
+           std::to_string(v) + ", " + (flat ? std::to_string(E) : std::to_string(TS)) + ", " +
+           (scaled ? "true" : "false") + ">(a)";
+  };
+  const int bounds = flat ? 512 : 256;
+  auto fin = [&](int k) { return "coot::reduce_stage2<X::S, " + std::to_string(k) + ", " + comp + ", false>(a)"; };
+  names->stage1 = pre + tag + "_v" + std::to_string(V) + vs;
+  names->stage1_fallback = pre + tag + "_v1" + vs;
+  wrap(names->stage1, inst(rk, V, false), bounds);
+  if (V != 1) wrap(names->stage1_fallback, inst(rk, 1, false), bounds);
+  names->stage2 = "coot_rfin_" + hs + "_" + tag;
+  wrap(names->stage2, fin(var ? (int)RK_VARMEAN : rk), 256);
   if (rk == RK_SUMSQ) {
+    names->stage1_rescale = pre + tag + "_rescale";
+    wrap(names->stage1_rescale, inst(rk, 1, true), bounds);
     names->stage2_rescale = names->stage2 + "_rescale";
     wrap(names->stage2_rescale, "coot::reduce_stage2<X::S, " + rks + ", " + comp + ", true>(a)", 256);
+  }
+  if (var) {
+    const std::string dtag = "k" + std::to_string((int)RK_DEV2) + "c" + cs;
+    names->stage1_dev = pre + dtag + "_v" + std::to_string(V) + vs;
+    names->stage1_dev_fallback = pre + dtag + "_v1" + vs;
+    wrap(names->stage1_dev, inst(RK_DEV2, V, false), bounds);
+    if (V != 1) wrap(names->stage1_dev_fallback, inst(RK_DEV2, 1, false), bounds);
+    names->stage2_dev = "coot_rfin_" + hs + "_k" + std::to_string((int)RK_VAR) + "c" + cs + "_dev";
+    names->stage2_dev_n = "coot_rfin_" + hs + "_k" + std::to_string((int)RK_VARN) + "c" + cs + "_dev";
+    wrap(names->stage2_dev, fin(RK_VAR), 256);
+    wrap(names->stage2_dev_n, fin(RK_VARN), 256);
   }
   return os.str();
 }

@@ -275,6 +275,14 @@ __device__ __forceinline__ void dw_add(F& h, F& l, F h2, F l2) {
 
 // Reduction kinds
 enum { RK_SUM = 0, RK_DOT = 1, RK_SUMSQ = 2, RK_ABSSUM = 3, RK_MAX = 4, RK_MIN = 5, RK_AMAX = 6, RK_MEAN = 7 };
+// Variance in two passes.  Pass 1 is the compensated sum (stage 1 of RK_MEAN);
+// its stage 2 (RK_VARMEAN) writes the mean to the control block as an unevaluated
+// pair (hi, lo) of the compute type.  Pass 2 (RK_DEV2) accumulates the squared
+// deviations ((v - hi) - lo)^2, compensated; its stage 2 divides by N - 1
+// (RK_VAR) or N (RK_VARN).  With the mean carried to about twice the working
+// precision the deviations have no cancellation however large the mean is next
+// to the spread: each is rounded at most twice (relative 2^-p each).
+enum { RK_DEV2 = 8, RK_VARMEAN = 9, RK_VAR = 10, RK_VARN = 11 };
 
 // Extremum kinds keep, per lane and in the compute type, the largest value
 // (RK_MAX), the smallest (RK_MIN) or the largest magnitude (RK_AMAX), plus a flag
@@ -458,6 +466,13 @@ __device__ __forceinline__ void consume(A& acc, Ext<typename X::T, RK>& ext, con
   }
 }
 
+// What a full reduction's stage 1 does with one element: consume() for most kinds;
+// RK_SUMSQ also tracks the largest magnitude and applies the rescaling factor;
+// RK_DEV2 squares the deviation from the mean pair (mh, ml).
+template <class X, int RK, class A>
+__device__ __forceinline__ void take(A& acc, Ext<typename X::T, RK>& ext, double& amax, typename X::T scale,
+                                     typename X::T mh, typename X::T ml, const typename X::T* L, const u64* sc);
+
 // Integer accumulator: plain wrap-around sum.
 template <typename T>
 struct AccInt {
@@ -562,6 +577,35 @@ __device__ __forceinline__ double abs_of(T v) {
   }
 }
 
+template <class X, int RK, class A>
+__device__ __forceinline__ void take(A& acc, Ext<typename X::T, RK>& ext, double& amax, typename X::T scale,
+                                     typename X::T mh, typename X::T ml, const typename X::T* L, const u64* sc) {
+  typedef typename X::T T;
+  if constexpr (RK == RK_SUMSQ) {
+    T val = X::f(L, sc);
+    amax = __builtin_fmax(amax, abs_of<T>(val));
+    val = val * scale;
+    acc.add_prod(val, val);
+  } else if constexpr (RK == RK_DEV2) {
+    const T d = (X::f(L, sc) - mh) - ml;
+    acc.add_prod(d, d);
+  } else {
+    consume<X, RK>(acc, ext, L, sc);
+  }
+}
+
+// The mean pair written by pass 1 of a variance (control block words 2 and 3).
+template <typename T, int RK>
+__device__ __forceinline__ void mean_pair(const coot_kargs& a, T& mh, T& ml) {
+  mh = (T)0;
+  ml = (T)0;
+  if constexpr (RK == RK_DEV2) {
+    const double* ctl = (const double*)a.ws2;
+    mh = (T)ctl[2];
+    ml = (T)ctl[3];
+  }
+}
+
 // ===========================================================================
 // Full reduction, FLAT layout: grid-stride over V-groups, one record per block.
 // scale: the sum-of-squares rescaling pass multiplies each value by a power of two.
@@ -576,6 +620,8 @@ __device__ __forceinline__ void flat_reduce(const coot_kargs& a) {
     if (ctl[0] == 0.0) return;  // no rescaling requested: the whole grid exits
     scale = (T)ctl[1];
   }
+  T mh, ml;
+  mean_pair<T, RK>(a, mh, ml);
   Acc acc;
   acc.init();
   Ext<T, RK> ext;
@@ -601,14 +647,7 @@ __device__ __forceinline__ void flat_reduce(const coot_kargs& a) {
           T L[X::NL];
 #pragma unroll
           for (int k = 0; k < X::NL; ++k) L[k] = x[e][k].v[q];
-          if constexpr (RK == RK_SUMSQ) {
-            T val = X::f(L, a.sc);
-            amax = __builtin_fmax(amax, abs_of<T>(val));
-            val = val * scale;
-            acc.add_prod(val, val);
-          } else {
-            consume<X, RK>(acc, ext, L, a.sc);
-          }
+          take<X, RK>(acc, ext, amax, scale, mh, ml, L, a.sc);
         }
       }
     }
@@ -618,14 +657,7 @@ __device__ __forceinline__ void flat_reduce(const coot_kargs& a) {
       T L[X::NL];
 #pragma unroll
       for (int k = 0; k < X::NL; ++k) L[k] = leaf_at<X>(a, k, i);
-      if constexpr (RK == RK_SUMSQ) {
-        T val = X::f(L, a.sc);
-        amax = __builtin_fmax(amax, abs_of<T>(val));
-        val = val * scale;
-        acc.add_prod(val, val);
-      } else {
-        consume<X, RK>(acc, ext, L, a.sc);
-      }
+      take<X, RK>(acc, ext, amax, scale, mh, ml, L, a.sc);
     }
   }
   double h, l;
@@ -792,18 +824,11 @@ struct AllSink {
   Acc acc;
   Ext<T, RK> ext;
   double amax;
-  T scale;
+  T scale, mh, ml;
   __device__ __forceinline__ void begin_tile() {}
   __device__ __forceinline__ void elem(const coot_kargs& a, int, bool in, const T* L) {
     if (!in) return;
-    if constexpr (RK == RK_SUMSQ) {
-      T val = X::f(L, a.sc);
-      amax = __builtin_fmax(amax, abs_of<T>(val));
-      val = val * scale;
-      acc.add_prod(val, val);
-    } else {
-      consume<X, RK>(acc, ext, L, a.sc);
-    }
+    take<X, RK>(acc, ext, amax, scale, mh, ml, L, a.sc);
   }
   __device__ __forceinline__ void group(const coot_kargs&, i64, i64, int, int, bool) {}
   __device__ __forceinline__ void end_tile(const coot_kargs&, i64, i64, i64, i64, int, int) {}
@@ -817,6 +842,7 @@ __device__ __forceinline__ void tiled_reduce(const coot_kargs& a) {
   s.ext.init();
   s.amax = 0.0;
   s.scale = (T)1;
+  mean_pair<T, RK>(a, s.mh, s.ml);
   if constexpr (SCALED) {
     const double* ctl = (const double*)a.ws2;
     if (ctl[0] == 0.0) return;
@@ -838,6 +864,27 @@ __device__ __forceinline__ void tiled_reduce(const coot_kargs& a) {
 //   [2^-L, 2^L] the squares may have overflowed or underflowed, so the control
 //   block gets flag = 1 and scale = 2^-e (e the exponent of the largest |value|).
 // ===========================================================================
+// Mean of a binary64 pair sum (h + l) over n elements as a pair (mh, ml) of the
+// compute type T: the quotient q = h / n, its remainder by one fused multiply-add
+// (exact), and the correction (rem + l) / n, so that mh + ml carries the mean to
+// about twice T's precision.
+template <typename T>
+__device__ __forceinline__ void dd_mean_pair(double h, double l, double n, T& mh, T& ml) {
+  const double q = h / n;
+  const double ql = (__builtin_fma(-q, n, h) + l) / n;
+  mh = (T)q;
+  ml = (T)((q - (double)mh) + ql);
+}
+
+// Sum of squared deviations -> variance: divided by n - 1 (or n); a count of 1
+// gives 0 (the deviation of the single element is 0), NaN when it is NaN; no
+// elements give NaN (their mean is 0 / 0).
+__device__ __forceinline__ double var_of(double ss, double n, bool by_n) {
+  if (n == 0.0) return __builtin_nan("");
+  const double den = by_n ? n : n - 1.0;
+  return den > 0.0 ? ss / den : ss;
+}
+
 template <typename S, int RK, bool COMP, bool SCALED>
 __device__ __forceinline__ void reduce_stage2(const coot_kargs& a) {
   typedef typename St<S>::C T;  // compute type; the result is stored as S
@@ -896,6 +943,13 @@ __device__ __forceinline__ void reduce_stage2(const coot_kargs& a) {
       out[0] = St<S>::out((T)(u32)sh[0]);
     } else if (RK == RK_MEAN) {
       out[0] = St<S>::out((T)(tot / (double)(a.n_rows * a.n_cols)));
+    } else if (RK == RK_VARMEAN) {
+      T mh, ml;
+      dd_mean_pair<T>(sh[0], sl[0], (double)(a.n_rows * a.n_cols), mh, ml);
+      ctl[2] = (double)mh;
+      ctl[3] = (double)ml;
+    } else if (RK == RK_VAR || RK == RK_VARN) {
+      out[0] = St<S>::out((T)var_of(tot, (double)(a.n_rows * a.n_cols), RK == RK_VARN));
     } else if (RK != RK_SUMSQ) {
       // one rounding from binary64 (a second one, to a 16-bit type, is innocuous)
       out[0] = St<S>::out((T)tot);
@@ -986,7 +1040,7 @@ __device__ __forceinline__ void tiled_walk_seg(const coot_kargs& a, Sink& sink) 
     // neighbouring workgroups take neighbouring output strips of the same segment
     // (measured faster for sum(., 0) than neighbouring segments of one strip)
     const i64 keep = sgi % nkeep, sg = sgi / nkeep;
-    sink.begin_seg();
+    sink.begin_seg(a, keep * TS, lr, lc);
     const i64 r_end = sg * K + K < nred ? sg * K + K : nred;
     for (i64 r = sg * K; r < r_end; ++r) {
       const i64 ti = DIM == 0 ? r : keep, tj = DIM == 0 ? keep : r;
@@ -1040,9 +1094,15 @@ __device__ __forceinline__ void tiled_walk_seg(const coot_kargs& a, Sink& sink) 
 
 // One output's n_part partials folded by one wavefront: lane l takes k = l, l + 64,
 // ... in order, then a fixed butterfly combines the lanes (the result does not
-// depend on timing).  Stage 2 of a dimension sum runs one wavefront per output.
-template <typename S, bool COMP>
-__device__ __forceinline__ void fold_output(const coot_kargs& a, i64 o, int lane) {
+// depend on timing).  Stage 2 of a dimension reduction runs one wavefront per
+// output; MODE says what it writes for a sum h + l over cnt elements:
+//   DM_SUM the sum; DM_MEAN the sum / cnt, rounded once; DM_MEANPAIR the mean as a
+//   pair of the compute type into ws2 (pass 1 of a variance); DM_VAR / DM_VARN the
+//   sum of squared deviations / (cnt - 1) or / cnt (pass 2 of a variance).
+enum { DM_SUM = 0, DM_MEAN = 1, DM_MEANPAIR = 2, DM_VAR = 3, DM_VARN = 4 };
+
+template <typename S, bool COMP, int MODE>
+__device__ __forceinline__ void fold_output(const coot_kargs& a, i64 o, int lane, i64 cnt) {
   typedef typename St<S>::C T;  // partials in the compute type, the result stored as S
   const Pair<T>* ws = (const Pair<T>*)a.ws;
   T h = (T)0, l = (T)0;
@@ -1057,8 +1117,23 @@ __device__ __forceinline__ void fold_output(const coot_kargs& a, i64 o, int lane
   if (lane == 0) {
     if constexpr (is_int_t<T>::v) {
       ((S*)a.out)[o] = St<S>::out(h);
-    } else {
+    } else if constexpr (MODE == DM_SUM) {
       ((S*)a.out)[o] = St<S>::out(h + l);
+    } else if constexpr (MODE == DM_MEAN || MODE == DM_MEANPAIR) {
+      // the pair as binary64 words: exact for fp32; for fp64 (h, l) is already
+      // normalised, so h + l rounds to h
+      T mh, ml;
+      dd_mean_pair<T>((double)h, (double)l, (double)cnt, mh, ml);
+      if constexpr (MODE == DM_MEAN) {
+        ((S*)a.out)[o] = St<S>::out((T)((double)mh + (double)ml));
+      } else {
+        Pair<T> p;
+        p.hi = mh;
+        p.lo = ml;
+        ((Pair<T>*)a.ws2)[o] = p;
+      }
+    } else {
+      ((S*)a.out)[o] = St<S>::out((T)var_of((double)h + (double)l, (double)cnt, MODE == DM_VARN));
     }
   }
 }
@@ -1066,21 +1141,43 @@ __device__ __forceinline__ void fold_output(const coot_kargs& a, i64 o, int lane
 // sum(., 0): lane (lr, lc) of pass p covers column lr + p * CPP of the tile, rows
 // lc * V .. lc * V + V - 1; it keeps one accumulator per pass.  At the end of the
 // segment the TPC lanes of each column are combined in LDS by one thread per column.
-template <class X, bool COMP, int V, int TS>
+// DEV (pass 2 of a variance): each lane accumulates the squared deviations of its
+// columns' elements from the columns' mean pairs (ws2), read at the segment's start.
+template <class X, bool COMP, int V, int TS, bool DEV>
 struct Dim0SegSink {
   typedef typename X::T T;
   typedef typename AccSel<T, COMP>::type Acc;
   static constexpr int TPC = TS / V, CPP = 256 / TPC, NPASS = TS / CPP;
   Acc g[NPASS];
-  __device__ __forceinline__ void begin_seg() {
+  T mh[DEV ? NPASS : 1], ml[DEV ? NPASS : 1];
+  __device__ __forceinline__ void begin_seg(const coot_kargs& a, i64 j0, int lr, int) {
 #pragma unroll
     for (int p = 0; p < NPASS; ++p) g[p].init();
+    if constexpr (DEV) {
+#pragma unroll
+      for (int p = 0; p < NPASS; ++p) {
+        const i64 j = j0 + lr + p * CPP;
+        Pair<T> m;
+        m.hi = (T)0;
+        m.lo = (T)0;
+        if (j < a.n_cols) m = ((const Pair<T>*)a.ws2)[j];
+        mh[p] = m.hi;
+        ml[p] = m.lo;
+      }
+    }
   }
   __device__ __forceinline__ void elem(const coot_kargs& a, int p, int, bool in, const T* L) {
     if (in) {
 #pragma unroll
       for (int pp = 0; pp < NPASS; ++pp)
-        if (pp == p) g[pp].add(X::f(L, a.sc));
+        if (pp == p) {
+          if constexpr (DEV) {
+            const T d = (X::f(L, a.sc) - mh[pp]) - ml[pp];
+            g[pp].add_prod(d, d);
+          } else {
+            g[pp].add(X::f(L, a.sc));
+          }
+        }
     }
   }
   __device__ __forceinline__ void end_seg(const coot_kargs& a, i64 j0, i64 sg, int lr, int lc) {
@@ -1106,21 +1203,41 @@ struct Dim0SegSink {
 
 // sum(., 1): a lane's rows (lc * V .. lc * V + V - 1 of the row strip) stay fixed over
 // the segment; its V accumulators are combined across the CPP lanes of each row in LDS.
-template <class X, bool COMP, int V, int TS>
+template <class X, bool COMP, int V, int TS, bool DEV>
 struct Dim1SegSink {
   typedef typename X::T T;
   typedef typename AccSel<T, COMP>::type Acc;
   static constexpr int TPC = TS / V, CPP = 256 / TPC;
   Acc r[V];
-  __device__ __forceinline__ void begin_seg() {
+  T mh[DEV ? V : 1], ml[DEV ? V : 1];
+  __device__ __forceinline__ void begin_seg(const coot_kargs& a, i64 i0, int, int lc) {
 #pragma unroll
     for (int q = 0; q < V; ++q) r[q].init();
+    if constexpr (DEV) {
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        const i64 i = i0 + lc * V + q;
+        Pair<T> m;
+        m.hi = (T)0;
+        m.lo = (T)0;
+        if (i < a.n_rows) m = ((const Pair<T>*)a.ws2)[i];
+        mh[q] = m.hi;
+        ml[q] = m.lo;
+      }
+    }
   }
   __device__ __forceinline__ void elem(const coot_kargs& a, int, int q, bool in, const T* L) {
     if (in) {
 #pragma unroll
       for (int qq = 0; qq < V; ++qq)
-        if (qq == q) r[qq].add(X::f(L, a.sc));
+        if (qq == q) {
+          if constexpr (DEV) {
+            const T d = (X::f(L, a.sc) - mh[qq]) - ml[qq];
+            r[qq].add_prod(d, d);
+          } else {
+            r[qq].add(X::f(L, a.sc));
+          }
+        }
     }
   }
   __device__ __forceinline__ void end_seg(const coot_kargs& a, i64 i0, i64 sg, int lr, int lc) {
@@ -1144,23 +1261,24 @@ struct Dim1SegSink {
   }
 };
 
-template <class X, int DIM, bool COMP, int V, int TS>
+template <class X, int DIM, bool COMP, int V, int TS, bool DEV = false>
 __device__ __forceinline__ void tiled_reduce_dim(const coot_kargs& a) {
   if constexpr (DIM == 0) {
-    Dim0SegSink<X, COMP, V, TS> s;
+    Dim0SegSink<X, COMP, V, TS, DEV> s;
     tiled_walk_seg<X, V, TS, 0>(a, s);
   } else {
-    Dim1SegSink<X, COMP, V, TS> s;
+    Dim1SegSink<X, COMP, V, TS, DEV> s;
     tiled_walk_seg<X, V, TS, 1>(a, s);
   }
 }
 
-template <typename S, bool COMP>
-__device__ __forceinline__ void dim_stage2(const coot_kargs& a, i64 n_out) {
+// n_out outputs, each over cnt elements (n_rows along dim 0, n_cols along dim 1)
+template <typename S, bool COMP, int MODE>
+__device__ __forceinline__ void dim_stage2(const coot_kargs& a, i64 n_out, i64 cnt) {
   const int lane = threadIdx.x & 63;
   const int wpb = blockDim.x >> 6;
   for (i64 o = (i64)blockIdx.x * wpb + (threadIdx.x >> 6); o < n_out; o += (i64)gridDim.x * wpb)
-    fold_output<S, COMP>(a, o, lane);
+    fold_output<S, COMP, MODE>(a, o, lane, cnt);
 }
 
 }  // namespace coot

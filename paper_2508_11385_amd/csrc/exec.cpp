@@ -169,7 +169,7 @@ static bool aligned(const void* p, size_t bytes) { return ((uintptr_t)p % bytes)
 // (the tables hold 32- and 64-bit types; the 16-bit types' defaults are measured)
 coot_launch_cfg default_cfg(int fam, int mode, int dim, int dtype, int64_t n) {
   const uint16_t v16 = dtype == COOT_F64 ? 2 : (dtype_is_half(dtype) ? 8 : 4);  // 16-byte groups
-  if (mode == COOT_RED_SUM && dim >= 0) return {v16, 0, 4, 8};
+  if (is_dim_kind(mode) && dim >= 0) return {v16, 0, 4, 8};
   // 16-bit types: 16-byte groups, 8 waves and 16 workgroups per CU for element-wise
   // flat launches, 16 workgroups per CU for tiles (measured on the 4096 x 4096 step)
   if (dtype_is_half(dtype) && fam == FAM_FLAT && mode < 0) return {8, 1, 8, 16};
@@ -203,7 +203,7 @@ Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, in
   rq.mode = mode;
   rq.dim = dim;
   rq.comp = comp;
-  bool flat = e.n_p1 == 0 && !(mode == COOT_RED_SUM && dim >= 0);
+  bool flat = e.n_p1 == 0 && !(is_dim_kind(mode) && dim >= 0);
   for (auto& l : e.leaves)
     if (!contiguous(ops[l.slot])) flat = false;
   if (mode < 0 && out && !contiguous(*out)) flat = false;
@@ -217,8 +217,9 @@ Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, in
   if (rq.var.vec != 1 && rq.var.vec != 2 && rq.var.vec != 4 && !(rq.var.vec == 8 && dtype_is_half(e.dtype)))
     fail(COOT_EINVAL, "vec must be 1, 2 or 4 (or 8 for 16-bit types)");
   if (rq.var.ept != 1 && rq.var.ept != 2 && rq.var.ept != 4 && rq.var.ept != 8) fail(COOT_EINVAL, "ept must be 1, 2, 4 or 8");
-  // tile edge: 64, or 32 when the LDS staging of transposed leaves would exceed 64 KiB
-  const size_t es = dtype_size(e.dtype);
+  // tile edge: 64, or 32 when the LDS staging of transposed leaves (held in the
+  // compute type: binary32 for 16-bit types) would exceed 64 KiB
+  const size_t es = dtype_is_half(e.dtype) ? 4 : dtype_size(e.dtype);
   int ts = 64;
   if ((size_t)std::max(1, e.n_p1) * 64 * 65 * es > 65536) ts = 32;
   rq.var.ts = ts;
@@ -342,7 +343,7 @@ void eval_reduce(Expr& e, const coot_operand* ops, const double* scalars, const 
   const size_t es = dtype_size(e.dtype);
   check_alias(e, ops, out, es);
   check_red_mode(r, kind);
-  if (kind == COOT_RED_SUM || kind == COOT_RED_NORM)
+  if (is_dim_kind(kind) || kind == COOT_RED_NORM || kind == COOT_RED_VAR)
     fail(COOT_EUNSUPPORTED, "a fused statement pair closes with accu, dot, min, max, mean, norm1 or norm_inf");
   if (r_out.n_rows * r_out.n_cols != 1 || !r_out.data) fail(COOT_ESHAPE, "the reduction writes one element");
   if (e.n_scalars + r.n_scalars > (uint32_t)kMaxScalars) fail(COOT_EUNSUPPORTED, "more than 32 scalars in the pair");
@@ -392,11 +393,12 @@ void eval_reduce(Expr& e, const coot_operand* ops, const double* scalars, const 
 }
 
 void check_red_mode(const Expr& e, int mode) {
-  if (mode < COOT_RED_ACCU || mode > COOT_RED_NORMINF) fail(COOT_EINVAL, "unknown reduction");
+  if (mode < COOT_RED_ACCU || mode > COOT_RED_VAR_DIM) fail(COOT_EINVAL, "unknown reduction");
   if (mode == COOT_RED_DOT && !e.root_schur) fail(COOT_EINVAL, "dot needs an expression whose root is a % b");
   const bool float_only = mode == COOT_RED_NORM || mode == COOT_RED_MEAN || mode == COOT_RED_NORM1 ||
-                          mode == COOT_RED_NORMINF;
-  if (float_only && dtype_is_int(e.dtype)) fail(COOT_ETYPE, "norm / mean of an integer expression");
+                          mode == COOT_RED_NORMINF || mode == COOT_RED_MEAN_DIM || mode == COOT_RED_VAR ||
+                          mode == COOT_RED_VAR_DIM;
+  if (float_only && dtype_is_int(e.dtype)) fail(COOT_ETYPE, "norm / mean / var of an integer expression");
 }
 
 void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int kind, int dim, uint32_t flags,
@@ -408,14 +410,17 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
   int mode = kind;
   if (kind == COOT_RED_ACCU && e.root_schur) mode = COOT_RED_DOT;  // accu(x % y) is dot(x, y)
   check_red_mode(e, kind);
-  if (kind == COOT_RED_SUM && dim != 0 && dim != 1) fail(COOT_EINVAL, "sum needs dim 0 or 1");
-  if ((kind == COOT_RED_MIN || kind == COOT_RED_MAX || kind == COOT_RED_MEAN) && R * C == 0)
-    fail(COOT_EINVAL, "min / max / mean of an empty expression");
+  const bool dimk = is_dim_kind(kind);
+  if (dimk && dim != 0 && dim != 1) fail(COOT_EINVAL, "a reduction along a dimension needs dim 0 or 1");
+  if ((kind == COOT_RED_MIN || kind == COOT_RED_MAX || kind == COOT_RED_MEAN || kind == COOT_RED_VAR) && R * C == 0)
+    fail(COOT_EINVAL, "min / max / mean / var of an empty expression");
+  const bool var = kind == COOT_RED_VAR || kind == COOT_RED_VAR_DIM;
+  if ((flags & COOT_RF_VAR_N) && !var) fail(COOT_EINVAL, "COOT_RF_VAR_N applies to a variance only");
   int64_t n_out = 1;
-  if (kind == COOT_RED_SUM) {
+  if (dimk) {
     n_out = dim == 0 ? C : R;
     const bool ok = dim == 0 ? (out.n_rows == 1 && out.n_cols == C) : (out.n_rows == R && out.n_cols == 1);
-    if (!ok) fail(COOT_ESHAPE, dim == 0 ? "sum(X, 0) output must be 1 x n_cols" : "sum(X, 1) output must be n_rows x 1");
+    if (!ok) fail(COOT_ESHAPE, dim == 0 ? "a reduction along dim 0 writes 1 x n_cols" : "a reduction along dim 1 writes n_rows x 1");
     if (out.n_rows * out.n_cols > 1 && !contiguous(out)) fail(COOT_EINVAL, "reduction output must be contiguous");
   } else {
     if (out.n_rows * out.n_cols != 1) fail(COOT_ESHAPE, "a full reduction writes one element");
@@ -423,7 +428,8 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
   if (!out.data && n_out) fail(COOT_EINVAL, "NULL output");
   if (n_out == 0) return;
   const bool comp = !(flags & COOT_RF_PLAIN);
-  Request rq = plan(e, ops, nullptr, mode, kind == COOT_RED_SUM ? dim : -1, comp, cfg);
+  const bool by_n = (flags & COOT_RF_VAR_N) != 0;
+  Request rq = plan(e, ops, nullptr, mode, dimk ? dim : -1, comp, cfg);
   auto m = get_module(e, rq, true);
   KArgs a;
   fill_args(e, ops, scalars, &a);
@@ -433,9 +439,11 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
   a.n_cols = C;
   const bool v = vec_ok(e, rq, ops, nullptr, R, C);
   const std::string& kn = (v || rq.var.vec == 1) ? m->names.stage1 : m->names.stage1_fallback;
-  const size_t es = dtype_size(e.dtype);
-  const coot_launch_cfg c = resolve_cfg(cfg, rq.fam, mode, kind == COOT_RED_SUM ? dim : -1, e.dtype, R * C);
-  if (kind == COOT_RED_SUM) {
+  const std::string& kdev = (v || rq.var.vec == 1) ? m->names.stage1_dev : m->names.stage1_dev_fallback;
+  // partials and mean pairs are kept in the compute type (binary32 for 16-bit types)
+  const size_t cs = dtype_is_half(e.dtype) ? 4 : dtype_size(e.dtype);
+  const coot_launch_cfg c = resolve_cfg(cfg, rq.fam, mode, dimk ? dim : -1, e.dtype, R * C);
+  if (dimk) {
     const int ts = rq.var.ts;
     const int64_t tr = (R + ts - 1) / ts, tc = (C + ts - 1) / ts;
     // segments of K tiles along the reduced dimension, K growing once there are
@@ -443,11 +451,17 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
     const int64_t nred = dim == 0 ? tr : tc, nkeep = dim == 0 ? tc : tr;
     const int64_t K = std::max<int64_t>(1, std::min<int64_t>({16, nred, (nred * nkeep) / (8 * (int64_t)num_cus())}));
     a.n_part = std::max<int64_t>(1, (nred + K - 1) / K);
-    a.ws = workspace((size_t)std::max<int64_t>(1, a.n_part * n_out) * 2 * es, s, 0);
+    a.ws = workspace((size_t)std::max<int64_t>(1, a.n_part * n_out) * 2 * cs, s, 0);
+    if (var) a.ws2 = workspace((size_t)n_out * 2 * cs, s, 1);  // one mean pair per output
     const int64_t nseg = nkeep * a.n_part;
-    if (nseg > 0) launch(m->fn(kn), (unsigned)std::min<int64_t>(nseg, 1 << 30), 256, a, s);
+    const unsigned g1 = (unsigned)std::min<int64_t>(nseg, 1 << 30);
     const unsigned g2 = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_out + 3) / 4, 65536));
+    if (nseg > 0) launch(m->fn(kn), g1, 256, a, s);
     launch(m->fn(m->names.stage2), g2, 256, a, s);
+    if (var) {
+      if (nseg > 0) launch(m->fn(kdev), g1, 256, a, s);
+      launch(m->fn(by_n ? m->names.stage2_dev_n : m->names.stage2_dev), g2, 256, a, s);
+    }
     return;
   }
   unsigned grid;
@@ -464,6 +478,11 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
   a.ws2 = workspace(64 + (size_t)grid * 32, s, 1);
   launch(m->fn(kn), grid, block, a, s);
   launch(m->fn(m->names.stage2), 1, 256, a, s);
+  if (var) {
+    // pass 2: squared deviations from the mean pair stage 2 left in the control block
+    launch(m->fn(kdev), grid, block, a, s);
+    launch(m->fn(by_n ? m->names.stage2_dev_n : m->names.stage2_dev), 1, 256, a, s);
+  }
   if (mode == COOT_RED_NORM) {
     // runs only when stage 2 found squares that could have overflowed or underflowed
     launch(m->fn(m->names.stage1_rescale), grid, block, a, s);

@@ -166,6 +166,32 @@ class Mat(Expr):
         view = torch.as_strided(self.tensor, (1, n), (1, self.ld + 1), self.tensor.storage_offset())
         return Mat(view, self.dtype, "row")
 
+    # ---- submatrix views (Armadillo's submat / rows / cols / row / col) ----------------
+    def submat(self, r0: int, c0: int, r1: int, c1: int):
+        """Rows r0..r1 and columns c0..c1 (inclusive) as a view sharing this matrix's
+        storage: same leading dimension, base address moved to element (r0, c0).  Views
+        can be read in expressions and updated in place (s = X.submat(...); s += Y)."""
+        if self.kind == "bcast":
+            raise ValueError("a broadcast operand has no submatrix views")
+        if not (0 <= r0 <= r1 < self.n_rows and 0 <= c0 <= c1 < self.n_cols):
+            raise IndexError("submatrix bounds outside the matrix")
+        view = self.tensor[r0:r1 + 1, c0:c1 + 1]
+        kind = "row" if r0 == r1 and self.n_rows > 1 else ("col" if c0 == c1 and self.n_cols > 1 else self.kind)
+        return Mat(view, self.dtype, kind)
+
+    def rows(self, r0: int, r1: int):
+        return self.submat(r0, 0, r1, self.n_cols - 1)
+
+    def cols(self, c0: int, c1: int):
+        return self.submat(0, c0, self.n_rows - 1, c1)
+
+    def row(self, i: int):
+        """Row i as a 1 x n_cols view whose elements lie ld apart."""
+        return self.submat(i, 0, i, self.n_cols - 1)
+
+    def col(self, j: int):
+        return self.submat(0, j, self.n_rows - 1, j)
+
     def each_col(self):
         """Armadillo's each_col(): X.each_col() + v adds the column vector v to every column."""
         return _Each(self, bcast_col)
@@ -447,7 +473,7 @@ def eval_reduce(e: Expr, out: Mat, r: Expr, kind: str = "accu", cfg=None) -> Mat
     return res
 
 
-def _reduce(e, kind, dim, plain, out_shape, cfg, unfused):
+def _reduce(e, kind, dim, plain, out_shape, cfg, unfused, flags=0):
     flat = flatten(_lift(e))
     h = compiled(flat, cc.COOT_CF_UNFUSED if unfused else 0)
     ops = [m.operand() for m in flat.mats]
@@ -455,9 +481,15 @@ def _reduce(e, kind, dim, plain, out_shape, cfg, unfused):
     orr, oc = out_shape(r, c)
     okind = "mat" if orr == oc == 1 else ("row" if orr == 1 else "col")
     out = Mat.empty(orr, oc, flat.dtype, okind, device=flat.mats[0].tensor.device)
-    cc.coot_reduce(h, ops, flat.scalars, kind, dim, cc.COOT_RF_PLAIN if plain else 0, out.operand(), cfg,
+    cc.coot_reduce(h, ops, flat.scalars, kind, dim, (cc.COOT_RF_PLAIN if plain else 0) | flags, out.operand(), cfg,
                    _stream())
     return out
+
+
+def _along(dim):
+    if dim not in (0, 1):
+        raise ValueError("dim must be 0 or 1")
+    return (lambda r, c: (1, c)) if dim == 0 else (lambda r, c: (r, 1))
 
 
 def accu(e, plain=False, cfg=None, unfused=False) -> Mat:
@@ -497,9 +529,26 @@ def max(e, cfg=None, unfused=False) -> Mat:  # noqa: A001
     return _reduce(e, cc.COOT_RED_MAX, -1, False, lambda r, c: (1, 1), cfg, unfused)
 
 
-def mean(e, plain=False, cfg=None, unfused=False) -> Mat:
-    """Mean of all elements (compensated sum / count, rounded once)."""
-    return _reduce(e, cc.COOT_RED_MEAN, -1, plain, lambda r, c: (1, 1), cfg, unfused)
+def mean(e, dim=None, plain=False, cfg=None, unfused=False) -> Mat:
+    """Mean of all elements (compensated sum / count, rounded once), or with dim along a
+    dimension as Armadillo's mean(X, dim): dim 0 per column (1 x n_cols), dim 1 per row
+    (n_rows x 1)."""
+    if dim is None:
+        return _reduce(e, cc.COOT_RED_MEAN, -1, plain, lambda r, c: (1, 1), cfg, unfused)
+    return _reduce(e, cc.COOT_RED_MEAN_DIM, dim, plain, _along(dim), cfg, unfused)
+
+
+def var(e, norm_type=0, dim=None, plain=False, cfg=None, unfused=False) -> Mat:
+    """Variance as Armadillo's var(X, norm_type, dim): normalised by N - 1 (norm_type 0)
+    or N (norm_type 1); without dim over all elements, with dim 0 per column, dim 1 per
+    row.  Two passes over the expression: the mean, then the compensated sum of squared
+    deviations from it."""
+    if norm_type not in (0, 1):
+        raise ValueError("norm_type must be 0 or 1")
+    flags = cc.COOT_RF_VAR_N if norm_type == 1 else 0
+    if dim is None:
+        return _reduce(e, cc.COOT_RED_VAR, -1, plain, lambda r, c: (1, 1), cfg, unfused, flags)
+    return _reduce(e, cc.COOT_RED_VAR_DIM, dim, plain, _along(dim), cfg, unfused, flags)
 
 
 def norm1(e, plain=False, cfg=None, unfused=False) -> Mat:

@@ -118,6 +118,13 @@ FAMILIES = [
     (W, 2, 1, 6, -1, 0, 4, 4, 0, "f32"),      # mean
     (Z, 4, 1, 7, -1, 1, 2, 0, 32, "f64"),     # norm1
     (W, 2, 1, 8, -1, 0, 8, 1, 0, "f16"),      # norm_inf
+    (Z, 4, 1, 9, 0, 1, 4, 0, 64, "f32"),      # mean along dim 0
+    (Z, 4, 1, 9, 1, 1, 8, 0, 64, "bf16"),     # mean along dim 1
+    (W, 2, 1, 10, -1, 0, 4, 4, 0, "f32"),     # var, flat (two passes)
+    (Z, 4, 1, 10, -1, 1, 2, 0, 64, "f64"),    # var, tiled
+    (W, 2, 1, 10, -1, 0, 8, 1, 0, "f16"),     # var, 16-bit
+    (Z, 4, 1, 11, 0, 1, 4, 0, 64, "f32"),     # var along dim 0
+    (Z, 4, 1, 11, 1, 1, 2, 0, 32, "f64"),     # var along dim 1
 ]
 
 

@@ -1,0 +1,194 @@
+"""Statistics fused with the expression, against the oracle's exact values: mean along
+a dimension, variance of all elements and along a dimension (normalised by N - 1 or
+N).  fp32 within 1e-6 relative, fp64 within 1e-12, 16-bit types within 1 ulp of the
+exact value rounded to the type; degenerate counts (1 element: 0; no elements: NaN)
+and the error paths exactly."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import elementwise as ew
+from oracle import reduce as rd
+
+pytestmark = pytest.mark.gpu
+
+Z_POST = [("scalar", 0), ("load", 0), ("schur",), ("load", 1), ("load", 2), ("schur",), ("add",), ("load", 3),
+          ("trans",), ("sub",)]
+W_POST = [("load", 0), ("exp",), ("scalar", 0), ("load", 1), ("abs",), ("add",), ("div",)]
+REL = {"f32": 1e-6, "f64": 1e-12}
+SHAPES = [(1, 1), (67, 45), (1000, 3), (3, 1000), (130, 257)]
+
+
+@pytest.fixture(scope="module")
+def coot():
+    import torch
+    import paper_2508_11385_amd as coot
+    coot.init(0)
+    torch.cuda.synchronize()
+    return coot
+
+
+def up(coot, a, dtype):
+    return coot.Mat.from_numpy(a, dtype=dtype)
+
+
+def _ulp_dist(got, want, dtype):
+    g = np.array([got], np.float64)
+    w = np.array([want], np.float64)
+    if dtype == "f16":
+        return abs(int(g.astype(np.float16).view(np.int16)[0]) - int(w.astype(np.float16).view(np.int16)[0]))
+    return abs(int(g.astype(np.float32).view(np.int32)[0] >> 16) - int(w.astype(np.float32).view(np.int32)[0] >> 16))
+
+
+def _check(got, exact, dtype, scale=1.0):
+    """got (a float) against an exact value (Fraction), or NaN where exact is None."""
+    if exact is None:
+        assert math.isnan(got), got
+        return
+    if dtype in REL:
+        assert rd.rel_err(got, exact, scale) <= REL[dtype], (got, float(exact))
+    else:
+        assert _ulp_dist(got, rd.round_exact(exact, dtype), dtype) <= 1, (got, float(exact))
+
+
+def _exprs(coot, dtype, r, c):
+    A, B, C, D = synth.matrix_inputs(n_rows=r, n_cols=c, dtype=dtype)
+    gA, gB, gC, gD = (up(coot, x, dtype) for x in (A, B, C, D))
+    Zo = ew.evaluate(Z_POST, [A, B, C, D], [2.0], dtype)
+    Wo = ew.evaluate(W_POST, [A, B], [1.0], dtype)
+    return [(2.0 * gA + gB % gC - coot.trans(gD), Zo), (coot.exp(gA) / (1.0 + coot.abs(gB)), Wo)]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64", "f16", "bf16"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_mean_and_var_along_dims(coot, dtype, shape):
+    r, c = shape
+    for e, ref in _exprs(coot, dtype, r, c):
+        for dim in (0, 1):
+            m = coot.mean(e, dim=dim).numpy().ravel()
+            want_m = rd.mean_dim(ref, dim, dtype)
+            assert m.size == len(want_m) == (c if dim == 0 else r)
+            groups = [ref[:, j] for j in range(c)] if dim == 0 else [ref[i, :] for i in range(r)]
+            for got, q, grp in zip(m, want_m, groups):
+                _check(float(got), q, dtype, rd.sum_abs(grp) / grp.size)
+            for nt in (0, 1):
+                v = coot.var(e, norm_type=nt, dim=dim).numpy().ravel()
+                want_v = rd.var_dim(ref, dim, dtype, nt)
+                for got, q in zip(v, want_v):
+                    _check(float(got), q, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64", "f16", "bf16"])
+@pytest.mark.parametrize("shape", SHAPES + [(1, 70001)])
+def test_var_all_elements(coot, dtype, shape):
+    r, c = shape
+    for e, ref in _exprs(coot, dtype, r, c):
+        for nt in (0, 1):
+            got = float(coot.var(e, norm_type=nt).numpy().ravel()[0])
+            _check(got, rd.var(ref, dtype, nt), dtype)
+            if dtype in ("f32", "f64"):
+                got_plain = float(coot.var(e, norm_type=nt, plain=True).numpy().ravel()[0])
+                assert rd.rel_err(got_plain, rd.var(ref, dtype, nt), 1.0) <= 1e-4
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_var_large_offset_and_heavy_tail(coot, dtype):
+    """Data far from zero next to its spread (mean / std about 3.5e4) and lognormal data:
+    the mean pair keeps the deviations free of cancellation, in both passes' layouts."""
+    g = synth.rng_for(61)
+    npt = np.float32 if dtype == "f32" else np.float64
+    X = (1.0e4 + g.random((700, 300))).astype(npt)
+    Y = g.lognormal(0.0, 2.0, (700, 300)).astype(npt)
+    for M in (X, Y):
+        gm = up(coot, M, dtype)
+        _check(float(coot.var(gm).numpy()[0, 0]), rd.var(M, dtype), dtype)
+        _check(float(coot.var(coot.trans(gm)).numpy()[0, 0]), rd.var(M, dtype), dtype)
+        for dim in (0, 1):
+            v = coot.var(gm, dim=dim).numpy().ravel()
+            for got, q in zip(v, rd.var_dim(M, dim, dtype)):
+                _check(float(got), q, dtype)
+    # the same expression through the unfused comparator (materialised, then reduced)
+    gx = up(coot, X, dtype)
+    fused = float(coot.var(2.0 * gx - 1.0).numpy()[0, 0])
+    unf = float(coot.var(2.0 * gx - 1.0, unfused=True).numpy()[0, 0])
+    ref = rd.var(ew.evaluate([("scalar", 0), ("load", 0), ("schur",), ("scalar", 1), ("sub",)], [X], [2.0, 1.0],
+                             dtype), dtype)
+    _check(fused, ref, dtype)
+    _check(unf, ref, dtype)
+
+
+def test_degenerate_counts_and_errors(coot):
+    import paper_2508_11385_amd._coot as cc
+    one = up(coot, np.array([[3.5]], np.float32), "f32")
+    for nt in (0, 1):
+        assert coot.var(one, norm_type=nt).numpy()[0, 0] == 0.0
+    row = up(coot, np.array([[1.0, 2.0, 4.0]], np.float32), "f32")
+    assert np.all(coot.var(row, dim=0).numpy() == 0.0)                 # one element per column
+    assert coot.var(row, dim=1).numpy()[0, 0] == np.float32(7.0 / 3.0)
+    assert coot.mean(row, dim=1).numpy()[0, 0] == np.float32(7.0 / 3.0)
+    const = up(coot, np.full((50, 9), 0.1, np.float32), "f32")
+    assert coot.var(const).numpy()[0, 0] == 0.0
+    assert np.all(coot.var(const, dim=1).numpy() == 0.0)
+    # no elements along the reduced dimension: NaN (0 / 0)
+    import torch
+    empty = coot.Mat(torch.empty((5, 0), dtype=torch.float32, device="cuda").t(), "f32")     # 0 x 5
+    assert np.all(np.isnan(coot.mean(empty, dim=0).numpy()))
+    assert np.all(np.isnan(coot.var(empty, dim=0).numpy()))
+    assert coot.mean(empty, dim=1).numpy().size == 0
+    with pytest.raises(Exception):
+        coot.var(empty)                                                  # var of no elements
+    ints = up(coot, np.arange(6, dtype=np.int32).reshape(2, 3), "s32")
+    with pytest.raises(Exception, match="integer"):
+        coot.var(ints)
+    with pytest.raises(Exception, match="integer"):
+        coot.mean(ints, dim=0)
+    with pytest.raises(ValueError):
+        coot.var(one, norm_type=2)
+    # COOT_RF_VAR_N with another kind is rejected at the boundary
+    flat = coot.frontend.flatten(coot.frontend._lift(one))
+    h = coot.frontend.compiled(flat)
+    out = coot.Mat.empty(1, 1, "f32")
+    with pytest.raises(Exception, match="variance"):
+        cc.coot_reduce(h, [m.operand() for m in flat.mats], flat.scalars, cc.COOT_RED_ACCU, -1, cc.COOT_RF_VAR_N,
+                       out.operand(), None, None)
+    with pytest.raises(Exception, match="dim"):
+        cc.coot_reduce(h, [m.operand() for m in flat.mats], flat.scalars, cc.COOT_RED_VAR_DIM, 2, 0,
+                       out.operand(), None, None)
+
+
+def test_var_nan_and_inf(coot):
+    X = np.ones((40, 30), np.float32)
+    X[7, 11] = np.nan
+    Y = np.ones((40, 30), np.float32)
+    Y[3, 2] = np.inf
+    for M in (X, Y):
+        gm = up(coot, M, "f32")
+        assert math.isnan(float(coot.var(gm).numpy()[0, 0]))
+    v0 = coot.var(up(coot, X, "f32"), dim=0).numpy().ravel()
+    assert math.isnan(v0[11]) and np.all(v0[np.arange(30) != 11] == 0.0)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_full_size_sampled(coot, dtype):
+    """4096 x 4096 (the matrix workload's size): var along both dimensions on sampled
+    outputs (each recomputed by the oracle from its own column or row of the operands),
+    and the variance of all 2^24 elements of W."""
+    n = 4096
+    A, B, C, D = synth.matrix_inputs(n_rows=n, n_cols=n, dtype=dtype)
+    gA, gB, gC, gD = (up(coot, x, dtype) for x in (A, B, C, D))
+    Z = 2.0 * gA + gB % gC - coot.trans(gD)
+    v0 = coot.var(Z, dim=0).numpy().ravel()
+    v1 = coot.var(Z, dim=1).numpy().ravel()
+    m1 = coot.mean(Z, dim=1).numpy().ravel()
+    g = synth.rng_for(77)
+    for j in list(g.integers(0, n, 6)) + [0, n - 1]:
+        col = ew.evaluate(Z_POST, [A[:, j:j + 1], B[:, j:j + 1], C[:, j:j + 1], D[j:j + 1, :]], [2.0], dtype)
+        _check(float(v0[j]), rd.var(col, dtype), dtype)
+        row = ew.evaluate(Z_POST, [A[j:j + 1, :], B[j:j + 1, :], C[j:j + 1, :], D[:, j:j + 1]], [2.0], dtype)
+        _check(float(v1[j]), rd.var(row, dtype), dtype)
+        _check(float(m1[j]), rd.mean(row, dtype), dtype, rd.sum_abs(row) / n)
+    Wo = ew.evaluate(W_POST, [A, B], [1.0], dtype)
+    got = float(coot.var(coot.exp(gA) / (1.0 + coot.abs(gB))).numpy()[0, 0])
+    _check(got, rd.var(Wo, dtype), dtype)

@@ -9,6 +9,8 @@ from oracle import elementwise as ew
 from oracle import reduce as rd
 from tests.exact import ulp_distance
 
+REL = {"f32": 1e-6, "f64": 1e-12}
+
 pytestmark = pytest.mark.gpu
 
 
@@ -86,3 +88,45 @@ def test_broadcast_errors(coot):
     with pytest.raises(cc.CootError) as e:
         coot.Batch([(X + b, None)])
     assert e.value.status == cc.COOT_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_submatrix_views(coot, dtype):
+    """submat / rows / cols / row / col: views with the parent's leading dimension, read in
+    fused expressions and reductions and updated in place; the rest of the parent is
+    left untouched (element by element against the oracle)."""
+    g = synth.rng_for(93)
+    P = synth.uniform(g, (150, 97), dtype)
+    Q = synth.uniform(g, (150, 97), dtype)
+    gP, gQ = coot.Mat.from_numpy(P, dtype=dtype), coot.Mat.from_numpy(Q, dtype=dtype)
+    # Z-like expression over three views of P and Q (ragged 61 x 45 blocks, ld 150)
+    sa, sb = gP.submat(5, 7, 65, 51), gQ.submat(80, 40, 140, 84)
+    sc = gQ.submat(0, 0, 44, 60)                                # read through trans(): 45 x 61 -> 61 x 45
+    got = coot.eval(2.0 * sa + sa % sb - coot.trans(sc)).numpy()
+    A, B, C = P[5:66, 7:52], Q[80:141, 40:85], Q[0:45, 0:61]
+    want = ew.evaluate([("scalar", 0), ("load", 0), ("schur",), ("load", 0), ("load", 1), ("schur",), ("add",),
+                        ("load", 2), ("trans",), ("sub",)], [A, B, C], [2.0], dtype)
+    assert np.array_equal(got, want)
+    # reductions over a view
+    s0 = coot.sum(sa, 0).numpy().ravel()
+    for j in range(45):
+        assert rd.rel_err(float(s0[j]), rd.exact_sum(A[:, j]), rd.sum_abs(A[:, j])) <= REL[dtype]
+    v1 = coot.var(sa, dim=1).numpy().ravel()
+    for i, q in enumerate(rd.var_dim(A, 1, dtype)):
+        assert rd.rel_err(float(v1[i]), q, 1.0) <= REL[dtype]
+    # rows, cols, a row (elements ld apart) and a column
+    assert np.array_equal(coot.eval(gP.rows(10, 12) * 3.0).numpy(), P[10:13] * np.asarray(3.0, P.dtype))
+    assert np.array_equal(coot.eval(gP.cols(90, 96) - gQ.cols(0, 6)).numpy(), P[:, 90:97] - Q[:, 0:7])
+    r = gP.row(149)
+    assert (r.n_rows, r.n_cols, r.ld) == (1, 97, 150)
+    assert np.array_equal(coot.eval(r + gQ.row(0)).numpy(), (P[149] + Q[0]).reshape(1, -1))
+    assert np.array_equal(coot.eval(gP.col(96) % gQ.col(1)).numpy(), (P[:, 96] * Q[:, 1]).reshape(-1, 1))
+    # in-place update of a block (Armadillo's X.submat(...) += Y): only the block changes
+    blk = gP.submat(100, 20, 149, 60)
+    blk += 0.5 * gQ.submat(0, 0, 49, 40)
+    expect = P.copy()
+    expect[100:150, 20:61] = ew.evaluate([("load", 0), ("scalar", 0), ("load", 1), ("schur",), ("add",)],
+                                         [P[100:150, 20:61], Q[0:50, 0:41]], [0.5], dtype)
+    assert np.array_equal(gP.numpy(), expect)
+    with pytest.raises(IndexError):
+        gP.submat(0, 0, 150, 3)
