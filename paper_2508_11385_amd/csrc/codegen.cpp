@@ -278,7 +278,7 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
   }
   // full reductions: accu / dot / norm / min / max / mean / norm1 / norm_inf / var
   const bool var = rq.mode == COOT_RED_VAR;
-  const int rk = var ? (int)RK_MEAN : red_kind(rq.mode);  // what stage 1 accumulates
+  const int rk = var ? (int)RK_VAR1 : red_kind(rq.mode);  // what stage 1 accumulates
   const std::string rks = std::to_string(rk);
   const std::string cs = rq.comp ? "1" : "0";
   const std::string tag = "k" + std::to_string(red_kind(rq.mode)) + "c" + cs;
@@ -297,7 +297,7 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
   wrap(names->stage1, inst(rk, V, false), bounds);
   if (V != 1) wrap(names->stage1_fallback, inst(rk, 1, false), bounds);
   names->stage2 = "coot_rfin_" + hs + "_" + tag;
-  wrap(names->stage2, fin(var ? (int)RK_VARMEAN : rk), 256);
+  wrap(names->stage2, fin(var ? (int)RK_VAR : rk), 256);
   if (rk == RK_SUMSQ) {
     names->stage1_rescale = pre + tag + "_rescale";
     wrap(names->stage1_rescale, inst(rk, 1, true), bounds);
@@ -305,14 +305,8 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
     wrap(names->stage2_rescale, "coot::reduce_stage2<X::S, " + rks + ", " + comp + ", true>(a)", 256);
   }
   if (var) {
-    const std::string dtag = "k" + std::to_string((int)RK_DEV2) + "c" + cs;
-    names->stage1_dev = pre + dtag + "_v" + std::to_string(V) + vs;
-    names->stage1_dev_fallback = pre + dtag + "_v1" + vs;
-    wrap(names->stage1_dev, inst(RK_DEV2, V, false), bounds);
-    if (V != 1) wrap(names->stage1_dev_fallback, inst(RK_DEV2, 1, false), bounds);
-    names->stage2_dev = "coot_rfin_" + hs + "_k" + std::to_string((int)RK_VAR) + "c" + cs + "_dev";
-    names->stage2_dev_n = "coot_rfin_" + hs + "_k" + std::to_string((int)RK_VARN) + "c" + cs + "_dev";
-    wrap(names->stage2_dev, fin(RK_VAR), 256);
+    // the same records divided by N instead of N - 1
+    names->stage2_dev_n = "coot_rfin_" + hs + "_k" + std::to_string((int)RK_VARN) + "c" + cs;
     wrap(names->stage2_dev_n, fin(RK_VARN), 256);
   }
   return os.str();

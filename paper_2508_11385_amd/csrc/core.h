@@ -82,7 +82,7 @@ enum Family { FAM_FLAT = 0, FAM_TILE = 1 };
 // reduction kinds of the generated kernels (the same numbers as in coot_dev.h)
 enum RedKind {
   RK_SUM = 0, RK_DOT = 1, RK_SUMSQ = 2, RK_ABSSUM = 3, RK_MAX = 4, RK_MIN = 5, RK_AMAX = 6, RK_MEAN = 7,
-  RK_DEV2 = 8, RK_VARMEAN = 9, RK_VAR = 10, RK_VARN = 11
+  RK_VAR1 = 8, RK_VAR = 10, RK_VARN = 11
 };
 // reductions along a dimension (dim 0 or 1): sum, mean, variance
 inline bool is_dim_kind(int kind) { return kind == COOT_RED_SUM || kind == COOT_RED_MEAN_DIM || kind == COOT_RED_VAR_DIM; }
@@ -112,8 +112,9 @@ std::string variant_name(const Expr& e, const Request& rq, int vec, int ept);
 
 struct KernelNames {
   std::string stage1, stage1_fallback, stage2, stage1_rescale, stage2_rescale;
-  // variance: the deviation pass (and its scalar-load fallback) and its stage 2
-  // dividing by N - 1 (stage2_dev) or N (stage2_dev_n)
+  // variance along a dimension: the deviation pass (and its scalar-load fallback)
+  // and its stage 2 dividing by N - 1 (stage2_dev) or N (stage2_dev_n); variance of
+  // all elements: stage2_dev_n is its stage 2 dividing by N
   std::string stage1_dev, stage1_dev_fallback, stage2_dev, stage2_dev_n;
 };
 

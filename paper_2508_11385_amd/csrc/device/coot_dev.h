@@ -275,14 +275,15 @@ __device__ __forceinline__ void dw_add(F& h, F& l, F h2, F l2) {
 
 // Reduction kinds
 enum { RK_SUM = 0, RK_DOT = 1, RK_SUMSQ = 2, RK_ABSSUM = 3, RK_MAX = 4, RK_MIN = 5, RK_AMAX = 6, RK_MEAN = 7 };
-// Variance in two passes.  Pass 1 is the compensated sum (stage 1 of RK_MEAN);
-// its stage 2 (RK_VARMEAN) writes the mean to the control block as an unevaluated
-// pair (hi, lo) of the compute type.  Pass 2 (RK_DEV2) accumulates the squared
-// deviations ((v - hi) - lo)^2, compensated; its stage 2 divides by N - 1
-// (RK_VAR) or N (RK_VARN).  With the mean carried to about twice the working
-// precision the deviations have no cancellation however large the mean is next
-// to the spread: each is rounded at most twice (relative 2^-p each).
-enum { RK_DEV2 = 8, RK_VARMEAN = 9, RK_VAR = 10, RK_VARN = 11 };
+// Variance of all elements in one pass (RK_VAR1): each lane shifts its values by
+// its first value K and accumulates the shifted moments sum d and sum d^2, with
+// d = v - K and d^2 formed exactly (TwoDiff, TwoProd) and summed float-float; its
+// (count, mean, M2) then merge by Chan's formula in binary64 across lanes, waves
+// and workgroups.  Stage 2 (RK_VAR / RK_VARN) merges the records and divides M2 by
+// N - 1 or N.  The moments about a value of the lane's own data keep M2 free of
+// the cancellation of sum v^2 - (sum v)^2 / n however large the mean is next to
+// the spread.
+enum { RK_VAR1 = 8, RK_VAR = 10, RK_VARN = 11 };
 
 // Extremum kinds keep, per lane and in the compute type, the largest value
 // (RK_MAX), the smallest (RK_MIN) or the largest magnitude (RK_AMAX), plus a flag
@@ -468,10 +469,10 @@ __device__ __forceinline__ void consume(A& acc, Ext<typename X::T, RK>& ext, con
 
 // What a full reduction's stage 1 does with one element: consume() for most kinds;
 // RK_SUMSQ also tracks the largest magnitude and applies the rescaling factor;
-// RK_DEV2 squares the deviation from the mean pair (mh, ml).
+// RK_VAR1 feeds the lane's variance state.
 template <class X, int RK, class A>
 __device__ __forceinline__ void take(A& acc, Ext<typename X::T, RK>& ext, double& amax, typename X::T scale,
-                                     typename X::T mh, typename X::T ml, const typename X::T* L, const u64* sc);
+                                     const typename X::T* L, const u64* sc);
 
 // Integer accumulator: plain wrap-around sum.
 template <typename T>
@@ -579,30 +580,113 @@ __device__ __forceinline__ double abs_of(T v) {
 
 template <class X, int RK, class A>
 __device__ __forceinline__ void take(A& acc, Ext<typename X::T, RK>& ext, double& amax, typename X::T scale,
-                                     typename X::T mh, typename X::T ml, const typename X::T* L, const u64* sc) {
+                                     const typename X::T* L, const u64* sc) {
   typedef typename X::T T;
   if constexpr (RK == RK_SUMSQ) {
     T val = X::f(L, sc);
     amax = __builtin_fmax(amax, abs_of<T>(val));
     val = val * scale;
     acc.add_prod(val, val);
-  } else if constexpr (RK == RK_DEV2) {
-    const T d = (X::f(L, sc) - mh) - ml;
-    acc.add_prod(d, d);
+  } else if constexpr (RK == RK_VAR1) {
+    acc.add(X::f(L, sc));
   } else {
     consume<X, RK>(acc, ext, L, sc);
   }
 }
 
-// The mean pair written by pass 1 of a variance (control block words 2 and 3).
-template <typename T, int RK>
-__device__ __forceinline__ void mean_pair(const coot_kargs& a, T& mh, T& ml) {
-  mh = (T)0;
-  ml = (T)0;
-  if constexpr (RK == RK_DEV2) {
-    const double* ctl = (const double*)a.ws2;
-    mh = (T)ctl[2];
-    ml = (T)ctl[3];
+// One lane's variance state (RK_VAR1): shift K (its first value), count, and the
+// shifted moments as float-float pairs (plain sums when not compensated).
+template <typename T, bool COMP>
+struct AccVar {
+  T K, s1h, s1l, s2h, s2l;
+  u32 n;
+  __device__ __forceinline__ void init() {
+    K = s1h = s1l = s2h = s2l = (T)0;
+    n = 0;
+  }
+  __device__ __forceinline__ void add(T x) {
+    if (n == 0) K = x;
+    n += 1;
+    T dh, dl;
+    two_sum(x, -K, dh, dl);  // d = x - K exactly: dh + dl
+    if constexpr (COMP) {
+      T p, pe;
+      two_prod(dh, dh, p, pe);  // dh^2 exactly: p + pe
+      T s, e;
+      two_sum(s1h, dh, s, e);
+      s1h = s;
+      s1l += e + dl;
+      two_sum(s2h, p, s, e);
+      s2h = s;
+      s2l += e + (pe + (T)2 * dh * dl);
+    } else {
+      s1h += dh;
+      s2h += dh * dh;
+    }
+  }
+  // (count, mean, M2) of the lane in binary64
+  __device__ __forceinline__ void moments(double& cn, double& mean, double& m2) const {
+    cn = (double)n;
+    if (n == 0) {
+      mean = 0.0;
+      m2 = 0.0;
+      return;
+    }
+    const double s1 = (double)s1h + (double)s1l, s2 = (double)s2h + (double)s2l;
+    mean = (double)K + s1 / cn;
+    m2 = s2 - s1 * (s1 / cn);
+  }
+};
+
+// Chan's merge of (count, mean, M2) summaries: b into a.
+__device__ __forceinline__ void chan_merge(double& na, double& ma, double& qa, double nb, double mb, double qb) {
+  if (nb == 0.0) return;
+  if (na == 0.0) {
+    na = nb;
+    ma = mb;
+    qa = qb;
+    return;
+  }
+  const double n = na + nb, d = mb - ma;
+  ma = ma + d * (nb / n);
+  qa = qa + qb + d * d * (na * (nb / n));
+  na = n;
+}
+
+// A workgroup's lanes merged (wave butterfly, then the waves in order) into one
+// record: hi = M2, lo = mean, amax = count.
+__device__ __forceinline__ void block_var_to_record(double n, double m, double q, PartRec* dst) {
+  __shared__ double sn[16], sm[16], sq[16];
+#pragma unroll
+  for (int k = 1; k < 64; k <<= 1) {
+    const double n2 = __shfl_xor(n, k, 64), m2 = __shfl_xor(m, k, 64), q2 = __shfl_xor(q, k, 64);
+    // the lower lane of each pair keeps the order (a, b); both end with the same value
+    if ((threadIdx.x & k) == 0) {
+      chan_merge(n, m, q, n2, m2, q2);
+    } else {
+      double nb = n2, mb = m2, qb = q2;
+      chan_merge(nb, mb, qb, n, m, q);
+      n = nb;
+      m = mb;
+      q = qb;
+    }
+  }
+  const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sn[w] = n;
+    sm[w] = m;
+    sq[w] = q;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double N = sn[0], M = sm[0], Q = sq[0];
+    for (int k = 1; k < nw; ++k) chan_merge(N, M, Q, sn[k], sm[k], sq[k]);
+    PartRec r;
+    r.hi = Q;
+    r.lo = M;
+    r.amax = N;
+    r.pad = 0.0;
+    *dst = r;
   }
 }
 
@@ -610,18 +694,38 @@ __device__ __forceinline__ void mean_pair(const coot_kargs& a, T& mh, T& ml) {
 // Full reduction, FLAT layout: grid-stride over V-groups, one record per block.
 // scale: the sum-of-squares rescaling pass multiplies each value by a power of two.
 // ===========================================================================
+// the accumulator of a full reduction's lane
+template <typename T, int RK, bool COMP>
+struct RedAcc { typedef typename AccSel<T, COMP>::type type; };
+template <typename T, bool COMP>
+struct RedAcc<T, RK_VAR1, COMP> { typedef AccVar<T, COMP> type; };
+
+// The lane's accumulator (and extremum / magnitude word) combined across the
+// workgroup into its record.
+template <typename T, int RK, bool COMP, class Acc>
+__device__ __forceinline__ void lane_to_record(const Acc& acc, const Ext<T, RK>& ext, double amax, PartRec* dst) {
+  if constexpr (RK == RK_VAR1) {
+    double n, m, q;
+    acc.moments(n, m, q);
+    block_var_to_record(n, m, q, dst);
+  } else {
+    double h, l;
+    lane_to_words<T, COMP>(acc, h, l);
+    if constexpr (RK == RK_MAX || RK == RK_MIN || RK == RK_AMAX) amax = ext.word();
+    block_words_to_record<T, COMP>(h, l, amax, dst);
+  }
+}
+
 template <class X, int RK, bool COMP, int V, int E, bool SCALED>
 __device__ __forceinline__ void flat_reduce(const coot_kargs& a) {
   typedef typename X::T T;
-  typedef typename AccSel<T, COMP>::type Acc;
+  typedef typename RedAcc<T, RK, COMP>::type Acc;
   T scale = (T)1;
   if constexpr (SCALED) {
     const double* ctl = (const double*)a.ws2;
     if (ctl[0] == 0.0) return;  // no rescaling requested: the whole grid exits
     scale = (T)ctl[1];
   }
-  T mh, ml;
-  mean_pair<T, RK>(a, mh, ml);
   Acc acc;
   acc.init();
   Ext<T, RK> ext;
@@ -647,7 +751,7 @@ __device__ __forceinline__ void flat_reduce(const coot_kargs& a) {
           T L[X::NL];
 #pragma unroll
           for (int k = 0; k < X::NL; ++k) L[k] = x[e][k].v[q];
-          take<X, RK>(acc, ext, amax, scale, mh, ml, L, a.sc);
+          take<X, RK>(acc, ext, amax, scale, L, a.sc);
         }
       }
     }
@@ -657,14 +761,11 @@ __device__ __forceinline__ void flat_reduce(const coot_kargs& a) {
       T L[X::NL];
 #pragma unroll
       for (int k = 0; k < X::NL; ++k) L[k] = leaf_at<X>(a, k, i);
-      take<X, RK>(acc, ext, amax, scale, mh, ml, L, a.sc);
+      take<X, RK>(acc, ext, amax, scale, L, a.sc);
     }
   }
-  double h, l;
-  lane_to_words<T, COMP>(acc, h, l);
-  if constexpr (RK == RK_MAX || RK == RK_MIN || RK == RK_AMAX) amax = ext.word();
   PartRec* recs = (PartRec*)(SCALED ? (void*)((char*)a.ws2 + 64) : a.ws);
-  block_words_to_record<T, COMP>(h, l, amax, recs + blockIdx.x);
+  lane_to_record<T, RK, COMP>(acc, ext, amax, recs + blockIdx.x);
 }
 
 // ===========================================================================
@@ -820,15 +921,15 @@ __device__ __forceinline__ void tiled_eval(const coot_kargs& a) {
 template <class X, int RK, bool COMP, bool SCALED>
 struct AllSink {
   typedef typename X::T T;
-  typedef typename AccSel<T, COMP>::type Acc;
+  typedef typename RedAcc<T, RK, COMP>::type Acc;
   Acc acc;
   Ext<T, RK> ext;
   double amax;
-  T scale, mh, ml;
+  T scale;
   __device__ __forceinline__ void begin_tile() {}
   __device__ __forceinline__ void elem(const coot_kargs& a, int, bool in, const T* L) {
     if (!in) return;
-    take<X, RK>(acc, ext, amax, scale, mh, ml, L, a.sc);
+    take<X, RK>(acc, ext, amax, scale, L, a.sc);
   }
   __device__ __forceinline__ void group(const coot_kargs&, i64, i64, int, int, bool) {}
   __device__ __forceinline__ void end_tile(const coot_kargs&, i64, i64, i64, i64, int, int) {}
@@ -842,18 +943,14 @@ __device__ __forceinline__ void tiled_reduce(const coot_kargs& a) {
   s.ext.init();
   s.amax = 0.0;
   s.scale = (T)1;
-  mean_pair<T, RK>(a, s.mh, s.ml);
   if constexpr (SCALED) {
     const double* ctl = (const double*)a.ws2;
     if (ctl[0] == 0.0) return;
     s.scale = (T)ctl[1];
   }
   tiled_walk<X, V, TS>(a, s);
-  double h, l;
-  lane_to_words<T, COMP>(s.acc, h, l);
-  if constexpr (RK == RK_MAX || RK == RK_MIN || RK == RK_AMAX) s.amax = s.ext.word();
   PartRec* recs = (PartRec*)(SCALED ? (void*)((char*)a.ws2 + 64) : a.ws);
-  block_words_to_record<T, COMP>(h, l, s.amax, recs + blockIdx.x);
+  lane_to_record<T, RK, COMP>(s.acc, s.ext, s.amax, recs + blockIdx.x);
 }
 
 // ===========================================================================
@@ -885,9 +982,42 @@ __device__ __forceinline__ double var_of(double ss, double n, bool by_n) {
   return den > 0.0 ? ss / den : ss;
 }
 
+// Stage 2 of the one-pass variance: the records' (count, mean, M2) merged by
+// Chan's formula in a fixed order (thread-strided, then a tree), M2 / (N - 1) or / N.
+template <typename S, bool BY_N>
+__device__ __forceinline__ void var_stage2(const coot_kargs& a) {
+  typedef typename St<S>::C T;
+  __shared__ double sn[256], sm[256], sq[256];
+  const PartRec* recs = (const PartRec*)a.ws;
+  double N = 0.0, M = 0.0, Q = 0.0;
+  for (i64 k = threadIdx.x; k < a.n_part; k += 256) {
+    const PartRec r = recs[k];
+    chan_merge(N, M, Q, r.amax, r.lo, r.hi);
+  }
+  sn[threadIdx.x] = N;
+  sm[threadIdx.x] = M;
+  sq[threadIdx.x] = Q;
+  __syncthreads();
+  for (int s = 128; s >= 1; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      double n1 = sn[threadIdx.x], m1 = sm[threadIdx.x], q1 = sq[threadIdx.x];
+      chan_merge(n1, m1, q1, sn[threadIdx.x + s], sm[threadIdx.x + s], sq[threadIdx.x + s]);
+      sn[threadIdx.x] = n1;
+      sm[threadIdx.x] = m1;
+      sq[threadIdx.x] = q1;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ((S*)a.out)[0] = St<S>::out((T)var_of(sq[0], sn[0], BY_N));
+}
+
 template <typename S, int RK, bool COMP, bool SCALED>
 __device__ __forceinline__ void reduce_stage2(const coot_kargs& a) {
   typedef typename St<S>::C T;  // compute type; the result is stored as S
+  if constexpr (RK == RK_VAR || RK == RK_VARN) {
+    var_stage2<S, RK == RK_VARN>(a);
+    return;
+  }
   __shared__ double sh[256], sl[256], sm[256];
   const PartRec* recs = (const PartRec*)(SCALED ? (const void*)((const char*)a.ws2 + 64) : (const void*)a.ws);
   double* ctl = (double*)a.ws2;
@@ -943,13 +1073,6 @@ __device__ __forceinline__ void reduce_stage2(const coot_kargs& a) {
       out[0] = St<S>::out((T)(u32)sh[0]);
     } else if (RK == RK_MEAN) {
       out[0] = St<S>::out((T)(tot / (double)(a.n_rows * a.n_cols)));
-    } else if (RK == RK_VARMEAN) {
-      T mh, ml;
-      dd_mean_pair<T>(sh[0], sl[0], (double)(a.n_rows * a.n_cols), mh, ml);
-      ctl[2] = (double)mh;
-      ctl[3] = (double)ml;
-    } else if (RK == RK_VAR || RK == RK_VARN) {
-      out[0] = St<S>::out((T)var_of(tot, (double)(a.n_rows * a.n_cols), RK == RK_VARN));
     } else if (RK != RK_SUMSQ) {
       // one rounding from binary64 (a second one, to a 16-bit type, is innocuous)
       out[0] = St<S>::out((T)tot);

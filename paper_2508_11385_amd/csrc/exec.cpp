@@ -477,12 +477,8 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
   a.ws = workspace((size_t)grid * 32, s, 0);
   a.ws2 = workspace(64 + (size_t)grid * 32, s, 1);
   launch(m->fn(kn), grid, block, a, s);
-  launch(m->fn(m->names.stage2), 1, 256, a, s);
-  if (var) {
-    // pass 2: squared deviations from the mean pair stage 2 left in the control block
-    launch(m->fn(kdev), grid, block, a, s);
-    launch(m->fn(by_n ? m->names.stage2_dev_n : m->names.stage2_dev), 1, 256, a, s);
-  }
+  // a variance's stage 2 merges the records' (count, mean, M2) and divides by N - 1 or N
+  launch(m->fn(var && by_n ? m->names.stage2_dev_n : m->names.stage2), 1, 256, a, s);
   if (mode == COOT_RED_NORM) {
     // runs only when stage 2 found squares that could have overflowed or underflowed
     launch(m->fn(m->names.stage1_rescale), grid, block, a, s);
