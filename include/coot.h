@@ -227,15 +227,14 @@ coot_status coot_expr_eval(coot_expr* e, const coot_operand* operands, const dou
  * NORM1 use the compensated sum (MEAN divides it by the element count in
  * binary64 and rounds once); MIN, MAX and NORMINF are exact (an element value).
  * Statistics (the paper lists mean and variance among the functions, Section 2):
- * MEAN_DIM divides each compensated sum by the count along dim.  VAR is one pass:
- * each lane accumulates the moments of its values about its first value (exact
- * differences and squares, float-float sums), and the lanes' and workgroups'
- * (count, mean, M2) merge by Chan's formula in binary64.  VAR_DIM takes two passes
- * over the expression (evaluated twice, operands read twice): the first writes
- * each output's mean as an unevaluated pair of the compute type into library
- * workspace, the second accumulates the squared deviations from that pair
- * (compensated).  M2 is divided by N - 1 (or N) in binary64 and rounded once.  A
- * count of 1 gives 0 for either normalisation.  Inf or NaN elements give NaN.
+ * MEAN_DIM divides each compensated sum by the count along dim.  VAR and VAR_DIM
+ * are one pass over the expression: moments about a shift taken from the data
+ * (VAR: each lane's first value, the lanes' and workgroups' (count, mean, M2)
+ * merged by Chan's formula in binary64; VAR_DIM: each output's first element,
+ * shared by all segments, M2 = S2 - S1^2 / N in binary64), with exact differences
+ * and squares summed float-float.  M2 is divided by N - 1 (or N) in binary64 and
+ * rounded once.  A count of 1 gives 0 for either normalisation.  Inf or NaN
+ * elements give NaN.
  * The result is deterministic: a fixed combine order and no floating-point
  * atomics.  Workspace is taken from a per-stream cache owned by the library.
  * Errors: as coot_expr_eval; COOT_ETYPE for NORM, MEAN, NORM1, NORMINF of an

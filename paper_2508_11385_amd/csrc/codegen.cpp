@@ -61,9 +61,12 @@ std::string variant_name(const Expr& e, const Request& rq, int V, int E) {
     if (rq.fam == FAM_FLAT) return "coot_flat_" + hs + "_v" + std::to_string(V) + "e" + std::to_string(E);
     return "coot_tile_" + hs + "_v" + std::to_string(V) + "t" + std::to_string(rq.var.ts);
   }
-  if (is_dim_kind(rq.mode) && rq.dim >= 0)
-    return "coot_rdim_" + hs + "_d" + std::to_string(rq.dim) + "c" + (rq.comp ? "1" : "0") + "_v" + std::to_string(V) +
-           "t" + std::to_string(rq.var.ts);
+  if (is_dim_kind(rq.mode) && rq.dim >= 0) {
+    // the sum's stage 1 serves the mean too; a variance has its own
+    const char* kind = rq.mode == COOT_RED_SUM ? "" : (rq.mode == COOT_RED_VAR_DIM ? "_var" : "_mean");
+    return "coot_rdim_" + hs + "_d" + std::to_string(rq.dim) + "c" + (rq.comp ? "1" : "0") + kind + "_v" +
+           std::to_string(V) + "t" + std::to_string(rq.var.ts);
+  }
   const std::string tag = "k" + std::to_string(red_kind(rq.mode)) + "c" + (rq.comp ? "1" : "0");
   if (rq.fam == FAM_FLAT) return "coot_rall_" + hs + "_" + tag + "_v" + std::to_string(V) + "e" + std::to_string(E);
   return "coot_rtall_" + hs + "_" + tag + "_v" + std::to_string(V) + "t" + std::to_string(rq.var.ts);
@@ -236,42 +239,29 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
     return os.str();
   }
   if (is_dim_kind(rq.mode) && rq.dim >= 0) {
-    // sum / mean / variance along dim: the sum pass (stage 1) and its stage 2; a
-    // variance adds the deviation pass and its stage 2
+    // sum / mean / variance along dim: one stage 1 (a variance accumulates the shifted
+    // moments) and a stage 2 per result (a variance: divided by N - 1, or by N)
+    const bool var = rq.mode == COOT_RED_VAR_DIM;
     const std::string d = std::to_string(rq.dim);
     const std::string dc = "_d" + d + "c" + (rq.comp ? "1" : "0");
-    const std::string vt = "_v" + std::to_string(V) + "t" + std::to_string(TS);
-    const std::string v1t = "_v1t" + std::to_string(TS);
     const std::string n_out = rq.dim == 0 ? "a.n_cols" : "a.n_rows";
     const std::string cnt = rq.dim == 0 ? "a.n_rows" : "a.n_cols";
-    auto inst = [&](int v, bool dev) {
+    const std::string kind = rq.mode == COOT_RED_SUM ? "" : (var ? "_var" : "_mean");
+    auto inst = [&](int v) {
       return "coot::tiled_reduce_dim<X, " + d + ", " + comp + ", " + std::to_string(v) + ", " + std::to_string(TS) +
-             (dev ? ", true" : ", false") + ">(a)";
+             (var ? ", true" : ", false") + ">(a)";
     };
     auto fin = [&](const std::string& mode) {
       return "coot::dim_stage2<X::S, " + comp + ", coot::" + mode + ">(a, " + n_out + ", " + cnt + ")";
     };
-    names->stage1 = "coot_rdim_" + hs + dc + vt;
-    names->stage1_fallback = "coot_rdim_" + hs + dc + v1t;
-    wrap(names->stage1, inst(V, false), 256);
-    if (V != 1) wrap(names->stage1_fallback, inst(1, false), 256);
-    const std::string fin_name = "coot_rdfin_" + hs + dc;
-    if (rq.mode == COOT_RED_SUM) {
-      names->stage2 = fin_name;
-      wrap(names->stage2, fin("DM_SUM"), 256);
-    } else if (rq.mode == COOT_RED_MEAN_DIM) {
-      names->stage2 = fin_name + "_mean";
-      wrap(names->stage2, fin("DM_MEAN"), 256);
-    } else {
-      names->stage2 = fin_name + "_mpair";
-      wrap(names->stage2, fin("DM_MEANPAIR"), 256);
-      names->stage1_dev = "coot_rdvar_" + hs + dc + vt;
-      names->stage1_dev_fallback = "coot_rdvar_" + hs + dc + v1t;
-      wrap(names->stage1_dev, inst(V, true), 256);
-      if (V != 1) wrap(names->stage1_dev_fallback, inst(1, true), 256);
-      names->stage2_dev = fin_name + "_var";
-      names->stage2_dev_n = fin_name + "_varn";
-      wrap(names->stage2_dev, fin("DM_VAR"), 256);
+    names->stage1 = "coot_rdim_" + hs + dc + kind + "_v" + std::to_string(V) + "t" + std::to_string(TS);
+    names->stage1_fallback = "coot_rdim_" + hs + dc + kind + "_v1t" + std::to_string(TS);
+    wrap(names->stage1, inst(V), 256);
+    if (V != 1) wrap(names->stage1_fallback, inst(1), 256);
+    names->stage2 = "coot_rdfin_" + hs + dc + kind;
+    wrap(names->stage2, fin(rq.mode == COOT_RED_SUM ? "DM_SUM" : (var ? "DM_VAR" : "DM_MEAN")), 256);
+    if (var) {
+      names->stage2_dev_n = names->stage2 + "n";
       wrap(names->stage2_dev_n, fin("DM_VARN"), 256);
     }
     return os.str();

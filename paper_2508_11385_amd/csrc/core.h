@@ -112,10 +112,8 @@ std::string variant_name(const Expr& e, const Request& rq, int vec, int ept);
 
 struct KernelNames {
   std::string stage1, stage1_fallback, stage2, stage1_rescale, stage2_rescale;
-  // variance along a dimension: the deviation pass (and its scalar-load fallback)
-  // and its stage 2 dividing by N - 1 (stage2_dev) or N (stage2_dev_n); variance of
-  // all elements: stage2_dev_n is its stage 2 dividing by N
-  std::string stage1_dev, stage1_dev_fallback, stage2_dev, stage2_dev_n;
+  // a variance's stage 2 dividing by N (stage2 divides by N - 1)
+  std::string stage2_dev_n;
 };
 
 std::string generate(const Expr& e, const Request& rq, const std::string& hash_hint, KernelNames* names);

@@ -1217,19 +1217,12 @@ __device__ __forceinline__ void tiled_walk_seg(const coot_kargs& a, Sink& sink) 
 
 // One output's n_part partials folded by one wavefront: lane l takes k = l, l + 64,
 // ... in order, then a fixed butterfly combines the lanes (the result does not
-// depend on timing).  Stage 2 of a dimension reduction runs one wavefront per
-// output; MODE says what it writes for a sum h + l over cnt elements:
-//   DM_SUM the sum; DM_MEAN the sum / cnt, rounded once; DM_MEANPAIR the mean as a
-//   pair of the compute type into ws2 (pass 1 of a variance); DM_VAR / DM_VARN the
-//   sum of squared deviations / (cnt - 1) or / cnt (pass 2 of a variance).
-enum { DM_SUM = 0, DM_MEAN = 1, DM_MEANPAIR = 2, DM_VAR = 3, DM_VARN = 4 };
-
-template <typename S, bool COMP, int MODE>
-__device__ __forceinline__ void fold_output(const coot_kargs& a, i64 o, int lane, i64 cnt) {
-  typedef typename St<S>::C T;  // partials in the compute type, the result stored as S
-  const Pair<T>* ws = (const Pair<T>*)a.ws;
-  T h = (T)0, l = (T)0;
-  for (i64 k = lane; k < a.n_part; k += 64) pair_add<T, COMP>(h, l, ws[o * a.n_part + k]);
+// depend on timing).
+template <typename T, bool COMP>
+__device__ __forceinline__ void fold_pairs(const Pair<T>* ws, i64 o, i64 n_part, int lane, T& h, T& l) {
+  h = (T)0;
+  l = (T)0;
+  for (i64 k = lane; k < n_part; k += 64) pair_add<T, COMP>(h, l, ws[o * n_part + k]);
   if constexpr (is_int_t<T>::v) {
     h = wave_sum<T>(h);
   } else if constexpr (COMP) {
@@ -1237,160 +1230,224 @@ __device__ __forceinline__ void fold_output(const coot_kargs& a, i64 o, int lane
   } else {
     h = wave_sum<T>(h);
   }
+}
+
+// Stage 2 of a dimension reduction runs one wavefront per output; MODE says what it
+// writes from the folded partials over cnt elements:
+//   DM_SUM the sum; DM_MEAN the sum / cnt, rounded once; DM_VAR / DM_VARN the
+//   variance from the shifted moments (sum d^2 in ws, sum d in ws2):
+//   M2 = S2 - S1^2 / cnt in binary64, divided by cnt - 1 or cnt.
+enum { DM_SUM = 0, DM_MEAN = 1, DM_VAR = 3, DM_VARN = 4 };
+
+template <typename S, bool COMP, int MODE>
+__device__ __forceinline__ void fold_output(const coot_kargs& a, i64 o, int lane, i64 cnt) {
+  typedef typename St<S>::C T;  // partials in the compute type, the result stored as S
+  T h, l;
+  fold_pairs<T, COMP>((const Pair<T>*)a.ws, o, a.n_part, lane, h, l);
+  if constexpr (MODE == DM_VAR || MODE == DM_VARN) {
+    T h1, l1;
+    fold_pairs<T, COMP>((const Pair<T>*)a.ws2, o, a.n_part, lane, h1, l1);
+    if (lane == 0) {
+      // the pairs as binary64 words: exact for fp32; for fp64 h + l rounds to h
+      const double s2 = (double)h + (double)l, s1 = (double)h1 + (double)l1, n = (double)cnt;
+      ((S*)a.out)[o] = St<S>::out((T)var_of(s2 - s1 * (s1 / n), n, MODE == DM_VARN));
+    }
+    return;
+  }
   if (lane == 0) {
     if constexpr (is_int_t<T>::v) {
       ((S*)a.out)[o] = St<S>::out(h);
     } else if constexpr (MODE == DM_SUM) {
       ((S*)a.out)[o] = St<S>::out(h + l);
-    } else if constexpr (MODE == DM_MEAN || MODE == DM_MEANPAIR) {
-      // the pair as binary64 words: exact for fp32; for fp64 (h, l) is already
-      // normalised, so h + l rounds to h
+    } else {
       T mh, ml;
       dd_mean_pair<T>((double)h, (double)l, (double)cnt, mh, ml);
-      if constexpr (MODE == DM_MEAN) {
-        ((S*)a.out)[o] = St<S>::out((T)((double)mh + (double)ml));
-      } else {
-        Pair<T> p;
-        p.hi = mh;
-        p.lo = ml;
-        ((Pair<T>*)a.ws2)[o] = p;
-      }
-    } else {
-      ((S*)a.out)[o] = St<S>::out((T)var_of((double)h + (double)l, (double)cnt, MODE == DM_VARN));
+      ((S*)a.out)[o] = St<S>::out((T)((double)mh + (double)ml));
     }
   }
 }
 
+// The expression's value at element (i, j), whatever its leaves' layouts (a
+// transposed leaf reads its element (j, i); a broadcast leaf has column stride 0).
+template <class X>
+__device__ __forceinline__ typename X::T value_at(const coot_kargs& a, i64 i, i64 j) {
+  typedef typename X::T T;
+  T L[X::NL];
+#pragma unroll
+  for (int k = 0; k < X::NL; ++k) {
+    const typename X::S* p = (const typename X::S*)a.leaf[X::slot(k)];
+    const i64 ld = a.ld[X::slot(k)];
+    L[k] = ldc<typename X::S, 1>(X::par(k) ? p + j + i * ld : p + i + j * ld).v[0];
+  }
+  return X::f(L, a.sc);
+}
+
+// Shifted moments of one output's elements (variance along a dimension, one pass):
+// d = v - K exactly (TwoSum), d^2 exactly (TwoProd), sum d and sum d^2 float-float
+// (plain sums when not compensated).  K, the output's first element, is the same in
+// every segment, so the segments' sums add up and M2 = S2 - S1^2 / n at the end.
+template <typename T, bool COMP>
+struct AccShift {
+  T s1h, s1l, s2h, s2l;
+  __device__ __forceinline__ void init() { s1h = s1l = s2h = s2l = (T)0; }
+  __device__ __forceinline__ void add(T x, T K) {
+    T dh, dl;
+    two_sum(x, -K, dh, dl);
+    if constexpr (COMP) {
+      T p, pe, t, e;
+      two_prod(dh, dh, p, pe);
+      two_sum(s1h, dh, t, e);
+      s1h = t;
+      s1l += e + dl;
+      two_sum(s2h, p, t, e);
+      s2h = t;
+      s2l += e + (pe + (T)2 * dh * dl);
+    } else {
+      s1h += dh;
+      s2h += dh * dh;
+    }
+  }
+};
+
+// Per-lane accumulator of a dimension reduction: a sum, or (VAR) shifted moments.
+template <typename T, bool COMP, bool VAR>
+struct DimAcc {
+  typename AccSel<T, COMP>::type g;
+  __device__ __forceinline__ void init() { g.init(); }
+  __device__ __forceinline__ void add(T x, T) { g.add(x); }
+  __device__ __forceinline__ Pair<T> part(int) const { return acc_pair<T, COMP>(g); }
+};
+template <typename T, bool COMP>
+struct DimAcc<T, COMP, true> {
+  AccShift<T, COMP> g;
+  __device__ __forceinline__ void init() { g.init(); }
+  __device__ __forceinline__ void add(T x, T K) { g.add(x, K); }
+  // moment m: 1 -> (s1h, s1l), 2 -> (s2h, s2l)
+  __device__ __forceinline__ Pair<T> part(int m) const {
+    Pair<T> q;
+    q.hi = m == 1 ? g.s1h : g.s2h;
+    q.lo = m == 1 ? g.s1l : g.s2l;
+    return q;
+  }
+};
+
 // sum(., 0): lane (lr, lc) of pass p covers column lr + p * CPP of the tile, rows
 // lc * V .. lc * V + V - 1; it keeps one accumulator per pass.  At the end of the
 // segment the TPC lanes of each column are combined in LDS by one thread per column.
-// DEV (pass 2 of a variance): each lane accumulates the squared deviations of its
-// columns' elements from the columns' mean pairs (ws2), read at the segment's start.
-template <class X, bool COMP, int V, int TS, bool DEV>
+// VAR: each accumulator holds the shifted moments of its column about the column's
+// first element, evaluated at the segment's start; sum d^2 goes to ws and sum d to
+// ws2, one LDS combine each.
+template <class X, bool COMP, int V, int TS, bool VAR>
 struct Dim0SegSink {
   typedef typename X::T T;
-  typedef typename AccSel<T, COMP>::type Acc;
   static constexpr int TPC = TS / V, CPP = 256 / TPC, NPASS = TS / CPP;
-  Acc g[NPASS];
-  T mh[DEV ? NPASS : 1], ml[DEV ? NPASS : 1];
+  DimAcc<T, COMP, VAR> g[NPASS];
+  T K[VAR ? NPASS : 1];
   __device__ __forceinline__ void begin_seg(const coot_kargs& a, i64 j0, int lr, int) {
 #pragma unroll
     for (int p = 0; p < NPASS; ++p) g[p].init();
-    if constexpr (DEV) {
+    if constexpr (VAR) {
 #pragma unroll
       for (int p = 0; p < NPASS; ++p) {
         const i64 j = j0 + lr + p * CPP;
-        Pair<T> m;
-        m.hi = (T)0;
-        m.lo = (T)0;
-        if (j < a.n_cols) m = ((const Pair<T>*)a.ws2)[j];
-        mh[p] = m.hi;
-        ml[p] = m.lo;
+        K[p] = (j < a.n_cols && a.n_rows > 0) ? value_at<X>(a, 0, j) : (T)0;
       }
+    } else {
+      K[0] = (T)0;
     }
   }
   __device__ __forceinline__ void elem(const coot_kargs& a, int p, int, bool in, const T* L) {
     if (in) {
 #pragma unroll
       for (int pp = 0; pp < NPASS; ++pp)
-        if (pp == p) {
-          if constexpr (DEV) {
-            const T d = (X::f(L, a.sc) - mh[pp]) - ml[pp];
-            g[pp].add_prod(d, d);
-          } else {
-            g[pp].add(X::f(L, a.sc));
-          }
-        }
+        if (pp == p) g[pp].add(X::f(L, a.sc), K[VAR ? pp : 0]);
     }
   }
   __device__ __forceinline__ void end_seg(const coot_kargs& a, i64 j0, i64 sg, int lr, int lc) {
     __shared__ Pair<T> red[TS][TPC + 1];
 #pragma unroll
-    for (int p = 0; p < NPASS; ++p) red[lr + p * CPP][lc] = acc_pair<T, COMP>(g[p]);
-    __syncthreads();
-    if ((int)threadIdx.x < TS) {
-      const int jl = threadIdx.x;
-      T h = red[jl][0].hi, l = red[jl][0].lo;
-      for (int k = 1; k < TPC; ++k) pair_add<T, COMP>(h, l, red[jl][k]);
-      const i64 j = j0 + jl;
-      if (j < a.n_cols) {
-        Pair<T> q;
-        q.hi = h;
-        q.lo = l;
-        ((Pair<T>*)a.ws)[j * a.n_part + sg] = q;
+    for (int m = VAR ? 2 : 0; m >= (VAR ? 1 : 0); --m) {
+#pragma unroll
+      for (int p = 0; p < NPASS; ++p) red[lr + p * CPP][lc] = g[p].part(m);
+      __syncthreads();
+      if ((int)threadIdx.x < TS) {
+        const int jl = threadIdx.x;
+        T h = red[jl][0].hi, l = red[jl][0].lo;
+        for (int k = 1; k < TPC; ++k) pair_add<T, COMP>(h, l, red[jl][k]);
+        const i64 j = j0 + jl;
+        if (j < a.n_cols) {
+          Pair<T> q;
+          q.hi = h;
+          q.lo = l;
+          ((Pair<T>*)(m == 1 ? a.ws2 : a.ws))[j * a.n_part + sg] = q;
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 };
 
 // sum(., 1): a lane's rows (lc * V .. lc * V + V - 1 of the row strip) stay fixed over
 // the segment; its V accumulators are combined across the CPP lanes of each row in LDS.
-template <class X, bool COMP, int V, int TS, bool DEV>
+// VAR: as for columns, about each row's first element.
+template <class X, bool COMP, int V, int TS, bool VAR>
 struct Dim1SegSink {
   typedef typename X::T T;
-  typedef typename AccSel<T, COMP>::type Acc;
   static constexpr int TPC = TS / V, CPP = 256 / TPC;
-  Acc r[V];
-  T mh[DEV ? V : 1], ml[DEV ? V : 1];
+  DimAcc<T, COMP, VAR> r[V];
+  T K[VAR ? V : 1];
   __device__ __forceinline__ void begin_seg(const coot_kargs& a, i64 i0, int, int lc) {
 #pragma unroll
     for (int q = 0; q < V; ++q) r[q].init();
-    if constexpr (DEV) {
+    if constexpr (VAR) {
 #pragma unroll
       for (int q = 0; q < V; ++q) {
         const i64 i = i0 + lc * V + q;
-        Pair<T> m;
-        m.hi = (T)0;
-        m.lo = (T)0;
-        if (i < a.n_rows) m = ((const Pair<T>*)a.ws2)[i];
-        mh[q] = m.hi;
-        ml[q] = m.lo;
+        K[q] = (i < a.n_rows && a.n_cols > 0) ? value_at<X>(a, i, 0) : (T)0;
       }
+    } else {
+      K[0] = (T)0;
     }
   }
   __device__ __forceinline__ void elem(const coot_kargs& a, int, int q, bool in, const T* L) {
     if (in) {
 #pragma unroll
       for (int qq = 0; qq < V; ++qq)
-        if (qq == q) {
-          if constexpr (DEV) {
-            const T d = (X::f(L, a.sc) - mh[qq]) - ml[qq];
-            r[qq].add_prod(d, d);
-          } else {
-            r[qq].add(X::f(L, a.sc));
-          }
-        }
+        if (qq == q) r[qq].add(X::f(L, a.sc), K[VAR ? qq : 0]);
     }
   }
   __device__ __forceinline__ void end_seg(const coot_kargs& a, i64 i0, i64 sg, int lr, int lc) {
     __shared__ Pair<T> red[CPP][TS];
 #pragma unroll
-    for (int q = 0; q < V; ++q) red[lr][lc * V + q] = acc_pair<T, COMP>(r[q]);
-    __syncthreads();
-    if ((int)threadIdx.x < TS) {
-      const int il = threadIdx.x;
-      T h = red[0][il].hi, l = red[0][il].lo;
-      for (int k = 1; k < CPP; ++k) pair_add<T, COMP>(h, l, red[k][il]);
-      const i64 i = i0 + il;
-      if (i < a.n_rows) {
-        Pair<T> q;
-        q.hi = h;
-        q.lo = l;
-        ((Pair<T>*)a.ws)[i * a.n_part + sg] = q;
+    for (int m = VAR ? 2 : 0; m >= (VAR ? 1 : 0); --m) {
+#pragma unroll
+      for (int q = 0; q < V; ++q) red[lr][lc * V + q] = r[q].part(m);
+      __syncthreads();
+      if ((int)threadIdx.x < TS) {
+        const int il = threadIdx.x;
+        T h = red[0][il].hi, l = red[0][il].lo;
+        for (int k = 1; k < CPP; ++k) pair_add<T, COMP>(h, l, red[k][il]);
+        const i64 i = i0 + il;
+        if (i < a.n_rows) {
+          Pair<T> p;
+          p.hi = h;
+          p.lo = l;
+          ((Pair<T>*)(m == 1 ? a.ws2 : a.ws))[i * a.n_part + sg] = p;
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 };
 
-template <class X, int DIM, bool COMP, int V, int TS, bool DEV = false>
+// VAR: one-pass variance (shifted moments; sum d^2 partials in ws, sum d in ws2)
+template <class X, int DIM, bool COMP, int V, int TS, bool VAR = false>
 __device__ __forceinline__ void tiled_reduce_dim(const coot_kargs& a) {
   if constexpr (DIM == 0) {
-    Dim0SegSink<X, COMP, V, TS, DEV> s;
+    Dim0SegSink<X, COMP, V, TS, VAR> s;
     tiled_walk_seg<X, V, TS, 0>(a, s);
   } else {
-    Dim1SegSink<X, COMP, V, TS, DEV> s;
+    Dim1SegSink<X, COMP, V, TS, VAR> s;
     tiled_walk_seg<X, V, TS, 1>(a, s);
   }
 }

@@ -439,7 +439,6 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
   a.n_cols = C;
   const bool v = vec_ok(e, rq, ops, nullptr, R, C);
   const std::string& kn = (v || rq.var.vec == 1) ? m->names.stage1 : m->names.stage1_fallback;
-  const std::string& kdev = (v || rq.var.vec == 1) ? m->names.stage1_dev : m->names.stage1_dev_fallback;
   // partials and mean pairs are kept in the compute type (binary32 for 16-bit types)
   const size_t cs = dtype_is_half(e.dtype) ? 4 : dtype_size(e.dtype);
   const coot_launch_cfg c = resolve_cfg(cfg, rq.fam, mode, dimk ? dim : -1, e.dtype, R * C);
@@ -451,17 +450,14 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
     const int64_t nred = dim == 0 ? tr : tc, nkeep = dim == 0 ? tc : tr;
     const int64_t K = std::max<int64_t>(1, std::min<int64_t>({16, nred, (nred * nkeep) / (8 * (int64_t)num_cus())}));
     a.n_part = std::max<int64_t>(1, (nred + K - 1) / K);
-    a.ws = workspace((size_t)std::max<int64_t>(1, a.n_part * n_out) * 2 * cs, s, 0);
-    if (var) a.ws2 = workspace((size_t)n_out * 2 * cs, s, 1);  // one mean pair per output
+    const size_t part_bytes = (size_t)std::max<int64_t>(1, a.n_part * n_out) * 2 * cs;
+    a.ws = workspace(part_bytes, s, 0);
+    if (var) a.ws2 = workspace(part_bytes, s, 1);  // a variance: sum d^2 in ws, sum d in ws2
     const int64_t nseg = nkeep * a.n_part;
     const unsigned g1 = (unsigned)std::min<int64_t>(nseg, 1 << 30);
     const unsigned g2 = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_out + 3) / 4, 65536));
     if (nseg > 0) launch(m->fn(kn), g1, 256, a, s);
-    launch(m->fn(m->names.stage2), g2, 256, a, s);
-    if (var) {
-      if (nseg > 0) launch(m->fn(kdev), g1, 256, a, s);
-      launch(m->fn(by_n ? m->names.stage2_dev_n : m->names.stage2_dev), g2, 256, a, s);
-    }
+    launch(m->fn(var && by_n ? m->names.stage2_dev_n : m->names.stage2), g2, 256, a, s);
     return;
   }
   unsigned grid;
