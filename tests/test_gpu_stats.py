@@ -192,3 +192,22 @@ def test_full_size_sampled(coot, dtype):
     Wo = ew.evaluate(W_POST, [A, B], [1.0], dtype)
     got = float(coot.var(coot.exp(gA) / (1.0 + coot.abs(gB))).numpy()[0, 0])
     _check(got, rd.var(Wo, dtype), dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_var_shift_at_an_outlier(coot, dtype):
+    """The shifts are values of the data (a lane's first value; an output's first
+    element): the worst case puts an extreme outlier there.  One squared deviation
+    never exceeds their sum, so S2 = M2 (1 + z^2) with z^2 <= N and the float-float
+    sums keep the error far below the tolerance."""
+    g = synth.rng_for(62)
+    npt = np.float32 if dtype == "f32" else np.float64
+    X = g.random((3000, 40)).astype(npt)
+    X[0, :] = npt(1.0e6)                     # every column's first element, every row 0
+    X[:, 0] = npt(-3.0e5)                    # every row's first element
+    gx = up(coot, X, dtype)
+    _check(float(coot.var(gx).numpy()[0, 0]), rd.var(X, dtype), dtype)
+    for dim in (0, 1):
+        v = coot.var(gx, dim=dim).numpy().ravel()
+        for got, q in zip(v, rd.var_dim(X, dim, dtype)):
+            _check(float(got), q, dtype)
