@@ -439,7 +439,7 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
   a.n_cols = C;
   const bool v = vec_ok(e, rq, ops, nullptr, R, C);
   const std::string& kn = (v || rq.var.vec == 1) ? m->names.stage1 : m->names.stage1_fallback;
-  // partials and mean pairs are kept in the compute type (binary32 for 16-bit types)
+  // dimension partials are kept in the compute type (binary32 for 16-bit types)
   const size_t cs = dtype_is_half(e.dtype) ? 4 : dtype_size(e.dtype);
   const coot_launch_cfg c = resolve_cfg(cfg, rq.fam, mode, dimk ? dim : -1, e.dtype, R * C);
   if (dimk) {

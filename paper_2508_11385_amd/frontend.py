@@ -541,8 +541,8 @@ def mean(e, dim=None, plain=False, cfg=None, unfused=False) -> Mat:
 def var(e, norm_type=0, dim=None, plain=False, cfg=None, unfused=False) -> Mat:
     """Variance as Armadillo's var(X, norm_type, dim): normalised by N - 1 (norm_type 0)
     or N (norm_type 1); without dim over all elements, with dim 0 per column, dim 1 per
-    row.  Two passes over the expression: the mean, then the compensated sum of squared
-    deviations from it."""
+    row.  One pass over the expression: compensated moments about a value of the data,
+    combined in binary64."""
     if norm_type not in (0, 1):
         raise ValueError("norm_type must be 0 or 1")
     flags = cc.COOT_RF_VAR_N if norm_type == 1 else 0
