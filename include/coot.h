@@ -451,7 +451,9 @@ void coot_costmodel_release(coot_costmodel* cm);
  * 1 exhaustive (every configuration timed, the fastest kept), 2 the cost model's
  * argmin over the configurations these operands allow (cm required).  Timing is
  * that of coot_tune_table with 5 rounds and no flush (the per-launch time of
- * repeated calls); best_us (may be NULL) is the chosen configuration's median.
+ * repeated calls); under policy 1 the finalists (within 5 % of the fastest, at
+ * most 4) are timed again over 21 interleaved rounds and the fastest of those is
+ * kept.  best_us (may be NULL) is the chosen configuration's median.
  * Synchronises the stream. */
 coot_status coot_tune(coot_expr* e, const coot_operand* operands, const double* scalars, coot_operand* out,
                       int32_t mode, int32_t policy, coot_costmodel* cm, coot_launch_cfg* best, float* best_us,
