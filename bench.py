@@ -468,8 +468,8 @@ def bench_suite(args):
         del gA, gB, gC, gD, Z, W, oz, ow
         torch.cuda.empty_cache()
         log(f"{dt} step: {res[f'step_4096_{dt}']}")
-    # statistics along a dimension on the fp32 Z (algorithmic bytes: one read of the four
-    # operands; a variance makes two passes, so it moves twice that)
+    # statistics on the fp32 Z (algorithmic bytes: one read of the four operands; mean and
+    # variance are one pass each)
     A, B, C, D = synth.matrix_inputs(N, "f32")
     gA, gB, gC, gD = (coot.Mat.from_numpy(m, dtype="f32") for m in (A, B, C, D))
     del A, B, C, D
