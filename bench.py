@@ -9,8 +9,8 @@ One step runs all four.  Algorithmic bytes per step: every operand read once and
 every output written once: (5 + 3 + 4 + 4) x 64 MiB + 2 x 16 KiB.
 Inputs are seeded synthetic U[-1,1] data resident in HBM before timing starts.
 
-Prints ONE JSON line (see README / DESIGN for the fields).  --gpus above 1 exits:
-this build runs on one GPU.
+Prints ONE JSON line (its fields are described in the README).  --gpus above 1 exits:
+the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -62,8 +62,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is "
-              "described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); sharding across GPUs "
+              "is designed but not built", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

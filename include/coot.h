@@ -55,7 +55,7 @@ typedef enum {
   COOT_ECOMPILE = -5,     /* runtime compilation failed (the log is in coot_last_error) */
   COOT_EHIP = -6,         /* a HIP runtime call failed */
   COOT_ENOMEM = -7,       /* device workspace could not be allocated */
-  COOT_EUNSUPPORTED = -8  /* valid request outside what this build implements */
+  COOT_EUNSUPPORTED = -8  /* valid request outside what the library implements */
 } coot_status;
 
 /* ---- element types and operand kinds (Section 2: Mat<eT>, Col, Row) ------ */

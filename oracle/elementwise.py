@@ -11,7 +11,7 @@ Semantics followed:
     Mat<eT> template, and so do the 16-bit storage types f16 (IEEE binary16) and
     bf16 (bfloat16: binary32's exponent range, 8 significant bits).
 
-Readings where the paper is silent (each is listed in the design doc):
+Readings where the paper is silent:
   * `%` is the element-wise (Schur) product, as in Armadillo.
   * Floating point: every operator's exact result is rounded once, to nearest-even,
     to the element type; subnormals are kept.  For + - * / and sqrt on binary32

@@ -1,6 +1,6 @@
 """Cost-model feature vector (test infrastructure only).
 
-Reading chosen for the learned tuner (the paper has none; listed in the design doc):
+Reading chosen for the learned tuner (the paper has none):
 an expression signature on a shape, plus one launch configuration, becomes
 
     [ n_ops, n_operands, onehot(dtype: u32 s32 f32 f64),

@@ -1,7 +1,7 @@
 """Binary64 reference of the launch-configuration cost model (test infrastructure only).
 
 The paper has no learned component; this network is the reading of the learned
-tuner chosen for the fused path (the reading is listed in the design doc):
+tuner chosen for the fused path (a reading of ours):
 
     h1  = relu(X W1^T + b1)          W1: H1 x F
     h2  = relu(h1 W2^T + b2)         W2: H2 x H1

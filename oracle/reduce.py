@@ -16,7 +16,7 @@ the statistics mean and variance along a dimension and variance of all elements
 * norm(x) = sqrt(exact sum of x_i^2).
 * Integer types: the sum reduced mod 2^32 (order-independent, so bit-exact).
 
-Readings (listed in the design doc): accu(x % y) is dot(x, y) — the whole-expression
+Readings: accu(x % y) is dot(x, y) — the whole-expression
 pattern matching of Section 3 applied to a reduction; sum(X, 0) is per column
 (1 x n_cols), sum(X, 1) per row (n_rows x 1); the reduction of an empty operand is 0.
 """
