@@ -9,8 +9,10 @@ One step runs all four.  Algorithmic bytes per step: every operand read once and
 every output written once: (5 + 3 + 4 + 4) x 64 MiB + 2 x 16 KiB.
 Inputs are seeded synthetic U[-1,1] data resident in HBM before timing starts.
 
-Prints ONE JSON line (its fields are described in the README).  --gpus above 1 exits:
-the benchmark runs on one GPU.
+Prints ONE JSON line: metric, value (GB/s), unit, ms_per_step, dtype, config, the
+roofline of the dominant kernel (achieved and peak bandwidth, their ratio, HBM traffic
+from the committed counter summary) and the CPU oracle's rate on a sample.  --gpus
+above 1 exits: the benchmark runs on one GPU.
 """
 from __future__ import annotations
 
