@@ -259,3 +259,28 @@ def test_set_allocator_needs_both_functions(cc):
     assert e.value.status == cc.COOT_EINVAL
     with pytest.raises(ValueError):
         cc.coot_set_allocator(lambda n, s: 0, None)
+
+
+def test_binding_constants_match_the_header():
+    """Every COOT_* enumerator and flag of include/coot.h has the same value in the
+    Python binding (the binding marshals numbers, so a drift would be silent)."""
+    import re
+    from paper_2508_11385_amd import _coot as cc
+    text = open(os.path.join(ROOT, "include", "coot.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    found = {}
+    for name, val in re.findall(r"\b(COOT_[A-Z0-9_]+)\s*=\s*(-?\d+)", text):
+        found[name] = int(val)
+    for name, val in re.findall(r"#define\s+(COOT_[A-Z0-9_]+)\s+(0x[0-9a-fA-F]+|\d+)u?", text):
+        found[name] = int(val, 0)
+    checked = 0
+    for name, val in found.items():
+        if hasattr(cc, name):
+            assert getattr(cc, name) == val, name
+            checked += 1
+    for name in ("COOT_RED_MEAN_DIM", "COOT_RED_VAR", "COOT_RED_VAR_DIM", "COOT_RF_VAR_N", "COOT_RF_PLAIN"):
+        assert name in found and hasattr(cc, name), name
+    assert checked >= 15
+    # op codes: the binding's name -> code table
+    ops = {n[len("COOT_OP_"):].lower(): v for n, v in found.items() if n.startswith("COOT_OP_")}
+    assert ops and ops == {k: v for k, v in cc.OPCODES.items() if k in ops} and set(ops) <= set(cc.OPCODES)
