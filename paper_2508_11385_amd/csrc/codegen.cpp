@@ -199,7 +199,7 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
       if (v == 8 && !dtype_is_half(e.dtype)) continue;
       for (int ept : {1, 2, 4, 8}) {
         if (rq.fam == FAM_TILE && ept != 1) continue;
-        if (rq.fam == FAM_TILE && v > ts / 4) continue;
+        if (rq.fam == FAM_TILE && v > tile_vec_cap(ts)) continue;
         const std::string nm = variant_name(e, rq, v, rq.fam == FAM_FLAT ? ept : 0);
         std::string call;
         if (rq.mode < 0) {

@@ -91,6 +91,10 @@ int red_kind(int mode);
 // a reduction mode's arguments are valid for this expression (fails with the reason)
 void check_red_mode(const Expr& e, int mode);
 
+// Largest vector width of a TS x TS tile of 256 threads: the TS / V threads of a
+// column segment times TS columns must cover the 256 threads (V <= TS^2 / 256).
+inline int tile_vec_cap(int ts) { return ts * ts / 256; }
+
 struct Variant {  // compile-time parameters of one kernel instance
   int vec = 4;
   int ept = 4;     // flat families

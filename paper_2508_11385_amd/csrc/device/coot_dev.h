@@ -853,6 +853,7 @@ __device__ __forceinline__ void tiled_walk(const coot_kargs& a, Sink& sink) {
   constexpr int TPC = TS / V;     // threads along a column segment
   constexpr int CPP = NB / TPC;   // columns per pass
   constexpr int NPS = X::NP1 > 0 ? X::NP1 : 1;
+  static_assert(TS % V == 0 && CPP <= TS && TS % CPP == 0, "a tile's passes must cover its columns");
   __shared__ T lds[NPS][TS][TS + 1];
   const i64 R = a.n_rows, C = a.n_cols;
   const i64 tr = (R + TS - 1) / TS, tc = (C + TS - 1) / TS, nt = tr * tc;
@@ -1161,6 +1162,7 @@ __device__ __forceinline__ void tiled_walk_seg(const coot_kargs& a, Sink& sink) 
   constexpr int CPP = NB / TPC;     // columns per pass
   constexpr int NPASS = TS / CPP;   // passes per tile
   constexpr int NPS = X::NP1 > 0 ? X::NP1 : 1;
+  static_assert(TS % V == 0 && CPP <= TS && TS % CPP == 0, "a tile's passes must cover its columns");
   __shared__ T lds[NPS][TS][TS + 1];
   const i64 R = a.n_rows, C = a.n_cols;
   const i64 tr = (R + TS - 1) / TS, tc = (C + TS - 1) / TS;

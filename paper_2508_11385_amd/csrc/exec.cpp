@@ -223,7 +223,8 @@ Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, in
   int ts = 64;
   if ((size_t)std::max(1, e.n_p1) * 64 * 65 * es > 65536) ts = 32;
   rq.var.ts = ts;
-  if (rq.fam == FAM_TILE && rq.var.vec > ts / 4) rq.var.vec = ts / 4;
+  // a tile's 256 threads cover whole column segments in at most TS passes: V <= TS^2 / 256
+  if (rq.fam == FAM_TILE && rq.var.vec > tile_vec_cap(ts)) rq.var.vec = tile_vec_cap(ts);
   if (rq.fam == FAM_FLAT) rq.var.ts = 0;
   if (rq.fam == FAM_TILE) rq.var.ept = 0;
   return rq;

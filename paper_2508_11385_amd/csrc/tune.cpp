@@ -55,7 +55,7 @@ bool cfg_runnable(Expr& e, const Prepared& p, const coot_launch_cfg& c, const co
   if (c.vec == 8 && !dtype_is_half(e.dtype)) return false;  // 16-byte groups of 16-bit elements only
   Request rq = p.rq;
   rq.var.vec = c.vec;
-  if (rq.fam == FAM_TILE && c.vec > rq.var.ts / 4) return false;
+  if (rq.fam == FAM_TILE && c.vec > tile_vec_cap(rq.var.ts)) return false;
   return vec_ok(e, rq, ops, out, p.R, p.C);
 }
 

@@ -2,55 +2,18 @@
 g++ and compared with the oracle's correctly rounded exp on a large sample
 (binary32 and binary64, edges included).  The GPU parity tests check the device
 build of the same code; this test pins its arithmetic without a GPU."""
-import ctypes
-import os
-import shutil
-import subprocess
-import tempfile
-
 import numpy as np
 import pytest
 
 from oracle import elementwise as ew
-
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-DEV = os.path.join(ROOT, "paper_2508_11385_amd", "csrc", "device")
-
-SRC = r"""
-#define __host__
-#define __device__
-#define __forceinline__ inline
-#include "coot_exp.h"
-extern "C" void expf_n(const float* x, float* y, long n) { for (long i = 0; i < n; ++i) y[i] = coot::exp_cr<float>(x[i]); }
-extern "C" void exp_n(const double* x, double* y, long n) { for (long i = 0; i < n; ++i) y[i] = coot::exp_cr<double>(x[i]); }
-extern "C" void expf_rn_n(const float* x, float* y, long n) { for (long i = 0; i < n; ++i) y[i] = coot::exp_rn<float>(x[i]); }
-extern "C" void exp_rn_n(const double* x, double* y, long n) { for (long i = 0; i < n; ++i) y[i] = coot::exp_rn<double>(x[i]); }
-extern "C" long expf_fast_misses(const float* x, long n) {
-  long m = 0;
-  for (long i = 0; i < n; ++i) { bool ok; (void)coot::exp_fast<float>(x[i], ok); m += !ok; }
-  return m;
-}
-"""
+from tests import hostexp
 
 
 @pytest.fixture(scope="module")
 def lib():
-    gxx = shutil.which("g++")
-    if not gxx:
+    L = hostexp.build()
+    if L is None:
         pytest.skip("g++ not available")
-    d = tempfile.mkdtemp()
-    src = os.path.join(d, "e.cpp")
-    so = os.path.join(d, "e.so")
-    open(src, "w").write(SRC)
-    subprocess.run([gxx, "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared", "-I", DEV, src, "-o", so],
-                   check=True)
-    L = ctypes.CDLL(so)
-    L.expf_n.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long]
-    L.exp_n.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long]
-    L.expf_rn_n.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long]
-    L.exp_rn_n.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long]
-    L.expf_fast_misses.argtypes = [ctypes.c_void_p, ctypes.c_long]
-    L.expf_fast_misses.restype = ctypes.c_long
     return L
 
 
@@ -79,8 +42,9 @@ def test_binary64_sample(lib):
 
 
 def test_binary32_two_level_path(lib):
-    """exp_rn<float>: the binary64-evaluated fast path with its ambiguity test, plus the
-    exact slow path for the lanes it rejects, on a sample dense in the fast range."""
+    """exp_rn<float>: the fast path (double-word arithmetic in binary32 words) with its
+    ambiguity test, plus the exact slow path for the lanes it rejects, on a sample
+    dense in the fast range."""
     rng = np.random.default_rng(33)
     bits = rng.integers(0, 1 << 32, size=1 << 20, dtype=np.uint64).astype(np.uint32)
     x = np.concatenate([bits.view(np.float32), rng.uniform(-86, 88, 1 << 20).astype(np.float32),

@@ -217,3 +217,40 @@ def test_sixteen_byte_groups(coot, dtype, cfg):
         s0 = coot.sum(_z(coot, gA, gB, gC, gD), 0, cfg=cfg).numpy().ravel()
         want = [rd.round_exact(q, dtype) for q in rd.sum_dim(ew.evaluate(Z_POST, [A, B, C, D], [2.0], dtype), 0, dtype)]
         assert ulp16(s0, want, dtype).max() <= 1
+
+
+@pytest.mark.parametrize("dtype", HALVES)
+@pytest.mark.parametrize("shape", [(128, 96), (67, 45), (130, 257)])
+def test_dim_reductions_four_transposed_leaves(coot, dtype, shape):
+    """Four transposed 16-bit leaves stage through 32 x 32 tiles; the dimension sums,
+    means and variances (16-byte groups requested: planned as 4-element groups, the
+    widest a 32 x 32 tile of 256 threads covers) against the oracle on aligned and
+    ragged shapes."""
+    r, c = shape
+    g = synth.rng_for(71, r, c)
+    A = synth.uniform(g, (r, c), dtype)
+    Ts = [synth.uniform(g, (c, r), dtype) for _ in range(4)]
+    post = [("load", 0)]
+    for k in range(4):
+        post += [("load", k + 1), ("trans",), ("add",)]
+    ref = ew.evaluate(post, [A] + Ts, [], dtype)
+    gA = up(coot, A, dtype)
+    gT = [up(coot, t, dtype) for t in Ts]
+
+    def e():
+        x = gA
+        for t in gT:
+            x = x + coot.trans(t)
+        return x
+
+    def close(got, exact, what):
+        want = np.array([rd.round_exact(q, dtype) for q in exact])
+        d = ulp16(np.asarray(got).ravel(), want, dtype)
+        assert d.max() <= 1, f"{what}: worst {int(d.max())} ulp"
+
+    for cfg in (None, (8, 0, 0, 0)):
+        for dim in (0, 1):
+            close(coot.sum(e(), dim, cfg=cfg).numpy(), rd.sum_dim(ref, dim, dtype), f"sum dim {dim} {cfg}")
+            close(coot.mean(e(), dim=dim, cfg=cfg).numpy(), rd.mean_dim(ref, dim, dtype), f"mean dim {dim} {cfg}")
+            v = coot.var(e(), dim=dim, cfg=cfg).numpy().ravel()
+            close(v, rd.var_dim(ref, dim, dtype, 0), f"var dim {dim} {cfg}")

@@ -188,16 +188,16 @@ def _build(coot, spec, mats):
     return st[0]
 
 
-@pytest.mark.parametrize("dtype", ["f32", "u32", "s32"])
+@pytest.mark.parametrize("dtype", ["f32", "f64", "u32", "s32"])
 def test_random_trees(coot, dtype):
-    g = synth.rng_for(123, {"f32": 0, "u32": 1, "s32": 2}[dtype])
+    g = synth.rng_for(123, {"f32": 0, "u32": 1, "s32": 2, "f64": 3}[dtype])
     n_exp_1ulp = 0
     for trial in range(60):
         r, c = int(g.integers(1, 150)), int(g.integers(1, 150))
         spec = synth.random_tree(g, int(g.integers(1, 7)), int(g.integers(2, 6)), r, c, dtype)
         ops = synth.operands_for(spec, g)
         got, want = _tree_case(coot, spec, ops, dtype)
-        if dtype == "f32":
+        if dtype in ("f32", "f64"):
             d = ulp_distance(got, want)
             has_exp = any(p[0] == "exp" for p in spec.postfix)
             limit = 1 if has_exp else 0

@@ -118,6 +118,59 @@ def test_log_matches_decimal_and_specials():
     assert s[0] == -np.inf and np.isnan(s[1]) and s[2] == 0 and s[3] == np.inf
 
 
+def _decimal_log_rounded(x: float, dtype: str):
+    from decimal import Decimal, localcontext
+    with localcontext() as ctx:
+        ctx.prec = 80
+        return exact.round_fraction(Fraction(Decimal(x).ln()), dtype)
+
+
+def test_log_f64_correctly_rounded_against_decimal():
+    """The binary64 branch (extended-precision fast path, Decimal fallback) against an
+    80-digit Decimal logarithm rounded by the IEEE definition: wide magnitudes,
+    subnormals, values next to 1 (where log is tiny and its rounding hardest) and
+    exact powers of two."""
+    rng = np.random.default_rng(8)
+    x = np.concatenate([np.exp(rng.uniform(-700, 700, 600)), rng.uniform(0.5, 2.0, 300),
+                        1.0 + np.arange(1, 40) * 2.0 ** -52, 1.0 - np.arange(1, 40) * 2.0 ** -53,
+                        2.0 ** np.arange(-1074, 1024, 37).astype(np.float64),
+                        [5e-324, 1e-310, 2.2250738585072014e-308, 1.7976931348623157e308, 0.1, 10.0, 3.0]])
+    got = ew.log_rounded(x, "f64")
+    for i in range(x.size):
+        want = _decimal_log_rounded(float(x[i]), "f64")
+        assert got[i] == want, (float(x[i]), float(got[i]), float(want))
+    s = ew.log_rounded(np.array([0.0, -0.0, -1.0, 1.0, np.inf, np.nan]), "f64")
+    assert s[0] == -np.inf and s[1] == -np.inf and np.isnan(s[2]) and s[3] == 0 and s[4] == np.inf
+    assert np.isnan(s[5])
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_log_of_16bit_values_against_decimal(dtype):
+    """16-bit log (binary64 log correctly rounded, then rounded to the type) equals the
+    80-digit Decimal logarithm rounded straight to the type by a brute-force search
+    over its finite values: every positive finite f16 value, a bf16 sample."""
+    from tests.test_oracle_halves import _all_finite, _brute_round
+    vals, even = _all_finite(dtype)
+    top_half_ulp = Fraction(2) ** (4 if dtype == "f16" else 119)
+    pos = vals[vals > 0]
+    if dtype == "bf16":
+        pos = pos[np.random.default_rng(9).choice(pos.size, 3000, replace=False)]
+    x = pos.astype(np.float16) if dtype == "f16" else pos.astype(np.float32)
+    got = ew.evaluate([("load", 0), ("log",)], [x.reshape(-1, 1)], [], dtype).ravel()
+    from decimal import Decimal, localcontext
+    for i in range(x.size):
+        with localcontext() as ctx:
+            ctx.prec = 80
+            q = Decimal(float(x[i])).ln()
+        # the 80-digit value lies between the binary64 neighbours of float(q); when
+        # both round to the same 16-bit value, so does the 80-digit value
+        f = float(q)
+        want = _brute_round(f, vals, even, top_half_ulp)
+        assert _brute_round(math.nextafter(f, -math.inf), vals, even, top_half_ulp) == want
+        assert _brute_round(math.nextafter(f, math.inf), vals, even, top_half_ulp) == want
+        assert float(got[i]) == want, (float(x[i]), float(got[i]), want)
+
+
 def _py_int_eval(postfix, ops, scalars, dtype, i, j):
     """Pure-Python big-integer evaluation of one output element, reduced mod 2^32 per op."""
     M = 1 << 32

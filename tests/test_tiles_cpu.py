@@ -1,0 +1,69 @@
+"""CPU checks of the tiled kernels' launch planning: the vector width the library
+plans for a tile fits it (the tile's 256 threads cover whole column segments in at
+most as many passes as the tile has columns), and a kernel instance whose vector
+width does not fit its tile is refused at compile time.  No device is needed."""
+import re
+
+import pytest
+
+
+@pytest.fixture(scope="module")
+def cc():
+    from paper_2508_11385_amd import _coot
+    return _coot
+
+
+def _expr(cc, dt, n_p1):
+    """sum of n_p1 transposed leaves and one untransposed leaf (n_p1 + 1 slots)."""
+    post = [("load", 0)]
+    for k in range(n_p1):
+        post += [("load", k + 1), ("trans",), ("add",)]
+    slots = [(cc.DTYPE_CODE[dt], 0)] * (n_p1 + 1)
+    return cc.coot_expr_compile(post, slots, 0)
+
+
+def _vt(name):
+    m = re.search(r"_v(\d+)t(\d+)", name)
+    assert m, name
+    return int(m.group(1)), int(m.group(2))
+
+
+@pytest.mark.parametrize("dt", ["f16", "bf16", "f32", "f64"])
+@pytest.mark.parametrize("n_p1", [1, 4])
+def test_planned_vector_width_fits_the_tile(cc, dt, n_p1):
+    h = _expr(cc, dt, n_p1)
+    vecs = (1, 2, 4, 8) if dt in ("f16", "bf16") else (1, 2, 4)
+    modes = [(-1, -1), (cc.COOT_RED_ACCU, -1), (cc.COOT_RED_SUM, 0), (cc.COOT_RED_SUM, 1),
+             (cc.COOT_RED_MEAN_DIM, 0), (cc.COOT_RED_VAR_DIM, 1)]
+    if dt in ("u32", "s32"):
+        modes = modes[:4]
+    for mode, dim in modes:
+        for v in vecs:
+            V, TS = _vt(cc.coot_expr_kernel_name(h, mode, dim, (v, 0, 0, 0)))
+            assert V <= v and V * 256 <= TS * TS, (mode, dim, v, V, TS)
+    cc.coot_expr_release(h)
+
+
+@pytest.mark.parametrize("dt", ["f16", "bf16"])
+def test_four_transposed_16bit_leaves_compile_with_their_widest_groups(cc, dt, tmp_path, monkeypatch):
+    """Four transposed 16-bit leaves take 32 x 32 tiles (their LDS staging), where
+    16-byte groups (8 elements) would leave a pass wider than the tile: the library
+    plans 4-element groups and the dimension sums compile."""
+    monkeypatch.setenv("COOT_CACHE_DIR", str(tmp_path))
+    h = _expr(cc, dt, 4)
+    for mode, dim in ((cc.COOT_RED_SUM, 0), (cc.COOT_RED_SUM, 1), (cc.COOT_RED_VAR_DIM, 0)):
+        assert _vt(cc.coot_expr_kernel_name(h, mode, dim, (8, 0, 0, 0))) == (4, 32)
+        cc.coot_expr_prepare(h, mode, dim, cc.COOT_PF_COMPILE_ONLY, (8, 0, 0, 0))
+    cc.coot_expr_release(h)
+
+
+def test_a_vector_width_wider_than_the_tile_is_refused(cc):
+    """The tile walks assert at compile time that their passes cover the tile."""
+    h = _expr(cc, "f16", 4)
+    with pytest.raises(cc.CootError) as e:
+        cc.coot_debug_codegen(h, cc.COOT_RED_SUM, 0, 0, 1, 8, 0, 32, True)
+    assert e.value.status == cc.COOT_ECOMPILE
+    assert "passes must cover" in str(e.value) or "static" in str(e.value).lower()
+    src, size = cc.coot_debug_codegen(h, cc.COOT_RED_SUM, 0, 0, 1, 4, 0, 32, True)
+    assert size > 1000
+    cc.coot_expr_release(h)
