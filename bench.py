@@ -37,6 +37,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--cpu-cols", type=int, default=4096, help="columns of the problem the CPU oracle is timed on")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-other-configs", action="store_true",
+                   help="skip the other workloads (axpy+dot, fp64 step, integers, 2^28 reductions, batch)")
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic_tile_Z_4096_f32.json"))
     p.add_argument("--workload", default="expr4096", choices=["expr4096", "batch", "tuner", "suite"],
                    help="expr4096: the fused 2-D expression step (default); batch: 10,000 small expressions")
@@ -205,6 +207,45 @@ def main():
     z_ms = sum(a.elapsed_time(b) for a, b in z_events) / len(z_events)
     t_unfused = run(unfused, max(3, args.steps // 4), 2)
 
+    # cache-cold protocol: before each measured kernel a 512 MiB read evicts L2 and the
+    # Infinity Cache; HIP events bracket that kernel (or the statement's kernels) only;
+    # median of `reps` after 3 warm-ups
+    def cold(fn, reps=20):
+        ts = []
+        for i in range(reps + 3):
+            cc.coot_flush_caches(stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            if i >= 3:
+                ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[len(ts) // 2] * 1e-3
+
+    hz, hw = fused
+    parts = {
+        "Z": (lambda: cc.coot_expr_eval(hz, zops, zf.scalars, zo, cfgs["Z"], stream), 5 * MIB64),
+        "W": (lambda: cc.coot_expr_eval(hw, wops, wf.scalars, wo, cfgs["W"], stream), 3 * MIB64),
+        "sumZ0": (lambda: cc.coot_reduce(hz, zops, zf.scalars, cc.COOT_RED_SUM, 0, 0, s0o, None, stream),
+                  4 * MIB64 + N * 4),
+        "sumZ1": (lambda: cc.coot_reduce(hz, zops, zf.scalars, cc.COOT_RED_SUM, 1, 0, s1o, None, stream),
+                  4 * MIB64 + N * 4),
+    }
+    cold_s = {k: cold(fn) for k, (fn, nb) in parts.items()}
+    cold_step = sum(cold_s.values())
+    hzu, hwu = unfused
+    uparts = {
+        "Z": lambda: cc.coot_expr_eval(hzu, zops, zf.scalars, zo, None, stream),
+        "W": lambda: cc.coot_expr_eval(hwu, wops, wf.scalars, wo, None, stream),
+        "sumZ0": lambda: cc.coot_reduce(hzu, zops, zf.scalars, cc.COOT_RED_SUM, 0, 0, s0o, None, stream),
+        "sumZ1": lambda: cc.coot_reduce(hzu, zops, zf.scalars, cc.COOT_RED_SUM, 1, 0, s1o, None, stream),
+    }
+    cold_unfused = sum(cold(fn, 10) for fn in uparts.values())
+    # unfused bytes per step: every operator reads its operands and writes a temporary
+    # (Z: 13, W: 9, each fused sum: Z's 13 + 1) x 64 MiB, against 16 x 64 MiB fused
+    byte_ceiling = (13 + 9 + 14 + 14) / 16
+
     value = bytes_step / t_fused / 1e9
     z_gbs = 5 * MIB64 / (z_ms * 1e-3) / 1e9
     zname = cc.coot_expr_kernel_name(fused[0], cfg=cfgs["Z"])
@@ -213,6 +254,11 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(A, B, C, D, args.cpu_cols)
+    others = None
+    if not args.no_other_configs:
+        del gA, gB, gC, gD, Zout, Wout, copy_out, zexpr, wexpr, zf, wf, copy_flat, zops, wops, cops
+        torch.cuda.empty_cache()
+        others = other_configs(args)
 
     out = {
         "metric": "fused-expr effective HBM GB/s (% of peak); speedup vs unfused per-op kernels",
@@ -244,13 +290,210 @@ def main():
         "default_cfg_ms_per_step": round(t_default * 1e3, 4),
         "unfused_ms_per_step": round(t_unfused * 1e3, 4),
         "speedup_vs_unfused": round(t_unfused / t_fused, 2),
+        "speedup_byte_ceiling": byte_ceiling,
+        "unfused_comparator": "one kernel and one temporary per operator, plain stores (temporaries stay "
+                              "in L2 / the Infinity Cache for the next operator), steps back to back",
+        "cold": {
+            "protocol": "512 MiB read before each measured kernel (evicts L2 and the Infinity Cache), HIP "
+                        "events around that kernel (a sum: its two stages) only, median of 20",
+            "ms_per_step": round(cold_step * 1e3, 4),
+            "GBps": round(bytes_step / cold_step / 1e9, 1),
+            "pct_of_peak": round(100 * bytes_step / cold_step / 1e9 / PEAK_HBM_GBS, 1),
+            "kernels": {k: {"us": round(cold_s[k] * 1e6, 2), "GBps": round(nb / cold_s[k] / 1e9, 1),
+                            "frac": round(nb / cold_s[k] / 1e9 / PEAK_HBM_GBS, 3)} for k, (fn, nb) in parts.items()},
+            "unfused_ms_per_step": round(cold_unfused * 1e3, 4),
+            "speedup_vs_unfused": round(cold_unfused / cold_step, 2),
+        },
         "roofline": {"bound": "hbm", "kernel": zname,
                      "achieved": round(z_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(z_gbs / PEAK_HBM_GBS, 3), "traffic": traffic,
                      "avg_kernel_us": round(z_ms * 1e3, 2), "algorithmic_bytes": 5 * MIB64},
         "cpu_baseline": cpu,
+        "other_configs": others,
     }
     print(json.dumps(out), flush=True)
+
+
+def other_configs(args):
+    """The other workloads the method is specified on, each at its full size, GPU time by HIP
+    events (inputs resident in HBM): axpy then dot on 1e6 fp32 (two statements, and one pass),
+    the 4096 x 4096 step in fp64, u32 (A+B)%C and s32 A-3*B on 8192 x 8192, compensated
+    accu and norm over 2^28 lognormal fp32 values, and 10,000 small expressions as one
+    autotuned batch launch.  Bytes are algorithmic (operands read once, results written
+    once); `cold` times single launches after a 512 MiB cache flush (median of 10)."""
+    import numpy as np
+    import torch
+    import paper_2508_11385_amd as coot
+    from paper_2508_11385_amd import _coot as cc
+    import synth
+
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def warm_us(fn, reps=20):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e3
+
+    def cold_us(fn, reps=10):
+        ts = []
+        for i in range(reps + 2):
+            cc.coot_flush_caches(stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            if i >= 2:
+                ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[len(ts) // 2] * 1e3
+
+    def entry(nbytes, fn, cold=True, reps=20):
+        us = warm_us(fn, reps)
+        r = {"us": round(us, 2), "GBps": round(nbytes / us / 1e3, 1),
+             "frac": round(nbytes / us / 1e3 / PEAK_HBM_GBS, 3), "bytes": nbytes}
+        if cold:
+            uc = cold_us(fn)
+            r.update({"us_cold": round(uc, 2), "GBps_cold": round(nbytes / uc / 1e3, 1),
+                      "frac_cold": round(nbytes / uc / 1e3 / PEAK_HBM_GBS, 3)})
+        return r
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    res = {}
+    # axpy y = 2.5 x + y in place, then accu(x % y) with the new y, on 1e6 fp32
+    x, y = synth.axpy_inputs()
+    gx, gy = coot.Mat.from_numpy(x, kind="col"), coot.Mat.from_numpy(y, kind="col")
+    n = x.shape[0]
+
+    def two_statements():
+        coot.eval(2.5 * gx + gy, out=gy)
+        coot.accu(gx % gy)
+
+    # statements built once and called repeatedly (the front end keeps each expression
+    # object's flattened form and argument arrays)
+    axpy, dotx = 2.5 * gx + gy, gx % gy
+    d1 = coot.Mat.empty(1, 1, "f32")
+
+    def two_statements():
+        coot.eval(axpy, out=gy)
+        coot.accu(dotx, out=d1)
+
+    res["axpy_then_dot_1e6_f32"] = {
+        "two_statements": entry(20 * n, two_statements, cold=False, reps=200),
+        "one_pass": entry(12 * n, lambda: coot.eval_reduce(axpy, gy, dotx, res=d1), cold=False, reps=200),
+        "note": "4 + 4 MB operands stay in the Infinity Cache between calls: latency-bound, not a "
+                "bandwidth workload"}
+    log(f"axpy+dot {res['axpy_then_dot_1e6_f32']}")
+    # host cost of one call on a cached expression: calls queued back to back on a tiny
+    # operand, wall time per call with the GPU work far shorter than the host's
+    t1 = coot.Mat.from_numpy(np.ones((256, 1), np.float32), kind="col")
+    t2 = coot.Mat.empty(256, 1, "f32", "col")
+    te = 2.0 * t1 + t1
+    tflat = coot.flatten(te)
+    th = coot.frontend.compiled(tflat)
+    tops = cc._arr(cc.coot_operand, [m.operand() for m in tflat.mats])
+    tsc = cc._arr(cc.C.c_double, tflat.scalars)
+    tout = t2.operand()
+
+    def host_us(fn, reps=2000):
+        for _ in range(50):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        t = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        return t / reps * 1e6
+
+    res["host_us_per_call"] = {
+        "abi_eval": round(host_us(lambda: cc.lib.coot_expr_eval(th, tops, tsc, cc.C.byref(tout), None, stream)), 2),
+        "frontend_eval": round(host_us(lambda: coot.eval(te, out=t2)), 2),
+        "frontend_accu": round(host_us(lambda: coot.accu(te, out=d1)), 2),
+        "frontend_eval_new_tree": round(host_us(lambda: coot.eval(2.0 * t1 + t1, out=t2)), 2),
+        "note": "wall time per call of calls queued back to back (256-element operands): the library "
+                "call alone (ctypes), and through the front end on a cached expression object, "
+                "and with the tree built anew each call"}
+    log(f"host {res['host_us_per_call']}")
+    del gx, gy, t1, t2
+
+    # the 2-D step in fp64
+    A, B, C, D = synth.matrix_inputs(N, "f64")
+    gA, gB, gC, gD = (coot.Mat.from_numpy(m) for m in (A, B, C, D))
+    del A, B, C, D
+    Z = 2.0 * gA + gB % gC - coot.trans(gD)
+    W = coot.exp(gA) / (1.0 + coot.abs(gB))
+    oz, ow = coot.Mat.empty(N, N, "f64"), coot.Mat.empty(N, N, "f64")
+    s0, s1 = coot.Mat.empty(1, N, "f64", "row"), coot.Mat.empty(N, 1, "f64", "col")
+
+    def step64():
+        coot.eval(Z, out=oz)
+        coot.eval(W, out=ow)
+        coot.sum(Z, 0, out=s0)
+        coot.sum(Z, 1, out=s1)
+
+    res["step_4096_f64"] = entry(2 * (16 * MIB64 + 2 * N * 4), step64, reps=10)
+    del gA, gB, gC, gD, Z, W, oz, ow, s0, s1
+    torch.cuda.empty_cache()
+    log(f"fp64 step {res['step_4096_f64']}")
+
+    # integers on 8192 x 8192
+    M = 8192
+    Ai, Bi, Ci = synth.int_inputs(M, "u32")
+    gA, gB, gC = (coot.Mat.from_numpy(m) for m in (Ai, Bi, Ci))
+    del Ai, Bi, Ci
+    o = coot.Mat.empty(M, M, "u32")
+    eu = (gA + gB) % gC
+    res["u32_(A+B)%C_8192"] = entry(4 * 4 * M * M, lambda: coot.eval(eu, out=o), reps=10)
+    del gA, gB, gC, o, eu
+    As, Bs = synth.int_inputs(M, "s32_full")
+    gA, gB = coot.Mat.from_numpy(As), coot.Mat.from_numpy(Bs)
+    del As, Bs
+    o = coot.Mat.empty(M, M, "s32")
+    es = gA - 3 * gB
+    res["s32_A-3B_8192"] = entry(3 * 4 * M * M, lambda: coot.eval(es, out=o), reps=10)
+    del gA, gB, o, es
+    torch.cuda.empty_cache()
+    log("integers done")
+
+    # compensated accu and norm over 2^28 lognormal(0, 4) fp32 values with random signs
+    h = synth.hard_reduction_inputs()
+    gh = coot.Mat.from_numpy(h, kind="col")
+    del h
+    nb = 4 * (1 << 28)
+    o1 = coot.Mat.empty(1, 1, "f32")
+    res["accu_2^28_f32"] = entry(nb, lambda: coot.accu(gh, out=o1), reps=10)
+    res["norm_2^28_f32"] = entry(nb, lambda: coot.norm(gh, out=o1), reps=10)
+    res["accu_plain_2^28_f32"] = entry(nb, lambda: coot.accu(gh, plain=True, out=o1), cold=False, reps=10)
+    del gh, o1
+    torch.cuda.empty_cache()
+    log("2^28 reductions done")
+
+    # 10,000 small expressions in one autotuned graph launch
+    specs = synth.batch_workload(args.batch_n, seed=3)
+    g = synth.rng_for(3, 1)
+    exprs = [_tree(coot, spec, [coot.Mat.from_numpy(o) for o in synth.operands_for(spec, g)]) for spec in specs]
+    b = coot.Batch([(e, None) for e in exprs])
+    t0 = time.perf_counter()
+    b.tune()
+    t_tune = time.perf_counter() - t0
+    info = b.info()
+    r = entry(info["bytes"], b.launch, reps=20)
+    r.update({"expressions": info["n_exprs"], "tiles": info["n_tiles"], "tuning_s": round(t_tune, 2)})
+    res["batch_10000_f32"] = r
+    del b, exprs
+    torch.cuda.empty_cache()
+    log(f"batch {r}")
+    res["learned_tuner"] = "bench.py --workload tuner (trains on ~50,000 autotuner timings: minutes)"
+    return res
 
 
 def _tree(coot, spec, mats):
@@ -640,18 +883,22 @@ def cpu_baseline(A, B, C, D, ncols):
     wp = [("load", 0), ("exp",), ("scalar", 0), ("load", 1), ("abs",), ("add",), ("div",)]
     a, b, c, d = A[:, :ncols], B[:, :ncols], C[:, :ncols], D[:ncols, :]
     t0 = time.perf_counter()
-    Z = ew.evaluate(zp, [a, b, c, d], [2.0], "f32")
-    ew.evaluate(wp, [a, b], [1.0], "f32")
-    Z2 = ew.evaluate(zp, [a, b, c, d], [2.0], "f32")
-    [rd.to_float(q) for q in rd.sum_dim(Z2, 0, "f32")]
-    Z3 = ew.evaluate(zp, [a, b, c, d], [2.0], "f32")
-    [rd.to_float(q) for q in rd.sum_dim(Z3, 1, "f32")]
+    rounds = 0
+    while True:   # whole steps until about 10 s of CPU work
+        ew.evaluate(zp, [a, b, c, d], [2.0], "f32")
+        ew.evaluate(wp, [a, b], [1.0], "f32")
+        Z2 = ew.evaluate(zp, [a, b, c, d], [2.0], "f32")
+        [rd.to_float(q) for q in rd.sum_dim(Z2, 0, "f32")]
+        Z3 = ew.evaluate(zp, [a, b, c, d], [2.0], "f32")
+        [rd.to_float(q) for q in rd.sum_dim(Z3, 1, "f32")]
+        rounds += 1
+        if time.perf_counter() - t0 >= 10.0:
+            break
     dt = time.perf_counter() - t0
-    nbytes = 16 * N * ncols * 4
-    del Z
+    nbytes = 16 * N * ncols * 4 * rounds
     return {"value": round(nbytes / dt / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
             "sample": f"the same four expressions on columns 0..{ncols - 1} of the 4096x4096 operands "
-                      f"({ncols / N:.3f} of one step), {dt:.1f} s, numpy single-threaded "
+                      f"({ncols / N:.3f} of one step), {rounds} rounds in {dt:.1f} s, numpy single-threaded "
                       f"(1 of {os.cpu_count()} host cores)"}
 
 

@@ -113,15 +113,27 @@ typedef struct {
 } coot_operand;
 
 /* Launch configuration.  Any field 0 = chosen by the library.
- *   vec       elements per 128-bit access group: 1, 2 or 4
- *   ept       vector groups per thread per loop trip: 1, 2, 4 or 8
- *   waves     64-lane wavefronts per workgroup: 1, 2, 4 or 8
- *   grid_mult workgroups per compute unit for grid-stride kernels: 1..16        */
+ *   vec       elements per access group: 1, 2 or 4 (8 for 16-bit types: 16 bytes)
+ *   ept       vector groups per thread per loop trip: 1, 2, 4 or 8 (flat kernels)
+ *   waves     64-lane wavefronts per workgroup: 1, 2, 4 or 8 (flat kernels; the tiled
+ *             kernels run 4)
+ *   grid_mult workgroups per compute unit for grid-stride kernels: 1..16
+ *   tile_r, tile_c  output tile of the tiled kernels (transposed or strided leaves,
+ *             dimension reductions), rows x columns: powers of two in [16, 256] with
+ *             1024 <= tile_r * tile_c <= 8192, both given or both 0; the staged
+ *             transposed leaves must fit 64 KiB of LDS (tile_r * (tile_c + 1) elements
+ *             of the compute type each), else COOT_EINVAL.  A tall tile gives the
+ *             untransposed operands longer contiguous segments, a wide one the
+ *             transposed operands.  The vector width is capped at
+ *             tile_r * tile_c / 256.  Default 64 x 64 (32 x 32 when four or more
+ *             transposed leaves would not fit).  Flat kernels ignore them. */
 typedef struct {
   uint16_t vec;
   uint16_t ept;
   uint16_t waves;
   uint16_t grid_mult;
+  uint16_t tile_r;
+  uint16_t tile_c;
 } coot_launch_cfg;
 
 typedef enum {
@@ -417,21 +429,22 @@ coot_status coot_mlp_train(coot_mlp* m, const float* X, const float* y, const fl
                            void* stream);
 void coot_mlp_release(coot_mlp* m);
 
-/* Feature vectors (n x 21, host) of an expression on an n_rows x n_cols shape for
+/* Feature vectors (n x 23, host) of an expression on an n_rows x n_cols shape for
  * each configuration: n_ops, n_operands, one-hot dtype (u32 s32 f32 f64),
  * log2(1+rows), log2(1+cols), n_trans, one-hot reduction red (0 none, 1 all,
  * 2 dim0, 3 dim1), log2 vec, log2 ept, log2 waves, log2 grid_mult, then the launch
  * the configuration implies for contiguous operands on 256 CUs: log2(1+elements),
- * tiled family (transposed leaves or a dimension sum: 64 x 64 tiles, 256 threads),
- * log2(workgroups), log2(1 + elements per thread). */
+ * tiled family (transposed leaves or a dimension sum: 256 threads per tile),
+ * log2(workgroups), log2(1 + elements per thread), and log2(tile_r), log2(tile_c)
+ * of the tiled family (64 x 64 when the configuration gives none; 0, 0 for flat). */
 coot_status coot_costmodel_features(const coot_expr* e, int64_t n_rows, int64_t n_cols, int32_t red,
                                     const coot_launch_cfg* cfgs, uint32_t n, float* out);
-/* Train a cost model on N host rows: feats (N x 21), target = log(time in us)
+/* Train a cost model on N host rows: feats (N x 23), target = log(time in us)
  * (any per-signature offset may be subtracted: only the ranking within a
  * signature matters), mask (1 = use the row).  Inputs and target are z-scored with
  * the training statistics (kept in the model).  The model is an ensemble of
  * n_models (1..16) networks; network k starts from init_params[k * P .. (k+1) * P)
- * (P parameters each, layout as for coot_mlp_create with n_in 21) and draws its
+ * (P parameters each, layout as for coot_mlp_create with n_in 23) and draws its
  * batches with seed + k.  losses (may be NULL): the networks' mean loss per epoch. */
 coot_status coot_costmodel_train(const float* feats, const float* target, const float* mask, int32_t N,
                                  const float* init_params, int32_t n_models, int32_t h1, int32_t h2, int32_t epochs,
@@ -459,6 +472,12 @@ coot_status coot_tune(coot_expr* e, const coot_operand* operands, const double* 
                       int32_t mode, int32_t policy, coot_costmodel* cm, coot_launch_cfg* best, float* best_us,
                       void* stream);
 
+/* Queue on `stream` a read of a 512 MiB library buffer (allocated on first use and
+ * kept), larger than the L2 caches and the Infinity Cache together: every line a
+ * previous kernel left in them is evicted, so that the next kernel reads its operands
+ * from HBM (cache-cold timing).  Errors: COOT_ENOMEM, COOT_EHIP. */
+coot_status coot_flush_caches(void* stream);
+
 /* Counters since process start: out[0] compiles, out[1] memory-cache hits,
  * out[2] disk-cache hits, out[3] launches, out[4] total compile milliseconds. */
 void coot_stats(double out[5]);
@@ -468,11 +487,13 @@ const char* coot_last_error(void);
 /* Diagnostic: write the HIP source generated for one request into buf (at most
  * cap bytes including the terminator) and, if compile != 0, compile it with
  * hipRTC for gfx950 and report the code-object size.  Needs no device.
- *   mode -1 eval or a coot_red; fam 0 flat / 1 tiled; vec, ept, ts the
- *   compile-time variant (ept for flat, ts = tile edge 32 or 64 for tiled).
+ *   mode -1 eval or a coot_red; fam 0 flat / 1 tiled; vec, ept, tile_r, tile_c the
+ *   compile-time variant (ept for flat, the tile for tiled kernels; no checks: a
+ *   variant the kernels cannot run fails to compile, with the reason in the log).
  * Errors: COOT_EINVAL, COOT_ECOMPILE (log in coot_last_error). */
 coot_status coot_debug_codegen(coot_expr* e, int32_t mode, int32_t dim, uint32_t rflags, int32_t fam, int32_t vec,
-                               int32_t ept, int32_t ts, int32_t compile, char* buf, size_t cap, size_t* code_size);
+                               int32_t ept, int32_t tile_r, int32_t tile_c, int32_t compile, char* buf, size_t cap,
+                               size_t* code_size);
 
 #ifdef __cplusplus
 }

@@ -29,7 +29,7 @@ COOT_RF_VAR_N = 0x2
 COOT_PF_COMPILE_ONLY = 0x100
 DTYPE_CODE = {"u32": COOT_U32, "s32": COOT_S32, "f32": COOT_F32, "f64": COOT_F64, "f16": COOT_F16,
               "bf16": COOT_BF16}
-N_FEATURES = 21  # cost-model feature vector length
+N_FEATURES = 23  # cost-model feature vector length
 STATUS_NAME = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "ETYPE", -4: "EALIAS", -5: "ECOMPILE", -6: "EHIP",
                -7: "ENOMEM", -8: "EUNSUPPORTED"}
 
@@ -48,7 +48,13 @@ class coot_operand(C.Structure):
 
 
 class coot_launch_cfg(C.Structure):
-    _fields_ = [("vec", C.c_uint16), ("ept", C.c_uint16), ("waves", C.c_uint16), ("grid_mult", C.c_uint16)]
+    _fields_ = [("vec", C.c_uint16), ("ept", C.c_uint16), ("waves", C.c_uint16), ("grid_mult", C.c_uint16),
+                ("tile_r", C.c_uint16), ("tile_c", C.c_uint16)]
+
+
+def cfg_tuple(c: coot_launch_cfg) -> tuple:
+    """(vec, ept, waves, grid_mult, tile_r, tile_c) of a launch configuration."""
+    return (c.vec, c.ept, c.waves, c.grid_mult, c.tile_r, c.tile_c)
 
 
 class CootError(RuntimeError):
@@ -77,6 +83,7 @@ _sig = {
                                  C.POINTER(coot_launch_cfg), _P]),
     "coot_reduce": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(C.c_double), C.c_int32, C.c_int32,
                               C.c_uint32, C.POINTER(coot_operand), C.POINTER(coot_launch_cfg), _P]),
+    "coot_flush_caches": (C.c_int, [_P]),
     "coot_expr_eval_reduce": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(C.c_double), C.POINTER(coot_operand),
                                         _P, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int32,
                                         C.POINTER(coot_operand), C.POINTER(coot_launch_cfg), _P]),
@@ -86,7 +93,8 @@ _sig = {
     "coot_stats": (None, [C.POINTER(C.c_double)]),
     "coot_last_error": (C.c_char_p, []),
     "coot_debug_codegen": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_uint32, C.c_int32, C.c_int32, C.c_int32,
-                                     C.c_int32, C.c_int32, C.c_char_p, C.c_size_t, C.POINTER(C.c_size_t)]),
+                                     C.c_int32, C.c_int32, C.c_int32, C.c_char_p, C.c_size_t,
+                                     C.POINTER(C.c_size_t)]),
     "coot_batch_create": (C.c_int, [C.c_uint32, C.POINTER(_P), C.POINTER(C.POINTER(coot_operand)),
                                     C.POINTER(C.POINTER(C.c_double)), C.POINTER(coot_operand),
                                     C.POINTER(coot_launch_cfg), _P, C.POINTER(_P)]),
@@ -153,8 +161,7 @@ def _cfg(cfg):
         return None
     if isinstance(cfg, coot_launch_cfg):
         return C.byref(cfg)
-    vec, ept, waves, grid_mult = cfg
-    return C.byref(coot_launch_cfg(vec, ept, waves, grid_mult))
+    return C.byref(coot_launch_cfg(*cfg))   # (vec, ept, waves, grid_mult[, tile_r, tile_c])
 
 
 # ---- entry points -----------------------------------------------------------------
@@ -222,6 +229,10 @@ def coot_reduce(h: int, operands, scalars, kind: int, dim: int, flags: int, out:
     _check(lib.coot_reduce(h, ops, sc, kind, dim, flags, C.byref(out), _cfg(cfg), stream))
 
 
+def coot_flush_caches(stream: int = 0) -> None:
+    _check(lib.coot_flush_caches(stream))
+
+
 def coot_expr_release(h: int) -> None:
     lib.coot_expr_release(h)
 
@@ -242,11 +253,13 @@ def coot_last_error() -> str:
     return lib.coot_last_error().decode(errors="replace")
 
 
-def coot_debug_codegen(h: int, mode: int, dim: int, rflags: int, fam: int, vec: int, ept: int, ts: int,
+def coot_debug_codegen(h: int, mode: int, dim: int, rflags: int, fam: int, vec: int, ept: int, tile,
                        compile: bool):
     buf = C.create_string_buffer(1 << 18)
     n = C.c_size_t()
-    _check(lib.coot_debug_codegen(h, mode, dim, rflags, fam, vec, ept, ts, int(compile), buf, 1 << 18, C.byref(n)))
+    tr, tc = (tile, tile) if isinstance(tile, int) else tile     # an edge, or (tile_r, tile_c)
+    _check(lib.coot_debug_codegen(h, mode, dim, rflags, fam, vec, ept, tr, tc, int(compile), buf, 1 << 18,
+                                  C.byref(n)))
     return buf.value.decode(), n.value
 
 
@@ -298,7 +311,7 @@ def coot_tune_space(family: int) -> list:
     n = lib.coot_tune_space(family, None, 0)
     a = (coot_launch_cfg * n)()
     lib.coot_tune_space(family, a, n)
-    return [(c.vec, c.ept, c.waves, c.grid_mult) for c in a]
+    return [cfg_tuple(c) for c in a]
 
 
 def _cfgs(cfgs):
@@ -336,7 +349,7 @@ def coot_tune(h: int, operands, scalars, out: coot_operand, mode: int, policy: i
     us = C.c_float()
     _check(lib.coot_tune(h, _arr(coot_operand, operands), _arr(C.c_double, scalars), C.byref(out), mode, policy,
                          cm or None, C.byref(best), C.byref(us), stream))
-    return (best.vec, best.ept, best.waves, best.grid_mult), us.value
+    return cfg_tuple(best), us.value
 
 
 # ---- MLP and cost model -------------------------------------------------------------------

@@ -186,7 +186,8 @@ const char* coot_last_error(void) { return last_error().c_str(); }
 // Diagnostic: the generated source for a request, optionally compiled with
 // hipRTC (no device needed).  mode -1 = eval; fam 0 flat / 1 tiled.
 coot_status coot_debug_codegen(coot_expr* h, int32_t mode, int32_t dim, uint32_t rflags, int32_t fam, int32_t vec,
-                               int32_t ept, int32_t ts, int32_t compile, char* buf, size_t cap, size_t* code_size) {
+                               int32_t ept, int32_t tile_r, int32_t tile_c, int32_t compile, char* buf, size_t cap,
+                               size_t* code_size) {
   return guarded([&] {
     if (!h || !buf || cap == 0) fail(COOT_EINVAL, "NULL argument");
     Expr& e = *h->e;
@@ -198,7 +199,8 @@ coot_status coot_debug_codegen(coot_expr* h, int32_t mode, int32_t dim, uint32_t
     rq.fam = fam ? FAM_TILE : FAM_FLAT;
     rq.var.vec = vec;
     rq.var.ept = ept;
-    rq.var.ts = ts;
+    rq.var.tr = tile_r;
+    rq.var.tc = tile_c;
     KernelNames names;
     const std::string src = generate(e, rq, hex128(e.canon), &names);
     std::strncpy(buf, src.c_str(), cap - 1);

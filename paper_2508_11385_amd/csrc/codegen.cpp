@@ -27,11 +27,33 @@ const std::vector<std::pair<std::string, std::string>>& device_headers() {
   return h;
 }
 
+// A request's key: its fields as bytes (short enough for the string's inline buffer,
+// so a cache lookup on the hot path allocates nothing).
 std::string Request::key() const {
-  std::ostringstream os;
-  os << mode << ":" << dim << ":" << (comp ? 1 : 0) << ":" << (int)fam << ":" << var.vec << ":" << var.ept << ":"
-     << var.ts << ":" << (all_variants ? 1 : 0);
-  return os.str();
+  const char b[] = {(char)(mode + 2), (char)(dim + 2), (char)comp,        (char)fam,           (char)var.vec,
+                    (char)var.ept,    (char)(var.tr & 0xff), (char)(var.tr >> 8), (char)(var.tc & 0xff),
+                    (char)(var.tc >> 8), (char)all_variants, (char)plain_store};
+  return std::string(b, sizeof b);
+}
+
+bool tile_shape_ok(int tr, int tc) {
+  auto pow2 = [](int v) { return v >= 16 && v <= 256 && (v & (v - 1)) == 0; };
+  return pow2(tr) && pow2(tc) && tr * tc >= 1024 && tr * tc <= 8192;
+}
+
+size_t tile_lds_bytes(int n_p1, int dtype, int tr, int tc) {
+  const size_t es = dtype_is_half(dtype) ? 4 : dtype_size(dtype);
+  return (size_t)(n_p1 > 0 ? n_p1 : 0) * tr * (tc + 1) * es;
+}
+
+const std::vector<std::pair<int, int>>& tile_shapes() {
+  static const std::vector<std::pair<int, int>> v = {{64, 64}, {128, 32}, {32, 128}, {256, 16}, {128, 64}, {32, 32}};
+  return v;
+}
+
+// tile part of a kernel name: t<rows>x<cols>
+static std::string tile_tag(const Request& rq) {
+  return "t" + std::to_string(rq.var.tr) + "x" + std::to_string(rq.var.tc);
 }
 
 int red_kind(int mode) {
@@ -59,17 +81,17 @@ std::string variant_name(const Expr& e, const Request& rq, int V, int E) {
   const std::string hs = hex128(e.canon).substr(0, 16);
   if (rq.mode < 0) {
     if (rq.fam == FAM_FLAT) return "coot_flat_" + hs + "_v" + std::to_string(V) + "e" + std::to_string(E);
-    return "coot_tile_" + hs + "_v" + std::to_string(V) + "t" + std::to_string(rq.var.ts);
+    return "coot_tile_" + hs + "_v" + std::to_string(V) + tile_tag(rq);
   }
   if (is_dim_kind(rq.mode) && rq.dim >= 0) {
     // the sum's stage 1 serves the mean too; a variance has its own
     const char* kind = rq.mode == COOT_RED_SUM ? "" : (rq.mode == COOT_RED_VAR_DIM ? "_var" : "_mean");
     return "coot_rdim_" + hs + "_d" + std::to_string(rq.dim) + "c" + (rq.comp ? "1" : "0") + kind + "_v" +
-           std::to_string(V) + "t" + std::to_string(rq.var.ts);
+           std::to_string(V) + tile_tag(rq);
   }
   const std::string tag = "k" + std::to_string(red_kind(rq.mode)) + "c" + (rq.comp ? "1" : "0");
   if (rq.fam == FAM_FLAT) return "coot_rall_" + hs + "_" + tag + "_v" + std::to_string(V) + "e" + std::to_string(E);
-  return "coot_rtall_" + hs + "_" + tag + "_v" + std::to_string(V) + "t" + std::to_string(rq.var.ts);
+  return "coot_rtall_" + hs + "_" + tag + "_v" + std::to_string(V) + tile_tag(rq);
 }
 
 static const char* op_fn(int c) {
@@ -143,6 +165,7 @@ static std::string meta_fn(const char* fname, const std::vector<int>& v) {
 std::string generate(const Expr& e, const Request& rq, const std::string& h, KernelNames* names) {
   std::ostringstream os;
   os << "// generated by libcoot: " << e.canon << "\n";
+  if (rq.plain_store) os << "#define COOT_PLAIN_STORES 1\n";
   os << "#include \"coot_dev.h\"\n";
   os << "namespace {\n";
   os << "struct X {\n";
@@ -180,7 +203,8 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
   os << "  }\n};\n}  // namespace\n";
 
   const std::string T = dtype_cname(e.dtype);
-  const int V = rq.var.vec, E = rq.var.ept, TS = rq.var.ts;
+  const int V = rq.var.vec, E = rq.var.ept;
+  const std::string TT = std::to_string(rq.var.tr) + ", " + std::to_string(rq.var.tc);  // template tile args
   const std::string comp = rq.comp ? "true" : "false";
   // kernels of an expression with exp first copy the exp table to LDS
   bool has_exp = false;
@@ -193,28 +217,38 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
   const std::string hs = h.substr(0, 16);
   if (rq.all_variants) {
     // tuning module: every variant of the family (vec in {1,2,4}, and 8 for 16-bit types;
-    // ept in {1,2,4,8} for flat kernels)
-    const int ts = rq.var.ts;
-    for (int v : {1, 2, 4, 8}) {
-      if (v == 8 && !dtype_is_half(e.dtype)) continue;
-      for (int ept : {1, 2, 4, 8}) {
-        if (rq.fam == FAM_TILE && ept != 1) continue;
-        if (rq.fam == FAM_TILE && v > tile_vec_cap(ts)) continue;
-        const std::string nm = variant_name(e, rq, v, rq.fam == FAM_FLAT ? ept : 0);
-        std::string call;
-        if (rq.mode < 0) {
-          call = rq.fam == FAM_FLAT
-                     ? "coot::flat_eval<X, " + std::to_string(v) + ", " + std::to_string(ept) + ">(a)"
-                     : "coot::tiled_eval<X, " + std::to_string(v) + ", " + std::to_string(ts) + ">(a)";
-        } else {
-          const std::string rks2 = std::to_string(red_kind(rq.mode));
-          call = rq.fam == FAM_FLAT ? "coot::flat_reduce<X, " + rks2 + ", " + comp + ", " + std::to_string(v) + ", " +
-                                          std::to_string(ept) + ", false>(a)"
-                                    : "coot::tiled_reduce<X, " + rks2 + ", " + comp + ", " + std::to_string(v) + ", " +
-                                          std::to_string(ts) + ", false>(a)";
+    // ept in {1,2,4,8} for flat kernels; every tile shape whose staging fits, for tiled ones)
+    std::vector<std::pair<int, int>> tiles = {{0, 0}};
+    if (rq.fam == FAM_TILE) {
+      tiles.clear();
+      for (auto& t : tile_shapes())
+        if (tile_lds_bytes(e.n_p1, e.dtype, t.first, t.second) <= kTileLdsMax) tiles.push_back(t);
+    }
+    for (auto& t : tiles) {
+      Request rt = rq;
+      rt.var.tr = t.first;
+      rt.var.tc = t.second;
+      const std::string tt = std::to_string(t.first) + ", " + std::to_string(t.second);
+      for (int v : {1, 2, 4, 8}) {
+        if (v == 8 && !dtype_is_half(e.dtype)) continue;
+        for (int ept : {1, 2, 4, 8}) {
+          if (rq.fam == FAM_TILE && ept != 1) continue;
+          if (rq.fam == FAM_TILE && v > tile_vec_cap(t.first, t.second)) continue;
+          const std::string nm = variant_name(e, rt, v, rq.fam == FAM_FLAT ? ept : 0);
+          std::string call;
+          if (rq.mode < 0) {
+            call = rq.fam == FAM_FLAT ? "coot::flat_eval<X, " + std::to_string(v) + ", " + std::to_string(ept) + ">(a)"
+                                      : "coot::tiled_eval<X, " + std::to_string(v) + ", " + tt + ">(a)";
+          } else {
+            const std::string rks2 = std::to_string(red_kind(rq.mode));
+            call = rq.fam == FAM_FLAT ? "coot::flat_reduce<X, " + rks2 + ", " + comp + ", " + std::to_string(v) +
+                                            ", " + std::to_string(ept) + ", false>(a)"
+                                      : "coot::tiled_reduce<X, " + rks2 + ", " + comp + ", " + std::to_string(v) +
+                                            ", " + tt + ", false>(a)";
+          }
+          wrap(nm, call, rq.fam == FAM_FLAT ? 512 : 256);
+          if (names->stage1.empty()) names->stage1 = nm;
         }
-        wrap(nm, call, rq.fam == FAM_FLAT ? 512 : 256);
-        if (names->stage1.empty()) names->stage1 = nm;
       }
     }
     if (rq.mode >= 0) {
@@ -231,10 +265,10 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
       wrap(names->stage1, "coot::flat_eval<X, " + std::to_string(V) + ", " + std::to_string(E) + ">(a)", 512);
       if (V != 1) wrap(names->stage1_fallback, "coot::flat_eval<X, 1, " + std::to_string(E) + ">(a)", 512);
     } else {
-      names->stage1 = "coot_tile_" + hs + "_v" + std::to_string(V) + "t" + std::to_string(TS);
-      names->stage1_fallback = "coot_tile_" + hs + "_v1t" + std::to_string(TS);
-      wrap(names->stage1, "coot::tiled_eval<X, " + std::to_string(V) + ", " + std::to_string(TS) + ">(a)", 256);
-      if (V != 1) wrap(names->stage1_fallback, "coot::tiled_eval<X, 1, " + std::to_string(TS) + ">(a)", 256);
+      names->stage1 = "coot_tile_" + hs + "_v" + std::to_string(V) + tile_tag(rq);
+      names->stage1_fallback = "coot_tile_" + hs + "_v1" + tile_tag(rq);
+      wrap(names->stage1, "coot::tiled_eval<X, " + std::to_string(V) + ", " + TT + ">(a)", 256);
+      if (V != 1) wrap(names->stage1_fallback, "coot::tiled_eval<X, 1, " + TT + ">(a)", 256);
     }
     return os.str();
   }
@@ -248,14 +282,14 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
     const std::string cnt = rq.dim == 0 ? "a.n_rows" : "a.n_cols";
     const std::string kind = rq.mode == COOT_RED_SUM ? "" : (var ? "_var" : "_mean");
     auto inst = [&](int v) {
-      return "coot::tiled_reduce_dim<X, " + d + ", " + comp + ", " + std::to_string(v) + ", " + std::to_string(TS) +
+      return "coot::tiled_reduce_dim<X, " + d + ", " + comp + ", " + std::to_string(v) + ", " + TT +
              (var ? ", true" : ", false") + ">(a)";
     };
     auto fin = [&](const std::string& mode) {
       return "coot::dim_stage2<X::S, " + comp + ", coot::" + mode + ">(a, " + n_out + ", " + cnt + ")";
     };
-    names->stage1 = "coot_rdim_" + hs + dc + kind + "_v" + std::to_string(V) + "t" + std::to_string(TS);
-    names->stage1_fallback = "coot_rdim_" + hs + dc + kind + "_v1t" + std::to_string(TS);
+    names->stage1 = "coot_rdim_" + hs + dc + kind + "_v" + std::to_string(V) + tile_tag(rq);
+    names->stage1_fallback = "coot_rdim_" + hs + dc + kind + "_v1" + tile_tag(rq);
     wrap(names->stage1, inst(V), 256);
     if (V != 1) wrap(names->stage1_fallback, inst(1), 256);
     names->stage2 = "coot_rdfin_" + hs + dc + kind;
@@ -274,11 +308,10 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
   const std::string tag = "k" + std::to_string(red_kind(rq.mode)) + "c" + cs;
   const bool flat = rq.fam == FAM_FLAT;
   const std::string pre = (flat ? "coot_rall_" : "coot_rtall_") + hs + "_";
-  const std::string vs = flat ? "e" + std::to_string(E) : "t" + std::to_string(TS);
+  const std::string vs = flat ? "e" + std::to_string(E) : tile_tag(rq);
   auto inst = [&](int k, int v, bool scaled) {
     return (flat ? "coot::flat_reduce<X, " : "coot::tiled_reduce<X, ") + std::to_string(k) + ", " + comp + ", " +
-           std::to_string(v) + ", " + (flat ? std::to_string(E) : std::to_string(TS)) + ", " +
-           (scaled ? "true" : "false") + ">(a)";
+           std::to_string(v) + ", " + (flat ? std::to_string(E) : TT) + ", " + (scaled ? "true" : "false") + ">(a)";
   };
   const int bounds = flat ? 512 : 256;
   auto fin = [&](int k) { return "coot::reduce_stage2<X::S, " + std::to_string(k) + ", " + comp + ", false>(a)"; };

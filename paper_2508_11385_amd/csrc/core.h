@@ -91,14 +91,24 @@ int red_kind(int mode);
 // a reduction mode's arguments are valid for this expression (fails with the reason)
 void check_red_mode(const Expr& e, int mode);
 
-// Largest vector width of a TS x TS tile of 256 threads: the TS / V threads of a
-// column segment times TS columns must cover the 256 threads (V <= TS^2 / 256).
-inline int tile_vec_cap(int ts) { return ts * ts / 256; }
+// Tiles of the tiled families: tr x tc output elements (rows x columns), 256 threads.
+// The tr / V threads of a column segment times tc columns must cover the 256 threads
+// (V <= tr * tc / 256); V divides both edges.  Edges are powers of two in [16, 256]
+// with 1024 <= tr * tc <= 8192 (4 to 32 elements per thread).
+inline int tile_vec_cap(int tr, int tc) { return tr * tc / 256; }
+bool tile_shape_ok(int tr, int tc);
+// LDS bytes the staged transposed leaves of a tile take (compute-type elements, one
+// padded tr x (tc + 1) tile per transposed leaf); the library keeps this <= 64 KiB.
+size_t tile_lds_bytes(int n_p1, int dtype, int tr, int tc);
+constexpr size_t kTileLdsMax = 65536;
+// Tile shapes the autotuner tries (those whose staging fits kTileLdsMax).
+const std::vector<std::pair<int, int>>& tile_shapes();
 
 struct Variant {  // compile-time parameters of one kernel instance
   int vec = 4;
   int ept = 4;     // flat families
-  int ts = 64;     // tiled families
+  int tr = 64;     // tiled families: tile rows
+  int tc = 64;     //                 tile columns
 };
 
 struct Request {
@@ -108,10 +118,11 @@ struct Request {
   Family fam = FAM_FLAT;
   Variant var;
   bool all_variants = false;  // tuning module: every vec x ept (flat) or vec (tiled) variant
+  bool plain_store = false;   // results stored with plain (cached) stores: the unfused comparator's temporaries
   std::string key() const;
 };
 
-// Kernel name of one variant (the naming convention codegen uses).
+// Kernel name of one variant (the naming convention codegen uses); the tile is rq.var's.
 std::string variant_name(const Expr& e, const Request& rq, int vec, int ept);
 
 struct KernelNames {
@@ -168,8 +179,10 @@ void temp_free(void* p, size_t bytes, hipStream_t s);
 
 // Execution ---------------------------------------------------------------------
 void launch(hipFunction_t f, unsigned grid, unsigned block, const KArgs& args, hipStream_t s);
+// plain_store: the kernel stores its result with plain stores (kept in L2 and the
+// Infinity Cache for a kernel that reads it next), as the unfused comparator does
 void eval_fused(Expr& e, const coot_operand* ops, const double* scalars, const coot_operand& out,
-                const coot_launch_cfg* cfg, hipStream_t s);
+                const coot_launch_cfg* cfg, hipStream_t s, bool plain_store = false);
 void eval_unfused(Expr& e, const coot_operand* ops, const double* scalars, const coot_operand& out,
                   const coot_launch_cfg* cfg, hipStream_t s);
 void eval_reduce(Expr& e, const coot_operand* ops, const double* scalars, const coot_operand& out, Expr& r,
@@ -188,7 +201,7 @@ int64_t ld_of(const coot_operand& o);
 bool vec_ok(const Expr& e, const Request& rq, const coot_operand* ops, const coot_operand* out, int64_t R, int64_t C);
 void fill_args(const Expr& e, const coot_operand* ops, const double* scalars, KArgs* a);
 unsigned flat_grid(int64_t n, int V, int E, int bs, int gm);
-unsigned tile_grid(int64_t R, int64_t C, int ts, int gm);
+unsigned tile_grid(int64_t R, int64_t C, int tr, int tc, int gm);
 
 // Thread-local message behind coot_last_error().
 std::string& last_error();

@@ -3,11 +3,12 @@
 // predicts log(time) for every configuration of an expression signature on a
 // shape; the prediction's argmin is the chosen configuration.
 //
-// Feature vector (21 values): n_ops, n_operands, one-hot dtype (u32 s32 f32 f64),
+// Feature vector (23 values): n_ops, n_operands, one-hot dtype (u32 s32 f32 f64),
 // log2(1 + rows), log2(1 + cols), n_trans, one-hot reduction (none all dim0 dim1),
 // log2 vec, log2 ept, log2 waves, log2 grid_mult, then four launch quantities the
 // configuration implies (for contiguous operands on 256 CUs): log2(1 + elements),
-// the tiled-family flag, log2(workgroups launched), log2(1 + elements per thread).
+// the tiled-family flag, log2(workgroups launched), log2(1 + elements per thread),
+// and the tile of the tiled family, log2(tile_r) and log2(tile_c) (0 for flat kernels).
 // Inputs and the target are z-scored with the training set's statistics, stored
 // with the weights.  A model is an ensemble of networks trained from different
 // initial parameters and batch orders; its prediction is their mean.
@@ -251,7 +252,7 @@ void coot_mlp_release(coot_mlp* m) { delete m; }
 // ---------------------------------------------------------------------------------
 // Cost model
 // ---------------------------------------------------------------------------------
-static constexpr int kNF = 21;
+static constexpr int kNF = 23;
 static constexpr int kFeatCUs = 256;  // CU count the launch-quantity features assume
 static constexpr int kMaxModels = 16;
 
@@ -300,14 +301,15 @@ void features_of(const Expr& e, int64_t R, int64_t C, int red, const coot_launch
   f[k++] = (float)std::log2((double)c.waves);
   f[k++] = (float)std::log2((double)c.grid_mult);
   // launch quantities: the tiled family (transposed leaves or a dimension sum) runs
-  // 256 threads per 64 x 64 tile; the flat family 64 * waves threads, each taking
-  // ept groups of vec elements per pass
+  // 256 threads per tile_r x tile_c tile (64 x 64 when the configuration names none);
+  // the flat family 64 * waves threads, each taking ept groups of vec elements per pass
   const double n = (double)R * (double)C;
   const bool tiled = e.n_p1 > 0 || red >= 2;
   const double cap = (double)c.grid_mult * kFeatCUs;
+  const double tr = c.tile_r ? c.tile_r : 64, tcl = c.tile_c ? c.tile_c : 64;
   double grid, threads;
   if (tiled) {
-    grid = std::min(std::ceil((double)R / 64) * std::ceil((double)C / 64), cap);
+    grid = std::min(std::ceil((double)R / tr) * std::ceil((double)C / tcl), cap);
     threads = 256;
   } else {
     threads = 64.0 * c.waves;
@@ -318,6 +320,8 @@ void features_of(const Expr& e, int64_t R, int64_t C, int red, const coot_launch
   f[k++] = tiled ? 1.0f : 0.0f;
   f[k++] = (float)std::log2(grid);
   f[k++] = (float)std::log2(1.0 + n / (grid * threads));
+  f[k++] = tiled ? (float)std::log2(tr) : 0.0f;
+  f[k++] = tiled ? (float)std::log2(tcl) : 0.0f;
 }
 
 }  // namespace
@@ -521,7 +525,7 @@ coot_status coot_tune(coot_expr* h, const coot_operand* operands, const double* 
       cand = space;
       if (dtype_is_half(h->e->dtype))  // 16-byte groups of 16-bit elements as well
         for (const auto& c : space)
-          if (c.vec == 4) cand.push_back({8, c.ept, c.waves, c.grid_mult});
+          if (c.vec == 4) cand.push_back({8, c.ept, c.waves, c.grid_mult, c.tile_r, c.tile_c});
     } else if (policy == 2) {
       if (!cm) fail(COOT_EINVAL, "the MLP policy needs a cost model");
       int64_t R, C;

@@ -197,32 +197,43 @@ __device__ __forceinline__ vt<T, V> ldv(const T* p) {
 
 // Results are written with non-temporal stores: an expression's output is streamed
 // once, and keeping it out of L2 and the Infinity Cache leaves no dirty lines to be
-// written back while the next kernel streams its own operands.
+// written back while the next kernel streams its own operands.  A module generated
+// with COOT_PLAIN_STORES (the unfused comparator, whose temporaries the next operator
+// reads at once) stores through the caches instead.
+template <typename W>
+__device__ __forceinline__ void st_word(W* p, W q) {
+#ifdef COOT_PLAIN_STORES
+  *p = q;
+#else
+  __builtin_nontemporal_store(q, p);
+#endif
+}
+
 template <typename T, int V>
 __device__ __forceinline__ void stv(T* p, const vt<T, V>& r) {
   constexpr int B = V * (int)sizeof(T);
   if constexpr (B == 2) {
     unsigned short q;
     __builtin_memcpy(&q, &r, 2);
-    __builtin_nontemporal_store(q, reinterpret_cast<unsigned short*>(p));
+    st_word(reinterpret_cast<unsigned short*>(p), q);
   } else if constexpr (B == 4) {
     u32 q;
     __builtin_memcpy(&q, &r, 4);
-    __builtin_nontemporal_store(q, reinterpret_cast<u32*>(p));
+    st_word(reinterpret_cast<u32*>(p), q);
   } else if constexpr (B == 8) {
     u32x2 q;
     __builtin_memcpy(&q, &r, 8);
-    __builtin_nontemporal_store(q, reinterpret_cast<u32x2*>(p));
+    st_word(reinterpret_cast<u32x2*>(p), q);
   } else if constexpr (B == 16) {
     u32x4 q;
     __builtin_memcpy(&q, &r, 16);
-    __builtin_nontemporal_store(q, reinterpret_cast<u32x4*>(p));
+    st_word(reinterpret_cast<u32x4*>(p), q);
   } else {
     u32x4 q0, q1;
     __builtin_memcpy(&q0, &r, 16);
     __builtin_memcpy(&q1, reinterpret_cast<const char*>(&r) + 16, 16);
-    __builtin_nontemporal_store(q0, reinterpret_cast<u32x4*>(p));
-    __builtin_nontemporal_store(q1, reinterpret_cast<u32x4*>(p) + 1);
+    st_word(reinterpret_cast<u32x4*>(p), q0);
+    st_word(reinterpret_cast<u32x4*>(p) + 1, q1);
   }
 }
 
@@ -839,67 +850,120 @@ __device__ __forceinline__ void flat_eval_reduce(const coot_kargs& a) {
 }
 
 // ===========================================================================
-// TILED traversal.  TS x TS output tiles, 256 threads.  Parity-1 leaves (stored
-// n_cols x n_rows) are read along their own contiguous dimension into LDS;
-// parity-0 leaves and the output are accessed along output columns.  Any
-// leading dimensions and ragged edges; V > 1 only when every contiguous extent,
-// leading dimension and base address allows it (host-checked).
+// TILED traversal.  TR x TC output tiles (rows x columns), 256 threads.  Parity-1
+// leaves (stored n_cols x n_rows) are read along their own contiguous dimension
+// into an LDS tile; parity-0 leaves and the output are accessed along output
+// columns: TR / V threads cover a column segment of the tile with V-element
+// accesses, and the 256 threads cover TC columns in NPASS passes.  A tall tile
+// (TR > TC) gives the untransposed operands longer contiguous segments, a wide one
+// the transposed operands.  Any leading dimensions and ragged edges; V > 1 only
+// when every contiguous extent, leading dimension and base address allows it
+// (host-checked).  The parity-0 loads of every pass are issued before the
+// transposed leaves are staged (when they fit in NPASS * NL * V <= 64 registers'
+// worth), so a tile's two load phases overlap instead of following each other.
 // A Sink receives each element (with its leaf values) and each finished group.
 // ===========================================================================
-template <class X, int V, int TS, class Sink>
+template <class X, int V, int TR, int TC>
+struct TileGeom {
+  static constexpr int NB = 256;
+  static constexpr int TPC = TR / V;       // threads along a column segment
+  static constexpr int CPP = NB / TPC;     // columns per pass
+  static constexpr int NPASS = TC / CPP;   // passes per tile
+  static constexpr int TPS = TC / V;       // staging: threads along a stored segment of a transposed leaf
+  static constexpr int RPS = NB / TPS;     // staging: stored segments (tile rows) per pass
+  static constexpr int NPS = X::NP1 > 0 ? X::NP1 : 1;
+  static constexpr int N0 = X::NL - X::NP1;  // parity-0 leaves
+  static constexpr bool HOIST = NPASS * (N0 > 0 ? N0 : 1) * V * (int)sizeof(typename X::T) <= 256;
+  static_assert(TR % V == 0 && TC % V == 0 && TPC <= NB && TPS <= NB, "vector width must divide the tile");
+  static_assert(CPP <= TC && TC % CPP == 0, "a tile's passes must cover its columns");
+};
+
+// Stage the transposed leaves of tile (i0, j0) into LDS (lds[p1][il][jl], zero
+// outside the matrix).
+template <class X, int V, int TR, int TC>
+__device__ __forceinline__ void stage_transposed(const coot_kargs& a, typename X::T (*lds)[TR][TC + 1], i64 i0,
+                                                 i64 j0) {
+  typedef typename X::T T;
+  typedef TileGeom<X, V, TR, TC> G;
+  const int sc = threadIdx.x % G::TPS, sr = threadIdx.x / G::TPS;
+  for (int il = sr; il < TR; il += G::RPS) {
+    const i64 i = i0 + il, j = j0 + (i64)sc * V;
+    const bool in = (i < a.n_rows) && (j < a.n_cols);
+#pragma unroll
+    for (int k = 0; k < X::NL; ++k) {
+      if (X::par(k) == 0) continue;
+      vt<T, V> v;
+      if (in) {
+        v = ldc<typename X::S, V>((const typename X::S*)a.leaf[X::slot(k)] + j + i * a.ld[X::slot(k)]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < V; ++q) v.v[q] = (T)0;
+      }
+#pragma unroll
+      for (int q = 0; q < V; ++q) lds[X::p1(k) < 0 ? 0 : X::p1(k)][il][sc * V + q] = v.v[q];
+    }
+  }
+}
+
+// The parity-0 leaves of one pass of tile (i0, j0): column j0 + jl, rows i0 + lc * V ...
+template <class X, int V>
+__device__ __forceinline__ void load_pass(const coot_kargs& a, i64 i, i64 j, bool in, vt<typename X::T, V> (&x)[X::NL]) {
+  if (in) {
+#pragma unroll
+    for (int k = 0; k < X::NL; ++k)
+      if (X::par(k) == 0) x[k] = ldc<typename X::S, V>((const typename X::S*)a.leaf[X::slot(k)] + i + j * a.ld[X::slot(k)]);
+  }
+}
+
+// One pass's elements handed to the sink: leaf values from the registers (parity 0)
+// or the staged LDS tile (parity 1).  ELEM(q, in, L) receives element q of the group.
+template <class X, int V, int TR, int TC, class F>
+__device__ __forceinline__ void pass_elems(typename X::T (*lds)[TR][TC + 1], const vt<typename X::T, V> (&x)[X::NL],
+                                           int lc, int jl, bool in, F&& elem) {
+  typedef typename X::T T;
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    T L[X::NL];
+#pragma unroll
+    for (int k = 0; k < X::NL; ++k)
+      L[k] = X::par(k) ? lds[X::p1(k) < 0 ? 0 : X::p1(k)][lc * V + q][jl] : (in ? x[k].v[q] : (T)0);
+    elem(q, in, L);
+  }
+}
+
+template <class X, int V, int TR, int TC, class Sink>
 __device__ __forceinline__ void tiled_walk(const coot_kargs& a, Sink& sink) {
   typedef typename X::T T;
-  constexpr int NB = 256;
-  constexpr int TPC = TS / V;     // threads along a column segment
-  constexpr int CPP = NB / TPC;   // columns per pass
-  constexpr int NPS = X::NP1 > 0 ? X::NP1 : 1;
-  static_assert(TS % V == 0 && CPP <= TS && TS % CPP == 0, "a tile's passes must cover its columns");
-  __shared__ T lds[NPS][TS][TS + 1];
+  typedef TileGeom<X, V, TR, TC> G;
+  __shared__ T lds[G::NPS][TR][TC + 1];
   const i64 R = a.n_rows, C = a.n_cols;
-  const i64 tr = (R + TS - 1) / TS, tc = (C + TS - 1) / TS, nt = tr * tc;
-  const int lc = threadIdx.x % TPC, lr = threadIdx.x / TPC;
+  const i64 tr = (R + TR - 1) / TR, tc = (C + TC - 1) / TC, nt = tr * tc;
+  const int lc = threadIdx.x % G::TPC, lr = threadIdx.x / G::TPC;
   for (i64 t = blockIdx.x; t < nt; t += gridDim.x) {
     const i64 ti = t % tr, tj = t / tr;
-    const i64 i0 = ti * TS, j0 = tj * TS;
+    const i64 i0 = ti * TR, j0 = tj * TC;
+    const i64 i = i0 + (i64)lc * V;
     sink.begin_tile();
-    if constexpr (X::NP1 > 0) {
-      for (int il = lr; il < TS; il += CPP) {
-        const i64 i = i0 + il, j = j0 + (i64)lc * V;
-        const bool in = (i < R) && (j < C);
+    vt<T, V> x[G::HOIST ? G::NPASS : 1][X::NL];
+    if constexpr (G::HOIST) {
 #pragma unroll
-        for (int k = 0; k < X::NL; ++k) {
-          if (X::par(k) == 0) continue;
-          vt<T, V> v;
-          if (in) {
-            v = ldc<typename X::S, V>((const typename X::S*)a.leaf[X::slot(k)] + j + i * a.ld[X::slot(k)]);
-          } else {
-#pragma unroll
-            for (int q = 0; q < V; ++q) v.v[q] = (T)0;
-          }
-#pragma unroll
-          for (int q = 0; q < V; ++q) lds[X::p1(k) < 0 ? 0 : X::p1(k)][il][lc * V + q] = v.v[q];
-        }
+      for (int p = 0; p < G::NPASS; ++p) {
+        const i64 j = j0 + lr + p * G::CPP;
+        load_pass<X, V>(a, i, j, (i < R) && (j < C), x[p]);
       }
+    }
+    if constexpr (X::NP1 > 0) {
+      stage_transposed<X, V, TR, TC>(a, lds, i0, j0);
       __syncthreads();
     }
-    for (int jl = lr; jl < TS; jl += CPP) {
-      const i64 j = j0 + jl, i = i0 + (i64)lc * V;
+#pragma unroll
+    for (int p = 0; p < G::NPASS; ++p) {
+      const int jl = lr + p * G::CPP;
+      const i64 j = j0 + jl;
       const bool in = (i < R) && (j < C);
-      vt<T, V> x[X::NL];
-      if (in) {
-#pragma unroll
-        for (int k = 0; k < X::NL; ++k)
-          if (X::par(k) == 0)
-            x[k] = ldc<typename X::S, V>((const typename X::S*)a.leaf[X::slot(k)] + i + j * a.ld[X::slot(k)]);
-      }
-#pragma unroll
-      for (int q = 0; q < V; ++q) {
-        T L[X::NL];
-#pragma unroll
-        for (int k = 0; k < X::NL; ++k)
-          L[k] = X::par(k) ? lds[X::p1(k) < 0 ? 0 : X::p1(k)][lc * V + q][jl] : (in ? x[k].v[q] : (T)0);
-        sink.elem(a, q, in, L);
-      }
+      if constexpr (!G::HOIST) load_pass<X, V>(a, i, j, in, x[0]);
+      pass_elems<X, V, TR, TC>(lds, x[G::HOIST ? p : 0], lc, jl, in,
+                               [&](int q, bool inq, const T* L) { sink.elem(a, q, inq, L); });
       sink.group(a, i, j, jl, lc, in);
     }
     sink.end_tile(a, ti, tj, i0, j0, lr, lc);
@@ -921,10 +985,10 @@ struct EvalSink {
   __device__ __forceinline__ void end_tile(const coot_kargs&, i64, i64, i64, i64, int, int) {}
 };
 
-template <class X, int V, int TS>
+template <class X, int V, int TR, int TC>
 __device__ __forceinline__ void tiled_eval(const coot_kargs& a) {
   EvalSink<X, V> s;
-  tiled_walk<X, V, TS>(a, s);
+  tiled_walk<X, V, TR, TC>(a, s);
 }
 
 // Full reduction over the tiled traversal (transposed or strided leaves).
@@ -945,7 +1009,7 @@ struct AllSink {
   __device__ __forceinline__ void end_tile(const coot_kargs&, i64, i64, i64, i64, int, int) {}
 };
 
-template <class X, int RK, bool COMP, int V, int TS, bool SCALED>
+template <class X, int RK, bool COMP, int V, int TR, int TC, bool SCALED>
 __device__ __forceinline__ void tiled_reduce(const coot_kargs& a) {
   typedef typename X::T T;
   AllSink<X, RK, COMP, SCALED> s;
@@ -958,7 +1022,7 @@ __device__ __forceinline__ void tiled_reduce(const coot_kargs& a) {
     if (ctl[0] == 0.0) return;
     s.scale = (T)ctl[1];
   }
-  tiled_walk<X, V, TS>(a, s);
+  tiled_walk<X, V, TR, TC>(a, s);
   PartRec* recs = (PartRec*)(SCALED ? (void*)((char*)a.ws2 + 64) : a.ws);
   lane_to_record<T, RK, COMP>(s.acc, s.ext, s.amax, recs + blockIdx.x);
 }
@@ -1154,75 +1218,51 @@ __device__ __forceinline__ void pair_add(T& h, T& l, const Pair<T>& p) {
 // (coalesced column segments, transposed leaves staged through LDS) is the one of
 // tiled_walk.
 // ===========================================================================
-template <class X, int V, int TS, int DIM, class Sink>
+template <class X, int V, int TR, int TC, int DIM, class Sink>
 __device__ __forceinline__ void tiled_walk_seg(const coot_kargs& a, Sink& sink) {
   typedef typename X::T T;
-  constexpr int NB = 256;
-  constexpr int TPC = TS / V;       // threads along a column segment
-  constexpr int CPP = NB / TPC;     // columns per pass
-  constexpr int NPASS = TS / CPP;   // passes per tile
-  constexpr int NPS = X::NP1 > 0 ? X::NP1 : 1;
-  static_assert(TS % V == 0 && CPP <= TS && TS % CPP == 0, "a tile's passes must cover its columns");
-  __shared__ T lds[NPS][TS][TS + 1];
+  typedef TileGeom<X, V, TR, TC> G;
+  __shared__ T lds[G::NPS][TR][TC + 1];
   const i64 R = a.n_rows, C = a.n_cols;
-  const i64 tr = (R + TS - 1) / TS, tc = (C + TS - 1) / TS;
+  const i64 tr = (R + TR - 1) / TR, tc = (C + TC - 1) / TC;
   const i64 nred = DIM == 0 ? tr : tc, nkeep = DIM == 0 ? tc : tr;
   const i64 K = (nred + a.n_part - 1) / a.n_part;
   const i64 nseg = nkeep * a.n_part;
-  const int lc = threadIdx.x % TPC, lr = threadIdx.x / TPC;
+  const int lc = threadIdx.x % G::TPC, lr = threadIdx.x / G::TPC;
   for (i64 sgi = blockIdx.x; sgi < nseg; sgi += gridDim.x) {
     // neighbouring workgroups take neighbouring output strips of the same segment
     // (measured faster for sum(., 0) than neighbouring segments of one strip)
     const i64 keep = sgi % nkeep, sg = sgi / nkeep;
-    sink.begin_seg(a, keep * TS, lr, lc);
+    sink.begin_seg(a, keep * (DIM == 0 ? TC : TR), lr, lc);
     const i64 r_end = sg * K + K < nred ? sg * K + K : nred;
     for (i64 r = sg * K; r < r_end; ++r) {
       const i64 ti = DIM == 0 ? r : keep, tj = DIM == 0 ? keep : r;
-      const i64 i0 = ti * TS, j0 = tj * TS;
-      if constexpr (X::NP1 > 0) {
-        for (int il = lr; il < TS; il += CPP) {
-          const i64 i = i0 + il, j = j0 + (i64)lc * V;
-          const bool in = (i < R) && (j < C);
+      const i64 i0 = ti * TR, j0 = tj * TC;
+      const i64 i = i0 + (i64)lc * V;
+      vt<T, V> x[G::HOIST ? G::NPASS : 1][X::NL];
+      if constexpr (G::HOIST) {
 #pragma unroll
-          for (int k = 0; k < X::NL; ++k) {
-            if (X::par(k) == 0) continue;
-            vt<T, V> v;
-            if (in) {
-              v = ldc<typename X::S, V>((const typename X::S*)a.leaf[X::slot(k)] + j + i * a.ld[X::slot(k)]);
-            } else {
-#pragma unroll
-              for (int q = 0; q < V; ++q) v.v[q] = (T)0;
-            }
-#pragma unroll
-            for (int q = 0; q < V; ++q) lds[X::p1(k) < 0 ? 0 : X::p1(k)][il][lc * V + q] = v.v[q];
-          }
+        for (int p = 0; p < G::NPASS; ++p) {
+          const i64 j = j0 + lr + p * G::CPP;
+          load_pass<X, V>(a, i, j, (i < R) && (j < C), x[p]);
         }
+      }
+      if constexpr (X::NP1 > 0) {
+        stage_transposed<X, V, TR, TC>(a, lds, i0, j0);
         __syncthreads();
       }
 #pragma unroll
-      for (int p = 0; p < NPASS; ++p) {
-        const int jl = lr + p * CPP;
-        const i64 j = j0 + jl, i = i0 + (i64)lc * V;
+      for (int p = 0; p < G::NPASS; ++p) {
+        const int jl = lr + p * G::CPP;
+        const i64 j = j0 + jl;
         const bool in = (i < R) && (j < C);
-        vt<T, V> x[X::NL];
-        if (in) {
-#pragma unroll
-          for (int k = 0; k < X::NL; ++k)
-            if (X::par(k) == 0)
-            x[k] = ldc<typename X::S, V>((const typename X::S*)a.leaf[X::slot(k)] + i + j * a.ld[X::slot(k)]);
-        }
-#pragma unroll
-        for (int q = 0; q < V; ++q) {
-          T L[X::NL];
-#pragma unroll
-          for (int k = 0; k < X::NL; ++k)
-            L[k] = X::par(k) ? lds[X::p1(k) < 0 ? 0 : X::p1(k)][lc * V + q][jl] : (in ? x[k].v[q] : (T)0);
-          sink.elem(a, p, q, in, L);
-        }
+        if constexpr (!G::HOIST) load_pass<X, V>(a, i, j, in, x[0]);
+        pass_elems<X, V, TR, TC>(lds, x[G::HOIST ? p : 0], lc, jl, in,
+                                 [&](int q, bool inq, const T* L) { sink.elem(a, p, q, inq, L); });
       }
       if constexpr (X::NP1 > 0) __syncthreads();
     }
-    sink.end_seg(a, keep * TS, sg, lr, lc);
+    sink.end_seg(a, keep * (DIM == 0 ? TC : TR), sg, lr, lc);
   }
 }
 
@@ -1348,10 +1388,10 @@ struct DimAcc<T, COMP, true> {
 // VAR: each accumulator holds the shifted moments of its column about the column's
 // first element, evaluated at the segment's start; sum d^2 goes to ws and sum d to
 // ws2, one LDS combine each.
-template <class X, bool COMP, int V, int TS, bool VAR>
+template <class X, bool COMP, int V, int TR, int TC, bool VAR>
 struct Dim0SegSink {
   typedef typename X::T T;
-  static constexpr int TPC = TS / V, CPP = 256 / TPC, NPASS = TS / CPP;
+  static constexpr int TPC = TR / V, CPP = 256 / TPC, NPASS = TC / CPP;
   DimAcc<T, COMP, VAR> g[NPASS];
   T K[VAR ? NPASS : 1];
   __device__ __forceinline__ void begin_seg(const coot_kargs& a, i64 j0, int lr, int) {
@@ -1375,13 +1415,13 @@ struct Dim0SegSink {
     }
   }
   __device__ __forceinline__ void end_seg(const coot_kargs& a, i64 j0, i64 sg, int lr, int lc) {
-    __shared__ Pair<T> red[TS][TPC + 1];
+    __shared__ Pair<T> red[TC][TPC + 1];
 #pragma unroll
     for (int m = VAR ? 2 : 0; m >= (VAR ? 1 : 0); --m) {
 #pragma unroll
       for (int p = 0; p < NPASS; ++p) red[lr + p * CPP][lc] = g[p].part(m);
       __syncthreads();
-      if ((int)threadIdx.x < TS) {
+      if ((int)threadIdx.x < TC) {
         const int jl = threadIdx.x;
         T h = red[jl][0].hi, l = red[jl][0].lo;
         for (int k = 1; k < TPC; ++k) pair_add<T, COMP>(h, l, red[jl][k]);
@@ -1401,10 +1441,10 @@ struct Dim0SegSink {
 // sum(., 1): a lane's rows (lc * V .. lc * V + V - 1 of the row strip) stay fixed over
 // the segment; its V accumulators are combined across the CPP lanes of each row in LDS.
 // VAR: as for columns, about each row's first element.
-template <class X, bool COMP, int V, int TS, bool VAR>
+template <class X, bool COMP, int V, int TR, int TC, bool VAR>
 struct Dim1SegSink {
   typedef typename X::T T;
-  static constexpr int TPC = TS / V, CPP = 256 / TPC;
+  static constexpr int TPC = TR / V, CPP = 256 / TPC;
   DimAcc<T, COMP, VAR> r[V];
   T K[VAR ? V : 1];
   __device__ __forceinline__ void begin_seg(const coot_kargs& a, i64 i0, int, int lc) {
@@ -1428,13 +1468,13 @@ struct Dim1SegSink {
     }
   }
   __device__ __forceinline__ void end_seg(const coot_kargs& a, i64 i0, i64 sg, int lr, int lc) {
-    __shared__ Pair<T> red[CPP][TS];
+    __shared__ Pair<T> red[CPP][TR];
 #pragma unroll
     for (int m = VAR ? 2 : 0; m >= (VAR ? 1 : 0); --m) {
 #pragma unroll
       for (int q = 0; q < V; ++q) red[lr][lc * V + q] = r[q].part(m);
       __syncthreads();
-      if ((int)threadIdx.x < TS) {
+      if ((int)threadIdx.x < TR) {
         const int il = threadIdx.x;
         T h = red[0][il].hi, l = red[0][il].lo;
         for (int k = 1; k < CPP; ++k) pair_add<T, COMP>(h, l, red[k][il]);
@@ -1452,14 +1492,14 @@ struct Dim1SegSink {
 };
 
 // VAR: one-pass variance (shifted moments; sum d^2 partials in ws, sum d in ws2)
-template <class X, int DIM, bool COMP, int V, int TS, bool VAR = false>
+template <class X, int DIM, bool COMP, int V, int TR, int TC, bool VAR = false>
 __device__ __forceinline__ void tiled_reduce_dim(const coot_kargs& a) {
   if constexpr (DIM == 0) {
-    Dim0SegSink<X, COMP, V, TS, VAR> s;
-    tiled_walk_seg<X, V, TS, 0>(a, s);
+    Dim0SegSink<X, COMP, V, TR, TC, VAR> s;
+    tiled_walk_seg<X, V, TR, TC, 0>(a, s);
   } else {
-    Dim1SegSink<X, COMP, V, TS, VAR> s;
-    tiled_walk_seg<X, V, TS, 1>(a, s);
+    Dim1SegSink<X, COMP, V, TR, TC, VAR> s;
+    tiled_walk_seg<X, V, TR, TC, 1>(a, s);
   }
 }
 

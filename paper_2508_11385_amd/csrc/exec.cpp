@@ -169,21 +169,21 @@ static bool aligned(const void* p, size_t bytes) { return ((uintptr_t)p % bytes)
 // (the tables hold 32- and 64-bit types; the 16-bit types' defaults are measured)
 coot_launch_cfg default_cfg(int fam, int mode, int dim, int dtype, int64_t n) {
   const uint16_t v16 = dtype == COOT_F64 ? 2 : (dtype_is_half(dtype) ? 8 : 4);  // 16-byte groups
-  if (is_dim_kind(mode) && dim >= 0) return {v16, 0, 4, 8};
+  if (is_dim_kind(mode) && dim >= 0) return {v16, 0, 4, 8, 0, 0};
   // 16-bit types: 16-byte groups, 8 waves and 16 workgroups per CU for element-wise
   // flat launches, 16 workgroups per CU for tiles (measured on the 4096 x 4096 step)
-  if (dtype_is_half(dtype) && fam == FAM_FLAT && mode < 0) return {8, 1, 8, 16};
-  if (dtype_is_half(dtype) && fam != FAM_FLAT) return {8, 0, 4, 16};
+  if (dtype_is_half(dtype) && fam == FAM_FLAT && mode < 0) return {8, 1, 8, 16, 0, 0};
+  if (dtype_is_half(dtype) && fam != FAM_FLAT) return {8, 0, 4, 16, 0, 0};
   if (fam == FAM_FLAT) {
     // Past 2^24 elements (the streaming regime) fewer, longer-lived workgroups win:
     // the best geomean over the largest signatures of the autotuner's timing tables.
     if (n > kStreamElems) {
-      if (mode < 0) return {v16, 1, 4, 2};
-      return dtype == COOT_F64 ? coot_launch_cfg{2, 4, 8, 8} : coot_launch_cfg{4, 4, 4, 2};
+      if (mode < 0) return {v16, 1, 4, 2, 0, 0};
+      return dtype == COOT_F64 ? coot_launch_cfg{2, 4, 8, 8, 0, 0} : coot_launch_cfg{4, 4, 4, 2, 0, 0};
     }
-    return {v16, 1, 4, 4};
+    return {v16, 1, 4, 4, 0, 0};
   }
-  return {2, 0, 4, 8};
+  return {2, 0, 4, 8, 0, 0};
 }
 
 coot_launch_cfg resolve_cfg(const coot_launch_cfg* cfg, int fam, int mode, int dim, int dtype, int64_t n) {
@@ -193,6 +193,8 @@ coot_launch_cfg resolve_cfg(const coot_launch_cfg* cfg, int fam, int mode, int d
     if (cfg->ept) c.ept = cfg->ept;
     if (cfg->waves) c.waves = cfg->waves;
     if (cfg->grid_mult) c.grid_mult = cfg->grid_mult;
+    if (cfg->tile_r) c.tile_r = cfg->tile_r;
+    if (cfg->tile_c) c.tile_c = cfg->tile_c;
   }
   return c;
 }
@@ -217,15 +219,24 @@ Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, in
   if (rq.var.vec != 1 && rq.var.vec != 2 && rq.var.vec != 4 && !(rq.var.vec == 8 && dtype_is_half(e.dtype)))
     fail(COOT_EINVAL, "vec must be 1, 2 or 4 (or 8 for 16-bit types)");
   if (rq.var.ept != 1 && rq.var.ept != 2 && rq.var.ept != 4 && rq.var.ept != 8) fail(COOT_EINVAL, "ept must be 1, 2, 4 or 8");
-  // tile edge: 64, or 32 when the LDS staging of transposed leaves (held in the
-  // compute type: binary32 for 16-bit types) would exceed 64 KiB
-  const size_t es = dtype_is_half(e.dtype) ? 4 : dtype_size(e.dtype);
-  int ts = 64;
-  if ((size_t)std::max(1, e.n_p1) * 64 * 65 * es > 65536) ts = 32;
-  rq.var.ts = ts;
-  // a tile's 256 threads cover whole column segments in at most TS passes: V <= TS^2 / 256
-  if (rq.fam == FAM_TILE && rq.var.vec > tile_vec_cap(ts)) rq.var.vec = tile_vec_cap(ts);
-  if (rq.fam == FAM_FLAT) rq.var.ts = 0;
+  // tile: the caller's, else 64 x 64, or 32 x 32 when the LDS staging of the transposed
+  // leaves (held in the compute type: binary32 for 16-bit types) would exceed 64 KiB
+  if ((c.tile_r == 0) != (c.tile_c == 0)) fail(COOT_EINVAL, "give tile_r and tile_c together");
+  int tr = c.tile_r, tc = c.tile_c;
+  if (tr) {
+    if (!tile_shape_ok(tr, tc))
+      fail(COOT_EINVAL, "tile edges must be powers of two in [16, 256] with 1024 <= tile_r * tile_c <= 8192");
+    if (rq.fam == FAM_TILE && tile_lds_bytes(e.n_p1, e.dtype, tr, tc) > kTileLdsMax)
+      fail(COOT_EINVAL, "the staged transposed leaves of a " + std::to_string(tr) + " x " + std::to_string(tc) +
+                            " tile exceed 64 KiB of LDS");
+  } else {
+    tr = tc = tile_lds_bytes(e.n_p1, e.dtype, 64, 64) > kTileLdsMax ? 32 : 64;
+  }
+  rq.var.tr = tr;
+  rq.var.tc = tc;
+  // a tile's 256 threads cover whole column segments within its columns: V <= tr * tc / 256
+  if (rq.fam == FAM_TILE && rq.var.vec > tile_vec_cap(tr, tc)) rq.var.vec = tile_vec_cap(tr, tc);
+  if (rq.fam == FAM_FLAT) rq.var.tr = rq.var.tc = 0;
   if (rq.fam == FAM_TILE) rq.var.ept = 0;
   return rq;
 }
@@ -289,14 +300,14 @@ unsigned flat_grid(int64_t n, int V, int E, int bs, int gm) {
   return (unsigned)std::max<int64_t>(1, std::min(need, cap));
 }
 
-unsigned tile_grid(int64_t R, int64_t C, int ts, int gm) {
-  const int64_t nt = ((R + ts - 1) / ts) * ((C + ts - 1) / ts);
+unsigned tile_grid(int64_t R, int64_t C, int tr, int tc, int gm) {
+  const int64_t nt = ((R + tr - 1) / tr) * ((C + tc - 1) / tc);
   const int64_t cap = (int64_t)gm * num_cus();
   return (unsigned)std::max<int64_t>(1, std::min(nt, cap));
 }
 
 void eval_fused(Expr& e, const coot_operand* ops, const double* scalars, const coot_operand& out,
-                const coot_launch_cfg* cfg, hipStream_t s) {
+                const coot_launch_cfg* cfg, hipStream_t s, bool plain_store) {
   check_operands(e, ops);
   int64_t R = 0, C = 0;
   infer_shape(e, ops, &R, &C);
@@ -308,6 +319,7 @@ void eval_fused(Expr& e, const coot_operand* ops, const double* scalars, const c
   check_alias(e, ops, out, es);
   if (R * C == 0) return;
   Request rq = plan(e, ops, &out, -1, -1, true, cfg);
+  rq.plain_store = plain_store;
   auto m = get_module(e, rq, true);
   KArgs a;
   fill_args(e, ops, scalars, &a);
@@ -323,7 +335,7 @@ void eval_fused(Expr& e, const coot_operand* ops, const double* scalars, const c
     const int bs = 64 * c.waves;
     launch(f, flat_grid(R * C, v ? rq.var.vec : 1, rq.var.ept, bs, c.grid_mult), bs, a, s);
   } else {
-    launch(f, tile_grid(R, C, rq.var.ts, c.grid_mult), 256, a, s);
+    launch(f, tile_grid(R, C, rq.var.tr, rq.var.tc, c.grid_mult), 256, a, s);
   }
 }
 
@@ -444,8 +456,7 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
   const size_t cs = dtype_is_half(e.dtype) ? 4 : dtype_size(e.dtype);
   const coot_launch_cfg c = resolve_cfg(cfg, rq.fam, mode, dimk ? dim : -1, e.dtype, R * C);
   if (dimk) {
-    const int ts = rq.var.ts;
-    const int64_t tr = (R + ts - 1) / ts, tc = (C + ts - 1) / ts;
+    const int64_t tr = (R + rq.var.tr - 1) / rq.var.tr, tc = (C + rq.var.tc - 1) / rq.var.tc;
     // segments of K tiles along the reduced dimension, K growing once there are
     // more than 8 tiles per CU (at most 16): fewer partials, fewer lane combines
     const int64_t nred = dim == 0 ? tr : tc, nkeep = dim == 0 ? tc : tr;
@@ -468,7 +479,7 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
     grid = flat_grid(R * C, v ? rq.var.vec : 1, rq.var.ept, block, c.grid_mult);
   } else {
     block = 256;
-    grid = tile_grid(R, C, rq.var.ts, c.grid_mult);
+    grid = tile_grid(R, C, rq.var.tr, rq.var.tc, c.grid_mult);
   }
   a.n_part = grid;
   a.ws = workspace((size_t)grid * 32, s, 0);
@@ -532,7 +543,7 @@ void eval_unfused(Expr& e, const coot_operand* ops, const double* scalars, const
   };
   const size_t n_ops = e.ops.size();
   if (n_ops == 1) {  // a bare LOAD: a copy
-    eval_fused(e, ops, scalars, out, cfg, s);
+    eval_fused(e, ops, scalars, out, cfg, s, true);
     return;
   }
   for (size_t i = 0; i < n_ops; ++i) {
@@ -607,7 +618,7 @@ void eval_unfused(Expr& e, const coot_operand* ops, const double* scalars, const
     }
     // operand kinds of the temporaries must match the slots just declared
     for (size_t k = 0; k < sopnds.size(); ++k) sslots[k].kind = sopnds[k].kind;
-    eval_fused(se, sopnds.data(), ssc.data(), res.op, cfg, s);
+    eval_fused(se, sopnds.data(), ssc.data(), res.op, cfg, s, true);
     for (auto& v : in) release(v);
     st.push_back(res);
   }

@@ -1,10 +1,11 @@
 // Autotuning of the fused kernels' launch configuration.
 //
-// A configuration is (vec, ept, waves, grid_mult): elements per 128-bit group,
-// groups in flight per thread, wavefronts per workgroup and workgroups per CU.
-// vec and ept are compile-time (one tuning module per signature holds every
-// variant), waves and grid_mult are launch parameters.  The tiled family runs
-// 256-thread workgroups, so only vec and grid_mult vary there.
+// A configuration is (vec, ept, waves, grid_mult, tile_r, tile_c): elements per
+// access group, groups in flight per thread, wavefronts per workgroup, workgroups
+// per CU and the output tile of the tiled family.  vec, ept and the tile are
+// compile-time (one tuning module per signature holds every variant), waves and
+// grid_mult are launch parameters.  The tiled family runs 256-thread workgroups, so
+// vec, grid_mult and the tile vary there.
 // Timing: one warm-up launch per configuration, then `reps` rounds; in each round
 // every configuration is timed once with HIP events on the caller's stream around
 // enough back-to-back launches to span 40 us (the per-launch time of a repeated
@@ -24,6 +25,7 @@ using namespace coot;
 namespace {
 
 constexpr size_t kFlushBytes = 512u << 20;
+unsigned g_flush_value = 1;  // what each flush folds its reads with (any value; it varies)
 constexpr float kSampleUs = 40.0f;  // a timing sample spans at least this many microseconds
 
 bool tune_mode_ok(int mode) { return mode == -1 || mode == COOT_RED_ACCU; }
@@ -49,13 +51,31 @@ Prepared prepare(Expr& e, const coot_operand* ops, const coot_operand* out, int 
   return p;
 }
 
-// Whether a configuration can run on these operands (vector width vs alignment and tile).
+// The tuning module's request for one configuration: its vector width and, for the
+// tiled family, its tile (the library's default tile when the configuration has none).
+Request cfg_request(const Prepared& p, const coot_launch_cfg& c) {
+  Request rq = p.rq;
+  rq.var.vec = c.vec;
+  if (rq.fam == FAM_TILE && c.tile_r) {
+    rq.var.tr = c.tile_r;
+    rq.var.tc = c.tile_c;
+  }
+  return rq;
+}
+
+// Whether a configuration can run on these operands (vector width vs alignment and
+// tile, the tile's LDS staging).
 bool cfg_runnable(Expr& e, const Prepared& p, const coot_launch_cfg& c, const coot_operand* ops,
                   const coot_operand* out) {
   if (c.vec == 8 && !dtype_is_half(e.dtype)) return false;  // 16-byte groups of 16-bit elements only
-  Request rq = p.rq;
-  rq.var.vec = c.vec;
-  if (rq.fam == FAM_TILE && c.vec > tile_vec_cap(rq.var.ts)) return false;
+  const Request rq = cfg_request(p, c);
+  if (rq.fam == FAM_TILE) {
+    if (c.vec > tile_vec_cap(rq.var.tr, rq.var.tc)) return false;
+    if (tile_lds_bytes(e.n_p1, e.dtype, rq.var.tr, rq.var.tc) > kTileLdsMax) return false;
+    bool listed = false;  // the tuning module holds the tile shapes of tile_shapes()
+    for (auto& t : tile_shapes()) listed = listed || (t.first == rq.var.tr && t.second == rq.var.tc);
+    if (!listed) return false;
+  }
   return vec_ok(e, rq, ops, out, p.R, p.C);
 }
 
@@ -63,8 +83,7 @@ bool cfg_runnable(Expr& e, const Prepared& p, const coot_launch_cfg& c, const co
 bool launch_cfg(Expr& e, Prepared& p, const coot_launch_cfg& c, const coot_operand* ops, const double* scalars,
                 const coot_operand* out, hipStream_t s) {
   if (!cfg_runnable(e, p, c, ops, out)) return false;
-  Request rq = p.rq;
-  rq.var.vec = c.vec;
+  const Request rq = cfg_request(p, c);
   const int ept = rq.fam == FAM_FLAT ? c.ept : 0;
   hipFunction_t f = p.m->fn(variant_name(e, rq, c.vec, ept));
   KArgs a;
@@ -77,7 +96,7 @@ bool launch_cfg(Expr& e, Prepared& p, const coot_launch_cfg& c, const coot_opera
     grid = flat_grid(p.R * p.C, c.vec, c.ept, (int)block, c.grid_mult);
   } else {
     block = 256;
-    grid = tile_grid(p.R, p.C, rq.var.ts, c.grid_mult);
+    grid = tile_grid(p.R, p.C, rq.var.tr, rq.var.tc, c.grid_mult);
   }
   if (rq.mode < 0) {
     a.out = out->data;
@@ -96,7 +115,8 @@ bool launch_cfg(Expr& e, Prepared& p, const coot_launch_cfg& c, const coot_opera
 
 bool valid_cfg(const coot_launch_cfg& c) {
   auto pow2 = [](int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; };
-  return pow2(c.vec, 1, 8) && pow2(c.ept, 1, 8) && pow2(c.waves, 1, 8) && pow2(c.grid_mult, 1, 16);
+  const bool tile = (c.tile_r == 0 && c.tile_c == 0) || tile_shape_ok(c.tile_r, c.tile_c);
+  return pow2(c.vec, 1, 8) && pow2(c.ept, 1, 8) && pow2(c.waves, 1, 8) && pow2(c.grid_mult, 1, 16) && tile;
 }
 
 }  // namespace
@@ -105,13 +125,16 @@ extern "C" {
 
 uint32_t coot_tune_space(int32_t family, coot_launch_cfg* cfgs, uint32_t cap) {
   std::vector<coot_launch_cfg> v;
-  for (uint16_t vec : {1, 2, 4})
-    for (uint16_t ept : {1, 2, 4, 8})
-      for (uint16_t waves : {1, 2, 4, 8})
-        for (uint16_t gm : {2, 4, 8, 16}) {
-          if (family == 1 && (ept != 1 || waves != 4)) continue;
-          v.push_back({vec, ept, waves, gm});
-        }
+  if (family == 1) {
+    for (auto& t : tile_shapes())
+      for (uint16_t vec : {1, 2, 4})
+        for (uint16_t gm : {2, 4, 8, 16}) v.push_back({vec, 1, 4, gm, (uint16_t)t.first, (uint16_t)t.second});
+  } else {
+    for (uint16_t vec : {1, 2, 4})
+      for (uint16_t ept : {1, 2, 4, 8})
+        for (uint16_t waves : {1, 2, 4, 8})
+          for (uint16_t gm : {2, 4, 8, 16}) v.push_back({vec, ept, waves, gm, 0, 0});
+  }
   if (cfgs)
     for (uint32_t i = 0; i < std::min<uint32_t>(cap, (uint32_t)v.size()); ++i) cfgs[i] = v[i];
   return (uint32_t)v.size();
@@ -134,6 +157,14 @@ coot_status coot_tune_runnable(coot_expr* h, const coot_operand* operands, const
       if (!valid_cfg(cfgs[k])) fail(COOT_EINVAL, "invalid launch configuration");
       runnable[k] = cfg_runnable(*h->e, p, cfgs[k], operands, mode < 0 ? out : nullptr) ? 1 : 0;
     }
+  });
+}
+
+coot_status coot_flush_caches(void* stream) {
+  return guarded([&] {
+    hipStream_t s = (hipStream_t)stream;
+    void* buf = workspace(kFlushBytes, s, 4);
+    hip_check(coot_flush_launch(buf, kFlushBytes, g_flush_value++, s), "cache flush");
   });
 }
 

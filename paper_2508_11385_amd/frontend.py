@@ -428,62 +428,145 @@ def _stream() -> int:
     return torch.cuda.current_stream().cuda_stream
 
 
+class _Bound:
+    """What a call on one expression object needs, built once: the flattened form, the
+    library handle, the ctypes operand and scalar arrays, the result's dimensions and,
+    when the caller gives it, the output operand.  Expression trees are immutable (their
+    Mats keep their storage), so a repeated call on the same object does no tree walk."""
+    __slots__ = ("flat", "h", "ops", "sc", "shape", "out", "out_op", "cfg")
+
+    def __init__(self, e, flags, cfg):
+        self.flat = flatten(e)
+        self.h = compiled(self.flat, flags)
+        self.ops = cc._arr(cc.coot_operand, [m.operand() for m in self.flat.mats])
+        self.sc = cc._arr(cc.C.c_double, self.flat.scalars)
+        self.shape = None
+        self.out = None
+        self.out_op = None
+        self.cfg = cc._cfg(cfg)
+
+
+def _bound(e, flags, cfg, out, tag):
+    """The cached call state of expression object e for (tag, flags, cfg, out)."""
+    try:
+        cache = e.__dict__.setdefault("_calls", {})
+    except AttributeError:                      # e.g. a Scalar (no instance dict)
+        cache = {}
+    key = (tag, flags, None if cfg is None else tuple(cfg), id(out) if out is not None else None)
+    b = cache.get(key)
+    if b is None or (out is not None and b.out is not out):
+        if len(cache) >= 8:                     # bounded: an entry holds its output alive
+            cache.clear()
+        b = _Bound(e, flags, cfg)
+        if out is not None:
+            b.out = out
+            b.out_op = out.operand()
+        cache[key] = b
+    return b
+
+
+def _fresh_out(b, r, c):
+    kind = "col" if c == 1 and r != 1 else ("row" if r == 1 and c != 1 else "mat")
+    return Mat.empty(r, c, b.flat.dtype, kind, device=b.flat.mats[0].tensor.device)
+
+
 def eval(e: Expr, out: Mat | None = None, cfg=None, unfused: bool = False) -> Mat:  # noqa: A001
     """Assignment: evaluate the whole expression in one fused pass (or the unfused comparator)."""
     if isinstance(e, (int, float)):
         raise TypeError("nothing to evaluate")
-    flat = flatten(_lift(e))
-    h = compiled(flat, cc.COOT_CF_UNFUSED if unfused else 0)
-    ops = [m.operand() for m in flat.mats]
+    e = _lift(e)
+    b = _bound(e, cc.COOT_CF_UNFUSED if unfused else 0, cfg, out, "eval")
     if out is None:
-        r, c = cc.coot_expr_out_shape(h, ops)
-        kind = "col" if c == 1 and r != 1 else ("row" if r == 1 and c != 1 else "mat")
-        out = Mat.empty(r, c, flat.dtype, kind, device=flat.mats[0].tensor.device)
-    cc.coot_expr_eval(h, ops, flat.scalars, out.operand(), cfg, _stream())
-    return out
+        if b.shape is None:
+            b.shape = cc.coot_expr_out_shape(b.h, b.ops)
+        res = _fresh_out(b, *b.shape)
+        res_op = res.operand()
+    else:
+        res, res_op = b.out, b.out_op
+    st = cc.lib.coot_expr_eval(b.h, b.ops, b.sc, cc.C.byref(res_op), b.cfg, _stream())
+    if st != cc.COOT_OK:
+        cc._check(st)
+    return res
 
 
 _RED_KIND = {"accu": cc.COOT_RED_ACCU, "dot": cc.COOT_RED_DOT, "min": cc.COOT_RED_MIN, "max": cc.COOT_RED_MAX,
              "mean": cc.COOT_RED_MEAN, "norm1": cc.COOT_RED_NORM1, "norm_inf": cc.COOT_RED_NORMINF}
 
 
-def eval_reduce(e: Expr, out: Mat, r: Expr, kind: str = "accu", cfg=None) -> Mat:
+class _Pair:
+    """Cached call state of a statement pair (see eval_reduce)."""
+    __slots__ = ("e", "r", "out", "res", "he", "hr", "ops", "sc", "out_op", "src", "rsc", "res_op", "cfg")
+
+
+def eval_reduce(e: Expr, out: Mat, r: Expr, kind: str = "accu", cfg=None, res: Mat | None = None) -> Mat:
     """Two statements in one pass: out = e, then the reduction `kind` of r, which may read
     e's operands and `out` (the value just computed): y = 2.5*x + y; d = accu(x % y) becomes
-    eval_reduce(2.5 * x + y, y, x % y).  Returns the 1x1 result."""
-    fe, fr = flatten(_lift(e)), flatten(_lift(r))
-    he, hr = compiled(fe), compiled(fr)
+    eval_reduce(2.5 * x + y, y, x % y).  Returns the 1x1 result (written into res when
+    given).  A repeated call on the same expression objects reuses their flattened forms."""
+    e, r = _lift(e), _lift(r)
+    cache = e.__dict__.setdefault("_calls", {})
+    key = ("pair", id(r), kind, None if cfg is None else tuple(cfg), id(out), id(res) if res is not None else None)
+    p = cache.get(key)
+    if p is None or p.r is not r or p.out is not out or (res is not None and p.res is not res):
+        fe, fr = flatten(e), flatten(r)
 
-    def same(a: Mat, b: Mat):
-        return (a.tensor.data_ptr() == b.tensor.data_ptr() and a.n_rows == b.n_rows and a.n_cols == b.n_cols
-                and a.ld == b.ld)
+        def same(a: Mat, b: Mat):
+            return (a.tensor.data_ptr() == b.tensor.data_ptr() and a.n_rows == b.n_rows and a.n_cols == b.n_cols
+                    and a.ld == b.ld)
 
-    src = []
-    for m in fr.mats:
-        if same(m, out):
-            src.append(-1)
-        else:
-            k = next((i for i, a in enumerate(fe.mats) if same(m, a)), None)
-            if k is None:
-                raise ValueError("the reduced statement may read only the operands of the first one and its result")
-            src.append(k)
-    res = Mat.empty(1, 1, fe.dtype, device=out.tensor.device)
-    cc.coot_expr_eval_reduce(he, [m.operand() for m in fe.mats], fe.scalars, out.operand(), hr, src, fr.scalars,
-                             _RED_KIND[kind], res.operand(), cfg, _stream())
+        src = []
+        for m in fr.mats:
+            if same(m, out):
+                src.append(-1)
+            else:
+                k = next((i for i, a in enumerate(fe.mats) if same(m, a)), None)
+                if k is None:
+                    raise ValueError("the reduced statement may read only the operands of the first one and its "
+                                     "result")
+                src.append(k)
+        if len(cache) >= 8:
+            cache.clear()
+        p = _Pair()
+        p.e, p.r, p.out = e, r, out
+        p.he, p.hr = compiled(fe), compiled(fr)
+        p.ops = cc._arr(cc.coot_operand, [m.operand() for m in fe.mats])
+        p.sc = cc._arr(cc.C.c_double, fe.scalars)
+        p.out_op = out.operand()
+        p.src = cc._arr(cc.C.c_int32, src)
+        p.rsc = cc._arr(cc.C.c_double, fr.scalars)
+        p.res = res
+        p.res_op = res.operand() if res is not None else None
+        p.cfg = cc._cfg(cfg)
+        cache[key] = p
+    if res is None:
+        dst = Mat.empty(1, 1, out.dtype, device=out.tensor.device)
+        dst_op = dst.operand()
+    else:
+        dst, dst_op = p.res, p.res_op
+    st = cc.lib.coot_expr_eval_reduce(p.he, p.ops, p.sc, cc.C.byref(p.out_op), p.hr, p.src, p.rsc, _RED_KIND[kind],
+                                      cc.C.byref(dst_op), p.cfg, _stream())
+    if st != cc.COOT_OK:
+        cc._check(st)
+    return dst
+
+
+def _reduce(e, kind, dim, plain, out_shape, cfg, unfused, flags=0, out=None):
+    e = _lift(e)
+    b = _bound(e, cc.COOT_CF_UNFUSED if unfused else 0, cfg, out, "reduce")
+    if out is None:
+        if b.shape is None:
+            b.shape = cc.coot_expr_out_shape(b.h, b.ops)
+        orr, oc = out_shape(*b.shape)
+        okind = "mat" if orr == oc == 1 else ("row" if orr == 1 else "col")
+        res = Mat.empty(orr, oc, b.flat.dtype, okind, device=b.flat.mats[0].tensor.device)
+        res_op = res.operand()
+    else:
+        res, res_op = b.out, b.out_op
+    st = cc.lib.coot_reduce(b.h, b.ops, b.sc, kind, dim, (cc.COOT_RF_PLAIN if plain else 0) | flags,
+                            cc.C.byref(res_op), b.cfg, _stream())
+    if st != cc.COOT_OK:
+        cc._check(st)
     return res
-
-
-def _reduce(e, kind, dim, plain, out_shape, cfg, unfused, flags=0):
-    flat = flatten(_lift(e))
-    h = compiled(flat, cc.COOT_CF_UNFUSED if unfused else 0)
-    ops = [m.operand() for m in flat.mats]
-    r, c = cc.coot_expr_out_shape(h, ops)
-    orr, oc = out_shape(r, c)
-    okind = "mat" if orr == oc == 1 else ("row" if orr == 1 else "col")
-    out = Mat.empty(orr, oc, flat.dtype, okind, device=flat.mats[0].tensor.device)
-    cc.coot_reduce(h, ops, flat.scalars, kind, dim, (cc.COOT_RF_PLAIN if plain else 0) | flags, out.operand(), cfg,
-                   _stream())
-    return out
 
 
 def _along(dim):
@@ -492,53 +575,54 @@ def _along(dim):
     return (lambda r, c: (1, c)) if dim == 0 else (lambda r, c: (r, 1))
 
 
-def accu(e, plain=False, cfg=None, unfused=False) -> Mat:
-    """Sum of all elements, as a 1x1 device Mat (Fig. 1: sum(A) of a vector)."""
-    return _reduce(e, cc.COOT_RED_ACCU, -1, plain, lambda r, c: (1, 1), cfg, unfused)
+def accu(e, plain=False, cfg=None, unfused=False, out=None) -> Mat:
+    """Sum of all elements, as a 1x1 device Mat (Fig. 1: sum(A) of a vector); out: a 1x1
+    Mat to write instead of a new one (every reduction takes it)."""
+    return _reduce(e, cc.COOT_RED_ACCU, -1, plain, lambda r, c: (1, 1), cfg, unfused, out=out)
 
 
-def sum(e, dim=None, plain=False, cfg=None, unfused=False) -> Mat:  # noqa: A001
+def sum(e, dim=None, plain=False, cfg=None, unfused=False, out=None) -> Mat:  # noqa: A001
     """sum(X, 0): per column (1 x n_cols); sum(X, 1): per row (n_rows x 1).
     Without dim: a vector gives its total, a matrix sums per column (Armadillo's convention)."""
     if dim is None:
         flat = flatten(_lift(e))
         r, c = cc.coot_expr_out_shape(compiled(flat), [m.operand() for m in flat.mats])
         if r == 1 or c == 1:
-            return accu(e, plain, cfg, unfused)
+            return accu(e, plain, cfg, unfused, out)
         dim = 0
     shape = (lambda r, c: (1, c)) if dim == 0 else (lambda r, c: (r, 1))
-    return _reduce(e, cc.COOT_RED_SUM, dim, plain, shape, cfg, unfused)
+    return _reduce(e, cc.COOT_RED_SUM, dim, plain, shape, cfg, unfused, out=out)
 
 
-def dot(a, b, plain=False, cfg=None, unfused=False) -> Mat:
-    return _reduce(_bin("schur", a, b), cc.COOT_RED_DOT, -1, plain, lambda r, c: (1, 1), cfg, unfused)
+def dot(a, b, plain=False, cfg=None, unfused=False, out=None) -> Mat:
+    return _reduce(_bin("schur", a, b), cc.COOT_RED_DOT, -1, plain, lambda r, c: (1, 1), cfg, unfused, out=out)
 
 
-def norm(e, plain=False, cfg=None, unfused=False) -> Mat:
+def norm(e, plain=False, cfg=None, unfused=False, out=None) -> Mat:
     """2-norm of a vector / Frobenius norm of a matrix expression."""
-    return _reduce(e, cc.COOT_RED_NORM, -1, plain, lambda r, c: (1, 1), cfg, unfused)
+    return _reduce(e, cc.COOT_RED_NORM, -1, plain, lambda r, c: (1, 1), cfg, unfused, out=out)
 
 
-def min(e, cfg=None, unfused=False) -> Mat:  # noqa: A001 — the Armadillo name
+def min(e, cfg=None, unfused=False, out=None) -> Mat:  # noqa: A001 — the Armadillo name
     """Smallest element, as a 1x1 device Mat (NaN if any element is NaN)."""
-    return _reduce(e, cc.COOT_RED_MIN, -1, False, lambda r, c: (1, 1), cfg, unfused)
+    return _reduce(e, cc.COOT_RED_MIN, -1, False, lambda r, c: (1, 1), cfg, unfused, out=out)
 
 
-def max(e, cfg=None, unfused=False) -> Mat:  # noqa: A001
+def max(e, cfg=None, unfused=False, out=None) -> Mat:  # noqa: A001
     """Largest element, as a 1x1 device Mat (NaN if any element is NaN)."""
-    return _reduce(e, cc.COOT_RED_MAX, -1, False, lambda r, c: (1, 1), cfg, unfused)
+    return _reduce(e, cc.COOT_RED_MAX, -1, False, lambda r, c: (1, 1), cfg, unfused, out=out)
 
 
-def mean(e, dim=None, plain=False, cfg=None, unfused=False) -> Mat:
+def mean(e, dim=None, plain=False, cfg=None, unfused=False, out=None) -> Mat:
     """Mean of all elements (compensated sum / count, rounded once), or with dim along a
     dimension as Armadillo's mean(X, dim): dim 0 per column (1 x n_cols), dim 1 per row
     (n_rows x 1)."""
     if dim is None:
-        return _reduce(e, cc.COOT_RED_MEAN, -1, plain, lambda r, c: (1, 1), cfg, unfused)
-    return _reduce(e, cc.COOT_RED_MEAN_DIM, dim, plain, _along(dim), cfg, unfused)
+        return _reduce(e, cc.COOT_RED_MEAN, -1, plain, lambda r, c: (1, 1), cfg, unfused, out=out)
+    return _reduce(e, cc.COOT_RED_MEAN_DIM, dim, plain, _along(dim), cfg, unfused, out=out)
 
 
-def var(e, norm_type=0, dim=None, plain=False, cfg=None, unfused=False) -> Mat:
+def var(e, norm_type=0, dim=None, plain=False, cfg=None, unfused=False, out=None) -> Mat:
     """Variance as Armadillo's var(X, norm_type, dim): normalised by N - 1 (norm_type 0)
     or N (norm_type 1); without dim over all elements, with dim 0 per column, dim 1 per
     row.  One pass over the expression: compensated moments about a value of the data,
@@ -547,18 +631,18 @@ def var(e, norm_type=0, dim=None, plain=False, cfg=None, unfused=False) -> Mat:
         raise ValueError("norm_type must be 0 or 1")
     flags = cc.COOT_RF_VAR_N if norm_type == 1 else 0
     if dim is None:
-        return _reduce(e, cc.COOT_RED_VAR, -1, plain, lambda r, c: (1, 1), cfg, unfused, flags)
-    return _reduce(e, cc.COOT_RED_VAR_DIM, dim, plain, _along(dim), cfg, unfused, flags)
+        return _reduce(e, cc.COOT_RED_VAR, -1, plain, lambda r, c: (1, 1), cfg, unfused, flags, out)
+    return _reduce(e, cc.COOT_RED_VAR_DIM, dim, plain, _along(dim), cfg, unfused, flags, out)
 
 
-def norm1(e, plain=False, cfg=None, unfused=False) -> Mat:
+def norm1(e, plain=False, cfg=None, unfused=False, out=None) -> Mat:
     """Sum of |x| over the elements (the 1-norm of the elements taken as a vector)."""
-    return _reduce(e, cc.COOT_RED_NORM1, -1, plain, lambda r, c: (1, 1), cfg, unfused)
+    return _reduce(e, cc.COOT_RED_NORM1, -1, plain, lambda r, c: (1, 1), cfg, unfused, out=out)
 
 
-def norm_inf(e, cfg=None, unfused=False) -> Mat:
+def norm_inf(e, cfg=None, unfused=False, out=None) -> Mat:
     """Largest |x| over the elements (the infinity norm of the elements as a vector)."""
-    return _reduce(e, cc.COOT_RED_NORMINF, -1, False, lambda r, c: (1, 1), cfg, unfused)
+    return _reduce(e, cc.COOT_RED_NORMINF, -1, False, lambda r, c: (1, 1), cfg, unfused, out=out)
 
 
 def init(device: int = 0) -> None:

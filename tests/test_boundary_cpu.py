@@ -93,7 +93,7 @@ def test_shape_inference(cc):
 
 
 FAMILIES = [
-    # (postfix, n_slots, n_scalars, mode, dim, fam, vec, ept, ts, dtype)
+    # (postfix, n_slots, n_scalars, mode, dim, fam, vec, ept, tile edge or (rows, cols), dtype)
     (Z, 4, 1, -1, -1, 1, 4, 0, 64, "f32"),
     (Z, 4, 1, -1, -1, 1, 2, 0, 32, "f64"),
     (W, 2, 1, -1, -1, 0, 4, 4, 0, "f32"),
@@ -125,6 +125,14 @@ FAMILIES = [
     (W, 2, 1, 10, -1, 0, 8, 1, 0, "f16"),     # var, 16-bit
     (Z, 4, 1, 11, 0, 1, 4, 0, 64, "f32"),     # var along dim 0
     (Z, 4, 1, 11, 1, 1, 2, 0, 32, "f64"),     # var along dim 1
+    # rectangular tiles (rows x columns)
+    (Z, 4, 1, -1, -1, 1, 4, 0, (128, 32), "f32"),
+    (Z, 4, 1, -1, -1, 1, 2, 0, (32, 128), "f64"),
+    (Z, 4, 1, 1, 0, 1, 4, 0, (256, 16), "f32"),
+    (Z, 4, 1, 1, 1, 1, 4, 0, (128, 64), "f32"),
+    (Z, 4, 1, 11, 0, 1, 8, 0, (128, 32), "bf16"),
+    (Z, 4, 1, 0, -1, 1, 4, 0, (32, 128), "f16"),
+    (Z, 4, 1, 3, -1, 1, 1, 0, (16, 256), "f32"),   # norm (with its rescaled pass)
 ]
 
 
@@ -184,8 +192,8 @@ def test_random_trees_generate_and_leaf_parities(cc):
 def test_costmodel_features_match_oracle_definition(cc):
     from oracle import features as of
     g = synth.rng_for(78)
-    space = cc.coot_tune_space(0)
-    assert len(space) == 192 and len(cc.coot_tune_space(1)) == 12
+    space = cc.coot_tune_space(0) + cc.coot_tune_space(1)
+    assert len(cc.coot_tune_space(0)) == 192 and len(cc.coot_tune_space(1)) == 72
     for trial in range(25):
         dt = ["u32", "s32", "f32", "f64"][trial % 4]
         r, c = int(g.integers(1, 20000)), int(g.integers(1, 20000))
@@ -227,10 +235,16 @@ def test_runnable_configurations(cc):
     ok = cc.coot_tune_runnable(h, [mis, _opnd(cc, 100, 50)], _opnd(cc, 100, 50), -1, flat)
     assert all(o == (c[0] == 1) for o, c in zip(ok, flat))
     tiled = cc.coot_tune_space(1)
+    assert {(c[4], c[5]) for c in tiled} == {(64, 64), (128, 32), (32, 128), (256, 16), (128, 64), (32, 32)}
     hz = cc.coot_expr_compile(Z, _ops(4), 1)
     ops = [_opnd(cc, 6, 8)] * 3 + [_opnd(cc, 8, 6)]                            # 6 rows: 2 | 6, 4 does not
     ok = cc.coot_tune_runnable(hz, ops, _opnd(cc, 6, 8), -1, tiled)
     assert all(o == (c[0] in (1, 2)) for o, c in zip(ok, tiled))
+    # four transposed fp64 leaves: 128 x 64 tiles would stage 4 x 128 x 65 x 8 bytes > 64 KiB
+    h4 = cc.coot_expr_compile([("load", 0), ("trans",), ("load", 1), ("trans",), ("add",), ("load", 2), ("trans",),
+                               ("add",), ("load", 3), ("trans",), ("add",)], _ops(4, "f64"), 0)
+    ok = cc.coot_tune_runnable(h4, [_opnd(cc, 64, 64, "f64")] * 4, _opnd(cc, 64, 64, "f64"), -1, tiled)
+    assert all(o == (c[4] * (c[5] + 1) * 8 * 4 <= 65536) for o, c in zip(ok, tiled))
     with pytest.raises(cc.CootError) as e:
         cc.coot_tune_runnable(hz, ops, None, -1, tiled)
     assert e.value.status == cc.COOT_EINVAL

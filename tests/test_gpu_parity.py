@@ -378,3 +378,32 @@ def test_caller_allocator_for_workspaces_and_temporaries(coot):
     assert during - torch.cuda.memory_allocated() >= 65536
     assert all(np.array_equal(a, b) for a, b in zip(ref, got))
     assert all(np.array_equal(a, b) for a, b in zip(ref, run()))
+
+
+TILES = [(64, 64), (128, 32), (32, 128), (256, 16), (16, 256), (128, 64), (32, 32)]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("tile", TILES)
+def test_tile_shapes(coot, dtype, tile):
+    """Every tile shape of the tiled kernels, through element-wise evaluation, full and
+    dimension reductions, on a ragged shape (partial tiles on both edges) and an aligned
+    one with 4-element groups: Z 0 ulp, sums within the reduction tolerance, max exact."""
+    for (r, c), vec in (((300, 170), 1), ((512, 256), 4 if dtype == "f32" else 2)):
+        cfg = (vec, 0, 0, 0) + tile
+        A, B, C, D = synth.matrix_inputs(n_rows=r, n_cols=c, dtype=dtype)
+        gA, gB, gC, gD = (up(coot, x) for x in (A, B, C, D))
+        Zo = ew.evaluate(Z_POST, [A, B, C, D], [2.0], dtype)
+        Z = coot.eval(_z(coot, gA, gB, gC, gD), cfg=cfg).numpy()
+        assert np.max(ulp_distance(Z, Zo)) == 0, (tile, r, c)
+        for dim in (0, 1):
+            got = coot.sum(_z(coot, gA, gB, gC, gD), dim, cfg=cfg).numpy().ravel()
+            scale = [rd.sum_abs(v) for v in (Zo.T if dim == 0 else Zo)]
+            _check_rel(got, rd.sum_dim(Zo, dim, dtype), scale, REL[dtype], f"sum dim {dim} {tile}")
+        got = float(coot.accu(_z(coot, gA, gB, gC, gD), cfg=cfg).numpy()[0, 0])
+        assert rd.rel_err(got, rd.accu(Zo, dtype), rd.sum_abs(Zo)) <= REL[dtype], tile
+        assert float(coot.max(_z(coot, gA, gB, gC, gD), cfg=cfg).numpy()[0, 0]) == float(np.max(Zo))
+        v1 = coot.var(_z(coot, gA, gB, gC, gD), dim=1, cfg=cfg).numpy().ravel()
+        want = rd.var_dim(Zo, 1, dtype, 0)
+        for gv, q in zip(v1, want):
+            assert rd.rel_err(float(gv), q, abs(float(q))) <= REL[dtype], tile

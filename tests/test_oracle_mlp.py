@@ -82,14 +82,22 @@ def test_features_hand_example():
     assert f.shape == (features.N_FEATURES,)
     # tiled: 64 x 64 = 4096 tiles, capped at 8 * 256 = 2048 workgroups of 256 threads, 32 elements each
     want = [5, 4, 0, 0, 1, 0, math.log2(4097), math.log2(4097), 1, 0, 0, 0, 1, 2, 1, 2, 3,
-            math.log2(1 + 4096 * 4096), 1, 11, math.log2(33)]
+            math.log2(1 + 4096 * 4096), 1, 11, math.log2(33), 6, 6]
     assert np.allclose(f, want)
+    # the same with 128 x 32 tiles: 32 x 128 = 4096 tiles, again capped at 2048 workgroups
+    f = features.features(postfix, "f32", 4096, 4096, "dim1", (4, 1, 4, 8, 128, 32))
+    want[14] = 0                 # log2(ept = 1)
+    want[21:] = [7, 5]
+    assert np.allclose(f, want)
+    # 256 x 16 tiles on 300 x 50: 2 x 4 = 8 tiles (below the cap), 15000 / 2048 elements per thread
+    f = features.features(postfix, "f32", 300, 50, "none", (2, 1, 4, 16, 256, 16))
+    assert np.allclose(f[17:], [math.log2(15001), 1, 3, math.log2(1 + 15000 / 2048), 8, 4])
     # exp(A) / (1 + abs(B)) on 1000 x 3, element-wise: flat, 750 groups of 4 fit one workgroup of
     # 256 threads x 4 groups; 3000 / 256 elements per thread
     wpost = [("load", 0), ("exp",), ("scalar", 0), ("load", 1), ("abs",), ("add",), ("div",)]
     f = features.features(wpost, "f32", 1000, 3, "none", (4, 4, 4, 8))
     want = [4, 2, 0, 0, 1, 0, math.log2(1001), 2, 0, 1, 0, 0, 0, 2, 2, 2, 3,
-            math.log2(3001), 0, 0, math.log2(1 + 3000 / 256)]
+            math.log2(3001), 0, 0, math.log2(1 + 3000 / 256), 0, 0]
     assert np.allclose(f, want)
 
 
