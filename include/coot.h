@@ -222,8 +222,12 @@ coot_status coot_expr_out_shape(const coot_expr* e, const coot_operand* operands
  * `out` may be the same buffer as an operand that is read untransposed with the
  * same layout (y = 2.5*x + y, B += 3*A): every element is read before it is
  * written by the same thread.  Any other overlap gives COOT_EALIAS.
+ * The fused evaluation takes no workspace and may be recorded into a HIP graph
+ * (stream capture) once its code is loaded (a first call or coot_expr_prepare
+ * outside the capture); the unfused comparator's temporaries may not.
  * Errors: COOT_EINVAL, COOT_ESHAPE, COOT_ETYPE, COOT_EALIAS, COOT_ECOMPILE,
- * COOT_EHIP, COOT_ENOMEM (unfused temporaries). */
+ * COOT_EHIP, COOT_ENOMEM (unfused temporaries), COOT_EUNSUPPORTED (the unfused
+ * comparator on a stream that is capturing). */
 coot_status coot_expr_eval(coot_expr* e, const coot_operand* operands, const double* scalars,
                            coot_operand* out, const coot_launch_cfg* cfg, void* stream);
 
@@ -248,8 +252,10 @@ coot_status coot_expr_eval(coot_expr* e, const coot_operand* operands, const dou
  * rounded once.  A count of 1 gives 0 for either normalisation.  Inf or NaN
  * elements give NaN.
  * The result is deterministic: a fixed combine order and no floating-point
- * atomics.  Workspace is taken from a per-stream cache owned by the library.
- * Errors: as coot_expr_eval; COOT_ETYPE for NORM, MEAN, NORM1, NORMINF of an
+ * atomics.  Workspace is taken from a per-stream cache owned by the library,
+ * which a later call may free and reallocate: a stream that is capturing is
+ * refused (COOT_EUNSUPPORTED), since a replayed graph would read freed memory.
+ * Errors: as coot_expr_eval; COOT_EUNSUPPORTED under stream capture; COOT_ETYPE for NORM, MEAN, NORM1, NORMINF of an
  * integer expression (and for MEAN_DIM, VAR, VAR_DIM); COOT_EINVAL for DOT whose
  * root is not a Schur product, for MIN, MAX, MEAN, VAR of an empty expression and
  * for COOT_RF_VAR_N with another kind. */
@@ -272,8 +278,8 @@ coot_status coot_reduce(coot_expr* e, const coot_operand* operands, const double
  *                      MEAN, NORM1, NORMINF; r_out: one element of the dtype
  * Both statements must take the flat kernels: every leaf untransposed and
  * contiguous, out contiguous, the same shape; r may read only operands that e
- * reads.  Errors: as coot_expr_eval and coot_reduce; COOT_EUNSUPPORTED for
- * transposed or strided leaves, SUM / NORM, more than 32 scalars in the pair, or
+ * reads.  Errors: as coot_expr_eval and coot_reduce; COOT_EUNSUPPORTED under
+ * stream capture (workspace, as coot_reduce), for transposed or strided leaves, SUM / NORM, more than 32 scalars in the pair, or
  * compile-flagged comparators. */
 coot_status coot_expr_eval_reduce(coot_expr* e, const coot_operand* operands, const double* scalars, coot_operand* out,
                                   coot_expr* r, const int32_t* r_src, const double* r_scalars, int32_t kind,

@@ -89,9 +89,10 @@ coot_status coot_expr_eval(coot_expr* h, const coot_operand* operands, const dou
                            const coot_launch_cfg* cfg, void* stream) {
   return guarded([&] {
     if (!h || !out) fail(COOT_EINVAL, "NULL argument");
-    if (h->e->flags & COOT_CF_UNFUSED)
+    if (h->e->flags & COOT_CF_UNFUSED) {
+      reject_capture((hipStream_t)stream, "the unfused comparator");
       eval_unfused(*h->e, operands, scalars, *out, cfg, (hipStream_t)stream);
-    else
+    } else
       eval_fused(*h->e, operands, scalars, *out, cfg, (hipStream_t)stream);
   });
 }
@@ -102,6 +103,7 @@ coot_status coot_expr_eval_reduce(coot_expr* h, const coot_operand* operands, co
   return guarded([&] {
     if (!h || !out || !r || !r_out) fail(COOT_EINVAL, "NULL argument");
     if ((h->e->flags | r->e->flags) & COOT_CF_UNFUSED) fail(COOT_EUNSUPPORTED, "the comparator has no fused pair");
+    reject_capture((hipStream_t)stream, "coot_expr_eval_reduce");
     eval_reduce(*h->e, operands, scalars, *out, *r->e, r_src, r_scalars, kind, *r_out, cfg, (hipStream_t)stream);
   });
 }
@@ -113,6 +115,7 @@ coot_status coot_reduce(coot_expr* h, const coot_operand* operands, const double
     if (flags & ~(COOT_RF_PLAIN | COOT_RF_VAR_N)) fail(COOT_EINVAL, "unknown reduce flag");
     Expr& e = *h->e;
     hipStream_t s = (hipStream_t)stream;
+    reject_capture(s, "coot_reduce");
     if (!(e.flags & COOT_CF_UNFUSED)) {
       reduce_fused(e, operands, scalars, kind, dim, flags, *out, cfg, s);
       return;

@@ -174,6 +174,10 @@ void* dev_alloc(size_t bytes, hipStream_t s, DevAllocator* used);
 void dev_free(void* p, hipStream_t s, const DevAllocator& used);
 void set_allocator(const DevAllocator& a);
 void* workspace(size_t bytes, hipStream_t s, int which);
+// Calls that take workspace or temporaries refuse a stream under capture: the
+// library may free or hand out those buffers again after the call returns, which a
+// replayed graph would not see (COOT_EUNSUPPORTED).
+void reject_capture(hipStream_t s, const char* call);
 void* temp_alloc(size_t bytes, hipStream_t s);
 void temp_free(void* p, size_t bytes, hipStream_t s);
 

@@ -88,6 +88,14 @@ std::map<void*, DevAllocator>& temps_out() {
 }
 }  // namespace
 
+void reject_capture(hipStream_t s, const char* call) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  hip_check(hipStreamIsCapturing(s, &st), "hipStreamIsCapturing");
+  if (st != hipStreamCaptureStatusNone)
+    fail(COOT_EUNSUPPORTED, std::string(call) +
+                                " takes library workspace and cannot be recorded into a graph (the stream is capturing)");
+}
+
 void* workspace(size_t bytes, hipStream_t s, int which) {
   std::lock_guard<std::mutex> g(global_mutex());
   WsBuf& b = ws_map()[{s, which}];

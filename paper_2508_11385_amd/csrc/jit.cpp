@@ -200,6 +200,7 @@ static std::shared_ptr<Module> module_for(Expr& e, const std::string& rk, const 
                                           const KernelNames& names, bool load) {
   std::string opt_text;
   for (auto& o : rtc_options()) opt_text += o + " ";
+  if (const char* extra = std::getenv("COOT_HIPRTC_EXTRA")) opt_text += std::string("extra:") + extra;
   std::string hdr_text;
   for (auto& h : device_headers()) hdr_text += h.second;
   const std::string key = hex128(src + "\n" + opt_text + rtc_version() + hex128(hdr_text));

@@ -1,0 +1,82 @@
+"""Failures forced from the host, without a device: a compilation error reaches the
+caller as COOT_ECOMPILE with the hipRTC log and leaves nothing in the caches; a
+damaged file of the on-disk code-object cache (truncated, or one byte changed) is
+recompiled silently and rewritten whole."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+AXPY = [("load", 0), ("scalar", 0), ("schur",), ("load", 1), ("add",)]
+
+
+@pytest.fixture(scope="module")
+def cc():
+    from paper_2508_11385_amd import _coot
+    return _coot
+
+
+def test_compile_error_is_reported_and_nothing_is_cached(cc, tmp_path, monkeypatch):
+    monkeypatch.setenv("COOT_CACHE_DIR", str(tmp_path))
+    # an include of a missing file: every module compiled under it fails
+    monkeypatch.setenv("COOT_HIPRTC_EXTRA", "-include/nonexistent/coot_missing.h")
+    h = cc.coot_expr_compile(AXPY, [(cc.COOT_F32, 0)] * 2, 1)
+    before = cc.coot_stats()["compiles"]
+    for _ in range(2):                       # a failed module is not remembered either
+        with pytest.raises(cc.CootError) as e:
+            cc.coot_expr_prepare(h, -1, rflags=cc.COOT_PF_COMPILE_ONLY)
+        assert e.value.status == cc.COOT_ECOMPILE
+        assert "coot_missing.h" in str(e.value) and "hipRTC compilation failed" in str(e.value)
+    assert cc.coot_stats()["compiles"] == before
+    assert not [f for f in os.listdir(tmp_path) if f.endswith(".co")]
+    # the same request without the broken option compiles and is cached
+    monkeypatch.delenv("COOT_HIPRTC_EXTRA")
+    cc.coot_expr_prepare(h, -1, rflags=cc.COOT_PF_COMPILE_ONLY)
+    assert cc.coot_stats()["compiles"] == before + 1
+    assert len([f for f in os.listdir(tmp_path) if f.endswith(".co")]) == 1
+    cc.coot_expr_release(h)
+
+
+_CHILD = r"""
+import json, sys
+sys.path.insert(0, sys.argv[1])
+from paper_2508_11385_amd import _coot as cc
+h = cc.coot_expr_compile(%r, [(cc.COOT_F32, 0)] * 2, 1)
+cc.coot_expr_prepare(h, -1, rflags=cc.COOT_PF_COMPILE_ONLY)
+print(json.dumps(cc.coot_stats()))
+""" % (AXPY,)
+
+
+def _fresh_process(cache):
+    """Prepare the expression in a new process (empty memory cache); its counters."""
+    env = dict(os.environ, COOT_CACHE_DIR=str(cache))
+    env.pop("COOT_HIPRTC_EXTRA", None)
+    env.pop("COOT_NO_DISK_CACHE", None)
+    r = subprocess.run([sys.executable, "-c", _CHILD, ROOT], env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+@pytest.mark.parametrize("damage", ["truncate", "flip"])
+def test_damaged_disk_cache_file_is_recompiled(tmp_path, damage):
+    s = _fresh_process(tmp_path)
+    assert (s["compiles"], s["disk_hits"]) == (1, 0)
+    files = [f for f in os.listdir(tmp_path) if f.endswith(".co")]
+    assert len(files) == 1
+    path = os.path.join(tmp_path, files[0])
+    whole = open(path, "rb").read()
+    assert (_fresh_process(tmp_path)["compiles"], _fresh_process(tmp_path)["disk_hits"]) == (0, 1)
+    if damage == "truncate":
+        open(path, "wb").write(whole[:len(whole) // 2])
+    else:                                    # one byte of the code object changed: the checksum differs
+        b = bytearray(whole)
+        b[len(b) - 100] ^= 0x40
+        open(path, "wb").write(bytes(b))
+    s = _fresh_process(tmp_path)
+    assert (s["compiles"], s["disk_hits"]) == (1, 0)
+    assert open(path, "rb").read() == whole  # rewritten whole
+    s = _fresh_process(tmp_path)
+    assert (s["compiles"], s["disk_hits"]) == (0, 1)
