@@ -323,6 +323,33 @@ void capture(coot_batch* b) {
   hip_check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "hipGraphInstantiate");
 }
 
+// Every expression of a batch runs concurrently with every other (one persistent
+// launch, two captured streams), so no output may overlap another expression's
+// output or operand.  Outputs sorted by address: any overlap among them shows
+// between neighbours; each operand range is then looked up among the (disjoint,
+// sorted) outputs and every output it meets must be its own expression's.
+struct Interval {
+  uintptr_t lo, hi;  // [lo, hi)
+  uint32_t expr;
+};
+
+void check_batch_overlaps(std::vector<Interval>& outs, const std::vector<Interval>& ins) {
+  std::sort(outs.begin(), outs.end(), [](const Interval& a, const Interval& b) { return a.lo < b.lo; });
+  for (size_t i = 1; i < outs.size(); ++i)
+    if (outs[i].lo < outs[i - 1].hi)
+      fail(COOT_EALIAS, "outputs of batch expressions " + std::to_string(outs[i - 1].expr) + " and " +
+                            std::to_string(outs[i].expr) + " overlap");
+  for (const Interval& r : ins) {
+    // first output whose end lies past the operand's start (ends ascend with starts)
+    auto it = std::upper_bound(outs.begin(), outs.end(), r.lo,
+                               [](uintptr_t v, const Interval& o) { return v < o.hi; });
+    for (; it != outs.end() && it->lo < r.hi; ++it)
+      if (it->expr != r.expr)
+        fail(COOT_EALIAS, "batch expression " + std::to_string(r.expr) + " reads memory that expression " +
+                              std::to_string(it->expr) + " writes");
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -348,6 +375,7 @@ coot_status coot_batch_create(uint32_t n, coot_expr* const* exprs, const coot_op
     }
     int dtype = -1;
     std::vector<double> scal;
+    std::vector<Interval> out_iv, in_iv;  // byte ranges of the outputs and the operands
     for (uint32_t k = 0; k < n; ++k) {
       if (!exprs[k]) fail(COOT_EINVAL, "NULL expression in the batch");
       Expr& e = *exprs[k]->e;
@@ -393,11 +421,19 @@ coot_status coot_batch_create(uint32_t n, coot_expr* const* exprs, const coot_op
           v4 = v4 && lld % 4 == 0 && ((uintptr_t)lo.data % 16) == 0;
           flat = flat && (lld == lo.n_rows || lo.n_cols <= 1);
         }
-        // the output may only alias an operand read untransposed with its own layout
-        const char* ob = (const char*)o.data;
-        const char* lb = (const char*)lo.data;
-        if (R * C > 0 && lb == ob && (e.leaves[l].parity || lld != old))
-          fail(COOT_EALIAS, "batch output aliases a transposed or differently laid out operand");
+      }
+      // within the expression, the output may only alias an operand read untransposed
+      // with its own layout; overlaps across expressions are checked below
+      check_alias(e, ops, o, es);
+      if (R * C > 0) {
+        const uintptr_t ob = (uintptr_t)o.data;
+        out_iv.push_back({ob, ob + (uintptr_t)((C - 1) * old + R) * es, k});
+        for (size_t l = 0; l < e.slots.size(); ++l) {
+          const coot_operand& lo = ops[l];
+          if (lo.n_rows * lo.n_cols == 0) continue;
+          const uintptr_t lb = (uintptr_t)lo.data;
+          in_iv.push_back({lb, lb + (uintptr_t)((lo.n_cols - 1) * ld_of(lo) + lo.n_rows) * es, k});
+        }
       }
       if (flat) v4 = aligned;
       be.out = o.data;
@@ -427,6 +463,7 @@ coot_status coot_batch_create(uint32_t n, coot_expr* const* exprs, const coot_op
         }
       b->bytes += elems * (int64_t)es;
     }
+    check_batch_overlaps(out_iv, in_iv);
     b->dtype = dtype < 0 ? COOT_BATCH_F32 : dtype;
     // scalars in the element type, one 64-bit slot each (fp32 scalars use the low word of a float array)
     if (b->dtype == COOT_BATCH_F32) {

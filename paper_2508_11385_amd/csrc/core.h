@@ -202,6 +202,9 @@ Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, in
              const coot_launch_cfg* cfg);
 
 int64_t ld_of(const coot_operand& o);
+// COOT_EALIAS unless every operand that overlaps `out` is read untransposed with
+// out's own layout (the same base, leading dimension and dims)
+void check_alias(const Expr& e, const coot_operand* ops, const coot_operand& out, size_t es);
 bool vec_ok(const Expr& e, const Request& rq, const coot_operand* ops, const coot_operand* out, int64_t R, int64_t C);
 void fill_args(const Expr& e, const coot_operand* ops, const double* scalars, KArgs* a);
 unsigned flat_grid(int64_t n, int V, int E, int bs, int gm);

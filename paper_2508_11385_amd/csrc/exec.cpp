@@ -283,7 +283,7 @@ void fill_args(const Expr& e, const coot_operand* ops, const double* scalars, KA
   for (uint32_t k = 0; k < e.n_scalars; ++k) a->sc[k] = scalar_bits(scalars[k], e.dtype);
 }
 
-static void check_alias(const Expr& e, const coot_operand* ops, const coot_operand& out, size_t es) {
+void check_alias(const Expr& e, const coot_operand* ops, const coot_operand& out, size_t es) {
   const int64_t oc = out.n_cols, orr = out.n_rows;
   if (orr * oc == 0) return;
   const char* ob = (const char*)out.data;
