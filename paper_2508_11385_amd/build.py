@@ -28,7 +28,7 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-DEVICE_HEADERS = ("coot_dev.h", "coot_exp.h", "exp_tables.h")
+DEVICE_HEADERS = ("coot_dev.h", "coot_exp.h", "exp_tables.h", "coot_log.h", "log_tables.h")
 
 
 def _embed_header() -> str:

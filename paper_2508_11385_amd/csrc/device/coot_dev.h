@@ -25,6 +25,7 @@
 #pragma clang fp contract(off)
 
 #include "coot_exp.h"
+#include "coot_log.h"
 
 typedef unsigned int u32;
 typedef int s32;
@@ -125,7 +126,7 @@ __device__ __forceinline__ float op_abs(float a) { return __builtin_fabsf(a); }
 __device__ __forceinline__ float op_sqrt(float a) { return __builtin_sqrtf(a); }
 __device__ __forceinline__ float op_square(float a) { return a * a; }
 __device__ __forceinline__ float op_exp(float a) { return exp_rn<float>(a); }  // correctly rounded (coot_exp.h)
-__device__ __forceinline__ float op_log(float a) { return logf(a); }
+__device__ __forceinline__ float op_log(float a) { return log_lf(a); }
 
 __device__ __forceinline__ double op_add(double a, double b) { return a + b; }
 __device__ __forceinline__ double op_sub(double a, double b) { return a - b; }

@@ -1,5 +1,6 @@
-"""The kernels' exponential (csrc/device/coot_exp.h) built for the host with g++, so
-its arithmetic can be checked against the oracle without a GPU."""
+"""The kernels' exponential and binary32 logarithm (csrc/device/coot_exp.h,
+coot_log.h) built for the host with g++, so their arithmetic can be checked against
+the oracle without a GPU."""
 import ctypes
 import os
 import shutil
@@ -14,6 +15,8 @@ SRC = r"""
 #define __device__
 #define __forceinline__ inline
 #include "coot_exp.h"
+#include "coot_log.h"
+extern "C" void logf_n(const float* x, float* y, long n) { for (long i = 0; i < n; ++i) y[i] = coot::log_lf(x[i]); }
 extern "C" void expf_n(const float* x, float* y, long n) { for (long i = 0; i < n; ++i) y[i] = coot::exp_cr<float>(x[i]); }
 extern "C" void exp_n(const double* x, double* y, long n) { for (long i = 0; i < n; ++i) y[i] = coot::exp_cr<double>(x[i]); }
 extern "C" void expf_rn_n(const float* x, float* y, long n) { for (long i = 0; i < n; ++i) y[i] = coot::exp_rn<float>(x[i]); }
@@ -39,7 +42,7 @@ def build():
     subprocess.run([gxx, "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared", "-I", DEV, src, "-o", so],
                    check=True)
     L = ctypes.CDLL(so)
-    for name in ("expf_n", "exp_n", "expf_rn_n", "exp_rn_n"):
+    for name in ("expf_n", "exp_n", "expf_rn_n", "exp_rn_n", "logf_n"):
         getattr(L, name).argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_long]
     L.expf_fast_misses.argtypes = [ctypes.c_void_p, ctypes.c_long]
     L.expf_fast_misses.restype = ctypes.c_long
