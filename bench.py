@@ -109,7 +109,7 @@ def main():
 
     # launch configurations of the element-wise kernels: the project's autotuner (exhaustive
     # over the family's space, cold-cache timings), run once before any timed region
-    cfgs = {"Z": None, "W": None}
+    cfgs = {"Z": None, "W": None, "S0": None, "S1": None}
     for k, v in (("Z", args.z_cfg), ("W", args.w_cfg)):
         if v:
             cfgs[k] = tuple(int(x) for x in v.split(","))
@@ -117,13 +117,16 @@ def main():
     if args.tune == "exhaustive":
         cfgs["Z"] = cc.coot_tune(fused[0], zops, zf.scalars, zo, -1, 1, stream=stream)[0]
         cfgs["W"] = cc.coot_tune(fused[1], wops, wf.scalars, wo, -1, 1, stream=stream)[0]
+        cfgs["S0"] = cc.coot_tune(fused[0], zops, zf.scalars, s0o, cc.COOT_RED_SUM, 1, stream=stream, dim=0)[0]
+        cfgs["S1"] = cc.coot_tune(fused[0], zops, zf.scalars, s1o, cc.COOT_RED_SUM, 1, stream=stream, dim=1)[0]
     t_tune = time.perf_counter() - t0
+    tuned = any(cfgs.values())
 
-    def step(hz, hw, zc=None, wc=None):
+    def step(hz, hw, zc=None, wc=None, s0c=None, s1c=None):
         cc.coot_expr_eval(hz, zops, zf.scalars, zo, zc, stream)
         cc.coot_expr_eval(hw, wops, wf.scalars, wo, wc, stream)
-        cc.coot_reduce(hz, zops, zf.scalars, cc.COOT_RED_SUM, 0, 0, s0o, None, stream)
-        cc.coot_reduce(hz, zops, zf.scalars, cc.COOT_RED_SUM, 1, 0, s1o, None, stream)
+        cc.coot_reduce(hz, zops, zf.scalars, cc.COOT_RED_SUM, 0, 0, s0o, s0c, stream)
+        cc.coot_reduce(hz, zops, zf.scalars, cc.COOT_RED_SUM, 1, 0, s1o, s1c, stream)
 
     # copy probe: out = A through the flat family, 64 MiB read + 64 MiB written
     copy_flat = coot.flatten(gA + 0.0)
@@ -140,12 +143,12 @@ def main():
         for _ in range(3):
             copy()
         for _ in range(3):
-            step(*fused, cfgs["Z"], cfgs["W"])
+            step(*fused, cfgs["Z"], cfgs["W"], cfgs["S0"], cfgs["S1"])
         torch.cuda.synchronize()
         names = {"copy": cc.coot_expr_kernel_name(hcopy), "Z": cc.coot_expr_kernel_name(fused[0], cfg=cfgs["Z"]),
                  "W": cc.coot_expr_kernel_name(fused[1], cfg=cfgs["W"]),
-                 "sumZ0": cc.coot_expr_kernel_name(fused[0], cc.COOT_RED_SUM, 0),
-                 "sumZ1": cc.coot_expr_kernel_name(fused[0], cc.COOT_RED_SUM, 1)}
+                 "sumZ0": cc.coot_expr_kernel_name(fused[0], cc.COOT_RED_SUM, 0, cfg=cfgs["S0"]),
+                 "sumZ1": cc.coot_expr_kernel_name(fused[0], cc.COOT_RED_SUM, 1, cfg=cfgs["S1"])}
         print(json.dumps({"profiled_kernels": names, "copy_bytes": 2 * MIB64, "Z_bytes": 5 * MIB64,
                           "launches_each": 3}), flush=True)
         return
@@ -164,9 +167,9 @@ def main():
     copy_ms = sorted(a.elapsed_time(b) for a, b in cev)[len(cev) // 2]
     copy_gbs = 2 * MIB64 / (copy_ms * 1e-3) / 1e9
 
-    def run(h, steps, warmup, zc=None, wc=None, z_events=None):
+    def run(h, steps, warmup, zc=None, wc=None, z_events=None, s0c=None, s1c=None):
         for _ in range(warmup):
-            step(*h, zc, wc)
+            step(*h, zc, wc, s0c, s1c)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -178,32 +181,34 @@ def main():
                 ev1.record()
                 z_events.append((ev0, ev1))
                 cc.coot_expr_eval(h[1], wops, wf.scalars, wo, wc, stream)
-                cc.coot_reduce(h[0], zops, zf.scalars, cc.COOT_RED_SUM, 0, 0, s0o, None, stream)
-                cc.coot_reduce(h[0], zops, zf.scalars, cc.COOT_RED_SUM, 1, 0, s1o, None, stream)
+                cc.coot_reduce(h[0], zops, zf.scalars, cc.COOT_RED_SUM, 0, 0, s0o, s0c, stream)
+                cc.coot_reduce(h[0], zops, zf.scalars, cc.COOT_RED_SUM, 1, 0, s1o, s1c, stream)
             else:
-                step(*h, zc, wc)
+                step(*h, zc, wc, s0c, s1c)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
     # the chosen and the default configurations are timed in alternating blocks of steps, so
     # that clock and temperature drift over the run affects both alike; no events are
     # recorded inside these steps (a pair of event records costs several microseconds)
+    tc = (cfgs["Z"], cfgs["W"])
+    ts = {"s0c": cfgs["S0"], "s1c": cfgs["S1"]}
     for _ in range(args.warmup):
-        step(*fused, cfgs["Z"], cfgs["W"])
+        step(*fused, *tc, cfgs["S0"], cfgs["S1"])
         step(*fused)
     blocks = 4 if args.steps >= 4 else 1
     per = [args.steps // blocks + (1 if k < args.steps % blocks else 0) for k in range(blocks)]
     t_fused = t_default = 0.0
     for n in per:
-        t_fused += run(fused, n, 0, cfgs["Z"], cfgs["W"]) * n
-        if cfgs["Z"] or cfgs["W"]:
+        t_fused += run(fused, n, 0, *tc, **ts) * n
+        if tuned:
             t_default += run(fused, n, 0) * n
     t_fused /= args.steps
-    t_default = t_default / args.steps if (cfgs["Z"] or cfgs["W"]) else t_fused
+    t_default = t_default / args.steps if tuned else t_fused
     # the Z kernel's launch duration for the roofline: the same steps again, with HIP events
     # around each Z launch on its stream
     z_events = []
-    run(fused, args.steps, 0, cfgs["Z"], cfgs["W"], z_events)
+    run(fused, args.steps, 0, *tc, z_events, **ts)
     z_ms = sum(a.elapsed_time(b) for a, b in z_events) / len(z_events)
     t_unfused = run(unfused, max(3, args.steps // 4), 2)
 
@@ -227,9 +232,9 @@ def main():
     parts = {
         "Z": (lambda: cc.coot_expr_eval(hz, zops, zf.scalars, zo, cfgs["Z"], stream), 5 * MIB64),
         "W": (lambda: cc.coot_expr_eval(hw, wops, wf.scalars, wo, cfgs["W"], stream), 3 * MIB64),
-        "sumZ0": (lambda: cc.coot_reduce(hz, zops, zf.scalars, cc.COOT_RED_SUM, 0, 0, s0o, None, stream),
+        "sumZ0": (lambda: cc.coot_reduce(hz, zops, zf.scalars, cc.COOT_RED_SUM, 0, 0, s0o, cfgs["S0"], stream),
                   4 * MIB64 + N * 4),
-        "sumZ1": (lambda: cc.coot_reduce(hz, zops, zf.scalars, cc.COOT_RED_SUM, 1, 0, s1o, None, stream),
+        "sumZ1": (lambda: cc.coot_reduce(hz, zops, zf.scalars, cc.COOT_RED_SUM, 1, 0, s1o, cfgs["S1"], stream),
                   4 * MIB64 + N * 4),
     }
     cold_s = {k: cold(fn) for k, (fn, nb) in parts.items()}
@@ -281,11 +286,12 @@ def main():
         "pct_of_copy_probe": round(100 * value / copy_gbs, 1),
         "kernels": {"copy": cc.coot_expr_kernel_name(hcopy), "Z": zname,
                     "W": cc.coot_expr_kernel_name(fused[1], cfg=cfgs["W"]),
-                    "sumZ0": cc.coot_expr_kernel_name(fused[0], cc.COOT_RED_SUM, 0),
-                    "sumZ1": cc.coot_expr_kernel_name(fused[0], cc.COOT_RED_SUM, 1)},
-        "launch_cfgs": {"Z": cfgs["Z"], "W": cfgs["W"], "sums": "library default",
+                    "sumZ0": cc.coot_expr_kernel_name(fused[0], cc.COOT_RED_SUM, 0, cfg=cfgs["S0"]),
+                    "sumZ1": cc.coot_expr_kernel_name(fused[0], cc.COOT_RED_SUM, 1, cfg=cfgs["S1"])},
+        "launch_cfgs": {"Z": cfgs["Z"], "W": cfgs["W"], "sumZ0": cfgs["S0"], "sumZ1": cfgs["S1"],
+                        "fields": "vec, ept, waves, grid_mult, tile_r, tile_c",
                         "chosen_by": "exhaustive autotuner before timing" if args.tune == "exhaustive"
-                        else ("given" if (cfgs["Z"] or cfgs["W"]) else "library defaults"),
+                        else ("given" if tuned else "library defaults"),
                         "tuning_s": round(t_tune, 2)},
         "default_cfg_ms_per_step": round(t_default * 1e3, 4),
         "unfused_ms_per_step": round(t_unfused * 1e3, 4),

@@ -117,7 +117,9 @@ typedef struct {
  *   ept       vector groups per thread per loop trip: 1, 2, 4 or 8 (flat kernels)
  *   waves     64-lane wavefronts per workgroup: 1, 2, 4 or 8 (flat kernels; the tiled
  *             kernels run 4)
- *   grid_mult workgroups per compute unit for grid-stride kernels: 1..16
+ *   grid_mult workgroups per compute unit for grid-stride kernels: 1..16; for a
+ *             reduction along a dimension, the tiles per CU past which each
+ *             workgroup folds a longer segment of tiles (default 8)
  *   tile_r, tile_c  output tile of the tiled kernels (transposed or strided leaves,
  *             dimension reductions), rows x columns: powers of two in [16, 256] with
  *             1024 <= tile_r * tile_c <= 8192, both given or both 0; the staged
@@ -358,17 +360,25 @@ coot_status coot_batch_info(const coot_batch* b, int64_t info[13]);
 void coot_batch_release(coot_batch* b);
 
 /* ---- autotuning of the fused kernels' launch configuration ----------------
- * A configuration is (vec, ept, waves, grid_mult).  vec and ept select
- * compile-time variants (one tuning module per expression signature holds all
- * of them), waves and grid_mult are launch parameters.  Expressions that take
- * the tiled kernels (transposed or strided leaves) run 256-thread workgroups:
- * only vec and grid_mult vary there (ept = 1, waves = 4 in their configurations).
- * Tuning covers element-wise evaluation (mode -1) and accu (mode COOT_RED_ACCU). */
+ * A configuration is (vec, ept, waves, grid_mult, tile_r, tile_c).  vec, ept and
+ * the tile select compile-time variants (one tuning module per expression
+ * signature holds all of them), waves and grid_mult are launch parameters.
+ * Expressions that take the tiled kernels (transposed or strided leaves, and every
+ * reduction along a dimension) run 256-thread workgroups: vec, grid_mult and the
+ * tile vary there (ept = 1, waves = 4 in their configurations).  Along a dimension,
+ * grid_mult is the number of tiles per CU past which the library lengthens the
+ * segments each workgroup folds (fewer partial results).
+ * Tuning covers element-wise evaluation (mode -1), accu (mode COOT_RED_ACCU; dot
+ * when the root is a % b) and sum / mean / variance along dim 0 or 1 (COOT_RED_SUM,
+ * COOT_RED_MEAN_DIM, COOT_RED_VAR_DIM; dim is ignored for the others; a variance is
+ * timed with its N - 1 stage 2). */
 
 /* Write the configuration space of a kernel family (0 flat, 1 tiled) into
  * cfgs[0..cap) and return its size (cfgs may be NULL to query the size).
- * Flat: vec {1,2,4} x ept {1,2,4,8} x waves {1,2,4,8} x grid_mult {2,4,8,16} = 192;
- * tiled: vec {1,2,4} x grid_mult {2,4,8,16} = 12.  For the 16-bit types vec 8
+ * Flat: vec {1,2,4} x ept {1,2,4,8} x waves {1,2,4,8} x grid_mult {2,4,8,16} = 192
+ * (tile 0 x 0); tiled: tile {64x64, 128x32, 32x128, 256x16, 128x64, 32x32} x
+ * vec {1,2,4} x grid_mult {2,4,8,16} = 72 (a tile whose transposed-leaf staging
+ * exceeds 64 KiB, or whose vec exceeds tile_r * tile_c / 256, cannot run).  For the 16-bit types vec 8
  * (16-byte groups) is valid too: their tuning modules hold those variants,
  * coot_tune_table accepts them (NaN for other types) and coot_tune's exhaustive
  * policy adds them to this space. */
@@ -378,14 +388,15 @@ uint32_t coot_tune_space(int32_t family, coot_launch_cfg* cfgs, uint32_t cap);
  * report which family (0 flat, 1 tiled) the expression takes.  Safe to call from
  * several host threads at once (compilation runs outside the library's lock).
  * Errors: COOT_EINVAL, COOT_ESHAPE, COOT_ECOMPILE, COOT_EUNSUPPORTED (mode). */
-coot_status coot_tune_prepare(coot_expr* e, const coot_operand* operands, int32_t mode, int32_t* family);
+coot_status coot_tune_prepare(coot_expr* e, const coot_operand* operands, int32_t mode, int32_t dim,
+                              int32_t* family);
 
 /* runnable[k] = 1 when configuration k can run on these operands (its vector
  * width fits their alignment, leading dimensions and, for the tiled family, the
  * tile), else 0; no device work.  out is needed for mode -1 (element-wise).
  * Errors: as coot_tune_prepare, COOT_EINVAL for an invalid configuration. */
 coot_status coot_tune_runnable(coot_expr* e, const coot_operand* operands, const coot_operand* out, int32_t mode,
-                               const coot_launch_cfg* cfgs, uint32_t n_cfgs, int32_t* runnable);
+                               int32_t dim, const coot_launch_cfg* cfgs, uint32_t n_cfgs, int32_t* runnable);
 
 /* Time each configuration: one warm-up launch each, then `reps` rounds (1..101),
  * each round timing every configuration once with HIP events on `stream` around
@@ -397,12 +408,12 @@ coot_status coot_tune_runnable(coot_expr* e, const coot_operand* operands, const
  * Synchronises the stream.  out receives the result as in coot_expr_eval /
  * coot_reduce.  Errors: as coot_expr_eval, COOT_EINVAL for an invalid configuration. */
 coot_status coot_tune_table(coot_expr* e, const coot_operand* operands, const double* scalars, coot_operand* out,
-                            int32_t mode, const coot_launch_cfg* cfgs, uint32_t n_cfgs, uint32_t reps,
+                            int32_t mode, int32_t dim, const coot_launch_cfg* cfgs, uint32_t n_cfgs, uint32_t reps,
                             int32_t flush, float* times_us, void* stream);
 
 /* Evaluate with an explicit configuration through the tuning module. */
 coot_status coot_tune_launch(coot_expr* e, const coot_operand* operands, const double* scalars, coot_operand* out,
-                             int32_t mode, const coot_launch_cfg* cfg, void* stream);
+                             int32_t mode, int32_t dim, const coot_launch_cfg* cfg, void* stream);
 
 /* ---- learned tuner: MLP cost model ------------------------------------------
  * A 3-Linear-layer ReLU network in -> h1 -> h2 -> 1, binary32, trained on the
@@ -473,10 +484,11 @@ void coot_costmodel_release(coot_costmodel* cm);
  * repeated calls); under policy 1 the finalists (within 5 % of the fastest, at
  * most 4) are timed again over 21 interleaved rounds and the fastest of those is
  * kept.  best_us (may be NULL) is the chosen configuration's median.
- * Synchronises the stream. */
+ * The cost model (policy 2) covers element-wise evaluation and accu only
+ * (COOT_EUNSUPPORTED along a dimension).  Synchronises the stream. */
 coot_status coot_tune(coot_expr* e, const coot_operand* operands, const double* scalars, coot_operand* out,
-                      int32_t mode, int32_t policy, coot_costmodel* cm, coot_launch_cfg* best, float* best_us,
-                      void* stream);
+                      int32_t mode, int32_t dim, int32_t policy, coot_costmodel* cm, coot_launch_cfg* best,
+                      float* best_us, void* stream);
 
 /* Queue on `stream` a read of a 512 MiB library buffer (allocated on first use and
  * kept), larger than the L2 caches and the Infinity Cache together: every line a

@@ -104,14 +104,14 @@ _sig = {
     "coot_batch_info": (C.c_int, [_P, C.POINTER(C.c_int64)]),
     "coot_batch_release": (None, [_P]),
     "coot_tune_space": (C.c_uint32, [C.c_int32, C.POINTER(coot_launch_cfg), C.c_uint32]),
-    "coot_tune_prepare": (C.c_int, [_P, C.POINTER(coot_operand), C.c_int32, C.POINTER(C.c_int32)]),
-    "coot_tune_runnable": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(coot_operand), C.c_int32,
+    "coot_tune_prepare": (C.c_int, [_P, C.POINTER(coot_operand), C.c_int32, C.c_int32, C.POINTER(C.c_int32)]),
+    "coot_tune_runnable": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(coot_operand), C.c_int32, C.c_int32,
                                      C.POINTER(coot_launch_cfg), C.c_uint32, C.POINTER(C.c_int32)]),
     "coot_tune_table": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(C.c_double), C.POINTER(coot_operand),
-                                  C.c_int32, C.POINTER(coot_launch_cfg), C.c_uint32, C.c_uint32, C.c_int32,
+                                  C.c_int32, C.c_int32, C.POINTER(coot_launch_cfg), C.c_uint32, C.c_uint32, C.c_int32,
                                   C.POINTER(C.c_float), _P]),
     "coot_tune_launch": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(C.c_double), C.POINTER(coot_operand),
-                                   C.c_int32, C.POINTER(coot_launch_cfg), _P]),
+                                   C.c_int32, C.c_int32, C.POINTER(coot_launch_cfg), _P]),
     "coot_mlp_create": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_float), C.POINTER(_P)]),
     "coot_mlp_num_params": (C.c_uint32, [_P]),
     "coot_mlp_get_params": (C.c_int, [_P, C.POINTER(C.c_float)]),
@@ -133,7 +133,7 @@ _sig = {
     "coot_costmodel_load": (C.c_int, [C.c_char_p, C.POINTER(_P)]),
     "coot_costmodel_release": (None, [_P]),
     "coot_tune": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(C.c_double), C.POINTER(coot_operand), C.c_int32,
-                            C.c_int32, _P, C.POINTER(coot_launch_cfg), C.POINTER(C.c_float), _P]),
+                            C.c_int32, C.c_int32, _P, C.POINTER(coot_launch_cfg), C.POINTER(C.c_float), _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(lib, _name)
@@ -318,37 +318,39 @@ def _cfgs(cfgs):
     return _arr(coot_launch_cfg, [coot_launch_cfg(*c) for c in cfgs])
 
 
-def coot_tune_prepare(h: int, operands, mode: int = -1) -> int:
+def coot_tune_prepare(h: int, operands, mode: int = -1, dim: int = -1) -> int:
     fam = C.c_int32()
-    _check(lib.coot_tune_prepare(h, _arr(coot_operand, operands), mode, C.byref(fam)))
+    _check(lib.coot_tune_prepare(h, _arr(coot_operand, operands), mode, dim, C.byref(fam)))
     return fam.value
 
 
-def coot_tune_runnable(h: int, operands, out, mode: int, cfgs) -> list:
+def coot_tune_runnable(h: int, operands, out, mode: int, cfgs, dim: int = -1) -> list:
     ok = (C.c_int32 * max(1, len(cfgs)))()
     _check(lib.coot_tune_runnable(h, _arr(coot_operand, operands), C.byref(out) if out is not None else None, mode,
-                                  _cfgs(cfgs), len(cfgs), ok))
+                                  dim, _cfgs(cfgs), len(cfgs), ok))
     return [bool(ok[i]) for i in range(len(cfgs))]
 
 
 def coot_tune_table(h: int, operands, scalars, out: coot_operand, mode: int, cfgs, reps: int = 5, flush: bool = True,
-                    stream: int = 0) -> list:
+                    stream: int = 0, dim: int = -1) -> list:
     t = (C.c_float * max(1, len(cfgs)))()
-    _check(lib.coot_tune_table(h, _arr(coot_operand, operands), _arr(C.c_double, scalars), C.byref(out), mode,
+    _check(lib.coot_tune_table(h, _arr(coot_operand, operands), _arr(C.c_double, scalars), C.byref(out), mode, dim,
                                _cfgs(cfgs), len(cfgs), reps, int(flush), t, stream))
     return [t[i] for i in range(len(cfgs))]
 
 
-def coot_tune_launch(h: int, operands, scalars, out: coot_operand, mode: int, cfg, stream: int = 0) -> None:
-    _check(lib.coot_tune_launch(h, _arr(coot_operand, operands), _arr(C.c_double, scalars), C.byref(out), mode,
+def coot_tune_launch(h: int, operands, scalars, out: coot_operand, mode: int, cfg, stream: int = 0,
+                     dim: int = -1) -> None:
+    _check(lib.coot_tune_launch(h, _arr(coot_operand, operands), _arr(C.c_double, scalars), C.byref(out), mode, dim,
                                 C.byref(coot_launch_cfg(*cfg)), stream))
 
 
-def coot_tune(h: int, operands, scalars, out: coot_operand, mode: int, policy: int, cm: int = 0, stream: int = 0):
+def coot_tune(h: int, operands, scalars, out: coot_operand, mode: int, policy: int, cm: int = 0, stream: int = 0,
+              dim: int = -1):
     best = coot_launch_cfg()
     us = C.c_float()
-    _check(lib.coot_tune(h, _arr(coot_operand, operands), _arr(C.c_double, scalars), C.byref(out), mode, policy,
-                         cm or None, C.byref(best), C.byref(us), stream))
+    _check(lib.coot_tune(h, _arr(coot_operand, operands), _arr(C.c_double, scalars), C.byref(out), mode, dim,
+                         policy, cm or None, C.byref(best), C.byref(us), stream))
     return cfg_tuple(best), us.value
 
 

@@ -239,6 +239,9 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
           if (rq.mode < 0) {
             call = rq.fam == FAM_FLAT ? "coot::flat_eval<X, " + std::to_string(v) + ", " + std::to_string(ept) + ">(a)"
                                       : "coot::tiled_eval<X, " + std::to_string(v) + ", " + tt + ">(a)";
+          } else if (is_dim_kind(rq.mode) && rq.dim >= 0) {
+            call = "coot::tiled_reduce_dim<X, " + std::to_string(rq.dim) + ", " + comp + ", " + std::to_string(v) +
+                   ", " + tt + (rq.mode == COOT_RED_VAR_DIM ? ", true" : ", false") + ">(a)";
           } else {
             const std::string rks2 = std::to_string(red_kind(rq.mode));
             call = rq.fam == FAM_FLAT ? "coot::flat_reduce<X, " + rks2 + ", " + comp + ", " + std::to_string(v) +
@@ -251,7 +254,16 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
         }
       }
     }
-    if (rq.mode >= 0) {
+    if (is_dim_kind(rq.mode) && rq.dim >= 0) {
+      // stage 2 of a reduction along dim (a variance: divided by N - 1)
+      const std::string d = std::to_string(rq.dim);
+      const bool var = rq.mode == COOT_RED_VAR_DIM;
+      const std::string fm = rq.mode == COOT_RED_SUM ? "DM_SUM" : (var ? "DM_VAR" : "DM_MEAN");
+      names->stage2 = "coot_rdfin_" + hs + "_d" + d + "c" + (rq.comp ? "1" : "0") + "_m" + std::to_string(rq.mode) +
+                      "_tm";
+      wrap(names->stage2, "coot::dim_stage2<X::S, " + comp + ", coot::" + fm + ">(a, " +
+                              (rq.dim == 0 ? "a.n_cols, a.n_rows" : "a.n_rows, a.n_cols") + ")", 256);
+    } else if (rq.mode >= 0) {
       const std::string rks2 = std::to_string(red_kind(rq.mode));
       names->stage2 = "coot_rfin_" + hs + "_k" + rks2 + "c" + (rq.comp ? "1" : "0") + "_tm";
       wrap(names->stage2, "coot::reduce_stage2<X::S, " + rks2 + ", " + comp + ", false>(a)", 256);

@@ -192,6 +192,17 @@ void eval_unfused(Expr& e, const coot_operand* ops, const double* scalars, const
 void eval_reduce(Expr& e, const coot_operand* ops, const double* scalars, const coot_operand& out, Expr& r,
                  const int32_t* r_src, const double* r_scalars, int kind, const coot_operand& r_out,
                  const coot_launch_cfg* cfg, hipStream_t s);
+// Launch geometry of a reduction along a dimension: the reduced dimension's tiles cut
+// into n_part segments (K tiles each, K growing once there are more than per_cu tiles
+// per CU, at most 16), one workgroup per (segment, output strip); part_bytes of
+// float-float partials (compute type of cs bytes) per partial array.
+struct DimPlan {
+  int64_t n_out = 0, n_part = 1, nseg = 0;
+  size_t part_bytes = 0;
+};
+DimPlan dim_plan(int64_t R, int64_t C, int dim, int tile_r, int tile_c, int per_cu, size_t cs);
+// Stage 1 over p.nseg workgroups (none when empty), then stage 2, one wavefront per output.
+void launch_dim(hipFunction_t stage1, hipFunction_t stage2, KArgs& a, const DimPlan& p, hipStream_t s);
 void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int kind, int dim, uint32_t flags,
                   const coot_operand& out, const coot_launch_cfg* cfg, hipStream_t s);
 // The library's launch configuration for a family when the caller gives none

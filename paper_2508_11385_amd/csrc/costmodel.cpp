@@ -33,11 +33,6 @@ hipError_t coot_mlp_k_adam(float* P, const float* G, float* M, float* V, int n, 
                            float c1, float c2, hipStream_t s);
 hipError_t coot_mlp_k_gather(const float* X, const float* y, const float* mask, const int* idx, int B, int K,
                              float* Xb, float* yb, float* mb, hipStream_t s);
-uint32_t coot_tune_space(int32_t family, coot_launch_cfg* cfgs, uint32_t cap);
-coot_status coot_tune_table(coot_expr* h, const coot_operand* operands, const double* scalars, coot_operand* out,
-                            int32_t mode, const coot_launch_cfg* cfgs, uint32_t n_cfgs, uint32_t reps, int32_t flush,
-                            float* times_us, void* stream);
-coot_status coot_tune_prepare(coot_expr* h, const coot_operand* operands, int32_t mode, int32_t* family);
 }
 
 using namespace coot;
@@ -505,12 +500,12 @@ void coot_costmodel_release(coot_costmodel* cm) { delete cm; }
 
 // Choose a configuration: 0 DEFAULT, 1 EXHAUSTIVE (time all), 2 MLP (cost-model argmin, then timed).
 coot_status coot_tune(coot_expr* h, const coot_operand* operands, const double* scalars, coot_operand* out,
-                      int32_t mode, int32_t policy, coot_costmodel* cm, coot_launch_cfg* best, float* best_us,
-                      void* stream) {
+                      int32_t mode, int32_t dim, int32_t policy, coot_costmodel* cm, coot_launch_cfg* best,
+                      float* best_us, void* stream) {
   return guarded([&] {
     if (!h || !out || !best) fail(COOT_EINVAL, "NULL argument");
     int32_t fam = 0;
-    coot_status st = coot_tune_prepare(h, operands, mode, &fam);
+    coot_status st = coot_tune_prepare(h, operands, mode, dim, &fam);
     if (st != COOT_OK) fail(st, last_error());
     std::vector<coot_launch_cfg> space(coot_tune_space(fam, nullptr, 0));
     coot_tune_space(fam, space.data(), (uint32_t)space.size());
@@ -518,8 +513,13 @@ coot_status coot_tune(coot_expr* h, const coot_operand* operands, const double* 
     if (policy == 0) {
       int64_t R, C;
       infer_shape(*h->e, operands, &R, &C);
-      coot_launch_cfg d = default_cfg(fam == 0 ? FAM_FLAT : FAM_TILE, mode, -1, h->e->dtype, R * C);
+      coot_launch_cfg d = default_cfg(fam == 0 ? FAM_FLAT : FAM_TILE, mode, is_dim_kind(mode) ? dim : -1, h->e->dtype,
+                                      R * C);
       if (!d.ept) d.ept = 1;  // the tiled family's configurations carry ept 1
+      if (fam == 1 && !d.tile_r) {  // the library's tile: 64 x 64, or 32 x 32 when the staging does not fit
+        d.tile_r = d.tile_c = tile_lds_bytes(h->e->n_p1, h->e->dtype, 64, 64) > kTileLdsMax ? 32 : 64;
+        if (d.vec > tile_vec_cap(d.tile_r, d.tile_c)) d.vec = (uint16_t)tile_vec_cap(d.tile_r, d.tile_c);
+      }
       cand.push_back(d);
     } else if (policy == 1) {
       cand = space;
@@ -528,11 +528,12 @@ coot_status coot_tune(coot_expr* h, const coot_operand* operands, const double* 
           if (c.vec == 4) cand.push_back({8, c.ept, c.waves, c.grid_mult, c.tile_r, c.tile_c});
     } else if (policy == 2) {
       if (!cm) fail(COOT_EINVAL, "the MLP policy needs a cost model");
+      if (is_dim_kind(mode)) fail(COOT_EUNSUPPORTED, "the cost model covers element-wise evaluation and accu");
       int64_t R, C;
       infer_shape(*h->e, operands, &R, &C);
       // rank only the configurations these operands allow (alignment, tile)
       std::vector<int32_t> ok(space.size());
-      st = coot_tune_runnable(h, operands, out, mode, space.data(), (uint32_t)space.size(), ok.data());
+      st = coot_tune_runnable(h, operands, out, mode, dim, space.data(), (uint32_t)space.size(), ok.data());
       if (st != COOT_OK) fail(st, last_error());
       std::vector<coot_launch_cfg> live;
       for (size_t i = 0; i < space.size(); ++i)
@@ -546,7 +547,8 @@ coot_status coot_tune(coot_expr* h, const coot_operand* operands, const double* 
       fail(COOT_EINVAL, "policy must be 0, 1 or 2");
     }
     std::vector<float> t(cand.size());
-    st = coot_tune_table(h, operands, scalars, out, mode, cand.data(), (uint32_t)cand.size(), 5, 0, t.data(), stream);
+    st = coot_tune_table(h, operands, scalars, out, mode, dim, cand.data(), (uint32_t)cand.size(), 5, 0, t.data(),
+                         stream);
     if (st != COOT_OK) fail(st, last_error());
     size_t bi = 0;
     for (size_t i = 0; i < t.size(); ++i)
@@ -564,7 +566,7 @@ coot_status coot_tune(coot_expr* h, const coot_operand* operands, const double* 
         std::vector<coot_launch_cfg> fc;
         for (size_t i : fin) fc.push_back(cand[i]);
         std::vector<float> ft(fc.size());
-        st = coot_tune_table(h, operands, scalars, out, mode, fc.data(), (uint32_t)fc.size(), 21, 0, ft.data(),
+        st = coot_tune_table(h, operands, scalars, out, mode, dim, fc.data(), (uint32_t)fc.size(), 21, 0, ft.data(),
                              stream);
         if (st != COOT_OK) fail(st, last_error());
         size_t fb = 0;

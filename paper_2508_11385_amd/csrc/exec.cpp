@@ -413,6 +413,29 @@ void eval_reduce(Expr& e, const coot_operand* ops, const double* scalars, const 
   launch(m->fn(m->names.stage2), 1, 256, a, s);
 }
 
+DimPlan dim_plan(int64_t R, int64_t C, int dim, int tile_r, int tile_c, int per_cu, size_t cs) {
+  DimPlan p;
+  const int64_t tr = (R + tile_r - 1) / tile_r, tc = (C + tile_c - 1) / tile_c;
+  // segments of K tiles along the reduced dimension, K growing once there are more
+  // than per_cu tiles per CU (at most 16): fewer partials, fewer lane combines
+  const int64_t nred = dim == 0 ? tr : tc, nkeep = dim == 0 ? tc : tr;
+  const int64_t K =
+      std::max<int64_t>(1, std::min<int64_t>({16, nred, (nred * nkeep) / ((int64_t)std::max(1, per_cu) * num_cus())}));
+  p.n_out = dim == 0 ? C : R;
+  p.n_part = std::max<int64_t>(1, (nred + K - 1) / K);
+  p.nseg = nkeep * p.n_part;
+  p.part_bytes = (size_t)std::max<int64_t>(1, p.n_part * p.n_out) * 2 * cs;
+  return p;
+}
+
+void launch_dim(hipFunction_t stage1, hipFunction_t stage2, KArgs& a, const DimPlan& p, hipStream_t s) {
+  a.n_part = p.n_part;
+  const unsigned g1 = (unsigned)std::min<int64_t>(p.nseg, 1 << 30);
+  const unsigned g2 = (unsigned)std::max<int64_t>(1, std::min<int64_t>((p.n_out + 3) / 4, 65536));
+  if (p.nseg > 0) launch(stage1, g1, 256, a, s);
+  launch(stage2, g2, 256, a, s);
+}
+
 void check_red_mode(const Expr& e, int mode) {
   if (mode < COOT_RED_ACCU || mode > COOT_RED_VAR_DIM) fail(COOT_EINVAL, "unknown reduction");
   if (mode == COOT_RED_DOT && !e.root_schur) fail(COOT_EINVAL, "dot needs an expression whose root is a % b");
@@ -452,6 +475,7 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
   const bool by_n = (flags & COOT_RF_VAR_N) != 0;
   Request rq = plan(e, ops, nullptr, mode, dimk ? dim : -1, comp, cfg);
   auto m = get_module(e, rq, true);
+  auto part_buf = [&](size_t bytes, int which) -> void* { return workspace(bytes, s, which); };
   KArgs a;
   fill_args(e, ops, scalars, &a);
   a.out = out.data;
@@ -464,20 +488,10 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
   const size_t cs = dtype_is_half(e.dtype) ? 4 : dtype_size(e.dtype);
   const coot_launch_cfg c = resolve_cfg(cfg, rq.fam, mode, dimk ? dim : -1, e.dtype, R * C);
   if (dimk) {
-    const int64_t tr = (R + rq.var.tr - 1) / rq.var.tr, tc = (C + rq.var.tc - 1) / rq.var.tc;
-    // segments of K tiles along the reduced dimension, K growing once there are
-    // more than 8 tiles per CU (at most 16): fewer partials, fewer lane combines
-    const int64_t nred = dim == 0 ? tr : tc, nkeep = dim == 0 ? tc : tr;
-    const int64_t K = std::max<int64_t>(1, std::min<int64_t>({16, nred, (nred * nkeep) / (8 * (int64_t)num_cus())}));
-    a.n_part = std::max<int64_t>(1, (nred + K - 1) / K);
-    const size_t part_bytes = (size_t)std::max<int64_t>(1, a.n_part * n_out) * 2 * cs;
-    a.ws = workspace(part_bytes, s, 0);
-    if (var) a.ws2 = workspace(part_bytes, s, 1);  // a variance: sum d^2 in ws, sum d in ws2
-    const int64_t nseg = nkeep * a.n_part;
-    const unsigned g1 = (unsigned)std::min<int64_t>(nseg, 1 << 30);
-    const unsigned g2 = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_out + 3) / 4, 65536));
-    if (nseg > 0) launch(m->fn(kn), g1, 256, a, s);
-    launch(m->fn(var && by_n ? m->names.stage2_dev_n : m->names.stage2), g2, 256, a, s);
+    const DimPlan dp = dim_plan(R, C, dim, rq.var.tr, rq.var.tc, c.grid_mult, cs);
+    a.ws = part_buf(dp.part_bytes, 0);
+    if (var) a.ws2 = part_buf(dp.part_bytes, 1);  // a variance: sum d^2 in ws, sum d in ws2
+    launch_dim(m->fn(kn), m->fn(var && by_n ? m->names.stage2_dev_n : m->names.stage2), a, dp, s);
     return;
   }
   unsigned grid;
@@ -490,8 +504,8 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
     grid = tile_grid(R, C, rq.var.tr, rq.var.tc, c.grid_mult);
   }
   a.n_part = grid;
-  a.ws = workspace((size_t)grid * 32, s, 0);
-  a.ws2 = workspace(64 + (size_t)grid * 32, s, 1);
+  a.ws = part_buf((size_t)grid * 32, 0);
+  a.ws2 = part_buf(64 + (size_t)grid * 32, 1);
   launch(m->fn(kn), grid, block, a, s);
   // a variance's stage 2 merges the records' (count, mean, M2) and divides by N - 1 or N
   launch(m->fn(var && by_n ? m->names.stage2_dev_n : m->names.stage2), 1, 256, a, s);

@@ -182,6 +182,17 @@ std::shared_ptr<Module> get_module(Expr& e, const Request& rq, bool load) {
   return module_for(e, rk, src, names, load);
 }
 
+// Module key of a generated source: the source, the hipRTC options and version, the
+// device headers.
+static std::string module_key(const std::string& src) {
+  std::string opt_text;
+  for (auto& o : rtc_options()) opt_text += o + " ";
+  if (const char* extra = std::getenv("COOT_HIPRTC_EXTRA")) opt_text += std::string("extra:") + extra;
+  std::string hdr_text;
+  for (auto& h : device_headers()) hdr_text += h.second;
+  return hex128(src + "\n" + opt_text + rtc_version() + hex128(hdr_text));
+}
+
 std::shared_ptr<Module> get_module_pair(Expr& e, const Expr& r, const std::vector<int>& r_src, int kind,
                                         const Request& rq, bool load) {
   std::string rk = "pair:" + rq.key() + "|" + r.canon + "|" + std::to_string(kind) + "|";
@@ -198,12 +209,7 @@ std::shared_ptr<Module> get_module_pair(Expr& e, const Expr& r, const std::vecto
 
 static std::shared_ptr<Module> module_for(Expr& e, const std::string& rk, const std::string& src,
                                           const KernelNames& names, bool load) {
-  std::string opt_text;
-  for (auto& o : rtc_options()) opt_text += o + " ";
-  if (const char* extra = std::getenv("COOT_HIPRTC_EXTRA")) opt_text += std::string("extra:") + extra;
-  std::string hdr_text;
-  for (auto& h : device_headers()) hdr_text += h.second;
-  const std::string key = hex128(src + "\n" + opt_text + rtc_version() + hex128(hdr_text));
+  const std::string key = module_key(src);
   std::shared_ptr<Module> m;
   {
     std::lock_guard<std::mutex> g(global_mutex());

@@ -28,22 +28,29 @@ constexpr size_t kFlushBytes = 512u << 20;
 unsigned g_flush_value = 1;  // what each flush folds its reads with (any value; it varies)
 constexpr float kSampleUs = 40.0f;  // a timing sample spans at least this many microseconds
 
-bool tune_mode_ok(int mode) { return mode == -1 || mode == COOT_RED_ACCU; }
+bool tune_mode_ok(int mode, int dim) {
+  if (mode == -1 || mode == COOT_RED_ACCU) return true;
+  return is_dim_kind(mode) && (dim == 0 || dim == 1);
+}
 
 struct Prepared {
   Request rq;
   std::shared_ptr<Module> m;
   int64_t R = 0, C = 0;
+  int dim = -1;  // reductions along a dimension: 0 or 1
 };
 
-Prepared prepare(Expr& e, const coot_operand* ops, const coot_operand* out, int mode, bool load) {
-  if (!tune_mode_ok(mode)) fail(COOT_EUNSUPPORTED, "tuning covers element-wise evaluation and accu");
+Prepared prepare(Expr& e, const coot_operand* ops, const coot_operand* out, int mode, int dim, bool load) {
+  if (!tune_mode_ok(mode, dim))
+    fail(COOT_EUNSUPPORTED, "tuning covers element-wise evaluation, accu, and sum / mean / var along dim 0 or 1");
+  if (mode >= 0) check_red_mode(e, mode);
   Prepared p;
   check_operands(e, ops);
   infer_shape(e, ops, &p.R, &p.C);
   int m = mode;
   if (mode == COOT_RED_ACCU && e.root_schur) m = COOT_RED_DOT;
-  p.rq = plan(e, ops, mode < 0 ? out : nullptr, m, -1, true, nullptr);
+  p.dim = is_dim_kind(mode) ? dim : -1;
+  p.rq = plan(e, ops, mode < 0 ? out : nullptr, m, p.dim, true, nullptr);
   p.rq.all_variants = true;
   p.rq.var.vec = 4;
   p.rq.var.ept = p.rq.fam == FAM_FLAT ? 4 : 0;
@@ -98,7 +105,16 @@ bool launch_cfg(Expr& e, Prepared& p, const coot_launch_cfg& c, const coot_opera
     block = 256;
     grid = tile_grid(p.R, p.C, rq.var.tr, rq.var.tc, c.grid_mult);
   }
-  if (rq.mode < 0) {
+  if (p.dim >= 0) {
+    // along a dimension: grid_mult is the number of tiles per CU past which segments grow
+    const size_t cs = dtype_is_half(e.dtype) ? 4 : dtype_size(e.dtype);
+    const DimPlan dp = dim_plan(p.R, p.C, p.dim, rq.var.tr, rq.var.tc, c.grid_mult, cs);
+    a.out = out->data;
+    a.out_ld = ld_of(*out);
+    a.ws = workspace(dp.part_bytes, s, 2);
+    if (rq.mode == COOT_RED_VAR_DIM) a.ws2 = workspace(dp.part_bytes, s, 3);
+    launch_dim(f, p.m->fn(p.m->names.stage2), a, dp, s);
+  } else if (rq.mode < 0) {
     a.out = out->data;
     a.out_ld = ld_of(*out);
     launch(f, grid, block, a, s);
@@ -140,19 +156,21 @@ uint32_t coot_tune_space(int32_t family, coot_launch_cfg* cfgs, uint32_t cap) {
   return (uint32_t)v.size();
 }
 
-coot_status coot_tune_prepare(coot_expr* h, const coot_operand* operands, int32_t mode, int32_t* family) {
+coot_status coot_tune_prepare(coot_expr* h, const coot_operand* operands, int32_t mode, int32_t dim,
+                              int32_t* family) {
   return guarded([&] {
     if (!h) fail(COOT_EINVAL, "NULL expression");
-    Prepared p = prepare(*h->e, operands, nullptr, mode, false);
+    Prepared p = prepare(*h->e, operands, nullptr, mode, dim, false);
     if (family) *family = p.rq.fam == FAM_FLAT ? 0 : 1;
   });
 }
 
 coot_status coot_tune_runnable(coot_expr* h, const coot_operand* operands, const coot_operand* out, int32_t mode,
+                               int32_t dim,
                                const coot_launch_cfg* cfgs, uint32_t n_cfgs, int32_t* runnable) {
   return guarded([&] {
     if (!h || (n_cfgs && (!cfgs || !runnable)) || (mode < 0 && !out)) fail(COOT_EINVAL, "NULL argument");
-    Prepared p = prepare(*h->e, operands, nullptr, mode, false);
+    Prepared p = prepare(*h->e, operands, nullptr, mode, dim, false);
     for (uint32_t k = 0; k < n_cfgs; ++k) {
       if (!valid_cfg(cfgs[k])) fail(COOT_EINVAL, "invalid launch configuration");
       runnable[k] = cfg_runnable(*h->e, p, cfgs[k], operands, mode < 0 ? out : nullptr) ? 1 : 0;
@@ -169,7 +187,8 @@ coot_status coot_flush_caches(void* stream) {
 }
 
 coot_status coot_tune_table(coot_expr* h, const coot_operand* operands, const double* scalars, coot_operand* out,
-                            int32_t mode, const coot_launch_cfg* cfgs, uint32_t n_cfgs, uint32_t reps, int32_t flush,
+                            int32_t mode, int32_t dim, const coot_launch_cfg* cfgs, uint32_t n_cfgs, uint32_t reps,
+                            int32_t flush,
                             float* times_us, void* stream) {
   return guarded([&] {
     if (!h || !out || (n_cfgs && (!cfgs || !times_us))) fail(COOT_EINVAL, "NULL argument");
@@ -181,10 +200,18 @@ coot_status coot_tune_table(coot_expr* h, const coot_operand* operands, const do
       check_operands(e, operands);
       infer_shape(e, operands, &R, &C);
       if (out->n_rows != R || out->n_cols != C || out->dtype != e.dtype) fail(COOT_ESHAPE, "output shape");
+    } else if (is_dim_kind(mode)) {
+      int64_t R, C;
+      check_operands(e, operands);
+      infer_shape(e, operands, &R, &C);
+      const bool ok = dim == 0 ? (out->n_rows == 1 && out->n_cols == C) : (out->n_rows == R && out->n_cols == 1);
+      if (!ok || out->dtype != e.dtype) fail(COOT_ESHAPE, "a reduction along dim 0 writes 1 x n_cols, along dim 1 n_rows x 1");
+      if (out->n_rows * out->n_cols > 1 && !(ld_of(*out) == out->n_rows || out->n_cols <= 1))
+        fail(COOT_EINVAL, "reduction output must be contiguous");
     } else if (out->n_rows * out->n_cols != 1 || out->dtype != e.dtype) {
       fail(COOT_ESHAPE, "accu writes one element");
     }
-    Prepared p = prepare(e, operands, out, mode, true);
+    Prepared p = prepare(e, operands, out, mode, dim, true);
     void* fbuf = flush ? workspace(kFlushBytes, s, 4) : nullptr;
     hipEvent_t e0, e1;
     hip_check(hipEventCreate(&e0), "hipEventCreate");
@@ -236,11 +263,11 @@ coot_status coot_tune_table(coot_expr* h, const coot_operand* operands, const do
 
 // Launch with an explicit configuration through the tuning module (no extra compile).
 coot_status coot_tune_launch(coot_expr* h, const coot_operand* operands, const double* scalars, coot_operand* out,
-                             int32_t mode, const coot_launch_cfg* cfg, void* stream) {
+                             int32_t mode, int32_t dim, const coot_launch_cfg* cfg, void* stream) {
   return guarded([&] {
     if (!h || !out || !cfg) fail(COOT_EINVAL, "NULL argument");
     if (!valid_cfg(*cfg)) fail(COOT_EINVAL, "invalid launch configuration");
-    Prepared p = prepare(*h->e, operands, out, mode, true);
+    Prepared p = prepare(*h->e, operands, out, mode, dim, true);
     if (!launch_cfg(*h->e, p, *cfg, operands, scalars, out, (hipStream_t)stream))
       fail(COOT_EINVAL, "configuration not valid for these operands");
   });

@@ -495,7 +495,7 @@ _RED_KIND = {"accu": cc.COOT_RED_ACCU, "dot": cc.COOT_RED_DOT, "min": cc.COOT_RE
 
 class _Pair:
     """Cached call state of a statement pair (see eval_reduce)."""
-    __slots__ = ("e", "r", "out", "res", "he", "hr", "ops", "sc", "out_op", "src", "rsc", "res_op", "cfg")
+    __slots__ = ("r", "out", "res", "he", "hr", "ops", "sc", "out_op", "src", "rsc", "res_op", "cfg")
 
 
 def eval_reduce(e: Expr, out: Mat, r: Expr, kind: str = "accu", cfg=None, res: Mat | None = None) -> Mat:
@@ -527,7 +527,7 @@ def eval_reduce(e: Expr, out: Mat, r: Expr, kind: str = "accu", cfg=None, res: M
         if len(cache) >= 8:
             cache.clear()
         p = _Pair()
-        p.e, p.r, p.out = e, r, out
+        p.r, p.out = r, out                     # (not e: e holds this cache; no reference cycle)
         p.he, p.hr = compiled(fe), compiled(fr)
         p.ops = cc._arr(cc.coot_operand, [m.operand() for m in fe.mats])
         p.sc = cc._arr(cc.C.c_double, fe.scalars)

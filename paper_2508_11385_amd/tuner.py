@@ -136,15 +136,19 @@ def default_index(cfgs, dtype, t=None, n=0, mode=-1):
     element-wise, else a full reduction): the default configuration, or, when the operands
     do not allow its vector width (t[k] NaN), the same with scalar accesses."""
     v = 2 if dtype == "f64" else 4
-    if len(cfgs) <= 12:
-        want = (2, 1, 4, 8)
+    if cfgs[0][4]:                                  # tiled family: (vec, 1, 4, per CU, tile rows, tile cols)
+        want = (2, 1, 4, 8, 64, 64)
     elif n > STREAM_ELEMS:
-        want = (v, 1, 4, 2) if mode < 0 else ((2, 4, 8, 8) if dtype == "f64" else (4, 4, 4, 2))
+        want = (v, 1, 4, 2, 0, 0) if mode < 0 else ((2, 4, 8, 8, 0, 0) if dtype == "f64" else (4, 4, 4, 2, 0, 0))
     else:
-        want = (v, 1, 4, 4)
+        want = (v, 1, 4, 4, 0, 0)
     k = cfgs.index(want)
     if t is not None and not np.isfinite(t[k]):
         k = cfgs.index((1,) + want[1:])
+        if cfgs[0][4] and not np.isfinite(t[k]):    # 64 x 64 staging beyond LDS: the library takes 32 x 32
+            k = cfgs.index((2, 1, 4, 8, 32, 32))
+            if not np.isfinite(t[k]):
+                k = cfgs.index((1, 1, 4, 8, 32, 32))
     return k
 
 

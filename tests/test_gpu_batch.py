@@ -66,7 +66,8 @@ def test_batch_matches_oracle_and_fused(coot, dtype):
     _check_against_oracle(specs, host, b.outs, dtype)
     for e, out in zip(exprs[:40], b.outs[:40]):
         single = coot.eval(e).numpy()
-        assert np.array_equal(single.view(np.uint8), out.numpy().view(np.uint8))   # bitwise, signed zeros too
+        assert np.array_equal(np.ascontiguousarray(single).view(np.uint8),
+                              np.ascontiguousarray(out.numpy()).view(np.uint8))   # bitwise, signed zeros too
     info = b.info()
     assert info["n_exprs"] == 120 and info["n_tiles"] > 120
 

@@ -4,6 +4,7 @@ Tolerances: integers bit-exact; floating element-wise results within 1 ulp of
 the per-operator rounded oracle (0 ulp expected for + - * / sqrt abs neg, trans);
 fp32 reductions within 1e-6 relative error of the exact sum, fp64 within 1e-12.
 """
+import gc
 import math
 
 import numpy as np
@@ -364,6 +365,7 @@ def test_caller_allocator_for_workspaces_and_temporaries(coot):
         return s0.numpy(), u.numpy()
 
     ref = run()
+    gc.collect()                                 # nothing of earlier tests is freed while measuring
     torch.cuda.synchronize()
     base = torch.cuda.memory_allocated()
     coot.use_torch_allocator(True)
@@ -389,10 +391,17 @@ def test_tile_shapes(coot, dtype, tile):
     """Every tile shape of the tiled kernels, through element-wise evaluation, full and
     dimension reductions, on a ragged shape (partial tiles on both edges) and an aligned
     one with 4-element groups: Z 0 ulp, sums within the reduction tolerance, max exact."""
+    import paper_2508_11385_amd._coot as cc
     for (r, c), vec in (((300, 170), 1), ((512, 256), 4 if dtype == "f32" else 2)):
         cfg = (vec, 0, 0, 0) + tile
         A, B, C, D = synth.matrix_inputs(n_rows=r, n_cols=c, dtype=dtype)
         gA, gB, gC, gD = (up(coot, x) for x in (A, B, C, D))
+        if tile[0] * (tile[1] + 1) * (8 if dtype == "f64" else 4) > 65536:
+            # the staged transposed leaf of D does not fit 64 KiB of LDS: refused, nothing launched
+            with pytest.raises(cc.CootError) as ei:
+                coot.eval(_z(coot, gA, gB, gC, gD), cfg=cfg)
+            assert ei.value.status == cc.COOT_EINVAL and "64 KiB" in str(ei.value)
+            continue
         Zo = ew.evaluate(Z_POST, [A, B, C, D], [2.0], dtype)
         Z = coot.eval(_z(coot, gA, gB, gC, gD), cfg=cfg).numpy()
         assert np.max(ulp_distance(Z, Zo)) == 0, (tile, r, c)

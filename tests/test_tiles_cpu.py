@@ -93,3 +93,27 @@ def test_tile_arguments_are_checked(cc):
     assert e.value.status == cc.COOT_EINVAL
     cc.coot_expr_release(h)
     cc.coot_expr_release(h5)
+
+
+@pytest.mark.parametrize("dt", ["u32", "s32", "f32", "f64"])
+def test_tuner_default_index_names_the_library_default(cc, dt):
+    """The tuner's stand-in for "no tuner" is an entry of each family's configuration
+    space (six fields: vec, ept, waves, workgroups per CU, tile rows, tile columns), with
+    the library's fallbacks where the operands rule the default out (NaN times)."""
+    import numpy as np
+    from paper_2508_11385_amd import tuner
+    v = 2 if dt == "f64" else 4
+    flat, tiled = cc.coot_tune_space(0), cc.coot_tune_space(1)
+    assert all(len(c) == 6 for c in flat + tiled)
+    assert flat[tuner.default_index(flat, dt, None, 1000, -1)] == (v, 1, 4, 4, 0, 0)
+    assert flat[tuner.default_index(flat, dt, None, 1 << 25, -1)] == (v, 1, 4, 2, 0, 0)
+    big_red = (2, 4, 8, 8, 0, 0) if dt == "f64" else (4, 4, 4, 2, 0, 0)
+    assert flat[tuner.default_index(flat, dt, None, 1 << 25, 0)] == big_red
+    assert tiled[tuner.default_index(tiled, dt, None, 1000, -1)] == (2, 1, 4, 8, 64, 64)
+    t = np.ones(len(tiled))
+    for c in ((2, 1, 4, 8, 64, 64), (1, 1, 4, 8, 64, 64)):
+        t[tiled.index(c)] = np.nan              # 64 x 64 staging beyond LDS
+    assert tiled[tuner.default_index(tiled, dt, t, 1000, -1)] == (2, 1, 4, 8, 32, 32)
+    t = np.ones(len(flat))
+    t[flat.index((v, 1, 4, 4, 0, 0))] = np.nan   # misaligned operands: scalar accesses
+    assert flat[tuner.default_index(flat, dt, t, 1000, -1)] == (1, 1, 4, 4, 0, 0)
