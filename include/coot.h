@@ -265,6 +265,29 @@ coot_status coot_reduce(coot_expr* e, const coot_operand* operands, const double
                         int32_t kind, int32_t dim, uint32_t flags, coot_operand* out,
                         const coot_launch_cfg* cfg, void* stream);
 
+/* coot_reduce for callers that cannot allocate device memory: code recorded into a
+ * HIP graph (stream capture), tight serving loops, harnesses that forbid hipMalloc.
+ * Arguments, results and errors are those of coot_reduce, computed by the same
+ * kernels, bit for bit.  The partial results live in a file-scope device array of
+ * COOT_NOALLOC_SCRATCH_BYTES (16 MiB) that every device the library runs on holds
+ * until the process ends (its address is looked up by coot_init, else by the first
+ * call on a device).  The call allocates nothing, compiles nothing and loads nothing:
+ *   - the reduction's kernels must be loaded already: run coot_expr_prepare (same
+ *     kind, dim and flags) or one coot_reduce with the same expression, kind and
+ *     operand layout first; otherwise COOT_EINVAL;
+ *   - the partials must fit in half of the array each (full reductions always do;
+ *     along a dimension about 2 * n_outputs * n_segments elements of the compute
+ *     type): COOT_EUNSUPPORTED otherwise, with nothing launched;
+ *   - the unfused comparator (COOT_CF_UNFUSED) is refused with COOT_EUNSUPPORTED.
+ * A capturing stream is accepted.  Every call on one device shares that device's
+ * array and each call's kernels start by writing what they later read, so calls
+ * ordered on one stream are safe; calls that overlap in time on one device (other
+ * streams, host threads, graph replays) race on the array and give wrong results. */
+#define COOT_NOALLOC_SCRATCH_BYTES (16u << 20)
+coot_status coot_reduce_noalloc(coot_expr* e, const coot_operand* operands, const double* scalars,
+                                int32_t kind, int32_t dim, uint32_t flags, coot_operand* out,
+                                const coot_launch_cfg* cfg, void* stream);
+
 /* Two statements in one pass (multi-statement fusion): evaluate e into out and
  * close the expression r with a full reduction into r_out, reading every operand
  * once and writing out once (y = 2.5*x + y; d = accu(x % y) moves 12 bytes per

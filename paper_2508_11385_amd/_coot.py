@@ -83,6 +83,8 @@ _sig = {
                                  C.POINTER(coot_launch_cfg), _P]),
     "coot_reduce": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(C.c_double), C.c_int32, C.c_int32,
                               C.c_uint32, C.POINTER(coot_operand), C.POINTER(coot_launch_cfg), _P]),
+    "coot_reduce_noalloc": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(C.c_double), C.c_int32, C.c_int32,
+                                      C.c_uint32, C.POINTER(coot_operand), C.POINTER(coot_launch_cfg), _P]),
     "coot_flush_caches": (C.c_int, [_P]),
     "coot_expr_eval_reduce": (C.c_int, [_P, C.POINTER(coot_operand), C.POINTER(C.c_double), C.POINTER(coot_operand),
                                         _P, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int32,
@@ -227,6 +229,13 @@ def coot_reduce(h: int, operands, scalars, kind: int, dim: int, flags: int, out:
     ops = _arr(coot_operand, operands)
     sc = _arr(C.c_double, scalars)
     _check(lib.coot_reduce(h, ops, sc, kind, dim, flags, C.byref(out), _cfg(cfg), stream))
+
+
+def coot_reduce_noalloc(h: int, operands, scalars, kind: int, dim: int, flags: int, out: coot_operand, cfg=None,
+                        stream: int = 0) -> None:
+    ops = _arr(coot_operand, operands)
+    sc = _arr(C.c_double, scalars)
+    _check(lib.coot_reduce_noalloc(h, ops, sc, kind, dim, flags, C.byref(out), _cfg(cfg), stream))
 
 
 def coot_flush_caches(stream: int = 0) -> None:

@@ -22,6 +22,7 @@ coot_status coot_init(int hip_device) {
     if (hip_device < 0 || hip_device >= n) fail(COOT_EINVAL, "device index out of range");
     hip_check(hipSetDevice(hip_device), "hipSetDevice");
     (void)num_cus();
+    (void)noalloc_scratch();  // this device's address of the allocation-free scratch array
   });
 }
 
@@ -146,6 +147,21 @@ coot_status coot_reduce(coot_expr* h, const coot_operand* operands, const double
       throw;
     }
     temp_free(t.data, bytes, s);
+  });
+}
+
+coot_status coot_reduce_noalloc(coot_expr* h, const coot_operand* operands, const double* scalars, int32_t kind,
+                                int32_t dim, uint32_t flags, coot_operand* out, const coot_launch_cfg* cfg,
+                                void* stream) {
+  return guarded([&] {
+    if (!h || !out) fail(COOT_EINVAL, "NULL argument");
+    if (flags & ~(COOT_RF_PLAIN | COOT_RF_VAR_N)) fail(COOT_EINVAL, "unknown reduce flag");
+    if (h->e->flags & COOT_CF_UNFUSED)
+      fail(COOT_EUNSUPPORTED, "the unfused comparator allocates temporaries; use coot_reduce");
+    Scratch sc;
+    sc.p = noalloc_scratch();
+    sc.bytes = kNoallocScratchBytes;
+    reduce_fused(*h->e, operands, scalars, kind, dim, flags, *out, cfg, (hipStream_t)stream, &sc);
   });
 }
 

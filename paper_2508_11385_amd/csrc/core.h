@@ -150,6 +150,9 @@ struct Module {
 // Compile (or fetch) the module for a request; load it on the current device
 // unless load == false (compile-only, used where no device exists).
 std::shared_ptr<Module> get_module(Expr& e, const Request& rq, bool load);
+// The module of a request only if it is loaded on a device already (this expression's
+// cache, then the process-wide one); COOT_EINVAL otherwise.  Never compiles or loads.
+std::shared_ptr<Module> find_loaded_module(Expr& e, const Request& rq);
 std::shared_ptr<Module> get_module_pair(Expr& e, const Expr& r, const std::vector<int>& r_src, int kind,
                                         const Request& rq, bool load);
 std::string compile_source(const std::string& src, const std::string& name_hint, std::vector<char>* code);
@@ -203,8 +206,20 @@ struct DimPlan {
 DimPlan dim_plan(int64_t R, int64_t C, int dim, int tile_r, int tile_c, int per_cu, size_t cs);
 // Stage 1 over p.nseg workgroups (none when empty), then stage 2, one wavefront per output.
 void launch_dim(hipFunction_t stage1, hipFunction_t stage2, KArgs& a, const DimPlan& p, hipStream_t s);
+// Partial-result buffers of a reduction given by the caller (the allocation-free entry
+// point): two halves of `bytes` / 2, the first in place of workspace 0, the second of
+// workspace 1.  With one, reduce_fused allocates nothing and compiles nothing (the
+// kernels must be loaded already: COOT_EINVAL otherwise).
+struct Scratch {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
 void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int kind, int dim, uint32_t flags,
-                  const coot_operand& out, const coot_launch_cfg* cfg, hipStream_t s);
+                  const coot_operand& out, const coot_launch_cfg* cfg, hipStream_t s, const Scratch* sc = nullptr);
+// The device scratch array of coot_reduce_noalloc: kNoallocScratchBytes on every
+// device the library runs on, its address looked up once per device (current device).
+constexpr size_t kNoallocScratchBytes = COOT_NOALLOC_SCRATCH_BYTES;
+void* noalloc_scratch();
 // The library's launch configuration for a family when the caller gives none
 // (fields 0 there are filled from it); waves and ept are 0/unused where fixed.
 constexpr int64_t kStreamElems = int64_t(1) << 24;  // larger flat launches take the streaming defaults

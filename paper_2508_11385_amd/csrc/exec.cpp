@@ -446,7 +446,7 @@ void check_red_mode(const Expr& e, int mode) {
 }
 
 void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int kind, int dim, uint32_t flags,
-                  const coot_operand& out, const coot_launch_cfg* cfg, hipStream_t s) {
+                  const coot_operand& out, const coot_launch_cfg* cfg, hipStream_t s, const Scratch* sc) {
   check_operands(e, ops);
   int64_t R = 0, C = 0;
   infer_shape(e, ops, &R, &C);
@@ -474,8 +474,16 @@ void reduce_fused(Expr& e, const coot_operand* ops, const double* scalars, int k
   const bool comp = !(flags & COOT_RF_PLAIN);
   const bool by_n = (flags & COOT_RF_VAR_N) != 0;
   Request rq = plan(e, ops, nullptr, mode, dimk ? dim : -1, comp, cfg);
-  auto m = get_module(e, rq, true);
-  auto part_buf = [&](size_t bytes, int which) -> void* { return workspace(bytes, s, which); };
+  auto m = sc ? find_loaded_module(e, rq) : get_module(e, rq, true);
+  // partial results: the library's per-stream workspaces, or the halves of the caller's scratch
+  auto part_buf = [&](size_t bytes, int which) -> void* {
+    if (!sc) return workspace(bytes, s, which);
+    const size_t half = sc->bytes / 2;
+    if (bytes > half)
+      fail(COOT_EUNSUPPORTED, "the reduction needs " + std::to_string(bytes) + " bytes of partial results; the " +
+                                  "allocation-free scratch holds " + std::to_string(half) + " per buffer");
+    return (char*)sc->p + (size_t)which * half;
+  };
   KArgs a;
   fill_args(e, ops, scalars, &a);
   a.out = out.data;

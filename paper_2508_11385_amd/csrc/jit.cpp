@@ -193,6 +193,29 @@ static std::string module_key(const std::string& src) {
   return hex128(src + "\n" + opt_text + rtc_version() + hex128(hdr_text));
 }
 
+std::shared_ptr<Module> find_loaded_module(Expr& e, const Request& rq) {
+  const std::string rk = rq.key();
+  {
+    std::lock_guard<std::mutex> g(e.mu);
+    auto it = e.reqs.find(rk);
+    if (it != e.reqs.end() && it->second->loaded) return it->second;
+  }
+  KernelNames names;
+  const std::string key = module_key(generate(e, rq, hex128(e.canon), &names));
+  std::shared_ptr<Module> m;
+  {
+    std::lock_guard<std::mutex> g(global_mutex());
+    auto it = module_map().find(key);
+    if (it != module_map().end() && it->second->loaded) m = it->second;
+  }
+  if (!m)
+    fail(COOT_EINVAL, "the kernels of this reduction are not loaded: run coot_expr_prepare or coot_reduce "
+                      "with the same expression, kind and operand layout once first");
+  std::lock_guard<std::mutex> g2(e.mu);
+  e.reqs[rk] = m;
+  return m;
+}
+
 std::shared_ptr<Module> get_module_pair(Expr& e, const Expr& r, const std::vector<int>& r_src, int kind,
                                         const Request& rq, bool load) {
   std::string rk = "pair:" + rq.key() + "|" + r.canon + "|" + std::to_string(kind) + "|";
