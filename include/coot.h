@@ -335,10 +335,12 @@ coot_status coot_expr_kernel_name(coot_expr* e, int32_t mode, int32_t dim, const
  *   outs[n]             caller-allocated device outputs with the inferred dims
  *   cfg                 NULL = default (flat chunks and 2-D tiles of 32 x 32
  *                       elements, vectorised where aligned, 16 workgroups per
- *                       CU); else waves 1 / 4
- *                       selects tiles of 16 x 16 / 32 x 32 elements (4 per thread),
- *                       vec = 1 forbids 128-bit accesses, grid_mult sets
- *                       workgroups per CU, all for both parts.  Expressions with
+ *                       CU); else, for both parts: tile_r = tile_c = 16 or 32 the
+ *                       tile edge and waves the wavefronts per tile (16 x 16: 1;
+ *                       32 x 32: 4, 2 or 1, i.e. 4, 8 or 16 elements per thread);
+ *                       without a tile, waves 1 / 2 / 4 select 16 x 16 by one wave,
+ *                       32 x 32 by two, 32 x 32 by four; vec = 1 forbids 128-bit
+ *                       accesses; grid_mult sets workgroups per CU.  Expressions with
  *                       untransposed contiguous leaves are cut into flat chunks of
  *                       the same element count and run in a launch of their own
  *                       (the flat part); the others in 2-D tiles (the 2-D part).
@@ -363,8 +365,10 @@ coot_status coot_batch_launch_each(coot_batch* b, void* stream);
 
 /* Autotune the batch launch on `stream` (synchronises it).  The flat-chunk part
  * and the 2-D-tile part of the batch are tuned separately, each on its own
- * launch: every tile size (16, 32), grid multiplier (2, 4, 8, 16) and vector
- * width (128-bit where aligned, or scalar), median of 5 launches each; the
+ * launch: every tile shape (16 x 16 by one wavefront; 32 x 32 by four, two or
+ * one wavefront(s), i.e. 4, 8 or 16 elements per thread), grid multiplier
+ * (2, 4, 8, 16) and vector width (128-bit where aligned, or scalar), median of 5
+ * launches each; the
  * fastest of each part is kept.  Then the whole graph is timed with the parts
  * side by side and one after the other, and the faster is captured.  best (may
  * be NULL) receives the flat part's settings (coot_batch_info reports both
@@ -377,8 +381,9 @@ coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, 
  * [6] expressions cut into flat chunks, [7] LDS stack entries per thread,
  * [8] transposed-leaf tiles staged in LDS per workgroup, [9] tile edge of the 2-D
  * part, [10] its grid, [11] tiles of the flat part (the work-list's first),
- * [12] 1 if the graph runs the two parts side by side. */
-coot_status coot_batch_info(const coot_batch* b, int64_t info[13]);
+ * [12] 1 if the graph runs the two parts side by side, [13] / [14] elements per
+ * thread / 4 of the flat / 2-D part (1, 2 or 4). */
+coot_status coot_batch_info(const coot_batch* b, int64_t info[15]);
 
 void coot_batch_release(coot_batch* b);
 

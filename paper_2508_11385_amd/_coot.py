@@ -303,11 +303,11 @@ def coot_batch_tune(b: int, stream: int = 0):
 
 
 def coot_batch_info(b: int) -> dict:
-    a = (C.c_int64 * 13)()
+    a = (C.c_int64 * 15)()
     _check(lib.coot_batch_info(b, a))
     return {"n_exprs": a[0], "n_tiles": a[1], "bytes": a[2], "tile": a[3], "grid": a[4], "vec4_exprs": a[5],
             "flat_exprs": a[6], "lds_stack": a[7], "lds_staged": a[8], "tile_2d": a[9], "grid_2d": a[10],
-            "flat_tiles": a[11], "concurrent": a[12]}
+            "flat_tiles": a[11], "concurrent": a[12], "g": a[13], "g_2d": a[14]}
 
 
 def coot_batch_release(b: int) -> None:

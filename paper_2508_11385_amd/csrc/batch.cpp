@@ -16,9 +16,9 @@
 #include "batch_abi.h"
 #include "core.h"
 
-extern "C" hipError_t coot_batch_launch_kernel(int dtype, int ts, unsigned grid, const void* ex, const void* tiles,
-                                              int t_begin, int t_end, const void* code, const void* scal, int nstk,
-                                              int np1, int flat_only, hipStream_t s);
+extern "C" hipError_t coot_batch_launch_kernel(int dtype, int ts, int g, unsigned grid, const void* ex,
+                                              const void* tiles, int t_begin, int t_end, const void* code,
+                                              const void* scal, int nstk, int np1, int flat_only, hipStream_t s);
 
 using namespace coot;
 using coot::batch::BatchExpr;
@@ -182,6 +182,7 @@ struct coot_batch {
   DevBuf<uint64_t> d_scal32x2;  // scalars packed as the element type
   // launch settings of the two parts: [0] flat chunks, [1] 2-D tiles
   int ts[2] = {32, 32};             // tile edge (a flat chunk holds ts * ts elements)
+  int g[2] = {1, 1};                // groups of 4 elements per thread: ts * ts / (4 g) threads per tile
   int gm[2] = {16, 16};             // workgroups per CU
   bool allow_vec[2] = {true, true};  // 128-bit accesses where the layout allows them
   unsigned grid[2] = {1, 1};
@@ -255,18 +256,19 @@ void build_tiles(coot_batch* b) {
 }
 
 // Transposed-leaf tiles staged in LDS: as many as an expression needs (at most 4 on
-// one-wave 16 x 16 tiles, staged by LDS DMA; 2 on 32 x 32 tiles, staged through
-// registers) while the workgroup's LDS stays within 32 KB (several workgroups per
-// CU), and always within the 64 KB a workgroup may hold (2 KB of it hold the exp
-// table); the rest are read directly.
+// one-wave tiles, staged by LDS DMA; 2 on larger tiles, staged through registers)
+// while the workgroup's LDS stays within 32 KB (several workgroups per CU), and
+// always within the 64 KB a workgroup may hold (2 KB of it hold the exp table); the
+// rest are read directly.
 constexpr size_t kMaxDynLds = 65536 - 2048;
 int staged_tiles(const coot_batch* b) {
   const size_t es = b->dtype == COOT_BATCH_F32 ? 4 : 8;
   const int ts = b->ts[1];
-  const size_t stack = (size_t)b->nstk * (ts * ts / 4) * 4 * es;
-  const size_t slot = (size_t)ts * (ts == 16 ? ts : ts + 1) * es;  // as the kernel lays them out
+  const bool one_wave = ts * ts / (4 * b->g[1]) == 64;
+  const size_t stack = (size_t)b->nstk * ts * ts * es;                    // nstk entries of the tile's values
+  const size_t slot = (size_t)ts * (one_wave ? ts : ts + 1) * es;         // as the kernel lays them out
   const size_t budget = std::max<size_t>(32768, stack + slot);
-  size_t n = std::min<size_t>({(size_t)b->max_p1, ts == 16 ? 4u : 2u, budget > stack ? (budget - stack) / slot : 0});
+  size_t n = std::min<size_t>({(size_t)b->max_p1, one_wave ? 4u : 2u, budget > stack ? (budget - stack) / slot : 0});
   while (n > 0 && stack + n * slot > kMaxDynLds) --n;
   return (int)n;
 }
@@ -276,7 +278,7 @@ void launch_part(coot_batch* b, int part, hipStream_t s) {
   const int n_tiles = (int)(b->tiles.size() / 2), nf = b->n_flat_tiles;
   const int t0 = part == 0 ? 0 : nf, t1 = part == 0 ? nf : n_tiles;
   if (t1 <= t0) return;
-  hip_check(coot_batch_launch_kernel(b->dtype, b->ts[part], b->grid[part], b->d_ex.p, b->d_tiles.p, t0, t1,
+  hip_check(coot_batch_launch_kernel(b->dtype, b->ts[part], b->g[part], b->grid[part], b->d_ex.p, b->d_tiles.p, t0, t1,
                                      b->d_code.p, b->d_scal32x2.p, b->nstk, part == 0 ? 0 : staged_tiles(b),
                                      part == 0 ? 1 : 0, s),
             "batch kernel launch");
@@ -363,11 +365,21 @@ coot_status coot_batch_create(uint32_t n, coot_expr* const* exprs, const coot_op
     *out = nullptr;
     auto b = std::make_unique<coot_batch>();
     if (cfg) {  // the same settings for both parts
+      if (cfg->tile_r != cfg->tile_c || (cfg->tile_r && cfg->tile_r != 16 && cfg->tile_r != 32))
+        fail(COOT_EINVAL, "batch tiles are 16 x 16 or 32 x 32 elements");
+      int ts = 32, g = 1;
+      if (cfg->tile_r == 16 || (!cfg->tile_r && cfg->waves == 1)) {
+        ts = 16;
+        if (cfg->waves > 1) fail(COOT_EINVAL, "a 16 x 16 batch tile is one wavefront");
+      } else if (cfg->waves) {
+        if (cfg->waves != 1 && cfg->waves != 2 && cfg->waves != 4)
+          fail(COOT_EINVAL, "a 32 x 32 batch tile takes 1, 2 or 4 wavefronts");
+        g = 4 / cfg->waves;
+      }
       for (int p = 0; p < 2; ++p) {
-        if (cfg->waves) {
-          if (cfg->waves == 1) b->ts[p] = 16;
-          else if (cfg->waves == 4) b->ts[p] = 32;
-          else fail(COOT_EINVAL, "batch waves must be 1 or 4 (tiles of 16 x 16 or 32 x 32 elements)");
+        if (cfg->waves || cfg->tile_r) {
+          b->ts[p] = ts;
+          b->g[p] = g;
         }
         if (cfg->grid_mult) b->gm[p] = cfg->grid_mult;
         if (cfg->vec == 1) b->allow_vec[p] = false;
@@ -498,7 +510,7 @@ coot_status coot_batch_launch_each(coot_batch* b, void* stream) {
       if (r.second == r.first) continue;
       const int fl = r.second <= b->n_flat_tiles ? 1 : 0, part = fl ? 0 : 1;
       const unsigned g = (unsigned)std::min(r.second - r.first, (int)b->grid[part]);
-      hip_check(coot_batch_launch_kernel(b->dtype, b->ts[part], g, b->d_ex.p, b->d_tiles.p, r.first, r.second,
+      hip_check(coot_batch_launch_kernel(b->dtype, b->ts[part], b->g[part], g, b->d_ex.p, b->d_tiles.p, r.first, r.second,
                                          b->d_code.p, b->d_scal32x2.p, b->nstk, fl ? 0 : staged_tiles(b), fl,
                                          (hipStream_t)stream),
                 "batch kernel launch");
@@ -534,11 +546,13 @@ coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, 
       // each part is tuned on its own launch (the other part's settings do not affect it)
       for (int part = 0; part < 2; ++part) {
         float bt = 1e30f;
-        int bts = b->ts[part], bgm = b->gm[part];
+        int bts = b->ts[part], bg = b->g[part], bgm = b->gm[part];
         bool bvec = b->allow_vec[part];
-        for (int ts : {16, 32}) {
+        // tile shapes: 16 x 16 by one wave, 32 x 32 by four, two or one wave(s)
+        for (auto shape : {std::pair<int, int>{16, 1}, {32, 1}, {32, 2}, {32, 4}}) {
           for (bool vec : {true, false}) {
-            b->ts[part] = ts;
+            b->ts[part] = shape.first;
+            b->g[part] = shape.second;
             b->allow_vec[part] = vec;
             build_tiles(b);
             for (int gm : {2, 4, 8, 16}) {
@@ -547,7 +561,8 @@ coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, 
               const float t = median_ms([&] { launch_part(b, part, s); });
               if (t < bt) {
                 bt = t;
-                bts = ts;
+                bts = shape.first;
+                bg = shape.second;
                 bgm = gm;
                 bvec = vec;
               }
@@ -555,6 +570,7 @@ coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, 
           }
         }
         b->ts[part] = bts;
+        b->g[part] = bg;
         b->gm[part] = bgm;
         b->allow_vec[part] = bvec;
       }
@@ -583,14 +599,14 @@ coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, 
     if (best) {  // the flat part's settings (coot_batch_info reports both parts)
       best->vec = b->allow_vec[0] ? 4 : 1;
       best->ept = 4;
-      best->waves = (uint16_t)(b->ts[0] * b->ts[0] / 256);
+      best->waves = (uint16_t)(b->ts[0] * b->ts[0] / (256 * b->g[0]));
       best->grid_mult = (uint16_t)b->gm[0];
     }
     if (best_us) *best_us = total * 1000.0f;
   });
 }
 
-coot_status coot_batch_info(const coot_batch* b, int64_t info[13]) {
+coot_status coot_batch_info(const coot_batch* b, int64_t info[15]) {
   return guarded([&] {
     if (!b || !info) fail(COOT_EINVAL, "NULL argument");
     info[0] = (int64_t)b->ex.size();
@@ -602,6 +618,8 @@ coot_status coot_batch_info(const coot_batch* b, int64_t info[13]) {
     info[10] = b->grid[1];
     info[11] = b->n_flat_tiles;
     info[12] = b->concurrent ? 1 : 0;
+    info[13] = b->g[0];
+    info[14] = b->g[1];
     int64_t v4 = 0, fl = 0;
     for (auto& e : b->ex) {
       v4 += e.vec4;

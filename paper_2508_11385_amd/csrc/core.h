@@ -65,9 +65,38 @@ struct Expr {
   bool root_schur = false;      // root is a Schur product (dot pattern)
   bool scalar_only = false;     // no LOAD at all
   std::string canon;            // canonical text (the signature body)
+  uint64_t uid = 0;             // unique per analysed expression (never reused)
   // per-request kernel cache: request key -> module-level kernel handles
   std::mutex mu;
   std::map<std::string, std::shared_ptr<struct Module>> reqs;
+  // The last fused evaluation's launch (kernel, grid, block, arguments without the
+  // scalars): validation and planning depend only on the operands, the output and the
+  // configuration, so a call repeating all three reuses it (under mu).
+  struct EvalMemo {
+    bool valid = false;
+    std::vector<coot_operand> ops;
+    coot_operand out{};
+    coot_launch_cfg cfg{};
+    bool has_cfg = false, plain = false;
+    hipFunction_t f = nullptr;
+    unsigned grid = 0, block = 0;
+    KArgs a{};
+  } memo;
+  // The same for the last statement pair (eval_reduce) led by this expression: the
+  // second statement's uid, operand map, kind and output, and the two launches.
+  struct PairMemo {
+    bool valid = false;
+    std::vector<coot_operand> ops;
+    coot_operand out{}, r_out{};
+    uint64_t r_uid = 0;
+    std::vector<int32_t> r_src;
+    int kind = 0;
+    coot_launch_cfg cfg{};
+    bool has_cfg = false;
+    hipFunction_t f1 = nullptr, f2 = nullptr;
+    unsigned grid = 0, block = 0;
+    KArgs a{};
+  } pair_memo;
 };
 
 // Analysis

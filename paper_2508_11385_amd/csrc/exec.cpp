@@ -314,8 +314,31 @@ unsigned tile_grid(int64_t R, int64_t C, int tr, int tc, int gm) {
   return (unsigned)std::max<int64_t>(1, std::min(nt, cap));
 }
 
+static bool same_call(const Expr::EvalMemo& m, const Expr& e, const coot_operand* ops, const coot_operand& out,
+                      const coot_launch_cfg* cfg, bool plain_store) {
+  if (!m.valid || m.plain != plain_store || m.has_cfg != (cfg != nullptr)) return false;
+  if (cfg && std::memcmp(cfg, &m.cfg, sizeof *cfg) != 0) return false;
+  if (std::memcmp(&out, &m.out, sizeof out) != 0) return false;
+  const size_t n = e.slots.size();
+  return n == m.ops.size() && (n == 0 || std::memcmp(ops, m.ops.data(), n * sizeof(coot_operand)) == 0);
+}
+
 void eval_fused(Expr& e, const coot_operand* ops, const double* scalars, const coot_operand& out,
                 const coot_launch_cfg* cfg, hipStream_t s, bool plain_store) {
+  if (e.n_scalars && !scalars) fail(COOT_EINVAL, "scalars missing");
+  if (!e.slots.empty() && !ops) fail(COOT_EINVAL, "operands missing");
+  {
+    std::unique_lock<std::mutex> g(e.mu);
+    if (same_call(e.memo, e, ops, out, cfg, plain_store)) {
+      KArgs a = e.memo.a;
+      const hipFunction_t f = e.memo.f;
+      const unsigned grid = e.memo.grid, block = e.memo.block;
+      g.unlock();
+      for (uint32_t k = 0; k < e.n_scalars; ++k) a.sc[k] = scalar_bits(scalars[k], e.dtype);
+      launch(f, grid, block, a, s);
+      return;
+    }
+  }
   check_operands(e, ops);
   int64_t R = 0, C = 0;
   infer_shape(e, ops, &R, &C);
@@ -339,12 +362,28 @@ void eval_fused(Expr& e, const coot_operand* ops, const double* scalars, const c
   const std::string& kn = (v || rq.var.vec == 1) ? m->names.stage1 : m->names.stage1_fallback;
   hipFunction_t f = m->fn(kn);
   const coot_launch_cfg c = resolve_cfg(cfg, rq.fam, -1, -1, e.dtype, R * C);
+  unsigned grid, block;
   if (rq.fam == FAM_FLAT) {
-    const int bs = 64 * c.waves;
-    launch(f, flat_grid(R * C, v ? rq.var.vec : 1, rq.var.ept, bs, c.grid_mult), bs, a, s);
+    block = 64 * c.waves;
+    grid = flat_grid(R * C, v ? rq.var.vec : 1, rq.var.ept, (int)block, c.grid_mult);
   } else {
-    launch(f, tile_grid(R, C, rq.var.tr, rq.var.tc, c.grid_mult), 256, a, s);
+    block = 256;
+    grid = tile_grid(R, C, rq.var.tr, rq.var.tc, c.grid_mult);
   }
+  launch(f, grid, block, a, s);
+  std::lock_guard<std::mutex> g(e.mu);
+  Expr::EvalMemo& mm = e.memo;
+  mm.ops.assign(ops, ops + e.slots.size());
+  mm.out = out;
+  mm.has_cfg = cfg != nullptr;
+  if (cfg) mm.cfg = *cfg;
+  mm.plain = plain_store;
+  mm.f = f;
+  mm.grid = grid;
+  mm.block = block;
+  mm.a = a;
+  std::memset(mm.a.sc, 0, sizeof mm.a.sc);
+  mm.valid = true;
 }
 
 // out = e, then a full reduction of r over e's operands and the result, in one
@@ -353,6 +392,33 @@ void eval_fused(Expr& e, const coot_operand* ops, const double* scalars, const c
 void eval_reduce(Expr& e, const coot_operand* ops, const double* scalars, const coot_operand& out, Expr& r,
                  const int32_t* r_src, const double* r_scalars, int kind, const coot_operand& r_out,
                  const coot_launch_cfg* cfg, hipStream_t s) {
+  if (e.n_scalars && !scalars) fail(COOT_EINVAL, "scalars missing");
+  if (r.n_scalars && !r_scalars) fail(COOT_EINVAL, "scalars of the reduced statement missing");
+  if (!r.slots.empty() && !r_src) fail(COOT_EINVAL, "operand map of the reduced statement missing");
+  if (!e.slots.empty() && !ops) fail(COOT_EINVAL, "operands missing");
+  {
+    std::unique_lock<std::mutex> g(e.mu);
+    const Expr::PairMemo& pm = e.pair_memo;
+    const size_t n = e.slots.size(), nr = r.slots.size();
+    if (pm.valid && pm.r_uid == r.uid && pm.kind == kind && pm.has_cfg == (cfg != nullptr) &&
+        (!cfg || std::memcmp(cfg, &pm.cfg, sizeof *cfg) == 0) && std::memcmp(&out, &pm.out, sizeof out) == 0 &&
+        std::memcmp(&r_out, &pm.r_out, sizeof r_out) == 0 && pm.ops.size() == n && pm.r_src.size() == nr &&
+        (n == 0 || std::memcmp(ops, pm.ops.data(), n * sizeof(coot_operand)) == 0) &&
+        (nr == 0 || std::memcmp(r_src, pm.r_src.data(), nr * sizeof(int32_t)) == 0)) {
+      KArgs a = pm.a;
+      const hipFunction_t f1 = pm.f1, f2 = pm.f2;
+      const unsigned grid = pm.grid, block = pm.block;
+      g.unlock();
+      for (uint32_t k = 0; k < e.n_scalars; ++k) a.sc[k] = scalar_bits(scalars[k], e.dtype);
+      for (uint32_t k = 0; k < r.n_scalars; ++k) a.sc[e.n_scalars + k] = scalar_bits(r_scalars[k], e.dtype);
+      a.ws = workspace((size_t)grid * 32, s, 0);
+      a.out = out.data;
+      launch(f1, grid, block, a, s);
+      a.out = r_out.data;
+      launch(f2, 1, 256, a, s);
+      return;
+    }
+  }
   check_operands(e, ops);
   int64_t R = 0, C = 0;
   infer_shape(e, ops, &R, &C);
@@ -408,9 +474,27 @@ void eval_reduce(Expr& e, const coot_operand* ops, const double* scalars, const 
   const unsigned grid = flat_grid(R * C, v ? rq.var.vec : 1, rq.var.ept, (int)block, c.grid_mult);
   a.n_part = grid;
   a.ws = workspace((size_t)grid * 32, s, 0);
-  launch(m->fn(kn), grid, block, a, s);
+  const hipFunction_t f1 = m->fn(kn), f2 = m->fn(m->names.stage2);
+  launch(f1, grid, block, a, s);
   a.out = r_out.data;  // stage 2 writes the reduction's result
-  launch(m->fn(m->names.stage2), 1, 256, a, s);
+  launch(f2, 1, 256, a, s);
+  std::lock_guard<std::mutex> g(e.mu);
+  Expr::PairMemo& pm = e.pair_memo;
+  pm.ops.assign(ops, ops + e.slots.size());
+  pm.out = out;
+  pm.r_out = r_out;
+  pm.r_uid = r.uid;
+  pm.r_src.assign(r_src, r_src + r.slots.size());
+  pm.kind = kind;
+  pm.has_cfg = cfg != nullptr;
+  if (cfg) pm.cfg = *cfg;
+  pm.f1 = f1;
+  pm.f2 = f2;
+  pm.grid = grid;
+  pm.block = block;
+  pm.a = a;
+  std::memset(pm.a.sc, 0, sizeof pm.a.sc);
+  pm.valid = true;
 }
 
 DimPlan dim_plan(int64_t R, int64_t C, int dim, int tile_r, int tile_c, int per_cu, size_t cs) {

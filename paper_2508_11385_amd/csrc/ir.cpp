@@ -7,6 +7,7 @@
 // the tree arrives as a postfix list.  Every trans() is pushed down to the
 // leaves: a leaf under an odd number of trans() is read with its index map
 // swapped, so transposition never costs a pass of its own.
+#include <atomic>
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -70,6 +71,8 @@ std::unique_ptr<Expr> analyse(const coot_op* ops, uint32_t n_ops, const coot_slo
   if (n_slots > 0 && !slots) fail(COOT_EINVAL, "slot types missing");
   if (flags & ~COOT_CF_UNFUSED) fail(COOT_EINVAL, "unknown compile flag");
   auto e = std::make_unique<Expr>();
+  static std::atomic<uint64_t> next_uid{1};
+  e->uid = next_uid++;
   e->ops.assign(ops, ops + n_ops);
   e->slots.assign(slots, slots + n_slots);
   e->n_scalars = n_scalars;

@@ -72,6 +72,26 @@ def test_batch_matches_oracle_and_fused(coot, dtype):
     assert info["n_exprs"] == 120 and info["n_tiles"] > 120
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("cfg", [(4, 1, 2, 8), (4, 1, 1, 4, 32, 32)])
+def test_multi_element_threads_match_oracle_and_fused(coot, dtype, cfg):
+    """32 x 32 tiles by two wavefronts (8 elements per thread) and by one (16 per thread,
+    transposed leaves staged by LDS DMA): every output against the oracle and bitwise
+    against the single-expression fused path."""
+    import torch
+    specs, host, exprs = _make(coot, 80, 43 if dtype == "f32" else 44, dtype)
+    b = coot.Batch([(e, None) for e in exprs], cfg=cfg)
+    info = b.info()
+    assert (info["tile"], info["g"], info["tile_2d"], info["g_2d"]) == (32, 4 // cfg[2], 32, 4 // cfg[2])
+    b.launch()
+    torch.cuda.synchronize()
+    _check_against_oracle(specs, host, b.outs, dtype)
+    for e, out in zip(exprs[:30], b.outs[:30]):
+        single = coot.eval(e).numpy()
+        assert np.array_equal(np.ascontiguousarray(single).view(np.uint8),
+                              np.ascontiguousarray(out.numpy()).view(np.uint8))
+
+
 def test_graph_replays_with_eager_work_between(coot):
     import torch
     specs, host, exprs = _make(coot, 60, 43)
@@ -104,7 +124,7 @@ def test_per_expression_launches_and_tuning_agree(coot):
     for r, o in zip(ref, b.outs):
         assert np.array_equal(r, o.numpy())
     cfg, us = b.tune()
-    assert cfg[2] in (1, 4) and cfg[0] in (1, 4) and us > 0
+    assert cfg[2] in (1, 2, 4) and cfg[0] in (1, 4) and us > 0
     for o in b.outs:
         o.tensor.zero_()
     b.launch()
@@ -113,7 +133,8 @@ def test_per_expression_launches_and_tuning_agree(coot):
         assert np.array_equal(r, o.numpy())
 
 
-@pytest.mark.parametrize("cfg", [(1, 1, 1, 2), (4, 2, 4, 8), (4, 8, 1, 4), (1, 4, 4, 16)])
+@pytest.mark.parametrize("cfg", [(1, 1, 1, 2), (4, 2, 4, 8), (4, 8, 1, 4), (1, 4, 4, 16),
+                                 (4, 1, 2, 8), (1, 1, 2, 4), (4, 1, 1, 4, 32, 32), (1, 1, 1, 16, 32, 32)])
 def test_every_tile_size_and_vector_width(coot, cfg):
     import torch
     specs, host, exprs = _make(coot, 40, 45, lo=1, hi=200)
@@ -134,9 +155,10 @@ def test_many_transposed_leaves(coot):
         (1.0 + coot.abs(coot.trans(mats[4]))) + mats[5] % coot.trans(mats[5])
     post = coot.flatten(e).postfix
     want = ew.evaluate(post, mats_h, [1.0], "f32")
-    # 6 transposed leaves: 4 LDS slots filled by LDS DMA on 16 x 16 one-wave tiles,
-    # 2 slots filled through registers on 32 x 32 tiles; the rest read directly
-    for cfg, slots in (((4, 4, 1, 4), 4), ((4, 4, 4, 4), 2)):
+    # 6 transposed leaves: 4 LDS slots filled by LDS DMA on one-wave tiles (16 x 16, and
+    # 32 x 32 with 16 elements per thread), 2 slots filled through registers on 32 x 32
+    # tiles of two or four wavefronts; the rest read directly
+    for cfg, slots in (((4, 4, 1, 4), 4), ((4, 4, 4, 4), 2), ((4, 4, 2, 4), 2), ((4, 4, 1, 4, 32, 32), 4)):
         b = coot.Batch([(e, None)], cfg=cfg)
         assert b.info()["lds_staged"] == slots
         b.launch()
@@ -202,7 +224,7 @@ def test_flat_chunks_unaligned_and_padded(coot, dtype):
         exprs.append(e)
         post = coot.flatten(e).postfix
         want.append(ew.evaluate(post, [hs[0], hs[1], hs[2]], [1.0], dtype))
-    for cfg in (None, (4, 4, 1, 4), (1, 4, 4, 2)):
+    for cfg in (None, (4, 4, 1, 4), (1, 4, 4, 2), (4, 1, 2, 4), (4, 1, 1, 8, 32, 32), (1, 1, 1, 2, 32, 32)):
         b = coot.Batch([(e, None) for e in exprs], cfg=cfg)
         b.launch()
         torch.cuda.synchronize()
