@@ -58,6 +58,7 @@ def parse():
     p.add_argument("--tuner-models", type=int, default=5, help="networks in the cost-model ensemble")
     p.add_argument("--tuner-dump", default="", help="write the timing tables here (.npz)")
     p.add_argument("--tuner-out", default=os.path.join(ROOT, "gpurun_out", "costmodel_mi355x.bin"))
+    p.add_argument("--tuner-workers", type=int, default=14, help="processes compiling tuning modules")
     p.add_argument("--profile-kernels", action="store_true",
                    help="run the copy probe and each kernel of one step 3 times, print their names, exit")
     return p.parse_args()
@@ -144,13 +145,23 @@ def main():
             copy()
         for _ in range(3):
             step(*fused, cfgs["Z"], cfgs["W"], cfgs["S0"], cfgs["S1"])
+        # Z under every tile shape and vector width the autotuner can pick (its counters do
+        # not depend on the launch's workgroups per CU)
+        zvariants = {}
+        for tr, tc in ((64, 64), (128, 32), (32, 128), (256, 16), (128, 64), (32, 32)):
+            for vec in (1, 2, 4):
+                if vec <= tr * tc // 256:
+                    zc = (vec, 0, 0, 0, tr, tc)
+                    for _ in range(3):
+                        cc.coot_expr_eval(fused[0], zops, zf.scalars, zo, zc, stream)
+                    zvariants[cc.coot_expr_kernel_name(fused[0], cfg=zc)] = zc
         torch.cuda.synchronize()
         names = {"copy": cc.coot_expr_kernel_name(hcopy), "Z": cc.coot_expr_kernel_name(fused[0], cfg=cfgs["Z"]),
                  "W": cc.coot_expr_kernel_name(fused[1], cfg=cfgs["W"]),
                  "sumZ0": cc.coot_expr_kernel_name(fused[0], cc.COOT_RED_SUM, 0, cfg=cfgs["S0"]),
                  "sumZ1": cc.coot_expr_kernel_name(fused[0], cc.COOT_RED_SUM, 1, cfg=cfgs["S1"])}
-        print(json.dumps({"profiled_kernels": names, "copy_bytes": 2 * MIB64, "Z_bytes": 5 * MIB64,
-                          "launches_each": 3}), flush=True)
+        print(json.dumps({"profiled_kernels": names, "Z_variants": sorted(zvariants), "copy_bytes": 2 * MIB64,
+                          "Z_bytes": 5 * MIB64, "launches_each": 3}), flush=True)
         return
 
     for _ in range(3):
@@ -238,6 +249,67 @@ def main():
                   4 * MIB64 + N * 4),
     }
     cold_s = {k: cold(fn) for k, (fn, nb) in parts.items()}
+
+    # streaming protocol: Z back to back over four copies of its operands and output (1.25 GiB
+    # in rotation, far beyond the 256 MB Infinity Cache), so every launch reads HBM, in the
+    # steady state of repeated launches (no flush in between); HIP events around 32 launches
+    zsets = [(zops, zo)]
+    keep = []
+    for _ in range(3):
+        cp = [coot.Mat(m.tensor.clone(), "f32") for m in zf.mats]
+        zc_out = coot.Mat.empty(N, N, "f32")
+        keep.append((cp, zc_out))
+        zsets.append(([m.operand() for m in cp], zc_out.operand()))
+    for _ in range(2):
+        for ops_k, out_k in zsets:
+            cc.coot_expr_eval(hz, ops_k, zf.scalars, out_k, cfgs["Z"], stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(8):
+        for ops_k, out_k in zsets:
+            cc.coot_expr_eval(hz, ops_k, zf.scalars, out_k, cfgs["Z"], stream)
+    e1.record()
+    torch.cuda.synchronize()
+    z_stream_s = e0.elapsed_time(e1) * 1e-3 / (8 * len(zsets))
+    z_stream_gbs = 5 * MIB64 / z_stream_s / 1e9
+
+    # the same protocol for flat reference kernels moving the same streams as Z (four 64 MiB
+    # reads and one write: A + B - C + D; its accu, four reads) and for a copy (one read, one
+    # write): what HBM sustains for each stream pattern on this machine
+    def streamed(launch_k):
+        for _ in range(2):
+            for k in range(len(zsets)):
+                launch_k(k)
+        torch.cuda.synchronize()
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a0.record()
+        for _ in range(8):
+            for k in range(len(zsets)):
+                launch_k(k)
+        a1.record()
+        torch.cuda.synchronize()
+        return a0.elapsed_time(a1) * 1e-3 / (8 * len(zsets))
+
+    mats_k = [list(zf.mats)] + [cp for cp, _ in keep]
+    outs_k = [zo] + [o.operand() for _, o in keep]
+    ref_flat = coot.flatten(zf.mats[0] + zf.mats[1] - zf.mats[2] + zf.mats[3])
+    href = coot.frontend.compiled(ref_flat)
+    rops = [[m.operand() for m in ms] for ms in mats_k]
+    racc_m = coot.Mat.empty(1, 1, "f32")       # kept alive while its operand is used
+    racc = racc_m.operand()
+    cops_k = [[ms[0].operand()] for ms in mats_k]
+    references = {}
+    for name, nb, fn in (
+            ("copy_1read_1write", 2 * MIB64, lambda k: cc.coot_expr_eval(hcopy, cops_k[k], [], outs_k[k], None, stream)),
+            ("flat_4reads_1write", 5 * MIB64,
+             lambda k: cc.coot_expr_eval(href, rops[k], [], outs_k[k], None, stream)),
+            ("accu_4reads", 4 * MIB64,
+             lambda k: cc.coot_reduce(href, rops[k], [], cc.COOT_RED_ACCU, -1, 0, racc, None, stream))):
+        t = streamed(fn)
+        references[name] = {"us": round(t * 1e6, 2), "GBps": round(nb / t / 1e9, 1),
+                            "frac": round(nb / t / 1e9 / PEAK_HBM_GBS, 3)}
+    del keep, zsets, mats_k, rops, cops_k, racc_m
     cold_step = sum(cold_s.values())
     hzu, hwu = unfused
     uparts = {
@@ -311,9 +383,20 @@ def main():
             "speedup_vs_unfused": round(cold_unfused / cold_step, 2),
         },
         "roofline": {"bound": "hbm", "kernel": zname,
-                     "achieved": round(z_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(z_gbs / PEAK_HBM_GBS, 3), "traffic": traffic,
-                     "avg_kernel_us": round(z_ms * 1e3, 2), "algorithmic_bytes": 5 * MIB64},
+                     "achieved": round(z_stream_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(z_stream_gbs / PEAK_HBM_GBS, 3), "traffic": traffic,
+                     "avg_kernel_us": round(z_stream_s * 1e6, 2), "algorithmic_bytes": 5 * MIB64,
+                     "measured": "HIP events on the launch stream around 32 back-to-back Z launches over 4 copies "
+                                 "of its operands and output (1.25 GiB in rotation: every launch reads HBM, no "
+                                 "Infinity Cache reuse)",
+                     "of_same_stream_reference": round(references["flat_4reads_1write"]["us"] / (z_stream_s * 1e6), 3),
+                     "streaming_references": references,
+                     "in_step": {"us": round(z_ms * 1e3, 2), "frac": round(z_gbs / PEAK_HBM_GBS, 3),
+                                 "note": "HIP events around each Z launch of the timed steps: A, B, C, D are "
+                                         "re-read by the step's other kernels, partly from the Infinity Cache"},
+                     "cold": {"us": round(cold_s["Z"] * 1e6, 2),
+                              "frac": round(5 * MIB64 / cold_s["Z"] / 1e9 / PEAK_HBM_GBS, 3),
+                              "note": "one launch after a 512 MiB flush, median of 20"}},
         "cpu_baseline": cpu,
         "other_configs": others,
     }
@@ -605,8 +688,10 @@ def bench_batch(args):
             "expressions": ns, "ms_fused_kernel_launches": round(t_fused_each * 1e3, 3),
             "ms_batch": round(t_bsub * 1e3, 4), "speedup": round(t_fused_each / t_bsub, 1),
             "precompile_s": round(t_pre, 1)},
-        "tuned_cfg": {"flat_part": {"tile": info2["tile"], "grid": info2["grid"], "vec": cfg[0]},
-                      "2d_part": {"tile": info2["tile_2d"], "grid": info2["grid_2d"]},
+        "tuned_cfg": {"flat_part": {"tile": info2["tile"], "elements_per_thread": 4 * info2["g"],
+                                    "grid": info2["grid"], "vec": cfg[0]},
+                      "2d_part": {"tile": info2["tile_2d"], "elements_per_thread": 4 * info2["g_2d"],
+                                  "grid": info2["grid_2d"]},
                       "flat_tiles": info2["flat_tiles"], "parts_side_by_side": bool(info2["concurrent"])},
         "default_cfg": {"flat_part": {"tile": info["tile"], "grid": info["grid"]},
                         "2d_part": {"tile": info["tile_2d"], "grid": info["grid_2d"]},
@@ -790,8 +875,8 @@ def bench_tuner(args):
     train = tuner.sample_signatures(args.tuner_train, seed=1)
     test = tuner.sample_signatures(args.tuner_test, seed=3)
     t0 = time.perf_counter()
-    h_tr, f_tr = tuner.prepare_all(train, log=log)
-    h_te, f_te = tuner.prepare_all(test, log=log)
+    h_tr, f_tr = tuner.prepare_all(train, workers=args.tuner_workers, log=log)
+    h_te, f_te = tuner.prepare_all(test, workers=args.tuner_workers, log=log)
     t_compile = time.perf_counter() - t0
     log(f"compiled {len(train) + len(test)} tuning modules in {t_compile:.0f} s")
     t0 = time.perf_counter()
@@ -830,6 +915,27 @@ def bench_tuner(args):
     in_table = {name: tuner.summarize(tuner.regrets_from_table(tab_te, sets[:, j]))
                 for j, name in ((1, "mlp"), (2, "default_config"), (3, "untrained_mlp"))}
     rnd = lambda d: {k: round(v, 4) for k, v in d.items()}
+
+    # 95 % bootstrap intervals of the re-timed geomean regrets (signatures resampled), and
+    # the slices of the held-out set: small outputs, reductions, fp64, the tiled family
+    rng = np.random.default_rng(15)
+    lr = np.log(fresh[:, 1:] / fresh[:, :1])                  # log time ratios: mlp, default, untrained
+    boots = np.exp(np.stack([lr[rng.integers(0, len(lr), len(lr))].mean(0) for _ in range(2000)])) - 1.0
+    ci = {name: [round(float(np.percentile(boots[:, j], 2.5)), 4), round(float(np.percentile(boots[:, j], 97.5)), 4)]
+          for j, name in enumerate(("mlp", "default_config", "untrained_mlp"))}
+    gain = np.exp(np.stack([(lr[idx, 1] - lr[idx, 0]).mean() for idx in
+                            (rng.integers(0, len(lr), len(lr)) for _ in range(2000))]))
+    elems = np.array([s.out_shape[0] * s.out_shape[1] for s, _ in test])
+    slices = {"outputs < 2^16 elements": elems < (1 << 16), "outputs >= 2^20 elements": elems >= (1 << 20),
+              "accu": np.array([m == 0 for _, m in test]), "fp64": np.array([s.dtype == "f64" for s, _ in test]),
+              "tiled family": np.array(f_te) == 1}
+    by_slice = {}
+    for name, msk in slices.items():
+        if msk.sum() == 0:
+            continue
+        g = np.exp(lr[msk].mean(0)) - 1.0
+        by_slice[name] = {"signatures": int(msk.sum()), "mlp": round(float(g[0]), 4),
+                          "default_config": round(float(g[1]), 4)}
     out = {
         "metric": "learned tuner: geomean regret of MLP-chosen launch configs vs exhaustive autotune",
         "value": round(100 * reg["mlp"]["geomean"], 2), "unit": "% regret", "higher_is_better": False, "n_gpus": 1,
@@ -844,6 +950,10 @@ def bench_tuner(args):
         "mlp": rnd(reg["mlp"]), "default_config": rnd(reg["default_config"]),
         "untrained_mlp": rnd(reg["untrained_mlp"]),
         "regret_within_exhaustive_table": {k: rnd(v) for k, v in in_table.items()},
+        "geomean_95pct_bootstrap": ci,
+        "default_over_mlp_time_ratio_95pct": [round(float(np.percentile(gain, 2.5)), 4),
+                                              round(float(np.percentile(gain, 97.5)), 4)],
+        "by_slice": by_slice,
         "final_train_loss": round(float(losses[-1]), 4), "first_train_loss": round(float(losses[0]), 4),
         "mlp_predict_us_per_signature": round(1e6 * t_pred, 1),
         "exhaustive_tuning_s_per_signature": round(t_exh / len(test), 4),
@@ -866,17 +976,19 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic(path, kernel):
-    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary, or None when the
-    kernel or its sources changed since the counters were taken."""
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE summary
+    (every variant of the Z kernel is recorded there), or None when the kernel is not in it
+    or its sources changed since the counters were taken."""
     if not os.path.exists(path):
         return None
     try:
         t = json.load(open(path))
     except ValueError:
         return None
-    if t.get("kernel") != kernel or t.get("source_sha256") != kernel_source_hash():
+    if t.get("source_sha256") != kernel_source_hash():
         return None
-    return t.get("bytes_per_launch")
+    k = t.get("kernels", {}).get(kernel)
+    return k.get("bytes_per_launch") if k else None
 
 
 def cpu_baseline(A, B, C, D, ncols):

@@ -574,20 +574,39 @@ coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, 
         b->gm[part] = bgm;
         b->allow_vec[part] = bvec;
       }
-      // then the graph: the parts side by side or one after the other, the faster
+      // then the graph: the parts one after the other (each with its own best grid), or
+      // side by side.  A persistent grid that alone fills every CU leaves the other part
+      // no room until it drains, so side by side also tries smaller grid pairs that let
+      // both stay resident together.
       build_tiles(b);
-      bool best_c = true;
+      const int gm_best[2] = {b->gm[0], b->gm[1]};
+      bool best_c = false;
+      int best_gm[2] = {gm_best[0], gm_best[1]};
       total = 1e30f;
-      for (bool c : {true, false}) {
+      auto try_graph = [&](bool c, int g0, int g1) {
         b->concurrent = c;
+        b->gm[0] = g0;
+        b->gm[1] = g1;
+        set_grids(b);
         capture(b);
         const float t = median_ms([&] { hip_check(hipGraphLaunch(b->exec, s), "hipGraphLaunch"); });
         if (t < total) {
           total = t;
           best_c = c;
+          best_gm[0] = g0;
+          best_gm[1] = g1;
         }
-      }
+      };
+      try_graph(false, gm_best[0], gm_best[1]);
+      try_graph(true, gm_best[0], gm_best[1]);
+      if (b->n_flat_tiles > 0 && b->n_flat_tiles < (int)(b->tiles.size() / 2))
+        for (int g1 : {1, 2, 3, 4, 6})
+          for (int g0 : {1, 2, 4, 8})
+            if (g1 < gm_best[1] || g0 < gm_best[0]) try_graph(true, g0, g1);
       b->concurrent = best_c;
+      b->gm[0] = best_gm[0];
+      b->gm[1] = best_gm[1];
+      set_grids(b);
     } catch (...) {
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
