@@ -19,11 +19,17 @@ def cc():
     return _coot
 
 
+# an expression no other test compiles, so that the process-wide module cache cannot
+# already hold its module when this file runs after the others
+UNIQUE = [("load", 0), ("load", 1), ("div",), ("scalar", 0), ("add",), ("sqrt",), ("neg",), ("square",),
+          ("scalar", 1), ("sub",)]
+
+
 def test_compile_error_is_reported_and_nothing_is_cached(cc, tmp_path, monkeypatch):
     monkeypatch.setenv("COOT_CACHE_DIR", str(tmp_path))
     # an include of a missing file: every module compiled under it fails
     monkeypatch.setenv("COOT_HIPRTC_EXTRA", "-include/nonexistent/coot_missing.h")
-    h = cc.coot_expr_compile(AXPY, [(cc.COOT_F32, 0)] * 2, 1)
+    h = cc.coot_expr_compile(UNIQUE, [(cc.COOT_F32, 0)] * 2, 2)
     before = cc.coot_stats()["compiles"]
     for _ in range(2):                       # a failed module is not remembered either
         with pytest.raises(cc.CootError) as e:
