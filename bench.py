@@ -50,7 +50,7 @@ def parse():
     p.add_argument("--w-cfg", default="", help="launch configuration vec,ept,waves,grid_mult for W (default: library's)")
     p.add_argument("--batch-fused-sample", type=int, default=500,
                    help="expressions timed with the plain fused kernel, one launch each")
-    p.add_argument("--tuner-train", type=int, default=1800, help="training signatures (~50,000 timings)")
+    p.add_argument("--tuner-train", type=int, default=1350, help="training signatures (~50,000 timings)")
     p.add_argument("--tuner-test", type=int, default=2000, help="held-out signatures (timed exhaustively)")
     p.add_argument("--tuner-cfgs", type=int, default=50, help="configurations timed per training signature")
     p.add_argument("--tuner-epochs", type=int, default=200)
