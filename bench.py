@@ -292,6 +292,7 @@ def main():
         return a0.elapsed_time(a1) * 1e-3 / (8 * len(zsets))
 
     mats_k = [list(zf.mats)] + [cp for cp, _ in keep]
+    zsets_ops = [ops_k for ops_k, _ in zsets]
     outs_k = [zo] + [o.operand() for _, o in keep]
     ref_flat = coot.flatten(zf.mats[0] + zf.mats[1] - zf.mats[2] + zf.mats[3])
     href = coot.frontend.compiled(ref_flat)
@@ -299,16 +300,35 @@ def main():
     racc_m = coot.Mat.empty(1, 1, "f32")       # kept alive while its operand is used
     racc = racc_m.operand()
     cops_k = [[ms[0].operand()] for ms in mats_k]
+    # each reference at its fastest flat configuration under this protocol (every vec, ept,
+    # waves and 1-16 workgroups per CU, through the tuning module: one compilation)
+    flat_space = cc.coot_tune_space(0) + [(v, e, w, 1, 0, 0) for v in (1, 2, 4) for e in (1, 2, 4, 8)
+                                          for w in (1, 2, 4, 8)]
     references = {}
-    for name, nb, fn in (
-            ("copy_1read_1write", 2 * MIB64, lambda k: cc.coot_expr_eval(hcopy, cops_k[k], [], outs_k[k], None, stream)),
-            ("flat_4reads_1write", 5 * MIB64,
-             lambda k: cc.coot_expr_eval(href, rops[k], [], outs_k[k], None, stream)),
-            ("accu_4reads", 4 * MIB64,
-             lambda k: cc.coot_reduce(href, rops[k], [], cc.COOT_RED_ACCU, -1, 0, racc, None, stream))):
-        t = streamed(fn)
+    for name, nb, h_ref, ops_k, mode, out_of in (
+            ("copy_1read_1write", 2 * MIB64, hcopy, cops_k, -1, lambda k: outs_k[k]),
+            ("flat_4reads_1write", 5 * MIB64, href, rops, -1, lambda k: outs_k[k]),
+            ("accu_4reads", 4 * MIB64, href, rops, cc.COOT_RED_ACCU, lambda k: racc)):
+        best = None
+        for c in flat_space:
+            try:
+                t = streamed(lambda k: cc.coot_tune_launch(h_ref, ops_k[k], [], out_of(k), mode, c, stream))
+            except cc.CootError:
+                continue
+            if best is None or t < best[0]:
+                best = (t, c)
+        t, c = best
         references[name] = {"us": round(t * 1e6, 2), "GBps": round(nb / t / 1e9, 1),
-                            "frac": round(nb / t / 1e9 / PEAK_HBM_GBS, 3)}
+                            "frac": round(nb / t / 1e9 / PEAK_HBM_GBS, 3), "cfg": list(c[:4])}
+    # Z itself at its fastest tiled configuration under this protocol
+    zbest = None
+    for c in cc.coot_tune_space(1):
+        try:
+            t = streamed(lambda k: cc.coot_tune_launch(hz, zsets_ops[k], zf.scalars, outs_k[k], -1, c, stream))
+        except cc.CootError:
+            continue
+        if zbest is None or t < zbest[0]:
+            zbest = (t, c)
     del keep, zsets, mats_k, rops, cops_k, racc_m
     cold_step = sum(cold_s.values())
     hzu, hwu = unfused
@@ -391,6 +411,8 @@ def main():
                                  "Infinity Cache reuse)",
                      "of_same_stream_reference": round(references["flat_4reads_1write"]["us"] / (z_stream_s * 1e6), 3),
                      "streaming_references": references,
+                     "best_tiled_streaming": {"us": round(zbest[0] * 1e6, 2), "cfg": list(zbest[1]),
+                                              "frac": round(5 * MIB64 / zbest[0] / 1e9 / PEAK_HBM_GBS, 3)},
                      "in_step": {"us": round(z_ms * 1e3, 2), "frac": round(z_gbs / PEAK_HBM_GBS, 3),
                                  "note": "HIP events around each Z launch of the timed steps: A, B, C, D are "
                                          "re-read by the step's other kernels, partly from the Infinity Cache"},
