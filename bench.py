@@ -61,6 +61,10 @@ def parse():
     p.add_argument("--tuner-workers", type=int, default=14, help="processes compiling tuning modules")
     p.add_argument("--profile-kernels", action="store_true",
                    help="run the copy probe and each kernel of one step 3 times, print their names, exit")
+    p.add_argument("--batch-parts", default="",
+                   help="with --workload batch --profile-kernels: split the workload into its expressions "
+                        "with a trans() (2-D tiles) and the rest (flat chunks), build each as a batch of its "
+                        "own with this configuration (vec,ept,waves,grid_mult) and launch each 3 times")
     return p.parse_args()
 
 
@@ -638,6 +642,18 @@ def bench_batch(args):
         mats = [coot.Mat.from_numpy(o) for o in synth.operands_for(spec, g)]
         exprs.append(_tree(coot, spec, mats))
     t_gen = time.perf_counter() - t0
+    if args.profile_kernels and args.batch_parts:
+        cfg = tuple(int(x) for x in args.batch_parts.split(","))
+        has_t = [any(it[0] == "trans" for it in coot.flatten(e).postfix) for e in exprs]
+        parts = {"2d": coot.Batch([(e, None) for e, t in zip(exprs, has_t) if t], cfg=cfg),
+                 "flat": coot.Batch([(e, None) for e, t in zip(exprs, has_t) if not t], cfg=cfg)}
+        for _ in range(3):
+            for p in parts.values():
+                p.launch()
+        torch.cuda.synchronize()
+        print(json.dumps({"profiled": "batch parts x3", "cfg": cfg,
+                          "info": {k: p.info() for k, p in parts.items()}}), flush=True)
+        return
     t0 = time.perf_counter()
     b = coot.Batch([(e, None) for e in exprs])
     torch.cuda.synchronize()

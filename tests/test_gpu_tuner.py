@@ -199,3 +199,50 @@ def test_trained_cost_model_against_the_default(env):
     for h in h_tr + h_te:
         cc.coot_expr_release(h)
     cc.coot_costmodel_release(cm)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_dimension_tuning_module_matches_oracle(env, dtype):
+    """The tuning module's sum / mean / variance along each dimension (every tile shape,
+    vector width and tiles per CU of the tiled space, stage 2 included), launched through
+    coot_tune_launch on a ragged shape with a transposed leaf, against the oracle; then
+    coot_tune's exhaustive pick, evaluated through coot_reduce, against the oracle too."""
+    coot, cc, torch = env
+    from oracle import reduce as rd
+    R, C = 300, 170
+    A, B, Cm, D = synth.matrix_inputs(n_rows=R, n_cols=C, dtype=dtype)
+    gs = [coot.Mat.from_numpy(m) for m in (A, B, Cm, D)]
+    e = 2.0 * gs[0] + gs[1] % gs[2] - coot.trans(gs[3])
+    flat = coot.flatten(e)
+    h = coot.frontend.compiled(flat)
+    ops = [m.operand() for m in flat.mats]
+    Zo = ew.evaluate(flat.postfix, [A, B, Cm, D], flat.scalars, dtype)   # the leaves appear once, in this order
+    tol = 1e-6 if dtype == "f32" else 1e-12
+    space = cc.coot_tune_space(1)
+    for kind, dim in ((cc.COOT_RED_SUM, 0), (cc.COOT_RED_SUM, 1), (cc.COOT_RED_MEAN_DIM, 0), (cc.COOT_RED_VAR_DIM, 1)):
+        n_out = C if dim == 0 else R
+        out = coot.Mat.empty(1, n_out, dtype, "row") if dim == 0 else coot.Mat.empty(n_out, 1, dtype, "col")
+        if kind == cc.COOT_RED_VAR_DIM:
+            want = rd.var_dim(Zo, dim, dtype, 0)
+            scale = [abs(float(w)) for w in want]
+        else:
+            want = rd.sum_dim(Zo, dim, dtype) if kind == cc.COOT_RED_SUM else rd.mean_dim(Zo, dim, dtype)
+            cnt = R if dim == 0 else C
+            scale = [rd.sum_abs(v) / (1 if kind == cc.COOT_RED_SUM else cnt) for v in (Zo.T if dim == 0 else Zo)]
+        ok = cc.coot_tune_runnable(h, ops, out.operand(), kind, space, dim=dim)
+        assert sum(ok) >= 30
+        for cfg, run in zip(space, ok):
+            if not run:
+                continue
+            out.tensor.fill_(float("nan"))
+            cc.coot_tune_launch(h, ops, flat.scalars, out.operand(), kind, cfg, dim=dim)
+            torch.cuda.synchronize()
+            got = out.numpy().ravel()
+            for g, w, sc in zip(got, want, scale):
+                assert rd.rel_err(float(g), w, sc) <= tol, (kind, dim, cfg)
+        best, us = cc.coot_tune(h, ops, flat.scalars, out.operand(), kind, 1, dim=dim)
+        assert best in [tuple(c) for c in space] and us > 0
+        got = coot.frontend._reduce(e, kind, dim, False, lambda r, c: (1, c) if dim == 0 else (r, 1), best,
+                                    False).numpy().ravel()
+        for g, w, sc in zip(got, want, scale):
+            assert rd.rel_err(float(g), w, sc) <= tol, (kind, dim, best)
