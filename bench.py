@@ -64,7 +64,8 @@ def parse():
     p.add_argument("--batch-parts", default="",
                    help="with --workload batch --profile-kernels: split the workload into its expressions "
                         "with a trans() (2-D tiles) and the rest (flat chunks), build each as a batch of its "
-                        "own with this configuration (vec,ept,waves,grid_mult) and launch each 3 times")
+                        "own with this configuration (vec,ept,waves,grid_mult) and launch the 2-D one 3 times, "
+                        "then the flat one")
     return p.parse_args()
 
 
@@ -647,10 +648,10 @@ def bench_batch(args):
         has_t = [any(it[0] == "trans" for it in coot.flatten(e).postfix) for e in exprs]
         parts = {"2d": coot.Batch([(e, None) for e, t in zip(exprs, has_t) if t], cfg=cfg),
                  "flat": coot.Batch([(e, None) for e, t in zip(exprs, has_t) if not t], cfg=cfg)}
-        for _ in range(3):
-            for p in parts.values():
+        for p in parts.values():         # one batch after the other: a trace tells them apart by order
+            for _ in range(3):
                 p.launch()
-        torch.cuda.synchronize()
+            torch.cuda.synchronize()
         print(json.dumps({"profiled": "batch parts x3", "cfg": cfg,
                           "info": {k: p.info() for k, p in parts.items()}}), flush=True)
         return
