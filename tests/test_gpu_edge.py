@@ -1,7 +1,8 @@
 """Edge values through the fp32 / fp64 kernels, against the oracle (IEEE semantics:
 round-to-nearest-even, subnormals kept, signed zeros, infinities, NaN propagation).
 
-Every operator is correctly rounded on the device except log (the device library's,
+Every operator is correctly rounded on the device except log (binary32: the
+library's own table method, within 1 ulp; binary64: the device math library's,
 faithful): results must have the oracle's bits (any NaN matches any NaN), log
 within 1 ulp.  Covers every pair of edge values through each binary operator, each
 unary operator, exp at its overflow and underflow thresholds, the 2-D workload
