@@ -524,6 +524,21 @@ coot_status coot_tune(coot_expr* e, const coot_operand* operands, const double* 
  * from HBM (cache-cold timing).  Errors: COOT_ENOMEM, COOT_EHIP. */
 coot_status coot_flush_caches(void* stream);
 
+/* The in-memory code-object cache (the kernel cache of Section 4, before the disk):
+ * out[0] modules it holds, out[1] its capacity (least recently used modules are
+ * evicted past it; environment variable COOT_MODULE_CACHE, default 1024), out[2]
+ * evictions so far, out[3] modules that no expression holds any more, still loaded
+ * on the device.  An evicted module stays usable by the expressions that hold it; a
+ * later request for it is served from the disk cache.  Errors: COOT_EINVAL (NULL). */
+coot_status coot_cache_info(int64_t out[4]);
+
+/* Unload from the device every module that no expression holds any more (out[3]
+ * above), after waiting for the device to finish its work; *unloaded (may be NULL)
+ * receives how many.  A HIP graph recorded with kernels of a released expression must
+ * not be replayed after this call.  Call it while no stream is capturing.
+ * Errors: COOT_EHIP. */
+coot_status coot_cache_trim(int64_t* unloaded);
+
 /* Counters since process start: out[0] compiles, out[1] memory-cache hits,
  * out[2] disk-cache hits, out[3] launches, out[4] total compile milliseconds. */
 void coot_stats(double out[5]);

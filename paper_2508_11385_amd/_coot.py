@@ -92,6 +92,8 @@ _sig = {
     "coot_expr_release": (None, [_P]),
     "coot_expr_kernel_name": (C.c_int, [_P, C.c_int32, C.c_int32, C.POINTER(coot_launch_cfg), C.c_char_p,
                                         C.c_size_t]),
+    "coot_cache_info": (C.c_int, [C.POINTER(C.c_int64)]),
+    "coot_cache_trim": (C.c_int, [C.POINTER(C.c_int64)]),
     "coot_stats": (None, [C.POINTER(C.c_double)]),
     "coot_last_error": (C.c_char_p, []),
     "coot_debug_codegen": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_uint32, C.c_int32, C.c_int32, C.c_int32,
@@ -250,6 +252,18 @@ def coot_expr_kernel_name(h: int, mode: int = -1, dim: int = -1, cfg=None) -> st
     buf = C.create_string_buffer(256)
     _check(lib.coot_expr_kernel_name(h, mode, dim, _cfg(cfg), buf, 256))
     return buf.value.decode()
+
+
+def coot_cache_info() -> dict:
+    a = (C.c_int64 * 4)()
+    _check(lib.coot_cache_info(a))
+    return {"modules": a[0], "cap": a[1], "evictions": a[2], "awaiting_unload": a[3]}
+
+
+def coot_cache_trim() -> int:
+    n = C.c_int64()
+    _check(lib.coot_cache_trim(C.byref(n)))
+    return n.value
 
 
 def coot_stats() -> dict:

@@ -190,6 +190,20 @@ coot_status coot_expr_kernel_name(coot_expr* h, int32_t mode, int32_t dim, const
   });
 }
 
+coot_status coot_cache_info(int64_t out[4]) {
+  return guarded([&] {
+    if (!out) fail(COOT_EINVAL, "out is NULL");
+    cache_info(out);
+  });
+}
+
+coot_status coot_cache_trim(int64_t* unloaded) {
+  return guarded([&] {
+    const int64_t n = cache_trim();
+    if (unloaded) *unloaded = n;
+  });
+}
+
 void coot_stats(double out[5]) {
   if (!out) return;
   std::lock_guard<std::mutex> g(global_mutex());

@@ -174,7 +174,14 @@ struct Module {
   std::vector<char> code;   // code object (kept when not loaded, e.g. compile-only)
   bool loaded = false;
   hipFunction_t fn(const std::string& name);
+  ~Module();  // hands a loaded module to the unload queue (coot_cache_trim)
 };
+// Module cache: out[0] modules cached, out[1] the cap, out[2] evictions so far,
+// out[3] modules waiting to be unloaded.
+void cache_info(int64_t out[4]);
+// Synchronises the device and unloads every module no expression holds any more;
+// returns how many.
+int64_t cache_trim();
 
 // Compile (or fetch) the module for a request; load it on the current device
 // unless load == false (compile-only, used where no device exists).

@@ -16,6 +16,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <list>
 #include <unordered_map>
 
 #include "core.h"
@@ -160,9 +161,82 @@ hipFunction_t Module::fn(const std::string& name) {
   return f;
 }
 
-static std::unordered_map<std::string, std::shared_ptr<Module>>& module_map() {
-  static std::unordered_map<std::string, std::shared_ptr<Module>> m;
-  return m;
+// Process-wide modules by key, least recently used evicted past `cap` entries
+// (COOT_MODULE_CACHE, default 1024).  An evicted module stays alive while an
+// expression still holds it; once none does, its device code waits in `graveyard`
+// until coot_cache_trim unloads it after a device synchronisation (a kernel of it may
+// still be queued when its last holder goes).  Members are used under global_mutex.
+struct ModuleCache {
+  std::list<std::string> order;  // most recently used first
+  std::unordered_map<std::string, std::pair<std::shared_ptr<Module>, std::list<std::string>::iterator>> map;
+  size_t cap = 1024;
+  double evictions = 0;
+};
+static ModuleCache& module_cache() {
+  static ModuleCache* c = [] {
+    auto* mc = new ModuleCache;  // never destroyed: modules may outlive static destruction order
+    if (const char* v = std::getenv("COOT_MODULE_CACHE")) {
+      const long n = std::strtol(v, nullptr, 10);
+      if (n > 0) mc->cap = (size_t)n;
+    }
+    return mc;
+  }();
+  return *c;
+}
+static std::shared_ptr<Module> cache_find(const std::string& key) {
+  ModuleCache& c = module_cache();
+  auto it = c.map.find(key);
+  if (it == c.map.end()) return nullptr;
+  c.order.splice(c.order.begin(), c.order, it->second.second);
+  return it->second.first;
+}
+static void cache_put(const std::string& key, const std::shared_ptr<Module>& m) {
+  ModuleCache& c = module_cache();
+  c.order.push_front(key);
+  c.map[key] = {m, c.order.begin()};
+  while (c.map.size() > c.cap) {
+    c.map.erase(c.order.back());
+    c.order.pop_back();
+    c.evictions += 1;
+  }
+}
+
+static std::mutex& graveyard_mutex() {
+  static std::mutex* m = new std::mutex;
+  return *m;
+}
+static std::vector<hipModule_t>& graveyard() {
+  static auto* v = new std::vector<hipModule_t>;
+  return *v;
+}
+
+Module::~Module() {
+  if (loaded && mod) {
+    std::lock_guard<std::mutex> g(graveyard_mutex());
+    graveyard().push_back(mod);
+  }
+}
+
+void cache_info(int64_t out[4]) {
+  std::lock_guard<std::mutex> g(global_mutex());
+  const ModuleCache& c = module_cache();
+  out[0] = (int64_t)c.map.size();
+  out[1] = (int64_t)c.cap;
+  out[2] = (int64_t)c.evictions;
+  std::lock_guard<std::mutex> g2(graveyard_mutex());
+  out[3] = (int64_t)graveyard().size();
+}
+
+int64_t cache_trim() {
+  std::vector<hipModule_t> dead;
+  {
+    std::lock_guard<std::mutex> g(graveyard_mutex());
+    dead.swap(graveyard());
+  }
+  if (dead.empty()) return 0;
+  hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  for (hipModule_t m : dead) hip_check(hipModuleUnload(m), "hipModuleUnload");
+  return (int64_t)dead.size();
 }
 
 // The module of one generated source, cached under the request key `rk` of `owner`
@@ -205,8 +279,8 @@ std::shared_ptr<Module> find_loaded_module(Expr& e, const Request& rq) {
   std::shared_ptr<Module> m;
   {
     std::lock_guard<std::mutex> g(global_mutex());
-    auto it = module_map().find(key);
-    if (it != module_map().end() && it->second->loaded) m = it->second;
+    m = cache_find(key);
+    if (m && !m->loaded) m = nullptr;
   }
   if (!m)
     fail(COOT_EINVAL, "the kernels of this reduction are not loaded: run coot_expr_prepare or coot_reduce "
@@ -236,12 +310,8 @@ static std::shared_ptr<Module> module_for(Expr& e, const std::string& rk, const 
   std::shared_ptr<Module> m;
   {
     std::lock_guard<std::mutex> g(global_mutex());
-    auto& mm = module_map();
-    auto it = mm.find(key);
-    if (it != mm.end()) {
-      m = it->second;
-      stats().mem_hits += 1;
-    }
+    m = cache_find(key);
+    if (m) stats().mem_hits += 1;
   }
   if (!m) {
     // compile without holding the global lock so that several host threads can compile at once
@@ -257,13 +327,10 @@ static std::shared_ptr<Module> module_for(Expr& e, const std::string& rk, const 
       disk_store(key, fresh->code);
     }
     std::lock_guard<std::mutex> g(global_mutex());
-    auto& mm = module_map();
-    auto it = mm.find(key);
-    if (it != mm.end()) {
-      m = it->second;  // another thread finished first
-    } else {
+    m = cache_find(key);  // another thread may have finished first
+    if (!m) {
       m = fresh;
-      mm[key] = m;
+      cache_put(key, m);
     }
     if (from_disk) stats().disk_hits += 1;
     else {

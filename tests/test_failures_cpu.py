@@ -86,3 +86,43 @@ def test_damaged_disk_cache_file_is_recompiled(tmp_path, damage):
     assert open(path, "rb").read() == whole  # rewritten whole
     s = _fresh_process(tmp_path)
     assert (s["compiles"], s["disk_hits"]) == (0, 1)
+
+
+_LRU_CHILD = r"""
+import json, sys
+sys.path.insert(0, sys.argv[1])
+from paper_2508_11385_amd import _coot as cc
+ops = ["neg", "abs", "sqrt", "exp", "square", "log"]
+def compile_one(op):
+    h = cc.coot_expr_compile([("load", 0), (op,), ("load", 1), ("sub",)], [(cc.COOT_F32, 0)] * 2, 0)
+    cc.coot_expr_prepare(h, -1, rflags=cc.COOT_PF_COMPILE_ONLY)
+    return h
+hs = [compile_one(op) for op in ops]
+out = {"after_six": cc.coot_cache_info(), "stats_six": cc.coot_stats()}
+cc.coot_expr_prepare(hs[0], -1, rflags=cc.COOT_PF_COMPILE_ONLY)   # held by its expression: no lookup
+out["stats_held"] = cc.coot_stats()
+h2 = compile_one(ops[0])                                            # evicted: back from the disk cache
+out["stats_again"] = cc.coot_stats()
+out["after_again"] = cc.coot_cache_info()
+out["trimmed"] = cc.coot_cache_trim()                               # nothing was loaded on a device
+print(json.dumps(out))
+"""
+
+
+def test_module_cache_evicts_least_recently_used(tmp_path):
+    """A memory cache capped at 3 modules (COOT_MODULE_CACHE) over six distinct modules
+    keeps the three most recent and evicts the rest; an expression keeps its own module;
+    a new expression asking for an evicted module gets it from the disk cache."""
+    env = dict(os.environ, COOT_CACHE_DIR=str(tmp_path), COOT_MODULE_CACHE="3")
+    env.pop("COOT_HIPRTC_EXTRA", None)
+    env.pop("COOT_NO_DISK_CACHE", None)
+    r = subprocess.run([sys.executable, "-c", _LRU_CHILD, ROOT], env=env, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode == 0, r.stderr
+    o = json.loads(r.stdout.strip().splitlines()[-1])
+    assert o["after_six"] == {"modules": 3, "cap": 3, "evictions": 3, "awaiting_unload": 0}
+    assert o["stats_six"]["compiles"] == 6
+    assert o["stats_held"] == o["stats_six"]
+    assert o["stats_again"]["compiles"] == 6 and o["stats_again"]["disk_hits"] == o["stats_six"]["disk_hits"] + 1
+    assert o["after_again"]["modules"] == 3 and o["after_again"]["evictions"] == 4
+    assert o["trimmed"] == 0

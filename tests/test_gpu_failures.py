@@ -107,3 +107,63 @@ def test_fused_eval_is_recorded_into_a_graph_and_replays(env):
         torch.cuda.synchronize()
         want = ew.evaluate(zp, mats, [2.0], "f32")
         assert np.array_equal(z.numpy(), want), rep
+
+
+_TRIM_CHILD = r"""
+import json, os, sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+import torch
+import paper_2508_11385_amd as coot
+from paper_2508_11385_amd import _coot as cc
+from oracle import elementwise as ew
+from tests.exact import ulp_distance
+coot.init(0)
+g = np.random.default_rng(7)
+A = g.uniform(0.5, 2.0, (300, 7)).astype(np.float32)
+B = g.uniform(-1.0, 1.0, (300, 7)).astype(np.float32)
+mA, mB = coot.Mat.from_numpy(A), coot.Mat.from_numpy(B)
+out = coot.Mat.empty(300, 7, "f32")
+ok = True
+def run(op):
+    post = [("load", 0), (op,), ("load", 1), ("sub",)]
+    h = cc.coot_expr_compile(post, [(cc.COOT_F32, 0)] * 2, 0)
+    cc.coot_expr_eval(h, [mA.operand(), mB.operand()], [], out.operand(), None,
+                      torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    good = float(np.max(ulp_distance(out.numpy(), ew.evaluate(post, [A, B], [], "f32")))) <= (1 if op in ("exp", "log") else 0)
+    cc.coot_expr_release(h)   # queued work done; its module is now held by the cache alone
+    return good
+ops = ["neg", "abs", "sqrt", "square", "exp", "log"]
+for op in ops:
+    ok &= run(op)
+res = {"ok": ok, "info": cc.coot_cache_info()}
+res["trimmed"] = cc.coot_cache_trim()
+res["info_after"] = cc.coot_cache_info()
+for op in ops:                                  # evicted and unloaded modules come back from the disk cache
+    ok &= run(op)
+res["ok_again"] = ok
+print(json.dumps(res), flush=True)
+"""
+
+
+def test_module_cache_eviction_and_trim_on_device(tmp_path):
+    """Six modules loaded and used through a memory cache capped at two, each
+    expression released after its launch: the four evicted modules wait for unloading,
+    coot_cache_trim unloads them after a device synchronisation, and every expression
+    evaluates correctly again afterwards (from the disk cache), in a process of its own."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, COOT_CACHE_DIR=str(tmp_path), COOT_MODULE_CACHE="2")
+    env.pop("COOT_HIPRTC_EXTRA", None)
+    r = subprocess.run([sys.executable, "-c", _TRIM_CHILD, root], env=env, capture_output=True, text=True,
+                       timeout=240)
+    assert r.returncode == 0, r.stderr[-3000:]
+    o = json.loads(r.stdout.strip().splitlines()[-1])
+    assert o["ok"] and o["ok_again"]
+    assert o["info"] == {"modules": 2, "cap": 2, "evictions": 4, "awaiting_unload": 4}
+    assert o["trimmed"] == 4
+    assert o["info_after"]["awaiting_unload"] == 0
