@@ -20,6 +20,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -57,7 +58,8 @@ def parse():
     p.add_argument("--tuner-reps", type=int, default=5, help="timing rounds per configuration")
     p.add_argument("--tuner-models", type=int, default=5, help="networks in the cost-model ensemble")
     p.add_argument("--tuner-dump", default="", help="write the timing tables here (.npz)")
-    p.add_argument("--tuner-out", default=os.path.join(ROOT, "gpurun_out", "costmodel_mi355x.bin"))
+    p.add_argument("--tuner-out", default=os.path.join(tempfile.gettempdir(), "costmodel_mi355x.bin"),
+                   help="where the trained cost model is saved")
     p.add_argument("--tuner-workers", type=int, default=14, help="processes compiling tuning modules")
     p.add_argument("--profile-kernels", action="store_true",
                    help="run the copy probe and each kernel of one step 3 times, print their names, exit")

@@ -5,7 +5,7 @@ trees, and trees with transposed leaves that take the tiled kernels).
 
 Compiler combining of the narrowing and widening conversions around the operators
 once crashed instruction selection inside hipRTC, which aborts the calling process;
-on a GPU machine that takes every test of the process with it.  This test finds such a
+in a GPU test run that takes every test of the process with it.  This test finds such a
 crash here, before any device run."""
 import pytest
 
