@@ -32,7 +32,7 @@ const std::vector<std::pair<std::string, std::string>>& device_headers() {
 std::string Request::key() const {
   const char b[] = {(char)(mode + 2), (char)(dim + 2), (char)comp,        (char)fam,           (char)var.vec,
                     (char)var.ept,    (char)(var.tr & 0xff), (char)(var.tr >> 8), (char)(var.tc & 0xff),
-                    (char)(var.tc >> 8), (char)all_variants, (char)plain_store};
+                    (char)(var.tc >> 8), (char)all_variants, (char)plain_store, (char)stream_ld};
   return std::string(b, sizeof b);
 }
 
@@ -237,7 +237,8 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
           const std::string nm = variant_name(e, rt, v, rq.fam == FAM_FLAT ? ept : 0);
           std::string call;
           if (rq.mode < 0) {
-            call = rq.fam == FAM_FLAT ? "coot::flat_eval<X, " + std::to_string(v) + ", " + std::to_string(ept) + ">(a)"
+            call = rq.fam == FAM_FLAT ? "coot::flat_eval<X, " + std::to_string(v) + ", " + std::to_string(ept) +
+                                            (rq.stream_ld ? ", true" : ", false") + ">(a)"
                                       : "coot::tiled_eval<X, " + std::to_string(v) + ", " + tt + ">(a)";
           } else if (is_dim_kind(rq.mode) && rq.dim >= 0) {
             call = "coot::tiled_reduce_dim<X, " + std::to_string(rq.dim) + ", " + comp + ", " + std::to_string(v) +
@@ -274,8 +275,9 @@ std::string generate(const Expr& e, const Request& rq, const std::string& h, Ker
     if (rq.fam == FAM_FLAT) {
       names->stage1 = "coot_flat_" + hs + "_v" + std::to_string(V) + "e" + std::to_string(E);
       names->stage1_fallback = "coot_flat_" + hs + "_v1e" + std::to_string(E);
-      wrap(names->stage1, "coot::flat_eval<X, " + std::to_string(V) + ", " + std::to_string(E) + ">(a)", 512);
-      if (V != 1) wrap(names->stage1_fallback, "coot::flat_eval<X, 1, " + std::to_string(E) + ">(a)", 512);
+      const std::string nt = rq.stream_ld ? ", true" : ", false";
+      wrap(names->stage1, "coot::flat_eval<X, " + std::to_string(V) + ", " + std::to_string(E) + nt + ">(a)", 512);
+      if (V != 1) wrap(names->stage1_fallback, "coot::flat_eval<X, 1, " + std::to_string(E) + nt + ">(a)", 512);
     } else {
       names->stage1 = "coot_tile_" + hs + "_v" + std::to_string(V) + tile_tag(rq);
       names->stage1_fallback = "coot_tile_" + hs + "_v1" + tile_tag(rq);

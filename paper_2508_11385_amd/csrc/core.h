@@ -130,6 +130,9 @@ bool tile_shape_ok(int tr, int tc);
 // padded tr x (tc + 1) tile per transposed leaf); the library keeps this <= 64 KiB.
 size_t tile_lds_bytes(int n_p1, int dtype, int tr, int tc);
 constexpr size_t kTileLdsMax = 65536;
+// Flat evaluations whose operands exceed this many bytes together load them
+// non-temporally: the MI355X's Infinity Cache holds 256 MiB.
+constexpr size_t kStreamLoadBytes = size_t(256) << 20;
 // Tile shapes the autotuner tries (those whose staging fits kTileLdsMax).
 const std::vector<std::pair<int, int>>& tile_shapes();
 
@@ -148,6 +151,7 @@ struct Request {
   Variant var;
   bool all_variants = false;  // tuning module: every vec x ept (flat) or vec (tiled) variant
   bool plain_store = false;   // results stored with plain (cached) stores: the unfused comparator's temporaries
+  bool stream_ld = false;     // flat evaluation: non-temporal leaf loads (operands beyond the Infinity Cache)
   std::string key() const;
 };
 

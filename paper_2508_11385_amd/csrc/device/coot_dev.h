@@ -163,10 +163,12 @@ typedef u32 u32x4 __attribute__((ext_vector_type(4)));
 
 // Flat full reductions read every operand once, in order, and write nothing but
 // their records: their 8- to 32-byte loads are non-temporal (NT), measured faster
-// (accu over 2^28 fp32 172 -> 156 us).  Flat element-wise kernels gained 4-6 % and
-// keep plain loads (the autotuner's tables and its learned model were measured with
-// them); the tiled walks read 256-byte column segments and keep plain loads (with
-// NT loads the 4096 x 4096 Z tile kernel took 78 instead of 53 us).
+// (accu over 2^28 fp32 172 -> 156 us).  Flat element-wise kernels take NT loads when
+// their operands together exceed the Infinity Cache (256 MiB), where no later kernel
+// could find them there anyway; below that, plain loads leave them cached for the
+// kernels that re-read them next.  The tiled walks read 256-byte column segments and
+// keep plain loads (with NT loads the 4096 x 4096 Z tile kernel took 78 instead of
+// 53 us).
 template <typename T, int V, bool NT = false>
 __device__ __forceinline__ vt<T, V> ldv(const T* p) {
   vt<T, V> r;
@@ -423,7 +425,7 @@ __device__ __forceinline__ typename X::T leaf_at(const coot_kargs& a, int k, i64
 // Grid-stride over V-element groups, E groups in flight per thread per trip,
 // then a scalar tail of n mod V elements handled by the last workgroup.
 // ===========================================================================
-template <class X, int V, int E>
+template <class X, int V, int E, bool NT = false>
 __device__ __forceinline__ void flat_eval(const coot_kargs& a) {
   typedef typename X::T T;
   const i64 n = a.n_rows * a.n_cols;
@@ -437,7 +439,7 @@ __device__ __forceinline__ void flat_eval(const coot_kargs& a) {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const i64 v = b + (i64)e * bs;
-      if (v < nv) load_flat<X, V>(a, v, x[e]);
+      if (v < nv) load_flat<X, V, NT>(a, v, x[e]);
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {

@@ -246,6 +246,13 @@ Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, in
   if (rq.fam == FAM_TILE && rq.var.vec > tile_vec_cap(tr, tc)) rq.var.vec = tile_vec_cap(tr, tc);
   if (rq.fam == FAM_FLAT) rq.var.tr = rq.var.tc = 0;
   if (rq.fam == FAM_TILE) rq.var.ept = 0;
+  if (rq.fam == FAM_FLAT && mode < 0) {
+    // operands larger than the Infinity Cache together: streamed past it (non-temporal loads)
+    size_t leaf_bytes = 0;
+    for (size_t k = 0; k < e.slots.size(); ++k)
+      if (ops[k].kind != COOT_BCAST) leaf_bytes += (size_t)(R * C) * dtype_size(e.dtype);
+    rq.stream_ld = leaf_bytes > kStreamLoadBytes;
+  }
   return rq;
 }
 

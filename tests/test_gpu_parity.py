@@ -310,6 +310,32 @@ def test_full_size_matrix_workload(coot, dtype):
         assert rd.rel_err(float(s1[i]), rd.exact_sum(row), rd.sum_abs(row)) <= REL[dtype]
 
 
+@pytest.mark.parametrize("dtype,shape", [("f32", (8192, 8192)), ("f64", (4096, 4200))])
+def test_flat_evaluation_beyond_the_infinity_cache(coot, dtype, shape):
+    """W over operands larger than 256 MiB together (512 MiB fp32, 262.5 MiB fp64): the
+    flat kernel then loads them non-temporally; sampled outputs against the oracle,
+    and a misaligned view of the same data (the one-element fallback kernel)."""
+    import torch
+    R, C = shape
+    g = synth.rng_for(49, 0 if dtype == "f32" else 1)
+    A = synth.uniform(g, (R, C), dtype)
+    B = synth.uniform(g, (R, C), dtype)
+    gA, gB = up(coot, A), up(coot, B)
+    W = coot.eval(_w(coot, gA, gB)).numpy()
+    r = np.random.default_rng(3)
+    rows, cols = r.integers(0, R, 50_000), r.integers(0, C, 50_000)
+    wo = ew.evaluate_at(W_POST, [A, B], [1.0], dtype, rows, cols)
+    assert np.max(ulp_distance(W[rows, cols], wo)) <= 1
+    del W
+    # the same values one element off a 16-byte boundary
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    base = torch.empty(R * C + 1, dtype=tdt, device="cuda")
+    base[1:].copy_(gA.tensor.t().reshape(-1))
+    mA = coot.Mat(base[1:].view(C, R).t(), dtype)
+    W1 = coot.eval(_w(coot, mA, gB)).numpy()
+    assert np.max(ulp_distance(W1[rows, cols], wo)) <= 1
+
+
 def test_full_size_integer_workload(coot):
     A, B, C = synth.int_inputs(8192, "u32")
     got = coot.eval((up(coot, A) + up(coot, B)) % up(coot, C)).numpy()
