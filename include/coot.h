@@ -532,8 +532,9 @@ coot_status coot_flush_caches(void* stream);
  * later request for it is served from the disk cache.  Errors: COOT_EINVAL (NULL). */
 coot_status coot_cache_info(int64_t out[4]);
 
-/* Unload from the device every module that no expression holds any more (out[3]
- * above), after waiting for the device to finish its work; *unloaded (may be NULL)
+/* Unload every module that no expression holds any more (out[3] above), each from
+ * the device it was loaded on after waiting for that device to finish its work (the
+ * calling thread's current device is kept); *unloaded (may be NULL)
  * receives how many.  A HIP graph recorded with kernels of a released expression must
  * not be replayed after this call.  Call it while no stream is capturing.
  * Errors: COOT_EHIP. */

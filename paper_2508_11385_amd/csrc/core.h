@@ -177,6 +177,7 @@ struct Module {
   KernelNames names;
   std::vector<char> code;   // code object (kept when not loaded, e.g. compile-only)
   bool loaded = false;
+  int device = 0;           // the device it is loaded on
   hipFunction_t fn(const std::string& name);
   ~Module();  // hands a loaded module to the unload queue (coot_cache_trim)
 };

@@ -4,13 +4,15 @@
 // found and cached, so the cost is paid once.  Here every (expression
 // signature, request) gets its own module: hipRTC compiles the generated source
 // for gfx950, the code object is kept in memory (process-wide map keyed by a
-// 128-bit hash of source + options + compiler version) and on disk
+// 128-bit hash of source + options + compiler version, least recently used entries
+// evicted past a cap) and on disk
 // (COOT_CACHE_DIR, default ~/.cache/coot; a header with magic, key and checksum
 // guards every file, and a bad file is simply recompiled).
 #include <hip/hiprtc.h>
 #include <sys/stat.h>
 #include <unistd.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -205,15 +207,15 @@ static std::mutex& graveyard_mutex() {
   static std::mutex* m = new std::mutex;
   return *m;
 }
-static std::vector<hipModule_t>& graveyard() {
-  static auto* v = new std::vector<hipModule_t>;
+static std::vector<std::pair<int, hipModule_t>>& graveyard() {  // (device, module)
+  static auto* v = new std::vector<std::pair<int, hipModule_t>>;
   return *v;
 }
 
 Module::~Module() {
   if (loaded && mod) {
     std::lock_guard<std::mutex> g(graveyard_mutex());
-    graveyard().push_back(mod);
+    graveyard().push_back({device, mod});
   }
 }
 
@@ -228,14 +230,23 @@ void cache_info(int64_t out[4]) {
 }
 
 int64_t cache_trim() {
-  std::vector<hipModule_t> dead;
+  std::vector<std::pair<int, hipModule_t>> dead;
   {
     std::lock_guard<std::mutex> g(graveyard_mutex());
     dead.swap(graveyard());
   }
   if (dead.empty()) return 0;
-  hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
-  for (hipModule_t m : dead) hip_check(hipModuleUnload(m), "hipModuleUnload");
+  std::sort(dead.begin(), dead.end());
+  int cur = 0;
+  hip_check(hipGetDevice(&cur), "hipGetDevice");
+  for (size_t i = 0; i < dead.size(); ++i) {
+    if (i == 0 || dead[i].first != dead[i - 1].first) {  // each device that holds some: drained first
+      hip_check(hipSetDevice(dead[i].first), "hipSetDevice");
+      hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    }
+    hip_check(hipModuleUnload(dead[i].second), "hipModuleUnload");
+  }
+  hip_check(hipSetDevice(cur), "hipSetDevice");
   return (int64_t)dead.size();
 }
 
@@ -342,6 +353,7 @@ static std::shared_ptr<Module> module_for(Expr& e, const std::string& rk, const 
     std::lock_guard<std::mutex> g(global_mutex());
     if (!m->loaded) {
       hip_check(hipModuleLoadData(&m->mod, m->code.data()), "hipModuleLoadData");
+      hip_check(hipGetDevice(&m->device), "hipGetDevice");
       m->loaded = true;
     }
   }
