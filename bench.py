@@ -155,7 +155,7 @@ def main():
         # Z under every tile shape and vector width the autotuner can pick (its counters do
         # not depend on the launch's workgroups per CU)
         zvariants = {}
-        for tr, tc in ((64, 64), (128, 32), (32, 128), (256, 16), (128, 64), (32, 32)):
+        for tr, tc in sorted({(c[4], c[5]) for c in cc.coot_tune_space(1)}):
             for vec in (1, 2, 4):
                 if vec <= tr * tc // 256:
                     zc = (vec, 0, 0, 0, tr, tc)

@@ -404,8 +404,8 @@ void coot_batch_release(coot_batch* b);
 /* Write the configuration space of a kernel family (0 flat, 1 tiled) into
  * cfgs[0..cap) and return its size (cfgs may be NULL to query the size).
  * Flat: vec {1,2,4} x ept {1,2,4,8} x waves {1,2,4,8} x grid_mult {2,4,8,16} = 192
- * (tile 0 x 0); tiled: tile {64x64, 128x32, 32x128, 256x16, 128x64, 32x32} x
- * vec {1,2,4} x grid_mult {2,4,8,16} = 72 (a tile whose transposed-leaf staging
+ * (tile 0 x 0); tiled: tile {64x64, 128x32, 32x128, 256x16, 128x64, 32x32, 64x16,
+ * 16x64} x vec {1,2,4} x grid_mult {2,4,8,16} = 96 (a tile whose transposed-leaf staging
  * exceeds 64 KiB, or whose vec exceeds tile_r * tile_c / 256, cannot run).  For the 16-bit types vec 8
  * (16-byte groups) is valid too: their tuning modules hold those variants,
  * coot_tune_table accepts them (NaN for other types) and coot_tune's exhaustive

@@ -47,7 +47,8 @@ size_t tile_lds_bytes(int n_p1, int dtype, int tr, int tc) {
 }
 
 const std::vector<std::pair<int, int>>& tile_shapes() {
-  static const std::vector<std::pair<int, int>> v = {{64, 64}, {128, 32}, {32, 128}, {256, 16}, {128, 64}, {32, 32}};
+  static const std::vector<std::pair<int, int>> v = {{64, 64}, {128, 32}, {32, 128}, {256, 16},
+                                                      {128, 64}, {32, 32},  {64, 16},  {16, 64}};
   return v;
 }
 
