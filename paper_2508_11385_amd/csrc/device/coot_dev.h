@@ -494,7 +494,7 @@ __device__ __forceinline__ void consume(A& acc, Ext<typename X::T, RK>& ext, con
 // RK_SUMSQ also tracks the largest magnitude and applies the rescaling factor;
 // RK_VAR1 feeds the lane's variance state.
 template <class X, int RK, class A>
-__device__ __forceinline__ void take(A& acc, Ext<typename X::T, RK>& ext, double& amax, typename X::T scale,
+__device__ __forceinline__ void take(A& acc, Ext<typename X::T, RK>& ext, typename X::T& amax, typename X::T scale,
                                      const typename X::T* L, const u64* sc);
 
 // Integer accumulator: plain wrap-around sum.
@@ -592,22 +592,28 @@ __device__ __forceinline__ void block_words_to_record(double h, double l, double
   }
 }
 
+// a lane's largest magnitude as the record's binary64 word (integers track none)
 template <typename T>
-__device__ __forceinline__ double abs_of(T v) {
+__device__ __forceinline__ double mag_word(T m) {
   if constexpr (is_int_t<T>::v) {
     return 0.0;
   } else {
-    return __builtin_fabs((double)v);
+    return (double)m;
   }
 }
 
+// amax: the lane's largest magnitude in the compute type (exact: a maximum rounds
+// nothing), widened to binary64 once per lane for the record.
 template <class X, int RK, class A>
-__device__ __forceinline__ void take(A& acc, Ext<typename X::T, RK>& ext, double& amax, typename X::T scale,
+__device__ __forceinline__ void take(A& acc, Ext<typename X::T, RK>& ext, typename X::T& amax, typename X::T scale,
                                      const typename X::T* L, const u64* sc) {
   typedef typename X::T T;
   if constexpr (RK == RK_SUMSQ) {
     T val = X::f(L, sc);
-    amax = __builtin_fmax(amax, abs_of<T>(val));
+    if constexpr (sizeof(T) == 4)
+      amax = __builtin_fmaxf(amax, __builtin_fabsf(val));
+    else
+      amax = __builtin_fmax(amax, __builtin_fabs(val));
     val = val * scale;
     acc.add_prod(val, val);
   } else if constexpr (RK == RK_VAR1) {
@@ -753,7 +759,7 @@ __device__ __forceinline__ void flat_reduce(const coot_kargs& a) {
   acc.init();
   Ext<T, RK> ext;
   ext.init();
-  double amax = 0.0;  // largest magnitude (sum of squares: the rescaling decision)
+  T amax = (T)0;  // largest magnitude (sum of squares: the rescaling decision)
   const i64 n = a.n_rows * a.n_cols;
   const i64 nv = n / V;
   const int bs = blockDim.x;
@@ -788,7 +794,7 @@ __device__ __forceinline__ void flat_reduce(const coot_kargs& a) {
     }
   }
   PartRec* recs = (PartRec*)(SCALED ? (void*)((char*)a.ws2 + 64) : a.ws);
-  lane_to_record<T, RK, COMP>(acc, ext, amax, recs + blockIdx.x);
+  lane_to_record<T, RK, COMP>(acc, ext, mag_word(amax), recs + blockIdx.x);
 }
 
 // ===========================================================================
@@ -1001,7 +1007,7 @@ struct AllSink {
   typedef typename RedAcc<T, RK, COMP>::type Acc;
   Acc acc;
   Ext<T, RK> ext;
-  double amax;
+  T amax;
   T scale;
   __device__ __forceinline__ void begin_tile() {}
   __device__ __forceinline__ void elem(const coot_kargs& a, int, bool in, const T* L) {
@@ -1018,7 +1024,7 @@ __device__ __forceinline__ void tiled_reduce(const coot_kargs& a) {
   AllSink<X, RK, COMP, SCALED> s;
   s.acc.init();
   s.ext.init();
-  s.amax = 0.0;
+  s.amax = (T)0;
   s.scale = (T)1;
   if constexpr (SCALED) {
     const double* ctl = (const double*)a.ws2;
@@ -1027,7 +1033,7 @@ __device__ __forceinline__ void tiled_reduce(const coot_kargs& a) {
   }
   tiled_walk<X, V, TR, TC>(a, s);
   PartRec* recs = (PartRec*)(SCALED ? (void*)((char*)a.ws2 + 64) : a.ws);
-  lane_to_record<T, RK, COMP>(s.acc, s.ext, s.amax, recs + blockIdx.x);
+  lane_to_record<T, RK, COMP>(s.acc, s.ext, mag_word(s.amax), recs + blockIdx.x);
 }
 
 // ===========================================================================
