@@ -121,7 +121,7 @@ typedef struct {
  *             reduction along a dimension, the tiles per CU past which each
  *             workgroup folds a longer segment of tiles (default 8)
  *   tile_r, tile_c  output tile of the tiled kernels (transposed or strided leaves,
- *             dimension reductions), rows x columns: powers of two in [16, 256] with
+ *             dimension reductions), rows x columns: powers of two in [8, 256] with
  *             1024 <= tile_r * tile_c <= 8192, both given or both 0; the staged
  *             transposed leaves must fit 64 KiB of LDS (tile_r * (tile_c + 1) elements
  *             of the compute type each), else COOT_EINVAL.  A tall tile gives the
@@ -405,7 +405,8 @@ void coot_batch_release(coot_batch* b);
  * cfgs[0..cap) and return its size (cfgs may be NULL to query the size).
  * Flat: vec {1,2,4} x ept {1,2,4,8} x waves {1,2,4,8} x grid_mult {2,4,8,16} = 192
  * (tile 0 x 0); tiled: tile {64x64, 128x32, 32x128, 256x16, 128x64, 32x32, 64x16,
- * 16x64} x vec {1,2,4} x grid_mult {2,4,8,16} = 96 (a tile whose transposed-leaf staging
+ * 16x64, 128x8, 256x8, 128x16, 64x32} x vec {1,2,4} x grid_mult {2,4,8,16} = 144 (a
+ * tile whose transposed-leaf staging
  * exceeds 64 KiB, or whose vec exceeds tile_r * tile_c / 256, cannot run).  For the 16-bit types vec 8
  * (16-byte groups) is valid too: their tuning modules hold those variants,
  * coot_tune_table accepts them (NaN for other types) and coot_tune's exhaustive

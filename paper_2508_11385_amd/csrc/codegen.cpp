@@ -37,7 +37,7 @@ std::string Request::key() const {
 }
 
 bool tile_shape_ok(int tr, int tc) {
-  auto pow2 = [](int v) { return v >= 16 && v <= 256 && (v & (v - 1)) == 0; };
+  auto pow2 = [](int v) { return v >= 8 && v <= 256 && (v & (v - 1)) == 0; };
   return pow2(tr) && pow2(tc) && tr * tc >= 1024 && tr * tc <= 8192;
 }
 
@@ -47,8 +47,8 @@ size_t tile_lds_bytes(int n_p1, int dtype, int tr, int tc) {
 }
 
 const std::vector<std::pair<int, int>>& tile_shapes() {
-  static const std::vector<std::pair<int, int>> v = {{64, 64}, {128, 32}, {32, 128}, {256, 16},
-                                                      {128, 64}, {32, 32},  {64, 16},  {16, 64}};
+  static const std::vector<std::pair<int, int>> v = {{64, 64}, {128, 32}, {32, 128}, {256, 16}, {128, 64}, {32, 32},
+                                                      {64, 16}, {16, 64},  {128, 8},  {256, 8},  {128, 16}, {64, 32}};
   return v;
 }
 

@@ -122,7 +122,7 @@ void check_red_mode(const Expr& e, int mode);
 
 // Tiles of the tiled families: tr x tc output elements (rows x columns), 256 threads.
 // The tr / V threads of a column segment times tc columns must cover the 256 threads
-// (V <= tr * tc / 256); V divides both edges.  Edges are powers of two in [16, 256]
+// (V <= tr * tc / 256); V divides both edges.  Edges are powers of two in [8, 256]
 // with 1024 <= tr * tc <= 8192 (4 to 32 elements per thread).
 inline int tile_vec_cap(int tr, int tc) { return tr * tc / 256; }
 bool tile_shape_ok(int tr, int tc);

@@ -233,7 +233,7 @@ Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, in
   int tr = c.tile_r, tc = c.tile_c;
   if (tr) {
     if (!tile_shape_ok(tr, tc))
-      fail(COOT_EINVAL, "tile edges must be powers of two in [16, 256] with 1024 <= tile_r * tile_c <= 8192");
+      fail(COOT_EINVAL, "tile edges must be powers of two in [8, 256] with 1024 <= tile_r * tile_c <= 8192");
     if (rq.fam == FAM_TILE && tile_lds_bytes(e.n_p1, e.dtype, tr, tc) > kTileLdsMax)
       fail(COOT_EINVAL, "the staged transposed leaves of a " + std::to_string(tr) + " x " + std::to_string(tc) +
                             " tile exceed 64 KiB of LDS");

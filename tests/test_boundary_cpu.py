@@ -193,7 +193,7 @@ def test_costmodel_features_match_oracle_definition(cc):
     from oracle import features as of
     g = synth.rng_for(78)
     space = cc.coot_tune_space(0) + cc.coot_tune_space(1)
-    assert len(cc.coot_tune_space(0)) == 192 and len(cc.coot_tune_space(1)) == 96
+    assert len(cc.coot_tune_space(0)) == 192 and len(cc.coot_tune_space(1)) == 144
     for trial in range(25):
         dt = ["u32", "s32", "f32", "f64"][trial % 4]
         r, c = int(g.integers(1, 20000)), int(g.integers(1, 20000))
@@ -236,7 +236,7 @@ def test_runnable_configurations(cc):
     assert all(o == (c[0] == 1) for o, c in zip(ok, flat))
     tiled = cc.coot_tune_space(1)
     assert {(c[4], c[5]) for c in tiled} == {(64, 64), (128, 32), (32, 128), (256, 16), (128, 64), (32, 32),
-                                            (64, 16), (16, 64)}
+                                            (64, 16), (16, 64), (128, 8), (256, 8), (128, 16), (64, 32)}
     hz = cc.coot_expr_compile(Z, _ops(4), 1)
     ops = [_opnd(cc, 6, 8)] * 3 + [_opnd(cc, 8, 6)]                            # 6 rows: 2 | 6, 4 does not
     ok = cc.coot_tune_runnable(hz, ops, _opnd(cc, 6, 8), -1, tiled)

@@ -408,7 +408,8 @@ def test_caller_allocator_for_workspaces_and_temporaries(coot):
     assert all(np.array_equal(a, b) for a, b in zip(ref, run()))
 
 
-TILES = [(64, 64), (128, 32), (32, 128), (256, 16), (16, 256), (128, 64), (32, 32), (64, 16), (16, 64)]
+TILES = [(64, 64), (128, 32), (32, 128), (256, 16), (16, 256), (128, 64), (32, 32), (64, 16), (16, 64), (128, 8),
+         (256, 8), (128, 16), (64, 32)]
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
