@@ -543,18 +543,11 @@ coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, 
       return t_ms[2];
     };
     try {
-      // each part is timed on its own launch over its settings; the three fastest
-      // settings of each part (distinct tile shape, groups per thread, access width)
-      // are then paired in the graph, since the parts share the CUs' issue slots when
-      // side by side and the fastest alone need not pair best.
-      struct PartCfg {
-        float t;
-        int ts, g, gm;
-        bool vec;
-      };
-      std::vector<PartCfg> top[2];
+      // each part is tuned on its own launch (the other part's settings do not affect it)
       for (int part = 0; part < 2; ++part) {
-        std::vector<PartCfg> all;
+        float bt = 1e30f;
+        int bts = b->ts[part], bg = b->g[part], bgm = b->gm[part];
+        bool bvec = b->allow_vec[part];
         // tile shapes: 16 x 16 by one wave, 32 x 32 by four, two or one wave(s)
         for (auto shape : {std::pair<int, int>{16, 1}, {32, 1}, {32, 2}, {32, 4}}) {
           for (bool vec : {true, false}) {
@@ -562,67 +555,54 @@ coot_status coot_batch_tune(coot_batch* b, void* stream, coot_launch_cfg* best, 
             b->g[part] = shape.second;
             b->allow_vec[part] = vec;
             build_tiles(b);
-            PartCfg bestg{1e30f, shape.first, shape.second, 2, vec};
             for (int gm : {2, 4, 8, 16}) {
               b->gm[part] = gm;
               set_grids(b);
               const float t = median_ms([&] { launch_part(b, part, s); });
-              if (t < bestg.t) bestg = {t, shape.first, shape.second, gm, vec};
+              if (t < bt) {
+                bt = t;
+                bts = shape.first;
+                bg = shape.second;
+                bgm = gm;
+                bvec = vec;
+              }
             }
-            all.push_back(bestg);
           }
         }
-        std::sort(all.begin(), all.end(), [](const PartCfg& x, const PartCfg& y) { return x.t < y.t; });
-        all.resize(std::min<size_t>(3, all.size()));
-        top[part] = all;
+        b->ts[part] = bts;
+        b->g[part] = bg;
+        b->gm[part] = bgm;
+        b->allow_vec[part] = bvec;
       }
       // then the graph: the parts one after the other (each with its own best grid), or
       // side by side.  A persistent grid that alone fills every CU leaves the other part
       // no room until it drains, so side by side also tries smaller grid pairs that let
       // both stay resident together.
-      bool best_c = false;
-      int best_gm[2] = {top[0][0].gm, top[1][0].gm};
-      PartCfg best_p[2] = {top[0][0], top[1][0]};
-      total = 1e30f;
-      for (const PartCfg& c0 : top[0]) {
-        for (const PartCfg& c1 : top[1]) {
-          const PartCfg pc[2] = {c0, c1};
-          for (int part = 0; part < 2; ++part) {
-            b->ts[part] = pc[part].ts;
-            b->g[part] = pc[part].g;
-            b->allow_vec[part] = pc[part].vec;
-          }
-          build_tiles(b);
-          auto try_graph = [&](bool c, int g0, int g1) {
-            b->concurrent = c;
-            b->gm[0] = g0;
-            b->gm[1] = g1;
-            set_grids(b);
-            capture(b);
-            const float t = median_ms([&] { hip_check(hipGraphLaunch(b->exec, s), "hipGraphLaunch"); });
-            if (t < total) {
-              total = t;
-              best_c = c;
-              best_gm[0] = g0;
-              best_gm[1] = g1;
-              best_p[0] = c0;
-              best_p[1] = c1;
-            }
-          };
-          try_graph(false, c0.gm, c1.gm);
-          try_graph(true, c0.gm, c1.gm);
-          if (b->n_flat_tiles > 0 && b->n_flat_tiles < (int)(b->tiles.size() / 2))
-            for (int g1 : {1, 2, 3, 4, 6})
-              for (int g0 : {1, 2, 4, 8})
-                if (g1 < c1.gm || g0 < c0.gm) try_graph(true, g0, g1);
-        }
-      }
-      for (int part = 0; part < 2; ++part) {
-        b->ts[part] = best_p[part].ts;
-        b->g[part] = best_p[part].g;
-        b->allow_vec[part] = best_p[part].vec;
-      }
       build_tiles(b);
+      const int gm_best[2] = {b->gm[0], b->gm[1]};
+      bool best_c = false;
+      int best_gm[2] = {gm_best[0], gm_best[1]};
+      total = 1e30f;
+      auto try_graph = [&](bool c, int g0, int g1) {
+        b->concurrent = c;
+        b->gm[0] = g0;
+        b->gm[1] = g1;
+        set_grids(b);
+        capture(b);
+        const float t = median_ms([&] { hip_check(hipGraphLaunch(b->exec, s), "hipGraphLaunch"); });
+        if (t < total) {
+          total = t;
+          best_c = c;
+          best_gm[0] = g0;
+          best_gm[1] = g1;
+        }
+      };
+      try_graph(false, gm_best[0], gm_best[1]);
+      try_graph(true, gm_best[0], gm_best[1]);
+      if (b->n_flat_tiles > 0 && b->n_flat_tiles < (int)(b->tiles.size() / 2))
+        for (int g1 : {1, 2, 3, 4, 6})
+          for (int g0 : {1, 2, 4, 8})
+            if (g1 < gm_best[1] || g0 < gm_best[0]) try_graph(true, g0, g1);
       b->concurrent = best_c;
       b->gm[0] = best_gm[0];
       b->gm[1] = best_gm[1];
