@@ -47,8 +47,10 @@ def parse():
     p.add_argument("--tune", default="exhaustive", choices=["exhaustive", "none"],
                    help="launch configurations of Z and W: the exhaustive autotuner's pick (before the timed "
                         "region; the step with the library defaults is timed too) or the library defaults")
-    p.add_argument("--z-cfg", default="", help="launch configuration vec,ept,waves,grid_mult for Z (default: library's)")
-    p.add_argument("--w-cfg", default="", help="launch configuration vec,ept,waves,grid_mult for W (default: library's)")
+    p.add_argument("--z-cfg", default="", help="launch configuration vec,ept,waves,grid_mult[,tile_r,tile_c] for Z "
+                                              "(default: the autotuner's pick)")
+    p.add_argument("--w-cfg", default="", help="launch configuration vec,ept,waves,grid_mult for W "
+                                              "(default: the autotuner's pick)")
     p.add_argument("--batch-fused-sample", type=int, default=500,
                    help="expressions timed with the plain fused kernel, one launch each")
     p.add_argument("--tuner-train", type=int, default=1350, help="training signatures (~50,000 timings)")
@@ -115,16 +117,19 @@ def main():
     fused = handles(0)
     unfused = handles(cc.COOT_CF_UNFUSED)
 
-    # launch configurations of the element-wise kernels: the project's autotuner (exhaustive
-    # over the family's space, cold-cache timings), run once before any timed region
+    # launch configurations of the step's statements: the ones given on the command line,
+    # else the project's autotuner (exhaustive over the family's space: repeated-call
+    # timings, near-ties broken by cache-cold ones), run once before any timed region
     cfgs = {"Z": None, "W": None, "S0": None, "S1": None}
     for k, v in (("Z", args.z_cfg), ("W", args.w_cfg)):
         if v:
             cfgs[k] = tuple(int(x) for x in v.split(","))
     t0 = time.perf_counter()
     if args.tune == "exhaustive":
-        cfgs["Z"] = cc.coot_tune(fused[0], zops, zf.scalars, zo, -1, 1, stream=stream)[0]
-        cfgs["W"] = cc.coot_tune(fused[1], wops, wf.scalars, wo, -1, 1, stream=stream)[0]
+        if not cfgs["Z"]:
+            cfgs["Z"] = cc.coot_tune(fused[0], zops, zf.scalars, zo, -1, 1, stream=stream)[0]
+        if not cfgs["W"]:
+            cfgs["W"] = cc.coot_tune(fused[1], wops, wf.scalars, wo, -1, 1, stream=stream)[0]
         cfgs["S0"] = cc.coot_tune(fused[0], zops, zf.scalars, s0o, cc.COOT_RED_SUM, 1, stream=stream, dim=0)[0]
         cfgs["S1"] = cc.coot_tune(fused[0], zops, zf.scalars, s1o, cc.COOT_RED_SUM, 1, stream=stream, dim=1)[0]
     t_tune = time.perf_counter() - t0
@@ -389,8 +394,11 @@ def main():
                     "sumZ1": cc.coot_expr_kernel_name(fused[0], cc.COOT_RED_SUM, 1, cfg=cfgs["S1"])},
         "launch_cfgs": {"Z": cfgs["Z"], "W": cfgs["W"], "sumZ0": cfgs["S0"], "sumZ1": cfgs["S1"],
                         "fields": "vec, ept, waves, grid_mult, tile_r, tile_c",
-                        "chosen_by": "exhaustive autotuner before timing" if args.tune == "exhaustive"
-                        else ("given" if tuned else "library defaults"),
+                        "chosen_by": ("exhaustive autotuner before timing" +
+                                      ("; given on the command line: " + ", ".join(
+                                          k for k, v in (("Z", args.z_cfg), ("W", args.w_cfg)) if v)
+                                       if (args.z_cfg or args.w_cfg) else ""))
+                        if args.tune == "exhaustive" else ("given" if tuned else "library defaults"),
                         "tuning_s": round(t_tune, 2)},
         "default_cfg_ms_per_step": round(t_default * 1e3, 4),
         "unfused_ms_per_step": round(t_unfused * 1e3, 4),

@@ -575,6 +575,27 @@ coot_status coot_tune(coot_expr* h, const coot_operand* operands, const double* 
         if (!std::isnan(ft[fb])) {
           bi = fin[fb];
           t[bi] = ft[fb];
+          // Finalists the repeated-call timing cannot tell apart (within 2 %) are
+          // told apart by one launch after a cache flush (operands from HBM): the
+          // kept configuration then also suits callers whose operands are not cached.
+          std::vector<size_t> tie;
+          for (size_t i = 0; i < ft.size(); ++i)
+            if (!std::isnan(ft[i]) && ft[i] <= 1.02f * ft[fb]) tie.push_back(i);
+          if (tie.size() > 1) {
+            std::vector<coot_launch_cfg> tc;
+            for (size_t i : tie) tc.push_back(fc[i]);
+            std::vector<float> ct(tc.size());
+            st = coot_tune_table(h, operands, scalars, out, mode, dim, tc.data(), (uint32_t)tc.size(), 5, 1,
+                                 ct.data(), stream);
+            if (st != COOT_OK) fail(st, last_error());
+            size_t cb = 0;
+            for (size_t i = 0; i < ct.size(); ++i)
+              if (!std::isnan(ct[i]) && (std::isnan(ct[cb]) || ct[i] < ct[cb])) cb = i;
+            if (!std::isnan(ct[cb])) {
+              bi = fin[tie[cb]];
+              t[bi] = ft[tie[cb]];
+            }
+          }
         }
       }
     }
