@@ -443,7 +443,7 @@ def main():
 def other_configs(args):
     """The other workloads the method is specified on, each at its full size, GPU time by HIP
     events (inputs resident in HBM): axpy then dot on 1e6 fp32 (two statements, and one pass),
-    the 4096 x 4096 step in fp64, u32 (A+B)%C and s32 A-3*B on 8192 x 8192, compensated
+    the 4096 x 4096 step in fp64 (library defaults, and autotuned), u32 (A+B)%C and s32 A-3*B on 8192 x 8192, compensated
     accu and norm over 2^28 lognormal fp32 values, and 10,000 small expressions as one
     autotuned batch launch.  Bytes are algorithmic (operands read once, results written
     once); `cold` times single launches after a 512 MiB cache flush (median of 10)."""
@@ -567,7 +567,28 @@ def other_configs(args):
         coot.sum(Z, 1, out=s1)
 
     res["step_4096_f64"] = entry(2 * (16 * MIB64 + 2 * N * 4), step64, reps=10)
-    del gA, gB, gC, gD, Z, W, oz, ow, s0, s1
+    # the same step with the autotuner's picks (exhaustive, as for the fp32 step)
+    zf, wf = coot.flatten(Z), coot.flatten(W)
+    hz, hw = coot.frontend.compiled(zf), coot.frontend.compiled(wf)
+    zo, wo_, s0o, s1o = oz.operand(), ow.operand(), s0.operand(), s1.operand()
+    zops, wops = [m.operand() for m in zf.mats], [m.operand() for m in wf.mats]
+    t0 = time.perf_counter()
+    pz = cc.coot_tune(hz, zops, zf.scalars, zo, -1, 1, stream=stream)[0]
+    pw = cc.coot_tune(hw, wops, wf.scalars, wo_, -1, 1, stream=stream)[0]
+    p0 = cc.coot_tune(hz, zops, zf.scalars, s0o, cc.COOT_RED_SUM, 1, stream=stream, dim=0)[0]
+    p1 = cc.coot_tune(hz, zops, zf.scalars, s1o, cc.COOT_RED_SUM, 1, stream=stream, dim=1)[0]
+    t_tune = time.perf_counter() - t0
+
+    def step64_tuned():
+        cc.coot_expr_eval(hz, zops, zf.scalars, zo, pz, stream)
+        cc.coot_expr_eval(hw, wops, wf.scalars, wo_, pw, stream)
+        cc.coot_reduce(hz, zops, zf.scalars, cc.COOT_RED_SUM, 0, 0, s0o, p0, stream)
+        cc.coot_reduce(hz, zops, zf.scalars, cc.COOT_RED_SUM, 1, 0, s1o, p1, stream)
+
+    t = entry(2 * (16 * MIB64 + 2 * N * 4), step64_tuned, reps=10)
+    t.update({"picks": {"Z": pz, "W": pw, "sumZ0": p0, "sumZ1": p1}, "tuning_s": round(t_tune, 2)})
+    res["step_4096_f64"]["autotuned"] = t
+    del gA, gB, gC, gD, Z, W, oz, ow, s0, s1, zf, wf
     torch.cuda.empty_cache()
     log(f"fp64 step {res['step_4096_f64']}")
 
