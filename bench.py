@@ -480,6 +480,22 @@ def other_configs(args):
                 ts.append(e0.elapsed_time(e1))
         return sorted(ts)[len(ts) // 2] * 1e3
 
+    def autotuned(nbytes, e, out, mode=-1, reps=10):
+        """The same call with coot_tune's exhaustive pick (element-wise or accu)."""
+        f = coot.flatten(e)
+        h = coot.frontend.compiled(f)
+        ops, oo = [m.operand() for m in f.mats], out.operand()
+        t0 = time.perf_counter()
+        pick = cc.coot_tune(h, ops, f.scalars, oo, mode, 1, stream=stream)[0]
+        t_tune = time.perf_counter() - t0
+        if mode < 0:
+            fn = lambda: cc.coot_expr_eval(h, ops, f.scalars, oo, pick, stream)  # noqa: E731
+        else:
+            fn = lambda: cc.coot_reduce(h, ops, f.scalars, mode, -1, 0, oo, pick, stream)  # noqa: E731
+        r = entry(nbytes, fn, reps=reps)
+        r.update({"pick": pick, "tuning_s": round(t_tune, 2)})
+        return r
+
     def entry(nbytes, fn, cold=True, reps=20):
         us = warm_us(fn, reps)
         r = {"us": round(us, 2), "GBps": round(nbytes / us / 1e3, 1),
@@ -600,6 +616,7 @@ def other_configs(args):
     o = coot.Mat.empty(M, M, "u32")
     eu = (gA + gB) % gC
     res["u32_(A+B)%C_8192"] = entry(4 * 4 * M * M, lambda: coot.eval(eu, out=o), reps=10)
+    res["u32_(A+B)%C_8192"]["autotuned"] = autotuned(4 * 4 * M * M, eu, o)
     del gA, gB, gC, o, eu
     As, Bs = synth.int_inputs(M, "s32_full")
     gA, gB = coot.Mat.from_numpy(As), coot.Mat.from_numpy(Bs)
@@ -607,6 +624,7 @@ def other_configs(args):
     o = coot.Mat.empty(M, M, "s32")
     es = gA - 3 * gB
     res["s32_A-3B_8192"] = entry(3 * 4 * M * M, lambda: coot.eval(es, out=o), reps=10)
+    res["s32_A-3B_8192"]["autotuned"] = autotuned(3 * 4 * M * M, es, o)
     del gA, gB, o, es
     torch.cuda.empty_cache()
     log("integers done")
@@ -618,6 +636,7 @@ def other_configs(args):
     nb = 4 * (1 << 28)
     o1 = coot.Mat.empty(1, 1, "f32")
     res["accu_2^28_f32"] = entry(nb, lambda: coot.accu(gh, out=o1), reps=10)
+    res["accu_2^28_f32"]["autotuned"] = autotuned(nb, gh, o1, cc.COOT_RED_ACCU)
     res["norm_2^28_f32"] = entry(nb, lambda: coot.norm(gh, out=o1), reps=10)
     res["accu_plain_2^28_f32"] = entry(nb, lambda: coot.accu(gh, plain=True, out=o1), cold=False, reps=10)
     del gh, o1
