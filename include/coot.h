@@ -512,8 +512,9 @@ void coot_costmodel_release(coot_costmodel* cm);
  * that of coot_tune_table with 5 rounds and no flush (the per-launch time of
  * repeated calls); under policy 1 the finalists (within 5 % of the fastest, at
  * most 4) are timed again over 21 interleaved rounds, and of those within 2 % of the
- * fastest the one fastest in a launch after a cache flush (coot_tune_table's flush)
- * is kept.  best_us (may be NULL) is the chosen configuration's repeated-call median.
+ * fastest the one fastest in a launch after a cache flush (coot_tune_table's flush;
+ * the 512 MiB flush buffer is allocated on first use) is kept.  best_us (may be
+ * NULL) is the chosen configuration's repeated-call median.
  * The cost model (policy 2) covers element-wise evaluation and accu only
  * (COOT_EUNSUPPORTED along a dimension).  Synchronises the stream. */
 coot_status coot_tune(coot_expr* e, const coot_operand* operands, const double* scalars, coot_operand* out,
