@@ -126,6 +126,8 @@ void check_red_mode(const Expr& e, int mode);
 // with 1024 <= tr * tc <= 8192 (4 to 32 elements per thread).
 inline int tile_vec_cap(int tr, int tc) { return tr * tc / 256; }
 bool tile_shape_ok(int tr, int tc);
+// The library's tile (rows x columns) for a request that gives none.
+void default_tile(const Expr& e, int mode, int dim, int* tr, int* tc);
 // LDS bytes the staged transposed leaves of a tile take (compute-type elements, one
 // padded tr x (tc + 1) tile per transposed leaf); the library keeps this <= 64 KiB.
 size_t tile_lds_bytes(int n_p1, int dtype, int tr, int tc);

@@ -516,8 +516,11 @@ coot_status coot_tune(coot_expr* h, const coot_operand* operands, const double* 
       coot_launch_cfg d = default_cfg(fam == 0 ? FAM_FLAT : FAM_TILE, mode, is_dim_kind(mode) ? dim : -1, h->e->dtype,
                                       R * C);
       if (!d.ept) d.ept = 1;  // the tiled family's configurations carry ept 1
-      if (fam == 1 && !d.tile_r) {  // the library's tile: 64 x 64, or 32 x 32 when the staging does not fit
-        d.tile_r = d.tile_c = tile_lds_bytes(h->e->n_p1, h->e->dtype, 64, 64) > kTileLdsMax ? 32 : 64;
+      if (fam == 1 && !d.tile_r) {  // the library's tile (default_tile)
+        int tr = 0, tc = 0;
+        default_tile(*h->e, mode, is_dim_kind(mode) ? dim : -1, &tr, &tc);
+        d.tile_r = (uint16_t)tr;
+        d.tile_c = (uint16_t)tc;
         if (d.vec > tile_vec_cap(d.tile_r, d.tile_c)) d.vec = (uint16_t)tile_vec_cap(d.tile_r, d.tile_c);
       }
       cand.push_back(d);
