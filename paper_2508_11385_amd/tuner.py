@@ -247,5 +247,7 @@ def save_tables(path, sigs, fams, handles, tables, split):
         for k, c in enumerate(cfgs):
             rows.append((i, *c, t[k], *f[k]))
     rows = np.asarray(rows, np.float64)
+    nc = len(tables[0][0][0]) if tables else 6   # fields of a configuration (vec, ept, waves, grid_mult, tile_r, tile_c)
     np.savez_compressed(path, meta=np.asarray(meta, np.int64), sig=rows[:, 0].astype(np.int64),
-                        cfg=rows[:, 1:5].astype(np.int64), us=rows[:, 5], feat=rows[:, 6:].astype(np.float32))
+                        cfg=rows[:, 1:1 + nc].astype(np.int64), us=rows[:, 1 + nc],
+                        feat=rows[:, 2 + nc:].astype(np.float32))

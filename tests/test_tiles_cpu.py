@@ -122,3 +122,23 @@ def test_tuner_default_index_names_the_library_default(cc, dt):
     t = np.ones(len(flat))
     t[flat.index((v, 1, 4, 4, 0, 0))] = np.nan   # misaligned operands: scalar accesses
     assert flat[tuner.default_index(flat, dt, t, 1000, -1)] == (1, 1, 4, 4, 0, 0)
+
+
+def test_timing_tables_are_saved_with_whole_configurations(cc, tmp_path):
+    """The tuner's table dump keeps all six fields of each configuration next to its
+    time and features (plain arrays, loadable without pickling)."""
+    import numpy as np
+    from paper_2508_11385_amd import tuner
+    sigs = tuner.sample_signatures(3, seed=77)
+    handles = [tuner._handle(spec) for spec, _ in sigs]
+    space = cc.coot_tune_space(1)[:5]
+    tables = [(space, [10.0 + i + 0.5 * k for k in range(len(space))]) for i in range(len(sigs))]
+    path = str(tmp_path / "t.npz")
+    tuner.save_tables(path, sigs, [1] * len(sigs), handles, tables, [0, 0, 1])
+    z = np.load(path)
+    assert z["cfg"].shape == (3 * len(space), 6)
+    assert [tuple(r) for r in z["cfg"][:len(space)]] == [tuple(c) for c in space]
+    assert np.allclose(z["us"], np.concatenate([t for _, t in tables]))
+    assert z["feat"].shape[0] == 3 * len(space) and z["meta"].shape == (3, 9)
+    for h in handles:
+        cc.coot_expr_release(h)
