@@ -985,12 +985,13 @@ def bench_tuner(args):
     cm, losses = cc.coot_costmodel_train(X, y, np.ones(len(y), np.float32), init, 64, 64, args.tuner_epochs, 256, 7,
                                          1e-3, n_models=args.tuner_models)
     t_fit = time.perf_counter() - t0
-    P, t_pred = tuner.picks(cm, test, h_te, tab_te)
+    P, t_pred = tuner.picks(cm, test, h_te, tab_te)            # the library's cost-model policy
+    Pa, _ = tuner.picks(cm, test, h_te, tab_te, margin=0.0)     # the network's argmin alone
     cm0, _ = cc.coot_costmodel_train(X, y, np.ones(len(y), np.float32), init, 64, 64, 0, 256, 7, 1e-3,
                                      n_models=args.tuner_models)
-    P0, _ = tuner.picks(cm0, test, h_te, tab_te)
-    # columns: exhaustive, MLP, default configuration, untrained MLP
-    sets = np.stack([P[:, 0], P[:, 1], P[:, 2], P0[:, 1]], 1)
+    P0, _ = tuner.picks(cm0, test, h_te, tab_te, margin=0.0)
+    # columns: exhaustive, MLP policy, default configuration, untrained MLP argmin, MLP argmin
+    sets = np.stack([P[:, 0], P[:, 1], P[:, 2], P0[:, 1], Pa[:, 1]], 1)
     t0 = time.perf_counter()
     fresh = tuner.retime(test, h_te, tab_te, sets, reps=11, seed=14)
     t_retime = time.perf_counter() - t0
@@ -999,19 +1000,18 @@ def bench_tuner(args):
         np.savez_compressed(base + "_picks.npz", picks=sets, fresh_us=fresh)
     os.makedirs(os.path.dirname(args.tuner_out), exist_ok=True)
     cc.coot_costmodel_save(cm, args.tuner_out)
-    reg = {name: tuner.summarize(fresh[:, j] / fresh[:, 0] - 1.0)
-           for j, name in ((1, "mlp"), (2, "default_config"), (3, "untrained_mlp"))}
-    in_table = {name: tuner.summarize(tuner.regrets_from_table(tab_te, sets[:, j]))
-                for j, name in ((1, "mlp"), (2, "default_config"), (3, "untrained_mlp"))}
+    cols = ((1, "mlp"), (2, "default_config"), (3, "untrained_mlp"), (4, "mlp_argmin"))
+    reg = {name: tuner.summarize(fresh[:, j] / fresh[:, 0] - 1.0) for j, name in cols}
+    in_table = {name: tuner.summarize(tuner.regrets_from_table(tab_te, sets[:, j])) for j, name in cols}
     rnd = lambda d: {k: round(v, 4) for k, v in d.items()}
 
     # 95 % bootstrap intervals of the re-timed geomean regrets (signatures resampled), and
     # the slices of the held-out set: small outputs, reductions, fp64, the tiled family
     rng = np.random.default_rng(15)
-    lr = np.log(fresh[:, 1:] / fresh[:, :1])                  # log time ratios: mlp, default, untrained
+    lr = np.log(fresh[:, 1:] / fresh[:, :1])   # log time ratios: mlp, default, untrained, mlp argmin
     boots = np.exp(np.stack([lr[rng.integers(0, len(lr), len(lr))].mean(0) for _ in range(2000)])) - 1.0
     ci = {name: [round(float(np.percentile(boots[:, j], 2.5)), 4), round(float(np.percentile(boots[:, j], 97.5)), 4)]
-          for j, name in enumerate(("mlp", "default_config", "untrained_mlp"))}
+          for j, name in enumerate(("mlp", "default_config", "untrained_mlp", "mlp_argmin"))}
     gain = np.exp(np.stack([(lr[idx, 1] - lr[idx, 0]).mean() for idx in
                             (rng.integers(0, len(lr), len(lr)) for _ in range(2000))]))
     elems = np.array([s.out_shape[0] * s.out_shape[1] for s, _ in test])
@@ -1024,7 +1024,7 @@ def bench_tuner(args):
             continue
         g = np.exp(lr[msk].mean(0)) - 1.0
         by_slice[name] = {"signatures": int(msk.sum()), "mlp": round(float(g[0]), 4),
-                          "default_config": round(float(g[1]), 4)}
+                          "default_config": round(float(g[1]), 4), "mlp_argmin": round(float(g[3]), 4)}
     out = {
         "metric": "learned tuner: geomean regret of MLP-chosen launch configs vs exhaustive autotune",
         "value": round(100 * reg["mlp"]["geomean"], 2), "unit": "% regret", "higher_is_better": False, "n_gpus": 1,
@@ -1037,7 +1037,9 @@ def bench_tuner(args):
         "regret_definition": "t(pick)/t(exhaustive argmin) - 1, both picks re-timed side by side (11 interleaved "
                              "rounds of back-to-back launches) after the exhaustive table chose its argmin",
         "mlp": rnd(reg["mlp"]), "default_config": rnd(reg["default_config"]),
-        "untrained_mlp": rnd(reg["untrained_mlp"]),
+        "untrained_mlp": rnd(reg["untrained_mlp"]), "mlp_argmin": rnd(reg["mlp_argmin"]),
+        "mlp_policy": f"the network's argmin where it predicts at least {tuner.COST_MODEL_MARGIN:.0%} over the "
+                      "library default, else the default (mlp_argmin: the argmin always)",
         "regret_within_exhaustive_table": {k: rnd(v) for k, v in in_table.items()},
         "geomean_95pct_bootstrap": ci,
         "default_over_mlp_time_ratio_95pct": [round(float(np.percentile(gain, 2.5)), 4),

@@ -127,8 +127,11 @@ typedef struct {
  *             of the compute type each), else COOT_EINVAL.  A tall tile gives the
  *             untransposed operands longer contiguous segments, a wide one the
  *             transposed operands.  The vector width is capped at
- *             tile_r * tile_c / 256.  Default 64 x 64 (32 x 32 when four or more
- *             transposed leaves would not fit).  Flat kernels ignore them. */
+ *             tile_r * tile_c / 256.  Default 32 x 32, or 64 x 32 for a reduction
+ *             along a dimension (32 x 32 when its staging would not fit); with
+ *             neither given and even 32 x 32 staging beyond 64 KiB (8 or more
+ *             transposed fp64 leaves, 16 fp32) COOT_EUNSUPPORTED.  Flat kernels
+ *             ignore them. */
 typedef struct {
   uint16_t vec;
   uint16_t ept;
@@ -508,7 +511,8 @@ void coot_costmodel_release(coot_costmodel* cm);
 
 /* Pick a configuration for these operands: policy 0 the library default,
  * 1 exhaustive (every configuration timed, the fastest kept), 2 the cost model's
- * argmin over the configurations these operands allow (cm required).  Timing is
+ * argmin over the configurations these operands allow where it is predicted at least
+ * 5 % faster than the library default, else the default (cm required).  Timing is
  * that of coot_tune_table with 5 rounds and no flush (the per-launch time of
  * repeated calls); under policy 1 the finalists (within 5 % of the fastest, at
  * most 4) are timed again over 21 interleaved rounds, and of those within 2 % of the

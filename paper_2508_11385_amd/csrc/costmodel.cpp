@@ -498,6 +498,9 @@ coot_status coot_costmodel_load(const char* path, coot_costmodel** out) {
 
 void coot_costmodel_release(coot_costmodel* cm) { delete cm; }
 
+// The cost model's pick replaces the library default only when predicted this much faster.
+constexpr float kCostModelMargin = 0.05f;
+
 // Choose a configuration: 0 DEFAULT, 1 EXHAUSTIVE (time all), 2 MLP (cost-model argmin, then timed).
 coot_status coot_tune(coot_expr* h, const coot_operand* operands, const double* scalars, coot_operand* out,
                       int32_t mode, int32_t dim, int32_t policy, coot_costmodel* cm, coot_launch_cfg* best,
@@ -510,7 +513,8 @@ coot_status coot_tune(coot_expr* h, const coot_operand* operands, const double* 
     std::vector<coot_launch_cfg> space(coot_tune_space(fam, nullptr, 0));
     coot_tune_space(fam, space.data(), (uint32_t)space.size());
     std::vector<coot_launch_cfg> cand;
-    if (policy == 0) {
+    // the configuration the library launches without a tuner, as an entry of the space
+    auto library_default = [&]() {
       int64_t R, C;
       infer_shape(*h->e, operands, &R, &C);
       coot_launch_cfg d = default_cfg(fam == 0 ? FAM_FLAT : FAM_TILE, mode, is_dim_kind(mode) ? dim : -1, h->e->dtype,
@@ -523,7 +527,10 @@ coot_status coot_tune(coot_expr* h, const coot_operand* operands, const double* 
         d.tile_c = (uint16_t)tc;
         if (d.vec > tile_vec_cap(d.tile_r, d.tile_c)) d.vec = (uint16_t)tile_vec_cap(d.tile_r, d.tile_c);
       }
-      cand.push_back(d);
+      return d;
+    };
+    if (policy == 0) {
+      cand.push_back(library_default());
     } else if (policy == 1) {
       cand = space;
       if (dtype_is_half(h->e->dtype))  // 16-byte groups of 16-bit elements as well
@@ -542,9 +549,17 @@ coot_status coot_tune(coot_expr* h, const coot_operand* operands, const double* 
       for (size_t i = 0; i < space.size(); ++i)
         if (ok[i]) live.push_back(space[i]);
       uint32_t bi = 0;
-      st = coot_costmodel_predict(cm, h, R, C, mode < 0 ? 0 : 1, live.data(), (uint32_t)live.size(), nullptr, &bi,
+      std::vector<float> pred(live.size());
+      st = coot_costmodel_predict(cm, h, R, C, mode < 0 ? 0 : 1, live.data(), (uint32_t)live.size(), pred.data(), &bi,
                                   stream);
       if (st != COOT_OK) fail(st, last_error());
+      // Leave the library default only for a predicted gain of kCostModelMargin or more
+      // (predictions are log times): where the network sees no clear winner, the default,
+      // chosen from the same kind of timing tables, is as likely to be right.
+      const coot_launch_cfg d = library_default();
+      for (size_t i = 0; i < live.size(); ++i)
+        if (std::memcmp(&live[i], &d, sizeof d) == 0 && pred[bi] > pred[i] - std::log(1.0f + kCostModelMargin))
+          bi = (uint32_t)i;
       cand.push_back(live[bi]);
     } else {
       fail(COOT_EINVAL, "policy must be 0, 1 or 2");

@@ -197,11 +197,14 @@ coot_launch_cfg default_cfg(int fam, int mode, int dim, int dtype, int64_t n) {
 // The library's tile when the caller gives none: 64 x 32 for reductions along a
 // dimension (the fastest fixed shape over sums and means of eight shapes from 300 x 170
 // to 16384 x 256 in fp32 and fp64: 0.97 of the exhaustive picks' time against 1.04 for
-// 64 x 64), 64 x 64 otherwise; 32 x 32 when the staged transposed leaves would not fit.
+// 64 x 64), else 32 x 32 (over the autotuner's held-out tables of the tiled family,
+// 767 element-wise and 196 accu signatures with outputs of 1 to 16384 rows and
+// columns, geometric-mean time 1.08 and 1.06 of each signature's best, against 1.41 and
+// 1.25 for 64 x 64); 32 x 32 when the staged transposed leaves would not fit.
 void default_tile(const Expr& e, int mode, int dim, int* tr, int* tc) {
   const bool dimk = is_dim_kind(mode) && dim >= 0;
-  *tr = 64;
-  *tc = dimk ? 32 : 64;
+  *tr = dimk ? 64 : 32;
+  *tc = 32;
   if (tile_lds_bytes(e.n_p1, e.dtype, *tr, *tc) > kTileLdsMax) *tr = *tc = 32;
 }
 
@@ -250,6 +253,8 @@ Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, in
                             " tile exceed 64 KiB of LDS");
   } else {
     default_tile(e, mode, dim, &tr, &tc);
+    if (rq.fam == FAM_TILE && tile_lds_bytes(e.n_p1, e.dtype, tr, tc) > kTileLdsMax)
+      fail(COOT_EUNSUPPORTED, std::to_string(e.n_p1) + " transposed leaves: their staged 32 x 32 tiles exceed 64 KiB of LDS");
   }
   rq.var.tr = tr;
   rq.var.tc = tc;

@@ -137,7 +137,7 @@ def default_index(cfgs, dtype, t=None, n=0, mode=-1):
     do not allow its vector width (t[k] NaN), the same with scalar accesses."""
     v = 2 if dtype == "f64" else 4
     if cfgs[0][4]:                                  # tiled family: (vec, 1, 4, per CU, tile rows, tile cols)
-        want = (2, 1, 4, 8, 64, 64)
+        want = (2, 1, 4, 8, 32, 32)
     elif n > STREAM_ELEMS:
         want = (v, 1, 4, 2, 0, 0) if mode < 0 else ((2, 4, 8, 8, 0, 0) if dtype == "f64" else (4, 4, 4, 2, 0, 0))
     else:
@@ -145,10 +145,8 @@ def default_index(cfgs, dtype, t=None, n=0, mode=-1):
     k = cfgs.index(want)
     if t is not None and not np.isfinite(t[k]):
         k = cfgs.index((1,) + want[1:])
-        if cfgs[0][4] and not np.isfinite(t[k]):    # 64 x 64 staging beyond LDS: the library takes 32 x 32
-            k = cfgs.index((2, 1, 4, 8, 32, 32))
-            if not np.isfinite(t[k]):
-                k = cfgs.index((1, 1, 4, 8, 32, 32))
+        if cfgs[0][4] and not np.isfinite(t[k]):    # (32 x 32 staging beyond LDS: refused by the library)
+            k = cfgs.index((1, 1, 4, 8, 32, 32))
     return k
 
 
@@ -192,18 +190,27 @@ def he_init(seed: int, f: int = cc.N_FEATURES, h1: int = 64, h2: int = 64, n_mod
     return np.concatenate(out).astype(np.float32)
 
 
-def picks(cm, sigs, handles, tables):
-    """Per signature: (exhaustive argmin, cost-model argmin, default) as indices into its
-    configuration list; the cost model ranks only the runnable configurations."""
+COST_MODEL_MARGIN = 0.05   # coot_tune's kCostModelMargin
+
+
+def picks(cm, sigs, handles, tables, margin=COST_MODEL_MARGIN):
+    """Per signature: (exhaustive argmin, cost-model pick, default) as indices into its
+    configuration list; the cost model ranks only the runnable configurations, and its
+    argmin replaces the default only when predicted `margin` faster (0: always)."""
     out, t_pred = [], 0.0
     for (spec, mode), h, (cfgs, t) in zip(sigs, handles, tables):
         ok = _valid(t)
         exh = int(ok[np.argmin(t[ok])])
         t0 = time.perf_counter()
-        k, _ = cc.coot_costmodel_predict(cm, h, spec.out_shape[0], spec.out_shape[1], 0 if mode < 0 else 1,
-                                         [cfgs[i] for i in ok])
+        k, pred = cc.coot_costmodel_predict(cm, h, spec.out_shape[0], spec.out_shape[1], 0 if mode < 0 else 1,
+                                            [cfgs[i] for i in ok])
+        d = default_index(cfgs, spec.dtype, t, spec.out_shape[0] * spec.out_shape[1], mode)
+        # as coot_tune's cost-model policy: the default unless the network predicts a clear gain
+        pos = np.flatnonzero(ok == d)
+        if margin > 0 and pos.size and pred[k] > pred[pos[0]] - np.log1p(margin):
+            k = int(pos[0])
         t_pred += time.perf_counter() - t0
-        out.append((exh, int(ok[k]), default_index(cfgs, spec.dtype, t, spec.out_shape[0] * spec.out_shape[1], mode)))
+        out.append((exh, int(ok[k]), d))
     return np.asarray(out, np.int64), t_pred / max(1, len(sigs))
 
 

@@ -114,11 +114,10 @@ def test_tuner_default_index_names_the_library_default(cc, dt):
     assert flat[tuner.default_index(flat, dt, None, 1 << 25, -1)] == (v, 1, 4, 2, 0, 0)
     big_red = (2, 4, 8, 8, 0, 0) if dt == "f64" else (4, 4, 4, 2, 0, 0)
     assert flat[tuner.default_index(flat, dt, None, 1 << 25, 0)] == big_red
-    assert tiled[tuner.default_index(tiled, dt, None, 1000, -1)] == (2, 1, 4, 8, 64, 64)
+    assert tiled[tuner.default_index(tiled, dt, None, 1000, -1)] == (2, 1, 4, 8, 32, 32)
     t = np.ones(len(tiled))
-    for c in ((2, 1, 4, 8, 64, 64), (1, 1, 4, 8, 64, 64)):
-        t[tiled.index(c)] = np.nan              # 64 x 64 staging beyond LDS
-    assert tiled[tuner.default_index(tiled, dt, t, 1000, -1)] == (2, 1, 4, 8, 32, 32)
+    t[tiled.index((2, 1, 4, 8, 32, 32))] = np.nan   # operands that rule out 2-element groups
+    assert tiled[tuner.default_index(tiled, dt, t, 1000, -1)] == (1, 1, 4, 8, 32, 32)
     t = np.ones(len(flat))
     t[flat.index((v, 1, 4, 4, 0, 0))] = np.nan   # misaligned operands: scalar accesses
     assert flat[tuner.default_index(flat, dt, t, 1000, -1)] == (1, 1, 4, 4, 0, 0)
