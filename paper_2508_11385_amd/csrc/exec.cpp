@@ -200,11 +200,18 @@ coot_launch_cfg default_cfg(int fam, int mode, int dim, int dtype, int64_t n) {
 // 64 x 64), else 32 x 32 (over the autotuner's held-out tables of the tiled family,
 // 767 element-wise and 196 accu signatures with outputs of 1 to 16384 rows and
 // columns, geometric-mean time 1.08 and 1.06 of each signature's best, against 1.41 and
-// 1.25 for 64 x 64); 32 x 32 when the staged transposed leaves would not fit.
+// 1.25 for 64 x 64); 32 x 32 when the staged transposed leaves would not fit.  16-bit
+// types, outside both measurements, keep 64 x 64: their 16-byte groups (8 elements) need
+// tiles of 2048 elements or more, and the 4096 x 4096 f16 step measured Z 28 against
+// 47 us and the sums 24-27 against 45-50 us on 64 x 64 tiles rather than the shapes above.
 void default_tile(const Expr& e, int mode, int dim, int* tr, int* tc) {
   const bool dimk = is_dim_kind(mode) && dim >= 0;
-  *tr = dimk ? 64 : 32;
-  *tc = 32;
+  if (dtype_is_half(e.dtype)) {
+    *tr = *tc = 64;
+  } else {
+    *tr = dimk ? 64 : 32;
+    *tc = 32;
+  }
   if (tile_lds_bytes(e.n_p1, e.dtype, *tr, *tc) > kTileLdsMax) *tr = *tc = 32;
 }
 
