@@ -248,8 +248,8 @@ Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, in
   if (rq.var.vec != 1 && rq.var.vec != 2 && rq.var.vec != 4 && !(rq.var.vec == 8 && dtype_is_half(e.dtype)))
     fail(COOT_EINVAL, "vec must be 1, 2 or 4 (or 8 for 16-bit types)");
   if (rq.var.ept != 1 && rq.var.ept != 2 && rq.var.ept != 4 && rq.var.ept != 8) fail(COOT_EINVAL, "ept must be 1, 2, 4 or 8");
-  // tile: the caller's, else 64 x 64, or 32 x 32 when the LDS staging of the transposed
-  // leaves (held in the compute type: binary32 for 16-bit types) would exceed 64 KiB
+  // tile: the caller's, else the library default (default_tile); the LDS staging of the
+  // transposed leaves (held in the compute type: binary32 for 16-bit types) fits 64 KiB
   if ((c.tile_r == 0) != (c.tile_c == 0)) fail(COOT_EINVAL, "give tile_r and tile_c together");
   int tr = c.tile_r, tc = c.tile_c;
   if (tr) {

@@ -139,3 +139,27 @@ def test_timing_tables_are_saved_with_whole_configurations(cc, tmp_path):
     assert z["feat"].shape[0] == 3 * len(space) and z["meta"].shape == (3, 9)
     for h in handles:
         cc.coot_expr_release(h)
+
+
+def test_library_default_tiles(cc):
+    """Without a configuration the tiled kernels take 32 x 32 tiles for element-wise
+    evaluation and full reductions, 64 x 32 for reductions along a dimension, 64 x 64 for
+    16-bit types; 32 x 32 where the staged transposed leaves would not fit; and a request
+    whose staging does not fit even 32 x 32 (eight transposed fp64 leaves) is refused."""
+    for dt, n_p1, want_eval, want_dim in (("f32", 1, (32, 32), (64, 32)), ("f64", 1, (32, 32), (64, 32)),
+                                          ("u32", 1, (32, 32), (64, 32)), ("f64", 4, (32, 32), (32, 32)),
+                                          ("f16", 1, (64, 64), (64, 64)), ("bf16", 4, (32, 32), (32, 32))):
+        h = _expr(cc, dt, n_p1)
+        assert _vt(cc.coot_expr_kernel_name(h, -1, -1))[1:] == want_eval, (dt, n_p1)
+        assert _vt(cc.coot_expr_kernel_name(h, cc.COOT_RED_ACCU, -1))[1:] == want_eval, (dt, n_p1)
+        for dim in (0, 1):
+            assert _vt(cc.coot_expr_kernel_name(h, cc.COOT_RED_SUM, dim))[1:] == want_dim, (dt, n_p1, dim)
+        cc.coot_expr_release(h)
+    h = _expr(cc, "f64", 7)                     # 7 x 32 x 33 x 8 B = 59136 B: fits
+    assert _vt(cc.coot_expr_kernel_name(h, -1, -1))[1:] == (32, 32)
+    cc.coot_expr_release(h)
+    h = _expr(cc, "f64", 8)                     # 8 x 32 x 33 x 8 B = 67584 B > 64 KiB
+    with pytest.raises(cc.CootError) as e:
+        cc.coot_expr_kernel_name(h, -1, -1)
+    assert e.value.status == cc.COOT_EUNSUPPORTED and "64 KiB" in str(e.value)
+    cc.coot_expr_release(h)
