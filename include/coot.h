@@ -127,11 +127,12 @@ typedef struct {
  *             of the compute type each), else COOT_EINVAL.  A tall tile gives the
  *             untransposed operands longer contiguous segments, a wide one the
  *             transposed operands.  The vector width is capped at
- *             tile_r * tile_c / 256.  Default 32 x 32, or 64 x 32 for a reduction
- *             along a dimension (32 x 32 when its staging would not fit); with
- *             neither given and even 32 x 32 staging beyond 64 KiB (8 or more
- *             transposed fp64 leaves, 16 fp32) COOT_EUNSUPPORTED.  Flat kernels
- *             ignore them. */
+ *             tile_r * tile_c / 256.  Default 32 x 32 below 2^22 elements and
+ *             64 x 64 from there (the expression's rows x columns), 64 x 32 for a
+ *             reduction along a dimension, 64 x 64 for 16-bit types (32 x 32 when
+ *             its staging would not fit); with neither given and even 32 x 32
+ *             staging beyond 64 KiB (8 or more transposed fp64 leaves, 16 fp32)
+ *             COOT_EUNSUPPORTED.  Flat kernels ignore them. */
 typedef struct {
   uint16_t vec;
   uint16_t ept;

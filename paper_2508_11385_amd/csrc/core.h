@@ -127,7 +127,8 @@ void check_red_mode(const Expr& e, int mode);
 inline int tile_vec_cap(int tr, int tc) { return tr * tc / 256; }
 bool tile_shape_ok(int tr, int tc);
 // The library's tile (rows x columns) for a request that gives none.
-void default_tile(const Expr& e, int mode, int dim, int* tr, int* tc);
+// n: elements of the expression's shape (the output of an element-wise evaluation)
+void default_tile(const Expr& e, int mode, int dim, int64_t n, int* tr, int* tc);
 // LDS bytes the staged transposed leaves of a tile take (compute-type elements, one
 // padded tr x (tc + 1) tile per transposed leaf); the library keeps this <= 64 KiB.
 size_t tile_lds_bytes(int n_p1, int dtype, int tr, int tc);
@@ -266,6 +267,7 @@ void* noalloc_scratch();
 // The library's launch configuration for a family when the caller gives none
 // (fields 0 there are filled from it); waves and ept are 0/unused where fixed.
 constexpr int64_t kStreamElems = int64_t(1) << 24;  // larger flat launches take the streaming defaults
+constexpr int64_t kTileLargeElems = int64_t(1) << 22;  // from here tiled launches default to 64 x 64
 coot_launch_cfg default_cfg(int fam, int mode, int dim, int dtype, int64_t n);
 Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, int mode, int dim, bool comp,
              const coot_launch_cfg* cfg);

@@ -522,7 +522,7 @@ coot_status coot_tune(coot_expr* h, const coot_operand* operands, const double* 
       if (!d.ept) d.ept = 1;  // the tiled family's configurations carry ept 1
       if (fam == 1 && !d.tile_r) {  // the library's tile (default_tile)
         int tr = 0, tc = 0;
-        default_tile(*h->e, mode, is_dim_kind(mode) ? dim : -1, &tr, &tc);
+        default_tile(*h->e, mode, is_dim_kind(mode) ? dim : -1, R * C, &tr, &tc);
         d.tile_r = (uint16_t)tr;
         d.tile_c = (uint16_t)tc;
         if (d.vec > tile_vec_cap(d.tile_r, d.tile_c)) d.vec = (uint16_t)tile_vec_cap(d.tile_r, d.tile_c);

@@ -197,20 +197,26 @@ coot_launch_cfg default_cfg(int fam, int mode, int dim, int dtype, int64_t n) {
 // The library's tile when the caller gives none: 64 x 32 for reductions along a
 // dimension (the fastest fixed shape over sums and means of eight shapes from 300 x 170
 // to 16384 x 256 in fp32 and fp64: 0.97 of the exhaustive picks' time against 1.04 for
-// 64 x 64), else 32 x 32 (over the autotuner's held-out tables of the tiled family,
-// 767 element-wise and 196 accu signatures with outputs of 1 to 16384 rows and
-// columns, geometric-mean time 1.08 and 1.06 of each signature's best, against 1.41 and
-// 1.25 for 64 x 64); 32 x 32 when the staged transposed leaves would not fit.  16-bit
-// types, outside both measurements, keep 64 x 64: their 16-byte groups (8 elements) need
-// tiles of 2048 elements or more, and the 4096 x 4096 f16 step measured Z 28 against
-// 47 us and the sums 24-27 against 45-50 us on 64 x 64 tiles rather than the shapes above.
-void default_tile(const Expr& e, int mode, int dim, int* tr, int* tc) {
+// 64 x 64).  Element-wise evaluation and full reductions: 32 x 32 below 2^22 elements
+// and 64 x 64 from there.  Over the autotuner's timing tables of the tiled family (time
+// over each signature's best, geometric mean), 32 x 32 takes 1.07 below 2^22 elements
+// against 1.41 for 64 x 64 (1.12 against 1.22 from 2^20), and 64 x 64 is ahead from 2^22
+// (1.15 against 1.18 up to 2^24, 1.15 against 1.26 beyond); the threshold is the best on
+// the training signatures.  Timed one launch after a flush of the caches, 47 signatures
+// of 2^24 to 2^26 elements in four types put 64 x 64 at 1.08 against 1.13.  32 x 32
+// whenever the staged transposed leaves would not fit.
+// 16-bit types keep 64 x 64: their 16-byte groups (8 elements) need tiles of 2048
+// elements or more, and the 4096 x 4096 f16 step measured Z 28 against 47 us and the
+// sums 24-27 against 45-50 us on 64 x 64 tiles rather than smaller shapes.
+void default_tile(const Expr& e, int mode, int dim, int64_t n, int* tr, int* tc) {
   const bool dimk = is_dim_kind(mode) && dim >= 0;
   if (dtype_is_half(e.dtype)) {
     *tr = *tc = 64;
-  } else {
-    *tr = dimk ? 64 : 32;
+  } else if (dimk) {
+    *tr = 64;
     *tc = 32;
+  } else {
+    *tr = *tc = n >= kTileLargeElems ? 64 : 32;
   }
   if (tile_lds_bytes(e.n_p1, e.dtype, *tr, *tc) > kTileLdsMax) *tr = *tc = 32;
 }
@@ -259,7 +265,7 @@ Request plan(const Expr& e, const coot_operand* ops, const coot_operand* out, in
       fail(COOT_EINVAL, "the staged transposed leaves of a " + std::to_string(tr) + " x " + std::to_string(tc) +
                             " tile exceed 64 KiB of LDS");
   } else {
-    default_tile(e, mode, dim, &tr, &tc);
+    default_tile(e, mode, dim, R * C, &tr, &tc);
     if (rq.fam == FAM_TILE && tile_lds_bytes(e.n_p1, e.dtype, tr, tc) > kTileLdsMax)
       fail(COOT_EUNSUPPORTED, std::to_string(e.n_p1) + " transposed leaves: their staged 32 x 32 tiles exceed 64 KiB of LDS");
   }

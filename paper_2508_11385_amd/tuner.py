@@ -129,24 +129,32 @@ def _valid(t):
 
 
 STREAM_ELEMS = 1 << 24  # flat launches past this many elements take the library's streaming defaults
+TILE_LARGE_ELEMS = 1 << 22  # tiled launches of this many elements or more default to 64 x 64 tiles
 
 
 def default_index(cfgs, dtype, t=None, n=0, mode=-1):
     """What the library launches without a tuner for n elements in this mode (-1
     element-wise, else a full reduction): the default configuration, or, when the operands
-    do not allow its vector width (t[k] NaN), the same with scalar accesses."""
+    do not allow its vector width (t[k] NaN), the same with scalar accesses; a tiled
+    default whose staging does not fit takes 32 x 32 tiles."""
     v = 2 if dtype == "f64" else 4
-    if cfgs[0][4]:                                  # tiled family: (vec, 1, 4, per CU, tile rows, tile cols)
-        want = (2, 1, 4, 8, 32, 32)
+    tiled = bool(cfgs[0][4])
+    if tiled:                                       # (vec, 1, 4, per CU, tile rows, tile cols)
+        ts = 64 if n >= TILE_LARGE_ELEMS else 32
+        want = (2, 1, 4, 8, ts, ts)
     elif n > STREAM_ELEMS:
         want = (v, 1, 4, 2, 0, 0) if mode < 0 else ((2, 4, 8, 8, 0, 0) if dtype == "f64" else (4, 4, 4, 2, 0, 0))
     else:
         want = (v, 1, 4, 4, 0, 0)
-    k = cfgs.index(want)
-    if t is not None and not np.isfinite(t[k]):
-        k = cfgs.index((1,) + want[1:])
-        if cfgs[0][4] and not np.isfinite(t[k]):    # (32 x 32 staging beyond LDS: refused by the library)
-            k = cfgs.index((1, 1, 4, 8, 32, 32))
+    chain = [want, (1,) + want[1:]]
+    if tiled and want[4] != 32:
+        chain += [(2, 1, 4, 8, 32, 32), (1, 1, 4, 8, 32, 32)]
+    elif tiled:                                     # (32 x 32 staging beyond LDS: refused by the library)
+        chain += [(1, 1, 4, 8, 32, 32)]
+    for c in chain:
+        k = cfgs.index(c)
+        if t is None or np.isfinite(t[k]):
+            return k
     return k
 
 

@@ -256,3 +256,36 @@ def test_dimension_tuning_module_matches_oracle(env, dtype):
                                     False).numpy().ravel()
         for g, w, sc in zip(got, want, scale):
             assert rd.rel_err(float(g), w, sc) <= tol, (kind, dim, best)
+
+
+def test_library_default_tile_follows_the_output_size(env):
+    """Without a configuration the library tiles element-wise evaluation and accu with
+    32 x 32 tiles below 2^22 elements and 64 x 64 from there, and reductions along a
+    dimension with 64 x 32 (coot_tune's policy 0 reports the default it launches, which
+    the tuner's stand-in names too); the default launches match the oracle."""
+    coot, cc, torch = env
+    from paper_2508_11385_amd import tuner
+    space = cc.coot_tune_space(1)
+    for R, C in ((2048, 2047), (2048, 2048)):
+        A, _, _, D = synth.matrix_inputs(n_rows=R, n_cols=C)
+        gA, gD = coot.Mat.from_numpy(A), coot.Mat.from_numpy(D)
+        e = gA + coot.trans(gD)
+        flat = coot.flatten(e)
+        h = coot.frontend.compiled(flat)
+        ops = [m_.operand() for m_ in flat.mats]
+        ts = 64 if R * C >= 1 << 22 else 32
+        out = coot.Mat.empty(R, C)
+        d, _ = cc.coot_tune(h, ops, flat.scalars, out.operand(), -1, 0)
+        assert d[4:] == (ts, ts), (R, C, d)
+        assert space[tuner.default_index(space, "f32", None, R * C, -1)] == d
+        acc = coot.Mat.empty(1, 1)
+        d, _ = cc.coot_tune(h, ops, flat.scalars, acc.operand(), cc.COOT_RED_ACCU, 0)
+        assert d[4:] == (ts, ts), (R, C, d)
+        s0 = coot.Mat.empty(1, C, "f32", "row")
+        d, _ = cc.coot_tune(h, ops, flat.scalars, s0.operand(), cc.COOT_RED_SUM, 0, dim=0)
+        assert d[4:] == (64, 32), (R, C, d)
+        want = ew.evaluate(flat.postfix, [A, D], flat.scalars, "f32")
+        got = coot.eval(e).numpy()
+        torch.cuda.synchronize()
+        assert np.array_equal(got, want), (R, C)
+        del gA, gD, out

@@ -116,6 +116,19 @@ def test_tuner_default_index_names_the_library_default(cc, dt):
     t = np.ones(len(tiled))
     t[tiled.index((2, 1, 4, 8, 32, 32))] = np.nan   # operands that rule out 2-element groups
     assert tiled[tuner.default_index(tiled, dt, t, 1000, -1)] == (1, 1, 4, 8, 32, 32)
+    # from 2^22 elements the tiled default is 64 x 64; its fallbacks: scalar accesses, then
+    # 32 x 32 tiles where the staging of 64 x 64 ones does not fit
+    big = 1 << 22
+    assert tiled[tuner.default_index(tiled, dt, None, big - 1, -1)] == (2, 1, 4, 8, 32, 32)
+    assert tiled[tuner.default_index(tiled, dt, None, big, -1)] == (2, 1, 4, 8, 64, 64)
+    assert tiled[tuner.default_index(tiled, dt, None, big, 0)] == (2, 1, 4, 8, 64, 64)
+    t = np.ones(len(tiled))
+    t[tiled.index((2, 1, 4, 8, 64, 64))] = np.nan
+    assert tiled[tuner.default_index(tiled, dt, t, big, -1)] == (1, 1, 4, 8, 64, 64)
+    t[tiled.index((1, 1, 4, 8, 64, 64))] = np.nan
+    assert tiled[tuner.default_index(tiled, dt, t, big, -1)] == (2, 1, 4, 8, 32, 32)
+    t[tiled.index((2, 1, 4, 8, 32, 32))] = np.nan
+    assert tiled[tuner.default_index(tiled, dt, t, big, -1)] == (1, 1, 4, 8, 32, 32)
     t = np.ones(len(flat))
     t[flat.index((v, 1, 4, 4, 0, 0))] = np.nan   # misaligned operands: scalar accesses
     assert flat[tuner.default_index(flat, dt, t, 1000, -1)] == (1, 1, 4, 4, 0, 0)
@@ -142,10 +155,11 @@ def test_timing_tables_are_saved_with_whole_configurations(cc, tmp_path):
 
 
 def test_library_default_tiles(cc):
-    """Without a configuration the tiled kernels take 32 x 32 tiles for element-wise
-    evaluation and full reductions, 64 x 32 for reductions along a dimension, 64 x 64 for
-    16-bit types; 32 x 32 where the staged transposed leaves would not fit; and a request
-    whose staging does not fit even 32 x 32 (eight transposed fp64 leaves) is refused."""
+    """Without a configuration the tiled kernels take, for outputs below 2^22 elements
+    (the names are planned for 1 x 1 operands), 32 x 32 tiles for element-wise evaluation
+    and full reductions, 64 x 32 for reductions along a dimension, 64 x 64 for 16-bit
+    types; 32 x 32 where the staged transposed leaves would not fit; and a request whose
+    staging does not fit even 32 x 32 (eight transposed fp64 leaves) is refused."""
     for dt, n_p1, want_eval, want_dim in (("f32", 1, (32, 32), (64, 32)), ("f64", 1, (32, 32), (64, 32)),
                                           ("u32", 1, (32, 32), (64, 32)), ("f64", 4, (32, 32), (32, 32)),
                                           ("f16", 1, (64, 64), (64, 64)), ("bf16", 4, (32, 32), (32, 32))):
