@@ -262,7 +262,8 @@ def test_library_default_tile_follows_the_output_size(env):
     """Without a configuration the library tiles element-wise evaluation and accu with
     32 x 32 tiles below 2^22 elements and 64 x 64 from there, and reductions along a
     dimension with 64 x 32 (coot_tune's policy 0 reports the default it launches, which
-    the tuner's stand-in names too); the default launches match the oracle."""
+    the tuner's stand-in names too), 32 x 32 where the staging of 64 x 64 tiles does not
+    fit; the default launches match the oracle."""
     coot, cc, torch = env
     from paper_2508_11385_amd import tuner
     space = cc.coot_tune_space(1)
@@ -289,3 +290,18 @@ def test_library_default_tile_follows_the_output_size(env):
         torch.cuda.synchronize()
         assert np.array_equal(got, want), (R, C)
         del gA, gD, out
+    # two transposed fp64 leaves stage 2 x 64 x 65 x 8 bytes > 64 KiB on 64 x 64 tiles:
+    # the default falls back to 32 x 32 at any size
+    A, B, _, D = synth.matrix_inputs(dtype="f64", n_rows=2048, n_cols=2048)
+    gA, gB, gD = (coot.Mat.from_numpy(m) for m in (A, B, D))
+    e = gA + coot.trans(gB) - coot.trans(gD)
+    flat = coot.flatten(e)
+    h = coot.frontend.compiled(flat)
+    ops = [m_.operand() for m_ in flat.mats]
+    d, _ = cc.coot_tune(h, ops, flat.scalars, coot.Mat.empty(2048, 2048, "f64").operand(), -1, 0)
+    assert d[4:] == (32, 32), d
+    src = {id(gA): A, id(gB): B, id(gD): D}
+    want = ew.evaluate(flat.postfix, [src[id(m_)] for m_ in flat.mats], flat.scalars, "f64")
+    got = coot.eval(e).numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(got, want)
