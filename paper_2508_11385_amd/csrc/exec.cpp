@@ -172,6 +172,7 @@ static bool aligned(const void* p, size_t bytes) { return ((uintptr_t)p % bytes)
 // exhaustive tables over 3,000 random signatures on MI355X as the single
 // configuration with the lowest geometric-mean time ratio to each signature's best:
 //   flat family:   16-byte groups, 1 group per thread per trip, 4 waves, 4 workgroups per CU
+//                  (past 2^24 elements: below)
 //   tiled family:  2-element groups, 4 waves (fixed), 8 workgroups per CU
 //   dimension sums: 16-byte groups (one workgroup per segment)
 // (the tables hold 32- and 64-bit types; the 16-bit types' defaults are measured)
@@ -183,10 +184,17 @@ coot_launch_cfg default_cfg(int fam, int mode, int dim, int dtype, int64_t n) {
   if (dtype_is_half(dtype) && fam == FAM_FLAT && mode < 0) return {8, 1, 8, 16, 0, 0};
   if (dtype_is_half(dtype) && fam != FAM_FLAT) return {8, 0, 4, 16, 0, 0};
   if (fam == FAM_FLAT) {
-    // Past 2^24 elements (the streaming regime) fewer, longer-lived workgroups win:
-    // the best geomean over the largest signatures of the autotuner's timing tables.
+    // Past 2^24 elements (the streaming regime).  Reductions: fewer, longer-lived
+    // workgroups, the best geomean over the largest signatures of the autotuner's timing
+    // tables.  Element-wise: 2-element groups, 8 groups per thread per trip, 16
+    // workgroups per CU, the best fixed configuration over 32 signatures of 2^25 to 2^28
+    // elements (four types, 1 to 4 operands, exp-heavy and plain) timed one launch after
+    // a flush of the caches each (1.05 of each signature's best in geometric mean
+    // against 1.11 for the 16-byte groups with 2 workgroups per CU taken from the tables
+    // before), and as good on the tables' signatures past 2^24 elements (1.05 against
+    // 1.05-1.06): the many loads in flight per thread hide the latency of HBM.
     if (n > kStreamElems) {
-      if (mode < 0) return {v16, 1, 4, 2, 0, 0};
+      if (mode < 0) return {2, 8, 4, 16, 0, 0};
       return dtype == COOT_F64 ? coot_launch_cfg{2, 4, 8, 8, 0, 0} : coot_launch_cfg{4, 4, 4, 2, 0, 0};
     }
     return {v16, 1, 4, 4, 0, 0};

@@ -143,7 +143,7 @@ def default_index(cfgs, dtype, t=None, n=0, mode=-1):
         ts = 64 if n >= TILE_LARGE_ELEMS else 32
         want = (2, 1, 4, 8, ts, ts)
     elif n > STREAM_ELEMS:
-        want = (v, 1, 4, 2, 0, 0) if mode < 0 else ((2, 4, 8, 8, 0, 0) if dtype == "f64" else (4, 4, 4, 2, 0, 0))
+        want = (2, 8, 4, 16, 0, 0) if mode < 0 else ((2, 4, 8, 8, 0, 0) if dtype == "f64" else (4, 4, 4, 2, 0, 0))
     else:
         want = (v, 1, 4, 4, 0, 0)
     chain = [want, (1,) + want[1:]]

@@ -336,6 +336,39 @@ def test_flat_evaluation_beyond_the_infinity_cache(coot, dtype, shape):
     assert np.max(ulp_distance(W1[rows, cols], wo)) <= 1
 
 
+FLAT_CFGS = [(2, 8, 4, 16), (4, 8, 8, 2), (1, 8, 1, 16), (4, 2, 4, 4), (2, 4, 8, 16), (1, 1, 4, 4),
+             (4, 1, 4, 2), (2, 2, 2, 8)]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64", "u32"])
+def test_flat_launch_settings_match_oracle(coot, dtype):
+    """Flat evaluation on a ragged 1000 x 333 shape under a spread of launch settings
+    (vector width, groups per thread per trip, waves, workgroups per CU), the element-wise
+    default past 2^24 elements first: every element against the oracle (0 ulp, and at
+    most 1 ulp where exp appears)."""
+    R, C = 1000, 333
+    if dtype == "u32":
+        A, B, Cm = synth.int_inputs(which="u32", n_rows=R, n_cols=C)
+        gA, gB, gC = up(coot, A), up(coot, B), up(coot, Cm)
+        exprs = [((gA + gB) % gC, [A, B, Cm], 0)]
+    else:
+        A, B, Cm, _ = synth.matrix_inputs(dtype=dtype, n_rows=R, n_cols=C)
+        gA, gB, gC = up(coot, A), up(coot, B), up(coot, Cm)
+        exprs = [(2.0 * gA + gB % gC - gA, [A, B, Cm], 0), (_w(coot, gA, gB), [A, B], 1)]
+    for e, leaves, tol in exprs:
+        flat = coot.flatten(e)
+        src = {id(gA): A, id(gB): B, id(gC): Cm}
+        assert [src[id(m)] is l for m, l in zip(flat.mats, leaves)] == [True] * len(leaves)
+        want = ew.evaluate(flat.postfix, leaves, flat.scalars, dtype)
+        for cfg in FLAT_CFGS:
+            got = coot.eval(e, cfg=cfg).numpy()
+            if tol == 0:
+                assert got.dtype == want.dtype and np.array_equal(
+                    np.ascontiguousarray(got).view(np.uint8), np.ascontiguousarray(want).view(np.uint8)), (dtype, cfg)
+            else:
+                assert np.max(ulp_distance(got, want)) <= tol, (dtype, cfg)
+
+
 def test_full_size_integer_workload(coot):
     A, B, C = synth.int_inputs(8192, "u32")
     got = coot.eval((up(coot, A) + up(coot, B)) % up(coot, C)).numpy()

@@ -109,7 +109,7 @@ def test_tuner_default_index_names_the_library_default(cc, dt):
     flat, tiled = cc.coot_tune_space(0), cc.coot_tune_space(1)
     assert all(len(c) == 6 for c in flat + tiled)
     assert flat[tuner.default_index(flat, dt, None, 1000, -1)] == (v, 1, 4, 4, 0, 0)
-    assert flat[tuner.default_index(flat, dt, None, 1 << 25, -1)] == (v, 1, 4, 2, 0, 0)
+    assert flat[tuner.default_index(flat, dt, None, 1 << 25, -1)] == (2, 8, 4, 16, 0, 0)
     big_red = (2, 4, 8, 8, 0, 0) if dt == "f64" else (4, 4, 4, 2, 0, 0)
     assert flat[tuner.default_index(flat, dt, None, 1 << 25, 0)] == big_red
     assert tiled[tuner.default_index(tiled, dt, None, 1000, -1)] == (2, 1, 4, 8, 32, 32)
